@@ -1,0 +1,477 @@
+/*
+ * glo_oracle.c -- CPU oracle for exact 2-, 3- and 4-node graphlet counts.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's CPU
+ * baseline may load this code.  It shares nothing with the GPU library: no headers, no
+ * helpers, no tables.  It is deliberately plain and slow.
+ *
+ * Two independent methods live here:
+ *
+ *  (1) brute_*  -- the definition (Section 3, Definitions 1-3 and Problem 1): every 3- and
+ *      4-vertex subset is classified by the induced subgraph it spans.  Per-edge counts
+ *      enumerate every vertex pair outside the edge.  Feasible for a few hundred vertices.
+ *
+ *  (2) glo_*    -- the paper's edge-centric method (Section 4): for each edge the hash
+ *      Psi with per-edge unique tags (Alg. "3-Graphlets" and Section 4.5), the
+ *      neighbour-iteration scans for cliques (Alg. "Clique") and cycles (Alg. "Cycle"),
+ *      then the local counts, the unrestricted counts C3..C16 (Section 4.5) and the global
+ *      frequencies X1..X17 (Section 4.6).  Readings taken where the text is garbled:
+ *        - local x5 is n - x4 - |T| - 2 (the printed sign of |T| contradicts C5);
+ *        - C9 sums |T|*(|S_u|+|S_v|), not the triple product;
+ *        - X11 uses C11, not C9;
+ *        - the cycle scan tests for the S_v tag (lambda_1, kept by neighbours of v that
+ *          are not neighbours of u), since lambda_2 marks S_u itself;
+ *        - the clique scan counts each unordered adjacent pair of T once (sequential
+ *          reading of the parallel loop);
+ *        - |T| + |S_u| = d_u - 1 (v is excluded).
+ *      The remaining 4-node per-edge counts (chordal cycle, tailed triangle, 3-star,
+ *      4-path and the disconnected ones) follow from a partition of V \ {u,v} into
+ *      T, S_u, S_v and D (neither endpoint) and the edge counts between those classes,
+ *      derived from |T|, the clique and cycle counts, three extra scan counters and
+ *      vertex triangle / neighbour-degree sums.
+ *
+ * Edge numbering (shared convention of the C interface, re-implemented here): edge k is
+ * the k-th CSR entry (i, col[j]) with i < col[j] in row-major order.
+ *
+ * Per-edge output is 13 slots x m (slot-major), slots in graphlet order
+ *   0:H3 triangle 1:H4 2-star 2:H5 3-node-1-edge 3:H7 4-clique 4:H8 chordal-cycle
+ *   5:H9 tailed-triangle 6:H10 4-cycle 7:H11 3-star 8:H12 4-path 9:H13 4-node-1-triangle
+ *   10:H14 4-node-2-edge 11:H15 4-node-2-star 12:H16 4-node-1-edge
+ * Global output is 17 graphlets x (lo, hi) 64-bit words of an unsigned 128-bit count.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+typedef __int128 i128;
+typedef unsigned __int128 u128;
+
+#define ORC_OK 0
+#define ORC_E_ARG -1
+#define ORC_E_INEXACT -2   /* a division that must be exact was not: a bug */
+#define ORC_E_NEGATIVE -3  /* a count came out negative: a bug */
+#define ORC_E_NOMEM -4
+
+/* ------------------------------------------------------------------------------------ */
+/* small helpers                                                                         */
+/* ------------------------------------------------------------------------------------ */
+
+static i128 choose2(i128 x) { return x < 2 ? 0 : x * (x - 1) / 2; }
+static i128 choose3(i128 x) { return x < 3 ? 0 : x * (x - 1) * (x - 2) / 6; }
+static i128 choose4(i128 x) { return x < 4 ? 0 : x * (x - 1) * (x - 2) * (x - 3) / 24; }
+
+static void put128(uint64_t* out, int i, i128 v) {
+    u128 u = (u128)v;
+    out[2 * i] = (uint64_t)u;
+    out[2 * i + 1] = (uint64_t)(u >> 64);
+}
+
+/* edge list in the shared numbering */
+static int64_t build_edges(int64_t n, const int64_t* rp, const int32_t* col,
+                           int32_t* eu, int32_t* ev) {
+    int64_t k = 0;
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t j = rp[i]; j < rp[i + 1]; j++)
+            if ((int64_t)col[j] > i) {
+                if (eu) { eu[k] = (int32_t)i; ev[k] = col[j]; }
+                k++;
+            }
+    return k;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* (1) brute force from the definition                                                   */
+/* ------------------------------------------------------------------------------------ */
+
+/* Graphlet id (1-based, Table 1) of the induced subgraph on k vertices given its
+ * adjacency bits.  Classification of 4-vertex graphs by edge count and sorted degree
+ * sequence, which separates the 11 isomorphism classes. */
+static int classify3(int e) {
+    switch (e) { case 3: return 3; case 2: return 4; case 1: return 5; default: return 6; }
+}
+
+static int classify4(int e, int deg[4]) {
+    int d[4] = {deg[0], deg[1], deg[2], deg[3]};
+    for (int i = 1; i < 4; i++)
+        for (int j = i; j > 0 && d[j - 1] > d[j]; j--) { int t = d[j]; d[j] = d[j - 1]; d[j - 1] = t; }
+    switch (e) {
+    case 6: return 7;
+    case 5: return 8;
+    case 4: return (d[0] == 2) ? 10 : 9;           /* (2,2,2,2) cycle, (1,2,2,3) tailed */
+    case 3:
+        if (d[0] == 0) return 13;                  /* triangle + isolated */
+        if (d[3] == 3) return 11;                  /* star */
+        return 12;                                 /* path */
+    case 2: return (d[0] == 1) ? 14 : 15;          /* two disjoint edges, or wedge + K1 */
+    case 1: return 16;
+    default: return 17;
+    }
+}
+
+static inline int adjbit(const uint8_t* A, int64_t n, int64_t a, int64_t b) { return A[a * n + b]; }
+
+int brute_count(int64_t n, const int64_t* rp, const int32_t* col,
+                uint64_t* X /* [17] */, uint64_t* per_edge /* [13*m] or NULL */) {
+    if (n < 0 || n > 4096 || !rp || (!col && rp[n] > 0) || !X) return ORC_E_ARG;
+    uint8_t* A = (uint8_t*)calloc((size_t)(n > 0 ? n * n : 1), 1);
+    if (!A) return ORC_E_NOMEM;
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t j = rp[i]; j < rp[i + 1]; j++) A[i * n + col[j]] = 1;
+    uint64_t cnt[18] = {0};
+    for (int64_t a = 0; a < n; a++)
+        for (int64_t b = a + 1; b < n; b++) {
+            cnt[adjbit(A, n, a, b) ? 1 : 2]++;
+            for (int64_t c = b + 1; c < n; c++) {
+                int e3 = adjbit(A, n, a, b) + adjbit(A, n, a, c) + adjbit(A, n, b, c);
+                cnt[classify3(e3)]++;
+                for (int64_t d = c + 1; d < n; d++) {
+                    int64_t v[4] = {a, b, c, d};
+                    int deg[4] = {0, 0, 0, 0}, e = 0;
+                    for (int x = 0; x < 4; x++)
+                        for (int y = x + 1; y < 4; y++)
+                            if (adjbit(A, n, v[x], v[y])) { e++; deg[x]++; deg[y]++; }
+                    cnt[classify4(e, deg)]++;
+                }
+            }
+        }
+    for (int i = 0; i < 17; i++) X[i] = cnt[i + 1];
+    if (per_edge) {
+        int64_t m = build_edges(n, rp, col, NULL, NULL);
+        int32_t* eu = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
+        int32_t* ev = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
+        if (!eu || !ev) { free(A); free(eu); free(ev); return ORC_E_NOMEM; }
+        build_edges(n, rp, col, eu, ev);
+        /* graphlet id -> per-edge slot */
+        static const int slot_of[18] = {-1, -1, -1, 0, 1, 2, -1, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, -1};
+        memset(per_edge, 0, sizeof(uint64_t) * 13 * (size_t)m);
+        for (int64_t k = 0; k < m; k++) {
+            int64_t a = eu[k], b = ev[k];
+            for (int64_t w = 0; w < n; w++) {
+                if (w == a || w == b) continue;
+                int e3 = 1 + adjbit(A, n, a, w) + adjbit(A, n, b, w);
+                per_edge[(size_t)slot_of[classify3(e3)] * m + k]++;
+                for (int64_t r = w + 1; r < n; r++) {
+                    if (r == a || r == b) continue;
+                    int64_t v[4] = {a, b, w, r};
+                    int deg[4] = {0, 0, 0, 0}, e = 0;
+                    for (int x = 0; x < 4; x++)
+                        for (int y = x + 1; y < 4; y++)
+                            if (adjbit(A, n, v[x], v[y])) { e++; deg[x]++; deg[y]++; }
+                    per_edge[(size_t)slot_of[classify4(e, deg)] * m + k]++;
+                }
+            }
+        }
+        free(eu); free(ev);
+    }
+    free(A);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* (2) the paper's edge-centric method                                                   */
+/* ------------------------------------------------------------------------------------ */
+
+/* Preprocessing P1/P3 (Section 4.2): vertices are ordered by (degree, id) ascending; for
+ * an edge the endpoint called v is the later one in that order, so d_v >= d_u.  The
+ * order is only used to name the endpoints, so it is applied as a comparison rather than
+ * a physical relabelling. */
+static inline int ranks_above(const int64_t* deg, int64_t a, int64_t b) {
+    return deg[a] > deg[b] || (deg[a] == deg[b] && a > b);
+}
+
+/* Per-vertex pre-pass: tri[x] = edges among N(x) (triangles at x), sdeg[x] = sum of the
+ * degrees of x's neighbours.  Plain neighbour iteration with a mark array. */
+static int vertex_terms(int64_t n, const int64_t* rp, const int32_t* col, const int64_t* deg,
+                        const uint8_t* want, int64_t* tri, int64_t* sdeg, int nthreads) {
+    int fail = 0;
+#pragma omp parallel num_threads(nthreads)
+    {
+        int64_t* mark = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+        if (!mark) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t x = 0; x < n; x++) {
+            if (!mark || (want && !want[x])) continue;
+            int64_t tag = x + 1;
+            int64_t s = 0, c = 0;
+            for (int64_t j = rp[x]; j < rp[x + 1]; j++) { mark[col[j]] = tag; s += deg[col[j]]; }
+            for (int64_t j = rp[x]; j < rp[x + 1]; j++) {
+                int64_t y = col[j];
+                for (int64_t k = rp[y]; k < rp[y + 1]; k++)
+                    if (mark[col[k]] == tag) c++;
+            }
+            tri[x] = c / 2;   /* every edge among N(x) was seen from both of its ends */
+            sdeg[x] = s;
+        }
+        free(mark);
+    }
+    return fail ? ORC_E_NOMEM : ORC_OK;
+}
+
+typedef struct {
+    int64_t t, su, sv, D;     /* |T|, |S_u|, |S_v|, vertices adjacent to neither */
+    int64_t K;                /* edges inside T: 4-cliques on the edge  (X_{k,7})  */
+    int64_t Q;                /* edges between S_u and S_v: 4-cycles     (X_{k,10}) */
+    int64_t au, av;           /* edges T-S_u and T-S_v                             */
+    int64_t sigT;             /* sum of degrees over T                             */
+} edge_terms;
+
+/* One edge neighbourhood: Alg. "3-Graphlets" builds T and S_u with the tags
+ * lambda1 (neighbours of v), lambda2 (S_u) and lambda3 (T); Alg. "Clique" scans N(w) for
+ * w in T (extended to also count tags lambda2 and lambda1, i.e. T-S_u and T-S_v edges),
+ * Alg. "Cycle" scans N(w) for w in S_u counting neighbours still tagged lambda1 (S_v). */
+static void edge_neighbourhood(int64_t u, int64_t v, const int64_t* rp, const int32_t* col,
+                               const int64_t* deg, int64_t* psi, int64_t* Tbuf, int64_t* Sbuf,
+                               int64_t serial, edge_terms* out) {
+    const int64_t l1 = 3 * serial + 1, l2 = 3 * serial + 2, l3 = 3 * serial + 3;
+    int64_t nt = 0, ns = 0;
+    for (int64_t j = rp[v]; j < rp[v + 1]; j++)
+        if (col[j] != u) psi[col[j]] = l1;
+    for (int64_t j = rp[u]; j < rp[u + 1]; j++) {
+        int64_t w = col[j];
+        if (w == v) continue;
+        if (psi[w] == l1) { Tbuf[nt++] = w; psi[w] = l3; }
+        else { Sbuf[ns++] = w; psi[w] = l2; }
+    }
+    int64_t twoK = 0, au = 0, av = 0, sig = 0, Q = 0;
+    for (int64_t i = 0; i < nt; i++) {
+        int64_t w = Tbuf[i];
+        sig += deg[w];
+        for (int64_t j = rp[w]; j < rp[w + 1]; j++) {
+            int64_t tag = psi[col[j]];
+            if (tag == l3) twoK++;
+            else if (tag == l2) au++;
+            else if (tag == l1) av++;
+        }
+    }
+    for (int64_t i = 0; i < ns; i++) {
+        int64_t w = Sbuf[i];
+        for (int64_t j = rp[w]; j < rp[w + 1]; j++)
+            if (psi[col[j]] == l1) Q++;
+    }
+    out->t = nt;
+    out->su = ns;
+    out->sv = deg[v] - 1 - nt;
+    out->K = twoK / 2;
+    out->Q = Q;
+    out->au = au;
+    out->av = av;
+    out->sigT = sig;
+}
+
+/* The 13 local counts of an edge from its terms (class-pair edge counts, see header). */
+static int local_counts(const edge_terms* e, int64_t n, int64_t m, int64_t du, int64_t dv,
+                        int64_t tri_u, int64_t tri_v, int64_t sdeg_u, int64_t sdeg_v,
+                        int64_t out[13]) {
+    int64_t t = e->t, su = e->su, sv = e->sv, K = e->K, Q = e->Q, au = e->au, av = e->av;
+    int64_t D = n - 2 - t - su - sv;
+    int64_t Esu = tri_u - t - K - au;               /* edges inside S_u */
+    int64_t Esv = tri_v - t - K - av;               /* edges inside S_v */
+    int64_t ETD = e->sigT - 2 * t - 2 * K - au - av;
+    int64_t sig_u = sdeg_u - dv - e->sigT;          /* sum of degrees over S_u */
+    int64_t sig_v = sdeg_v - du - e->sigT;
+    int64_t ESuD = sig_u - su - 2 * Esu - au - Q;
+    int64_t ESvD = sig_v - sv - 2 * Esv - av - Q;
+    int64_t EDD = m - 1 - 2 * t - su - sv -
+                  (K + Esu + Esv + au + av + Q + ETD + ESuD + ESvD);
+    out[0] = t;
+    out[1] = su + sv;
+    out[2] = D;
+    out[3] = K;
+    out[4] = (t * (t - 1) / 2 - K) + au + av;
+    out[5] = (t * su - au) + (t * sv - av) + ETD + Esu + Esv;
+    out[6] = Q;
+    out[7] = (su * (su - 1) / 2 - Esu) + (sv * (sv - 1) / 2 - Esv);
+    out[8] = (su * sv - Q) + ESuD + ESvD;
+    out[9] = t * D - ETD;
+    out[10] = EDD;
+    out[11] = (su + sv) * D - ESuD - ESvD;
+    out[12] = D * (D - 1) / 2 - EDD;
+    if (D < 0 || Esu < 0 || Esv < 0 || ETD < 0 || ESuD < 0 || ESvD < 0 || EDD < 0)
+        return ORC_E_NEGATIVE;
+    for (int i = 0; i < 13; i++)
+        if (out[i] < 0) return ORC_E_NEGATIVE;
+    return ORC_OK;
+}
+
+/* Global frequencies from the unrestricted counts (Section 4.6). */
+static int global_from_unrestricted(int64_t n, int64_t m, const i128 C[17], i128 X[18]) {
+#define EXACT(num, den, dst) do { i128 _n = (num); if (_n % (den) != 0 || _n < 0) return ORC_E_INEXACT; dst = _n / (den); } while (0)
+    X[1] = m;
+    X[2] = choose2(n) - m;
+    EXACT(C[3], 3, X[3]);
+    EXACT(C[4], 2, X[4]);
+    X[5] = C[5];
+    X[6] = choose3(n) - X[3] - X[4] - X[5];
+    EXACT(C[7], 6, X[7]);
+    X[8] = C[8] - C[7];
+    EXACT(C[9] - 4 * X[8], 2, X[9]);
+    EXACT(C[10], 4, X[10]);
+    EXACT(C[11] - X[9], 3, X[11]);
+    X[12] = C[12] - C[10];
+    EXACT(C[13] - X[9], 3, X[13]);
+    EXACT(C[14] - 6 * X[7] - 4 * X[8] - 2 * X[9] - 4 * X[10] - 2 * X[12], 2, X[14]);
+    EXACT(C[15] - 2 * X[12], 2, X[15]);
+    X[16] = C[16] - 2 * X[14];
+    i128 s = 0;
+    for (int i = 7; i <= 16; i++) s += X[i];
+    X[17] = choose4(n) - s;
+    for (int i = 1; i <= 17; i++)
+        if (X[i] < 0) return ORC_E_NEGATIVE;
+    return ORC_OK;
+#undef EXACT
+}
+
+/* Full count: global X1..X17 (as 17 x (lo,hi)), optional unrestricted sums C (index 3..16
+ * meaningful, same layout), optional per-edge counts [13][m]. */
+int glo_count(int64_t n, const int64_t* rp, const int32_t* col, int nthreads,
+              uint64_t* Xout, uint64_t* Cout, uint64_t* per_edge) {
+    if (n < 0 || !rp || !Xout || nthreads < 1) return ORC_E_ARG;
+    int64_t m = build_edges(n, rp, col, NULL, NULL);
+    int32_t* eu = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
+    int32_t* ev = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
+    int64_t* deg = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t* tri = (int64_t*)calloc((size_t)(n + 1), sizeof(int64_t));
+    int64_t* sdeg = (int64_t*)calloc((size_t)(n + 1), sizeof(int64_t));
+    int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m + 1));
+    int rc = ORC_OK;
+    if (!eu || !ev || !deg || !tri || !sdeg || !order) { rc = ORC_E_NOMEM; goto done; }
+    build_edges(n, rp, col, eu, ev);
+    for (int64_t x = 0; x < n; x++) deg[x] = rp[x + 1] - rp[x];
+    rc = vertex_terms(n, rp, col, deg, NULL, tri, sdeg, nthreads);
+    if (rc) goto done;
+    /* Edge order Pi (Section 4.3): heaviest edges first, by d_u + d_v, ties by id; workers
+     * take one edge at a time (chunk b = 1, the paper's CPU setting). */
+    {
+        int64_t maxkey = 0;
+        for (int64_t k = 0; k < m; k++) {
+            int64_t key = deg[eu[k]] + deg[ev[k]];
+            if (key > maxkey) maxkey = key;
+        }
+        int64_t* bucket = (int64_t*)calloc((size_t)(maxkey + 2), sizeof(int64_t));
+        if (!bucket) { rc = ORC_E_NOMEM; goto done; }
+        for (int64_t k = 0; k < m; k++) bucket[maxkey - (deg[eu[k]] + deg[ev[k]])]++;
+        int64_t acc = 0;
+        for (int64_t b = 0; b <= maxkey; b++) { int64_t c = bucket[b]; bucket[b] = acc; acc += c; }
+        for (int64_t k = 0; k < m; k++) order[bucket[maxkey - (deg[eu[k]] + deg[ev[k]])]++] = k;
+        free(bucket);
+    }
+    {
+        i128 Csum[17];
+        memset(Csum, 0, sizeof(Csum));
+        int fail = 0;
+#pragma omp parallel num_threads(nthreads)
+        {
+            int64_t* psi = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+            int64_t* Tb = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+            int64_t* Sb = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+            i128 loc[17];
+            memset(loc, 0, sizeof(loc));
+            int64_t serial = 0;
+            int lfail = (!psi || !Tb || !Sb) ? ORC_E_NOMEM : 0;
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t q = 0; q < m; q++) {
+                if (lfail) continue;
+                int64_t k = order[q];
+                int64_t a = eu[k], b = ev[k];
+                int64_t v = ranks_above(deg, a, b) ? a : b;
+                int64_t u = (v == a) ? b : a;
+                edge_terms e;
+                edge_neighbourhood(u, v, rp, col, deg, psi, Tb, Sb, serial++, &e);
+                int64_t x[13];
+                int r = local_counts(&e, n, m, deg[u], deg[v], tri[u], tri[v], sdeg[u], sdeg[v], x);
+                if (r) { lfail = r; continue; }
+                if (per_edge)
+                    for (int i = 0; i < 13; i++) per_edge[(size_t)i * m + k] = (uint64_t)x[i];
+                /* unrestricted counts (Section 4.5) */
+                i128 t = e.t, s = e.su + e.sv, D = x[2];
+                loc[3] += t;
+                loc[4] += s;
+                loc[5] += D;
+                loc[7] += e.K;
+                loc[8] += choose2(t);
+                loc[9] += t * s;
+                loc[10] += e.Q;
+                loc[11] += choose2(e.su) + choose2(e.sv);
+                loc[12] += (i128)e.su * e.sv;
+                loc[13] += t * D;
+                loc[14] += (i128)(m - deg[u] - deg[v] + 1);
+                loc[15] += s * D;
+                loc[16] += choose2(D);
+            }
+#pragma omp critical
+            {
+                for (int i = 0; i < 17; i++) Csum[i] += loc[i];
+                if (lfail) fail = lfail;
+            }
+            free(psi); free(Tb); free(Sb);
+        }
+        if (fail) { rc = fail; goto done; }
+        i128 X[18];
+        rc = global_from_unrestricted(n, m, Csum, X);
+        if (rc) goto done;
+        for (int i = 0; i < 17; i++) put128(Xout, i, X[i + 1]);
+        if (Cout)
+            for (int i = 0; i < 17; i++) put128(Cout, i, Csum[i]);
+    }
+done:
+    free(eu); free(ev); free(deg); free(tri); free(sdeg); free(order);
+    return rc;
+}
+
+/* Per-edge counts for selected edges only (no global sums).  Vertex terms are computed
+ * just for the endpoints involved, so this runs on graphs far too large for glo_count. */
+int glo_count_edges(int64_t n, const int64_t* rp, const int32_t* col, int nthreads,
+                    const int64_t* eids, int64_t k, uint64_t* out /* [13][k] */) {
+    if (n < 0 || !rp || nthreads < 1 || (k > 0 && (!eids || !out))) return ORC_E_ARG;
+    int64_t m = build_edges(n, rp, col, NULL, NULL);
+    for (int64_t i = 0; i < k; i++)
+        if (eids[i] < 0 || eids[i] >= m) return ORC_E_ARG;
+    int32_t* eu = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
+    int32_t* ev = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
+    int64_t* deg = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t* tri = (int64_t*)calloc((size_t)(n + 1), sizeof(int64_t));
+    int64_t* sdeg = (int64_t*)calloc((size_t)(n + 1), sizeof(int64_t));
+    uint8_t* want = (uint8_t*)calloc((size_t)(n + 1), 1);
+    int rc = ORC_OK;
+    if (!eu || !ev || !deg || !tri || !sdeg || !want) { rc = ORC_E_NOMEM; goto done; }
+    build_edges(n, rp, col, eu, ev);
+    for (int64_t x = 0; x < n; x++) deg[x] = rp[x + 1] - rp[x];
+    for (int64_t i = 0; i < k; i++) { want[eu[eids[i]]] = 1; want[ev[eids[i]]] = 1; }
+    rc = vertex_terms(n, rp, col, deg, want, tri, sdeg, nthreads);
+    if (rc) goto done;
+    {
+        int fail = 0;
+#pragma omp parallel num_threads(nthreads)
+        {
+            int64_t* psi = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+            int64_t* Tb = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+            int64_t* Sb = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+            int64_t serial = 0;
+            int lfail = (!psi || !Tb || !Sb) ? ORC_E_NOMEM : 0;
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t i = 0; i < k; i++) {
+                if (lfail) continue;
+                int64_t a = eu[eids[i]], b = ev[eids[i]];
+                int64_t v = ranks_above(deg, a, b) ? a : b;
+                int64_t u = (v == a) ? b : a;
+                edge_terms e;
+                edge_neighbourhood(u, v, rp, col, deg, psi, Tb, Sb, serial++, &e);
+                int64_t x[13];
+                int r = local_counts(&e, n, m, deg[u], deg[v], tri[u], tri[v], sdeg[u], sdeg[v], x);
+                if (r) { lfail = r; continue; }
+                for (int s = 0; s < 13; s++) out[(size_t)s * k + i] = (uint64_t)x[s];
+            }
+#pragma omp critical
+            { if (lfail) fail = lfail; }
+            free(psi); free(Tb); free(Sb);
+        }
+        rc = fail;
+    }
+done:
+    free(eu); free(ev); free(deg); free(tri); free(sdeg); free(want);
+    return rc;
+}

@@ -1,0 +1,354 @@
+"""Pins for the CPU oracle (no GPU).
+
+The oracle is checked against things other than itself: the Table 1 catalogue (labelled
+copy counts and complement pairs), hand-derived counts of each graphlet taken as a whole
+graph, a pure-Python enumeration, the brute-force definition, closed forms for complete,
+cycle, path, star and complete-bipartite graphs, trace(A^3)/6, the complement identity with
+an independently computed 4-node-independent count, and edge/global consistency.
+"""
+import itertools
+import os
+from math import comb
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+# complement pairs of Table 1 (graphlet id -> id of its complement); the 4-path is
+# self-complementary
+COMPLEMENT = {1: 2, 2: 1, 3: 6, 6: 3, 4: 5, 5: 4, 7: 17, 17: 7, 8: 16, 16: 8, 9: 15, 15: 9,
+              10: 14, 14: 10, 11: 13, 13: 11, 12: 12}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+
+
+def _csr(n, pairs):
+    return gg.from_pairs(n, pairs)[1]
+
+
+# --------------------------------------------------------------------------------------
+# the catalogue itself
+# --------------------------------------------------------------------------------------
+
+def test_labelled_copies_per_class():
+    """Every labelled graph on 4 (3) vertices falls in exactly one class, with the textbook
+    number of labelled copies 4!/|Aut(H)| (3!/|Aut(H)|)."""
+    expect4 = {7: 1, 8: 6, 9: 12, 10: 3, 11: 4, 12: 12, 13: 4, 14: 3, 15: 12, 16: 6, 17: 1}
+    pairs4 = list(itertools.combinations(range(4), 2))
+    got = {}
+    for mask in range(64):
+        adj = [[False] * 4 for _ in range(4)]
+        for b, (i, j) in enumerate(pairs4):
+            if mask >> b & 1:
+                adj[i][j] = adj[j][i] = True
+        g = oracle._iso_class((0, 1, 2, 3), adj)
+        got[g] = got.get(g, 0) + 1
+    assert got == expect4
+    expect3 = {3: 1, 4: 3, 5: 3, 6: 1}
+    pairs3 = list(itertools.combinations(range(3), 2))
+    got = {}
+    for mask in range(8):
+        adj = [[False] * 3 for _ in range(3)]
+        for b, (i, j) in enumerate(pairs3):
+            if mask >> b & 1:
+                adj[i][j] = adj[j][i] = True
+        g = oracle._iso_class((0, 1, 2), adj)
+        got[g] = got.get(g, 0) + 1
+    assert got == expect3
+
+
+def test_complement_pairs_of_table1():
+    """The complement of each Table 1 representative is isomorphic to its listed partner."""
+    for gid, (k, rep) in oracle._REPS.items():
+        adj = [[False] * k for _ in range(k)]
+        for i, j in itertools.combinations(range(k), 2):
+            if (i, j) not in rep and (j, i) not in rep:
+                adj[i][j] = adj[j][i] = True
+        assert oracle._iso_class(tuple(range(k)), adj) == COMPLEMENT[gid]
+
+
+def _golden_table1():
+    rows = []
+    with open(os.path.join(GOLDEN, "table1_graphlets.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            gid, edges, counts = [p.strip() for p in line.split("|")]
+            pairs = [(int(e[0]), int(e[1])) for e in edges.split()]
+            rows.append((int(gid), pairs, [int(c) for c in counts.split()]))
+    return rows
+
+
+@pytest.mark.parametrize("row", _golden_table1(), ids=lambda r: f"H{r[0]}")
+def test_table1_graphlet_as_whole_graph(row):
+    gid, pairs, expect = row
+    X, _ = oracle.brute_py(4, pairs)
+    assert X == expect
+    rp, col = _csr(4, pairs)
+    assert oracle.brute(4, rp, col)["X"] == expect
+    assert oracle.count(4, rp, col)["X"] == expect
+
+
+# --------------------------------------------------------------------------------------
+# brute force (C) against the pure-Python enumeration
+# --------------------------------------------------------------------------------------
+
+def _random_pairs(n, p, rng):
+    return [(i, j) for i, j in itertools.combinations(range(n), 2) if rng.random() < p]
+
+
+def test_brute_c_matches_python():
+    rng = np.random.default_rng(11)
+    for trial in range(40):
+        n = int(rng.integers(2, 9))
+        pairs = _random_pairs(n, float(rng.uniform(0.1, 0.9)), rng)
+        X, per = oracle.brute_py(n, pairs)
+        rp, col = _csr(n, pairs)
+        b = oracle.brute(n, rp, col, per_edge=True)
+        assert b["X"] == X
+        # edge numbering: row-major (i, col[j]) with i < col[j]
+        src = np.repeat(np.arange(n), np.diff(rp))
+        edges = [(int(s), int(c)) for s, c in zip(src, col) if c > s]
+        for k, e in enumerate(edges):
+            assert list(b["per_edge"][:, k]) == per[e]
+
+
+# --------------------------------------------------------------------------------------
+# the paper's method against the definition
+# --------------------------------------------------------------------------------------
+
+def _check_against_brute(n, rp, col):
+    r = oracle.count(n, rp, col, per_edge=True, nthreads=2)
+    b = oracle.brute(n, rp, col, per_edge=True)
+    assert r["X"] == b["X"]
+    np.testing.assert_array_equal(r["per_edge"], b["per_edge"])
+    return r
+
+
+def test_method_matches_brute_random():
+    rng = np.random.default_rng(12)
+    for trial in range(250):
+        n = int(rng.integers(4, 41))
+        p = float(rng.choice([0.05, 0.1, 0.2, 0.35, 0.5, 0.7, 0.9, 0.95]))
+        pairs = _random_pairs(n, p, rng)
+        rp, col = _csr(n, pairs)
+        # neighbour order must not matter
+        col = gg.shuffle_rows(rp, col, trial)
+        _check_against_brute(n, rp, col)
+
+
+def test_method_matches_brute_powerlaw():
+    for s in range(30):
+        n = 20 + s
+        m = min(n * (n - 1) // 4, 3 * n)
+        rp, col = gg.chung_lu(n, m, 2.2, float(n - 1), 1000 + s)
+        _check_against_brute(n, rp, col)
+
+
+@pytest.mark.parametrize("name,n,pairs", [
+    ("empty-graph", 5, []),
+    ("no-vertices-but-4", 4, []),
+    ("single-edge", 2, [(0, 1)]),
+    ("single-edge-isolated", 7, [(0, 1)]),
+    ("triangle", 3, [(0, 1), (1, 2), (0, 2)]),
+    ("two-triangles-disjoint", 6, [(0, 1), (1, 2), (0, 2), (3, 4), (4, 5), (3, 5)]),
+    ("star-plus-isolated", 9, [(0, i) for i in range(1, 7)]),
+    ("clique-plus-pendant", 8, [p for p in itertools.combinations(range(6), 2)] + [(5, 6)]),
+    ("equal-degree-ties", 8, [(i, (i + 1) % 8) for i in range(8)] + [(i, (i + 4) % 8) for i in range(4)]),
+])
+def test_method_degenerate(name, n, pairs):
+    rp, col = _csr(n, pairs)
+    _check_against_brute(n, rp, col)
+
+
+def test_method_zero_and_one_vertex():
+    for n in (0, 1):
+        rp = np.zeros(n + 1, dtype=np.int64)
+        col = np.zeros(0, dtype=np.int32)
+        r = oracle.count(n, rp, col, per_edge=True)
+        assert r["X"] == [0] * 17
+        assert r["per_edge"].shape == (13, 0)
+
+
+# --------------------------------------------------------------------------------------
+# closed forms (independent formulas), small n against brute force, large n exact
+# --------------------------------------------------------------------------------------
+
+def _full(n, nz):
+    """17-vector with X2 = C(n,2)-X1, X6 = C(n,3)-X3-X4-X5, X17 = C(n,4)-sum X7..X16."""
+    X = [0] * 18
+    for k, v in nz.items():
+        X[k] = v
+    X[2] = comb(n, 2) - X[1]
+    X[6] = comb(n, 3) - X[3] - X[4] - X[5] if 6 not in nz else X[6]
+    X[17] = comb(n, 4) - sum(X[7:17]) if 17 not in nz else X[17]
+    return X[1:]
+
+
+def closed_complete(n):
+    return _full(n, {1: comb(n, 2), 3: comb(n, 3), 7: comb(n, 4)})
+
+
+def closed_cycle(n):
+    assert n >= 6
+    return _full(n, {1: n, 4: n, 5: n * (n - 4), 12: n, 14: n * (n - 5) // 2,
+                     15: n * (n - 5), 16: n * (comb(n - 4, 2) - (n - 5))})
+
+
+def closed_path(n):
+    assert n >= 5
+    return _full(n, {1: n - 1, 4: n - 2, 5: (n - 2) * (n - 3), 12: n - 3, 14: comb(n - 3, 2),
+                     15: (n - 3) * (n - 4), 16: (n - 3) * (n - 4) * (n - 5) // 2})
+
+
+def closed_star(s):
+    N = s + 1
+    return _full(N, {1: s, 4: comb(s, 2), 6: comb(s, 3), 11: comb(s, 3), 17: comb(s, 4)})
+
+
+def closed_bipartite(a, b):
+    N = a + b
+    return _full(N, {1: a * b, 4: a * comb(b, 2) + b * comb(a, 2), 6: comb(a, 3) + comb(b, 3),
+                     10: comb(a, 2) * comb(b, 2), 11: a * comb(b, 3) + b * comb(a, 3),
+                     17: comb(a, 4) + comb(b, 4)})
+
+
+def test_closed_forms_small_against_brute():
+    cases = [(gg.complete(n), closed_complete(n)) for n in (1, 2, 3, 4, 5, 9)]
+    cases += [(gg.cycle(n), closed_cycle(n)) for n in (6, 7, 11)]
+    cases += [(gg.path(n), closed_path(n)) for n in (5, 6, 10)]
+    cases += [(gg.star(s), closed_star(s)) for s in (1, 3, 4, 8)]
+    cases += [(gg.complete_bipartite(a, b), closed_bipartite(a, b))
+              for a, b in ((1, 1), (2, 3), (3, 3), (4, 6))]
+    for (n, (rp, col)), expect in cases:
+        assert oracle.brute(n, rp, col)["X"] == expect
+        assert oracle.count(n, rp, col)["X"] == expect
+
+
+def test_special_small_cycles():
+    # C4 and C5 are below the generic cycle formula's range
+    n, (rp, col) = gg.cycle(4)
+    assert oracle.count(n, rp, col)["X"] == _full(4, {1: 4, 4: 4, 10: 1})
+    n, (rp, col) = gg.cycle(5)
+    assert oracle.count(n, rp, col)["X"] == _full(5, {1: 5, 4: 5, 5: 5, 12: 5})
+
+
+def test_closed_forms_large_exact_128bit():
+    # C(n,4) > 2^64 here: the global path must be exact beyond 64 bits
+    n = 3_000_000
+    N, (rp, col) = gg.cycle(n)
+    X = oracle.count(N, rp, col)["X"]
+    assert X == closed_cycle(n)
+    assert X[16] > 2**64
+    n = 200_000
+    N, (rp, col) = gg.path(n)
+    assert oracle.count(N, rp, col)["X"] == closed_path(n)
+    N, (rp, col) = gg.complete(90)
+    assert oracle.count(N, rp, col)["X"] == closed_complete(90)
+    N, (rp, col) = gg.star(5000)
+    assert oracle.count(N, rp, col)["X"] == closed_star(5000)
+    N, (rp, col) = gg.complete_bipartite(7, 900)
+    assert oracle.count(N, rp, col)["X"] == closed_bipartite(7, 900)
+
+
+# --------------------------------------------------------------------------------------
+# invariants
+# --------------------------------------------------------------------------------------
+
+def _adj(n, rp, col):
+    A = np.zeros((n, n), dtype=np.int64)
+    src = np.repeat(np.arange(n), np.diff(np.asarray(rp, dtype=np.int64)))
+    A[src, col] = 1
+    return A
+
+
+def test_triangles_trace():
+    for seed, (n, m) in enumerate([(300, 4000), (800, 20000), (1500, 30000)]):
+        rp, col = gg.er(n, m, 77 + seed)
+        A = _adj(n, rp, col)
+        tr = int(np.trace(A @ A @ A))
+        assert tr % 6 == 0
+        assert oracle.count(n, rp, col)["X"][2] == tr // 6
+
+
+def test_complement_identity_and_subset_sums():
+    rng = np.random.default_rng(5)
+    for trial in range(25):
+        n = int(rng.integers(5, 60))
+        pairs = _random_pairs(n, float(rng.uniform(0.05, 0.95)), rng)
+        rp, col = _csr(n, pairs)
+        X = oracle.count(n, rp, col)["X"]
+        cn, (crp, ccol) = gg.complement(n, rp, col)
+        Xc = oracle.count(cn, crp, ccol)["X"]
+        for i in range(1, 18):
+            assert X[i - 1] == Xc[COMPLEMENT[i] - 1], (trial, i)
+        # subset-count identities with the 4-node-independent count taken from the
+        # complement's 4-cliques (not from the remainder formula)
+        assert X[0] + X[1] == comb(n, 2)
+        assert sum(X[2:6]) == comb(n, 3)
+        assert sum(X[6:16]) + Xc[6] == comb(n, 4)
+
+
+def test_edge_sums_equal_edges_times_global():
+    for seed in range(8):
+        n, m = 60 + 10 * seed, 300 + 100 * seed
+        rp, col = gg.chung_lu(n, m, 2.3, float(n - 1), 300 + seed)
+        r = oracle.count(n, rp, col, per_edge=True)
+        for s, gid in enumerate(oracle.EDGE_SLOTS):
+            assert int(r["per_edge"][s].sum()) == oracle.GRAPHLET_EDGES[gid - 1] * r["X"][gid - 1]
+
+
+def test_invariant_under_relabelling_and_row_order():
+    n, m = 400, 3000
+    rp, col = gg.chung_lu(n, m, 2.2, float(n - 1), 9)
+    X = oracle.count(n, rp, col)["X"]
+    perm = np.random.default_rng(3).permutation(n)
+    n2, (rp2, col2) = gg.relabel(n, rp, col, perm)
+    assert oracle.count(n2, rp2, col2)["X"] == X
+    col3 = gg.shuffle_rows(rp, col, 4)
+    r1 = oracle.count(n, rp, col, per_edge=True)
+    r3 = oracle.count(n, rp, col3, per_edge=True)
+    assert r3["X"] == X
+    # same edges, same numbering (numbering depends only on the row-major scan of (i<j)
+    # entries, which row shuffling permutes within a row), so compare as edge -> counts
+    def by_edge(rp_, col_, pe):
+        src = np.repeat(np.arange(n), np.diff(rp_))
+        ed = [(int(s), int(c)) for s, c in zip(src, col_) if c > s]
+        return {e: tuple(pe[:, k]) for k, e in enumerate(ed)}
+    assert by_edge(rp, col, r1["per_edge"]) == by_edge(rp, col3, r3["per_edge"])
+
+
+def test_threads_do_not_change_result():
+    n, (rp, col) = gg.config_er_1k()
+    a = oracle.count(n, rp, col, per_edge=True, nthreads=1)
+    b = oracle.count(n, rp, col, per_edge=True, nthreads=4)
+    assert a["X"] == b["X"]
+    np.testing.assert_array_equal(a["per_edge"], b["per_edge"])
+
+
+def test_count_edges_matches_full():
+    n, (rp, col) = gg.config_er_1k()
+    full = oracle.count(n, rp, col, per_edge=True)
+    eids = np.array([0, 1, 17, 500, 9999, 4242], dtype=np.int64)
+    sub = oracle.count_edges(n, rp, col, eids)
+    np.testing.assert_array_equal(sub, full["per_edge"][:, eids])
+
+
+def test_er_expectation_smoke():
+    """Global connected 4-node counts of G(n,p) near C(n,4) * a_i * p^e (1-p)^(6-e)."""
+    n, p = 400, 0.08
+    m = int(round(p * comb(n, 2)))
+    rp, col = gg.er(n, m, 2024)
+    X = oracle.count(n, rp, col)["X"]
+    labelled = {7: (1, 6), 8: (6, 5), 9: (12, 4), 10: (3, 4), 11: (4, 3), 12: (12, 3)}
+    for gid, (a, e) in labelled.items():
+        expect = comb(n, 4) * a * p**e * (1 - p)**(6 - e)
+        if expect > 2000:
+            assert abs(X[gid - 1] - expect) / expect < 0.25, (gid, X[gid - 1], expect)
