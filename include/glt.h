@@ -1,0 +1,130 @@
+/*
+ * glt.h -- exact 2-, 3- and 4-node graphlet (network motif) counts on an AMD MI355X.
+ *
+ * C ABI of libglt.  The library counts, for a simple undirected graph, the number of
+ * induced embeddings of every graphlet H1..H17 of the paper's Table 1 (global counts,
+ * Section 3 "Problem Formulation", global graphlet counting problem), and optionally the
+ * number of those embeddings that contain each edge (per-edge or "micro" counts,
+ * Section 4.3 and Section 4.5 "Unrestricted counts").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Graph input is a symmetric CSR: row_ptr has n+1 offsets, col holds 2m neighbour ids,
+ * both directions of every edge, neighbours in any order within a row.  Self-loops,
+ * duplicate entries, asymmetric entries and out-of-range ids are rejected with an error;
+ * the library never reads outside [row_ptr[0], row_ptr[n]) of col.
+ *
+ * Edge numbering for per-edge output: edge k is the k-th CSR entry (i, col[j]) with
+ * i < col[j], scanning rows i = 0..n-1 and, within a row, entries in storage order.
+ *
+ * Per-edge output layout: 13 slots x m, slot-major (slot s of edge k at s*m + k),
+ * uint64, slots in graphlet order
+ *   0 H3 triangle        1 H4 2-star          2 H5 3-node-1-edge     3 H7 4-clique
+ *   4 H8 chordal-cycle   5 H9 tailed-triangle 6 H10 4-cycle          7 H11 3-star
+ *   8 H12 4-path         9 H13 4-node-1-tri  10 H14 4-node-2-edge   11 H15 4-node-2-star
+ *  12 H16 4-node-1-edge
+ * (H1 is the edge itself; H2, H6 and H17 contain no edge.)
+ *
+ * Global output: 17 unsigned 128-bit counts X1..X17 (index i-1), exact for any n < 2^31.
+ *
+ * Ownership: every buffer passed in belongs to the caller and is never freed or retained
+ * past the call.  Library state lives only in the handles created here and is released
+ * by the matching destroy call.  Errors are returned as negative glt_status values; the
+ * message is available from glt_last_error() until the next call on the same handle.
+ * On error, outputs are unspecified.  No C++ exception crosses this interface.
+ *
+ * Streams: "stream" is a hipStream_t (passed as void*); NULL selects the handle's own
+ * stream.  Every call in this header returns only after its results are complete and
+ * visible to the host (global counts) and on the device (per-edge counts).
+ */
+#ifndef GLT_H
+#define GLT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { uint64_t lo, hi; } glt_u128;
+
+typedef struct {
+    int64_t n;                 /* vertices, isolated ones included; 0 <= n < 2^31        */
+    int64_t m;                 /* undirected edges; row_ptr[n] - row_ptr[0] == 2*m        */
+    const void* row_ptr;       /* int32[n+1] or int64[n+1] (see offsets_are_64bit)        */
+    const int32_t* col;        /* int32[2m] neighbour ids                                 */
+    int32_t offsets_are_64bit; /* 0: row_ptr is int32, 1: int64                           */
+    int32_t on_device;         /* 1: row_ptr/col/out_per_edge are device pointers (hipMalloc
+                                  or a torch CUDA tensor on the handle's device); 0: host  */
+} glt_csr;
+
+typedef enum {
+    GLT_OK = 0,
+    GLT_E_INVALID_ARG = -1,    /* null pointer, bad size, offsets not monotone, id out of range */
+    GLT_E_NOT_SIMPLE = -2,     /* self-loop or duplicate entry                                  */
+    GLT_E_NOT_SYMMETRIC = -3,  /* an entry (i,j) without its (j,i)                              */
+    GLT_E_OOM = -4,            /* device workspace would exceed the handle's HBM budget         */
+    GLT_E_DEVICE = -5,         /* a HIP runtime error                                           */
+    GLT_E_UNSUPPORTED = -6,    /* n >= 2^31 or 2m >= 2^31                                       */
+    GLT_E_INTERNAL = -7        /* an internal consistency check failed (a library bug)          */
+} glt_status;
+
+enum {
+    GLT_GLOBAL = 1,            /* compute X1..X17 (always done; the flag is accepted for clarity) */
+    GLT_PER_EDGE = 2           /* also write the 13 per-edge counts                               */
+};
+
+typedef struct glt_ctx glt_ctx;
+
+/* Create a handle bound to HIP device `device`.  hbm_budget_bytes caps the device
+ * workspace the handle may hold (0 = no cap beyond the device's free memory). */
+glt_status glt_create(int device, size_t hbm_budget_bytes, glt_ctx** out);
+
+/* Release the handle and all device memory it holds.  NULL is ignored. */
+void glt_destroy(glt_ctx* ctx);
+
+/* Message of the last error on this handle ("" if none).  Valid until the next call. */
+const char* glt_last_error(const glt_ctx* ctx);
+
+/* Library version string. */
+const char* glt_version(void);
+
+/*
+ * Count graphlets of one graph (Problem 1 of Section 3 for the global counts, the
+ * edge-centric decomposition of Sections 4.3-4.6 for the per-edge counts).
+ *   g             graph (see conventions); validated before any count is computed
+ *   flags         GLT_GLOBAL | optional GLT_PER_EDGE
+ *   out_global    host array of 17 glt_u128 (X1..X17); required
+ *   out_per_edge  NULL, or uint64[13*m] (device memory if g->on_device, else host);
+ *                 required when GLT_PER_EDGE is set
+ *   stream        hipStream_t or NULL
+ * Errors: GLT_E_INVALID_ARG, GLT_E_NOT_SIMPLE, GLT_E_NOT_SYMMETRIC, GLT_E_OOM,
+ *         GLT_E_DEVICE, GLT_E_UNSUPPORTED, GLT_E_INTERNAL.
+ */
+glt_status glt_count(glt_ctx* ctx, const glt_csr* g, uint32_t flags,
+                     glt_u128 out_global[17], uint64_t* out_per_edge, void* stream);
+
+/*
+ * Timing breakdown of the last successful glt_count on this handle, in milliseconds
+ * measured with HIP events on the call's stream: [0] validation + preprocessing (degree
+ * order, sorted oriented CSR), [1] triangle / 4-clique pass, [2] per-edge gather pass,
+ * [3] 4-cycle wedge pass, [4] combine + reduction.  Returns the number of entries
+ * written (<= cap).
+ */
+int glt_last_timing(const glt_ctx* ctx, float* ms, int cap);
+
+/*
+ * Work counters of the last successful glt_count on this handle: [0] n, [1] m,
+ * [2] wedges y - w - x with x ranked above y and w (the 4-cycle pass's unit of work),
+ * [3] out-list entries scanned by the triangle pass (sum over oriented edges (a,b) of
+ * |N+(b)|).  Returns the number of entries written (<= cap).  Used to state the
+ * algorithmic bytes of each pass.
+ */
+int glt_last_work(const glt_ctx* ctx, uint64_t* out, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GLT_H */

@@ -1,0 +1,199 @@
+"""Exact 2-, 3- and 4-node graphlet counts on an AMD MI355X (libglt, HIP for gfx950).
+
+Thin ctypes binding over the C ABI declared in ``include/glt.h``: every count is computed by
+the library's kernels; this module only marshals pointers and sizes.  PyTorch provides
+device memory and streams.  There is no CPU fallback: if ``libglt.so`` is missing the
+import of the binding raises.
+
+Example::
+
+    import torch, paper_1608_05138_amd as glt
+    ctx = glt.Context()
+    X, per_edge = ctx.count(row_ptr_cuda, col_cuda, per_edge=True)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libglt.so")
+
+GRAPHLETS = ["edge", "2-node-indep", "triangle", "2-star", "3-node-1-edge", "3-node-indep",
+             "4-clique", "chordal-cycle", "tailed-triangle", "4-cycle", "3-star", "4-path",
+             "4-node-1-triangle", "4-node-2-edge", "4-node-2-star", "4-node-1-edge",
+             "4-node-indep"]
+# graphlet ids (1-based, Table 1) of the 13 per-edge slots
+EDGE_SLOTS = [3, 4, 5, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16]
+
+GLT_GLOBAL = 1
+GLT_PER_EDGE = 2
+
+STATUS = {0: "GLT_OK", -1: "GLT_E_INVALID_ARG", -2: "GLT_E_NOT_SIMPLE", -3: "GLT_E_NOT_SYMMETRIC",
+          -4: "GLT_E_OOM", -5: "GLT_E_DEVICE", -6: "GLT_E_UNSUPPORTED", -7: "GLT_E_INTERNAL"}
+
+# the C-ABI symbols declared in include/glt.h
+EXPORTS = ["glt_create", "glt_destroy", "glt_last_error", "glt_version", "glt_count",
+           "glt_last_timing", "glt_last_work"]
+
+
+class GltError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class glt_u128(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+
+class glt_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("offsets_are_64bit", ctypes.c_int32),
+                ("on_device", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libglt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libglt.so not found at {path}; build it with "
+                           "`python paper_1608_05138_amd/build.py` (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.glt_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(P)]
+    lib.glt_create.restype = ctypes.c_int
+    lib.glt_destroy.argtypes = [P]
+    lib.glt_destroy.restype = None
+    lib.glt_last_error.argtypes = [P]
+    lib.glt_last_error.restype = ctypes.c_char_p
+    lib.glt_version.argtypes = []
+    lib.glt_version.restype = ctypes.c_char_p
+    lib.glt_count.argtypes = [P, ctypes.POINTER(glt_csr), ctypes.c_uint32,
+                              ctypes.POINTER(glt_u128), P, P]
+    lib.glt_count.restype = ctypes.c_int
+    lib.glt_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
+    lib.glt_last_timing.restype = ctypes.c_int
+    lib.glt_last_work.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
+    lib.glt_last_work.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+class Context:
+    """A libglt handle bound to one HIP device."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self._lib = load_library()
+        h = ctypes.c_void_p()
+        rc = self._lib.glt_create(device, hbm_budget_bytes, ctypes.byref(h))
+        if rc != 0:
+            raise GltError(rc, "glt_create failed")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.glt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return self._lib.glt_last_error(self._h).decode()
+
+    def last_timing(self):
+        buf = (ctypes.c_float * 5)()
+        k = self._lib.glt_last_timing(self._h, buf, 5)
+        return list(buf[:k])
+
+    def last_work(self):
+        """dict(n, m, wedges, tri_list_entries) of the last count."""
+        buf = (ctypes.c_uint64 * 4)()
+        self._lib.glt_last_work(self._h, buf, 4)
+        return {"n": buf[0], "m": buf[1], "wedges": buf[2], "tri_list_entries": buf[3]}
+
+    def count(self, row_ptr, col, n: int | None = None, per_edge: bool = False, out=None,
+              stream=None):
+        """Count graphlets of the CSR graph (row_ptr, col).
+
+        Device inputs: torch CUDA tensors (int32/int64 row_ptr, int32 col); per-edge output
+        is a torch int64 tensor [13, m] on the same device (values are exact uint64 counts,
+        all below 2^63).  Host inputs: numpy arrays; per-edge output is a numpy uint64 array.
+        Returns (X, per_edge_or_None) with X a list of 17 Python ints (X1..X17).
+        """
+        dev = _is_torch(row_ptr) and row_ptr.is_cuda
+        if dev:
+            import torch
+            if not (_is_torch(col) and col.is_cuda):
+                raise ValueError("row_ptr and col must both be device tensors")
+            if row_ptr.dtype not in (torch.int32, torch.int64) or col.dtype != torch.int32:
+                raise ValueError("row_ptr int32/int64, col int32 expected")
+            row_ptr = row_ptr.contiguous()
+            col = col.contiguous()
+            nn = row_ptr.numel() - 1 if n is None else n
+            m = col.numel() // 2
+            rp_ptr, col_ptr = row_ptr.data_ptr(), col.data_ptr()
+            rp64 = row_ptr.dtype == torch.int64
+            if per_edge:
+                if out is None:
+                    out = torch.empty((13, m), dtype=torch.int64, device=row_ptr.device)
+                out_ptr = out.data_ptr()
+            else:
+                out_ptr = None
+            if stream is None:
+                stream = torch.cuda.current_stream(row_ptr.device).cuda_stream
+        else:
+            row_ptr = np.ascontiguousarray(row_ptr)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            if row_ptr.dtype not in (np.int32, np.int64):
+                row_ptr = row_ptr.astype(np.int64)
+            nn = row_ptr.size - 1 if n is None else n
+            m = col.size // 2
+            rp_ptr, col_ptr = row_ptr.ctypes.data, col.ctypes.data
+            rp64 = row_ptr.dtype == np.int64
+            if per_edge:
+                if out is None:
+                    out = np.zeros((13, m), dtype=np.uint64)
+                out_ptr = out.ctypes.data
+            else:
+                out_ptr = None
+        g = glt_csr(nn, m, rp_ptr, col_ptr, 1 if rp64 else 0, 1 if dev else 0)
+        X = (glt_u128 * 17)()
+        flags = GLT_GLOBAL | (GLT_PER_EDGE if per_edge else 0)
+        rc = self._lib.glt_count(self._h, ctypes.byref(g), flags, X,
+                                 ctypes.c_void_p(out_ptr) if out_ptr else None,
+                                 ctypes.c_void_p(stream) if stream else None)
+        if rc != 0:
+            raise GltError(rc, self.last_error())
+        return [int(x.lo) | (int(x.hi) << 64) for x in X], (out if per_edge else None)
+
+
+_default = {}
+
+
+def count(row_ptr, col, n=None, per_edge=False, device=0):
+    """Convenience wrapper with a cached per-device Context."""
+    ctx = _default.get(device)
+    if ctx is None:
+        ctx = _default[device] = Context(device)
+    return ctx.count(row_ptr, col, n=n, per_edge=per_edge)
+
+
+def version() -> str:
+    return load_library().glt_version().decode()

@@ -1,0 +1,366 @@
+// api.hip -- the C ABI of libglt: handles, workspace, validation, the exact combination of
+// the unrestricted counts into global frequencies (Section 4.6).
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "../../include/glt.h"
+#include "glt_internal.h"
+
+typedef __int128 i128;
+typedef unsigned __int128 u128;
+
+int glt_combine_blocks(int m);
+int glt_max_out_degree();
+int glt_wedge_table();
+int glt_wave_table();
+
+struct glt_ctx {
+    int device = 0;
+    size_t budget = 0;
+    hipStream_t stream = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    std::string err;
+    float timing[5] = {0, 0, 0, 0, 0};
+    hipEvent_t ev[6] = {};
+    u64* hbuf = nullptr;   // pinned host buffer for small read-backs
+    int wedge_wave_max = 0;
+    int wedge_limit = 0;
+    uint64_t work[4] = {0, 0, 0, 0};   // n, m, wedges, triangle-pass list entries
+};
+
+#define GLT_VERSION "glt 0.1 (gfx950)"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kGScratchWords = 8 << 20;   // 32 MiB of global bitmap rows
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <typename T>
+    T* take(int64_t count) {
+        off = (off + kAlign - 1) / kAlign * kAlign;
+        T* p = (T*)(base ? base + off : nullptr);
+        off += (size_t)(count > 0 ? count : 1) * sizeof(T);
+        return p;
+    }
+};
+
+// Lays out every array of one graph's workspace (also used with base == nullptr to size).
+size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, Dev& d, void** st_rp,
+             int** st_col, u64** st_out) {
+    Carver c(base);
+    const int64_t S = 2 * (int64_t)m;
+    const int64_t big = S > n ? S : n;
+    d.n = n; d.m = m; d.S = (int)S;
+    d.err = c.take<int>(4);
+    d.counts = c.take<int>(TB_N + WB_N + TB_N);
+    d.work = c.take<u64>(2);
+    d.final_sums = c.take<u64>(2 * 13 + NSUMS);
+    d.deg = c.take<int>(n);
+    d.order = c.take<int>(n);
+    d.rank = c.take<int>(n);
+    d.ndeg = c.take<int>(n);
+    d.nrp = c.take<int>(n + 1);
+    d.dlo = c.take<int>(n);
+    d.optr = c.take<int>(n + 1);
+    d.ncol = c.take<int>(S);
+    d.ocol = c.take<int>(m);
+    d.s2k = c.take<int>(S);
+    d.eid2k = c.take<int>(m);
+    d.acc = c.take<EdgeAcc>(m);
+    d.tri = c.take<u64>(n);
+    d.sdeg = c.take<u64>(n);
+    d.tlist = c.take<int>((int64_t)TB_N * n);
+    d.wlist = c.take<int>((int64_t)WB_N * n);
+    d.nsum_slots = glt_combine_blocks(m > 0 ? m : 1);
+    d.sums = c.take<u64>((int64_t)d.nsum_slots * 13 * 2);
+    d.gscratch_words = kGScratchWords;
+    d.gscratch = c.take<u32>(kGScratchWords);
+    d.key0 = c.take<u64>(big);
+    d.key1 = c.take<u64>(big);
+    d.val0 = c.take<u32>(big);
+    d.val1 = c.take<u32>(big);
+    d.upx = c.take<u32>(S + 1);
+    const int64_t rsc = rs_counts_elems(big);
+    d.rs_counts = c.take<u32>(rsc);
+    d.rs_tmp = c.take<u32>(scan_tmp_elems(rsc > big ? rsc : big));
+    d.itmp = c.take<int>(scan_tmp_elems(S + n + 1) + n + 1);
+    d.ltmp = nullptr;
+    *st_rp = host_in ? (void*)c.take<char>((int64_t)(n + 1) * (rp64 ? 8 : 4)) : nullptr;
+    *st_col = host_in ? c.take<int>(S) : nullptr;
+    *st_out = host_out ? c.take<u64>(13 * (int64_t)m) : nullptr;
+    return c.off + kAlign;
+}
+
+glt_status fail(glt_ctx* ctx, glt_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return s;
+}
+
+#define HIPCHK(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(ctx, GLT_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_));       \
+    } while (0)
+
+i128 ch2(i128 x) { return x < 2 ? 0 : x * (x - 1) / 2; }
+i128 ch3(i128 x) { return x < 3 ? 0 : x * (x - 1) * (x - 2) / 6; }
+i128 ch4(i128 x) { return x < 4 ? 0 : x * (x - 1) / 2 * (x - 2) * (x - 3) / 12; }
+
+// Global frequencies from the unrestricted counts (Section 4.6, with C9 = sum |T|(|S_u|+|S_v|)
+// and X11 from C11).  Returns false if a division that must be exact is not, or a count
+// is negative: both indicate a library bug.
+bool globals(int64_t n, int64_t m, const i128 C[17], i128 k4, i128 nc4, bool per_edge, i128 X[18],
+             std::string& why) {
+    auto exact = [&](i128 num, int den, i128& dst, const char* name) {
+        if (num < 0 || num % den != 0) { why = std::string("inexact ") + name; return false; }
+        dst = num / den;
+        return true;
+    };
+    X[1] = m;
+    X[2] = ch2(n) - m;
+    if (!exact(C[3], 3, X[3], "X3")) return false;
+    if (!exact(C[4], 2, X[4], "X4")) return false;
+    X[5] = C[5];
+    X[6] = ch3(n) - X[3] - X[4] - X[5];
+    X[7] = k4;
+    if (per_edge && C[7] != 6 * k4) { why = "4-clique totals disagree"; return false; }
+    X[8] = C[8] - 6 * X[7];
+    if (!exact(C[9] - 4 * X[8], 2, X[9], "X9")) return false;
+    X[10] = nc4 - X[8] - 3 * X[7];   // non-induced 4-cycles minus those inside diamonds and 4-cliques
+    if (per_edge && C[10] != 4 * X[10]) { why = "4-cycle totals disagree"; return false; }
+    if (!exact(C[11] - X[9], 3, X[11], "X11")) return false;
+    X[12] = C[12] - 4 * X[10];
+    if (!exact(C[13] - X[9], 3, X[13], "X13")) return false;
+    if (!exact(C[14] - 6 * X[7] - 4 * X[8] - 2 * X[9] - 4 * X[10] - 2 * X[12], 2, X[14], "X14")) return false;
+    if (!exact(C[15] - 2 * X[12], 2, X[15], "X15")) return false;
+    X[16] = C[16] - 2 * X[14];
+    i128 s = 0;
+    for (int i = 7; i <= 16; i++) s += X[i];
+    X[17] = ch4(n) - s;
+    for (int i = 1; i <= 17; i++)
+        if (X[i] < 0) { why = "negative global count"; return false; }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* glt_version(void) { return GLT_VERSION; }
+
+glt_status glt_create(int device, size_t hbm_budget_bytes, glt_ctx** out) {
+    glt_ctx* ctx = nullptr;
+    if (!out) return GLT_E_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return GLT_E_INVALID_ARG;
+    ctx = new (std::nothrow) glt_ctx();
+    if (!ctx) return GLT_E_OOM;
+    ctx->device = device;
+    ctx->budget = hbm_budget_bytes;
+    // work-split thresholds; the environment may lower them (used by tests to force the
+    // workgroup path and range splitting on small graphs)
+    ctx->wedge_wave_max = glt_wave_table() / 2;
+    ctx->wedge_limit = glt_wedge_table() / 2;
+    if (const char* e = getenv("GLT_WEDGE_WAVE_MAX")) {
+        int v = atoi(e);
+        if (v >= 0 && v < ctx->wedge_wave_max) ctx->wedge_wave_max = v;
+    }
+    if (const char* e = getenv("GLT_WEDGE_RANGE_LIMIT")) {
+        int v = atoi(e);
+        if (v >= 1 && v < ctx->wedge_limit) ctx->wedge_limit = v;
+    }
+    if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete ctx;
+        return GLT_E_DEVICE;
+    }
+    for (int i = 0; i < 6; i++)
+        if (hipEventCreate(&ctx->ev[i]) != hipSuccess) { glt_destroy(ctx); return GLT_E_DEVICE; }
+    if (hipHostMalloc((void**)&ctx->hbuf, 4096, hipHostMallocDefault) != hipSuccess) {
+        glt_destroy(ctx);
+        return GLT_E_DEVICE;
+    }
+    *out = ctx;
+    return GLT_OK;
+}
+
+void glt_destroy(glt_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    for (int i = 0; i < 6; i++)
+        if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    if (ctx->hbuf) (void)hipHostFree(ctx->hbuf);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char* glt_last_error(const glt_ctx* ctx) { return ctx ? ctx->err.c_str() : "null handle"; }
+
+int glt_last_work(const glt_ctx* ctx, uint64_t* out, int cap) {
+    if (!ctx || !out) return 0;
+    int k = cap < 4 ? cap : 4;
+    for (int i = 0; i < k; i++) out[i] = ctx->work[i];
+    return k;
+}
+
+int glt_last_timing(const glt_ctx* ctx, float* ms, int cap) {
+    if (!ctx || !ms) return 0;
+    int k = cap < 5 ? cap : 5;
+    for (int i = 0; i < k; i++) ms[i] = ctx->timing[i];
+    return k;
+}
+
+glt_status glt_count(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 out_global[17],
+                     uint64_t* out_per_edge, void* stream_) {
+    if (!ctx) return GLT_E_INVALID_ARG;
+    ctx->err.clear();
+    if (!g || !out_global) return fail(ctx, GLT_E_INVALID_ARG, "null graph or output");
+    const bool per_edge = (flags & GLT_PER_EDGE) != 0;
+    if (flags & ~(uint32_t)(GLT_GLOBAL | GLT_PER_EDGE)) return fail(ctx, GLT_E_INVALID_ARG, "unknown flags");
+    if (g->n < 0 || g->m < 0) return fail(ctx, GLT_E_INVALID_ARG, "negative size");
+    if (g->n >= ((int64_t)1 << 31) || 2 * g->m >= ((int64_t)1 << 31))
+        return fail(ctx, GLT_E_UNSUPPORTED, "n or 2m does not fit 31 bits");
+    if (!g->row_ptr || (g->m > 0 && !g->col)) return fail(ctx, GLT_E_INVALID_ARG, "null row_ptr or col");
+    if (per_edge && g->m > 0 && !out_per_edge) return fail(ctx, GLT_E_INVALID_ARG, "per-edge output missing");
+    const int n = (int)g->n, m = (int)g->m;
+    const int64_t S = 2 * (int64_t)m;
+    const int rp64 = g->offsets_are_64bit ? 1 : 0;
+    const bool host_in = !g->on_device;
+    const bool host_out = per_edge && !g->on_device && m > 0;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = stream_ ? (hipStream_t)stream_ : ctx->stream;
+
+    Dev d;
+    void* st_rp; int* st_col; u64* st_out;
+    const size_t need = carve(nullptr, n, m, rp64, host_in, host_out, d, &st_rp, &st_col, &st_out);
+    if (ctx->budget && need > ctx->budget)
+        return fail(ctx, GLT_E_OOM, "workspace of %zu bytes exceeds the budget of %zu", need, ctx->budget);
+    if (need > ctx->ws_bytes) {
+        HIPCHK(hipStreamSynchronize(st));
+        if (ctx->ws) { (void)hipFree(ctx->ws); ctx->ws = nullptr; ctx->ws_bytes = 0; }
+        if (hipMalloc(&ctx->ws, need) != hipSuccess) {
+            ctx->ws = nullptr;
+            (void)hipGetLastError();
+            return fail(ctx, GLT_E_OOM, "hipMalloc of %zu bytes failed", need);
+        }
+        ctx->ws_bytes = need;
+    }
+    carve(ctx->ws, n, m, rp64, host_in, host_out, d, &st_rp, &st_col, &st_out);
+    d.wedge_wave_max = ctx->wedge_wave_max;
+    d.wedge_limit = ctx->wedge_limit;
+
+    const void* rp = g->row_ptr;
+    const int* col = g->col;
+    if (host_in) {
+        HIPCHK(hipMemcpyAsync(st_rp, g->row_ptr, (size_t)(n + 1) * (rp64 ? 8 : 4), hipMemcpyHostToDevice, st));
+        if (S > 0) HIPCHK(hipMemcpyAsync(st_col, g->col, (size_t)S * 4, hipMemcpyHostToDevice, st));
+        rp = st_rp;
+        col = st_col;
+    }
+    u64* pe_dev = per_edge ? (host_out ? st_out : (u64*)out_per_edge) : nullptr;
+
+    HIPCHK(hipEventRecord(ctx->ev[0], st));
+    // offsets must start at 0 and end at 2m
+    {
+        const size_t w = rp64 ? 8 : 4;
+        HIPCHK(hipMemcpyAsync(ctx->hbuf, rp, w, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 8, (const char*)rp + (size_t)n * w, w, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        int64_t r0 = rp64 ? ((int64_t*)ctx->hbuf)[0] : ((int32_t*)ctx->hbuf)[0];
+        int64_t rn = rp64 ? ((int64_t*)ctx->hbuf)[1] : ((int32_t*)ctx->hbuf)[2];
+        if (r0 != 0 || rn != S)
+            return fail(ctx, GLT_E_INVALID_ARG, "row_ptr[0]=%lld, row_ptr[n]=%lld, expected 0 and 2m=%lld",
+                        (long long)r0, (long long)rn, (long long)S);
+    }
+    glt_prep_validate(d, rp, rp64, col, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(ctx->hbuf, d.err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int hc[TB_N + WB_N + TB_N + 1];
+    {
+        const int e = ((int*)ctx->hbuf)[0];
+        if (e & ERR_RANGE) return fail(ctx, GLT_E_INVALID_ARG, "row offsets not monotone or neighbour id out of range");
+        if (e & ERR_SELF) return fail(ctx, GLT_E_NOT_SIMPLE, "self-loop");
+        hc[0] = ((int*)ctx->hbuf)[1];   // maximum degree
+    }
+    glt_prep_build(d, rp, rp64, col, st, hc);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(ctx->hbuf, d.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 8, d.optr + n, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 16, d.counts, sizeof(int) * (TB_N + WB_N + TB_N), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    {
+        const int e = ((int*)ctx->hbuf)[0];
+        const int up = ((int*)ctx->hbuf)[2];
+        if (e & ERR_DUP) return fail(ctx, GLT_E_NOT_SIMPLE, "duplicate entry");
+        if ((e & ERR_ASYM) || up != m) return fail(ctx, GLT_E_NOT_SYMMETRIC, "adjacency is not symmetric");
+        memcpy(hc, (char*)ctx->hbuf + 16, sizeof(int) * (TB_N + WB_N + TB_N));
+        if (hc[TB_N + WB_N + TB_GLOBAL] > glt_max_out_degree())
+            return fail(ctx, GLT_E_UNSUPPORTED, "out-degree %d in the degree order exceeds %d",
+                        hc[TB_N + WB_N + TB_GLOBAL], glt_max_out_degree());
+    }
+    HIPCHK(hipEventRecord(ctx->ev[1], st));
+    glt_count_passes(d, per_edge ? 1 : 0, hc, pe_dev, st, ctx->ev + 2);
+    HIPCHK(hipGetLastError());
+    if (host_out)
+        HIPCHK(hipMemcpyAsync(out_per_edge, st_out, (size_t)13 * m * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ctx->hbuf, d.final_sums, sizeof(u64) * (2 * 13 + NSUMS), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 1024, d.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 1032, d.work, 2 * sizeof(u64), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (((int*)((char*)ctx->hbuf + 1024))[0] & ERR_NEG)
+        return fail(ctx, GLT_E_INTERNAL, "a per-edge count came out negative");
+    ctx->work[0] = (uint64_t)n;
+    ctx->work[1] = (uint64_t)m;
+    ctx->work[2] = n > 0 ? ((u64*)((char*)ctx->hbuf + 1032))[0] : 0;
+    ctx->work[3] = n > 0 ? ((u64*)((char*)ctx->hbuf + 1032))[1] : 0;
+    for (int i = 0; i < 4; i++) {
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]);
+        ctx->timing[i] = ms;
+    }
+    {
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ctx->ev[4], ctx->ev[5]);
+        ctx->timing[4] = ms;
+    }
+    // 128-bit unrestricted sums, in the order C3,C4,C5,C7,...,C16
+    static const int cidx[13] = {3, 4, 5, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16};
+    i128 C[17] = {0};
+    const u64* fs = ctx->hbuf;
+    for (int c = 0; c < 13; c++) C[cidx[c]] = (i128)(((u128)fs[2 * c + 1] << 64) | (u128)fs[2 * c]);
+    const u64* gs = fs + 2 * 13;
+    const i128 k4x3 = (i128)gs[S_K4x3];
+    if (k4x3 % 3 != 0) return fail(ctx, GLT_E_INTERNAL, "4-clique total not divisible by 3");
+    i128 X[18];
+    std::string why;
+    if (!globals(n, m, C, k4x3 / 3, (i128)gs[S_NC4], per_edge, X, why))
+        return fail(ctx, GLT_E_INTERNAL, "global combination failed: %s", why.c_str());
+    for (int i = 0; i < 17; i++) {
+        u128 v = (u128)X[i + 1];
+        out_global[i].lo = (uint64_t)v;
+        out_global[i].hi = (uint64_t)(v >> 64);
+    }
+    return GLT_OK;
+}
+
+}  // extern "C"

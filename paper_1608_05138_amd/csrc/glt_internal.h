@@ -1,0 +1,90 @@
+// glt_internal.h -- internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "prims.h"
+
+// Error bits raised by device-side validation.
+enum {
+    ERR_RANGE = 1,       // neighbour id outside [0, n) or offsets not monotone
+    ERR_SELF = 2,        // self-loop
+    ERR_DUP = 4,         // duplicate entry
+    ERR_ASYM = 8,        // entry without its reverse
+    ERR_NEG = 16,        // a per-edge count came out negative (internal)
+};
+
+// Per oriented edge (u -> v, u before v in the degree order) accumulators; one 64-byte
+// record per edge so that the final combine reads a single line per edge.
+struct __attribute__((aligned(64))) EdgeAcc {
+    u32 t;       // triangles on the edge
+    int32_t u;   // lower-ranked endpoint (relabelled id)
+    int32_t v;   // higher-ranked endpoint (relabelled id)
+    u32 pad;
+    u64 K;       // 4-cliques on the edge (edges inside T)
+    u64 P;       // non-induced 4-cycles through the edge
+    u64 gu;      // sum over w in T of t(w,u)
+    u64 gv;      // sum over w in T of t(w,v)
+    u64 sig;     // sum over w in T of d_w
+};
+
+// Sums produced by the counting passes, all reduced to 128 bits at the end.
+// Index layout of the per-block partials and of the final reduction:
+//   0..13  : unrestricted sums C3,C4,C5,C7,C8,C9,C10,C11,C12,C13,C14,C15,C16 (13 used)
+//   14     : 3 x (number of 4-cliques), from the triangle pass
+//   15     : number of non-induced 4-cycles, from the wedge pass
+#define NSUMS 16
+enum { S_C3 = 0, S_C4, S_C5, S_C7, S_C8, S_C9, S_C10, S_C11, S_C12, S_C13, S_C14, S_C15, S_C16,
+       S_SPARE, S_K4x3, S_NC4 };
+
+// Bucket ids for the vertex work lists.
+enum { TB_WAVE = 0, TB_BLK1, TB_BLK2, TB_GLOBAL, TB_N };   // triangle / gather passes
+enum { WB_WAVE = 0, WB_BLK, WB_N };                         // wedge pass
+
+// Device pointers of one graph's workspace.
+struct Dev {
+    int n;            // vertices
+    int m;            // undirected edges
+    int S;            // 2m CSR slots
+    int* err;         // error bits
+    int* deg;         // original ids: degree
+    int* order;       // rank -> original id
+    int* rank;        // original id -> rank (relabelled id)
+    int* ndeg;        // relabelled id -> degree
+    int* nrp;         // relabelled CSR offsets [n+1]
+    int* ncol;        // relabelled CSR columns [S], ascending within a row
+    int* dlo;         // number of lower-ranked neighbours of each vertex
+    int* optr;        // oriented (upward) CSR offsets [n+1]
+    int* ocol;        // oriented CSR columns [m], ascending
+    int* s2k;         // CSR slot -> oriented edge index [S]
+    int* eid2k;       // caller edge id -> oriented edge index [m]
+    EdgeAcc* acc;     // [m]
+    u64* tri;         // triangles at each relabelled vertex [n]
+    u64* sdeg;        // sum of neighbour degrees [n]
+    int* tlist;       // triangle-pass vertex lists, TB_N segments of n
+    int* wlist;       // wedge-pass vertex lists, WB_N segments of n
+    int* counts;      // bucket counts and maxima (TB_N + WB_N + TB_N)
+    u64* work;        // work counters: [0] wedges, [1] out-list entries scanned by the triangle pass
+    u64* sums;        // per-block partial sums, NSUMS per entry
+    int nsum_slots;   // capacity of sums (entries)
+    u64* final_sums;  // 2*NSUMS u64 (lo,hi) reduced 128-bit sums
+    u32* gscratch;    // global-memory adjacency bitmaps for very high out-degree
+    int64_t gscratch_words;
+    // preprocessing scratch
+    u64* key0; u64* key1; u32* val0; u32* val1;
+    u32* upx;         // prefix of "upward" flags over the caller's slots [S+1]
+    u32* rs_counts; u32* rs_tmp;
+    int* itmp; int64_t* ltmp;
+    // tuning (defaults; overridable per handle for testing)
+    int wedge_wave_max;   // wedge-pass vertices with at most this many wedges use one wavefront
+    int wedge_limit;      // distinct tops per hash range before the range is split
+};
+
+// Host-side entry points of the device pipeline (count.hip).
+struct Timing { float ms[5]; };
+
+int glt_prep_validate(const Dev& d, const void* rp, int rp64, const int* col, hipStream_t st);
+int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipStream_t st,
+                   int* host_counts /* TB_N + WB_N + TB_N */);
+void glt_count_passes(const Dev& d, int per_edge, const int* host_counts, u64* out_pe,
+                      hipStream_t st, hipEvent_t* ev /* 4 events or null */);

@@ -1,0 +1,267 @@
+// prims.h -- device primitives for gfx950 (wave64): wave/block scans and reductions,
+// a device-wide exclusive scan, a stable LSD radix sort of (u64 key, u32 value) pairs,
+// and fill kernels.  Used by the graph preprocessing (degree order, sorted CSR).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef unsigned long long u64;
+typedef unsigned int u32;
+
+#define GLT_WAVE 64
+
+__device__ __forceinline__ int glt_lane() { return (int)__lane_id(); }
+
+// Orders LDS accesses of one wavefront: writes before the call are visible to every lane
+// of the same wavefront after it.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const int l = glt_lane();
+#pragma unroll
+    for (int d = 1; d < GLT_WAVE; d <<= 1) {
+        T o = __shfl_up(v, d, GLT_WAVE);
+        if (l >= d) v += o;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = GLT_WAVE / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, GLT_WAVE);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int d = GLT_WAVE / 2; d >= 1; d >>= 1) {
+        T o = __shfl_xor(v, d, GLT_WAVE);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Exclusive scan over a block of BLOCK threads.  lds must hold BLOCK/64 elements.  All
+// threads of the block must call it (contains __syncthreads).
+template <typename T, int BLOCK>
+__device__ __forceinline__ T block_excl_scan(T v, T* lds, T& total) {
+    const int l = glt_lane(), w = threadIdx.x / GLT_WAVE;
+    T inc = wave_incl_scan(v);
+    if (l == GLT_WAVE - 1) lds[w] = inc;
+    __syncthreads();
+    T off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < BLOCK / GLT_WAVE; i++) {
+        T s = lds[i];
+        if (i < w) off += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - v;
+}
+
+// largest i in [0, n) with a[i] <= q, assuming a[0] <= q and a ascending
+template <typename T>
+__device__ __forceinline__ int upper_idx(const T* a, int n, T q) {
+    int lo = 0, hi = n;  // invariant: a[lo] <= q, answer in [lo, hi)
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] <= q) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// first index in [lo, hi) with a[idx] >= x (hi if none)
+__device__ __forceinline__ int lower_bound_i32(const int* a, int lo, int hi, int x) {
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------------------
+// fill
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+template <typename T>
+static inline void launch_fill(T* p, int64_t n, T v, hipStream_t st) {
+    if (n <= 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+}
+
+// ---------------------------------------------------------------------------------------
+// device-wide exclusive scan (tile = 256 threads x 16 items)
+// ---------------------------------------------------------------------------------------
+#define SCAN_THREADS 256
+#define SCAN_ITEMS 16
+#define SCAN_TILE (SCAN_THREADS * SCAN_ITEMS)
+
+template <typename Tin, typename T>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tile_sums(const Tin* in, int64_t n, T* sums) {
+    __shared__ T lds[SCAN_THREADS / GLT_WAVE];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    T acc = 0;
+    for (int r = 0; r < SCAN_ITEMS; r++) {
+        int64_t i = base + r * SCAN_THREADS + threadIdx.x;
+        if (i < n) acc += (T)in[i];
+    }
+    T tot;
+    block_excl_scan<T, SCAN_THREADS>(acc, lds, tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// single block of 1024 threads: exclusive scan of nb sums in place; writes grand total
+template <typename T>
+__global__ __launch_bounds__(1024) void k_scan_sums(T* sums, int64_t nb, T* total_out) {
+    __shared__ T lds[1024 / GLT_WAVE];
+    int64_t per = (nb + 1023) / 1024;
+    int64_t b0 = (int64_t)threadIdx.x * per;
+    T acc = 0;
+    for (int64_t i = 0; i < per; i++)
+        if (b0 + i < nb) acc += sums[b0 + i];
+    T tot;
+    T off = block_excl_scan<T, 1024>(acc, lds, tot);
+    for (int64_t i = 0; i < per; i++)
+        if (b0 + i < nb) { T s = sums[b0 + i]; sums[b0 + i] = off; off += s; }
+    if (threadIdx.x == 0 && total_out) *total_out = tot;
+}
+
+template <typename Tin, typename T>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tile_apply(const Tin* in, T* out, int64_t n,
+                                                                  const T* sums) {
+    __shared__ T tile[SCAN_TILE];
+    __shared__ T lds[SCAN_THREADS / GLT_WAVE];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    for (int r = 0; r < SCAN_ITEMS; r++) {
+        int idx = r * SCAN_THREADS + threadIdx.x;
+        int64_t i = base + idx;
+        tile[idx] = (i < n) ? (T)in[i] : (T)0;
+    }
+    __syncthreads();
+    T loc[SCAN_ITEMS];
+    T acc = 0;
+    for (int r = 0; r < SCAN_ITEMS; r++) { loc[r] = tile[threadIdx.x * SCAN_ITEMS + r]; acc += loc[r]; }
+    T tot;
+    T off = block_excl_scan<T, SCAN_THREADS>(acc, lds, tot) + sums[blockIdx.x];
+    for (int r = 0; r < SCAN_ITEMS; r++) { tile[threadIdx.x * SCAN_ITEMS + r] = off; off += loc[r]; }
+    __syncthreads();
+    for (int r = 0; r < SCAN_ITEMS; r++) {
+        int idx = r * SCAN_THREADS + threadIdx.x;
+        int64_t i = base + idx;
+        if (i < n) out[i] = tile[idx];
+    }
+}
+
+// out[i] = sum_{j<i} in[i]; out may alias in; total (device) optional.  tmp holds
+// ceil(n / SCAN_TILE) elements.
+template <typename Tin, typename T>
+static inline void launch_excl_scan(const Tin* in, T* out, int64_t n, T* tmp, T* total,
+                                    hipStream_t st) {
+    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb == 0) nb = 1;
+    hipLaunchKernelGGL((k_scan_tile_sums<Tin, T>), dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, in, n, tmp);
+    hipLaunchKernelGGL((k_scan_sums<T>), dim3(1), dim3(1024), 0, st, tmp, nb, total);
+    hipLaunchKernelGGL((k_scan_tile_apply<Tin, T>), dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, in, out, n, tmp);
+}
+
+static inline int64_t scan_tmp_elems(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+// ---------------------------------------------------------------------------------------
+// stable LSD radix sort, 8-bit digits, keys u64 and values u32
+// ---------------------------------------------------------------------------------------
+#define RS_THREADS 256
+#define RS_ITEMS 16
+#define RS_TILE (RS_THREADS * RS_ITEMS)
+
+static __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const u64* keys, int64_t n, int shift,
+                                                        u32* counts, int64_t nblocks) {
+    __shared__ u32 hist[256];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; r++) {
+        int64_t i = base + r * RS_THREADS + threadIdx.x;
+        if (i < n) atomicAdd(&hist[(u32)(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
+}
+
+static __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const u64* kin, const u32* vin, u64* kout,
+                                                           u32* vout, int64_t n, int shift,
+                                                           const u32* offs, int64_t nblocks) {
+    __shared__ u32 base[256];
+    __shared__ u32 wcnt[RS_THREADS / GLT_WAVE][256];
+    const int t = threadIdx.x, lane = glt_lane(), w = t / GLT_WAVE;
+    base[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+    for (int q = 0; q < RS_THREADS / GLT_WAVE; q++) wcnt[q][t] = 0;
+    __syncthreads();
+    const u64 lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (GLT_WAVE - lane));
+    int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; r++) {
+        int64_t i = tile0 + r * RS_THREADS + t;
+        bool valid = i < n;
+        u64 k = valid ? kin[i] : 0;
+        u32 v = valid ? vin[i] : 0;
+        u32 d = (u32)(k >> shift) & 255u;
+        u64 peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            u64 bb = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        u32 rank = (u32)__popcll(peers & lt_mask);
+        if (valid && rank == 0) wcnt[w][d] = (u32)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            u32 off = base[d];
+            for (int q = 0; q < w; q++) off += wcnt[q][d];
+            kout[off + rank] = k;
+            vout[off + rank] = v;
+        }
+        __syncthreads();
+        u32 add = 0;
+        for (int q = 0; q < RS_THREADS / GLT_WAVE; q++) { add += wcnt[q][t]; wcnt[q][t] = 0; }
+        base[t] += add;
+        __syncthreads();
+    }
+}
+
+// Sorts (keys, vals) of length n (< 2^32) by key bits [0, bits).  Ping-pongs between the
+// (k0,v0) and (k1,v1) buffers; returns 0 if the result is in (k0,v0), 1 if in (k1,v1).
+// counts: 256 * ceil(n/RS_TILE) u32; tmp: scan scratch for that many elements.
+static inline int launch_radix_sort(u64* k0, u32* v0, u64* k1, u32* v1, int64_t n, int bits,
+                                    u32* counts, u32* tmp, hipStream_t st) {
+    int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+    int cur = 0;
+    if (n <= 1) return 0;
+    for (int shift = 0; shift < bits; shift += 8) {
+        u64* ki = cur ? k1 : k0; u32* vi = cur ? v1 : v0;
+        u64* ko = cur ? k0 : k1; u32* vo = cur ? v0 : v1;
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(RS_THREADS), 0, st, ki, n, shift, counts, nb);
+        launch_excl_scan<u32, u32>(counts, counts, 256 * nb, tmp, (u32*)nullptr, st);
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(RS_THREADS), 0, st, ki, vi, ko, vo, n,
+                           shift, counts, nb);
+        cur ^= 1;
+    }
+    return cur;
+}
+
+static inline int64_t rs_counts_elems(int64_t n) { return 256 * ((n + RS_TILE - 1) / RS_TILE) + 1; }

@@ -1,0 +1,298 @@
+"""GPU parity: libglt (HIP, gfx950) against the CPU oracle, element by element.
+
+Every call goes through the C ABI (ctypes binding).  Counts are integers, so the bar is
+bit-exact equality of all 17 global counts and all 13 x m per-edge counts.  Sizes span
+every work bucket of the kernels (wave and workgroup paths, LDS and global bitmap rows,
+hash-range splitting in the wedge pass) with ragged tails.
+"""
+import sys
+from math import comb
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    sys.__stderr__.write(f"[gpu-case] {msg}\n")
+    sys.__stderr__.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1608_05138_amd as glt
+    c = glt.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _oracle_built():
+    oracle.build(force=False)
+
+
+def gpu(ctx, n, rp, col, per_edge=True, device=True):
+    import torch
+    if device:
+        rpt = torch.from_numpy(np.ascontiguousarray(rp)).cuda()
+        ct = torch.from_numpy(np.ascontiguousarray(col, dtype=np.int32)).cuda()
+        X, pe = ctx.count(rpt, ct, n=n, per_edge=per_edge)
+        torch.cuda.synchronize()
+        if per_edge:
+            pe = pe.cpu().numpy().view(np.uint64)
+        return X, pe
+    return ctx.count(np.ascontiguousarray(rp), np.ascontiguousarray(col, dtype=np.int32), n=n,
+                     per_edge=per_edge)
+
+
+def check_vs_oracle(ctx, name, n, rp, col, device=True, brute=False):
+    say(f"{name} n={n} m={col.size // 2} device={device}")
+    ref = oracle.brute(n, rp, col, per_edge=True) if brute else oracle.count(n, rp, col, per_edge=True)
+    X, pe = gpu(ctx, n, rp, col, per_edge=True, device=device)
+    assert X == ref["X"], name
+    np.testing.assert_array_equal(pe, ref["per_edge"], err_msg=name)
+    Xg, _ = gpu(ctx, n, rp, col, per_edge=False, device=device)
+    assert Xg == ref["X"], name + " (global mode)"
+    return X, pe
+
+
+def _random_pairs(n, p, rng):
+    iu = np.triu_indices(n, 1)
+    keep = rng.random(iu[0].size) < p
+    return np.stack([iu[0][keep], iu[1][keep]], 1)
+
+
+def test_small_random_vs_brute(ctx):
+    rng = np.random.default_rng(101)
+    for trial in range(60):
+        n = int(rng.integers(4, 41))
+        p = float(rng.choice([0.05, 0.15, 0.3, 0.5, 0.8, 0.95]))
+        n_, (rp, col) = gg.from_pairs(n, _random_pairs(n, p, rng))
+        col = gg.shuffle_rows(rp, col, trial)
+        check_vs_oracle(ctx, f"small-{trial}", n, rp, col, device=bool(trial % 2), brute=True)
+
+
+@pytest.mark.parametrize("name,n,pairs", [
+    ("no-edges", 6, []),
+    ("single-edge", 2, [(0, 1)]),
+    ("single-edge-isolated", 9, [(3, 7)]),
+    ("triangle", 3, [(0, 1), (1, 2), (0, 2)]),
+    ("two-triangles", 6, [(0, 1), (1, 2), (0, 2), (3, 4), (4, 5), (3, 5)]),
+    ("star", 12, [(0, i) for i in range(1, 12)]),
+    ("clique-pendant", 9, [(i, j) for i in range(7) for j in range(i + 1, 7)] + [(6, 7)]),
+])
+def test_degenerate(ctx, name, n, pairs):
+    n_, (rp, col) = gg.from_pairs(n, pairs)
+    check_vs_oracle(ctx, name, n, rp, col, brute=True)
+
+
+def test_zero_vertices(ctx):
+    say("zero-vertices")
+    rp = np.zeros(1, dtype=np.int32)
+    col = np.zeros(0, dtype=np.int32)
+    X, pe = gpu(ctx, 0, rp, col, per_edge=True, device=False)
+    assert X == [0] * 17
+
+
+def test_config_er_1k(ctx):
+    n, (rp, col) = gg.config_er_1k()
+    check_vs_oracle(ctx, "er-1000-10000", n, rp, col)
+    check_vs_oracle(ctx, "er-1000-10000-host", n, rp, col, device=False)
+
+
+def test_chung_lu_medium(ctx):
+    for n, m, seed in ((5000, 60000, 7), (20000, 200000, 8), (3001, 45000, 9)):
+        rp, col = gg.chung_lu(n, m, 2.1, float(n - 1), seed)
+        check_vs_oracle(ctx, f"chung-lu-{n}-{m}", n, rp, col)
+
+
+def test_clique_on_noise(ctx):
+    # a 300-clique (out-degrees up to 299: the LDS bitmap workgroup path) on sparse noise
+    rng = np.random.default_rng(3)
+    n = 2300
+    lo, hi = gg.er_pairs(n, 6000, rng)
+    iu = np.triu_indices(300, 1)
+    a = np.concatenate([lo, iu[0]])
+    b = np.concatenate([hi, iu[1]])
+    key = np.unique(np.minimum(a, b) * n + np.maximum(a, b))
+    perm = rng.permutation(n)
+    rp, col = gg.csr_from_pairs(n, perm[key // n], perm[key % n])
+    check_vs_oracle(ctx, "clique300-noise", n, rp, col)
+
+
+def _closed_complete(n):
+    X = [0] * 17
+    X[0] = comb(n, 2); X[2] = comb(n, 3); X[6] = comb(n, 4)
+    return X
+
+
+def test_complete_graph_global_bitmap_path(ctx):
+    # K_n: out-degrees up to n-1 > 640 use the global-memory bitmap rows
+    n = 760
+    N, (rp, col) = gg.complete(n)
+    say(f"complete-{n}")
+    X, pe = gpu(ctx, N, rp, col)
+    assert X == _closed_complete(n)
+    m = col.size // 2
+    expect = np.zeros((13, m), dtype=np.uint64)
+    expect[0] = n - 2                 # triangles on each edge
+    expect[3] = comb(n - 2, 2)        # 4-cliques on each edge
+    np.testing.assert_array_equal(pe, expect)
+
+
+def test_complete_bipartite(ctx):
+    # K_{a,b}, a < b: every bottom vertex on the a-side has b wedges to each top above it
+    a, b = 300, 340
+    N, (rp, col) = gg.complete_bipartite(a, b)
+    say(f"complete-bipartite-{a}-{b}")
+    X, pe = gpu(ctx, N, rp, col)
+    nz = {1: a * b, 4: a * comb(b, 2) + b * comb(a, 2), 6: comb(a, 3) + comb(b, 3),
+          10: comb(a, 2) * comb(b, 2), 11: a * comb(b, 3) + b * comb(a, 3),
+          17: comb(a, 4) + comb(b, 4)}
+    expect = [nz.get(i, 0) for i in range(1, 18)]
+    expect[1] = comb(N, 2) - a * b
+    assert X == expect
+    m = a * b
+    want = np.zeros((13, m), dtype=np.uint64)
+    want[1] = a + b - 2                                # 2-stars on the edge
+    want[6] = (a - 1) * (b - 1)                        # 4-cycles on the edge
+    want[7] = comb(a - 1, 2) + comb(b - 1, 2)          # 3-stars on the edge
+    np.testing.assert_array_equal(pe, want)
+
+
+def test_forced_workgroup_path_and_range_splitting(monkeypatch):
+    """Wedge pass with every vertex on the workgroup path and a tiny distinct-top limit,
+    so hash ranges are split many times; results must not change."""
+    import paper_1608_05138_amd as glt
+    monkeypatch.setenv("GLT_WEDGE_WAVE_MAX", "0")
+    monkeypatch.setenv("GLT_WEDGE_RANGE_LIMIT", "3")
+    c = glt.Context(0)
+    try:
+        for n, m, seed in ((3000, 30000, 31), (800, 24000, 32)):
+            rp, col = gg.chung_lu(n, m, 2.1, float(n - 1), seed)
+            check_vs_oracle(c, f"forced-split-{n}-{m}", n, rp, col)
+        N, (rp, col) = gg.complete_bipartite(40, 47)
+        check_vs_oracle(c, "forced-split-K40,47", N, rp, col)
+    finally:
+        c.close()
+
+
+def test_modes_and_layouts_agree(ctx):
+    n = 4000
+    rp, col = gg.chung_lu(n, 40000, 2.3, float(n - 1), 21)
+    say("layouts")
+    X1, pe1 = gpu(ctx, n, rp, col)
+    X2, pe2 = gpu(ctx, n, rp.astype(np.int64), col)            # 64-bit offsets
+    assert X1 == X2
+    np.testing.assert_array_equal(pe1, pe2)
+    col3 = gg.shuffle_rows(rp, col, 5)                          # neighbour order
+    X3, pe3 = gpu(ctx, n, rp, col3)
+    assert X3 == X1
+    perm = np.random.default_rng(1).permutation(n)               # vertex names
+    n4, (rp4, col4) = gg.relabel(n, rp, col, perm)
+    X4, _ = gpu(ctx, n4, rp4, col4, per_edge=False)
+    assert X4 == X1
+    # repeated calls on one handle give identical results
+    X5, pe5 = gpu(ctx, n, rp, col)
+    assert X5 == X1
+    np.testing.assert_array_equal(pe5, pe1)
+
+
+def test_invalid_inputs_rejected(ctx):
+    import paper_1608_05138_amd as glt
+    say("invalid-inputs")
+
+    def expect(status, n, rp, col):
+        with pytest.raises(glt.GltError) as ei:
+            ctx.count(np.asarray(rp, dtype=np.int32), np.asarray(col, dtype=np.int32), n=n)
+        assert ei.value.status == status, str(ei.value)
+
+    expect(-2, 2, [0, 2, 4], [0, 1, 0, 1])              # self-loops
+    expect(-2, 3, [0, 2, 3, 4], [1, 1, 0, 0])           # duplicate entry
+    expect(-3, 3, [0, 1, 2, 2], [1, 2])                 # (0,1),(1,2) without reverses
+    expect(-1, 2, [0, 1, 2], [1, 5])                    # id out of range
+    expect(-1, 2, [0, 2, 1], [1, 0])                    # offsets not monotone
+    expect(-1, 2, [0, 1, 3], [1, 0])                    # row_ptr[n] != 2m
+    # the handle still works after errors
+    n, (rp, col) = gg.cycle(7)
+    X, _ = gpu(ctx, n, rp, col, per_edge=False)
+    assert X[0] == 7
+
+
+def test_budget_is_enforced():
+    import paper_1608_05138_amd as glt
+    say("budget")
+    c = glt.Context(0, hbm_budget_bytes=1 << 16)
+    n, (rp, col) = gg.config_er_1k()
+    with pytest.raises(glt.GltError) as ei:
+        c.count(rp, col, n=n)
+    assert ei.value.status == -4
+    c.close()
+
+
+def _edge_sum_identity(X, pe):
+    for s, gid in enumerate(oracle.EDGE_SLOTS):
+        assert int(pe[s].sum(dtype=np.uint64)) == oracle.GRAPHLET_EDGES[gid - 1] * X[gid - 1], gid
+
+
+def _sampled_edges(n, rp, col, k, seed):
+    """Edge ids of k random edges plus the edges at the highest-degree vertices."""
+    m = col.size // 2
+    rng = np.random.default_rng(seed)
+    ids = set(int(x) for x in rng.integers(0, m, size=k))
+    rp64 = np.asarray(rp, dtype=np.int64)
+    src = np.repeat(np.arange(n), np.diff(rp64))
+    up = col > src
+    eid_of_slot = np.cumsum(up) - 1
+    deg = np.diff(rp64)
+    for h in np.argsort(-deg)[:3]:
+        slots = np.arange(rp64[h], rp64[h + 1])
+        for sl in slots[:8]:
+            if up[sl]:
+                ids.add(int(eid_of_slot[sl]))
+            else:
+                # the same edge, seen from its other endpoint's row
+                other = col[sl]
+                row = np.arange(rp64[other], rp64[other + 1])
+                hit = row[col[row] == h]
+                ids.add(int(eid_of_slot[hit[0]]))
+    return np.array(sorted(ids), dtype=np.int64)
+
+
+def _full_size(ctx, name, n, rp, col, golden=None):
+    say(f"{name} per-edge")
+    X, pe = gpu(ctx, n, rp, col, per_edge=True)
+    say(f"{name} global")
+    Xg, _ = gpu(ctx, n, rp, col, per_edge=False)
+    assert Xg == X
+    _edge_sum_identity(X, pe)
+    assert X[0] == col.size // 2
+    assert sum(X[2:6]) == comb(n, 3)
+    if golden is not None:
+        assert X == golden, name + " vs stored oracle counts"
+    eids = _sampled_edges(n, rp, col, 96, 7)
+    say(f"{name} oracle on {eids.size} sampled edges")
+    ref = oracle.count_edges(n, rp, col, eids)
+    np.testing.assert_array_equal(pe[:, eids], ref)
+    return X
+
+
+def test_config_chung_lu_1m(ctx):
+    import json
+    import os
+    n, (rp, col) = gg.config_chung_lu_1m()
+    path = os.path.join(os.path.dirname(__file__), "golden", "chung_lu_1m_global.json")
+    golden = None
+    if os.path.exists(path):
+        with open(path) as f:
+            golden = [int(x) for x in json.load(f)["X"]]
+    _full_size(ctx, "chung-lu-1m-10m", n, rp, col, golden)
+
+
+def test_config_rmat_s22(ctx):
+    n, (rp, col) = gg.config_rmat_s22()
+    _full_size(ctx, "rmat-s22-ef16", n, rp, col)
