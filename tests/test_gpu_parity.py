@@ -234,9 +234,17 @@ def test_budget_is_enforced():
     c.close()
 
 
+def _exact_sum(v):
+    """Exact sum of a uint64 array as a Python int (split in 32-bit halves)."""
+    v = np.asarray(v, dtype=np.uint64)
+    hi = int((v >> np.uint64(32)).sum(dtype=np.uint64))
+    lo = int((v & np.uint64(0xFFFFFFFF)).sum(dtype=np.uint64))
+    return (hi << 32) + lo
+
+
 def _edge_sum_identity(X, pe):
     for s, gid in enumerate(oracle.EDGE_SLOTS):
-        assert int(pe[s].sum(dtype=np.uint64)) == oracle.GRAPHLET_EDGES[gid - 1] * X[gid - 1], gid
+        assert _exact_sum(pe[s]) == oracle.GRAPHLET_EDGES[gid - 1] * X[gid - 1], gid
 
 
 def _sampled_edges(n, rp, col, k, seed):
