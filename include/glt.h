@@ -106,7 +106,32 @@ glt_status glt_count(glt_ctx* ctx, const glt_csr* g, uint32_t flags,
                      glt_u128 out_global[17], uint64_t* out_per_edge, void* stream);
 
 /*
- * Timing breakdown of the last successful glt_count on this handle, in milliseconds
+ * A batch of independent graphs packed back to back.  Graph g owns packed vertices
+ * [vtx_base[g], vtx_base[g+1]) and packed column entries [slot_base[g], slot_base[g+1]);
+ * its n_g + 1 local row offsets start at row_ptr[vtx_base[g] + g] and count from 0 to
+ * 2 m_g; its column entries hold local vertex ids in [0, n_g).  Edge numbering within a
+ * graph follows the single-graph convention.
+ */
+typedef struct {
+    int64_t num_graphs;        /* B >= 0                                                     */
+    const int64_t* vtx_base;   /* host int64[B+1], vtx_base[0] == 0                          */
+    const int64_t* slot_base;  /* host int64[B+1], slot_base[0] == 0, each difference even   */
+    const int32_t* row_ptr;    /* int32[vtx_base[B] + B] local offsets                       */
+    const int32_t* col;        /* int32[slot_base[B]] local neighbour ids                    */
+    int32_t on_device;         /* 1: row_ptr and col are device pointers, 0: host            */
+} glt_batch;
+
+/*
+ * Global counts X1..X17 of every graph of a batch (Problem 1 of Section 3 per graph; the
+ * graphs are independent, so their edge neighbourhoods are processed together in one pass
+ * over the packed graph, Section 4.1).  flags must be GLT_GLOBAL.
+ *   out  host array of B*17 glt_u128, graph g's counts at out[17*g .. 17*g+16]
+ * Errors as glt_count; any invalid graph fails the whole call.
+ */
+glt_status glt_count_batch(glt_ctx* ctx, const glt_batch* b, uint32_t flags, glt_u128* out, void* stream);
+
+/*
+ * Timing breakdown of the last successful glt_count or glt_count_batch on this handle, in milliseconds
  * measured with HIP events on the call's stream: [0] validation + preprocessing (degree
  * order, sorted oriented CSR), [1] triangle / 4-clique pass, [2] per-edge gather pass,
  * [3] 4-cycle wedge pass, [4] combine + reduction.  Returns the number of entries
@@ -115,7 +140,7 @@ glt_status glt_count(glt_ctx* ctx, const glt_csr* g, uint32_t flags,
 int glt_last_timing(const glt_ctx* ctx, float* ms, int cap);
 
 /*
- * Work counters of the last successful glt_count on this handle: [0] n, [1] m,
+ * Work counters of the last successful glt_count or glt_count_batch on this handle: [0] n, [1] m,
  * [2] wedges y - w - x with x ranked above y and w (the 4-cycle pass's unit of work),
  * [3] out-list entries scanned by the triangle pass (sum over oriented edges (a,b) of
  * |N+(b)|).  Returns the number of entries written (<= cap).  Used to state the

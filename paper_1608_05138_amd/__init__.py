@@ -36,7 +36,7 @@ STATUS = {0: "GLT_OK", -1: "GLT_E_INVALID_ARG", -2: "GLT_E_NOT_SIMPLE", -3: "GLT
 
 # the C-ABI symbols declared in include/glt.h
 EXPORTS = ["glt_create", "glt_destroy", "glt_last_error", "glt_version", "glt_count",
-           "glt_last_timing", "glt_last_work"]
+           "glt_last_timing", "glt_last_work", "glt_count_batch"]
 
 
 class GltError(RuntimeError):
@@ -53,6 +53,12 @@ class glt_csr(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col", ctypes.c_void_p), ("offsets_are_64bit", ctypes.c_int32),
                 ("on_device", ctypes.c_int32)]
+
+
+class glt_batch(ctypes.Structure):
+    _fields_ = [("num_graphs", ctypes.c_int64), ("vtx_base", ctypes.c_void_p),
+                ("slot_base", ctypes.c_void_p), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("on_device", ctypes.c_int32)]
 
 
 _lib = None
@@ -83,6 +89,9 @@ def load_library(path: str = LIB_PATH):
     lib.glt_last_timing.restype = ctypes.c_int
     lib.glt_last_work.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
     lib.glt_last_work.restype = ctypes.c_int
+    lib.glt_count_batch.argtypes = [P, ctypes.POINTER(glt_batch), ctypes.c_uint32,
+                                    ctypes.POINTER(glt_u128), P]
+    lib.glt_count_batch.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -182,6 +191,41 @@ class Context:
         if rc != 0:
             raise GltError(rc, self.last_error())
         return [int(x.lo) | (int(x.hi) << 64) for x in X], (out if per_edge else None)
+
+
+    def count_batch(self, packed, stream=None):
+        """Global counts of every graph of a packed batch.
+
+        packed: dict with vtx_base, slot_base (int64 numpy, B+1), row_ptr (int32), col
+        (int32); row_ptr/col may be torch CUDA tensors (device) or numpy arrays (host).
+        Returns a list of B lists of 17 Python ints.
+        """
+        vb = np.ascontiguousarray(packed["vtx_base"], dtype=np.int64)
+        sb = np.ascontiguousarray(packed["slot_base"], dtype=np.int64)
+        rp, col = packed["row_ptr"], packed["col"]
+        B = vb.size - 1
+        dev = _is_torch(rp) and rp.is_cuda
+        if dev:
+            import torch
+            rp = rp.contiguous()
+            col = col.contiguous()
+            if rp.dtype != torch.int32 or col.dtype != torch.int32:
+                raise ValueError("int32 row_ptr and col expected")
+            rp_ptr, col_ptr = rp.data_ptr(), col.data_ptr()
+            if stream is None:
+                stream = torch.cuda.current_stream(rp.device).cuda_stream
+        else:
+            rp = np.ascontiguousarray(rp, dtype=np.int32)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            rp_ptr, col_ptr = rp.ctypes.data, col.ctypes.data
+        b = glt_batch(B, vb.ctypes.data, sb.ctypes.data, rp_ptr, col_ptr, 1 if dev else 0)
+        X = (glt_u128 * (17 * max(B, 1)))()
+        rc = self._lib.glt_count_batch(self._h, ctypes.byref(b), GLT_GLOBAL, X,
+                                       ctypes.c_void_p(stream) if stream else None)
+        if rc != 0:
+            raise GltError(rc, self.last_error())
+        flat = [int(x.lo) | (int(x.hi) << 64) for x in X]
+        return [flat[17 * g: 17 * g + 17] for g in range(B)]
 
 
 _default = {}

@@ -8,6 +8,7 @@
 
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/glt.h"
 #include "glt_internal.h"
@@ -29,18 +30,18 @@ struct glt_ctx {
     std::string err;
     float timing[5] = {0, 0, 0, 0, 0};
     hipEvent_t ev[6] = {};
-    u64* hbuf = nullptr;   // pinned host buffer for small read-backs
+    u64* hbuf = nullptr;   // pinned host buffer for small read-backs (4 KiB)
     int wedge_wave_max = 0;
     int wedge_limit = 0;
     uint64_t work[4] = {0, 0, 0, 0};   // n, m, wedges, triangle-pass list entries
 };
 
-#define GLT_VERSION "glt 0.1 (gfx950)"
+#define GLT_VERSION "glt 0.2 (gfx950)"
 
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int64_t kGScratchWords = 8 << 20;   // 32 MiB of global bitmap rows
+constexpr int64_t kGScratchWords = 8 << 20;   // 32 MiB of global bitmap rows / accumulators
 
 struct Carver {
     char* base;
@@ -55,9 +56,19 @@ struct Carver {
     }
 };
 
-// Lays out every array of one graph's workspace (also used with base == nullptr to size).
-size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, Dev& d, void** st_rp,
-             int** st_col, u64** st_out) {
+// Input-side buffers of one call besides the pipeline arrays.
+struct Staging {
+    void* rp = nullptr;     // host-copied offsets (single graph) or union offsets (batched)
+    int* col = nullptr;     // host-copied columns (single) or union columns (batched)
+    u64* out = nullptr;     // device per-edge output when the caller's is host memory
+    int* lrp = nullptr;     // batched: host-copied local offsets
+    int* lcol = nullptr;    // batched: host-copied local columns
+};
+
+// Lays out every array of one call's workspace (with base == nullptr: only sizes it).
+// ngraphs > 0 selects the batched layout (union offsets/columns and per-graph arrays).
+size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, int ngraphs,
+             int64_t local_rp_len, Dev& d, Staging& sg) {
     Carver c(base);
     const int64_t S = 2 * (int64_t)m;
     const int64_t big = S > n ? S : n;
@@ -65,7 +76,7 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, De
     d.err = c.take<int>(4);
     d.counts = c.take<int>(TB_N + WB_N + TB_N);
     d.work = c.take<u64>(2);
-    d.final_sums = c.take<u64>(2 * 13 + NSUMS);
+    d.final_sums = c.take<u64>(2 * 13);
     d.deg = c.take<int>(n);
     d.order = c.take<int>(n);
     d.rank = c.take<int>(n);
@@ -77,7 +88,14 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, De
     d.ocol = c.take<int>(m);
     d.s2k = c.take<int>(S);
     d.eid2k = c.take<int>(m);
-    d.acc = c.take<EdgeAcc>(m);
+    d.e.t = c.take<u32>(m);
+    d.e.K = c.take<u64>(m);
+    d.e.P = c.take<u64>(m);
+    d.e.gu = c.take<u64>(m);
+    d.e.gv = c.take<u64>(m);
+    d.e.sig = c.take<u64>(m);
+    d.e.u = c.take<int>(m);
+    d.wcnt = c.take<int64_t>(n);
     d.tri = c.take<u64>(n);
     d.sdeg = c.take<u64>(n);
     d.tlist = c.take<int>((int64_t)TB_N * n);
@@ -96,9 +114,28 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, De
     d.rs_tmp = c.take<u32>(scan_tmp_elems(rsc > big ? rsc : big));
     d.itmp = c.take<int>(scan_tmp_elems(S + n + 1) + n + 1);
     d.ltmp = nullptr;
-    *st_rp = host_in ? (void*)c.take<char>((int64_t)(n + 1) * (rp64 ? 8 : 4)) : nullptr;
-    *st_col = host_in ? c.take<int>(S) : nullptr;
-    *st_out = host_out ? c.take<u64>(13 * (int64_t)m) : nullptr;
+    d.ngraphs = ngraphs;
+    d.gsum = c.take<u64>((int64_t)(ngraphs > 0 ? ngraphs : 1) * NSUMS);
+    if (ngraphs > 0) {
+        d.gid = c.take<int>(n);
+        d.ngid = c.take<int>(n);
+        d.gvb = c.take<int64_t>(ngraphs + 1);
+        d.gsb = c.take<int64_t>(ngraphs + 1);
+        d.gparts = c.take<u64>((int64_t)ngraphs * 13 * 2);
+        sg.rp = c.take<int>(n + 1);
+        sg.col = c.take<int>(S);
+        sg.lrp = host_in ? c.take<int>(local_rp_len) : nullptr;
+        sg.lcol = host_in ? c.take<int>(S) : nullptr;
+        sg.out = nullptr;
+    } else {
+        d.gid = d.ngid = nullptr;
+        d.gvb = d.gsb = nullptr;
+        d.gparts = nullptr;
+        sg.rp = host_in ? (void*)c.take<char>((int64_t)(n + 1) * (rp64 ? 8 : 4)) : nullptr;
+        sg.col = host_in ? c.take<int>(S) : nullptr;
+        sg.out = host_out ? c.take<u64>(13 * (int64_t)m) : nullptr;
+        sg.lrp = sg.lcol = nullptr;
+    }
     return c.off + kAlign;
 }
 
@@ -124,8 +161,10 @@ i128 ch3(i128 x) { return x < 3 ? 0 : x * (x - 1) * (x - 2) / 6; }
 i128 ch4(i128 x) { return x < 4 ? 0 : x * (x - 1) / 2 * (x - 2) * (x - 3) / 12; }
 
 // Global frequencies from the unrestricted counts (Section 4.6, with C9 = sum |T|(|S_u|+|S_v|)
-// and X11 from C11).  Returns false if a division that must be exact is not, or a count
-// is negative: both indicate a library bug.
+// and X11 from C11).  k4 is the number of 4-cliques and nc4 the number of non-induced
+// 4-cycles (each counted once by the triangle and wedge passes).  In per-edge mode C7 and C10
+// come from the per-edge counts too and must agree.  Returns false if a division that must
+// be exact is not, or a count is negative: both indicate a library bug.
 bool globals(int64_t n, int64_t m, const i128 C[17], i128 k4, i128 nc4, bool per_edge, i128 X[18],
              std::string& why) {
     auto exact = [&](i128 num, int den, i128& dst, const char* name) {
@@ -143,7 +182,7 @@ bool globals(int64_t n, int64_t m, const i128 C[17], i128 k4, i128 nc4, bool per
     if (per_edge && C[7] != 6 * k4) { why = "4-clique totals disagree"; return false; }
     X[8] = C[8] - 6 * X[7];
     if (!exact(C[9] - 4 * X[8], 2, X[9], "X9")) return false;
-    X[10] = nc4 - X[8] - 3 * X[7];   // non-induced 4-cycles minus those inside diamonds and 4-cliques
+    X[10] = nc4 - X[8] - 3 * X[7];   // a chordal cycle holds one 4-cycle, a 4-clique three
     if (per_edge && C[10] != 4 * X[10]) { why = "4-cycle totals disagree"; return false; }
     if (!exact(C[11] - X[9], 3, X[11], "X11")) return false;
     X[12] = C[12] - 4 * X[10];
@@ -157,6 +196,86 @@ bool globals(int64_t n, int64_t m, const i128 C[17], i128 k4, i128 nc4, bool per
     for (int i = 1; i <= 17; i++)
         if (X[i] < 0) { why = "negative global count"; return false; }
     return true;
+}
+
+// The unrestricted sums C3..C16 from 13 (lo,hi) pairs in the order C3,C4,C5,C7,...,C16.
+void unpack_c(const u64* fs, i128 C[17]) {
+    static const int cidx[13] = {3, 4, 5, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16};
+    for (int i = 0; i < 17; i++) C[i] = 0;
+    for (int c = 0; c < 13; c++) C[cidx[c]] = (i128)(((u128)fs[2 * c + 1] << 64) | (u128)fs[2 * c]);
+}
+
+void store_x(const i128 X[18], glt_u128* out) {
+    for (int i = 0; i < 17; i++) {
+        u128 v = (u128)X[i + 1];
+        out[i].lo = (uint64_t)v;
+        out[i].hi = (uint64_t)(v >> 64);
+    }
+}
+
+// Grows the handle's workspace to `need` bytes (respecting the budget).
+glt_status ensure_ws(glt_ctx* ctx, size_t need, hipStream_t st) {
+    if (ctx->budget && need > ctx->budget)
+        return fail(ctx, GLT_E_OOM, "workspace of %zu bytes exceeds the budget of %zu", need, ctx->budget);
+    if (need <= ctx->ws_bytes) return GLT_OK;
+    HIPCHK(hipStreamSynchronize(st));
+    if (ctx->ws) { (void)hipFree(ctx->ws); ctx->ws = nullptr; ctx->ws_bytes = 0; }
+    if (hipMalloc(&ctx->ws, need) != hipSuccess) {
+        ctx->ws = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, GLT_E_OOM, "hipMalloc of %zu bytes failed", need);
+    }
+    ctx->ws_bytes = need;
+    return GLT_OK;
+}
+
+// Validation, preprocessing and the counting passes on a prepared CSR (rp, col) on the
+// device.  Host read-backs: validation flags after the row check and after the build.
+glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const int* col, bool per_edge,
+                        u64* pe_dev, hipStream_t st) {
+    const int n = d.n, m = d.m;
+    d.wedge_wave_max = ctx->wedge_wave_max;
+    d.wedge_limit = ctx->wedge_limit;
+    HIPCHK(hipEventRecord(ctx->ev[0], st));
+    glt_prep_validate(d, rp, rp64, col, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(ctx->hbuf, d.err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int hc[TB_N + WB_N + TB_N + 1];
+    {
+        const int e = ((int*)ctx->hbuf)[0];
+        if (e & ERR_RANGE) return fail(ctx, GLT_E_INVALID_ARG, "row offsets not monotone or neighbour id out of range");
+        if (e & ERR_SELF) return fail(ctx, GLT_E_NOT_SIMPLE, "self-loop");
+        hc[0] = ((int*)ctx->hbuf)[1];   // maximum degree
+    }
+    glt_prep_build(d, rp, rp64, col, st, hc);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(ctx->hbuf, d.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 8, d.optr + n, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 16, d.counts, sizeof(int) * (TB_N + WB_N + TB_N), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    {
+        const int e = ((int*)ctx->hbuf)[0];
+        const int up = n > 0 ? ((int*)ctx->hbuf)[2] : 0;
+        if (e & ERR_DUP) return fail(ctx, GLT_E_NOT_SIMPLE, "duplicate entry");
+        if ((e & ERR_ASYM) || up != m) return fail(ctx, GLT_E_NOT_SYMMETRIC, "adjacency is not symmetric");
+        memcpy(hc, (char*)ctx->hbuf + 16, sizeof(int) * (TB_N + WB_N + TB_N));
+        if (hc[TB_N + WB_N + TB_GLOBAL] > glt_max_out_degree())
+            return fail(ctx, GLT_E_UNSUPPORTED, "out-degree %d in the degree order exceeds %d",
+                        hc[TB_N + WB_N + TB_GLOBAL], glt_max_out_degree());
+    }
+    HIPCHK(hipEventRecord(ctx->ev[1], st));
+    glt_count_passes(d, per_edge ? 1 : 0, hc, pe_dev, st, ctx->ev + 2);
+    HIPCHK(hipGetLastError());
+    return GLT_OK;
+}
+
+void record_timing(glt_ctx* ctx) {
+    for (int i = 0; i < 5; i++) {
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]);
+        ctx->timing[i] = ms;
+    }
 }
 
 }  // namespace
@@ -250,35 +369,21 @@ glt_status glt_count(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 ou
     hipStream_t st = stream_ ? (hipStream_t)stream_ : ctx->stream;
 
     Dev d;
-    void* st_rp; int* st_col; u64* st_out;
-    const size_t need = carve(nullptr, n, m, rp64, host_in, host_out, d, &st_rp, &st_col, &st_out);
-    if (ctx->budget && need > ctx->budget)
-        return fail(ctx, GLT_E_OOM, "workspace of %zu bytes exceeds the budget of %zu", need, ctx->budget);
-    if (need > ctx->ws_bytes) {
-        HIPCHK(hipStreamSynchronize(st));
-        if (ctx->ws) { (void)hipFree(ctx->ws); ctx->ws = nullptr; ctx->ws_bytes = 0; }
-        if (hipMalloc(&ctx->ws, need) != hipSuccess) {
-            ctx->ws = nullptr;
-            (void)hipGetLastError();
-            return fail(ctx, GLT_E_OOM, "hipMalloc of %zu bytes failed", need);
-        }
-        ctx->ws_bytes = need;
-    }
-    carve(ctx->ws, n, m, rp64, host_in, host_out, d, &st_rp, &st_col, &st_out);
-    d.wedge_wave_max = ctx->wedge_wave_max;
-    d.wedge_limit = ctx->wedge_limit;
+    Staging sg;
+    const size_t need = carve(nullptr, n, m, rp64, host_in, host_out, 0, 0, d, sg);
+    glt_status rc = ensure_ws(ctx, need, st);
+    if (rc) return rc;
+    carve(ctx->ws, n, m, rp64, host_in, host_out, 0, 0, d, sg);
 
     const void* rp = g->row_ptr;
     const int* col = g->col;
     if (host_in) {
-        HIPCHK(hipMemcpyAsync(st_rp, g->row_ptr, (size_t)(n + 1) * (rp64 ? 8 : 4), hipMemcpyHostToDevice, st));
-        if (S > 0) HIPCHK(hipMemcpyAsync(st_col, g->col, (size_t)S * 4, hipMemcpyHostToDevice, st));
-        rp = st_rp;
-        col = st_col;
+        HIPCHK(hipMemcpyAsync(sg.rp, g->row_ptr, (size_t)(n + 1) * (rp64 ? 8 : 4), hipMemcpyHostToDevice, st));
+        if (S > 0) HIPCHK(hipMemcpyAsync(sg.col, g->col, (size_t)S * 4, hipMemcpyHostToDevice, st));
+        rp = sg.rp;
+        col = sg.col;
     }
-    u64* pe_dev = per_edge ? (host_out ? st_out : (u64*)out_per_edge) : nullptr;
-
-    HIPCHK(hipEventRecord(ctx->ev[0], st));
+    u64* pe_dev = per_edge ? (host_out ? sg.out : (u64*)out_per_edge) : nullptr;
     // offsets must start at 0 and end at 2m
     {
         const size_t w = rp64 ? 8 : 4;
@@ -291,39 +396,12 @@ glt_status glt_count(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 ou
             return fail(ctx, GLT_E_INVALID_ARG, "row_ptr[0]=%lld, row_ptr[n]=%lld, expected 0 and 2m=%lld",
                         (long long)r0, (long long)rn, (long long)S);
     }
-    glt_prep_validate(d, rp, rp64, col, st);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(ctx->hbuf, d.err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    int hc[TB_N + WB_N + TB_N + 1];
-    {
-        const int e = ((int*)ctx->hbuf)[0];
-        if (e & ERR_RANGE) return fail(ctx, GLT_E_INVALID_ARG, "row offsets not monotone or neighbour id out of range");
-        if (e & ERR_SELF) return fail(ctx, GLT_E_NOT_SIMPLE, "self-loop");
-        hc[0] = ((int*)ctx->hbuf)[1];   // maximum degree
-    }
-    glt_prep_build(d, rp, rp64, col, st, hc);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(ctx->hbuf, d.err, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 8, d.optr + n, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 16, d.counts, sizeof(int) * (TB_N + WB_N + TB_N), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    {
-        const int e = ((int*)ctx->hbuf)[0];
-        const int up = ((int*)ctx->hbuf)[2];
-        if (e & ERR_DUP) return fail(ctx, GLT_E_NOT_SIMPLE, "duplicate entry");
-        if ((e & ERR_ASYM) || up != m) return fail(ctx, GLT_E_NOT_SYMMETRIC, "adjacency is not symmetric");
-        memcpy(hc, (char*)ctx->hbuf + 16, sizeof(int) * (TB_N + WB_N + TB_N));
-        if (hc[TB_N + WB_N + TB_GLOBAL] > glt_max_out_degree())
-            return fail(ctx, GLT_E_UNSUPPORTED, "out-degree %d in the degree order exceeds %d",
-                        hc[TB_N + WB_N + TB_GLOBAL], glt_max_out_degree());
-    }
-    HIPCHK(hipEventRecord(ctx->ev[1], st));
-    glt_count_passes(d, per_edge ? 1 : 0, hc, pe_dev, st, ctx->ev + 2);
-    HIPCHK(hipGetLastError());
+    rc = run_pipeline(ctx, d, rp, rp64, col, per_edge, pe_dev, st);
+    if (rc) return rc;
     if (host_out)
-        HIPCHK(hipMemcpyAsync(out_per_edge, st_out, (size_t)13 * m * 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(ctx->hbuf, d.final_sums, sizeof(u64) * (2 * 13 + NSUMS), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(out_per_edge, sg.out, (size_t)13 * m * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ctx->hbuf, d.final_sums, sizeof(u64) * 2 * 13, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 512, d.gsum, sizeof(u64) * NSUMS, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 1024, d.err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 1032, d.work, 2 * sizeof(u64), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -333,32 +411,88 @@ glt_status glt_count(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 ou
     ctx->work[1] = (uint64_t)m;
     ctx->work[2] = n > 0 ? ((u64*)((char*)ctx->hbuf + 1032))[0] : 0;
     ctx->work[3] = n > 0 ? ((u64*)((char*)ctx->hbuf + 1032))[1] : 0;
-    for (int i = 0; i < 4; i++) {
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]);
-        ctx->timing[i] = ms;
-    }
-    {
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, ctx->ev[4], ctx->ev[5]);
-        ctx->timing[4] = ms;
-    }
-    // 128-bit unrestricted sums, in the order C3,C4,C5,C7,...,C16
-    static const int cidx[13] = {3, 4, 5, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16};
-    i128 C[17] = {0};
-    const u64* fs = ctx->hbuf;
-    for (int c = 0; c < 13; c++) C[cidx[c]] = (i128)(((u128)fs[2 * c + 1] << 64) | (u128)fs[2 * c]);
-    const u64* gs = fs + 2 * 13;
+    record_timing(ctx);
+    i128 C[17];
+    unpack_c(ctx->hbuf, C);
+    const u64* gs = (const u64*)((char*)ctx->hbuf + 512);
     const i128 k4x3 = (i128)gs[S_K4x3];
     if (k4x3 % 3 != 0) return fail(ctx, GLT_E_INTERNAL, "4-clique total not divisible by 3");
     i128 X[18];
     std::string why;
     if (!globals(n, m, C, k4x3 / 3, (i128)gs[S_NC4], per_edge, X, why))
         return fail(ctx, GLT_E_INTERNAL, "global combination failed: %s", why.c_str());
-    for (int i = 0; i < 17; i++) {
-        u128 v = (u128)X[i + 1];
-        out_global[i].lo = (uint64_t)v;
-        out_global[i].hi = (uint64_t)(v >> 64);
+    store_x(X, out_global);
+    return GLT_OK;
+}
+
+glt_status glt_count_batch(glt_ctx* ctx, const glt_batch* b, uint32_t flags, glt_u128* out, void* stream_) {
+    if (!ctx) return GLT_E_INVALID_ARG;
+    ctx->err.clear();
+    if (!b || (b->num_graphs > 0 && (!out || !b->vtx_base || !b->slot_base)))
+        return fail(ctx, GLT_E_INVALID_ARG, "null batch, bases or output");
+    if (flags & ~(uint32_t)GLT_GLOBAL)
+        return fail(ctx, GLT_E_INVALID_ARG, "batched counting supports GLT_GLOBAL only");
+    const int64_t B = b->num_graphs;
+    if (B < 0 || B >= ((int64_t)1 << 31)) return fail(ctx, GLT_E_INVALID_ARG, "bad number of graphs");
+    if (B == 0) return GLT_OK;
+    const int64_t* vb = b->vtx_base;
+    const int64_t* sb = b->slot_base;
+    if (vb[0] != 0 || sb[0] != 0) return fail(ctx, GLT_E_INVALID_ARG, "bases must start at 0");
+    for (int64_t g = 0; g < B; g++) {
+        if (vb[g + 1] < vb[g] || sb[g + 1] < sb[g] || ((sb[g + 1] - sb[g]) & 1))
+            return fail(ctx, GLT_E_INVALID_ARG, "graph %lld: bases not monotone or odd slot count", (long long)g);
+    }
+    const int64_t N = vb[B], S = sb[B];
+    if (N >= ((int64_t)1 << 31) || S >= ((int64_t)1 << 31))
+        return fail(ctx, GLT_E_UNSUPPORTED, "packed vertices or slots do not fit 31 bits");
+    if (!b->row_ptr || (S > 0 && !b->col)) return fail(ctx, GLT_E_INVALID_ARG, "null row_ptr or col");
+    const int n = (int)N, m = (int)(S / 2);
+    const int64_t lrp_len = N + B;
+    const bool host_in = !b->on_device;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = stream_ ? (hipStream_t)stream_ : ctx->stream;
+
+    Dev d;
+    Staging sg;
+    const size_t need = carve(nullptr, n, m, 0, host_in, false, (int)B, lrp_len, d, sg);
+    glt_status rc = ensure_ws(ctx, need, st);
+    if (rc) return rc;
+    carve(ctx->ws, n, m, 0, host_in, false, (int)B, lrp_len, d, sg);
+    const int* lrp = b->row_ptr;
+    const int* lcol = b->col;
+    if (host_in) {
+        HIPCHK(hipMemcpyAsync(sg.lrp, b->row_ptr, (size_t)lrp_len * 4, hipMemcpyHostToDevice, st));
+        if (S > 0) HIPCHK(hipMemcpyAsync(sg.lcol, b->col, (size_t)S * 4, hipMemcpyHostToDevice, st));
+        lrp = sg.lrp;
+        lcol = sg.lcol;
+    }
+    HIPCHK(hipMemcpyAsync((void*)d.gvb, vb, (size_t)(B + 1) * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync((void*)d.gsb, sb, (size_t)(B + 1) * 8, hipMemcpyHostToDevice, st));
+    glt_union_build(d, lrp, lcol, (int*)sg.rp, sg.col, st);
+    HIPCHK(hipGetLastError());
+    rc = run_pipeline(ctx, d, sg.rp, 0, sg.col, false, nullptr, st);
+    if (rc) return rc;
+    std::vector<u64> parts((size_t)B * 13 * 2), gs((size_t)B * NSUMS);
+    HIPCHK(hipMemcpyAsync(parts.data(), d.gparts, parts.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(gs.data(), d.gsum, gs.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 1032, d.work, 2 * sizeof(u64), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    ctx->work[0] = (uint64_t)n;
+    ctx->work[1] = (uint64_t)m;
+    ctx->work[2] = ((u64*)((char*)ctx->hbuf + 1032))[0];
+    ctx->work[3] = ((u64*)((char*)ctx->hbuf + 1032))[1];
+    record_timing(ctx);
+    for (int64_t g = 0; g < B; g++) {
+        i128 C[17];
+        unpack_c(&parts[(size_t)g * 26], C);
+        const i128 k4x3 = (i128)gs[(size_t)g * NSUMS + S_K4x3];
+        if (k4x3 % 3 != 0) return fail(ctx, GLT_E_INTERNAL, "graph %lld: 4-clique total not divisible by 3", (long long)g);
+        i128 X[18];
+        std::string why;
+        if (!globals(vb[g + 1] - vb[g], (sb[g + 1] - sb[g]) / 2, C, k4x3 / 3, (i128)gs[(size_t)g * NSUMS + S_NC4],
+                     false, X, why))
+            return fail(ctx, GLT_E_INTERNAL, "graph %lld: global combination failed: %s", (long long)g, why.c_str());
+        store_x(X, out + g * 17);
     }
     return GLT_OK;
 }

@@ -21,6 +21,11 @@
 //  * vertex pass: triangles at each vertex and sums of neighbour degrees.
 //  * combine: the 13 per-edge counts and the unrestricted sums C3..C16 (Section 4.5),
 //    reduced exactly in 128 bits; the global frequencies (Section 4.6) follow on the host.
+//
+// Work items inside a wavefront are enumerated as flattened (source, offset) pairs with
+// consecutive lanes on consecutive entries of one out-list, so credits to the edges of one
+// list are coalesced atomics to consecutive oriented indices, and credits that all lanes of
+// a run send to the same source are first summed with a segmented wave reduction.
 #include "glt_internal.h"
 
 #define TB_THREADS 256
@@ -31,13 +36,13 @@
 template <bool PE>
 __global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__ list, int nlist,
                                                         const int* __restrict__ optr, const int* __restrict__ ocol,
-                                                        EdgeAcc* __restrict__ acc, u64* __restrict__ gsum) {
+                                                        EdgeArrays e, u64* __restrict__ gsum,
+                                                        const int* __restrict__ ngid) {
     __shared__ int sS[4][GLT_WAVE];
     __shared__ int sOb[4][GLT_WAVE];
     __shared__ int sPre[4][GLT_WAVE];
     __shared__ u64 sM[4][GLT_WAVE];
     __shared__ u64 sK[4][GLT_WAVE];
-    __shared__ u64 sRed[4];
     const int w = threadIdx.x / GLT_WAVE, l = glt_lane();
     const int idx = blockIdx.x * 4 + w;
     const bool active = idx < nlist;
@@ -67,40 +72,40 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__
     u64 k4 = 0;
     for (int q0 = 0; q0 < total; q0 += GLT_WAVE) {
         const int q = q0 + l;
+        int i = 0x7fffffff;
+        u64 tk = 0;
         if (q < total) {
-            const int i = upper_idx(sPre[w], s, q);
-            const int p = q - sPre[w][i];
-            const int x = ocol[sOb[w][i] + p];
+            i = upper_idx(sPre[w], s, q);
+            const int k = sOb[w][i] + (q - sPre[w][i]);
+            const int x = ocol[k];
             const int j = lower_bound_i32(sS[w], i + 1, s, x);
             if (j < s && sS[w][j] == x) {
-                const u64 tk = (u64)__popcll(sM[w][i] & sM[w][j]);
-                EdgeAcc* r = &acc[sOb[w][i] + p];
-                atomicAdd(&r->t, 1u);
+                tk = (u64)__popcll(sM[w][i] & sM[w][j]);
+                atomicAdd(&e.t[k], 1u);
                 if (PE && tk) {
-                    atomicAdd(&r->K, tk);
-                    atomicAdd(&sK[w][i], tk);
+                    atomicAdd(&e.K[k], tk);
                     atomicAdd(&sK[w][j], tk);
                 }
                 k4 += tk;
             }
         }
+        if (PE) {
+            bool last;
+            const u64 ssum = seg_sum_last(tk, i, last);
+            if (last && ssum) atomicAdd(&sK[w][i], ssum);
+        }
     }
     __syncthreads();
     if (l < s) {
         const u32 tl = (u32)__popcll(sM[w][l]);
-        if (tl) atomicAdd(&acc[o0 + l].t, tl);
+        if (tl) atomicAdd(&e.t[o0 + l], tl);
         if (PE) {
             const u64 kl = sK[w][l] >> 1;
-            if (kl) atomicAdd(&acc[o0 + l].K, kl);
+            if (kl) atomicAdd(&e.K[o0 + l], kl);
         }
     }
     k4 = wave_sum(k4);
-    if (l == 0) sRed[w] = k4;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const u64 tot = sRed[0] + sRed[1] + sRed[2] + sRed[3];
-        if (tot) atomicAdd(&gsum[S_K4x3], tot);
-    }
+    if (l == 0 && k4) atomicAdd(&gsum[(ngid ? ngid[a] : 0) * NSUMS + S_K4x3], k4);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -110,8 +115,8 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__
 template <bool PE, bool GM>
 __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ list, int nlist, int smax,
                                                        const int* __restrict__ optr, const int* __restrict__ ocol,
-                                                       EdgeAcc* __restrict__ acc, u64* __restrict__ gsum,
-                                                       u32* __restrict__ gscratch) {
+                                                       EdgeArrays e, u64* __restrict__ gsum,
+                                                       u32* __restrict__ gscratch, const int* __restrict__ ngid) {
     extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
     __shared__ int sScan[TB_THREADS / GLT_WAVE];
     __shared__ u64 sRed[TB_THREADS / GLT_WAVE];
@@ -156,32 +161,41 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
     }
     __syncthreads();
     u64 k4 = 0;
-    for (int q = tid; q < total; q += TB_THREADS) {
-        const int i = upper_idx(sPre, s, q);
-        const int p = q - sPre[i];
-        const int x = ocol[sOb[i] + p];
-        const int j = lower_bound_i32(sS, i + 1, s, x);
-        if (j < s && sS[j] == x) {
-            u64 tk = 0;
-            for (int wd = 0; wd < W; wd++) tk += (u64)__popc(M[i * W + wd] & M[j * W + wd]);
-            EdgeAcc* r = &acc[sOb[i] + p];
-            atomicAdd(&r->t, 1u);
-            if (PE && tk) {
-                atomicAdd(&r->K, tk);
-                atomicAdd(&sK[i], tk);
-                atomicAdd(&sK[j], tk);
+    // every thread runs the same number of iterations so the wave reductions see full waves
+    const int rounds = (total + TB_THREADS - 1) / TB_THREADS;
+    for (int r = 0; r < rounds; r++) {
+        const int q = r * TB_THREADS + tid;
+        int i = 0x7fffffff;
+        u64 tk = 0;
+        if (q < total) {
+            i = upper_idx(sPre, s, q);
+            const int k = sOb[i] + (q - sPre[i]);
+            const int x = ocol[k];
+            const int j = lower_bound_i32(sS, i + 1, s, x);
+            if (j < s && sS[j] == x) {
+                for (int wd = 0; wd < W; wd++) tk += (u64)__popc(M[i * W + wd] & M[j * W + wd]);
+                atomicAdd(&e.t[k], 1u);
+                if (PE && tk) {
+                    atomicAdd(&e.K[k], tk);
+                    atomicAdd(&sK[j], tk);
+                }
+                k4 += tk;
             }
-            k4 += tk;
+        }
+        if (PE) {
+            bool last;
+            const u64 ssum = seg_sum_last(tk, i, last);
+            if (last && ssum) atomicAdd(&sK[i], ssum);
         }
     }
     __syncthreads();
     for (int i = tid; i < s; i += TB_THREADS) {
         u32 tl = 0;
         for (int wd = 0; wd < W; wd++) tl += (u32)__popc(M[i * W + wd]);
-        if (tl) atomicAdd(&acc[o0 + i].t, tl);
+        if (tl) atomicAdd(&e.t[o0 + i], tl);
         if (PE) {
             const u64 kl = sK[i] >> 1;
-            if (kl) atomicAdd(&acc[o0 + i].K, kl);
+            if (kl) atomicAdd(&e.K[o0 + i], kl);
         }
     }
     k4 = wave_sum(k4);
@@ -190,7 +204,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
     if (tid == 0) {
         u64 tot = 0;
         for (int q = 0; q < TB_THREADS / GLT_WAVE; q++) tot += sRed[q];
-        if (tot) atomicAdd(&gsum[S_K4x3], tot);
+        if (tot) atomicAdd(&gsum[(ngid ? ngid[a] : 0) * NSUMS + S_K4x3], tot);
     }
 }
 
@@ -204,11 +218,41 @@ static inline size_t tri_blk_lds(int smax, bool gm) {
 // ---------------------------------------------------------------------------------------
 // gather pass (per-edge mode): for every triangle (a, b_i, b_j), a lowest
 // ---------------------------------------------------------------------------------------
+// Credits of one triangle found at (i, j, edge k = (b_i, b_j)):
+//   edge (a, b_i): gu += t(a, b_j), gv += t(b_i, b_j), sig += d(b_j)   [local, run-summed]
+//   edge (a, b_j): gu += t(a, b_i), gv += t(b_i, b_j), sig += d(b_i)   [local]
+//   edge (b_i, b_j): gu += t(a, b_i), gv += t(a, b_j), sig += d(a)     [global, coalesced]
+__device__ __forceinline__ void gather_credit(bool found, int i, int j, int k, const u32* sT, const int* sD, int da,
+                                              EdgeArrays& e, u64* sGu, u64* sGv, u64* sSg) {
+    u64 taj = 0, tij = 0, dj = 0;
+    if (found) {
+        tij = e.t[k];
+        const u64 tai = sT[i];
+        taj = sT[j];
+        dj = (u64)sD[j];
+        atomicAdd(&sGu[j], tai);
+        atomicAdd(&sGv[j], tij);
+        atomicAdd(&sSg[j], (u64)sD[i]);
+        atomicAdd(&e.gu[k], tai);
+        atomicAdd(&e.gv[k], taj);
+        atomicAdd(&e.sig[k], (u64)da);
+    }
+    // lanes of a wavefront hold non-decreasing i (idle lanes a larger sentinel, zero values)
+    bool last;
+    const u64 a1 = seg_sum_last(taj, i, last);
+    const u64 a2 = seg_sum_last(tij, i, last);
+    const u64 a3 = seg_sum_last(dj, i, last);
+    if (last && (a1 | a2 | a3)) {
+        if (a1) atomicAdd(&sGu[i], a1);
+        if (a2) atomicAdd(&sGv[i], a2);
+        if (a3) atomicAdd(&sSg[i], a3);
+    }
+}
+
 __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restrict__ list, int nlist,
                                                            const int* __restrict__ optr,
                                                            const int* __restrict__ ocol,
-                                                           const int* __restrict__ ndeg,
-                                                           EdgeAcc* __restrict__ acc) {
+                                                           const int* __restrict__ ndeg, EdgeArrays e) {
     __shared__ int sS[4][GLT_WAVE];
     __shared__ int sOb[4][GLT_WAVE];
     __shared__ int sPre[4][GLT_WAVE];
@@ -229,7 +273,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
     int degb = 0;
     if (l < s) {
         b = ocol[o0 + l]; ob = optr[b]; db = optr[b + 1] - ob;
-        tb = acc[o0 + l].t; degb = ndeg[b];
+        tb = e.t[o0 + l]; degb = ndeg[b];
     }
     const int inc = wave_incl_scan(db);
     const int total = __shfl(inc, GLT_WAVE - 1, GLT_WAVE);
@@ -238,33 +282,22 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
     __syncthreads();
     for (int q0 = 0; q0 < total; q0 += GLT_WAVE) {
         const int q = q0 + l;
+        int i = 0x3fffffff, j = 0, k = 0;
+        bool found = false;
         if (q < total) {
-            const int i = upper_idx(sPre[w], s, q);
-            const int p = q - sPre[w][i];
-            const int x = ocol[sOb[w][i] + p];
-            const int j = lower_bound_i32(sS[w], i + 1, s, x);
-            if (j < s && sS[w][j] == x) {
-                EdgeAcc* r = &acc[sOb[w][i] + p];
-                const u64 tij = r->t;
-                const u64 tai = sT[w][i], taj = sT[w][j];
-                atomicAdd(&sGu[w][i], taj);
-                atomicAdd(&sGv[w][i], tij);
-                atomicAdd(&sSg[w][i], (u64)sD[w][j]);
-                atomicAdd(&sGu[w][j], tai);
-                atomicAdd(&sGv[w][j], tij);
-                atomicAdd(&sSg[w][j], (u64)sD[w][i]);
-                atomicAdd(&r->gu, tai);
-                atomicAdd(&r->gv, taj);
-                atomicAdd(&r->sig, (u64)da);
-            }
+            i = upper_idx(sPre[w], s, q);
+            k = sOb[w][i] + (q - sPre[w][i]);
+            const int x = ocol[k];
+            j = lower_bound_i32(sS[w], i + 1, s, x);
+            found = (j < s && sS[w][j] == x);
         }
+        gather_credit(found, i, j, k, sT[w], sD[w], da, e, sGu[w], sGv[w], sSg[w]);
     }
     __syncthreads();
     if (l < s) {
-        EdgeAcc* r = &acc[o0 + l];
-        if (sGu[w][l]) atomicAdd(&r->gu, sGu[w][l]);
-        if (sGv[w][l]) atomicAdd(&r->gv, sGv[w][l]);
-        if (sSg[w][l]) atomicAdd(&r->sig, sSg[w][l]);
+        if (sGu[w][l]) atomicAdd(&e.gu[o0 + l], sGu[w][l]);
+        if (sGv[w][l]) atomicAdd(&e.gv[o0 + l], sGv[w][l]);
+        if (sSg[w][l]) atomicAdd(&e.sig[o0 + l], sSg[w][l]);
     }
 }
 
@@ -272,8 +305,8 @@ template <bool GM>
 __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict__ list, int nlist, int smax,
                                                           const int* __restrict__ optr,
                                                           const int* __restrict__ ocol,
-                                                          const int* __restrict__ ndeg,
-                                                          EdgeAcc* __restrict__ acc, u64* __restrict__ gslab) {
+                                                          const int* __restrict__ ndeg, EdgeArrays e,
+                                                          u64* __restrict__ gslab) {
     extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
     __shared__ int sScan[TB_THREADS / GLT_WAVE];
     int* sS = (int*)dyn;
@@ -297,7 +330,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict
             const int b = ocol[o0 + i];
             const int ob = optr[b];
             db = optr[b + 1] - ob;
-            sS[i] = b; sOb[i] = ob; sT[i] = acc[o0 + i].t; sD[i] = ndeg[b];
+            sS[i] = b; sOb[i] = ob; sT[i] = e.t[o0 + i]; sD[i] = ndeg[b];
             sGu[i] = 0; sGv[i] = 0; sSg[i] = 0;
         }
         int tot;
@@ -307,32 +340,25 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict
     }
     const int total = carry;
     __syncthreads();
-    for (int q = tid; q < total; q += TB_THREADS) {
-        const int i = upper_idx(sPre, s, q);
-        const int p = q - sPre[i];
-        const int x = ocol[sOb[i] + p];
-        const int j = lower_bound_i32(sS, i + 1, s, x);
-        if (j < s && sS[j] == x) {
-            EdgeAcc* r = &acc[sOb[i] + p];
-            const u64 tij = r->t;
-            const u64 tai = sT[i], taj = sT[j];
-            atomicAdd(&sGu[i], taj);
-            atomicAdd(&sGv[i], tij);
-            atomicAdd(&sSg[i], (u64)sD[j]);
-            atomicAdd(&sGu[j], tai);
-            atomicAdd(&sGv[j], tij);
-            atomicAdd(&sSg[j], (u64)sD[i]);
-            atomicAdd(&r->gu, tai);
-            atomicAdd(&r->gv, taj);
-            atomicAdd(&r->sig, (u64)da);
+    const int rounds = (total + TB_THREADS - 1) / TB_THREADS;
+    for (int r = 0; r < rounds; r++) {
+        const int q = r * TB_THREADS + tid;
+        int i = 0x3fffffff, j = 0, k = 0;
+        bool found = false;
+        if (q < total) {
+            i = upper_idx(sPre, s, q);
+            k = sOb[i] + (q - sPre[i]);
+            const int x = ocol[k];
+            j = lower_bound_i32(sS, i + 1, s, x);
+            found = (j < s && sS[j] == x);
         }
+        gather_credit(found, i, j, k, sT, sD, da, e, sGu, sGv, sSg);
     }
     __syncthreads();
     for (int i = tid; i < s; i += TB_THREADS) {
-        EdgeAcc* r = &acc[o0 + i];
-        if (sGu[i]) atomicAdd(&r->gu, sGu[i]);
-        if (sGv[i]) atomicAdd(&r->gv, sGv[i]);
-        if (sSg[i]) atomicAdd(&r->sig, sSg[i]);
+        if (sGu[i]) atomicAdd(&e.gu[o0 + i], sGu[i]);
+        if (sGv[i]) atomicAdd(&e.gv[o0 + i], sGv[i]);
+        if (sSg[i]) atomicAdd(&e.sig[o0 + i], sSg[i]);
     }
 }
 
@@ -360,14 +386,13 @@ template <bool PE>
 __global__ __launch_bounds__(256) void k_wedge_wave(const int* __restrict__ list, int nlist,
                                                     const int* __restrict__ nrp, const int* __restrict__ ncol,
                                                     const int* __restrict__ optr, const int* __restrict__ ocol,
-                                                    const int* __restrict__ s2k, EdgeAcc* __restrict__ acc,
-                                                    u64* __restrict__ gsum) {
+                                                    const int* __restrict__ s2k, EdgeArrays e,
+                                                    u64* __restrict__ gsum, const int* __restrict__ ngid) {
     __shared__ int hkey[4][WW_TABLE];
     __shared__ u32 hcnt[4][WW_TABLE];
     __shared__ int sK0[4][GLT_WAVE];
     __shared__ int sPre[4][GLT_WAVE];
     __shared__ u32 sB[4][GLT_WAVE];
-    __shared__ u64 sRed[4];
     const int w4 = threadIdx.x / GLT_WAVE, l = glt_lane();
     const int idx = blockIdx.x * 4 + w4;
     const bool active = idx < nlist;
@@ -423,30 +448,27 @@ __global__ __launch_bounds__(256) void k_wedge_wave(const int* __restrict__ list
             wave_sync();
             for (int q0 = 0; q0 < tot; q0 += GLT_WAVE) {
                 const int q = q0 + l;
+                int i = 0x7fffffff;
+                u32 c = 0;
                 if (q < tot) {
-                    const int i = upper_idx(sPre[w4], nsrc, q);
+                    i = upper_idx(sPre[w4], nsrc, q);
                     const int k = sK0[w4][i] + (q - sPre[w4][i]);
                     const int x = ocol[k];
                     u32 h = hslot(x, mask);
                     while (hkey[w4][h] != x) h = (h + 1) & mask;
-                    const u32 c = hcnt[w4][h] - 1;
-                    if (c) {
-                        atomicAdd(&acc[k].P, (u64)c);
-                        atomicAdd(&sB[w4][i], c);
-                    }
+                    c = hcnt[w4][h] - 1;
+                    if (c) atomicAdd(&e.P[k], (u64)c);
                 }
+                bool last;
+                const u32 ssum = seg_sum_last(c, i, last);
+                if (last && ssum) atomicAdd(&sB[w4][i], ssum);
             }
             wave_sync();
-            if (s < re && sB[w4][l]) atomicAdd(&acc[s2k[s]].P, (u64)sB[w4][l]);
+            if (s < re && sB[w4][l]) atomicAdd(&e.P[s2k[s]], (u64)sB[w4][l]);
         }
     }
     c4 = wave_sum(c4);
-    if (l == 0) sRed[w4] = c4;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const u64 tot = sRed[0] + sRed[1] + sRed[2] + sRed[3];
-        if (tot) atomicAdd(&gsum[S_NC4], tot);
-    }
+    if (l == 0 && c4) atomicAdd(&gsum[(ngid ? ngid[y] : 0) * NSUMS + S_NC4], c4);
 }
 
 #define WB_THREADS 256
@@ -454,14 +476,15 @@ __global__ __launch_bounds__(256) void k_wedge_wave(const int* __restrict__ list
 #define WB_STACK 96
 
 // One workgroup per bottom vertex with many wedges.  The x-range [lo, hi) is split in
-// halves whenever a range holds more distinct tops than `limit` (<= WB_TABLE/2); a range is credited only
-// after its count phase completed without overflow, so no wedge is credited twice.
+// halves whenever a range holds more distinct tops than `limit` (<= WB_TABLE/2); a range is
+// credited only after its count phase completed without overflow, so no wedge is credited
+// twice.
 template <bool PE>
 __global__ __launch_bounds__(WB_THREADS) void k_wedge_blk(const int* __restrict__ list, int nlist, int n, int limit,
                                                          const int* __restrict__ nrp, const int* __restrict__ ncol,
                                                          const int* __restrict__ optr, const int* __restrict__ ocol,
-                                                         const int* __restrict__ s2k, EdgeAcc* __restrict__ acc,
-                                                         u64* __restrict__ gsum) {
+                                                         const int* __restrict__ s2k, EdgeArrays e,
+                                                         u64* __restrict__ gsum, const int* __restrict__ ngid) {
     __shared__ int hkey[WB_TABLE];
     __shared__ u32 hcnt[WB_TABLE];
     __shared__ int sK0[WB_THREADS];
@@ -551,20 +574,26 @@ __global__ __launch_bounds__(WB_THREADS) void k_wedge_blk(const int* __restrict_
                 const int nsrc = min(WB_THREADS, re - c0);
                 sK0[tid] = k0; sPre[tid] = ex; sB[tid] = 0;
                 __syncthreads();
-                for (int q = tid; q < tot; q += WB_THREADS) {
-                    const int i = upper_idx(sPre, nsrc, q);
-                    const int k = sK0[i] + (q - sPre[i]);
-                    const int x = ocol[k];
-                    u32 h = hslot(x, mask);
-                    while (hkey[h] != x) h = (h + 1) & mask;
-                    const u32 c = hcnt[h] - 1;
-                    if (c) {
-                        atomicAdd(&acc[k].P, (u64)c);
-                        atomicAdd(&sB[i], (u64)c);
+                const int rounds = (tot + WB_THREADS - 1) / WB_THREADS;
+                for (int r = 0; r < rounds; r++) {
+                    const int q = r * WB_THREADS + tid;
+                    int i = 0x7fffffff;
+                    u64 c = 0;
+                    if (q < tot) {
+                        i = upper_idx(sPre, nsrc, q);
+                        const int k = sK0[i] + (q - sPre[i]);
+                        const int x = ocol[k];
+                        u32 h = hslot(x, mask);
+                        while (hkey[h] != x) h = (h + 1) & mask;
+                        c = hcnt[h] - 1;
+                        if (c) atomicAdd(&e.P[k], c);
                     }
+                    bool last;
+                    const u64 ssum = seg_sum_last(c, i, last);
+                    if (last && ssum) atomicAdd(&sB[i], ssum);
                 }
                 __syncthreads();
-                if (s < re && sB[tid]) atomicAdd(&acc[s2k[s]].P, sB[tid]);
+                if (s < re && sB[tid]) atomicAdd(&e.P[s2k[s]], sB[tid]);
                 __syncthreads();
             }
         }
@@ -576,7 +605,7 @@ __global__ __launch_bounds__(WB_THREADS) void k_wedge_blk(const int* __restrict_
     if (tid == 0) {
         u64 tot = 0;
         for (int q = 0; q < WB_THREADS / GLT_WAVE; q++) tot += sRed[q];
-        if (tot) atomicAdd(&gsum[S_NC4], tot);
+        if (tot) atomicAdd(&gsum[(ngid ? ngid[y] : 0) * NSUMS + S_NC4], tot);
     }
 }
 
@@ -585,7 +614,7 @@ __global__ __launch_bounds__(WB_THREADS) void k_wedge_blk(const int* __restrict_
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_vertex(const int* __restrict__ nrp, const int* __restrict__ ncol,
                                                 const int* __restrict__ s2k, const int* __restrict__ ndeg,
-                                                const EdgeAcc* __restrict__ acc, int n, u64* __restrict__ tri,
+                                                const u32* __restrict__ et, int n, u64* __restrict__ tri,
                                                 u64* __restrict__ sdeg) {
     const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GLT_WAVE;
     const int l = glt_lane();
@@ -593,7 +622,7 @@ __global__ __launch_bounds__(256) void k_vertex(const int* __restrict__ nrp, con
     const int x = (int)wid;
     u64 t = 0, sd = 0;
     for (int s = nrp[x] + l; s < nrp[x + 1]; s += GLT_WAVE) {
-        t += acc[s2k[s]].t;
+        t += et[s2k[s]];
         sd += (u64)ndeg[ncol[s]];
     }
     t = wave_sum(t);
@@ -604,8 +633,6 @@ __global__ __launch_bounds__(256) void k_vertex(const int* __restrict__ nrp, con
 // ---------------------------------------------------------------------------------------
 // combine: per-edge counts and unrestricted sums, 128-bit per-block partials
 // ---------------------------------------------------------------------------------------
-struct U128 { u64 lo, hi; };
-
 __device__ __forceinline__ void add128(u64& lo, u64& hi, u64 v) {
     const u64 o = lo;
     lo += v;
@@ -628,8 +655,8 @@ __device__ __forceinline__ void wave_sum128(u64& lo, u64& hi) {
 #define NCS 13
 
 template <bool PE>
-__global__ __launch_bounds__(CB_THREADS) void k_combine(const int* __restrict__ eid2k,
-                                                        const EdgeAcc* __restrict__ acc,
+__global__ __launch_bounds__(CB_THREADS) void k_combine(const int* __restrict__ eid2k, EdgeArrays e,
+                                                        const int* __restrict__ ocol,
                                                         const int* __restrict__ ndeg, const u64* __restrict__ tri,
                                                         const u64* __restrict__ sdeg, int n, int m,
                                                         u64* __restrict__ out, u64* __restrict__ part,
@@ -644,24 +671,24 @@ __global__ __launch_bounds__(CB_THREADS) void k_combine(const int* __restrict__ 
         const int64_t eid = e0 + (int64_t)r * CB_THREADS + threadIdx.x;
         if (eid >= m) break;
         const int k = eid2k[eid];
-        const EdgeAcc rec = acc[k];
-        const int64_t du = ndeg[rec.u], dv = ndeg[rec.v];
-        const int64_t t = rec.t;
+        const int u = e.u[k], v = ocol[k];
+        const int64_t du = ndeg[u], dv = ndeg[v];
+        const int64_t t = e.t[k];
         const int64_t su = du - 1 - t, sv = dv - 1 - t;
         const int64_t D = (int64_t)n - 2 - t - su - sv;
         int64_t K = 0, Q = 0;
         if (PE) {
-            K = (int64_t)rec.K;
-            const int64_t P = (int64_t)rec.P;
-            const int64_t au = (int64_t)rec.gu - t - 2 * K;
-            const int64_t av = (int64_t)rec.gv - t - 2 * K;
+            K = (int64_t)e.K[k];
+            const int64_t P = (int64_t)e.P[k];
+            const int64_t au = (int64_t)e.gu[k] - t - 2 * K;
+            const int64_t av = (int64_t)e.gv[k] - t - 2 * K;
             Q = P - 2 * K - au - av;
-            const int64_t sigT = (int64_t)rec.sig;
-            const int64_t Esu = (int64_t)tri[rec.u] - t - K - au;
-            const int64_t Esv = (int64_t)tri[rec.v] - t - K - av;
+            const int64_t sigT = (int64_t)e.sig[k];
+            const int64_t Esu = (int64_t)tri[u] - t - K - au;
+            const int64_t Esv = (int64_t)tri[v] - t - K - av;
             const int64_t ETD = sigT - 2 * t - 2 * K - au - av;
-            const int64_t ESuD = ((int64_t)sdeg[rec.u] - dv - sigT) - su - 2 * Esu - au - Q;
-            const int64_t ESvD = ((int64_t)sdeg[rec.v] - du - sigT) - sv - 2 * Esv - av - Q;
+            const int64_t ESuD = ((int64_t)sdeg[u] - dv - sigT) - su - 2 * Esu - au - Q;
+            const int64_t ESvD = ((int64_t)sdeg[v] - du - sigT) - sv - 2 * Esv - av - Q;
             const int64_t EDD = (int64_t)m - 1 - 2 * t - su - sv -
                                 (K + Esu + Esv + au + av + Q + ETD + ESuD + ESvD);
             int64_t x[13];
@@ -751,6 +778,60 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const u64* __restrict__ pa
     }
 }
 
+// Batched global mode: one workgroup per graph over its edges (edge ids of graph g are
+// [slot_base[g]/2, slot_base[g+1]/2) in the packed numbering), unrestricted sums with the
+// graph's own n and m.
+__global__ __launch_bounds__(CB_THREADS) void k_combine_graphs(const int64_t* __restrict__ vb,
+                                                               const int64_t* __restrict__ sb,
+                                                               const int* __restrict__ eid2k, EdgeArrays e,
+                                                               const int* __restrict__ ocol,
+                                                               const int* __restrict__ ndeg,
+                                                               u64* __restrict__ gparts) {
+    __shared__ u64 red[CB_THREADS / GLT_WAVE][NCS][2];
+    const int g = blockIdx.x;
+    const int64_t ng = vb[g + 1] - vb[g];
+    const int64_t e0 = sb[g] / 2, e1 = sb[g + 1] / 2, mg = e1 - e0;
+    u64 lo[NCS], hi[NCS];
+#pragma unroll
+    for (int c = 0; c < NCS; c++) { lo[c] = 0; hi[c] = 0; }
+    for (int64_t eid = e0 + threadIdx.x; eid < e1; eid += CB_THREADS) {
+        const int k = eid2k[eid];
+        const int64_t du = ndeg[e.u[k]], dv = ndeg[ocol[k]];
+        const int64_t t = e.t[k];
+        const int64_t su = du - 1 - t, sv = dv - 1 - t;
+        const int64_t D = ng - 2 - t - su - sv;
+        add128(lo[0], hi[0], (u64)t);
+        add128(lo[1], hi[1], (u64)(su + sv));
+        add128(lo[2], hi[2], (u64)D);
+        add128(lo[4], hi[4], (u64)(t * (t - 1) / 2));
+        add128(lo[5], hi[5], (u64)(t * (su + sv)));
+        add128(lo[7], hi[7], (u64)(su * (su - 1) / 2 + sv * (sv - 1) / 2));
+        add128(lo[8], hi[8], (u64)(su * sv));
+        add128(lo[9], hi[9], (u64)(t * D));
+        add128(lo[10], hi[10], (u64)(mg - du - dv + 1));
+        add128(lo[11], hi[11], (u64)((su + sv) * D));
+        add128(lo[12], hi[12], (u64)(D * (D - 1) / 2));
+    }
+    const int w = threadIdx.x / GLT_WAVE, l = glt_lane();
+#pragma unroll
+    for (int c = 0; c < NCS; c++) {
+        wave_sum128(lo[c], hi[c]);
+        if (l == 0) { red[w][c][0] = lo[c]; red[w][c][1] = hi[c]; }
+    }
+    __syncthreads();
+    if (threadIdx.x < NCS) {
+        const int c = threadIdx.x;
+        u64 L = 0, H = 0;
+        for (int q = 0; q < CB_THREADS / GLT_WAVE; q++) {
+            const u64 o = L;
+            L += red[q][c][0];
+            H += red[q][c][1] + ((L < o) ? 1ull : 0ull);
+        }
+        gparts[((int64_t)g * NCS + c) * 2] = L;
+        gparts[((int64_t)g * NCS + c) * 2 + 1] = H;
+    }
+}
+
 static inline int combine_blocks(int m) { return (int)(((int64_t)m + CB_THREADS * CB_EPT - 1) / (CB_THREADS * CB_EPT)); }
 
 // ---------------------------------------------------------------------------------------
@@ -758,21 +839,21 @@ static inline int combine_blocks(int m) { return (int)(((int64_t)m + CB_THREADS 
 // ---------------------------------------------------------------------------------------
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
-void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st,
-                      hipEvent_t* ev) {
+void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st, hipEvent_t* ev) {
     const int n = d.n, m = d.m;
-    u64* gsum = d.final_sums + 2 * NCS;   // [S_K4x3 .. S_NC4] u64 accumulators after the 128-bit part
-    launch_fill<u64>(gsum, NSUMS, 0ull, st);
+    u64* gsum = d.gsum;                   // [graph][NSUMS]: 3 x 4-cliques and non-induced 4-cycles
+    launch_fill<u64>(gsum, (int64_t)(d.ngraphs > 0 ? d.ngraphs : 1) * NSUMS, 0ull, st);
     const int* tl = d.tlist;
     const int* cnt = hc;                  // TB_N counts, WB_N counts, TB_N maxima
+    const EdgeArrays e = d.e;
     // triangle / 4-clique pass
     if (cnt[TB_WAVE] > 0) {
         if (per_edge)
             hipLaunchKernelGGL(k_tri_wave<true>, dim3(cdiv(cnt[TB_WAVE], 4)), dim3(TB_THREADS), 0, st,
-                               tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, d.acc, gsum);
+                               tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, e, gsum, d.ngid);
         else
             hipLaunchKernelGGL(k_tri_wave<false>, dim3(cdiv(cnt[TB_WAVE], 4)), dim3(TB_THREADS), 0, st,
-                               tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, d.acc, gsum);
+                               tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, e, gsum, d.ngid);
     }
     for (int bkt = TB_BLK1; bkt <= TB_GLOBAL; bkt++) {
         const int c = cnt[bkt];
@@ -790,18 +871,18 @@ void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hi
                 const int cc = (int)((c - off < grp) ? (c - off) : grp);
                 if (per_edge)
                     hipLaunchKernelGGL((k_tri_blk<true, true>), dim3(cc), dim3(TB_THREADS), lds, st, lst + off, cc,
-                                       smax, d.optr, d.ocol, d.acc, gsum, d.gscratch);
+                                       smax, d.optr, d.ocol, e, gsum, d.gscratch, d.ngid);
                 else
                     hipLaunchKernelGGL((k_tri_blk<false, true>), dim3(cc), dim3(TB_THREADS), lds, st, lst + off, cc,
-                                       smax, d.optr, d.ocol, d.acc, gsum, d.gscratch);
+                                       smax, d.optr, d.ocol, e, gsum, d.gscratch, d.ngid);
             }
         } else {
             if (per_edge)
                 hipLaunchKernelGGL((k_tri_blk<true, false>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax,
-                                   d.optr, d.ocol, d.acc, gsum, d.gscratch);
+                                   d.optr, d.ocol, e, gsum, d.gscratch, d.ngid);
             else
                 hipLaunchKernelGGL((k_tri_blk<false, false>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax,
-                                   d.optr, d.ocol, d.acc, gsum, d.gscratch);
+                                   d.optr, d.ocol, e, gsum, d.gscratch, d.ngid);
         }
     }
     if (ev) (void)hipEventRecord(ev[0], st);
@@ -809,7 +890,7 @@ void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hi
     if (per_edge) {
         if (cnt[TB_WAVE] > 0)
             hipLaunchKernelGGL(k_gather_wave, dim3(cdiv(cnt[TB_WAVE], 4)), dim3(TB_THREADS), 0, st,
-                               tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, d.ndeg, d.acc);
+                               tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, d.ndeg, e);
         for (int bkt = TB_BLK1; bkt <= TB_GLOBAL; bkt++) {
             const int c = cnt[bkt];
             if (c <= 0) continue;
@@ -822,11 +903,11 @@ void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hi
                 for (int64_t off = 0; off < c; off += grp) {
                     const int cc = (int)((c - off < grp) ? (c - off) : grp);
                     hipLaunchKernelGGL(k_gather_blk<true>, dim3(cc), dim3(TB_THREADS), gather_blk_lds(smax, true), st,
-                                       lst + off, cc, smax, d.optr, d.ocol, d.ndeg, d.acc, (u64*)d.gscratch);
+                                       lst + off, cc, smax, d.optr, d.ocol, d.ndeg, e, (u64*)d.gscratch);
                 }
             } else {
                 hipLaunchKernelGGL(k_gather_blk<false>, dim3(c), dim3(TB_THREADS), gather_blk_lds(smax, false), st,
-                                   lst, c, smax, d.optr, d.ocol, d.ndeg, d.acc, (u64*)d.gscratch);
+                                   lst, c, smax, d.optr, d.ocol, d.ndeg, e, (u64*)d.gscratch);
             }
         }
     }
@@ -837,34 +918,37 @@ void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hi
         if (per_edge)
             hipLaunchKernelGGL(k_wedge_wave<true>, dim3(cdiv(wc[WB_WAVE], 4)), dim3(256), 0, st,
                                d.wlist + (int64_t)WB_WAVE * n, wc[WB_WAVE], d.nrp, d.ncol, d.optr, d.ocol, d.s2k,
-                               d.acc, gsum);
+                               e, gsum, d.ngid);
         else
             hipLaunchKernelGGL(k_wedge_wave<false>, dim3(cdiv(wc[WB_WAVE], 4)), dim3(256), 0, st,
                                d.wlist + (int64_t)WB_WAVE * n, wc[WB_WAVE], d.nrp, d.ncol, d.optr, d.ocol, d.s2k,
-                               d.acc, gsum);
+                               e, gsum, d.ngid);
     }
     if (wc[WB_BLK] > 0) {
         if (per_edge)
             hipLaunchKernelGGL(k_wedge_blk<true>, dim3(wc[WB_BLK]), dim3(WB_THREADS), 0, st,
-                               d.wlist + (int64_t)WB_BLK * n, wc[WB_BLK], n, d.wedge_limit, d.nrp, d.ncol, d.optr, d.ocol, d.s2k,
-                               d.acc, gsum);
+                               d.wlist + (int64_t)WB_BLK * n, wc[WB_BLK], n, d.wedge_limit, d.nrp, d.ncol, d.optr,
+                               d.ocol, d.s2k, e, gsum, d.ngid);
         else
             hipLaunchKernelGGL(k_wedge_blk<false>, dim3(wc[WB_BLK]), dim3(WB_THREADS), 0, st,
-                               d.wlist + (int64_t)WB_BLK * n, wc[WB_BLK], n, d.wedge_limit, d.nrp, d.ncol, d.optr, d.ocol, d.s2k,
-                               d.acc, gsum);
+                               d.wlist + (int64_t)WB_BLK * n, wc[WB_BLK], n, d.wedge_limit, d.nrp, d.ncol, d.optr,
+                               d.ocol, d.s2k, e, gsum, d.ngid);
     }
     if (ev) (void)hipEventRecord(ev[2], st);
     // vertex pass + combine
     if (per_edge && n > 0)
         hipLaunchKernelGGL(k_vertex, dim3(cdiv((int64_t)n * GLT_WAVE, 256)), dim3(256), 0, st, d.nrp, d.ncol,
-                           d.s2k, d.ndeg, d.acc, n, d.tri, d.sdeg);
+                           d.s2k, d.ndeg, e.t, n, d.tri, d.sdeg);
     const int nb = combine_blocks(m);
-    if (m > 0) {
+    if (d.ngraphs > 0) {
+        hipLaunchKernelGGL(k_combine_graphs, dim3(d.ngraphs), dim3(CB_THREADS), 0, st, d.gvb, d.gsb, d.eid2k, e,
+                           d.ocol, d.ndeg, d.gparts);
+    } else if (m > 0) {
         if (per_edge)
-            hipLaunchKernelGGL(k_combine<true>, dim3(nb), dim3(CB_THREADS), 0, st, d.eid2k, d.acc, d.ndeg, d.tri,
+            hipLaunchKernelGGL(k_combine<true>, dim3(nb), dim3(CB_THREADS), 0, st, d.eid2k, e, d.ocol, d.ndeg, d.tri,
                                d.sdeg, n, m, out_pe, d.sums, d.err);
         else
-            hipLaunchKernelGGL(k_combine<false>, dim3(nb), dim3(CB_THREADS), 0, st, d.eid2k, d.acc, d.ndeg, d.tri,
+            hipLaunchKernelGGL(k_combine<false>, dim3(nb), dim3(CB_THREADS), 0, st, d.eid2k, e, d.ocol, d.ndeg, d.tri,
                                d.sdeg, n, m, out_pe, d.sums, d.err);
         hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, d.sums, nb, d.final_sums);
     } else {
@@ -874,7 +958,6 @@ void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hi
 }
 
 int glt_combine_blocks(int m) { return combine_blocks(m); }
-size_t glt_tri_blk_lds_max() { return tri_blk_lds(640, false); }
 // largest out-degree the block passes accept (LDS holds 5 ints per neighbour of a)
 int glt_max_out_degree() { return 3200; }
 int glt_wedge_table() { return WB_TABLE; }

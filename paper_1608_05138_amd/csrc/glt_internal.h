@@ -14,18 +14,17 @@ enum {
     ERR_NEG = 16,        // a per-edge count came out negative (internal)
 };
 
-// Per oriented edge (u -> v, u before v in the degree order) accumulators; one 64-byte
-// record per edge so that the final combine reads a single line per edge.
-struct __attribute__((aligned(64))) EdgeAcc {
-    u32 t;       // triangles on the edge
-    int32_t u;   // lower-ranked endpoint (relabelled id)
-    int32_t v;   // higher-ranked endpoint (relabelled id)
-    u32 pad;
-    u64 K;       // 4-cliques on the edge (edges inside T)
-    u64 P;       // non-induced 4-cycles through the edge
-    u64 gu;      // sum over w in T of t(w,u)
-    u64 gv;      // sum over w in T of t(w,v)
-    u64 sig;     // sum over w in T of d_w
+// Per oriented edge (u -> v, u before v in the degree order) accumulators, one dense
+// array per quantity indexed by the oriented index k.  Credits to the out-edges of one
+// vertex land on consecutive k, so a wavefront's atomics coalesce into few cache lines.
+struct EdgeArrays {
+    u32* t;      // triangles on the edge
+    u64* K;      // 4-cliques on the edge (edges inside T)
+    u64* P;      // non-induced 4-cycles through the edge
+    u64* gu;     // sum over w in T of t(w,u)
+    u64* gv;     // sum over w in T of t(w,v)
+    u64* sig;    // sum over w in T of d_w
+    int* u;      // lower-ranked endpoint (relabelled id); the other one is ocol[k]
 };
 
 // Sums produced by the counting passes, all reduced to 128 bits at the end.
@@ -58,13 +57,14 @@ struct Dev {
     int* ocol;        // oriented CSR columns [m], ascending
     int* s2k;         // CSR slot -> oriented edge index [S]
     int* eid2k;       // caller edge id -> oriented edge index [m]
-    EdgeAcc* acc;     // [m]
+    EdgeArrays e;     // per-edge accumulators [m] each
     u64* tri;         // triangles at each relabelled vertex [n]
     u64* sdeg;        // sum of neighbour degrees [n]
     int* tlist;       // triangle-pass vertex lists, TB_N segments of n
     int* wlist;       // wedge-pass vertex lists, WB_N segments of n
     int* counts;      // bucket counts and maxima (TB_N + WB_N + TB_N)
     u64* work;        // work counters: [0] wedges, [1] out-list entries scanned by the triangle pass
+    int64_t* wcnt;    // wedges per vertex [n] (wedge-pass bucketing)
     u64* sums;        // per-block partial sums, NSUMS per entry
     int nsum_slots;   // capacity of sums (entries)
     u64* final_sums;  // 2*NSUMS u64 (lo,hi) reduced 128-bit sums
@@ -75,6 +75,14 @@ struct Dev {
     u32* upx;         // prefix of "upward" flags over the caller's slots [S+1]
     u32* rs_counts; u32* rs_tmp;
     int* itmp; int64_t* ltmp;
+    // per-graph accumulation (batched mode: the input is a disjoint union of graphs)
+    int ngraphs;          // 0 for a single graph
+    int* gid;             // original vertex -> graph (batched mode)
+    int* ngid;            // relabelled vertex -> graph (batched mode), else null
+    u64* gsum;            // [max(1, ngraphs)][NSUMS] 4-clique / 4-cycle accumulators
+    const int64_t* gvb;   // device copy of the per-graph vertex bases [ngraphs+1]
+    const int64_t* gsb;   // device copy of the per-graph slot bases [ngraphs+1]
+    u64* gparts;          // [ngraphs][13][2] per-graph unrestricted sums (128-bit)
     // tuning (defaults; overridable per handle for testing)
     int wedge_wave_max;   // wedge-pass vertices with at most this many wedges use one wavefront
     int wedge_limit;      // distinct tops per hash range before the range is split
@@ -83,6 +91,7 @@ struct Dev {
 // Host-side entry points of the device pipeline (count.hip).
 struct Timing { float ms[5]; };
 
+int glt_union_build(const Dev& d, const int* lrp, const int* lcol, int* urp, int* ucol, hipStream_t st);
 int glt_prep_validate(const Dev& d, const void* rp, int rp64, const int* col, hipStream_t st);
 int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipStream_t st,
                    int* host_counts /* TB_N + WB_N + TB_N */);

@@ -20,7 +20,7 @@ __device__ __forceinline__ int wave_or(int v) {
 template <typename RP>
 __global__ __launch_bounds__(256) void k_validate_rows(const RP* __restrict__ rp, const int* __restrict__ col,
                                                        int n, int64_t S, int* __restrict__ deg,
-                                                       int* __restrict__ err, int* __restrict__ maxdeg) {
+                                                       int* __restrict__ err) {
     const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GLT_WAVE;
     const int lane = glt_lane();
     if (wid >= n) return;
@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void k_validate_rows(const RP* __restrict__ rp
         if (lane == 0) { deg[x] = 0; atomicOr(err, ERR_RANGE); }
         return;
     }
-    if (lane == 0) { deg[x] = (int)(e - b); atomicMax(maxdeg, (int)(e - b)); }
+    if (lane == 0) deg[x] = (int)(e - b);
     int bad = 0;
     for (int64_t j = b + lane; j < e; j += GLT_WAVE) {
         int c = col[j];
@@ -41,20 +41,99 @@ __global__ __launch_bounds__(256) void k_validate_rows(const RP* __restrict__ rp
     if (lane == 0 && bad) atomicOr(err, bad);
 }
 
+// Maximum degree: one atomic per workgroup.
+__global__ __launch_bounds__(256) void k_max_deg(const int* __restrict__ deg, int n, int* __restrict__ maxdeg) {
+    __shared__ int red[256 / GLT_WAVE];
+    int v = 0;
+    for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < n; x += (int64_t)gridDim.x * 256)
+        v = max(v, deg[x]);
+    v = wave_max(v);
+    if (glt_lane() == 0) red[threadIdx.x / GLT_WAVE] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int b = 0;
+        for (int q = 0; q < 256 / GLT_WAVE; q++) b = max(b, red[q]);
+        if (b) atomicMax(maxdeg, b);
+    }
+}
+
 __global__ void k_iota_keys(const int* __restrict__ deg, int n, u64* __restrict__ keys, u32* __restrict__ vals) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) { keys[i] = (u64)(u32)deg[i]; vals[i] = (u32)i; }
 }
 
 __global__ void k_apply_order(const u32* __restrict__ sorted_ids, const int* __restrict__ deg, int n,
-                              int* __restrict__ order, int* __restrict__ rank, int* __restrict__ ndeg) {
+                              int* __restrict__ order, int* __restrict__ rank, int* __restrict__ ndeg,
+                              const int* __restrict__ gid, int* __restrict__ ngid) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         int x = (int)sorted_ids[i];
         order[i] = x;
         rank[x] = i;
         ndeg[i] = deg[x];
+        if (ngid) ngid[i] = gid[x];
     }
+}
+
+// ---------------------------------------------------------------------------------------
+// batched input: graphs packed with per-graph bases become one disjoint union
+// ---------------------------------------------------------------------------------------
+// One workgroup per graph: union offsets from the graph's local offsets, graph id per vertex.
+// Local offsets outside [0, 2 m_g] or not starting at 0 / ending at 2 m_g are flagged and
+// replaced by in-range values so later kernels stay inside the arrays.
+__global__ __launch_bounds__(256) void k_union_rows(const int64_t* __restrict__ vb, const int64_t* __restrict__ sb,
+                                                    const int* __restrict__ lrp, int* __restrict__ urp,
+                                                    int* __restrict__ gid, int* __restrict__ err) {
+    const int g = blockIdx.x;
+    const int64_t v0 = vb[g], ng = vb[g + 1] - v0;
+    const int64_t s0 = sb[g], sg = sb[g + 1] - s0;
+    const int* lr = lrp + v0 + g;
+    int bad = 0;
+    for (int64_t i = threadIdx.x; i <= ng; i += blockDim.x) {
+        int64_t o = lr[i];
+        if (o < 0 || o > sg || (i == 0 && o != 0) || (i == ng && o != sg)) {
+            bad = ERR_RANGE;
+            o = (i == ng) ? sg : 0;
+        }
+        if (i < ng) { urp[v0 + i] = (int)(s0 + o); gid[v0 + i] = g; }
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+// One wavefront per union vertex: local neighbour ids -> union ids (out-of-range local ids
+// are flagged and replaced by the vertex itself, which the self-loop check then rejects too).
+__global__ __launch_bounds__(256) void k_union_cols(const int64_t* __restrict__ vb, const int* __restrict__ urp,
+                                                    const int* __restrict__ gid, const int* __restrict__ lcol,
+                                                    int N, int64_t S, int* __restrict__ ucol, int* __restrict__ err) {
+    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GLT_WAVE;
+    const int lane = glt_lane();
+    if (wid >= N) return;
+    const int v = (int)wid;
+    const int g = gid[v];
+    const int64_t v0 = vb[g], ng = vb[g + 1] - v0;
+    int64_t b = urp[v], e = urp[v + 1];
+    if (b < 0 || e < b || e > S) {
+        if (lane == 0) atomicOr(err, ERR_RANGE);
+        return;
+    }
+    int bad = 0;
+    for (int64_t j = b + lane; j < e; j += GLT_WAVE) {
+        const int c = lcol[j];
+        if (c < 0 || c >= ng) { bad = ERR_RANGE; ucol[j] = v; }
+        else ucol[j] = (int)(v0 + c);
+    }
+    bad = wave_or(bad);
+    if (lane == 0 && bad) atomicOr(err, bad);
+}
+
+int glt_union_build(const Dev& d, const int* lrp, const int* lcol, int* urp, int* ucol, hipStream_t st) {
+    (void)hipMemsetAsync(d.err, 0, 4 * sizeof(int), st);
+    if (d.ngraphs <= 0 || d.n <= 0) return 0;
+    hipLaunchKernelGGL(k_union_rows, dim3(d.ngraphs), dim3(256), 0, st, d.gvb, d.gsb, lrp, urp, d.gid, d.err);
+    launch_fill<int>(urp + d.n, 1, d.S, st);
+    hipLaunchKernelGGL(k_union_cols, dim3((unsigned)(((int64_t)d.n * GLT_WAVE + 255) / 256)), dim3(256), 0, st,
+                       d.gvb, urp, d.gid, lcol, d.n, (int64_t)d.S, ucol, d.err);
+    return 0;
 }
 
 // One wavefront per row of the caller's CSR: emit the relabelled (src, dst) key of every
@@ -108,7 +187,7 @@ __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ nrp,
                                                     const int* __restrict__ order, const u32* __restrict__ oslot,
                                                     const u32* __restrict__ upx, int n, int m, int* __restrict__ ocol,
                                                     int* __restrict__ s2k, int* __restrict__ eid2k,
-                                                    EdgeAcc* __restrict__ acc, int* __restrict__ err) {
+                                                    EdgeArrays ea, int* __restrict__ err) {
     const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GLT_WAVE;
     const int lane = glt_lane();
     if (wid >= n) return;
@@ -125,9 +204,7 @@ __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ nrp,
         s2k[s] = k;
         const int yb = nrp[y], ye = yb + dlo[y];
         const int sp = lower_bound_i32(ncol, yb, ye, x);
-        EdgeAcc r;
-        r.t = 0; r.u = x; r.v = y; r.pad = 0; r.K = 0; r.P = 0; r.gu = 0; r.gv = 0; r.sig = 0;
-        acc[k] = r;
+        ea.t[k] = 0; ea.K[k] = 0; ea.P[k] = 0; ea.gu[k] = 0; ea.gv[k] = 0; ea.sig[k] = 0; ea.u[k] = x;
         if (sp >= ye || ncol[sp] != x) { bad |= ERR_ASYM; continue; }
         s2k[sp] = k;
         const int oy = order[y];
@@ -168,38 +245,50 @@ __global__ __launch_bounds__(256) void k_tbuckets(const int* __restrict__ optr, 
     int b = (x < n) ? tbucket(s) : -1;
     for (int q = 0; q < TB_N; q++) {
         wave_append(&counts[q], tlist + (int64_t)q * n, b == q, x);
-        if (b == q) atomicMax(&tmax[q], s);
+        const int mx = wave_max(b == q ? s : 0);
+        if (glt_lane() == 0 && mx) atomicMax(&tmax[q], mx);
     }
 }
 
 // Wedge pass: wc[y] = number of wedges y - w - x with x above both y and w
-// (w in N(y), x in N+(w), x > y).  One wavefront per vertex; buckets by wc.
-__global__ __launch_bounds__(256) void k_wbuckets(const int* __restrict__ nrp, const int* __restrict__ ncol,
-                                                  const int* __restrict__ optr, const int* __restrict__ s2k, int n,
-                                                  int wave_max, int* __restrict__ wlist, int* __restrict__ counts,
-                                                  u64* __restrict__ work) {
+// (w in N(y), x in N+(w), x > y), and the triangle pass's list length sum over the
+// out-neighbours w of y of |N+(w)|.  One wavefront per vertex; work totals reduced per
+// workgroup before one atomic.
+__global__ __launch_bounds__(256) void k_wcount(const int* __restrict__ nrp, const int* __restrict__ ncol,
+                                                const int* __restrict__ optr, const int* __restrict__ s2k, int n,
+                                                int64_t* __restrict__ wcnt, u64* __restrict__ work) {
+    __shared__ u64 red[2][256 / GLT_WAVE];
     const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GLT_WAVE;
     const int lane = glt_lane();
-    if (wid >= n) return;
-    const int y = (int)wid;
     int64_t wc = 0, ls = 0;
-    for (int s = nrp[y] + lane; s < nrp[y + 1]; s += GLT_WAVE) {
-        int w = ncol[s];
-        const int dpw = optr[w + 1] - optr[w];
-        wc += (w > y) ? dpw : (optr[w + 1] - s2k[s] - 1);
-        ls += (w > y) ? dpw : 0;
+    if (wid < n) {
+        const int y = (int)wid;
+        for (int s = nrp[y] + lane; s < nrp[y + 1]; s += GLT_WAVE) {
+            const int w = ncol[s];
+            const int dpw = optr[w + 1] - optr[w];
+            wc += (w > y) ? dpw : (optr[w + 1] - s2k[s] - 1);
+            ls += (w > y) ? dpw : 0;
+        }
+        wc = wave_sum(wc);
+        ls = wave_sum(ls);
+        if (lane == 0) wcnt[y] = wc;
     }
-    wc = wave_sum(wc);
-    ls = wave_sum(ls);
-    if (lane == 0) {
-        if (wc) atomicAdd(&work[0], (u64)wc);
-        if (ls) atomicAdd(&work[1], (u64)ls);
+    if (lane == 0) { red[0][threadIdx.x / GLT_WAVE] = (u64)wc; red[1][threadIdx.x / GLT_WAVE] = (u64)ls; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 a = 0, b = 0;
+        for (int q = 0; q < 256 / GLT_WAVE; q++) { a += red[0][q]; b += red[1][q]; }
+        if (a) atomicAdd(&work[0], a);
+        if (b) atomicAdd(&work[1], b);
     }
-    if (lane == 0 && wc > 0) {
-        int q = (wc <= wave_max) ? WB_WAVE : WB_BLK;
-        int pos = atomicAdd(&counts[q], 1);
-        wlist[(int64_t)q * n + pos] = y;
-    }
+}
+
+__global__ __launch_bounds__(256) void k_wappend(const int64_t* __restrict__ wcnt, int n, int wave_max,
+                                                 int* __restrict__ wlist, int* __restrict__ counts) {
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t wc = (y < n) ? wcnt[y] : 0;
+    const int q = (wc == 0) ? -1 : (wc <= wave_max ? WB_WAVE : WB_BLK);
+    for (int b = 0; b < WB_N; b++) wave_append(&counts[b], wlist + (int64_t)b * n, q == b, y);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -208,16 +297,19 @@ __global__ __launch_bounds__(256) void k_wbuckets(const int* __restrict__ nrp, c
 static inline unsigned nblk(int64_t items, int per) { return (unsigned)((items + per - 1) / per); }
 
 int glt_prep_validate(const Dev& d, const void* rp, int rp64, const int* col, hipStream_t st) {
-    // err[0] error bits, err[1] max degree
-    (void)hipMemsetAsync(d.err, 0, 4 * sizeof(int), st);
+    // err[0] error bits (kept from the union build in batched mode), err[1] max degree
+    if (d.ngraphs <= 0) (void)hipMemsetAsync(d.err, 0, 4 * sizeof(int), st);
     if (d.n > 0) {
         unsigned g = nblk((int64_t)d.n * GLT_WAVE, 256);
         if (rp64)
             hipLaunchKernelGGL(k_validate_rows<int64_t>, dim3(g), dim3(256), 0, st, (const int64_t*)rp, col, d.n,
-                               (int64_t)d.S, d.deg, d.err, d.err + 1);
+                               (int64_t)d.S, d.deg, d.err);
         else
             hipLaunchKernelGGL(k_validate_rows<int32_t>, dim3(g), dim3(256), 0, st, (const int32_t*)rp, col, d.n,
-                               (int64_t)d.S, d.deg, d.err, d.err + 1);
+                               (int64_t)d.S, d.deg, d.err);
+        unsigned gm = nblk(d.n, 256);
+        if (gm > 2048) gm = 2048;
+        hipLaunchKernelGGL(k_max_deg, dim3(gm), dim3(256), 0, st, d.deg, d.n, d.err + 1);
     }
     return 0;
 }
@@ -235,7 +327,7 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
     hipLaunchKernelGGL(k_iota_keys, dim3(nblk(n, 256)), dim3(256), 0, st, d.deg, n, d.key0, d.val0);
     int cur = launch_radix_sort(d.key0, d.val0, d.key1, d.val1, n, bitlen((u64)maxdeg), d.rs_counts, d.rs_tmp, st);
     hipLaunchKernelGGL(k_apply_order, dim3(nblk(n, 256)), dim3(256), 0, st, cur ? d.val1 : d.val0, d.deg, n,
-                       d.order, d.rank, d.ndeg);
+                       d.order, d.rank, d.ndeg, d.gid, d.ngid);
     // relabelled CSR offsets
     launch_excl_scan<int, int>(d.ndeg, d.nrp, n, d.itmp, d.nrp + n, st);
     // P2: sort every slot by (relabelled src, relabelled dst)
@@ -261,13 +353,15 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
     launch_excl_scan<int, int>(dplus, d.optr, n, d.itmp, d.optr + n, st);
     if (S > 0)
         hipLaunchKernelGGL(k_edge_index, dim3(nblk((int64_t)n * GLT_WAVE, 256)), dim3(256), 0, st, d.nrp, d.ncol,
-                           d.dlo, d.optr, d.order, oslot, d.upx, n, d.m, d.ocol, d.s2k, d.eid2k, d.acc, d.err);
+                           d.dlo, d.optr, d.order, oslot, d.upx, n, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.err);
     // work lists
     {
         hipLaunchKernelGGL(k_tbuckets, dim3(nblk(n, 256)), dim3(256), 0, st, d.optr, n, d.tlist, d.counts,
                            d.counts + TB_N + WB_N);
-        hipLaunchKernelGGL(k_wbuckets, dim3(nblk((int64_t)n * GLT_WAVE, 256)), dim3(256), 0, st, d.nrp, d.ncol,
-                           d.optr, d.s2k, n, d.wedge_wave_max, d.wlist, d.counts + TB_N, d.work);
+        hipLaunchKernelGGL(k_wcount, dim3(nblk((int64_t)n * GLT_WAVE, 256)), dim3(256), 0, st, d.nrp, d.ncol,
+                           d.optr, d.s2k, n, d.wcnt, d.work);
+        hipLaunchKernelGGL(k_wappend, dim3(nblk(n, 256)), dim3(256), 0, st, d.wcnt, n, d.wedge_wave_max, d.wlist,
+                           d.counts + TB_N);
     }
     return 0;
 }

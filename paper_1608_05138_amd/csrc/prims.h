@@ -48,6 +48,22 @@ __device__ __forceinline__ T wave_max(T v) {
     return v;
 }
 
+// Segmented sum over the lanes of a wavefront whose keys are non-decreasing in lane order:
+// the last lane of each run of equal keys receives the run's sum (is_last is set there).
+template <typename T>
+__device__ __forceinline__ T seg_sum_last(T v, int key, bool& is_last) {
+    const int l = glt_lane();
+#pragma unroll
+    for (int d = 1; d < GLT_WAVE; d <<= 1) {
+        const T o = __shfl_up(v, d, GLT_WAVE);
+        const int ko = __shfl_up(key, d, GLT_WAVE);
+        if (l >= d && ko == key) v += o;
+    }
+    const int kn = __shfl_down(key, 1, GLT_WAVE);
+    is_last = (l == GLT_WAVE - 1) || (kn != key);
+    return v;
+}
+
 // Exclusive scan over a block of BLOCK threads.  lds must hold BLOCK/64 elements.  All
 // threads of the block must call it (contains __syncthreads).
 template <typename T, int BLOCK>

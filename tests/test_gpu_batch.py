@@ -1,0 +1,99 @@
+"""GPU parity of the batched path: many independent graphs in one call.
+
+Each graph's 17 global counts from glt_count_batch must equal the oracle's (bit-exact)
+and the same graph's counts from a single-graph glt_count call.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    sys.__stderr__.write(f"[gpu-case] {msg}\n")
+    sys.__stderr__.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1608_05138_amd as glt
+    c = glt.Context(0)
+    yield c
+    c.close()
+
+
+def _to_device(packed):
+    import torch
+    d = dict(packed)
+    d["row_ptr"] = torch.from_numpy(packed["row_ptr"]).cuda()
+    d["col"] = torch.from_numpy(packed["col"]).cuda()
+    return d
+
+
+def _random_graph(rng):
+    n = int(rng.integers(0, 41))
+    if n < 2:
+        return n, (np.zeros(n + 1, dtype=np.int32), np.zeros(0, dtype=np.int32))
+    iu = np.triu_indices(n, 1)
+    keep = rng.random(iu[0].size) < float(rng.choice([0.0, 0.1, 0.3, 0.6, 0.9]))
+    return n, gg.csr_from_pairs(n, iu[0][keep], iu[1][keep])
+
+
+def test_batch_small_random_vs_brute(ctx):
+    rng = np.random.default_rng(7)
+    graphs = [_random_graph(rng) for _ in range(120)]
+    packed = gg.pack_batch(graphs)
+    for dev in (False, True):
+        say(f"batch-small device={dev}")
+        res = ctx.count_batch(_to_device(packed) if dev else packed)
+        assert len(res) == len(graphs)
+        for g, (n, (rp, col)) in enumerate(graphs):
+            assert res[g] == oracle.brute(n, rp, col)["X"], g
+
+
+def test_batch_mix_vs_oracle_and_alone(ctx):
+    specs = gg.batch_spec(64)
+    graphs = [gg.batch_graph(s) for s in specs]
+    packed = gg.pack_batch(graphs)
+    say(f"batch-mix-64 edges={packed['col'].size // 2}")
+    res = ctx.count_batch(_to_device(packed))
+    for g, (n, (rp, col)) in enumerate(graphs):
+        ref = oracle.count(n, rp, col)["X"]
+        assert res[g] == ref, (g, specs[g][:3])
+        alone, _ = ctx.count(rp, col, n=n)
+        assert alone == res[g], g
+
+
+def test_batch_repeat_identical(ctx):
+    specs = gg.batch_spec(40, base=12345)
+    graphs = [gg.batch_graph(s) for s in specs]
+    packed = _to_device(gg.pack_batch(graphs))
+    say("batch-repeat")
+    first = ctx.count_batch(packed)
+    for _ in range(3):
+        assert ctx.count_batch(packed) == first
+
+
+def test_batch_invalid_graph_rejected(ctx):
+    import paper_1608_05138_amd as glt
+    good = gg.cycle(6)
+    bad_rp = np.array([0, 1, 2, 2], dtype=np.int32)        # (0,1), (1,2): asymmetric
+    bad_col = np.array([1, 2], dtype=np.int32)
+    packed = gg.pack_batch([good, (3, (bad_rp, bad_col)), good])
+    say("batch-invalid")
+    with pytest.raises(glt.GltError) as ei:
+        ctx.count_batch(packed)
+    assert ei.value.status == -3
+    # local id out of range in the second graph
+    packed = gg.pack_batch([good, (3, (np.array([0, 1, 2, 2], dtype=np.int32),
+                                       np.array([1, 7], dtype=np.int32)))])
+    with pytest.raises(glt.GltError) as ei:
+        ctx.count_batch(packed)
+    assert ei.value.status == -1
+    # the handle still works
+    assert ctx.count_batch(gg.pack_batch([good]))[0][0] == 6
