@@ -48,6 +48,116 @@ def gen_batch(num_graphs):
     return specs, graphs
 
 
+def _gen_large(seed):
+    import graphgen as gg
+    n = 200_000
+    return n, gg.chung_lu(n, 2_000_000, 2.5, float(n - 1), seed)
+
+
+def bench_served(args):
+    """Open-loop Poisson request stream against the continuous-batching server, beside the
+    same stream served one request per launch (FIFO).  Latency is measured from each
+    request's scheduled arrival time."""
+    import multiprocessing as mp
+    import threading
+
+    import numpy as np
+
+    import graphgen as gg
+    import paper_1608_05138_amd as glt
+
+    procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    print(f"[bench] generating request pool: {args.pool_small} small + {args.pool_large} large",
+          file=sys.stderr, flush=True)
+    specs = gg.batch_spec(args.pool_small, base=gg.BASE_SEED + 4)
+    with mp.get_context("fork").Pool(procs) as pool:
+        small = pool.map(_gen_batch_graph, specs, chunksize=8)
+        large = pool.map(_gen_large, [gg.graph_seed(gg.BASE_SEED + 5, i) for i in range(args.pool_large)])
+    ctx = glt.Context(0)
+    alone_small = [ctx.count(rp, col, n=n)[0] for n, (rp, col) in small]
+    alone_large = [ctx.count(rp, col, n=n)[0] for n, (rp, col) in large]
+    ctx.close()
+    rng = np.random.default_rng(gg.BASE_SEED + 6)
+    arrivals = []
+    t = 0.0
+    while True:
+        t += float(rng.exponential(1.0 / args.rate))
+        if t >= args.serve_seconds:
+            break
+        if args.pool_large and rng.random() < 0.01:
+            arrivals.append((t, 1, int(rng.integers(0, args.pool_large))))
+        else:
+            arrivals.append((t, 0, int(rng.integers(0, args.pool_small))))
+
+    def serve(max_batch_graphs):
+        srv = glt.Server(0, max_batch_graphs=max_batch_graphs)
+        got = {}
+        done_flag = threading.Event()
+
+        def poller():
+            while not done_flag.is_set() or len(got) < len(arrivals):
+                for r in srv.poll(256, 2000):
+                    got[r["req_id"]] = r
+                if done_flag.is_set() and len(got) >= len(arrivals):
+                    break
+
+        th = threading.Thread(target=poller, daemon=True)
+        th.start()
+        t0 = srv.clock() + 0.2
+        sched = np.empty(len(arrivals))
+        for i, (ta, kind, idx) in enumerate(arrivals):
+            target = t0 + ta
+            while True:
+                d = target - srv.clock()
+                if d <= 0:
+                    break
+                if d > 0.0005:
+                    time.sleep(d - 0.0003)
+            n, (rp, col) = (large if kind else small)[idx]
+            rc = srv.submit(rp, col, i, n=n)
+            if rc != 0:
+                raise RuntimeError(f"submit failed: {rc}")
+            sched[i] = target
+        done_flag.set()
+        deadline = time.time() + 600
+        while len(got) < len(arrivals) and time.time() < deadline:
+            time.sleep(0.01)
+        th.join(timeout=5)
+        srv.close()
+        if len(got) < len(arrivals):
+            raise RuntimeError(f"only {len(got)} of {len(arrivals)} requests completed")
+        lat = np.array([got[i]["t_done"] - sched[i] for i in range(len(arrivals))]) * 1e3
+        bad = sum(1 for i, (ta, kind, idx) in enumerate(arrivals)
+                  if got[i]["status"] != 0 or got[i]["X"] != (alone_large if kind else alone_small)[idx])
+        span = max(got[i]["t_done"] for i in got) - t0
+        sizes = [got[i]["batch_graphs"] for i in got]
+        return {"completed": len(got), "req_per_s": len(got) / span,
+                "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                               "max": float(lat.max())},
+                "mean_batch": float(np.mean(sizes)), "mismatches_vs_alone": bad}
+
+    print(f"[bench] serving {len(arrivals)} requests over {args.serve_seconds} s (continuous batching)",
+          file=sys.stderr, flush=True)
+    cb = serve(0)
+    print(f"[bench] continuous batching: {cb}", file=sys.stderr, flush=True)
+    fifo = None
+    if not args.no_per_graph:
+        print("[bench] same stream, one request per launch", file=sys.stderr, flush=True)
+        fifo = serve(1)
+        print(f"[bench] per-request FIFO: {fifo}", file=sys.stderr, flush=True)
+    line = {
+        "metric": "served requests/sec for exact 4-node motif counts, Poisson arrivals (1 GPU); p99 latency",
+        "value": cb["req_per_s"], "unit": "requests/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "served", "rate_per_s": args.rate, "seconds": args.serve_seconds,
+                   "requests": len(arrivals), "pool": f"{args.pool_small} mixed small + {args.pool_large} "
+                   "Chung-Lu n=200000 m=2000000 (1% of arrivals)", "latency": "t_done - scheduled arrival"},
+        "latency_ms": cb["latency_ms"], "continuous_batching": cb, "per_request_fifo": fifo,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_batch(args):
     """Batched global counts of the 10,000-graph mix: graphs/s of one glt_count_batch call,
     next to the plain per-graph path (glt_count looped over the same graphs)."""
@@ -175,9 +285,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="chung_lu_1m", choices=sorted(WORKLOADS) + ["batch_10k"])
+    ap.add_argument("--workload", default="chung_lu_1m", choices=sorted(WORKLOADS) + ["batch_10k", "served"])
     ap.add_argument("--batch-graphs", type=int, default=10_000)
-    ap.add_argument("--no-per-graph", action="store_true", help="batch: skip the per-graph comparison")
+    ap.add_argument("--no-per-graph", action="store_true", help="batch/served: skip the per-graph comparison")
+    ap.add_argument("--rate", type=float, default=2000.0, help="served: arrivals per second")
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="served: length of the arrival stream")
+    ap.add_argument("--pool-small", type=int, default=2000, help="served: pool of small request graphs")
+    ap.add_argument("--pool-large", type=int, default=16, help="served: pool of large request graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--global-only", action="store_true", help="skip per-edge output")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -200,6 +314,9 @@ def main():
 
     if args.workload == "batch_10k":
         bench_batch(args)
+        return
+    if args.workload == "served":
+        bench_served(args)
         return
 
     import numpy as np

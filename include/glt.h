@@ -67,7 +67,8 @@ typedef enum {
     GLT_E_OOM = -4,            /* device workspace would exceed the handle's HBM budget         */
     GLT_E_DEVICE = -5,         /* a HIP runtime error                                           */
     GLT_E_UNSUPPORTED = -6,    /* n >= 2^31 or 2m >= 2^31                                       */
-    GLT_E_INTERNAL = -7        /* an internal consistency check failed (a library bug)          */
+    GLT_E_INTERNAL = -7,       /* an internal consistency check failed (a library bug)          */
+    GLT_E_BUSY = -8            /* the server's request queue is full                            */
 } glt_status;
 
 enum {
@@ -147,6 +148,56 @@ int glt_last_timing(const glt_ctx* ctx, float* ms, int cap);
  * algorithmic bytes of each pass.
  */
 int glt_last_work(const glt_ctx* ctx, uint64_t* out, int cap);
+
+/* ------------------------------------------------------------------------------------ */
+/* Request server: continuous batching of graph-count requests on one device.            */
+/* Requests are admitted in arrival order into a device-resident pool as its budget      */
+/* allows (copied on a copy stream), and every admitted request whose copy has finished   */
+/* joins the next batched launch (global counts, as glt_count_batch) on a compute stream, */
+/* so requests arriving during a launch overlap with it.  A request whose graph is        */
+/* invalid fails alone.                                                                    */
+/* ------------------------------------------------------------------------------------ */
+
+typedef struct glt_server glt_server;
+
+typedef struct {
+    int32_t device;            /* HIP device                                                   */
+    int32_t max_batch_graphs;  /* requests per launch; 0 = no limit, 1 = one request per launch */
+    int64_t max_batch_edges;   /* edges per launch (a larger request runs alone); 0 = 8,388,608 */
+    size_t resident_bytes;     /* device pool for admitted graphs (the admission budget); 0 = 4 GiB */
+    size_t workspace_bytes;    /* cap of the counting workspace (0 = none)                      */
+    int32_t max_pending;       /* queued, not yet admitted requests before GLT_E_BUSY; 0 = 2^20 */
+    int32_t reserved;
+} glt_server_opts;
+
+typedef struct {
+    uint64_t req_id;           /* as passed to glt_server_submit                               */
+    int32_t status;            /* glt_status of this request                                   */
+    int32_t batch_graphs;      /* number of requests in the launch that counted it             */
+    glt_u128 X[17];            /* X1..X17 when status == GLT_OK                                 */
+    double t_submit, t_admit, t_start, t_done;   /* seconds on glt_server_clock()              */
+} glt_result;
+
+/* Create a server (starts its admission and compute threads).  opts may be NULL. */
+glt_status glt_server_create(const glt_server_opts* opts, glt_server** out);
+
+/* Queue one request.  g must describe host memory (on_device == 0); it is copied before the
+ * call returns.  Returns GLT_E_BUSY when max_pending requests are already queued, and
+ * GLT_E_INVALID_ARG / GLT_E_UNSUPPORTED for malformed sizes (n, 2m < 2^30 per request). */
+glt_status glt_server_submit(glt_server* s, const glt_csr* g, uint64_t req_id);
+
+/* Move up to max completed results to out, waiting up to timeout_us for the first one.
+ * Returns the number written. */
+int glt_server_poll(glt_server* s, glt_result* out, int max, int timeout_us);
+
+/* Requests submitted and not yet completed. */
+int64_t glt_server_inflight(glt_server* s);
+
+/* Monotonic clock (seconds) used for the result timestamps. */
+double glt_server_clock(void);
+
+/* Stop the threads and release everything; results not yet polled are discarded. */
+void glt_server_destroy(glt_server* s);
 
 #ifdef __cplusplus
 }

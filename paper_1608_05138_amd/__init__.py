@@ -32,11 +32,14 @@ GLT_GLOBAL = 1
 GLT_PER_EDGE = 2
 
 STATUS = {0: "GLT_OK", -1: "GLT_E_INVALID_ARG", -2: "GLT_E_NOT_SIMPLE", -3: "GLT_E_NOT_SYMMETRIC",
-          -4: "GLT_E_OOM", -5: "GLT_E_DEVICE", -6: "GLT_E_UNSUPPORTED", -7: "GLT_E_INTERNAL"}
+          -4: "GLT_E_OOM", -5: "GLT_E_DEVICE", -6: "GLT_E_UNSUPPORTED", -7: "GLT_E_INTERNAL",
+          -8: "GLT_E_BUSY"}
 
 # the C-ABI symbols declared in include/glt.h
 EXPORTS = ["glt_create", "glt_destroy", "glt_last_error", "glt_version", "glt_count",
-           "glt_last_timing", "glt_last_work", "glt_count_batch"]
+           "glt_last_timing", "glt_last_work", "glt_count_batch", "glt_server_create",
+           "glt_server_submit", "glt_server_poll", "glt_server_inflight", "glt_server_clock",
+           "glt_server_destroy"]
 
 
 class GltError(RuntimeError):
@@ -59,6 +62,20 @@ class glt_batch(ctypes.Structure):
     _fields_ = [("num_graphs", ctypes.c_int64), ("vtx_base", ctypes.c_void_p),
                 ("slot_base", ctypes.c_void_p), ("row_ptr", ctypes.c_void_p),
                 ("col", ctypes.c_void_p), ("on_device", ctypes.c_int32)]
+
+
+class glt_server_opts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_batch_graphs", ctypes.c_int32),
+                ("max_batch_edges", ctypes.c_int64), ("resident_bytes", ctypes.c_size_t),
+                ("workspace_bytes", ctypes.c_size_t), ("max_pending", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class glt_result(ctypes.Structure):
+    _fields_ = [("req_id", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("batch_graphs", ctypes.c_int32), ("X", glt_u128 * 17),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
 
 
 _lib = None
@@ -92,6 +109,18 @@ def load_library(path: str = LIB_PATH):
     lib.glt_count_batch.argtypes = [P, ctypes.POINTER(glt_batch), ctypes.c_uint32,
                                     ctypes.POINTER(glt_u128), P]
     lib.glt_count_batch.restype = ctypes.c_int
+    lib.glt_server_create.argtypes = [ctypes.POINTER(glt_server_opts), ctypes.POINTER(P)]
+    lib.glt_server_create.restype = ctypes.c_int
+    lib.glt_server_submit.argtypes = [P, ctypes.POINTER(glt_csr), ctypes.c_uint64]
+    lib.glt_server_submit.restype = ctypes.c_int
+    lib.glt_server_poll.argtypes = [P, ctypes.POINTER(glt_result), ctypes.c_int, ctypes.c_int]
+    lib.glt_server_poll.restype = ctypes.c_int
+    lib.glt_server_inflight.argtypes = [P]
+    lib.glt_server_inflight.restype = ctypes.c_int64
+    lib.glt_server_clock.argtypes = []
+    lib.glt_server_clock.restype = ctypes.c_double
+    lib.glt_server_destroy.argtypes = [P]
+    lib.glt_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -226,6 +255,65 @@ class Context:
             raise GltError(rc, self.last_error())
         flat = [int(x.lo) | (int(x.hi) << 64) for x in X]
         return [flat[17 * g: 17 * g + 17] for g in range(B)]
+
+
+class Server:
+    """Continuous-batching request server (glt_server_*)."""
+
+    def __init__(self, device=0, max_batch_graphs=0, max_batch_edges=0, resident_bytes=0,
+                 workspace_bytes=0, max_pending=0):
+        self._lib = load_library()
+        o = glt_server_opts(device, max_batch_graphs, max_batch_edges, resident_bytes,
+                            workspace_bytes, max_pending, 0)
+        h = ctypes.c_void_p()
+        rc = self._lib.glt_server_create(ctypes.byref(o), ctypes.byref(h))
+        if rc != 0:
+            raise GltError(rc, "glt_server_create failed")
+        self._h = h
+        self._res = (glt_result * 256)()
+
+    def clock(self) -> float:
+        return self._lib.glt_server_clock()
+
+    def submit(self, row_ptr, col, req_id, n=None):
+        """Queue a host CSR graph (numpy int32/int64 row_ptr, int32 col).  Returns the
+        status (0 = queued)."""
+        if not (isinstance(row_ptr, np.ndarray) and row_ptr.dtype in (np.int32, np.int64)
+                and row_ptr.flags.c_contiguous):
+            row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        if not (isinstance(col, np.ndarray) and col.dtype == np.int32 and col.flags.c_contiguous):
+            col = np.ascontiguousarray(col, dtype=np.int32)
+        nn = row_ptr.size - 1 if n is None else n
+        g = glt_csr(nn, col.size // 2, row_ptr.ctypes.data, col.ctypes.data,
+                    1 if row_ptr.dtype == np.int64 else 0, 0)
+        return self._lib.glt_server_submit(self._h, ctypes.byref(g), req_id)
+
+    def poll(self, max_results=256, timeout_us=1000):
+        """Completed results: list of dicts (req_id, status, X, t_submit, t_admit, t_start,
+        t_done, batch_graphs)."""
+        k = self._lib.glt_server_poll(self._h, self._res, min(max_results, 256), timeout_us)
+        out = []
+        for i in range(k):
+            r = self._res[i]
+            out.append({"req_id": r.req_id, "status": r.status, "batch_graphs": r.batch_graphs,
+                        "X": [int(x.lo) | (int(x.hi) << 64) for x in r.X],
+                        "t_submit": r.t_submit, "t_admit": r.t_admit, "t_start": r.t_start,
+                        "t_done": r.t_done})
+        return out
+
+    def inflight(self) -> int:
+        return self._lib.glt_server_inflight(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.glt_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _default = {}

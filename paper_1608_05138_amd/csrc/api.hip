@@ -34,6 +34,8 @@ struct glt_ctx {
     int wedge_wave_max = 0;
     int wedge_limit = 0;
     uint64_t work[4] = {0, 0, 0, 0};   // n, m, wedges, triangle-pass list entries
+    void* stage = nullptr;             // device staging of host batch inputs
+    size_t stage_bytes = 0;
 };
 
 #define GLT_VERSION "glt 0.2 (gfx950)"
@@ -91,11 +93,12 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
     d.e.t = c.take<u32>(m);
     d.e.K = c.take<u64>(m);
     d.e.P = c.take<u64>(m);
-    d.e.gu = c.take<u64>(m);
-    d.e.gv = c.take<u64>(m);
+    d.e.g = c.take<u64>(m);
     d.e.sig = c.take<u64>(m);
     d.e.u = c.take<int>(m);
-    d.wcnt = c.take<int64_t>(n);
+    d.wcnt = c.take<u64>(n);
+    d.rowx = c.take<u32>(S + 1);
+    d.nsrow = c.take<int>(S);
     d.tri = c.take<u64>(n);
     d.sdeg = c.take<u64>(n);
     d.tlist = c.take<int>((int64_t)TB_N * n);
@@ -122,15 +125,19 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
         d.gvb = c.take<int64_t>(ngraphs + 1);
         d.gsb = c.take<int64_t>(ngraphs + 1);
         d.gparts = c.take<u64>((int64_t)ngraphs * 13 * 2);
+        d.glrp = (const int**)c.take<int*>(ngraphs);
+        d.glcol = (const int**)c.take<int*>(ngraphs);
         sg.rp = c.take<int>(n + 1);
         sg.col = c.take<int>(S);
-        sg.lrp = host_in ? c.take<int>(local_rp_len) : nullptr;
-        sg.lcol = host_in ? c.take<int>(S) : nullptr;
+        sg.lrp = sg.lcol = nullptr;
         sg.out = nullptr;
+        (void)host_in;
+        (void)local_rp_len;
     } else {
         d.gid = d.ngid = nullptr;
         d.gvb = d.gsb = nullptr;
         d.gparts = nullptr;
+        d.glrp = d.glcol = nullptr;
         sg.rp = host_in ? (void*)c.take<char>((int64_t)(n + 1) * (rp64 ? 8 : 4)) : nullptr;
         sg.col = host_in ? c.take<int>(S) : nullptr;
         sg.out = host_out ? c.take<u64>(13 * (int64_t)m) : nullptr;
@@ -280,6 +287,59 @@ void record_timing(glt_ctx* ctx) {
 
 }  // namespace
 
+// Global counts of B graphs given per-graph device pointers to their local offsets
+// (n_g + 1 entries, 0 .. 2 m_g) and local columns; vb/sb are host bases (sizes of each graph).
+glt_status glt_run_batch_ptrs(glt_ctx* ctx, int64_t B, const int64_t* vb, const int64_t* sb,
+                              const int* const* rp_ptrs, const int* const* col_ptrs, glt_u128* out,
+                              hipStream_t st) {
+    ctx->err.clear();
+    for (int64_t g = 0; g < B; g++)
+        if (vb[g + 1] < vb[g] || sb[g + 1] < sb[g] || ((sb[g + 1] - sb[g]) & 1))
+            return fail(ctx, GLT_E_INVALID_ARG, "graph %lld: bases not monotone or odd slot count", (long long)g);
+    const int64_t N = vb[B], S = sb[B];
+    if (N >= ((int64_t)1 << 31) || S >= ((int64_t)1 << 31))
+        return fail(ctx, GLT_E_UNSUPPORTED, "packed vertices or slots do not fit 31 bits");
+    const int n = (int)N, m = (int)(S / 2);
+    HIPCHK(hipSetDevice(ctx->device));
+    Dev d;
+    Staging sg;
+    const size_t need = carve(nullptr, n, m, 0, false, false, (int)B, 0, d, sg);
+    glt_status rc = ensure_ws(ctx, need, st);
+    if (rc) return rc;
+    carve(ctx->ws, n, m, 0, false, false, (int)B, 0, d, sg);
+    HIPCHK(hipMemcpyAsync((void*)d.gvb, vb, (size_t)(B + 1) * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync((void*)d.gsb, sb, (size_t)(B + 1) * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync((void*)d.glrp, rp_ptrs, (size_t)B * sizeof(void*), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync((void*)d.glcol, col_ptrs, (size_t)B * sizeof(void*), hipMemcpyHostToDevice, st));
+    glt_union_build(d, (int*)sg.rp, sg.col, st);
+    HIPCHK(hipGetLastError());
+    rc = run_pipeline(ctx, d, sg.rp, 0, sg.col, false, nullptr, st);
+    if (rc) return rc;
+    std::vector<u64> parts((size_t)B * 13 * 2), gs((size_t)B * NSUMS);
+    HIPCHK(hipMemcpyAsync(parts.data(), d.gparts, parts.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(gs.data(), d.gsum, gs.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 1032, d.work, 2 * sizeof(u64), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    ctx->work[0] = (uint64_t)n;
+    ctx->work[1] = (uint64_t)m;
+    ctx->work[2] = ((u64*)((char*)ctx->hbuf + 1032))[0];
+    ctx->work[3] = ((u64*)((char*)ctx->hbuf + 1032))[1];
+    record_timing(ctx);
+    for (int64_t g = 0; g < B; g++) {
+        i128 C[17];
+        unpack_c(&parts[(size_t)g * 26], C);
+        const i128 k4x3 = (i128)gs[(size_t)g * NSUMS + S_K4x3];
+        if (k4x3 % 3 != 0) return fail(ctx, GLT_E_INTERNAL, "graph %lld: 4-clique total not divisible by 3", (long long)g);
+        i128 X[18];
+        std::string why;
+        if (!globals(vb[g + 1] - vb[g], (sb[g + 1] - sb[g]) / 2, C, k4x3 / 3, (i128)gs[(size_t)g * NSUMS + S_NC4],
+                     false, X, why))
+            return fail(ctx, GLT_E_INTERNAL, "graph %lld: global combination failed: %s", (long long)g, why.c_str());
+        store_x(X, out + g * 17);
+    }
+    return GLT_OK;
+}
+
 extern "C" {
 
 const char* glt_version(void) { return GLT_VERSION; }
@@ -325,6 +385,7 @@ void glt_destroy(glt_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->stage) (void)hipFree(ctx->stage);
     for (int i = 0; i < 6; i++)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     if (ctx->hbuf) (void)hipHostFree(ctx->hbuf);
@@ -438,63 +499,42 @@ glt_status glt_count_batch(glt_ctx* ctx, const glt_batch* b, uint32_t flags, glt
     const int64_t* vb = b->vtx_base;
     const int64_t* sb = b->slot_base;
     if (vb[0] != 0 || sb[0] != 0) return fail(ctx, GLT_E_INVALID_ARG, "bases must start at 0");
-    for (int64_t g = 0; g < B; g++) {
-        if (vb[g + 1] < vb[g] || sb[g + 1] < sb[g] || ((sb[g + 1] - sb[g]) & 1))
-            return fail(ctx, GLT_E_INVALID_ARG, "graph %lld: bases not monotone or odd slot count", (long long)g);
-    }
+    for (int64_t g = 0; g < B; g++)
+        if (vb[g + 1] < vb[g] || sb[g + 1] < sb[g])
+            return fail(ctx, GLT_E_INVALID_ARG, "graph %lld: bases not monotone", (long long)g);
     const int64_t N = vb[B], S = sb[B];
     if (N >= ((int64_t)1 << 31) || S >= ((int64_t)1 << 31))
         return fail(ctx, GLT_E_UNSUPPORTED, "packed vertices or slots do not fit 31 bits");
     if (!b->row_ptr || (S > 0 && !b->col)) return fail(ctx, GLT_E_INVALID_ARG, "null row_ptr or col");
-    const int n = (int)N, m = (int)(S / 2);
-    const int64_t lrp_len = N + B;
-    const bool host_in = !b->on_device;
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t st = stream_ ? (hipStream_t)stream_ : ctx->stream;
-
-    Dev d;
-    Staging sg;
-    const size_t need = carve(nullptr, n, m, 0, host_in, false, (int)B, lrp_len, d, sg);
-    glt_status rc = ensure_ws(ctx, need, st);
-    if (rc) return rc;
-    carve(ctx->ws, n, m, 0, host_in, false, (int)B, lrp_len, d, sg);
-    const int* lrp = b->row_ptr;
-    const int* lcol = b->col;
-    if (host_in) {
-        HIPCHK(hipMemcpyAsync(sg.lrp, b->row_ptr, (size_t)lrp_len * 4, hipMemcpyHostToDevice, st));
-        if (S > 0) HIPCHK(hipMemcpyAsync(sg.lcol, b->col, (size_t)S * 4, hipMemcpyHostToDevice, st));
-        lrp = sg.lrp;
-        lcol = sg.lcol;
+    const int* rp = b->row_ptr;
+    const int* col = b->col;
+    if (!b->on_device) {
+        const size_t need = (size_t)(N + B) * 4 + (size_t)S * 4 + 512;
+        if (need > ctx->stage_bytes) {
+            HIPCHK(hipStreamSynchronize(st));
+            if (ctx->stage) { (void)hipFree(ctx->stage); ctx->stage = nullptr; ctx->stage_bytes = 0; }
+            if (hipMalloc(&ctx->stage, need) != hipSuccess) {
+                ctx->stage = nullptr;
+                (void)hipGetLastError();
+                return fail(ctx, GLT_E_OOM, "hipMalloc of %zu staging bytes failed", need);
+            }
+            ctx->stage_bytes = need;
+        }
+        int* drp = (int*)ctx->stage;
+        int* dcol = drp + ((N + B + 63) / 64) * 64;
+        HIPCHK(hipMemcpyAsync(drp, b->row_ptr, (size_t)(N + B) * 4, hipMemcpyHostToDevice, st));
+        if (S > 0) HIPCHK(hipMemcpyAsync(dcol, b->col, (size_t)S * 4, hipMemcpyHostToDevice, st));
+        rp = drp;
+        col = dcol;
     }
-    HIPCHK(hipMemcpyAsync((void*)d.gvb, vb, (size_t)(B + 1) * 8, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync((void*)d.gsb, sb, (size_t)(B + 1) * 8, hipMemcpyHostToDevice, st));
-    glt_union_build(d, lrp, lcol, (int*)sg.rp, sg.col, st);
-    HIPCHK(hipGetLastError());
-    rc = run_pipeline(ctx, d, sg.rp, 0, sg.col, false, nullptr, st);
-    if (rc) return rc;
-    std::vector<u64> parts((size_t)B * 13 * 2), gs((size_t)B * NSUMS);
-    HIPCHK(hipMemcpyAsync(parts.data(), d.gparts, parts.size() * 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(gs.data(), d.gsum, gs.size() * 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 1032, d.work, 2 * sizeof(u64), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    ctx->work[0] = (uint64_t)n;
-    ctx->work[1] = (uint64_t)m;
-    ctx->work[2] = ((u64*)((char*)ctx->hbuf + 1032))[0];
-    ctx->work[3] = ((u64*)((char*)ctx->hbuf + 1032))[1];
-    record_timing(ctx);
+    std::vector<const int*> rps((size_t)B), cols((size_t)B);
     for (int64_t g = 0; g < B; g++) {
-        i128 C[17];
-        unpack_c(&parts[(size_t)g * 26], C);
-        const i128 k4x3 = (i128)gs[(size_t)g * NSUMS + S_K4x3];
-        if (k4x3 % 3 != 0) return fail(ctx, GLT_E_INTERNAL, "graph %lld: 4-clique total not divisible by 3", (long long)g);
-        i128 X[18];
-        std::string why;
-        if (!globals(vb[g + 1] - vb[g], (sb[g + 1] - sb[g]) / 2, C, k4x3 / 3, (i128)gs[(size_t)g * NSUMS + S_NC4],
-                     false, X, why))
-            return fail(ctx, GLT_E_INTERNAL, "graph %lld: global combination failed: %s", (long long)g, why.c_str());
-        store_x(X, out + g * 17);
+        rps[(size_t)g] = rp + vb[g] + g;
+        cols[(size_t)g] = col + sb[g];
     }
-    return GLT_OK;
+    return glt_run_batch_ptrs(ctx, B, vb, sb, rps.data(), cols.data(), out, st);
 }
 
 }  // extern "C"

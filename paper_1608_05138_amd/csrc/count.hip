@@ -11,8 +11,9 @@
 //    popcount(M_i & M_j) is the number of 4-cliques {a, b_i, b_j, c} with a lowest.  Each
 //    triangle credits its three edges once (t), each 4-clique its six edges once (K).
 //  * gather pass (per-edge mode): for every triangle (a, b_i, b_j) the third vertex w of
-//    each edge contributes t(w,u), t(w,v) and d_w, giving the T-S_u / T-S_v edge counts
-//    and the degree sum over T needed for the remaining per-edge 4-node counts.
+//    each edge contributes t(w,u) + t(w,v) and d_w, giving the number of edges between T and
+//    S_u or S_v and the degree sum over T needed for the remaining per-edge 4-node counts
+//    (every per-edge count depends on the T-S_u and T-S_v edge counts only through their sum).
 //  * wedge pass (per bottom vertex y): wedges y - w - x with x ranked above y and w are
 //    grouped by x in an LDS hash; a group of c wedges closes C(c,2) 4-cycles whose top
 //    vertex is x.  Each wedge's edges (y,w) and (w,x) lie on c-1 of them, which gives every
@@ -219,32 +220,28 @@ static inline size_t tri_blk_lds(int smax, bool gm) {
 // gather pass (per-edge mode): for every triangle (a, b_i, b_j), a lowest
 // ---------------------------------------------------------------------------------------
 // Credits of one triangle found at (i, j, edge k = (b_i, b_j)):
-//   edge (a, b_i): gu += t(a, b_j), gv += t(b_i, b_j), sig += d(b_j)   [local, run-summed]
-//   edge (a, b_j): gu += t(a, b_i), gv += t(b_i, b_j), sig += d(b_i)   [local]
-//   edge (b_i, b_j): gu += t(a, b_i), gv += t(a, b_j), sig += d(a)     [global, coalesced]
+//   edge (a, b_i): g += t(a, b_j) + t(b_i, b_j), sig += d(b_j)   [local, run-summed]
+//   edge (a, b_j): g += t(a, b_i) + t(b_i, b_j), sig += d(b_i)   [local]
+//   edge (b_i, b_j): g += t(a, b_i) + t(a, b_j), sig += d(a)     [global, coalesced]
 __device__ __forceinline__ void gather_credit(bool found, int i, int j, int k, const u32* sT, const int* sD, int da,
-                                              EdgeArrays& e, u64* sGu, u64* sGv, u64* sSg) {
-    u64 taj = 0, tij = 0, dj = 0;
+                                              EdgeArrays& e, u64* sG, u64* sSg) {
+    u64 gi = 0, di = 0;
     if (found) {
-        tij = e.t[k];
-        const u64 tai = sT[i];
-        taj = sT[j];
-        dj = (u64)sD[j];
-        atomicAdd(&sGu[j], tai);
-        atomicAdd(&sGv[j], tij);
+        const u64 tij = e.t[k];
+        const u64 tai = sT[i], taj = sT[j];
+        gi = taj + tij;
+        di = (u64)sD[j];
+        atomicAdd(&sG[j], tai + tij);
         atomicAdd(&sSg[j], (u64)sD[i]);
-        atomicAdd(&e.gu[k], tai);
-        atomicAdd(&e.gv[k], taj);
+        atomicAdd(&e.g[k], tai + taj);
         atomicAdd(&e.sig[k], (u64)da);
     }
     // lanes of a wavefront hold non-decreasing i (idle lanes a larger sentinel, zero values)
     bool last;
-    const u64 a1 = seg_sum_last(taj, i, last);
-    const u64 a2 = seg_sum_last(tij, i, last);
-    const u64 a3 = seg_sum_last(dj, i, last);
-    if (last && (a1 | a2 | a3)) {
-        if (a1) atomicAdd(&sGu[i], a1);
-        if (a2) atomicAdd(&sGv[i], a2);
+    const u64 a1 = seg_sum_last(gi, i, last);
+    const u64 a3 = seg_sum_last(di, i, last);
+    if (last) {
+        if (a1) atomicAdd(&sG[i], a1);
         if (a3) atomicAdd(&sSg[i], a3);
     }
 }
@@ -258,8 +255,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
     __shared__ int sPre[4][GLT_WAVE];
     __shared__ u32 sT[4][GLT_WAVE];
     __shared__ int sD[4][GLT_WAVE];
-    __shared__ u64 sGu[4][GLT_WAVE];
-    __shared__ u64 sGv[4][GLT_WAVE];
+    __shared__ u64 sG[4][GLT_WAVE];
     __shared__ u64 sSg[4][GLT_WAVE];
     const int w = threadIdx.x / GLT_WAVE, l = glt_lane();
     const int idx = blockIdx.x * 4 + w;
@@ -278,7 +274,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
     const int inc = wave_incl_scan(db);
     const int total = __shfl(inc, GLT_WAVE - 1, GLT_WAVE);
     sS[w][l] = b; sOb[w][l] = ob; sPre[w][l] = inc - db; sT[w][l] = tb; sD[w][l] = degb;
-    sGu[w][l] = 0; sGv[w][l] = 0; sSg[w][l] = 0;
+    sG[w][l] = 0; sSg[w][l] = 0;
     __syncthreads();
     for (int q0 = 0; q0 < total; q0 += GLT_WAVE) {
         const int q = q0 + l;
@@ -291,12 +287,11 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
             j = lower_bound_i32(sS[w], i + 1, s, x);
             found = (j < s && sS[w][j] == x);
         }
-        gather_credit(found, i, j, k, sT[w], sD[w], da, e, sGu[w], sGv[w], sSg[w]);
+        gather_credit(found, i, j, k, sT[w], sD[w], da, e, sG[w], sSg[w]);
     }
     __syncthreads();
     if (l < s) {
-        if (sGu[w][l]) atomicAdd(&e.gu[o0 + l], sGu[w][l]);
-        if (sGv[w][l]) atomicAdd(&e.gv[o0 + l], sGv[w][l]);
+        if (sG[w][l]) atomicAdd(&e.g[o0 + l], sG[w][l]);
         if (sSg[w][l]) atomicAdd(&e.sig[o0 + l], sSg[w][l]);
     }
 }
@@ -314,9 +309,8 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict
     int* sPre = sOb + smax;
     u32* sT = (u32*)(sPre + smax);
     int* sD = (int*)(sT + smax);
-    u64* sGu = GM ? gslab + (int64_t)blockIdx.x * 3 * smax : (u64*)(sD + smax + (smax & 1));
-    u64* sGv = sGu + smax;
-    u64* sSg = sGv + smax;
+    u64* sG = GM ? gslab + (int64_t)blockIdx.x * 2 * smax : (u64*)(sD + smax + (smax & 1));
+    u64* sSg = sG + smax;
     const int tid = threadIdx.x;
     const int a = list[blockIdx.x];
     const int o0 = optr[a];
@@ -331,7 +325,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict
             const int ob = optr[b];
             db = optr[b + 1] - ob;
             sS[i] = b; sOb[i] = ob; sT[i] = e.t[o0 + i]; sD[i] = ndeg[b];
-            sGu[i] = 0; sGv[i] = 0; sSg[i] = 0;
+            sG[i] = 0; sSg[i] = 0;
         }
         int tot;
         const int ex = block_excl_scan<int, TB_THREADS>(db, sScan, tot);
@@ -352,18 +346,17 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict
             j = lower_bound_i32(sS, i + 1, s, x);
             found = (j < s && sS[j] == x);
         }
-        gather_credit(found, i, j, k, sT, sD, da, e, sGu, sGv, sSg);
+        gather_credit(found, i, j, k, sT, sD, da, e, sG, sSg);
     }
     __syncthreads();
     for (int i = tid; i < s; i += TB_THREADS) {
-        if (sGu[i]) atomicAdd(&e.gu[o0 + i], sGu[i]);
-        if (sGv[i]) atomicAdd(&e.gv[o0 + i], sGv[i]);
+        if (sG[i]) atomicAdd(&e.g[o0 + i], sG[i]);
         if (sSg[i]) atomicAdd(&e.sig[o0 + i], sSg[i]);
     }
 }
 
 static inline size_t gather_blk_lds(int smax, bool gm) {
-    return (size_t)(smax + 1) * 4 * 5 + (gm ? 0 : (size_t)smax * 8 * 3);
+    return (size_t)(smax + 1) * 4 * 5 + (gm ? 0 : (size_t)smax * 8 * 2);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -420,8 +413,9 @@ __global__ __launch_bounds__(256) void k_wedge_wave(const int* __restrict__ list
                 const int x = ocol[sK0[w4][i] + (q - sPre[w4][i])];
                 u32 h = hslot(x, mask);
                 while (true) {
-                    const int old = atomicCAS(&hkey[w4][h], -1, x);
-                    if (old == -1 || old == x) { atomicAdd(&hcnt[w4][h], 1u); break; }
+                    int cur = hkey[w4][h];
+                    if (cur == -1) cur = atomicCAS(&hkey[w4][h], -1, x);
+                    if (cur == -1 || cur == x) { atomicAdd(&hcnt[w4][h], 1u); break; }
                     h = (h + 1) & mask;
                 }
             }
@@ -532,13 +526,16 @@ __global__ __launch_bounds__(WB_THREADS) void k_wedge_blk(const int* __restrict_
                 const int x = ocol[sK0[i] + (q - sPre[i])];
                 u32 h = hslot(x, mask);
                 while (true) {
-                    const int old = atomicCAS(&hkey[h], -1, x);
-                    if (old == -1) {
-                        atomicAdd(&hcnt[h], 1u);
-                        if (atomicAdd(&distinct, 1) + 1 > limit) ovf = 1;
-                        break;
+                    int cur = hkey[h];
+                    if (cur == -1) {
+                        cur = atomicCAS(&hkey[h], -1, x);
+                        if (cur == -1) {
+                            atomicAdd(&hcnt[h], 1u);
+                            if (atomicAdd(&distinct, 1) + 1 > limit) ovf = 1;
+                            break;
+                        }
                     }
-                    if (old == x) { atomicAdd(&hcnt[h], 1u); break; }
+                    if (cur == x) { atomicAdd(&hcnt[h], 1u); break; }
                     h = (h + 1) & mask;
                 }
             }
@@ -610,24 +607,29 @@ __global__ __launch_bounds__(WB_THREADS) void k_wedge_blk(const int* __restrict_
 }
 
 // ---------------------------------------------------------------------------------------
-// vertex pass: triangles at x (each incident edge's t, halved) and neighbour-degree sums
+// vertex pass: per relabelled entry (x -> y) the edge's t and d_y, summed per x (runs of one
+// row are summed in the wavefront first): tri[x] = 2 x (triangles at x), sdeg[x] = sum of
+// neighbour degrees.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_vertex(const int* __restrict__ nrp, const int* __restrict__ ncol,
+__global__ __launch_bounds__(256) void k_vertex(const int* __restrict__ nsrow, const int* __restrict__ ncol,
                                                 const int* __restrict__ s2k, const int* __restrict__ ndeg,
-                                                const u32* __restrict__ et, int n, u64* __restrict__ tri,
+                                                const u32* __restrict__ et, int64_t S, u64* __restrict__ tri,
                                                 u64* __restrict__ sdeg) {
-    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GLT_WAVE;
-    const int l = glt_lane();
-    if (wid >= n) return;
-    const int x = (int)wid;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     u64 t = 0, sd = 0;
-    for (int s = nrp[x] + l; s < nrp[x + 1]; s += GLT_WAVE) {
-        t += et[s2k[s]];
-        sd += (u64)ndeg[ncol[s]];
+    int x = 0x7fffffff;
+    if (s < S) {
+        x = nsrow[s];
+        t = et[s2k[s]];
+        sd = (u64)ndeg[ncol[s]];
     }
-    t = wave_sum(t);
-    sd = wave_sum(sd);
-    if (l == 0) { tri[x] = t / 2; sdeg[x] = sd; }
+    bool last;
+    const u64 rt = seg_sum_last(t, x, last);
+    const u64 rs = seg_sum_last(sd, x, last);
+    if (last && x != 0x7fffffff) {
+        if (rt) atomicAdd(&tri[x], rt);
+        if (rs) atomicAdd(&sdeg[x], rs);
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -680,33 +682,29 @@ __global__ __launch_bounds__(CB_THREADS) void k_combine(const int* __restrict__ 
         if (PE) {
             K = (int64_t)e.K[k];
             const int64_t P = (int64_t)e.P[k];
-            const int64_t au = (int64_t)e.gu[k] - t - 2 * K;
-            const int64_t av = (int64_t)e.gv[k] - t - 2 * K;
-            Q = P - 2 * K - au - av;
+            const int64_t A = (int64_t)e.g[k] - 2 * t - 4 * K;     // edges T-S_u plus T-S_v
+            Q = P - 2 * K - A;                                      // edges S_u-S_v
             const int64_t sigT = (int64_t)e.sig[k];
-            const int64_t Esu = (int64_t)tri[u] - t - K - au;
-            const int64_t Esv = (int64_t)tri[v] - t - K - av;
-            const int64_t ETD = sigT - 2 * t - 2 * K - au - av;
-            const int64_t ESuD = ((int64_t)sdeg[u] - dv - sigT) - su - 2 * Esu - au - Q;
-            const int64_t ESvD = ((int64_t)sdeg[v] - du - sigT) - sv - 2 * Esv - av - Q;
-            const int64_t EDD = (int64_t)m - 1 - 2 * t - su - sv -
-                                (K + Esu + Esv + au + av + Q + ETD + ESuD + ESvD);
+            const int64_t E2 = (int64_t)((tri[u] + tri[v]) >> 1) - 2 * t - 2 * K - A;   // inside S_u plus inside S_v
+            const int64_t ETD = sigT - 2 * t - 2 * K - A;           // edges T-D
+            const int64_t ESD = ((int64_t)sdeg[u] - dv - sigT) + ((int64_t)sdeg[v] - du - sigT) - su - sv - 2 * E2 - A -
+                                2 * Q;                              // edges S_u-D plus S_v-D
+            const int64_t EDD = (int64_t)m - 1 - 2 * t - su - sv - (K + E2 + A + Q + ETD + ESD);
             int64_t x[13];
             x[0] = t;
             x[1] = su + sv;
             x[2] = D;
             x[3] = K;
-            x[4] = (t * (t - 1) / 2 - K) + au + av;
-            x[5] = (t * su - au) + (t * sv - av) + ETD + Esu + Esv;
+            x[4] = (t * (t - 1) / 2 - K) + A;
+            x[5] = t * (su + sv) - A + ETD + E2;
             x[6] = Q;
-            x[7] = (su * (su - 1) / 2 - Esu) + (sv * (sv - 1) / 2 - Esv);
-            x[8] = (su * sv - Q) + ESuD + ESvD;
+            x[7] = su * (su - 1) / 2 + sv * (sv - 1) / 2 - E2;
+            x[8] = (su * sv - Q) + ESD;
             x[9] = t * D - ETD;
             x[10] = EDD;
-            x[11] = (su + sv) * D - ESuD - ESvD;
+            x[11] = (su + sv) * D - ESD;
             x[12] = D * (D - 1) / 2 - EDD;
-            int neg = (au < 0) | (av < 0) | (Q < 0) | (Esu < 0) | (Esv < 0) | (ETD < 0) | (ESuD < 0) |
-                      (ESvD < 0) | (EDD < 0);
+            int neg = (A < 0) | (Q < 0) | (E2 < 0) | (ETD < 0) | (ESD < 0) | (EDD < 0);
 #pragma unroll
             for (int c = 0; c < 13; c++) {
                 neg |= (x[c] < 0);
@@ -897,7 +895,7 @@ void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hi
             const int smax = cnt[TB_N + WB_N + bkt];
             const int* lst = tl + (int64_t)bkt * n;
             if (bkt == TB_GLOBAL) {
-                const int64_t per = 3 * (int64_t)smax * 2;   // u64 accumulators, in u32 words
+                const int64_t per = 2 * (int64_t)smax * 2;   // u64 accumulators, in u32 words
                 int64_t grp = d.gscratch_words / per;
                 if (grp < 1) grp = 1;
                 for (int64_t off = 0; off < c; off += grp) {
@@ -936,9 +934,12 @@ void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hi
     }
     if (ev) (void)hipEventRecord(ev[2], st);
     // vertex pass + combine
-    if (per_edge && n > 0)
-        hipLaunchKernelGGL(k_vertex, dim3(cdiv((int64_t)n * GLT_WAVE, 256)), dim3(256), 0, st, d.nrp, d.ncol,
-                           d.s2k, d.ndeg, e.t, n, d.tri, d.sdeg);
+    if (per_edge && n > 0 && m > 0) {
+        launch_fill<u64>(d.tri, n, 0ull, st);
+        launch_fill<u64>(d.sdeg, n, 0ull, st);
+        hipLaunchKernelGGL(k_vertex, dim3(cdiv(2 * (int64_t)m, 256)), dim3(256), 0, st, d.nsrow, d.ncol, d.s2k,
+                           d.ndeg, e.t, 2 * (int64_t)m, d.tri, d.sdeg);
+    }
     const int nb = combine_blocks(m);
     if (d.ngraphs > 0) {
         hipLaunchKernelGGL(k_combine_graphs, dim3(d.ngraphs), dim3(CB_THREADS), 0, st, d.gvb, d.gsb, d.eid2k, e,

@@ -21,8 +21,7 @@ struct EdgeArrays {
     u32* t;      // triangles on the edge
     u64* K;      // 4-cliques on the edge (edges inside T)
     u64* P;      // non-induced 4-cycles through the edge
-    u64* gu;     // sum over w in T of t(w,u)
-    u64* gv;     // sum over w in T of t(w,v)
+    u64* g;      // sum over w in T of t(w,u) + t(w,v)
     u64* sig;    // sum over w in T of d_w
     int* u;      // lower-ranked endpoint (relabelled id); the other one is ocol[k]
 };
@@ -58,13 +57,15 @@ struct Dev {
     int* s2k;         // CSR slot -> oriented edge index [S]
     int* eid2k;       // caller edge id -> oriented edge index [m]
     EdgeArrays e;     // per-edge accumulators [m] each
-    u64* tri;         // triangles at each relabelled vertex [n]
+    u64* tri;         // twice the triangles at each relabelled vertex [n]
     u64* sdeg;        // sum of neighbour degrees [n]
     int* tlist;       // triangle-pass vertex lists, TB_N segments of n
     int* wlist;       // wedge-pass vertex lists, WB_N segments of n
     int* counts;      // bucket counts and maxima (TB_N + WB_N + TB_N)
     u64* work;        // work counters: [0] wedges, [1] out-list entries scanned by the triangle pass
-    int64_t* wcnt;    // wedges per vertex [n] (wedge-pass bucketing)
+    u64* wcnt;        // wedges per vertex [n] (wedge-pass bucketing)
+    u32* rowx;        // [S+1] exclusive prefix of row starts of the input CSR: row of entry s = rowx[s+1]-1
+    int* nsrow;       // [S] row of each relabelled CSR entry
     u64* sums;        // per-block partial sums, NSUMS per entry
     int nsum_slots;   // capacity of sums (entries)
     u64* final_sums;  // 2*NSUMS u64 (lo,hi) reduced 128-bit sums
@@ -83,6 +84,8 @@ struct Dev {
     const int64_t* gvb;   // device copy of the per-graph vertex bases [ngraphs+1]
     const int64_t* gsb;   // device copy of the per-graph slot bases [ngraphs+1]
     u64* gparts;          // [ngraphs][13][2] per-graph unrestricted sums (128-bit)
+    const int** glrp;     // device array of per-graph local-offset pointers [ngraphs]
+    const int** glcol;    // device array of per-graph local-column pointers [ngraphs]
     // tuning (defaults; overridable per handle for testing)
     int wedge_wave_max;   // wedge-pass vertices with at most this many wedges use one wavefront
     int wedge_limit;      // distinct tops per hash range before the range is split
@@ -91,7 +94,7 @@ struct Dev {
 // Host-side entry points of the device pipeline (count.hip).
 struct Timing { float ms[5]; };
 
-int glt_union_build(const Dev& d, const int* lrp, const int* lcol, int* urp, int* ucol, hipStream_t st);
+int glt_union_build(const Dev& d, int* urp, int* ucol, hipStream_t st);
 int glt_prep_validate(const Dev& d, const void* rp, int rp64, const int* col, hipStream_t st);
 int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipStream_t st,
                    int* host_counts /* TB_N + WB_N + TB_N */);
