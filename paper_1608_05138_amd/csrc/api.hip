@@ -20,6 +20,7 @@ int glt_combine_blocks(int m);
 int glt_max_out_degree();
 int glt_wedge_table();
 int glt_wave_table();
+int glt_wedge_dense();
 
 struct glt_ctx {
     int device = 0;
@@ -33,6 +34,7 @@ struct glt_ctx {
     u64* hbuf = nullptr;   // pinned host buffer for small read-backs (4 KiB)
     int wedge_wave_max = 0;
     int wedge_limit = 0;
+    int wedge_dense = 0;
     uint64_t work[4] = {0, 0, 0, 0};   // n, m, wedges, triangle-pass list entries
     void* stage = nullptr;             // device staging of host batch inputs
     size_t stage_bytes = 0;
@@ -243,6 +245,7 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
     const int n = d.n, m = d.m;
     d.wedge_wave_max = ctx->wedge_wave_max;
     d.wedge_limit = ctx->wedge_limit;
+    d.wedge_dense = ctx->wedge_dense;
     HIPCHK(hipEventRecord(ctx->ev[0], st));
     glt_prep_validate(d, rp, rp64, col, st);
     HIPCHK(hipGetLastError());
@@ -254,6 +257,8 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
         if (e & ERR_RANGE) return fail(ctx, GLT_E_INVALID_ARG, "row offsets not monotone or neighbour id out of range");
         if (e & ERR_SELF) return fail(ctx, GLT_E_NOT_SIMPLE, "self-loop");
         hc[0] = ((int*)ctx->hbuf)[1];   // maximum degree
+        // K <= C(dmax,2), P <= dmax^2, sum over T of t(w,u)+t(w,v) <= 2 dmax^2, sum of d_w <= dmax^2
+        d.acc32 = (hc[0] <= 46340) ? 1 : 0;
     }
     glt_prep_build(d, rp, rp64, col, st, hc);
     HIPCHK(hipGetLastError());
@@ -365,6 +370,11 @@ glt_status glt_create(int device, size_t hbm_budget_bytes, glt_ctx** out) {
     if (const char* e = getenv("GLT_WEDGE_RANGE_LIMIT")) {
         int v = atoi(e);
         if (v >= 1 && v < ctx->wedge_limit) ctx->wedge_limit = v;
+    }
+    ctx->wedge_dense = glt_wedge_dense();
+    if (const char* e = getenv("GLT_WEDGE_DENSE")) {
+        int v = atoi(e);
+        if (v >= 0 && v < ctx->wedge_dense) ctx->wedge_dense = v;
     }
     if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
         delete ctx;

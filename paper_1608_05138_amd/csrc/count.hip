@@ -29,41 +29,78 @@
 // a run send to the same source are first summed with a segmented wave reduction.
 #include "glt_internal.h"
 
+// Per-edge accumulators K, P, g, sig are 64-bit, or 32-bit when the maximum degree bounds
+// every value below 2^32 (the host picks AT); the buffers are sized for 64-bit either way.
+template <typename AT>
+__device__ __forceinline__ void acc_add(u64* base, int64_t k, u64 v) {
+    atomicAdd(&((AT*)base)[k], (AT)v);
+}
+template <typename AT>
+__device__ __forceinline__ u64 acc_get(const u64* base, int64_t k) {
+    return (u64)((const AT*)base)[k];
+}
+
 #define TB_THREADS 256
 
 // ---------------------------------------------------------------------------------------
 // triangle / 4-clique pass, out-degree 2..64: one wavefront per vertex, M rows in one word
 // ---------------------------------------------------------------------------------------
-template <bool PE>
+// Membership of a vertex id in S = N+(a) (s <= 64) through a 128-entry LDS hash per
+// wavefront mapping id -> position in S.
+#define SH_SIZE 128
+__device__ __forceinline__ u32 shash(int x) { return ((u32)x * 2654435761u >> 9) & (SH_SIZE - 1); }
+
+__device__ __forceinline__ void sh_insert(int* hk, unsigned char* hv, int x, int pos) {
+    u32 h = shash(x);
+    while (atomicCAS(&hk[h], -1, x) != -1) h = (h + 1) & (SH_SIZE - 1);
+    hv[h] = (unsigned char)pos;
+}
+
+__device__ __forceinline__ int sh_find(const int* hk, const unsigned char* hv, int x) {
+    u32 h = shash(x);
+    while (true) {
+        const int k = hk[h];
+        if (k == x) return hv[h];
+        if (k == -1) return -1;
+        h = (h + 1) & (SH_SIZE - 1);
+    }
+}
+
+template <bool PE, typename AT>
 __global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__ list, int nlist,
                                                         const int* __restrict__ optr, const int* __restrict__ ocol,
                                                         EdgeArrays e, u64* __restrict__ gsum,
                                                         const int* __restrict__ ngid) {
-    __shared__ int sS[4][GLT_WAVE];
     __shared__ int sOb[4][GLT_WAVE];
     __shared__ int sPre[4][GLT_WAVE];
     __shared__ u64 sM[4][GLT_WAVE];
     __shared__ u64 sK[4][GLT_WAVE];
+    __shared__ int hk[4][SH_SIZE];
+    __shared__ unsigned char hv[4][SH_SIZE];
     const int w = threadIdx.x / GLT_WAVE, l = glt_lane();
     const int idx = blockIdx.x * 4 + w;
     const bool active = idx < nlist;
     const int a = active ? list[idx] : 0;
     const int o0 = active ? optr[a] : 0;
     const int s = active ? optr[a + 1] - o0 : 0;
-    int b = 0x7fffffff, ob = 0, db = 0;
+    int b = 0, ob = 0, db = 0;
     if (l < s) { b = ocol[o0 + l]; ob = optr[b]; db = optr[b + 1] - ob; }
     const int inc = wave_incl_scan(db);
     const int total = __shfl(inc, GLT_WAVE - 1, GLT_WAVE);
-    sS[w][l] = b; sOb[w][l] = ob; sPre[w][l] = inc - db; sM[w][l] = 0; sK[w][l] = 0;
+    sOb[w][l] = ob; sPre[w][l] = inc - db; sM[w][l] = 0; sK[w][l] = 0;
+    hk[w][l] = -1; hk[w][l + GLT_WAVE] = -1;
+    __syncthreads();
+    if (l < s) sh_insert(hk[w], hv[w], b, l);
     __syncthreads();
     // build the adjacency rows among S
+    int i = 0;
     for (int q0 = 0; q0 < total; q0 += GLT_WAVE) {
         const int q = q0 + l;
         if (q < total) {
-            const int i = upper_idx(sPre[w], s, q);
+            i = advance_idx(sPre[w], s, q, i);
             const int x = ocol[sOb[w][i] + (q - sPre[w][i])];
-            const int j = lower_bound_i32(sS[w], i + 1, s, x);
-            if (j < s && sS[w][j] == x) {
+            const int j = sh_find(hk[w], hv[w], x);
+            if (j >= 0) {
                 atomicOr(&sM[w][i], 1ull << j);
                 atomicOr(&sM[w][j], 1ull << i);
             }
@@ -71,20 +108,21 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__
     }
     __syncthreads();
     u64 k4 = 0;
+    i = 0;
     for (int q0 = 0; q0 < total; q0 += GLT_WAVE) {
         const int q = q0 + l;
-        int i = 0x7fffffff;
+        int key = 0x7fffffff;
         u64 tk = 0;
         if (q < total) {
-            i = upper_idx(sPre[w], s, q);
+            i = advance_idx(sPre[w], s, q, i);
+            key = i;
             const int k = sOb[w][i] + (q - sPre[w][i]);
-            const int x = ocol[k];
-            const int j = lower_bound_i32(sS[w], i + 1, s, x);
-            if (j < s && sS[w][j] == x) {
+            const int j = sh_find(hk[w], hv[w], ocol[k]);
+            if (j >= 0) {
                 tk = (u64)__popcll(sM[w][i] & sM[w][j]);
                 atomicAdd(&e.t[k], 1u);
                 if (PE && tk) {
-                    atomicAdd(&e.K[k], tk);
+                    acc_add<AT>(e.K, k, tk);
                     atomicAdd(&sK[w][j], tk);
                 }
                 k4 += tk;
@@ -92,8 +130,8 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__
         }
         if (PE) {
             bool last;
-            const u64 ssum = seg_sum_last(tk, i, last);
-            if (last && ssum) atomicAdd(&sK[w][i], ssum);
+            const u64 ssum = seg_sum_last(tk, key, last);
+            if (last && ssum) atomicAdd(&sK[w][key], ssum);
         }
     }
     __syncthreads();
@@ -102,7 +140,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__
         if (tl) atomicAdd(&e.t[o0 + l], tl);
         if (PE) {
             const u64 kl = sK[w][l] >> 1;
-            if (kl) atomicAdd(&e.K[o0 + l], kl);
+            if (kl) acc_add<AT>(e.K, o0 + l, kl);
         }
     }
     k4 = wave_sum(k4);
@@ -113,7 +151,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__
 // triangle / 4-clique pass, out-degree > 64: one workgroup per vertex, M rows of W words
 // in LDS (GM = false) or in a per-workgroup global slab (GM = true)
 // ---------------------------------------------------------------------------------------
-template <bool PE, bool GM>
+template <bool PE, bool GM, typename AT>
 __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ list, int nlist, int smax,
                                                        const int* __restrict__ optr, const int* __restrict__ ocol,
                                                        EdgeArrays e, u64* __restrict__ gsum,
@@ -151,8 +189,9 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
     const int total = carry;
     for (int q = tid; q < s * W; q += TB_THREADS) M[q] = 0;
     __syncthreads();
+    int ii = 0;
     for (int q = tid; q < total; q += TB_THREADS) {
-        const int i = upper_idx(sPre, s, q);
+        const int i = ii = advance_idx(sPre, s, q, ii);
         const int x = ocol[sOb[i] + (q - sPre[i])];
         const int j = lower_bound_i32(sS, i + 1, s, x);
         if (j < s && sS[j] == x) {
@@ -164,12 +203,13 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
     u64 k4 = 0;
     // every thread runs the same number of iterations so the wave reductions see full waves
     const int rounds = (total + TB_THREADS - 1) / TB_THREADS;
+    ii = 0;
     for (int r = 0; r < rounds; r++) {
         const int q = r * TB_THREADS + tid;
         int i = 0x7fffffff;
         u64 tk = 0;
         if (q < total) {
-            i = upper_idx(sPre, s, q);
+            i = ii = advance_idx(sPre, s, q, ii);
             const int k = sOb[i] + (q - sPre[i]);
             const int x = ocol[k];
             const int j = lower_bound_i32(sS, i + 1, s, x);
@@ -177,7 +217,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
                 for (int wd = 0; wd < W; wd++) tk += (u64)__popc(M[i * W + wd] & M[j * W + wd]);
                 atomicAdd(&e.t[k], 1u);
                 if (PE && tk) {
-                    atomicAdd(&e.K[k], tk);
+                    acc_add<AT>(e.K, k, tk);
                     atomicAdd(&sK[j], tk);
                 }
                 k4 += tk;
@@ -196,7 +236,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
         if (tl) atomicAdd(&e.t[o0 + i], tl);
         if (PE) {
             const u64 kl = sK[i] >> 1;
-            if (kl) atomicAdd(&e.K[o0 + i], kl);
+            if (kl) acc_add<AT>(e.K, o0 + i, kl);
         }
     }
     k4 = wave_sum(k4);
@@ -223,6 +263,7 @@ static inline size_t tri_blk_lds(int smax, bool gm) {
 //   edge (a, b_i): g += t(a, b_j) + t(b_i, b_j), sig += d(b_j)   [local, run-summed]
 //   edge (a, b_j): g += t(a, b_i) + t(b_i, b_j), sig += d(b_i)   [local]
 //   edge (b_i, b_j): g += t(a, b_i) + t(a, b_j), sig += d(a)     [global, coalesced]
+template <typename AT>
 __device__ __forceinline__ void gather_credit(bool found, int i, int j, int k, const u32* sT, const int* sD, int da,
                                               EdgeArrays& e, u64* sG, u64* sSg) {
     u64 gi = 0, di = 0;
@@ -233,8 +274,8 @@ __device__ __forceinline__ void gather_credit(bool found, int i, int j, int k, c
         di = (u64)sD[j];
         atomicAdd(&sG[j], tai + tij);
         atomicAdd(&sSg[j], (u64)sD[i]);
-        atomicAdd(&e.g[k], tai + taj);
-        atomicAdd(&e.sig[k], (u64)da);
+        acc_add<AT>(e.g, k, tai + taj);
+        acc_add<AT>(e.sig, k, (u64)da);
     }
     // lanes of a wavefront hold non-decreasing i (idle lanes a larger sentinel, zero values)
     bool last;
@@ -246,17 +287,19 @@ __device__ __forceinline__ void gather_credit(bool found, int i, int j, int k, c
     }
 }
 
+template <typename AT>
 __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restrict__ list, int nlist,
                                                            const int* __restrict__ optr,
                                                            const int* __restrict__ ocol,
                                                            const int* __restrict__ ndeg, EdgeArrays e) {
-    __shared__ int sS[4][GLT_WAVE];
     __shared__ int sOb[4][GLT_WAVE];
     __shared__ int sPre[4][GLT_WAVE];
     __shared__ u32 sT[4][GLT_WAVE];
     __shared__ int sD[4][GLT_WAVE];
     __shared__ u64 sG[4][GLT_WAVE];
     __shared__ u64 sSg[4][GLT_WAVE];
+    __shared__ int hk[4][SH_SIZE];
+    __shared__ unsigned char hv[4][SH_SIZE];
     const int w = threadIdx.x / GLT_WAVE, l = glt_lane();
     const int idx = blockIdx.x * 4 + w;
     const bool active = idx < nlist;
@@ -264,7 +307,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
     const int o0 = active ? optr[a] : 0;
     const int s = active ? optr[a + 1] - o0 : 0;
     const int da = active ? ndeg[a] : 0;
-    int b = 0x7fffffff, ob = 0, db = 0;
+    int b = 0, ob = 0, db = 0;
     u32 tb = 0;
     int degb = 0;
     if (l < s) {
@@ -273,30 +316,32 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
     }
     const int inc = wave_incl_scan(db);
     const int total = __shfl(inc, GLT_WAVE - 1, GLT_WAVE);
-    sS[w][l] = b; sOb[w][l] = ob; sPre[w][l] = inc - db; sT[w][l] = tb; sD[w][l] = degb;
+    sOb[w][l] = ob; sPre[w][l] = inc - db; sT[w][l] = tb; sD[w][l] = degb;
     sG[w][l] = 0; sSg[w][l] = 0;
+    hk[w][l] = -1; hk[w][l + GLT_WAVE] = -1;
     __syncthreads();
+    if (l < s) sh_insert(hk[w], hv[w], b, l);
+    __syncthreads();
+    int i = 0;
     for (int q0 = 0; q0 < total; q0 += GLT_WAVE) {
         const int q = q0 + l;
-        int i = 0x3fffffff, j = 0, k = 0;
-        bool found = false;
+        int key = 0x3fffffff, j = -1, k = 0;
         if (q < total) {
-            i = upper_idx(sPre[w], s, q);
+            i = advance_idx(sPre[w], s, q, i);
+            key = i;
             k = sOb[w][i] + (q - sPre[w][i]);
-            const int x = ocol[k];
-            j = lower_bound_i32(sS[w], i + 1, s, x);
-            found = (j < s && sS[w][j] == x);
+            j = sh_find(hk[w], hv[w], ocol[k]);
         }
-        gather_credit(found, i, j, k, sT[w], sD[w], da, e, sG[w], sSg[w]);
+        gather_credit<AT>(j >= 0, key, j, k, sT[w], sD[w], da, e, sG[w], sSg[w]);
     }
     __syncthreads();
     if (l < s) {
-        if (sG[w][l]) atomicAdd(&e.g[o0 + l], sG[w][l]);
-        if (sSg[w][l]) atomicAdd(&e.sig[o0 + l], sSg[w][l]);
+        if (sG[w][l]) acc_add<AT>(e.g, o0 + l, sG[w][l]);
+        if (sSg[w][l]) acc_add<AT>(e.sig, o0 + l, sSg[w][l]);
     }
 }
 
-template <bool GM>
+template <bool GM, typename AT>
 __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict__ list, int nlist, int smax,
                                                           const int* __restrict__ optr,
                                                           const int* __restrict__ ocol,
@@ -335,23 +380,24 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict
     const int total = carry;
     __syncthreads();
     const int rounds = (total + TB_THREADS - 1) / TB_THREADS;
+    int ii = 0;
     for (int r = 0; r < rounds; r++) {
         const int q = r * TB_THREADS + tid;
         int i = 0x3fffffff, j = 0, k = 0;
         bool found = false;
         if (q < total) {
-            i = upper_idx(sPre, s, q);
+            i = ii = advance_idx(sPre, s, q, ii);
             k = sOb[i] + (q - sPre[i]);
             const int x = ocol[k];
             j = lower_bound_i32(sS, i + 1, s, x);
             found = (j < s && sS[j] == x);
         }
-        gather_credit(found, i, j, k, sT, sD, da, e, sG, sSg);
+        gather_credit<AT>(found, i, j, k, sT, sD, da, e, sG, sSg);
     }
     __syncthreads();
     for (int i = tid; i < s; i += TB_THREADS) {
-        if (sG[i]) atomicAdd(&e.g[o0 + i], sG[i]);
-        if (sSg[i]) atomicAdd(&e.sig[o0 + i], sSg[i]);
+        if (sG[i]) acc_add<AT>(e.g, o0 + i, sG[i]);
+        if (sSg[i]) acc_add<AT>(e.sig, o0 + i, sSg[i]);
     }
 }
 
@@ -375,7 +421,7 @@ __device__ __forceinline__ void wedge_range(int y, int s, const int* __restrict_
 #define WW_TABLE 512   // per-wave hash entries; wave-path vertices have <= WW_TABLE/2 wedges
 
 // One wavefront per bottom vertex y with at most WW_TABLE/2 wedges.
-template <bool PE>
+template <bool PE, typename AT>
 __global__ __launch_bounds__(256) void k_wedge_wave(const int* __restrict__ list, int nlist,
                                                     const int* __restrict__ nrp, const int* __restrict__ ncol,
                                                     const int* __restrict__ optr, const int* __restrict__ ocol,
@@ -406,10 +452,11 @@ __global__ __launch_bounds__(256) void k_wedge_wave(const int* __restrict__ list
         wave_sync();
         sK0[w4][l] = k0; sPre[w4][l] = inc - len;
         wave_sync();
+        int ii = 0;
         for (int q0 = 0; q0 < tot; q0 += GLT_WAVE) {
             const int q = q0 + l;
             if (q < tot) {
-                const int i = upper_idx(sPre[w4], nsrc, q);
+                const int i = ii = advance_idx(sPre[w4], nsrc, q, ii);
                 const int x = ocol[sK0[w4][i] + (q - sPre[w4][i])];
                 u32 h = hslot(x, mask);
                 while (true) {
@@ -440,25 +487,26 @@ __global__ __launch_bounds__(256) void k_wedge_wave(const int* __restrict__ list
             wave_sync();
             sK0[w4][l] = k0; sPre[w4][l] = inc - len; sB[w4][l] = 0;
             wave_sync();
+            int ii = 0;
             for (int q0 = 0; q0 < tot; q0 += GLT_WAVE) {
                 const int q = q0 + l;
                 int i = 0x7fffffff;
                 u32 c = 0;
                 if (q < tot) {
-                    i = upper_idx(sPre[w4], nsrc, q);
+                    i = ii = advance_idx(sPre[w4], nsrc, q, ii);
                     const int k = sK0[w4][i] + (q - sPre[w4][i]);
                     const int x = ocol[k];
                     u32 h = hslot(x, mask);
                     while (hkey[w4][h] != x) h = (h + 1) & mask;
                     c = hcnt[w4][h] - 1;
-                    if (c) atomicAdd(&e.P[k], (u64)c);
+                    if (c) acc_add<AT>(e.P, k, (u64)c);
                 }
                 bool last;
                 const u32 ssum = seg_sum_last(c, i, last);
                 if (last && ssum) atomicAdd(&sB[w4][i], ssum);
             }
             wave_sync();
-            if (s < re && sB[w4][l]) atomicAdd(&e.P[s2k[s]], (u64)sB[w4][l]);
+            if (s < re && sB[w4][l]) acc_add<AT>(e.P, s2k[s], (u64)sB[w4][l]);
         }
     }
     c4 = wave_sum(c4);
@@ -466,19 +514,24 @@ __global__ __launch_bounds__(256) void k_wedge_wave(const int* __restrict__ list
 }
 
 #define WB_THREADS 256
-#define WB_TABLE 4096           // LDS hash entries per workgroup
+#define WB_TABLE 2048           // LDS hash entries per workgroup (tops below the dense window)
+#define WB_DENSE 8192           // dense LDS counters for the highest-ranked tops
 #define WB_STACK 96
 
-// One workgroup per bottom vertex with many wedges.  The x-range [lo, hi) is split in
-// halves whenever a range holds more distinct tops than `limit` (<= WB_TABLE/2); a range is
-// credited only after its count phase completed without overflow, so no wedge is credited
-// twice.
-template <bool PE>
+// One workgroup per bottom vertex with many wedges.  Tops x in the dense window
+// [n - dense, n) (the highest-ranked vertices, which close most wedges of a degree-ordered
+// graph) are counted in a dense LDS array; lower tops go to an LDS hash.  The x-range
+// [lo, hi) is split in halves whenever its hashed part holds more distinct tops than
+// `limit` (<= WB_TABLE/2); a range is credited only after its count phase completed without
+// overflow, so no wedge is credited twice.
+template <bool PE, typename AT>
 __global__ __launch_bounds__(WB_THREADS) void k_wedge_blk(const int* __restrict__ list, int nlist, int n, int limit,
-                                                         const int* __restrict__ nrp, const int* __restrict__ ncol,
-                                                         const int* __restrict__ optr, const int* __restrict__ ocol,
-                                                         const int* __restrict__ s2k, EdgeArrays e,
-                                                         u64* __restrict__ gsum, const int* __restrict__ ngid) {
+                                                         int dense, const int* __restrict__ nrp,
+                                                         const int* __restrict__ ncol, const int* __restrict__ optr,
+                                                         const int* __restrict__ ocol, const int* __restrict__ s2k,
+                                                         EdgeArrays e, u64* __restrict__ gsum,
+                                                         const int* __restrict__ ngid) {
+    __shared__ u32 dcnt[WB_DENSE];
     __shared__ int hkey[WB_TABLE];
     __shared__ u32 hcnt[WB_TABLE];
     __shared__ int sK0[WB_THREADS];
@@ -492,6 +545,8 @@ __global__ __launch_bounds__(WB_THREADS) void k_wedge_blk(const int* __restrict_
     const int y = list[blockIdx.x];
     const int rb = nrp[y], re = nrp[y + 1];
     const u32 mask = WB_TABLE - 1;
+    const int base = max(n - dense, y + 1);   // tops >= base are counted densely
+    const int nd = n - base;                  // dense counters in use (<= dense <= WB_DENSE)
     if (tid == 0) { stLo[0] = y + 1; stHi[0] = n; sp = 1; }
     u64 c4 = 0;
     __syncthreads();
@@ -502,6 +557,7 @@ __global__ __launch_bounds__(WB_THREADS) void k_wedge_blk(const int* __restrict_
         __syncthreads();
         if (tid == 0) { sp--; distinct = 0; ovf = 0; }
         for (int q = tid; q < WB_TABLE; q += WB_THREADS) { hkey[q] = -1; hcnt[q] = 0; }
+        for (int q = tid; q < nd; q += WB_THREADS) dcnt[q] = 0;
         __syncthreads();
         // count phase
         for (int c0 = rb; c0 < re; c0 += WB_THREADS) {
@@ -520,10 +576,15 @@ __global__ __launch_bounds__(WB_THREADS) void k_wedge_blk(const int* __restrict_
             const int nsrc = min(WB_THREADS, re - c0);
             sK0[tid] = k0; sPre[tid] = ex;
             __syncthreads();
+            int ii = 0;
             for (int q = tid; q < tot; q += WB_THREADS) {
                 if (*(volatile int*)&ovf) break;
-                const int i = upper_idx(sPre, nsrc, q);
+                const int i = ii = advance_idx(sPre, nsrc, q, ii);
                 const int x = ocol[sK0[i] + (q - sPre[i])];
+                if (x >= base) {
+                    atomicAdd(&dcnt[x - base], 1u);
+                    continue;
+                }
                 u32 h = hslot(x, mask);
                 while (true) {
                     int cur = hkey[h];
@@ -554,6 +615,10 @@ __global__ __launch_bounds__(WB_THREADS) void k_wedge_blk(const int* __restrict_
             const u64 c = hcnt[q];
             c4 += c * (c - (c > 0)) / 2;
         }
+        for (int q = tid; q < nd; q += WB_THREADS) {
+            const u64 c = dcnt[q];
+            c4 += c * (c - (c > 0)) / 2;
+        }
         if (PE) {
             for (int c0 = rb; c0 < re; c0 += WB_THREADS) {
                 const int s = c0 + tid;
@@ -572,25 +637,30 @@ __global__ __launch_bounds__(WB_THREADS) void k_wedge_blk(const int* __restrict_
                 sK0[tid] = k0; sPre[tid] = ex; sB[tid] = 0;
                 __syncthreads();
                 const int rounds = (tot + WB_THREADS - 1) / WB_THREADS;
+                int ii = 0;
                 for (int r = 0; r < rounds; r++) {
                     const int q = r * WB_THREADS + tid;
                     int i = 0x7fffffff;
                     u64 c = 0;
                     if (q < tot) {
-                        i = upper_idx(sPre, nsrc, q);
+                        i = ii = advance_idx(sPre, nsrc, q, ii);
                         const int k = sK0[i] + (q - sPre[i]);
                         const int x = ocol[k];
-                        u32 h = hslot(x, mask);
-                        while (hkey[h] != x) h = (h + 1) & mask;
-                        c = hcnt[h] - 1;
-                        if (c) atomicAdd(&e.P[k], c);
+                        if (x >= base) {
+                            c = dcnt[x - base] - 1;
+                        } else {
+                            u32 h = hslot(x, mask);
+                            while (hkey[h] != x) h = (h + 1) & mask;
+                            c = hcnt[h] - 1;
+                        }
+                        if (c) acc_add<AT>(e.P, k, c);
                     }
                     bool last;
                     const u64 ssum = seg_sum_last(c, i, last);
                     if (last && ssum) atomicAdd(&sB[i], ssum);
                 }
                 __syncthreads();
-                if (s < re && sB[tid]) atomicAdd(&e.P[s2k[s]], sB[tid]);
+                if (s < re && sB[tid]) acc_add<AT>(e.P, s2k[s], sB[tid]);
                 __syncthreads();
             }
         }
@@ -656,7 +726,7 @@ __device__ __forceinline__ void wave_sum128(u64& lo, u64& hi) {
 #define CB_EPT 4
 #define NCS 13
 
-template <bool PE>
+template <bool PE, typename AT>
 __global__ __launch_bounds__(CB_THREADS) void k_combine(const int* __restrict__ eid2k, EdgeArrays e,
                                                         const int* __restrict__ ocol,
                                                         const int* __restrict__ ndeg, const u64* __restrict__ tri,
@@ -680,11 +750,11 @@ __global__ __launch_bounds__(CB_THREADS) void k_combine(const int* __restrict__ 
         const int64_t D = (int64_t)n - 2 - t - su - sv;
         int64_t K = 0, Q = 0;
         if (PE) {
-            K = (int64_t)e.K[k];
-            const int64_t P = (int64_t)e.P[k];
-            const int64_t A = (int64_t)e.g[k] - 2 * t - 4 * K;     // edges T-S_u plus T-S_v
+            K = (int64_t)acc_get<AT>(e.K, k);
+            const int64_t P = (int64_t)acc_get<AT>(e.P, k);
+            const int64_t A = (int64_t)acc_get<AT>(e.g, k) - 2 * t - 4 * K;     // edges T-S_u plus T-S_v
             Q = P - 2 * K - A;                                      // edges S_u-S_v
-            const int64_t sigT = (int64_t)e.sig[k];
+            const int64_t sigT = (int64_t)acc_get<AT>(e.sig, k);
             const int64_t E2 = (int64_t)((tri[u] + tri[v]) >> 1) - 2 * t - 2 * K - A;   // inside S_u plus inside S_v
             const int64_t ETD = sigT - 2 * t - 2 * K - A;           // edges T-D
             const int64_t ESD = ((int64_t)sdeg[u] - dv - sigT) + ((int64_t)sdeg[v] - du - sigT) - su - sv - 2 * E2 - A -
@@ -830,6 +900,34 @@ __global__ __launch_bounds__(CB_THREADS) void k_combine_graphs(const int64_t* __
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// heaviest-first order of the workgroup work lists (the paper's edge order: hardest jobs
+// first, Section 4.3), so the longest jobs do not start last and run alone
+// ---------------------------------------------------------------------------------------
+// mode 0: work = wedges of y (wcnt); mode 1: work = out-degree of x
+__global__ void k_work_keys(const int* __restrict__ list, int nlist, int mode, const u64* __restrict__ wcnt,
+                            const int* __restrict__ optr, u64* __restrict__ keys, u32* __restrict__ vals) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nlist) return;
+    const int x = list[i];
+    const u64 w = mode == 0 ? wcnt[x] : (u64)(optr[x + 1] - optr[x]);
+    keys[i] = ((1ull << 40) - 1) - (w < (1ull << 40) ? w : (1ull << 40) - 1);
+    vals[i] = (u32)x;
+}
+
+__global__ void k_copy_list(const u32* __restrict__ vals, int nlist, int* __restrict__ list) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nlist) list[i] = (int)vals[i];
+}
+
+static void sort_heaviest_first(const Dev& d, int* list, int nlist, int mode, hipStream_t st) {
+    if (nlist < 2) return;
+    const unsigned g = (unsigned)((nlist + 255) / 256);
+    hipLaunchKernelGGL(k_work_keys, dim3(g), dim3(256), 0, st, list, nlist, mode, d.wcnt, d.optr, d.key0, d.val0);
+    const int cur = launch_radix_sort(d.key0, d.val0, d.key1, d.val1, nlist, 40, d.rs_counts, d.rs_tmp, st);
+    hipLaunchKernelGGL(k_copy_list, dim3(g), dim3(256), 0, st, cur ? d.val1 : d.val0, nlist, list);
+}
+
 static inline int combine_blocks(int m) { return (int)(((int64_t)m + CB_THREADS * CB_EPT - 1) / (CB_THREADS * CB_EPT)); }
 
 // ---------------------------------------------------------------------------------------
@@ -837,20 +935,23 @@ static inline int combine_blocks(int m) { return (int)(((int64_t)m + CB_THREADS 
 // ---------------------------------------------------------------------------------------
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
-void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st, hipEvent_t* ev) {
+template <typename AT>
+static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st, hipEvent_t* ev) {
     const int n = d.n, m = d.m;
     u64* gsum = d.gsum;                   // [graph][NSUMS]: 3 x 4-cliques and non-induced 4-cycles
     launch_fill<u64>(gsum, (int64_t)(d.ngraphs > 0 ? d.ngraphs : 1) * NSUMS, 0ull, st);
     const int* tl = d.tlist;
     const int* cnt = hc;                  // TB_N counts, WB_N counts, TB_N maxima
     const EdgeArrays e = d.e;
+    for (int bkt = TB_BLK1; bkt <= TB_GLOBAL; bkt++) sort_heaviest_first(d, d.tlist + (int64_t)bkt * n, cnt[bkt], 1, st);
+    sort_heaviest_first(d, d.wlist + (int64_t)WB_BLK * n, hc[TB_N + WB_BLK], 0, st);
     // triangle / 4-clique pass
     if (cnt[TB_WAVE] > 0) {
         if (per_edge)
-            hipLaunchKernelGGL(k_tri_wave<true>, dim3(cdiv(cnt[TB_WAVE], 4)), dim3(TB_THREADS), 0, st,
+            hipLaunchKernelGGL((k_tri_wave<true, AT>), dim3(cdiv(cnt[TB_WAVE], 4)), dim3(TB_THREADS), 0, st,
                                tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, e, gsum, d.ngid);
         else
-            hipLaunchKernelGGL(k_tri_wave<false>, dim3(cdiv(cnt[TB_WAVE], 4)), dim3(TB_THREADS), 0, st,
+            hipLaunchKernelGGL((k_tri_wave<false, AT>), dim3(cdiv(cnt[TB_WAVE], 4)), dim3(TB_THREADS), 0, st,
                                tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, e, gsum, d.ngid);
     }
     for (int bkt = TB_BLK1; bkt <= TB_GLOBAL; bkt++) {
@@ -868,18 +969,18 @@ void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hi
             for (int64_t off = 0; off < c; off += grp) {
                 const int cc = (int)((c - off < grp) ? (c - off) : grp);
                 if (per_edge)
-                    hipLaunchKernelGGL((k_tri_blk<true, true>), dim3(cc), dim3(TB_THREADS), lds, st, lst + off, cc,
+                    hipLaunchKernelGGL((k_tri_blk<true, true, AT>), dim3(cc), dim3(TB_THREADS), lds, st, lst + off, cc,
                                        smax, d.optr, d.ocol, e, gsum, d.gscratch, d.ngid);
                 else
-                    hipLaunchKernelGGL((k_tri_blk<false, true>), dim3(cc), dim3(TB_THREADS), lds, st, lst + off, cc,
+                    hipLaunchKernelGGL((k_tri_blk<false, true, AT>), dim3(cc), dim3(TB_THREADS), lds, st, lst + off, cc,
                                        smax, d.optr, d.ocol, e, gsum, d.gscratch, d.ngid);
             }
         } else {
             if (per_edge)
-                hipLaunchKernelGGL((k_tri_blk<true, false>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax,
+                hipLaunchKernelGGL((k_tri_blk<true, false, AT>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax,
                                    d.optr, d.ocol, e, gsum, d.gscratch, d.ngid);
             else
-                hipLaunchKernelGGL((k_tri_blk<false, false>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax,
+                hipLaunchKernelGGL((k_tri_blk<false, false, AT>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax,
                                    d.optr, d.ocol, e, gsum, d.gscratch, d.ngid);
         }
     }
@@ -887,7 +988,7 @@ void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hi
     // gather pass
     if (per_edge) {
         if (cnt[TB_WAVE] > 0)
-            hipLaunchKernelGGL(k_gather_wave, dim3(cdiv(cnt[TB_WAVE], 4)), dim3(TB_THREADS), 0, st,
+            hipLaunchKernelGGL(k_gather_wave<AT>, dim3(cdiv(cnt[TB_WAVE], 4)), dim3(TB_THREADS), 0, st,
                                tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, d.ndeg, e);
         for (int bkt = TB_BLK1; bkt <= TB_GLOBAL; bkt++) {
             const int c = cnt[bkt];
@@ -900,11 +1001,11 @@ void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hi
                 if (grp < 1) grp = 1;
                 for (int64_t off = 0; off < c; off += grp) {
                     const int cc = (int)((c - off < grp) ? (c - off) : grp);
-                    hipLaunchKernelGGL(k_gather_blk<true>, dim3(cc), dim3(TB_THREADS), gather_blk_lds(smax, true), st,
+                    hipLaunchKernelGGL((k_gather_blk<true, AT>), dim3(cc), dim3(TB_THREADS), gather_blk_lds(smax, true), st,
                                        lst + off, cc, smax, d.optr, d.ocol, d.ndeg, e, (u64*)d.gscratch);
                 }
             } else {
-                hipLaunchKernelGGL(k_gather_blk<false>, dim3(c), dim3(TB_THREADS), gather_blk_lds(smax, false), st,
+                hipLaunchKernelGGL((k_gather_blk<false, AT>), dim3(c), dim3(TB_THREADS), gather_blk_lds(smax, false), st,
                                    lst, c, smax, d.optr, d.ocol, d.ndeg, e, (u64*)d.gscratch);
             }
         }
@@ -914,23 +1015,23 @@ void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hi
     const int* wc = hc + TB_N;
     if (wc[WB_WAVE] > 0) {
         if (per_edge)
-            hipLaunchKernelGGL(k_wedge_wave<true>, dim3(cdiv(wc[WB_WAVE], 4)), dim3(256), 0, st,
+            hipLaunchKernelGGL((k_wedge_wave<true, AT>), dim3(cdiv(wc[WB_WAVE], 4)), dim3(256), 0, st,
                                d.wlist + (int64_t)WB_WAVE * n, wc[WB_WAVE], d.nrp, d.ncol, d.optr, d.ocol, d.s2k,
                                e, gsum, d.ngid);
         else
-            hipLaunchKernelGGL(k_wedge_wave<false>, dim3(cdiv(wc[WB_WAVE], 4)), dim3(256), 0, st,
+            hipLaunchKernelGGL((k_wedge_wave<false, AT>), dim3(cdiv(wc[WB_WAVE], 4)), dim3(256), 0, st,
                                d.wlist + (int64_t)WB_WAVE * n, wc[WB_WAVE], d.nrp, d.ncol, d.optr, d.ocol, d.s2k,
                                e, gsum, d.ngid);
     }
     if (wc[WB_BLK] > 0) {
         if (per_edge)
-            hipLaunchKernelGGL(k_wedge_blk<true>, dim3(wc[WB_BLK]), dim3(WB_THREADS), 0, st,
-                               d.wlist + (int64_t)WB_BLK * n, wc[WB_BLK], n, d.wedge_limit, d.nrp, d.ncol, d.optr,
-                               d.ocol, d.s2k, e, gsum, d.ngid);
+            hipLaunchKernelGGL((k_wedge_blk<true, AT>), dim3(wc[WB_BLK]), dim3(WB_THREADS), 0, st,
+                               d.wlist + (int64_t)WB_BLK * n, wc[WB_BLK], n, d.wedge_limit, d.wedge_dense, d.nrp,
+                               d.ncol, d.optr, d.ocol, d.s2k, e, gsum, d.ngid);
         else
-            hipLaunchKernelGGL(k_wedge_blk<false>, dim3(wc[WB_BLK]), dim3(WB_THREADS), 0, st,
-                               d.wlist + (int64_t)WB_BLK * n, wc[WB_BLK], n, d.wedge_limit, d.nrp, d.ncol, d.optr,
-                               d.ocol, d.s2k, e, gsum, d.ngid);
+            hipLaunchKernelGGL((k_wedge_blk<false, AT>), dim3(wc[WB_BLK]), dim3(WB_THREADS), 0, st,
+                               d.wlist + (int64_t)WB_BLK * n, wc[WB_BLK], n, d.wedge_limit, d.wedge_dense, d.nrp,
+                               d.ncol, d.optr, d.ocol, d.s2k, e, gsum, d.ngid);
     }
     if (ev) (void)hipEventRecord(ev[2], st);
     // vertex pass + combine
@@ -946,10 +1047,10 @@ void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hi
                            d.ocol, d.ndeg, d.gparts);
     } else if (m > 0) {
         if (per_edge)
-            hipLaunchKernelGGL(k_combine<true>, dim3(nb), dim3(CB_THREADS), 0, st, d.eid2k, e, d.ocol, d.ndeg, d.tri,
+            hipLaunchKernelGGL((k_combine<true, AT>), dim3(nb), dim3(CB_THREADS), 0, st, d.eid2k, e, d.ocol, d.ndeg, d.tri,
                                d.sdeg, n, m, out_pe, d.sums, d.err);
         else
-            hipLaunchKernelGGL(k_combine<false>, dim3(nb), dim3(CB_THREADS), 0, st, d.eid2k, e, d.ocol, d.ndeg, d.tri,
+            hipLaunchKernelGGL((k_combine<false, AT>), dim3(nb), dim3(CB_THREADS), 0, st, d.eid2k, e, d.ocol, d.ndeg, d.tri,
                                d.sdeg, n, m, out_pe, d.sums, d.err);
         hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, d.sums, nb, d.final_sums);
     } else {
@@ -958,8 +1059,16 @@ void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hi
     if (ev) (void)hipEventRecord(ev[3], st);
 }
 
+void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st, hipEvent_t* ev) {
+    if (d.acc32)
+        count_passes<u32>(d, per_edge, hc, out_pe, st, ev);
+    else
+        count_passes<u64>(d, per_edge, hc, out_pe, st, ev);
+}
+
 int glt_combine_blocks(int m) { return combine_blocks(m); }
 // largest out-degree the block passes accept (LDS holds 5 ints per neighbour of a)
 int glt_max_out_degree() { return 3200; }
 int glt_wedge_table() { return WB_TABLE; }
+int glt_wedge_dense() { return WB_DENSE; }
 int glt_wave_table() { return WW_TABLE; }

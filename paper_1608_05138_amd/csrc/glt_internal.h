@@ -88,7 +88,9 @@ struct Dev {
     const int** glcol;    // device array of per-graph local-column pointers [ngraphs]
     // tuning (defaults; overridable per handle for testing)
     int wedge_wave_max;   // wedge-pass vertices with at most this many wedges use one wavefront
-    int wedge_limit;      // distinct tops per hash range before the range is split
+    int wedge_limit;      // distinct hashed tops per range before the range is split
+    int wedge_dense;      // width of the dense window of highest-ranked tops
+    int acc32;            // per-edge accumulators fit 32 bits (maximum degree <= 46340)
 };
 
 // Host-side entry points of the device pipeline (count.hip).

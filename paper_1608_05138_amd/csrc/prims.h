@@ -95,6 +95,21 @@ __device__ __forceinline__ int upper_idx(const T* a, int n, T q) {
     return lo;
 }
 
+// Like upper_idx, starting from a previous answer i for a smaller q: gallops forward, then
+// bisects.  Cheap when consecutive queries of a lane move across few entries.
+template <typename T>
+__device__ __forceinline__ int advance_idx(const T* a, int n, T q, int i) {
+    if (i + 1 >= n || a[i + 1] > q) return i;
+    int step = 1, lo = i + 1;
+    while (lo + step < n && a[lo + step] <= q) { lo += step; step <<= 1; }
+    int hi = min(lo + step, n);   // a[lo] <= q, answer in [lo, hi)
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] <= q) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 // first index in [lo, hi) with a[idx] >= x (hi if none)
 __device__ __forceinline__ int lower_bound_i32(const int* a, int lo, int hi, int x) {
     while (lo < hi) {

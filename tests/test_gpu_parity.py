@@ -164,19 +164,22 @@ def test_complete_bipartite(ctx):
     np.testing.assert_array_equal(pe, want)
 
 
-def test_forced_workgroup_path_and_range_splitting(monkeypatch):
-    """Wedge pass with every vertex on the workgroup path and a tiny distinct-top limit,
-    so hash ranges are split many times; results must not change."""
+@pytest.mark.parametrize("dense", ["0", "7"])
+def test_forced_workgroup_path_and_range_splitting(monkeypatch, dense):
+    """Wedge pass with every vertex on the workgroup path, a tiny distinct-top limit (hash
+    ranges split many times) and no or a tiny dense window of top counters; results must
+    not change."""
     import paper_1608_05138_amd as glt
     monkeypatch.setenv("GLT_WEDGE_WAVE_MAX", "0")
     monkeypatch.setenv("GLT_WEDGE_RANGE_LIMIT", "3")
+    monkeypatch.setenv("GLT_WEDGE_DENSE", dense)
     c = glt.Context(0)
     try:
         for n, m, seed in ((3000, 30000, 31), (800, 24000, 32)):
             rp, col = gg.chung_lu(n, m, 2.1, float(n - 1), seed)
-            check_vs_oracle(c, f"forced-split-{n}-{m}", n, rp, col)
+            check_vs_oracle(c, f"forced-split-{n}-{m}-dense{dense}", n, rp, col)
         N, (rp, col) = gg.complete_bipartite(40, 47)
-        check_vs_oracle(c, "forced-split-K40,47", N, rp, col)
+        check_vs_oracle(c, f"forced-split-K40,47-dense{dense}", N, rp, col)
     finally:
         c.close()
 
