@@ -352,3 +352,25 @@ def test_er_expectation_smoke():
         expect = comb(n, 4) * a * p**e * (1 - p)**(6 - e)
         if expect > 2000:
             assert abs(X[gid - 1] - expect) / expect < 0.25, (gid, X[gid - 1], expect)
+
+
+def test_stored_chung_lu_1m_counts_consistent():
+    """The stored oracle counts of the 1M-vertex Chung-Lu workload belong to the graph the
+    generator makes today (content hash) and satisfy the partition identities: X1 + X2 covers
+    all vertex pairs, X3..X6 all triples, X7..X17 all quadruples (Section 2's graphlet
+    classes)."""
+    import hashlib
+    import json
+    path = os.path.join(os.path.dirname(__file__), "golden", "chung_lu_1m_global.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored counts")
+    with open(path) as f:
+        g = json.load(f)
+    X = [int(x) for x in g["X"]]
+    n, m = g["n"], g["m"]
+    assert X[0] == m and X[0] + X[1] == comb(n, 2)
+    assert sum(X[2:6]) == comb(n, 3)
+    assert sum(X[6:17]) == comb(n, 4)
+    n2, (rp, col) = gg.config_chung_lu_1m()
+    assert n2 == n and col.size == 2 * m
+    assert hashlib.sha256(np.ascontiguousarray(col).tobytes()).hexdigest()[:16] == g["col_sha256_prefix"]
