@@ -21,6 +21,32 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 
+# Measured HBM traffic (bytes per execution of each kernel group) of the per-edge run on
+# chung_lu_1m: rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, each a separate run of
+# `python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline`, scaled by the copy calibration
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0; see --copy-probe).  The figures belong to the kernel
+# source with the hash below and are reported only while it is unchanged.
+TRAFFIC = {
+    "source": "paper_1608_05138_amd/csrc/count.hip",
+    "sha256": "a351f08c094660544f995729ea601d74cc711d1c7d6725863fd0b4e4dbe3d59e",
+    "workload": "chung_lu_1m", "per_edge": True,
+    "bytes": {"tri_wave": 3676166496, "tri_wg": 4328773920, "gather_wave": 2080813952,
+              "gather_wg": 3374473216, "wedge_wave": 3967000032, "wedge_wg": 10492788064},
+}
+
+
+def measured_traffic(workload, per_edge, group):
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), TRAFFIC["source"])
+    try:
+        with open(src, "rb") as f:
+            ok = hashlib.sha256(f.read()).hexdigest() == TRAFFIC["sha256"]
+    except OSError:
+        ok = False
+    if not ok or workload != TRAFFIC["workload"] or bool(per_edge) != TRAFFIC["per_edge"]:
+        return None
+    return TRAFFIC["bytes"].get(group)
+
 WORKLOADS = {
     "chung_lu_1m": ("Chung-Lu n=1,000,000 m=10,000,000 exponent 2.1 weight cap 50,000, int32 CSR",
                     "config_chung_lu_1m"),
@@ -28,7 +54,10 @@ WORKLOADS = {
     "rmat_s22": ("R-MAT scale 22 edge factor 16 (0.57,0.19,0.19,0.05), int64 offsets", "config_rmat_s22"),
 }
 
-PHASES = ["prep", "triangle_4clique", "gather", "wedge_4cycle", "combine"]
+# kernel groups timed by the library (HIP events on the call's stream) and their kernels
+GROUPS = {"tri_wave": "k_tri_wave", "tri_wg": "k_tri_blk", "gather_wave": "k_gather_wave",
+          "gather_wg": "k_gather_blk", "wedge_wave": "k_wedge (wave and mid classes, 64-thread groups)",
+          "wedge_wg": "k_wedge (workgroup class, 256-thread groups)"}
 
 
 def _gen_batch_graph(spec):
@@ -182,14 +211,14 @@ def bench_batch(args):
     for _ in range(args.warmup):
         res = ctx.count_batch(dpk, stream=stream)
     torch.cuda.synchronize()
-    phase_ms = np.zeros(5)
+    timings = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         res = ctx.count_batch(dpk, stream=stream)
-        phase_ms += np.array(ctx.last_timing())
+        timings.append(ctx.last_timing())
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    phase_ms /= args.steps
+    timing = mean_timing(timings)
     work = ctx.last_work()
     # plain per-graph path over the same device-resident graphs (one call per graph)
     per_graph_ms = None
@@ -208,10 +237,7 @@ def bench_batch(args):
         torch.cuda.synchronize()
         per_graph_ms = (time.perf_counter() - t0) * 1e3
         assert alone == res, "batched and per-graph counts differ"
-    pb = phase_bytes(work, sum(r[2] for r in res), per_edge=False)
-    timed = {p: phase_ms[i] for i, p in enumerate(PHASES) if p in pb}
-    dom = max(timed, key=timed.get)
-    achieved = pb[dom] / (timed[dom] * 1e-3) / 1e9
+    maxdeg = int(np.diff(packed["row_ptr"]).max()) if packed["row_ptr"].size else 0
     line = {
         "metric": "graphs/sec for exact 4-node motif counts of a 10,000-graph batch (1 GPU)",
         "value": len(graphs) / (ms * 1e-3), "unit": "graphs/s",
@@ -224,34 +250,50 @@ def bench_batch(args):
         "edges_per_s": m_total / (ms * 1e-3),
         "per_graph_path": None if per_graph_ms is None else {
             "ms": round(per_graph_ms, 1), "graphs_per_s": len(graphs) / (per_graph_ms * 1e-3)},
-        "phases_ms": {p: round(float(v), 4) for p, v in zip(PHASES, phase_ms)},
-        "work": {k: int(v) for k, v in work.items()},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "alg_bytes": int(pb[dom]), "kernel_ms": round(float(timed[dom]), 4)},
+        "kernel_groups_ms": {k: round(float(v), 4) for k, v in timing.items()},
+        "work": work,
+        "roofline": roofline(timing, work, False, acc_width(maxdeg)),
     }
     ctx.close()
     print(json.dumps(line), flush=True)
 
 
-def phase_bytes(work, X3, per_edge=True):
-    """Algorithmic bytes of each counting pass (section Measurement)."""
-    m, L, W = work["m"], work["tri_list_entries"], work["wedges"]
-    if not per_edge:
-        return {
-            # out-lists scanned once (4 B ids) + one 4 B triangle credit per triangle
-            "triangle_4clique": 4 * (m + L) + 4 * X3,
-            # CSR rows (4 B) + per wedge the top's id (4 B)
-            "wedge_4cycle": 4 * 2 * m + 4 * W,
-        }
-    return {
-        # out-lists scanned once (4 B ids) + triangle credits (t 4 B, K 8 B) + per-edge record
-        "triangle_4clique": 4 * (m + L) + 12 * X3 + 12 * m,
-        # the same scan + three 8 B credits per triangle-edge incidence
-        "gather": 4 * (m + L) + 3 * 3 * 8 * X3,
-        # CSR rows (4 B) + per wedge the top's id (4 B) and one 8 B credit
-        "wedge_4cycle": 4 * 2 * m + 12 * W,
+def group_bytes(work, per_edge, acc_bytes):
+    """Algorithmic bytes of each counting kernel group (section Measurement):
+    per triangle-pass list entry one 4 B id; per triangle a 4 B triangle credit plus (per-edge
+    mode) one 4-clique credit; per triangle in the gather pass two credits; per wedge one 4 B
+    top id plus (per-edge mode) one 4-cycle credit.  Credits are acc_bytes wide."""
+    ab = acc_bytes
+    out = {
+        "tri_wave": 4 * work["tri_list_wave"] + (4 + (ab if per_edge else 0)) * work["triangles_wave"],
+        "tri_wg": 4 * work["tri_list_wg"] + (4 + (ab if per_edge else 0)) * work["triangles_wg"],
+        "wedge_wave": (4 + (ab if per_edge else 0)) * work["wedges_wave"],
+        "wedge_wg": (4 + (ab if per_edge else 0)) * work["wedges_wg"],
     }
+    if per_edge:
+        out["gather_wave"] = 4 * work["tri_list_wave"] + 2 * ab * work["triangles_wave"]
+        out["gather_wg"] = 4 * work["tri_list_wg"] + 2 * ab * work["triangles_wg"]
+    return out
+
+
+def roofline(timing, work, per_edge, acc_bytes, workload=None):
+    gb = group_bytes(work, per_edge, acc_bytes)
+    dom = max(gb, key=lambda g: timing[g])
+    achieved = gb[dom] / (timing[dom] * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": GROUPS[dom], "group": dom, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(workload, per_edge, dom),
+            "alg_bytes": int(gb[dom]), "kernel_ms": round(float(timing[dom]), 4)}
+
+
+def mean_timing(samples):
+    keys = samples[0].keys()
+    return {k: sum(t[k] for t in samples) / len(samples) for k in keys}
+
+
+def acc_width(max_degree):
+    """Width of the per-edge accumulators the library uses for this maximum degree."""
+    return 4 if max_degree <= 46340 else 8
 
 
 def cpu_baseline(n, rp, col, budget_s=15.0):
@@ -340,26 +382,21 @@ def main():
     for _ in range(args.warmup):
         X, _ = ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
     torch.cuda.synchronize()
-    phase_ms = np.zeros(5)
+    timings = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         X, _ = ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
-        phase_ms += np.array(ctx.last_timing())
+        timings.append(ctx.last_timing())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    phase_ms /= args.steps
+    timing = mean_timing(timings)
     work = ctx.last_work()
-    print(f"[bench] {ms_per_step:.3f} ms/step; phases " +
-          ", ".join(f"{p}={v:.3f}" for p, v in zip(PHASES, phase_ms)), file=sys.stderr, flush=True)
+    print(f"[bench] {ms_per_step:.3f} ms/step; kernel groups " +
+          ", ".join(f"{k}={v:.3f}" for k, v in timing.items()), file=sys.stderr, flush=True)
 
-    pb = phase_bytes(work, X[2], per_edge)
-    timed = {p: phase_ms[i] for i, p in enumerate(PHASES) if p in pb}
-    dom = max(timed, key=timed.get)
-    achieved = pb[dom] / (timed[dom] * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "alg_bytes": int(pb[dom]), "kernel_ms": round(float(timed[dom]), 4)}
+    maxdeg = int(np.diff(rp.astype(np.int64)).max()) if n else 0
+    roof = roofline(timing, work, per_edge, acc_width(maxdeg), args.workload)
     line = {
         "metric": "edges/sec for exact 4-node motif counts (1 GPU)",
         "value": m / (ms_per_step * 1e-3),
@@ -371,8 +408,8 @@ def main():
         "config": {"workload": args.workload, "graph": desc, "n": n, "m": m,
                    "outputs": "global X1..X17 (u128) + 13 per-edge counts (u64)" if per_edge
                    else "global X1..X17 (u128)"},
-        "phases_ms": {p: round(float(v), 4) for p, v in zip(PHASES, phase_ms)},
-        "work": {k: int(v) for k, v in work.items()},
+        "kernel_groups_ms": {k: round(float(v), 4) for k, v in timing.items()},
+        "work": work,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

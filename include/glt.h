@@ -132,22 +132,62 @@ typedef struct {
 glt_status glt_count_batch(glt_ctx* ctx, const glt_batch* b, uint32_t flags, glt_u128* out, void* stream);
 
 /*
- * Timing breakdown of the last successful glt_count or glt_count_batch on this handle, in milliseconds
- * measured with HIP events on the call's stream: [0] validation + preprocessing (degree
- * order, sorted oriented CSR), [1] triangle / 4-clique pass, [2] per-edge gather pass,
- * [3] 4-cycle wedge pass, [4] combine + reduction.  Returns the number of entries
- * written (<= cap).
+ * Timing breakdown of the last successful glt_count or glt_count_batch on this handle, in
+ * milliseconds measured with HIP events on the call's stream, one entry per kernel group:
+ * [0] validation + preprocessing (degree order, sorted oriented CSR, work lists),
+ * [1] triangle / 4-clique pass, one wavefront per vertex, [2] the same, one workgroup per
+ * vertex, [3] per-edge gather pass, wavefront path, [4] the same, workgroup path,
+ * [5] 4-cycle wedge pass, wavefront path, [6] the same, workgroup path, [7] vertex sums,
+ * combine and reduction.  Returns the number of entries written (<= cap, at most 8).
  */
 int glt_last_timing(const glt_ctx* ctx, float* ms, int cap);
 
 /*
- * Work counters of the last successful glt_count or glt_count_batch on this handle: [0] n, [1] m,
- * [2] wedges y - w - x with x ranked above y and w (the 4-cycle pass's unit of work),
- * [3] out-list entries scanned by the triangle pass (sum over oriented edges (a,b) of
- * |N+(b)|).  Returns the number of entries written (<= cap).  Used to state the
- * algorithmic bytes of each pass.
+ * Work counters of the last successful glt_count or glt_count_batch on this handle:
+ * [0] n, [1] m, [2] wedges y - w - x (x ranked above y and w; the 4-cycle pass's unit of
+ * work) handled by the wavefront path, [3] the same by the workgroup path, [4] out-list
+ * entries scanned by the triangle pass (sum over oriented edges (a,b) of |N+(b)|), wavefront
+ * path, [5] the same, workgroup path, [6] triangles found by the wavefront path, [7] by the
+ * workgroup path.  Returns the number of entries written (<= cap, at most 8).  Used to state
+ * the algorithmic bytes of each kernel group.
  */
 int glt_last_work(const glt_ctx* ctx, uint64_t* out, int cap);
+
+/*
+ * Work schedule of a handle: how the counting passes split their work among size classes
+ * (Section 4.3 splits edges by cost between workers; here vertices are split by their work
+ * between wavefront and workgroup kernels).  Every schedule yields the same counts; only
+ * the speed differs.  Defaults: 256, 2048, 4096, 1024, 1.
+ */
+typedef struct {
+    int32_t wedge_wave_max;    /* 4-cycle pass: bottom vertices with at most this many wedges
+                                  run one per wavefront with an LDS hash only (0..256)        */
+    int32_t wedge_mid_max;     /* up to this many: one per wavefront with a dense window of
+                                  top counters and a hash; more: one per workgroup (>= 0)     */
+    int32_t wedge_dense;       /* width of the dense window of highest-ranked tops (0..4096)  */
+    int32_t wedge_range_limit; /* distinct hashed tops per range before it is halved (1..1024) */
+    int32_t tri_records;       /* 1: store each triangle once for the 4-clique sweep and the
+                                  gather pass when the record buffer fits; 0: re-scan lists  */
+    int32_t reserved[3];       /* must be 0                                                  */
+} glt_schedule;
+
+/* The handle's current schedule. */
+glt_status glt_get_schedule(const glt_ctx* ctx, glt_schedule* out);
+
+/* Replace the handle's schedule; GLT_E_INVALID_ARG (and no change) if a field is outside its
+ * range. */
+glt_status glt_set_schedule(glt_ctx* ctx, const glt_schedule* s);
+
+/*
+ * Autotuner for batches: counts the batch once per candidate schedule (a fixed grid over
+ * the wedge class bounds and the dense window, after one warm-up call), checks that all
+ * candidates give identical counts (GLT_E_INTERNAL otherwise), installs the candidate with
+ * the least device time (sum of the glt_last_timing groups) on the handle and returns it.
+ *   best     out: the chosen schedule
+ *   best_ms  out (may be NULL): its device time in milliseconds
+ * Errors as glt_count_batch.
+ */
+glt_status glt_autotune_batch(glt_ctx* ctx, const glt_batch* b, glt_schedule* best, float* best_ms, void* stream);
 
 /* ------------------------------------------------------------------------------------ */
 /* Request server: continuous batching of graph-count requests on one device.            */

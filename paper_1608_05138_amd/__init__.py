@@ -39,7 +39,7 @@ STATUS = {0: "GLT_OK", -1: "GLT_E_INVALID_ARG", -2: "GLT_E_NOT_SIMPLE", -3: "GLT
 EXPORTS = ["glt_create", "glt_destroy", "glt_last_error", "glt_version", "glt_count",
            "glt_last_timing", "glt_last_work", "glt_count_batch", "glt_server_create",
            "glt_server_submit", "glt_server_poll", "glt_server_inflight", "glt_server_clock",
-           "glt_server_destroy"]
+           "glt_server_destroy", "glt_get_schedule", "glt_set_schedule", "glt_autotune_batch"]
 
 
 class GltError(RuntimeError):
@@ -62,6 +62,15 @@ class glt_batch(ctypes.Structure):
     _fields_ = [("num_graphs", ctypes.c_int64), ("vtx_base", ctypes.c_void_p),
                 ("slot_base", ctypes.c_void_p), ("row_ptr", ctypes.c_void_p),
                 ("col", ctypes.c_void_p), ("on_device", ctypes.c_int32)]
+
+
+class glt_schedule(ctypes.Structure):
+    _fields_ = [("wedge_wave_max", ctypes.c_int32), ("wedge_mid_max", ctypes.c_int32),
+                ("wedge_dense", ctypes.c_int32), ("wedge_range_limit", ctypes.c_int32),
+                ("tri_records", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+SCHEDULE_KEYS = ["wedge_wave_max", "wedge_mid_max", "wedge_dense", "wedge_range_limit", "tri_records"]
 
 
 class glt_server_opts(ctypes.Structure):
@@ -121,6 +130,13 @@ def load_library(path: str = LIB_PATH):
     lib.glt_server_clock.restype = ctypes.c_double
     lib.glt_server_destroy.argtypes = [P]
     lib.glt_server_destroy.restype = None
+    lib.glt_get_schedule.argtypes = [P, ctypes.POINTER(glt_schedule)]
+    lib.glt_get_schedule.restype = ctypes.c_int
+    lib.glt_set_schedule.argtypes = [P, ctypes.POINTER(glt_schedule)]
+    lib.glt_set_schedule.restype = ctypes.c_int
+    lib.glt_autotune_batch.argtypes = [P, ctypes.POINTER(glt_batch), ctypes.POINTER(glt_schedule),
+                                       ctypes.POINTER(ctypes.c_float), P]
+    lib.glt_autotune_batch.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -155,16 +171,22 @@ class Context:
     def last_error(self) -> str:
         return self._lib.glt_last_error(self._h).decode()
 
+    TIMING_KEYS = ["prep", "tri_wave", "tri_wg", "gather_wave", "gather_wg", "wedge_wave", "wedge_wg",
+                   "combine"]
+    WORK_KEYS = ["n", "m", "wedges_wave", "wedges_wg", "tri_list_wave", "tri_list_wg", "triangles_wave",
+                 "triangles_wg"]
+
     def last_timing(self):
-        buf = (ctypes.c_float * 5)()
-        k = self._lib.glt_last_timing(self._h, buf, 5)
-        return list(buf[:k])
+        """dict of kernel-group times (ms) of the last count (HIP events on its stream)."""
+        buf = (ctypes.c_float * 8)()
+        k = self._lib.glt_last_timing(self._h, buf, 8)
+        return {name: float(buf[i]) for i, name in enumerate(self.TIMING_KEYS[:k])}
 
     def last_work(self):
-        """dict(n, m, wedges, tri_list_entries) of the last count."""
-        buf = (ctypes.c_uint64 * 4)()
-        self._lib.glt_last_work(self._h, buf, 4)
-        return {"n": buf[0], "m": buf[1], "wedges": buf[2], "tri_list_entries": buf[3]}
+        """dict of work counters of the last count."""
+        buf = (ctypes.c_uint64 * 8)()
+        k = self._lib.glt_last_work(self._h, buf, 8)
+        return {name: int(buf[i]) for i, name in enumerate(self.WORK_KEYS[:k])}
 
     def count(self, row_ptr, col, n: int | None = None, per_edge: bool = False, out=None,
               stream=None):
@@ -222,13 +244,38 @@ class Context:
         return [int(x.lo) | (int(x.hi) << 64) for x in X], (out if per_edge else None)
 
 
-    def count_batch(self, packed, stream=None):
-        """Global counts of every graph of a packed batch.
+    def schedule(self) -> dict:
+        """The handle's work schedule (glt_get_schedule) as a dict."""
+        sc = glt_schedule()
+        rc = self._lib.glt_get_schedule(self._h, ctypes.byref(sc))
+        if rc != 0:
+            raise GltError(rc, self.last_error())
+        return {k: int(getattr(sc, k)) for k in SCHEDULE_KEYS}
 
-        packed: dict with vtx_base, slot_base (int64 numpy, B+1), row_ptr (int32), col
-        (int32); row_ptr/col may be torch CUDA tensors (device) or numpy arrays (host).
-        Returns a list of B lists of 17 Python ints.
-        """
+    def set_schedule(self, **fields):
+        """Change fields of the work schedule (glt_set_schedule)."""
+        cur = self.schedule()
+        unknown = set(fields) - set(SCHEDULE_KEYS)
+        if unknown:
+            raise ValueError(f"unknown schedule fields {sorted(unknown)}")
+        cur.update(fields)
+        sc = glt_schedule(*[int(cur[k]) for k in SCHEDULE_KEYS])
+        rc = self._lib.glt_set_schedule(self._h, ctypes.byref(sc))
+        if rc != 0:
+            raise GltError(rc, self.last_error())
+
+    def autotune_batch(self, packed, stream=None):
+        """Run the batch autotuner (glt_autotune_batch); returns (schedule dict, device ms)."""
+        b, _keep, stream = self._batch_struct(packed, stream)
+        sc = glt_schedule()
+        ms = ctypes.c_float(0)
+        rc = self._lib.glt_autotune_batch(self._h, ctypes.byref(b), ctypes.byref(sc), ctypes.byref(ms),
+                                          ctypes.c_void_p(stream) if stream else None)
+        if rc != 0:
+            raise GltError(rc, self.last_error())
+        return {k: int(getattr(sc, k)) for k in SCHEDULE_KEYS}, float(ms.value)
+
+    def _batch_struct(self, packed, stream):
         vb = np.ascontiguousarray(packed["vtx_base"], dtype=np.int64)
         sb = np.ascontiguousarray(packed["slot_base"], dtype=np.int64)
         rp, col = packed["row_ptr"], packed["col"]
@@ -248,6 +295,17 @@ class Context:
             col = np.ascontiguousarray(col, dtype=np.int32)
             rp_ptr, col_ptr = rp.ctypes.data, col.ctypes.data
         b = glt_batch(B, vb.ctypes.data, sb.ctypes.data, rp_ptr, col_ptr, 1 if dev else 0)
+        return b, (vb, sb, rp, col), stream
+
+    def count_batch(self, packed, stream=None):
+        """Global counts of every graph of a packed batch.
+
+        packed: dict with vtx_base, slot_base (int64 numpy, B+1), row_ptr (int32), col
+        (int32); row_ptr/col may be torch CUDA tensors (device) or numpy arrays (host).
+        Returns a list of B lists of 17 Python ints.
+        """
+        b, _keep, stream = self._batch_struct(packed, stream)
+        B = int(b.num_graphs)
         X = (glt_u128 * (17 * max(B, 1)))()
         rc = self._lib.glt_count_batch(self._h, ctypes.byref(b), GLT_GLOBAL, X,
                                        ctypes.c_void_p(stream) if stream else None)

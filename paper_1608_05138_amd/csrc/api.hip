@@ -29,15 +29,20 @@ struct glt_ctx {
     void* ws = nullptr;
     size_t ws_bytes = 0;
     std::string err;
-    float timing[5] = {0, 0, 0, 0, 0};
-    hipEvent_t ev[6] = {};
+    float timing[NSEG] = {};
+    hipEvent_t ev[NSEG + 1] = {};
     u64* hbuf = nullptr;   // pinned host buffer for small read-backs (4 KiB)
     int wedge_wave_max = 0;
+    int wedge_mid_max = 0;
     int wedge_limit = 0;
     int wedge_dense = 0;
-    uint64_t work[4] = {0, 0, 0, 0};   // n, m, wedges, triangle-pass list entries
+    uint64_t work[2 + NWORK] = {};     // n, m, then the device work counters
     void* stage = nullptr;             // device staging of host batch inputs
     size_t stage_bytes = 0;
+    void* trec = nullptr;              // triangle records (grown on demand)
+    size_t trec_bytes = 0;
+    size_t trec_cap = 0;               // largest record buffer the handle allocates
+    int tri_records = 1;               // schedule: use triangle records when they fit
 };
 
 #define GLT_VERSION "glt 0.2 (gfx950)"
@@ -77,9 +82,9 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
     const int64_t S = 2 * (int64_t)m;
     const int64_t big = S > n ? S : n;
     d.n = n; d.m = m; d.S = (int)S;
-    d.err = c.take<int>(4);
+    d.err = c.take<int>(ERR_WORDS);
     d.counts = c.take<int>(TB_N + WB_N + TB_N);
-    d.work = c.take<u64>(2);
+    d.work = c.take<u64>(NWORK);
     d.final_sums = c.take<u64>(2 * 13);
     d.deg = c.take<int>(n);
     d.order = c.take<int>(n);
@@ -99,6 +104,10 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
     d.e.sig = c.take<u64>(m);
     d.e.u = c.take<int>(m);
     d.wcnt = c.take<u64>(n);
+    d.toff = c.take<u64>(n + 1);
+    d.tcnt = c.take<int>(n);
+    d.tmp64 = c.take<u64>(scan_tmp_elems(n + 1));
+    d.wspread = c.take<u64>((int64_t)GSPREAD * WSPREAD_WORDS);
     d.rowx = c.take<u32>(S + 1);
     d.nsrow = c.take<int>(S);
     d.tri = c.take<u64>(n);
@@ -120,7 +129,7 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
     d.itmp = c.take<int>(scan_tmp_elems(S + n + 1) + n + 1);
     d.ltmp = nullptr;
     d.ngraphs = ngraphs;
-    d.gsum = c.take<u64>((int64_t)(ngraphs > 0 ? ngraphs : 1) * NSUMS);
+    d.gsum = c.take<u64>((int64_t)(ngraphs > 0 ? ngraphs : GSPREAD) * NSUMS);
     if (ngraphs > 0) {
         d.gid = c.take<int>(n);
         d.ngid = c.take<int>(n);
@@ -238,33 +247,56 @@ glt_status ensure_ws(glt_ctx* ctx, size_t need, hipStream_t st) {
     return GLT_OK;
 }
 
+// Triangle records need 8 bytes per slot (sum over vertices of C(out-degree, 2)).  They are
+// used when that fits the handle's record cap and budget; otherwise the passes re-scan the
+// out-lists, with the same results.
+u64* ensure_trec(glt_ctx* ctx, u64 slots, hipStream_t st) {
+    if (slots == 0 || ctx->trec_cap == 0 || !ctx->tri_records) return nullptr;
+    if (slots > (u64)(ctx->trec_cap / 8)) return nullptr;
+    const size_t need = (size_t)slots * 8;
+    if (ctx->budget && ctx->ws_bytes + need > ctx->budget) return nullptr;
+    if (need <= ctx->trec_bytes) return (u64*)ctx->trec;
+    if (hipStreamSynchronize(st) != hipSuccess) return nullptr;
+    if (ctx->trec) { (void)hipFree(ctx->trec); ctx->trec = nullptr; ctx->trec_bytes = 0; }
+    if (hipMalloc(&ctx->trec, need) != hipSuccess) {
+        ctx->trec = nullptr;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    ctx->trec_bytes = need;
+    return (u64*)ctx->trec;
+}
+
 // Validation, preprocessing and the counting passes on a prepared CSR (rp, col) on the
 // device.  Host read-backs: validation flags after the row check and after the build.
 glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const int* col, bool per_edge,
                         u64* pe_dev, hipStream_t st) {
     const int n = d.n, m = d.m;
     d.wedge_wave_max = ctx->wedge_wave_max;
+    d.wedge_mid_max = ctx->wedge_mid_max;
     d.wedge_limit = ctx->wedge_limit;
     d.wedge_dense = ctx->wedge_dense;
     HIPCHK(hipEventRecord(ctx->ev[0], st));
     glt_prep_validate(d, rp, rp64, col, st);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(ctx->hbuf, d.err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ctx->hbuf, d.err, (2 + RS_N) * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     int hc[TB_N + WB_N + TB_N + 1];
+    int vinfo[1 + RS_N];
     {
         const int e = ((int*)ctx->hbuf)[0];
         if (e & ERR_RANGE) return fail(ctx, GLT_E_INVALID_ARG, "row offsets not monotone or neighbour id out of range");
         if (e & ERR_SELF) return fail(ctx, GLT_E_NOT_SIMPLE, "self-loop");
-        hc[0] = ((int*)ctx->hbuf)[1];   // maximum degree
+        for (int i = 0; i < 1 + RS_N; i++) vinfo[i] = ((int*)ctx->hbuf)[1 + i];   // max degree, row classes
         // K <= C(dmax,2), P <= dmax^2, sum over T of t(w,u)+t(w,v) <= 2 dmax^2, sum of d_w <= dmax^2
-        d.acc32 = (hc[0] <= 46340) ? 1 : 0;
+        d.acc32 = (vinfo[0] <= 46340) ? 1 : 0;
     }
-    glt_prep_build(d, rp, rp64, col, st, hc);
+    glt_prep_build(d, rp, rp64, col, st, vinfo);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(ctx->hbuf, d.err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 8, d.optr + n, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 16, d.counts, sizeof(int) * (TB_N + WB_N + TB_N), hipMemcpyDeviceToHost, st));
+    if (n > 0) HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 64, d.toff + n, sizeof(u64), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     {
         const int e = ((int*)ctx->hbuf)[0];
@@ -276,14 +308,14 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
             return fail(ctx, GLT_E_UNSUPPORTED, "out-degree %d in the degree order exceeds %d",
                         hc[TB_N + WB_N + TB_GLOBAL], glt_max_out_degree());
     }
-    HIPCHK(hipEventRecord(ctx->ev[1], st));
-    glt_count_passes(d, per_edge ? 1 : 0, hc, pe_dev, st, ctx->ev + 2);
+    d.trec = ensure_trec(ctx, n > 0 ? *(u64*)((char*)ctx->hbuf + 64) : 0, st);
+    glt_count_passes(d, per_edge ? 1 : 0, hc, pe_dev, st, ctx->ev + 1);
     HIPCHK(hipGetLastError());
     return GLT_OK;
 }
 
 void record_timing(glt_ctx* ctx) {
-    for (int i = 0; i < 5; i++) {
+    for (int i = 0; i < NSEG; i++) {
         float ms = 0;
         (void)hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]);
         ctx->timing[i] = ms;
@@ -323,12 +355,14 @@ glt_status glt_run_batch_ptrs(glt_ctx* ctx, int64_t B, const int64_t* vb, const 
     std::vector<u64> parts((size_t)B * 13 * 2), gs((size_t)B * NSUMS);
     HIPCHK(hipMemcpyAsync(parts.data(), d.gparts, parts.size() * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(gs.data(), d.gsum, gs.size() * 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 1032, d.work, 2 * sizeof(u64), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 1024, d.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 1032, d.work, NWORK * sizeof(u64), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    if (((int*)((char*)ctx->hbuf + 1024))[0] & ERR_CAP)
+        return fail(ctx, GLT_E_INTERNAL, "an on-chip table bound of the wedge pass was exceeded");
     ctx->work[0] = (uint64_t)n;
     ctx->work[1] = (uint64_t)m;
-    ctx->work[2] = ((u64*)((char*)ctx->hbuf + 1032))[0];
-    ctx->work[3] = ((u64*)((char*)ctx->hbuf + 1032))[1];
+    for (int i = 0; i < NWORK; i++) ctx->work[2 + i] = ((u64*)((char*)ctx->hbuf + 1032))[i];
     record_timing(ctx);
     for (int64_t g = 0; g < B; g++) {
         i128 C[17];
@@ -367,6 +401,11 @@ glt_status glt_create(int device, size_t hbm_budget_bytes, glt_ctx** out) {
         int v = atoi(e);
         if (v >= 0 && v < ctx->wedge_wave_max) ctx->wedge_wave_max = v;
     }
+    ctx->wedge_mid_max = 2048;
+    if (const char* e = getenv("GLT_WEDGE_MID_MAX")) {
+        int v = atoi(e);
+        if (v >= 0) ctx->wedge_mid_max = v;
+    }
     if (const char* e = getenv("GLT_WEDGE_RANGE_LIMIT")) {
         int v = atoi(e);
         if (v >= 1 && v < ctx->wedge_limit) ctx->wedge_limit = v;
@@ -380,7 +419,13 @@ glt_status glt_create(int device, size_t hbm_budget_bytes, glt_ctx** out) {
         delete ctx;
         return GLT_E_DEVICE;
     }
-    for (int i = 0; i < 6; i++)
+    {
+        // triangle records may take up to a quarter of the device's memory (0 disables them)
+        size_t fr = 0, total = 0;
+        if (hipMemGetInfo(&fr, &total) == hipSuccess) ctx->trec_cap = total / 4;
+        if (const char* e = getenv("GLT_TRI_RECORD_BYTES")) ctx->trec_cap = (size_t)strtoull(e, nullptr, 10);
+    }
+    for (int i = 0; i <= NSEG; i++)
         if (hipEventCreate(&ctx->ev[i]) != hipSuccess) { glt_destroy(ctx); return GLT_E_DEVICE; }
     if (hipHostMalloc((void**)&ctx->hbuf, 4096, hipHostMallocDefault) != hipSuccess) {
         glt_destroy(ctx);
@@ -396,7 +441,8 @@ void glt_destroy(glt_ctx* ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->stage) (void)hipFree(ctx->stage);
-    for (int i = 0; i < 6; i++)
+    if (ctx->trec) (void)hipFree(ctx->trec);
+    for (int i = 0; i <= NSEG; i++)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     if (ctx->hbuf) (void)hipHostFree(ctx->hbuf);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -407,14 +453,14 @@ const char* glt_last_error(const glt_ctx* ctx) { return ctx ? ctx->err.c_str() :
 
 int glt_last_work(const glt_ctx* ctx, uint64_t* out, int cap) {
     if (!ctx || !out) return 0;
-    int k = cap < 4 ? cap : 4;
+    int k = cap < 2 + NWORK ? cap : 2 + NWORK;
     for (int i = 0; i < k; i++) out[i] = ctx->work[i];
     return k;
 }
 
 int glt_last_timing(const glt_ctx* ctx, float* ms, int cap) {
     if (!ctx || !ms) return 0;
-    int k = cap < 5 ? cap : 5;
+    int k = cap < NSEG ? cap : NSEG;
     for (int i = 0; i < k; i++) ms[i] = ctx->timing[i];
     return k;
 }
@@ -474,14 +520,15 @@ glt_status glt_count(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 ou
     HIPCHK(hipMemcpyAsync(ctx->hbuf, d.final_sums, sizeof(u64) * 2 * 13, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 512, d.gsum, sizeof(u64) * NSUMS, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 1024, d.err, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 1032, d.work, 2 * sizeof(u64), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 1032, d.work, NWORK * sizeof(u64), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (((int*)((char*)ctx->hbuf + 1024))[0] & ERR_NEG)
         return fail(ctx, GLT_E_INTERNAL, "a per-edge count came out negative");
+    if (((int*)((char*)ctx->hbuf + 1024))[0] & ERR_CAP)
+        return fail(ctx, GLT_E_INTERNAL, "an on-chip table bound of the wedge pass was exceeded");
     ctx->work[0] = (uint64_t)n;
     ctx->work[1] = (uint64_t)m;
-    ctx->work[2] = n > 0 ? ((u64*)((char*)ctx->hbuf + 1032))[0] : 0;
-    ctx->work[3] = n > 0 ? ((u64*)((char*)ctx->hbuf + 1032))[1] : 0;
+    for (int i = 0; i < NWORK; i++) ctx->work[2 + i] = n > 0 ? ((u64*)((char*)ctx->hbuf + 1032))[i] : 0;
     record_timing(ctx);
     i128 C[17];
     unpack_c(ctx->hbuf, C);
@@ -548,3 +595,79 @@ glt_status glt_count_batch(glt_ctx* ctx, const glt_batch* b, uint32_t flags, glt
 }
 
 }  // extern "C"
+
+glt_status glt_get_schedule(const glt_ctx* ctx, glt_schedule* out) {
+    if (!ctx || !out) return GLT_E_INVALID_ARG;
+    memset(out, 0, sizeof(*out));
+    out->wedge_wave_max = ctx->wedge_wave_max;
+    out->wedge_mid_max = ctx->wedge_mid_max;
+    out->wedge_dense = ctx->wedge_dense;
+    out->wedge_range_limit = ctx->wedge_limit;
+    out->tri_records = ctx->tri_records;
+    return GLT_OK;
+}
+
+glt_status glt_set_schedule(glt_ctx* ctx, const glt_schedule* s) {
+    if (!ctx) return GLT_E_INVALID_ARG;
+    ctx->err.clear();
+    if (!s) return fail(ctx, GLT_E_INVALID_ARG, "null schedule");
+    if (s->wedge_wave_max < 0 || s->wedge_wave_max > glt_wave_table() / 2)
+        return fail(ctx, GLT_E_INVALID_ARG, "wedge_wave_max must be in [0, %d]", glt_wave_table() / 2);
+    if (s->wedge_mid_max < 0) return fail(ctx, GLT_E_INVALID_ARG, "wedge_mid_max must be >= 0");
+    if (s->wedge_dense < 0 || s->wedge_dense > glt_wedge_dense())
+        return fail(ctx, GLT_E_INVALID_ARG, "wedge_dense must be in [0, %d]", glt_wedge_dense());
+    if (s->wedge_range_limit < 1 || s->wedge_range_limit > glt_wedge_table() / 2)
+        return fail(ctx, GLT_E_INVALID_ARG, "wedge_range_limit must be in [1, %d]", glt_wedge_table() / 2);
+    if (s->tri_records != 0 && s->tri_records != 1) return fail(ctx, GLT_E_INVALID_ARG, "tri_records must be 0 or 1");
+    for (int i = 0; i < 3; i++)
+        if (s->reserved[i]) return fail(ctx, GLT_E_INVALID_ARG, "reserved fields must be 0");
+    ctx->wedge_wave_max = s->wedge_wave_max;
+    ctx->wedge_mid_max = s->wedge_mid_max;
+    ctx->wedge_dense = s->wedge_dense;
+    ctx->wedge_limit = s->wedge_range_limit;
+    ctx->tri_records = s->tri_records;
+    return GLT_OK;
+}
+
+glt_status glt_autotune_batch(glt_ctx* ctx, const glt_batch* b, glt_schedule* best, float* best_ms, void* stream) {
+    if (!ctx) return GLT_E_INVALID_ARG;
+    ctx->err.clear();
+    if (!b || !best) return fail(ctx, GLT_E_INVALID_ARG, "null batch or output");
+    const int64_t B = b->num_graphs;
+    if (B <= 0) return fail(ctx, GLT_E_INVALID_ARG, "empty batch");
+    glt_schedule base;
+    glt_get_schedule(ctx, &base);
+    std::vector<glt_u128> ref((size_t)B * 17), got((size_t)B * 17);
+    glt_status rc = glt_count_batch(ctx, b, GLT_GLOBAL, ref.data(), stream);   // warm-up, reference counts
+    if (rc) return rc;
+    // candidate grid: wedge class bounds x dense window
+    static const int wave_c[2] = {128, 256};
+    static const int mid_c[3] = {1024, 2048, 4096};
+    static const int dense_c[2] = {1024, 4096};
+    glt_schedule win = base;
+    float win_ms = -1.f;
+    for (int a = 0; a < 2; a++)
+        for (int c = 0; c < 3; c++)
+            for (int e = 0; e < 2; e++) {
+                glt_schedule cand = base;
+                cand.wedge_wave_max = wave_c[a];
+                cand.wedge_mid_max = mid_c[c];
+                cand.wedge_dense = dense_c[e];
+                rc = glt_set_schedule(ctx, &cand);
+                if (rc) { glt_set_schedule(ctx, &base); return rc; }
+                rc = glt_count_batch(ctx, b, GLT_GLOBAL, got.data(), stream);
+                if (rc) { glt_set_schedule(ctx, &base); return rc; }
+                if (memcmp(got.data(), ref.data(), got.size() * sizeof(glt_u128)) != 0) {
+                    glt_set_schedule(ctx, &base);
+                    return fail(ctx, GLT_E_INTERNAL, "schedule (%d, %d, %d) changed the counts", wave_c[a], mid_c[c],
+                                dense_c[e]);
+                }
+                float ms = 0;
+                for (int i = 0; i < NSEG; i++) ms += ctx->timing[i];
+                if (win_ms < 0 || ms < win_ms) { win_ms = ms; win = cand; }
+            }
+    glt_set_schedule(ctx, &win);
+    *best = win;
+    if (best_ms) *best_ms = win_ms;
+    return GLT_OK;
+}

@@ -66,11 +66,26 @@ __device__ __forceinline__ int sh_find(const int* hk, const unsigned char* hv, i
     }
 }
 
-template <bool PE, typename AT>
+// Triangle records (REC): every triangle (a, b_i, b_j) found while the rows are built is
+// written as (k << 32 | j << 16 | i), k the oriented index of (b_i, b_j), into a's slots
+// [toff[a], toff[a] + C(|N+(a)|, 2)) (each pair i < j at most once), and tcnt[a] holds
+// their number.  The 4-clique sweep and the gather pass then walk the records instead of
+// re-scanning every out-list of N+(a).
+__device__ __forceinline__ u64 tri_rec(int i, int j, int k) {
+    return ((u64)(u32)k << 32) | (u64)(u32)(i | (j << 16));
+}
+__device__ __forceinline__ void tri_unrec(u64 v, int& i, int& j, int& k) {
+    i = (int)(v & 0xffffu);
+    j = (int)((v >> 16) & 0xffffu);
+    k = (int)(v >> 32);
+}
+
+template <bool PE, bool REC, typename AT>
 __global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__ list, int nlist,
                                                         const int* __restrict__ optr, const int* __restrict__ ocol,
                                                         EdgeArrays e, u64* __restrict__ gsum,
-                                                        const int* __restrict__ ngid) {
+                                                        const int* __restrict__ ngid, u64* __restrict__ trec,
+                                                        const u64* __restrict__ toff, int* __restrict__ tcnt) {
     __shared__ int sOb[4][GLT_WAVE];
     __shared__ int sPre[4][GLT_WAVE];
     __shared__ u64 sM[4][GLT_WAVE];
@@ -92,24 +107,58 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__
     __syncthreads();
     if (l < s) sh_insert(hk[w], hv[w], b, l);
     __syncthreads();
-    // build the adjacency rows among S
+    // build the adjacency rows among S (and record the triangles)
+    u64* rec = (REC && active) ? trec + toff[a] : nullptr;
+    const u64 lt = (l == 0) ? 0ull : ((~0ull) >> (GLT_WAVE - l));
+    int nh = 0;   // records so far (wave-uniform)
     int i = 0;
     for (int q0 = 0; q0 < total; q0 += GLT_WAVE) {
         const int q = q0 + l;
+        int j = -1, k = 0;
         if (q < total) {
             i = advance_idx(sPre[w], s, q, i);
-            const int x = ocol[sOb[w][i] + (q - sPre[w][i])];
-            const int j = sh_find(hk[w], hv[w], x);
+            k = sOb[w][i] + (q - sPre[w][i]);
+            j = sh_find(hk[w], hv[w], ocol[k]);
             if (j >= 0) {
                 atomicOr(&sM[w][i], 1ull << j);
                 atomicOr(&sM[w][j], 1ull << i);
             }
         }
+        if (REC) {
+            const u64 hm = __ballot(j >= 0);
+            if (j >= 0) rec[nh + __popcll(hm & lt)] = tri_rec(i, j, k);
+            nh += __popcll(hm);
+        }
     }
     __syncthreads();
     u64 k4 = 0;
+    if (REC) {
+        for (int r0 = 0; r0 < nh; r0 += GLT_WAVE) {
+            const int r = r0 + l;
+            int key = 0x7fffffff;
+            u64 tk = 0;
+            if (r < nh) {
+                int ri, rj, k;
+                tri_unrec(rec[r], ri, rj, k);
+                key = ri;
+                tk = (u64)__popcll(sM[w][ri] & sM[w][rj]);
+                atomicAdd(&e.t[k], 1u);
+                if (PE && tk) {
+                    acc_add<AT>(e.K, k, tk);
+                    atomicAdd(&sK[w][rj], tk);
+                }
+                k4 += tk;
+            }
+            if (PE) {   // records are in scan order: i non-decreasing across the lanes
+                bool last;
+                const u64 ssum = seg_sum_last(tk, key, last);
+                if (last && ssum) atomicAdd(&sK[w][key], ssum);
+            }
+        }
+        if (l == 0 && active) tcnt[a] = nh;
+    }
     i = 0;
-    for (int q0 = 0; q0 < total; q0 += GLT_WAVE) {
+    for (int q0 = 0; !REC && q0 < total; q0 += GLT_WAVE) {
         const int q = q0 + l;
         int key = 0x7fffffff;
         u64 tk = 0;
@@ -144,21 +193,29 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__
         }
     }
     k4 = wave_sum(k4);
-    if (l == 0 && k4) atomicAdd(&gsum[(ngid ? ngid[a] : 0) * NSUMS + S_K4x3], k4);
+    const u64 ntri = wave_sum((l < s) ? (u64)__popcll(sM[w][l]) : 0ull) / 2;
+    if (l == 0 && active) {
+        u64* gs = gsum + gslot(ngid, a) * NSUMS;
+        if (k4) atomicAdd(&gs[S_K4x3], k4);
+        if (ntri) atomicAdd(&gs[GS_TRI_WAVE], ntri);
+    }
 }
 
 // ---------------------------------------------------------------------------------------
 // triangle / 4-clique pass, out-degree > 64: one workgroup per vertex, M rows of W words
 // in LDS (GM = false) or in a per-workgroup global slab (GM = true)
 // ---------------------------------------------------------------------------------------
-template <bool PE, bool GM, typename AT>
+template <bool PE, bool GM, bool REC, typename AT>
 __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ list, int nlist, int smax,
                                                        const int* __restrict__ optr, const int* __restrict__ ocol,
                                                        EdgeArrays e, u64* __restrict__ gsum,
-                                                       u32* __restrict__ gscratch, const int* __restrict__ ngid) {
+                                                       u32* __restrict__ gscratch, const int* __restrict__ ngid,
+                                                       u64* __restrict__ trec, const u64* __restrict__ toff,
+                                                       int* __restrict__ tcnt) {
     extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
     __shared__ int sScan[TB_THREADS / GLT_WAVE];
     __shared__ u64 sRed[TB_THREADS / GLT_WAVE];
+    __shared__ int sNrec;
     u64* sK = (u64*)dyn;
     int* sS = (int*)(sK + smax);
     int* sOb = sS + smax;
@@ -188,21 +245,56 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
     }
     const int total = carry;
     for (int q = tid; q < s * W; q += TB_THREADS) M[q] = 0;
+    if (tid == 0) sNrec = 0;
     __syncthreads();
+    u64* rec = REC ? trec + toff[a] : nullptr;
+    const u64 lt = (glt_lane() == 0) ? 0ull : ((~0ull) >> (GLT_WAVE - glt_lane()));
     int ii = 0;
-    for (int q = tid; q < total; q += TB_THREADS) {
-        const int i = ii = advance_idx(sPre, s, q, ii);
-        const int x = ocol[sOb[i] + (q - sPre[i])];
-        const int j = lower_bound_i32(sS, i + 1, s, x);
-        if (j < s && sS[j] == x) {
-            atomicOr(&M[i * W + (j >> 5)], 1u << (j & 31));
-            atomicOr(&M[j * W + (i >> 5)], 1u << (i & 31));
+    for (int q0 = 0; q0 < total; q0 += TB_THREADS) {
+        const int q = q0 + tid;
+        int j = s, k = 0, i = 0;
+        if (q < total) {
+            i = ii = advance_idx(sPre, s, q, ii);
+            k = sOb[i] + (q - sPre[i]);
+            const int x = ocol[k];
+            j = lower_bound_i32(sS, i + 1, s, x);
+            if (j < s && sS[j] == x) {
+                atomicOr(&M[i * W + (j >> 5)], 1u << (j & 31));
+                atomicOr(&M[j * W + (i >> 5)], 1u << (i & 31));
+            } else {
+                j = s;
+            }
+        }
+        if (REC) {   // one slot reservation per wavefront and round
+            const u64 hm = __ballot(j < s);
+            int base = 0;
+            if (glt_lane() == 0 && hm) base = atomicAdd(&sNrec, __popcll(hm));
+            base = __shfl(base, 0, GLT_WAVE);
+            if (j < s) rec[base + __popcll(hm & lt)] = tri_rec(i, j, k);
         }
     }
     __syncthreads();
     u64 k4 = 0;
+    if (REC) {
+        // records of different wavefronts interleave: per-source sums go straight to LDS
+        const int nrec = sNrec;
+        for (int r = tid; r < nrec; r += TB_THREADS) {
+            int ri, rj, k;
+            tri_unrec(rec[r], ri, rj, k);
+            u64 tk = 0;
+            for (int wd = 0; wd < W; wd++) tk += (u64)__popc(M[ri * W + wd] & M[rj * W + wd]);
+            atomicAdd(&e.t[k], 1u);
+            if (PE && tk) {
+                acc_add<AT>(e.K, k, tk);
+                atomicAdd(&sK[rj], tk);
+                atomicAdd(&sK[ri], tk);
+            }
+            k4 += tk;
+        }
+        if (tid == 0) tcnt[a] = nrec;
+    }
     // every thread runs the same number of iterations so the wave reductions see full waves
-    const int rounds = (total + TB_THREADS - 1) / TB_THREADS;
+    const int rounds = REC ? 0 : (total + TB_THREADS - 1) / TB_THREADS;
     ii = 0;
     for (int r = 0; r < rounds; r++) {
         const int q = r * TB_THREADS + tid;
@@ -230,9 +322,11 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
         }
     }
     __syncthreads();
+    u64 ntri = 0;
     for (int i = tid; i < s; i += TB_THREADS) {
         u32 tl = 0;
         for (int wd = 0; wd < W; wd++) tl += (u32)__popc(M[i * W + wd]);
+        ntri += tl;
         if (tl) atomicAdd(&e.t[o0 + i], tl);
         if (PE) {
             const u64 kl = sK[i] >> 1;
@@ -245,8 +339,10 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
     if (tid == 0) {
         u64 tot = 0;
         for (int q = 0; q < TB_THREADS / GLT_WAVE; q++) tot += sRed[q];
-        if (tot) atomicAdd(&gsum[(ngid ? ngid[a] : 0) * NSUMS + S_K4x3], tot);
+        if (tot) atomicAdd(&gsum[gslot(ngid, a) * NSUMS + S_K4x3], tot);
     }
+    ntri = wave_sum(ntri) / 2;
+    if (glt_lane() == 0 && ntri) atomicAdd(&gsum[gslot(ngid, a) * NSUMS + GS_TRI_WG], ntri);
 }
 
 static inline size_t tri_blk_lds(int smax, bool gm) {
@@ -287,11 +383,14 @@ __device__ __forceinline__ void gather_credit(bool found, int i, int j, int k, c
     }
 }
 
-template <typename AT>
+template <bool REC, typename AT>
 __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restrict__ list, int nlist,
                                                            const int* __restrict__ optr,
                                                            const int* __restrict__ ocol,
-                                                           const int* __restrict__ ndeg, EdgeArrays e) {
+                                                           const int* __restrict__ ndeg, EdgeArrays e,
+                                                           const u64* __restrict__ trec,
+                                                           const u64* __restrict__ toff,
+                                                           const int* __restrict__ tcnt) {
     __shared__ int sOb[4][GLT_WAVE];
     __shared__ int sPre[4][GLT_WAVE];
     __shared__ u32 sT[4][GLT_WAVE];
@@ -322,17 +421,28 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
     __syncthreads();
     if (l < s) sh_insert(hk[w], hv[w], b, l);
     __syncthreads();
-    int i = 0;
-    for (int q0 = 0; q0 < total; q0 += GLT_WAVE) {
-        const int q = q0 + l;
-        int key = 0x3fffffff, j = -1, k = 0;
-        if (q < total) {
-            i = advance_idx(sPre[w], s, q, i);
-            key = i;
-            k = sOb[w][i] + (q - sPre[w][i]);
-            j = sh_find(hk[w], hv[w], ocol[k]);
+    if (REC) {
+        const int nh = active ? tcnt[a] : 0;
+        const u64* rec = trec + (active ? toff[a] : 0);
+        for (int r0 = 0; r0 < nh; r0 += GLT_WAVE) {
+            const int r = r0 + l;
+            int key = 0x3fffffff, j = -1, k = 0;
+            if (r < nh) tri_unrec(rec[r], key, j, k);
+            gather_credit<AT>(r < nh, key, j, k, sT[w], sD[w], da, e, sG[w], sSg[w]);
         }
-        gather_credit<AT>(j >= 0, key, j, k, sT[w], sD[w], da, e, sG[w], sSg[w]);
+    } else {
+        int i = 0;
+        for (int q0 = 0; q0 < total; q0 += GLT_WAVE) {
+            const int q = q0 + l;
+            int key = 0x3fffffff, j = -1, k = 0;
+            if (q < total) {
+                i = advance_idx(sPre[w], s, q, i);
+                key = i;
+                k = sOb[w][i] + (q - sPre[w][i]);
+                j = sh_find(hk[w], hv[w], ocol[k]);
+            }
+            gather_credit<AT>(j >= 0, key, j, k, sT[w], sD[w], da, e, sG[w], sSg[w]);
+        }
     }
     __syncthreads();
     if (l < s) {
@@ -341,12 +451,14 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
     }
 }
 
-template <bool GM, typename AT>
+template <bool GM, bool REC, typename AT>
 __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict__ list, int nlist, int smax,
                                                           const int* __restrict__ optr,
                                                           const int* __restrict__ ocol,
                                                           const int* __restrict__ ndeg, EdgeArrays e,
-                                                          u64* __restrict__ gslab) {
+                                                          u64* __restrict__ gslab, const u64* __restrict__ trec,
+                                                          const u64* __restrict__ toff,
+                                                          const int* __restrict__ tcnt) {
     extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
     __shared__ int sScan[TB_THREADS / GLT_WAVE];
     int* sS = (int*)dyn;
@@ -379,7 +491,24 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict
     }
     const int total = carry;
     __syncthreads();
-    const int rounds = (total + TB_THREADS - 1) / TB_THREADS;
+    if (REC) {
+        // records of different wavefronts interleave: the source's sums go straight to LDS
+        const int nh = tcnt[a];
+        const u64* rec = trec + toff[a];
+        for (int r = tid; r < nh; r += TB_THREADS) {
+            int i, j, k;
+            tri_unrec(rec[r], i, j, k);
+            const u64 tij = e.t[k];
+            const u64 tai = sT[i], taj = sT[j];
+            atomicAdd(&sG[i], taj + tij);
+            atomicAdd(&sSg[i], (u64)sD[j]);
+            atomicAdd(&sG[j], tai + tij);
+            atomicAdd(&sSg[j], (u64)sD[i]);
+            acc_add<AT>(e.g, k, tai + taj);
+            acc_add<AT>(e.sig, k, (u64)da);
+        }
+    }
+    const int rounds = REC ? 0 : (total + TB_THREADS - 1) / TB_THREADS;
     int ii = 0;
     for (int r = 0; r < rounds; r++) {
         const int q = r * TB_THREADS + tid;
@@ -410,270 +539,246 @@ static inline size_t gather_blk_lds(int smax, bool gm) {
 // ---------------------------------------------------------------------------------------
 __device__ __forceinline__ u32 hslot(int x, u32 mask) { return ((u32)x * 2654435761u >> 7) & mask; }
 
-// Range of oriented indices k (x = ocol[k]) of the wedges y - w - x for CSR slot s of row y.
-__device__ __forceinline__ void wedge_range(int y, int s, const int* __restrict__ ncol, const int* __restrict__ optr,
-                                            const int* __restrict__ s2k, int& w, int& k0, int& k1) {
-    w = ncol[s];
+// Oriented index range [k0, k1) of the wedges y - w - x for CSR slot s of row y (w = ncol[s]),
+// restricted to tops x in [lo, hi) unless the range is the full [y + 1, n).
+__device__ __forceinline__ void wedge_bounds(int y, int s, int lo, int hi, bool full, const int* __restrict__ ncol,
+                                             const int* __restrict__ optr, const int* __restrict__ ocol,
+                                             const int* __restrict__ s2k, int& k0, int& k1) {
+    const int w = ncol[s];
     k1 = optr[w + 1];
     k0 = (w > y) ? optr[w] : s2k[s] + 1;
+    if (!full) {
+        k0 = lower_bound_i32(ocol, k0, k1, lo);
+        k1 = lower_bound_i32(ocol, k0, k1, hi);
+    }
 }
 
-#define WW_TABLE 512   // per-wave hash entries; wave-path vertices have <= WW_TABLE/2 wedges
-
-// One wavefront per bottom vertex y with at most WW_TABLE/2 wedges.
-template <bool PE, typename AT>
-__global__ __launch_bounds__(256) void k_wedge_wave(const int* __restrict__ list, int nlist,
-                                                    const int* __restrict__ nrp, const int* __restrict__ ncol,
-                                                    const int* __restrict__ optr, const int* __restrict__ ocol,
-                                                    const int* __restrict__ s2k, EdgeArrays e,
-                                                    u64* __restrict__ gsum, const int* __restrict__ ngid) {
-    __shared__ int hkey[4][WW_TABLE];
-    __shared__ u32 hcnt[4][WW_TABLE];
-    __shared__ int sK0[4][GLT_WAVE];
-    __shared__ int sPre[4][GLT_WAVE];
-    __shared__ u32 sB[4][GLT_WAVE];
-    const int w4 = threadIdx.x / GLT_WAVE, l = glt_lane();
-    const int idx = blockIdx.x * 4 + w4;
-    const bool active = idx < nlist;
-    const int y = active ? list[idx] : 0;
-    const int rb = active ? nrp[y] : 0, re = active ? nrp[y + 1] : 0;
-    for (int q = l; q < WW_TABLE; q += GLT_WAVE) { hkey[w4][q] = -1; hcnt[w4][q] = 0; }
-    __syncthreads();
-    const u32 mask = WW_TABLE - 1;
-    // count phase
-    for (int c0 = rb; c0 < re; c0 += GLT_WAVE) {
-        const int s = c0 + l;
-        int wv = 0, k0 = 0, k1 = 0;
-        if (s < re) wedge_range(y, s, ncol, optr, s2k, wv, k0, k1);
-        const int len = k1 - k0;
-        const int inc = wave_incl_scan(len);
-        const int tot = __shfl(inc, GLT_WAVE - 1, GLT_WAVE);
-        const int nsrc = min(GLT_WAVE, re - c0);
-        wave_sync();
-        sK0[w4][l] = k0; sPre[w4][l] = inc - len;
-        wave_sync();
-        int ii = 0;
-        for (int q0 = 0; q0 < tot; q0 += GLT_WAVE) {
-            const int q = q0 + l;
-            if (q < tot) {
-                const int i = ii = advance_idx(sPre[w4], nsrc, q, ii);
-                const int x = ocol[sK0[w4][i] + (q - sPre[w4][i])];
-                u32 h = hslot(x, mask);
-                while (true) {
-                    int cur = hkey[w4][h];
-                    if (cur == -1) cur = atomicCAS(&hkey[w4][h], -1, x);
-                    if (cur == -1 || cur == x) { atomicAdd(&hcnt[w4][h], 1u); break; }
-                    h = (h + 1) & mask;
-                }
-            }
-        }
-    }
-    __syncthreads();
-    u64 c4 = 0;
-    for (int q = l; q < WW_TABLE; q += GLT_WAVE) {
-        const u64 c = hcnt[w4][q];
-        c4 += c * (c - (c > 0)) / 2;
-    }
-    // credit phase
-    if (PE) {
-        for (int c0 = rb; c0 < re; c0 += GLT_WAVE) {
-            const int s = c0 + l;
-            int wv = 0, k0 = 0, k1 = 0;
-            if (s < re) wedge_range(y, s, ncol, optr, s2k, wv, k0, k1);
-            const int len = k1 - k0;
-            const int inc = wave_incl_scan(len);
-            const int tot = __shfl(inc, GLT_WAVE - 1, GLT_WAVE);
-            const int nsrc = min(GLT_WAVE, re - c0);
-            wave_sync();
-            sK0[w4][l] = k0; sPre[w4][l] = inc - len; sB[w4][l] = 0;
-            wave_sync();
-            int ii = 0;
-            for (int q0 = 0; q0 < tot; q0 += GLT_WAVE) {
-                const int q = q0 + l;
-                int i = 0x7fffffff;
-                u32 c = 0;
-                if (q < tot) {
-                    i = ii = advance_idx(sPre[w4], nsrc, q, ii);
-                    const int k = sK0[w4][i] + (q - sPre[w4][i]);
-                    const int x = ocol[k];
-                    u32 h = hslot(x, mask);
-                    while (hkey[w4][h] != x) h = (h + 1) & mask;
-                    c = hcnt[w4][h] - 1;
-                    if (c) acc_add<AT>(e.P, k, (u64)c);
-                }
-                bool last;
-                const u32 ssum = seg_sum_last(c, i, last);
-                if (last && ssum) atomicAdd(&sB[w4][i], ssum);
-            }
-            wave_sync();
-            if (s < re && sB[w4][l]) acc_add<AT>(e.P, s2k[s], (u64)sB[w4][l]);
-        }
-    }
-    c4 = wave_sum(c4);
-    if (l == 0 && c4) atomicAdd(&gsum[(ngid ? ngid[y] : 0) * NSUMS + S_NC4], c4);
+template <int T>
+__device__ __forceinline__ void grp_sync() {
+    if constexpr (T == GLT_WAVE) wave_sync(); else __syncthreads();
 }
 
-#define WB_THREADS 256
-#define WB_TABLE 2048           // LDS hash entries per workgroup (tops below the dense window)
-#define WB_DENSE 8192           // dense LDS counters for the highest-ranked tops
-#define WB_STACK 96
+template <int T>
+__device__ __forceinline__ int grp_excl_scan(int v, int* lds, int& tot) {
+    if constexpr (T == GLT_WAVE) {
+        const int inc = wave_incl_scan(v);
+        tot = __shfl(inc, GLT_WAVE - 1, GLT_WAVE);
+        return inc - v;
+    } else {
+        return block_excl_scan<int, T>(v, lds, tot);
+    }
+}
 
-// One workgroup per bottom vertex with many wedges.  Tops x in the dense window
-// [n - dense, n) (the highest-ranked vertices, which close most wedges of a degree-ordered
-// graph) are counted in a dense LDS array; lower tops go to an LDS hash.  The x-range
-// [lo, hi) is split in halves whenever its hashed part holds more distinct tops than
-// `limit` (<= WB_TABLE/2); a range is credited only after its count phase completed without
-// overflow, so no wedge is credited twice.
-template <bool PE, typename AT>
-__global__ __launch_bounds__(WB_THREADS) void k_wedge_blk(const int* __restrict__ list, int nlist, int n, int limit,
-                                                         int dense, const int* __restrict__ nrp,
-                                                         const int* __restrict__ ncol, const int* __restrict__ optr,
-                                                         const int* __restrict__ ocol, const int* __restrict__ s2k,
-                                                         EdgeArrays e, u64* __restrict__ gsum,
-                                                         const int* __restrict__ ngid) {
-    __shared__ u32 dcnt[WB_DENSE];
-    __shared__ int hkey[WB_TABLE];
-    __shared__ u32 hcnt[WB_TABLE];
-    __shared__ int sK0[WB_THREADS];
-    __shared__ int sPre[WB_THREADS];
-    __shared__ u64 sB[WB_THREADS];
-    __shared__ int sScan[WB_THREADS / GLT_WAVE];
-    __shared__ u64 sRed[WB_THREADS / GLT_WAVE];
-    __shared__ int stLo[WB_STACK], stHi[WB_STACK];
-    __shared__ int sp, distinct, ovf;
-    const int tid = threadIdx.x;
-    const int y = list[blockIdx.x];
+#define WEDGE_STACK 40   // x-range stack per group (halving depth <= 32 for 31-bit ids)
+#define WEDGE_ILP 4      // wedges in flight per lane
+
+// Size classes of the wedge pass (wedges per bottom vertex y): threads per group, groups per
+// block, hash entries, dense top counters.
+#define WW_T 64
+#define WW_G 4
+#define WW_HT 512        // wave class: <= WW_HT / 2 wedges, so the hash never overflows
+#define WM_T 64
+#define WM_G 2
+#define WM_HT 1024
+#define WM_DW 1024
+#define WB_T 256
+#define WB_HT 2048
+#define WB_DW 4096
+
+// One group of T threads per bottom vertex y (G groups per block).  For every wedge
+// y - w - x with x above y the group counts c(y, x) = number of such w in LDS: tops x in
+// the dense window [n - dense, n) (the highest-ranked vertices, which close most wedges of a
+// degree-ordered graph) in a direct array, lower tops in an open-addressing hash.  The
+// non-induced 4-cycles with lowest vertex y and opposite vertex x number C(c, 2), summed
+// from the values the counter increments return (0 + 1 + ... + c - 1).  With PE, a second
+// sweep credits c(y, x) - 1 to each wedge's two edges (the top edge (w, x) directly, the
+// bottom edge (y, w) summed per source first).  Whenever more than `limit` distinct hashed
+// tops appear, the x-range [lo, hi) is halved and redone; a range is credited only after its
+// count sweep completed without overflow, so no wedge is credited twice.
+template <bool PE, typename AT, int T, int G, int HT, int DW>
+__global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, int nlist, int n, int limit,
+                                                 int dense, const int* __restrict__ nrp,
+                                                 const int* __restrict__ ncol, const int* __restrict__ optr,
+                                                 const int* __restrict__ ocol, const int* __restrict__ s2k,
+                                                 EdgeArrays e, u64* __restrict__ gsum, const int* __restrict__ ngid,
+                                                 const int64_t* __restrict__ gvb, int* __restrict__ err) {
+    static_assert(T == GLT_WAVE || G == 1, "multi-wave groups own the whole block");
+    static_assert(HT % 4 == 0 && DW % 4 == 0 && (HT & (HT - 1)) == 0, "table sizes");
+    constexpr int DWA = DW > 0 ? DW : 4;
+    constexpr u32 mask = HT - 1;
+    __shared__ __align__(16) u32 s_dc[G][DWA];
+    __shared__ __align__(16) int s_hk[G][HT];
+    __shared__ __align__(16) u32 s_hc[G][HT];
+    __shared__ int s_k0[G][T], s_pre[G][T];
+    __shared__ AT s_b[G][T];
+    __shared__ int s_scan[G][T / GLT_WAVE];
+    __shared__ int s_lo[G][WEDGE_STACK], s_hi[G][WEDGE_STACK];
+    __shared__ int s_sp[G], s_dist[G], s_ovf[G];
+    const int g = threadIdx.x / T, tid = threadIdx.x % T;
+    const int idx = blockIdx.x * G + g;
+    if (idx >= nlist) return;   // whole groups leave together (G == 1 when T > one wave)
+    const int y = list[idx];
     const int rb = nrp[y], re = nrp[y + 1];
-    const u32 mask = WB_TABLE - 1;
-    const int base = max(n - dense, y + 1);   // tops >= base are counted densely
-    const int nd = n - base;                  // dense counters in use (<= dense <= WB_DENSE)
-    if (tid == 0) { stLo[0] = y + 1; stHi[0] = n; sp = 1; }
+    // tops lie above y inside y's graph: a batch keeps each graph's ranks contiguous
+    const int top = ngid ? (int)gvb[ngid[y] + 1] : n;
+    const int base = max(top - min(dense, DW), y + 1);   // tops >= base are counted densely
+    const int nd = top - base;                            // dense counters in use, <= DW
+    u32* dc = s_dc[g];
+    int* hk = s_hk[g];
+    u32* hc = s_hc[g];
+    int* k0s = s_k0[g];
+    int* pre = s_pre[g];
+    AT* sb = s_b[g];
+    if (tid == 0) { s_lo[g][0] = y + 1; s_hi[g][0] = top; s_sp[g] = 1; }
     u64 c4 = 0;
-    __syncthreads();
+    grp_sync<T>();
     while (true) {
+        const int sp = s_sp[g];
         if (sp == 0) break;
-        const int lo = stLo[sp - 1], hi = stHi[sp - 1];
-        const bool full = (lo == y + 1) && (hi == n);
-        __syncthreads();
-        if (tid == 0) { sp--; distinct = 0; ovf = 0; }
-        for (int q = tid; q < WB_TABLE; q += WB_THREADS) { hkey[q] = -1; hcnt[q] = 0; }
-        for (int q = tid; q < nd; q += WB_THREADS) dcnt[q] = 0;
-        __syncthreads();
-        // count phase
-        for (int c0 = rb; c0 < re; c0 += WB_THREADS) {
+        const int lo = s_lo[g][sp - 1], hi = s_hi[g][sp - 1];
+        const bool full = (lo == y + 1) && (hi == top);
+        grp_sync<T>();
+        if (tid == 0) { s_sp[g] = sp - 1; s_dist[g] = 0; s_ovf[g] = 0; }
+        for (int q = tid; q < HT / 4; q += T) {
+            reinterpret_cast<int4*>(hk)[q] = make_int4(-1, -1, -1, -1);
+            reinterpret_cast<int4*>(hc)[q] = make_int4(0, 0, 0, 0);
+        }
+        for (int q = tid; q < (nd + 3) / 4; q += T) reinterpret_cast<int4*>(dc)[q] = make_int4(0, 0, 0, 0);
+        grp_sync<T>();
+        // count sweep
+        u64 c4r = 0;
+        for (int c0 = rb; c0 < re; c0 += T) {
             const int s = c0 + tid;
-            int wv = 0, k0 = 0, k1 = 0;
-            if (s < re) {
-                wedge_range(y, s, ncol, optr, s2k, wv, k0, k1);
-                if (!full) {
-                    k0 = lower_bound_i32(ocol, k0, k1, lo);
-                    k1 = lower_bound_i32(ocol, k0, k1, hi);
-                }
-            }
-            const int len = k1 - k0;
+            int k0 = 0, k1 = 0;
+            if (s < re) wedge_bounds(y, s, lo, hi, full, ncol, optr, ocol, s2k, k0, k1);
             int tot;
-            const int ex = block_excl_scan<int, WB_THREADS>(len, sScan, tot);
-            const int nsrc = min(WB_THREADS, re - c0);
-            sK0[tid] = k0; sPre[tid] = ex;
-            __syncthreads();
+            const int ex = grp_excl_scan<T>(k1 - k0, s_scan[g], tot);
+            const int nsrc = min(T, re - c0);
+            k0s[tid] = k0;
+            pre[tid] = ex;
+            grp_sync<T>();
             int ii = 0;
-            for (int q = tid; q < tot; q += WB_THREADS) {
-                if (*(volatile int*)&ovf) break;
-                const int i = ii = advance_idx(sPre, nsrc, q, ii);
-                const int x = ocol[sK0[i] + (q - sPre[i])];
-                if (x >= base) {
-                    atomicAdd(&dcnt[x - base], 1u);
-                    continue;
+            for (int q0 = 0; q0 < tot; q0 += WEDGE_ILP * T) {
+                if (*(volatile int*)&s_ovf[g]) break;
+                int xs[WEDGE_ILP];
+#pragma unroll
+                for (int j = 0; j < WEDGE_ILP; j++) {
+                    const int q = q0 + j * T + tid;
+                    xs[j] = -1;
+                    if (q < tot) {
+                        ii = advance_idx(pre, nsrc, q, ii);
+                        xs[j] = ocol[k0s[ii] + (q - pre[ii])];
+                    }
                 }
-                u32 h = hslot(x, mask);
-                while (true) {
-                    int cur = hkey[h];
-                    if (cur == -1) {
-                        cur = atomicCAS(&hkey[h], -1, x);
+#pragma unroll
+                for (int j = 0; j < WEDGE_ILP; j++) {
+                    const int x = xs[j];
+                    if (x < 0) continue;
+                    if (x >= base) {
+                        c4r += atomicAdd(&dc[x - base], 1u);
+                        continue;
+                    }
+                    u32 h = hslot(x, mask);
+                    bool placed = false;
+                    for (int p = 0; p < HT; p++) {   // bounded probe: a full table is an overflow
+                        int cur = hk[h];
                         if (cur == -1) {
-                            atomicAdd(&hcnt[h], 1u);
-                            if (atomicAdd(&distinct, 1) + 1 > limit) ovf = 1;
+                            cur = atomicCAS(&hk[h], -1, x);
+                            if (cur == -1) {
+                                c4r += atomicAdd(&hc[h], 1u);
+                                if (atomicAdd(&s_dist[g], 1) >= limit) s_ovf[g] = 1;
+                                placed = true;
+                                break;
+                            }
+                        }
+                        if (cur == x) {
+                            c4r += atomicAdd(&hc[h], 1u);
+                            placed = true;
                             break;
                         }
+                        h = (h + 1) & mask;
                     }
-                    if (cur == x) { atomicAdd(&hcnt[h], 1u); break; }
-                    h = (h + 1) & mask;
+                    if (!placed) s_ovf[g] = 1;
                 }
             }
-            __syncthreads();
+            grp_sync<T>();
         }
-        if (ovf) {
+        if (s_ovf[g]) {
             if (tid == 0) {
-                const int mid = lo + (hi - lo) / 2;
-                stLo[sp] = mid; stHi[sp] = hi; sp++;
-                stLo[sp] = lo; stHi[sp] = mid; sp++;
+                if (sp + 1 <= WEDGE_STACK && hi - lo >= 2) {
+                    const int mid = lo + (hi - lo) / 2;
+                    s_lo[g][sp - 1] = mid; s_hi[g][sp - 1] = hi;
+                    s_lo[g][sp] = lo; s_hi[g][sp] = mid;
+                    s_sp[g] = sp + 1;
+                } else {
+                    atomicOr(err, ERR_CAP);   // cannot happen while limit >= 1; reported, not hung
+                }
             }
-            __syncthreads();
+            grp_sync<T>();
             continue;
         }
-        for (int q = tid; q < WB_TABLE; q += WB_THREADS) {
-            const u64 c = hcnt[q];
-            c4 += c * (c - (c > 0)) / 2;
-        }
-        for (int q = tid; q < nd; q += WB_THREADS) {
-            const u64 c = dcnt[q];
-            c4 += c * (c - (c > 0)) / 2;
-        }
+        c4 += c4r;
         if (PE) {
-            for (int c0 = rb; c0 < re; c0 += WB_THREADS) {
+            // credit sweep: the counts of this range are final
+            for (int c0 = rb; c0 < re; c0 += T) {
                 const int s = c0 + tid;
-                int wv = 0, k0 = 0, k1 = 0;
-                if (s < re) {
-                    wedge_range(y, s, ncol, optr, s2k, wv, k0, k1);
-                    if (!full) {
-                        k0 = lower_bound_i32(ocol, k0, k1, lo);
-                        k1 = lower_bound_i32(ocol, k0, k1, hi);
-                    }
-                }
-                const int len = k1 - k0;
+                int k0 = 0, k1 = 0;
+                if (s < re) wedge_bounds(y, s, lo, hi, full, ncol, optr, ocol, s2k, k0, k1);
                 int tot;
-                const int ex = block_excl_scan<int, WB_THREADS>(len, sScan, tot);
-                const int nsrc = min(WB_THREADS, re - c0);
-                sK0[tid] = k0; sPre[tid] = ex; sB[tid] = 0;
-                __syncthreads();
-                const int rounds = (tot + WB_THREADS - 1) / WB_THREADS;
+                const int ex = grp_excl_scan<T>(k1 - k0, s_scan[g], tot);
+                const int nsrc = min(T, re - c0);
+                k0s[tid] = k0;
+                pre[tid] = ex;
+                sb[tid] = 0;
+                grp_sync<T>();
                 int ii = 0;
-                for (int r = 0; r < rounds; r++) {
-                    const int q = r * WB_THREADS + tid;
-                    int i = 0x7fffffff;
-                    u64 c = 0;
-                    if (q < tot) {
-                        i = ii = advance_idx(sPre, nsrc, q, ii);
-                        const int k = sK0[i] + (q - sPre[i]);
-                        const int x = ocol[k];
-                        if (x >= base) {
-                            c = dcnt[x - base] - 1;
-                        } else {
-                            u32 h = hslot(x, mask);
-                            while (hkey[h] != x) h = (h + 1) & mask;
-                            c = hcnt[h] - 1;
+                for (int q0 = 0; q0 < tot; q0 += WEDGE_ILP * T) {
+                    int xs[WEDGE_ILP], ks[WEDGE_ILP], is[WEDGE_ILP];
+#pragma unroll
+                    for (int j = 0; j < WEDGE_ILP; j++) {
+                        const int q = q0 + j * T + tid;
+                        is[j] = 0x7fffffff;
+                        ks[j] = 0;
+                        xs[j] = -1;
+                        if (q < tot) {
+                            ii = advance_idx(pre, nsrc, q, ii);
+                            is[j] = ii;
+                            ks[j] = k0s[ii] + (q - pre[ii]);
+                            xs[j] = ocol[ks[j]];
                         }
-                        if (c) acc_add<AT>(e.P, k, c);
                     }
-                    bool last;
-                    const u64 ssum = seg_sum_last(c, i, last);
-                    if (last && ssum) atomicAdd(&sB[i], ssum);
+#pragma unroll
+                    for (int j = 0; j < WEDGE_ILP; j++) {
+                        AT c = 0;
+                        const int x = xs[j];
+                        if (x >= 0) {
+                            u32 cnt = 1;
+                            if (x >= base) {
+                                cnt = dc[x - base];
+                            } else {
+                                u32 h = hslot(x, mask);
+                                int p = 0;
+                                while (p < HT && hk[h] != x) { h = (h + 1) & mask; p++; }
+                                if (p < HT) cnt = hc[h];
+                                else atomicOr(err, ERR_CAP);
+                            }
+                            c = (AT)(cnt - 1);
+                            if (c) acc_add<AT>(e.P, ks[j], (u64)c);
+                        }
+                        bool last;
+                        const AT ssum = seg_sum_last(c, is[j], last);
+                        if (last && ssum) atomicAdd(&sb[is[j]], ssum);
+                    }
                 }
-                __syncthreads();
-                if (s < re && sB[tid]) acc_add<AT>(e.P, s2k[s], sB[tid]);
-                __syncthreads();
+                grp_sync<T>();
+                if (s < re && sb[tid]) acc_add<AT>(e.P, s2k[s], (u64)sb[tid]);
+                grp_sync<T>();
             }
         }
-        __syncthreads();
+        grp_sync<T>();
     }
     c4 = wave_sum(c4);
-    if (glt_lane() == 0) sRed[tid / GLT_WAVE] = c4;
-    __syncthreads();
-    if (tid == 0) {
-        u64 tot = 0;
-        for (int q = 0; q < WB_THREADS / GLT_WAVE; q++) tot += sRed[q];
-        if (tot) atomicAdd(&gsum[(ngid ? ngid[y] : 0) * NSUMS + S_NC4], tot);
-    }
+    if (glt_lane() == 0 && c4) atomicAdd(&gsum[gslot(ngid, y) * NSUMS + S_NC4], c4);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -904,14 +1009,23 @@ __global__ __launch_bounds__(CB_THREADS) void k_combine_graphs(const int64_t* __
 // heaviest-first order of the workgroup work lists (the paper's edge order: hardest jobs
 // first, Section 4.3), so the longest jobs do not start last and run alone
 // ---------------------------------------------------------------------------------------
-// mode 0: work = wedges of y (wcnt); mode 1: work = out-degree of x
+// mode 0: work = wedges of y (wcnt); mode 1: work = out-degree of x.  The sort key is a
+// 13-bit monotone code of the work (exact below 256, else exponent and the 7 bits after the
+// leading one), so two 8-bit radix passes order the list.
+__device__ __forceinline__ u32 work_code(u64 w) {
+    if (w < 256) return (u32)w;
+    const int ex = 63 - __clzll((long long)w);          // >= 8
+    const u32 top = (u32)(w >> (ex - 7));               // [128, 256)
+    return 256u + (u32)(ex - 8) * 128u + (top - 128u);  // < 7424
+}
+
 __global__ void k_work_keys(const int* __restrict__ list, int nlist, int mode, const u64* __restrict__ wcnt,
                             const int* __restrict__ optr, u64* __restrict__ keys, u32* __restrict__ vals) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nlist) return;
     const int x = list[i];
     const u64 w = mode == 0 ? wcnt[x] : (u64)(optr[x + 1] - optr[x]);
-    keys[i] = ((1ull << 40) - 1) - (w < (1ull << 40) ? w : (1ull << 40) - 1);
+    keys[i] = (u64)(0xffffu - work_code(w));   // ascending sort = heaviest first
     vals[i] = (u32)x;
 }
 
@@ -924,8 +1038,47 @@ static void sort_heaviest_first(const Dev& d, int* list, int nlist, int mode, hi
     if (nlist < 2) return;
     const unsigned g = (unsigned)((nlist + 255) / 256);
     hipLaunchKernelGGL(k_work_keys, dim3(g), dim3(256), 0, st, list, nlist, mode, d.wcnt, d.optr, d.key0, d.val0);
-    const int cur = launch_radix_sort(d.key0, d.val0, d.key1, d.val1, nlist, 40, d.rs_counts, d.rs_tmp, st);
+    const int cur = launch_radix_sort(d.key0, d.val0, d.key1, d.val1, nlist, 16, d.rs_counts, d.rs_tmp, st);
     hipLaunchKernelGGL(k_copy_list, dim3(g), dim3(256), 0, st, cur ? d.val1 : d.val0, nlist, list);
+}
+
+// Per-group totals (4-cliques x 3, 4-cycles, triangles per path) are added with one atomic
+// per group into GSPREAD cache lines (single graph) or one line per graph (batch), so that
+// hundreds of thousands of groups do not contend on one address.  One workgroup folds the
+// lines: the single-graph sums land in line 0; the triangle totals go to work[4], work[5],
+// and the preprocessing counters (spread the same way) to work[0..3].
+__global__ __launch_bounds__(256) void k_fold_gsum(u64* __restrict__ gsum, int ngraphs, u64* __restrict__ work,
+                                                   const u64* __restrict__ wspread) {
+    __shared__ u64 red[2][256 / GLT_WAVE];
+    const int t = threadIdx.x;
+    // preprocessing work counters (wedges per path, triangle-pass list entries per path)
+    if (t < 4) {
+        u64 v = 0;
+        for (int q = 0; q < GSPREAD; q++) v += wspread[q * WSPREAD_WORDS + t];
+        work[t] = v;
+    }
+    if (ngraphs <= 0) {
+        u64 v = 0;
+        if (t < NSUMS)
+            for (int q = 0; q < GSPREAD; q++) v += gsum[q * NSUMS + t];
+        __syncthreads();
+        if (t < NSUMS) gsum[t] = v;
+        if (t == GS_TRI_WAVE) work[4] = v;
+        if (t == GS_TRI_WG) work[5] = v;
+        return;
+    }
+    u64 a = 0, b = 0;
+    for (int g = t; g < ngraphs; g += 256) { a += gsum[(int64_t)g * NSUMS + GS_TRI_WAVE]; b += gsum[(int64_t)g * NSUMS + GS_TRI_WG]; }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (glt_lane() == 0) { red[0][t / GLT_WAVE] = a; red[1][t / GLT_WAVE] = b; }
+    __syncthreads();
+    if (t == 0) {
+        u64 ta = 0, tb = 0;
+        for (int q = 0; q < 256 / GLT_WAVE; q++) { ta += red[0][q]; tb += red[1][q]; }
+        work[4] = ta;
+        work[5] = tb;
+    }
 }
 
 static inline int combine_blocks(int m) { return (int)(((int64_t)m + CB_THREADS * CB_EPT - 1) / (CB_THREADS * CB_EPT)); }
@@ -935,105 +1088,137 @@ static inline int combine_blocks(int m) { return (int)(((int64_t)m + CB_THREADS 
 // ---------------------------------------------------------------------------------------
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
+template <bool PE, typename AT>
+static void launch_tri_wave(const Dev& d, const int* lst, int c, hipStream_t st) {
+    if (d.trec)
+        hipLaunchKernelGGL((k_tri_wave<PE, true, AT>), dim3(cdiv(c, 4)), dim3(TB_THREADS), 0, st, lst, c, d.optr, d.ocol,
+                           d.e, d.gsum, d.ngid, d.trec, d.toff, d.tcnt);
+    else
+        hipLaunchKernelGGL((k_tri_wave<PE, false, AT>), dim3(cdiv(c, 4)), dim3(TB_THREADS), 0, st, lst, c, d.optr,
+                           d.ocol, d.e, d.gsum, d.ngid, d.trec, d.toff, d.tcnt);
+}
+
+template <bool PE, bool GM, typename AT>
+static void launch_tri_blk(const Dev& d, const int* lst, int c, int smax, hipStream_t st) {
+    const size_t lds = tri_blk_lds(smax, GM);
+    if (d.trec)
+        hipLaunchKernelGGL((k_tri_blk<PE, GM, true, AT>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax, d.optr,
+                           d.ocol, d.e, d.gsum, d.gscratch, d.ngid, d.trec, d.toff, d.tcnt);
+    else
+        hipLaunchKernelGGL((k_tri_blk<PE, GM, false, AT>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax, d.optr,
+                           d.ocol, d.e, d.gsum, d.gscratch, d.ngid, d.trec, d.toff, d.tcnt);
+}
+
+template <bool GM, typename AT>
+static void launch_gather_blk(const Dev& d, const int* lst, int c, int smax, hipStream_t st) {
+    const size_t lds = gather_blk_lds(smax, GM);
+    if (d.trec)
+        hipLaunchKernelGGL((k_gather_blk<GM, true, AT>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax, d.optr,
+                           d.ocol, d.ndeg, d.e, (u64*)d.gscratch, d.trec, d.toff, d.tcnt);
+    else
+        hipLaunchKernelGGL((k_gather_blk<GM, false, AT>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax, d.optr,
+                           d.ocol, d.ndeg, d.e, (u64*)d.gscratch, d.trec, d.toff, d.tcnt);
+}
+
+template <bool PE, typename AT, int T, int G, int HT, int DW>
+static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st) {
+    if (cnt <= 0) return;
+    const int limit = d.wedge_limit < HT / 2 ? d.wedge_limit : HT / 2;
+    hipLaunchKernelGGL((k_wedge<PE, AT, T, G, HT, DW>), dim3(cdiv(cnt, G)), dim3(T * G), 0, st,
+                       d.wlist + (int64_t)bkt * d.n, cnt, d.n, limit, d.wedge_dense, d.nrp, d.ncol, d.optr, d.ocol,
+                       d.s2k, d.e, d.gsum, d.ngid, d.gvb, d.err);
+}
+
 template <typename AT>
 static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st, hipEvent_t* ev) {
     const int n = d.n, m = d.m;
     u64* gsum = d.gsum;                   // [graph][NSUMS]: 3 x 4-cliques and non-induced 4-cycles
-    launch_fill<u64>(gsum, (int64_t)(d.ngraphs > 0 ? d.ngraphs : 1) * NSUMS, 0ull, st);
+    launch_fill<u64>(gsum, (int64_t)(d.ngraphs > 0 ? d.ngraphs : GSPREAD) * NSUMS, 0ull, st);
     const int* tl = d.tlist;
     const int* cnt = hc;                  // TB_N counts, WB_N counts, TB_N maxima
     const EdgeArrays e = d.e;
     for (int bkt = TB_BLK1; bkt <= TB_GLOBAL; bkt++) sort_heaviest_first(d, d.tlist + (int64_t)bkt * n, cnt[bkt], 1, st);
-    sort_heaviest_first(d, d.wlist + (int64_t)WB_BLK * n, hc[TB_N + WB_BLK], 0, st);
+    for (int bkt = WB_MID; bkt <= WB_BLK; bkt++) sort_heaviest_first(d, d.wlist + (int64_t)bkt * n, hc[TB_N + bkt], 0, st);
+    if (ev) (void)hipEventRecord(ev[0], st);
     // triangle / 4-clique pass
     if (cnt[TB_WAVE] > 0) {
-        if (per_edge)
-            hipLaunchKernelGGL((k_tri_wave<true, AT>), dim3(cdiv(cnt[TB_WAVE], 4)), dim3(TB_THREADS), 0, st,
-                               tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, e, gsum, d.ngid);
-        else
-            hipLaunchKernelGGL((k_tri_wave<false, AT>), dim3(cdiv(cnt[TB_WAVE], 4)), dim3(TB_THREADS), 0, st,
-                               tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, e, gsum, d.ngid);
+        if (per_edge) launch_tri_wave<true, AT>(d, tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], st);
+        else launch_tri_wave<false, AT>(d, tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], st);
     }
+    if (ev) (void)hipEventRecord(ev[1], st);
     for (int bkt = TB_BLK1; bkt <= TB_GLOBAL; bkt++) {
         const int c = cnt[bkt];
         if (c <= 0) continue;
         const int smax = cnt[TB_N + WB_N + bkt];
         const bool gm = (bkt == TB_GLOBAL);
-        const size_t lds = tri_blk_lds(smax, gm);
         const int* lst = tl + (int64_t)bkt * n;
+        // the global slab holds one M per workgroup: launch in groups that fit it
+        int64_t grp = c;
         if (gm) {
-            // the global slab holds one M per workgroup: launch in groups that fit it
             const int64_t per = (int64_t)smax * ((smax + 31) / 32);
-            int64_t grp = d.gscratch_words / per;
+            grp = d.gscratch_words / per;
             if (grp < 1) grp = 1;
-            for (int64_t off = 0; off < c; off += grp) {
-                const int cc = (int)((c - off < grp) ? (c - off) : grp);
-                if (per_edge)
-                    hipLaunchKernelGGL((k_tri_blk<true, true, AT>), dim3(cc), dim3(TB_THREADS), lds, st, lst + off, cc,
-                                       smax, d.optr, d.ocol, e, gsum, d.gscratch, d.ngid);
-                else
-                    hipLaunchKernelGGL((k_tri_blk<false, true, AT>), dim3(cc), dim3(TB_THREADS), lds, st, lst + off, cc,
-                                       smax, d.optr, d.ocol, e, gsum, d.gscratch, d.ngid);
+        }
+        for (int64_t off = 0; off < c; off += grp) {
+            const int cc = (int)((c - off < grp) ? (c - off) : grp);
+            if (per_edge) {
+                if (gm) launch_tri_blk<true, true, AT>(d, lst + off, cc, smax, st);
+                else launch_tri_blk<true, false, AT>(d, lst + off, cc, smax, st);
+            } else {
+                if (gm) launch_tri_blk<false, true, AT>(d, lst + off, cc, smax, st);
+                else launch_tri_blk<false, false, AT>(d, lst + off, cc, smax, st);
             }
-        } else {
-            if (per_edge)
-                hipLaunchKernelGGL((k_tri_blk<true, false, AT>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax,
-                                   d.optr, d.ocol, e, gsum, d.gscratch, d.ngid);
-            else
-                hipLaunchKernelGGL((k_tri_blk<false, false, AT>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax,
-                                   d.optr, d.ocol, e, gsum, d.gscratch, d.ngid);
         }
     }
-    if (ev) (void)hipEventRecord(ev[0], st);
+    if (ev) (void)hipEventRecord(ev[2], st);
     // gather pass
+    if (per_edge && cnt[TB_WAVE] > 0) {
+        if (d.trec)
+            hipLaunchKernelGGL((k_gather_wave<true, AT>), dim3(cdiv(cnt[TB_WAVE], 4)), dim3(TB_THREADS), 0, st,
+                               tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, d.ndeg, e, d.trec, d.toff,
+                               d.tcnt);
+        else
+            hipLaunchKernelGGL((k_gather_wave<false, AT>), dim3(cdiv(cnt[TB_WAVE], 4)), dim3(TB_THREADS), 0, st,
+                               tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, d.ndeg, e, d.trec, d.toff,
+                               d.tcnt);
+    }
+    if (ev) (void)hipEventRecord(ev[3], st);
     if (per_edge) {
-        if (cnt[TB_WAVE] > 0)
-            hipLaunchKernelGGL(k_gather_wave<AT>, dim3(cdiv(cnt[TB_WAVE], 4)), dim3(TB_THREADS), 0, st,
-                               tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, d.ndeg, e);
         for (int bkt = TB_BLK1; bkt <= TB_GLOBAL; bkt++) {
             const int c = cnt[bkt];
             if (c <= 0) continue;
             const int smax = cnt[TB_N + WB_N + bkt];
             const int* lst = tl + (int64_t)bkt * n;
-            if (bkt == TB_GLOBAL) {
+            const bool gm = (bkt == TB_GLOBAL);
+            int64_t grp = c;
+            if (gm) {
                 const int64_t per = 2 * (int64_t)smax * 2;   // u64 accumulators, in u32 words
-                int64_t grp = d.gscratch_words / per;
+                grp = d.gscratch_words / per;
                 if (grp < 1) grp = 1;
-                for (int64_t off = 0; off < c; off += grp) {
-                    const int cc = (int)((c - off < grp) ? (c - off) : grp);
-                    hipLaunchKernelGGL((k_gather_blk<true, AT>), dim3(cc), dim3(TB_THREADS), gather_blk_lds(smax, true), st,
-                                       lst + off, cc, smax, d.optr, d.ocol, d.ndeg, e, (u64*)d.gscratch);
-                }
-            } else {
-                hipLaunchKernelGGL((k_gather_blk<false, AT>), dim3(c), dim3(TB_THREADS), gather_blk_lds(smax, false), st,
-                                   lst, c, smax, d.optr, d.ocol, d.ndeg, e, (u64*)d.gscratch);
+            }
+            for (int64_t off = 0; off < c; off += grp) {
+                const int cc = (int)((c - off < grp) ? (c - off) : grp);
+                if (gm) launch_gather_blk<true, AT>(d, lst + off, cc, smax, st);
+                else launch_gather_blk<false, AT>(d, lst + off, cc, smax, st);
             }
         }
     }
-    if (ev) (void)hipEventRecord(ev[1], st);
-    // wedge pass
+    if (ev) (void)hipEventRecord(ev[4], st);
+    // wedge pass: wave and mid classes (one wavefront per bottom vertex), then workgroups
     const int* wc = hc + TB_N;
-    if (wc[WB_WAVE] > 0) {
-        if (per_edge)
-            hipLaunchKernelGGL((k_wedge_wave<true, AT>), dim3(cdiv(wc[WB_WAVE], 4)), dim3(256), 0, st,
-                               d.wlist + (int64_t)WB_WAVE * n, wc[WB_WAVE], d.nrp, d.ncol, d.optr, d.ocol, d.s2k,
-                               e, gsum, d.ngid);
-        else
-            hipLaunchKernelGGL((k_wedge_wave<false, AT>), dim3(cdiv(wc[WB_WAVE], 4)), dim3(256), 0, st,
-                               d.wlist + (int64_t)WB_WAVE * n, wc[WB_WAVE], d.nrp, d.ncol, d.optr, d.ocol, d.s2k,
-                               e, gsum, d.ngid);
+    if (per_edge) {
+        launch_wedge<true, AT, WW_T, WW_G, WW_HT, 0>(d, WB_WAVE, wc[WB_WAVE], st);
+        launch_wedge<true, AT, WM_T, WM_G, WM_HT, WM_DW>(d, WB_MID, wc[WB_MID], st);
+    } else {
+        launch_wedge<false, AT, WW_T, WW_G, WW_HT, 0>(d, WB_WAVE, wc[WB_WAVE], st);
+        launch_wedge<false, AT, WM_T, WM_G, WM_HT, WM_DW>(d, WB_MID, wc[WB_MID], st);
     }
-    if (wc[WB_BLK] > 0) {
-        if (per_edge)
-            hipLaunchKernelGGL((k_wedge_blk<true, AT>), dim3(wc[WB_BLK]), dim3(WB_THREADS), 0, st,
-                               d.wlist + (int64_t)WB_BLK * n, wc[WB_BLK], n, d.wedge_limit, d.wedge_dense, d.nrp,
-                               d.ncol, d.optr, d.ocol, d.s2k, e, gsum, d.ngid);
-        else
-            hipLaunchKernelGGL((k_wedge_blk<false, AT>), dim3(wc[WB_BLK]), dim3(WB_THREADS), 0, st,
-                               d.wlist + (int64_t)WB_BLK * n, wc[WB_BLK], n, d.wedge_limit, d.wedge_dense, d.nrp,
-                               d.ncol, d.optr, d.ocol, d.s2k, e, gsum, d.ngid);
-    }
-    if (ev) (void)hipEventRecord(ev[2], st);
+    if (ev) (void)hipEventRecord(ev[5], st);
+    if (per_edge)
+        launch_wedge<true, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], st);
+    else
+        launch_wedge<false, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], st);
+    if (ev) (void)hipEventRecord(ev[6], st);
     // vertex pass + combine
     if (per_edge && n > 0 && m > 0) {
         launch_fill<u64>(d.tri, n, 0ull, st);
@@ -1056,7 +1241,8 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
     } else {
         launch_fill<u64>(d.final_sums, 2 * NCS, 0ull, st);
     }
-    if (ev) (void)hipEventRecord(ev[3], st);
+    if (ev) (void)hipEventRecord(ev[7], st);
+    hipLaunchKernelGGL(k_fold_gsum, dim3(1), dim3(256), 0, st, gsum, d.ngraphs, d.work, d.wspread);
 }
 
 void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st, hipEvent_t* ev) {
@@ -1069,6 +1255,6 @@ void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hi
 int glt_combine_blocks(int m) { return combine_blocks(m); }
 // largest out-degree the block passes accept (LDS holds 5 ints per neighbour of a)
 int glt_max_out_degree() { return 3200; }
-int glt_wedge_table() { return WB_TABLE; }
-int glt_wedge_dense() { return WB_DENSE; }
-int glt_wave_table() { return WW_TABLE; }
+int glt_wedge_table() { return WB_HT; }
+int glt_wedge_dense() { return WB_DW; }
+int glt_wave_table() { return WW_HT; }

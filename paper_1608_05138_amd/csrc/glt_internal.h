@@ -12,7 +12,20 @@ enum {
     ERR_DUP = 4,         // duplicate entry
     ERR_ASYM = 8,        // entry without its reverse
     ERR_NEG = 16,        // a per-edge count came out negative (internal)
+    ERR_CAP = 32,        // an LDS table or range stack bound was exceeded (internal)
 };
+// d.err words: [0] error bits, [1] maximum degree, [2 + c] rows of sort class c (from the
+// validation), [2 + RS_N + c] append counters of the row lists (preprocessing).
+#define ERR_WORDS 16
+
+// Size classes of the per-row sort of P2 (entries per row).
+enum { RS_TINY = 0, RS_WAVE, RS_BLK, RS_BIG, RS_N };
+#define RT_MAX 16       // thread per row (sorting network in registers)
+#define RW_MAX 64       // wavefront per row (bitonic over lanes)
+#define RB_MAX 2048     // workgroup per row (bitonic in LDS); longer rows: radix passes
+__host__ __device__ inline int row_class(int64_t len) {
+    return len <= 1 ? -1 : len <= RT_MAX ? RS_TINY : len <= RW_MAX ? RS_WAVE : len <= RB_MAX ? RS_BLK : RS_BIG;
+}
 
 // Per oriented edge (u -> v, u before v in the degree order) accumulators, one dense
 // array per quantity indexed by the oriented index k.  Credits to the out-edges of one
@@ -32,12 +45,23 @@ struct EdgeArrays {
 //   14     : 3 x (number of 4-cliques), from the triangle pass
 //   15     : number of non-induced 4-cycles, from the wedge pass
 #define NSUMS 16
+#define NWORK 6
+#define NSEG 8      // timed segments: prep, tri wave, tri wg, gather wave, gather wg, wedge wave, wedge wg, combine
 enum { S_C3 = 0, S_C4, S_C5, S_C7, S_C8, S_C9, S_C10, S_C11, S_C12, S_C13, S_C14, S_C15, S_C16,
        S_SPARE, S_K4x3, S_NC4 };
+// The per-group totals array (gsum) holds NSUMS words per line and uses S_K4x3, S_NC4 and
+// the triangle counts of the two triangle-pass paths (measurement only).
+enum { GS_TRI_WAVE = 0, GS_TRI_WG = 1 };
+#define GSPREAD 64   // lines of gsum a single graph's groups spread their atomics over
+#define WSPREAD_WORDS 8   // u64 per line of the spread work counters (work[0..3] before folding)
+// gsum line of a group: its graph in a batch, else spread by workgroup index
+__device__ __forceinline__ int64_t gslot(const int* ngid, int v) {
+    return ngid ? (int64_t)ngid[v] : (int64_t)(blockIdx.x & (GSPREAD - 1));
+}
 
 // Bucket ids for the vertex work lists.
 enum { TB_WAVE = 0, TB_BLK1, TB_BLK2, TB_GLOBAL, TB_N };   // triangle / gather passes
-enum { WB_WAVE = 0, WB_BLK, WB_N };                         // wedge pass
+enum { WB_WAVE = 0, WB_MID, WB_BLK, WB_N };                 // wedge pass
 
 // Device pointers of one graph's workspace.
 struct Dev {
@@ -60,9 +84,15 @@ struct Dev {
     u64* tri;         // twice the triangles at each relabelled vertex [n]
     u64* sdeg;        // sum of neighbour degrees [n]
     int* tlist;       // triangle-pass vertex lists, TB_N segments of n
+    u64* toff;        // [n+1] triangle-record slots before vertex a: prefix of C(|N+(a)|, 2)
+    int* tcnt;        // [n] triangle records written for lowest vertex a
+    u64* tmp64;       // scan scratch for toff
+    u64* wspread;     // [GSPREAD][WSPREAD_WORDS] preprocessing work counters, folded into work[0..3]
+    u64* trec;        // triangle records (null: the passes re-scan the out-lists instead)
     int* wlist;       // wedge-pass vertex lists, WB_N segments of n
     int* counts;      // bucket counts and maxima (TB_N + WB_N + TB_N)
-    u64* work;        // work counters: [0] wedges, [1] out-list entries scanned by the triangle pass
+    u64* work;        // work counters [NWORK]: wedges (wave / workgroup path), triangle-pass list
+                      // entries (wave / workgroup path), triangles found (wave / workgroup path)
     u64* wcnt;        // wedges per vertex [n] (wedge-pass bucketing)
     u32* rowx;        // [S+1] exclusive prefix of row starts of the input CSR: row of entry s = rowx[s+1]-1
     int* nsrow;       // [S] row of each relabelled CSR entry
@@ -87,7 +117,8 @@ struct Dev {
     const int** glrp;     // device array of per-graph local-offset pointers [ngraphs]
     const int** glcol;    // device array of per-graph local-column pointers [ngraphs]
     // tuning (defaults; overridable per handle for testing)
-    int wedge_wave_max;   // wedge-pass vertices with at most this many wedges use one wavefront
+    int wedge_wave_max;   // wedge-pass vertices with at most this many wedges: wave class (hash only)
+    int wedge_mid_max;    // up to this many: mid class (one wavefront, dense window + hash)
     int wedge_limit;      // distinct hashed tops per range before the range is split
     int wedge_dense;      // width of the dense window of highest-ranked tops
     int acc32;            // per-edge accumulators fit 32 bits (maximum degree <= 46340)
@@ -99,6 +130,6 @@ struct Timing { float ms[5]; };
 int glt_union_build(const Dev& d, int* urp, int* ucol, hipStream_t st);
 int glt_prep_validate(const Dev& d, const void* rp, int rp64, const int* col, hipStream_t st);
 int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipStream_t st,
-                   int* host_counts /* TB_N + WB_N + TB_N */);
+                   const int* vinfo /* max degree, then RS_N row-class counts */);
 void glt_count_passes(const Dev& d, int per_edge, const int* host_counts, u64* out_pe,
-                      hipStream_t st, hipEvent_t* ev /* 4 events or null */);
+                      hipStream_t st, hipEvent_t* ev /* NSEG events (segment ends 1..NSEG) or null */);

@@ -21,6 +21,37 @@ __device__ __forceinline__ int wave_or(int v) {
     return v;
 }
 
+// Appends `value` to list `cls` (one of NL lists, `stride` apart) for every thread whose
+// cls is in [0, NL), with one global atomic per workgroup and list (per-wavefront counts are
+// combined in LDS first: hundreds of thousands of wavefronts on a few counters would
+// serialise).  Every thread of the 256-thread workgroup must call it, once per kernel.
+template <int NL>
+__device__ __forceinline__ void block_append(int* counters, int* lists, int64_t stride, int cls, int value) {
+    __shared__ int wc[NL][256 / GLT_WAVE];
+    __shared__ int base[NL];
+    const int lane = glt_lane(), w = threadIdx.x / GLT_WAVE;
+    const u64 lt = (lane == 0) ? 0ull : ((~0ull) >> (GLT_WAVE - lane));
+    u64 mine = 0;
+#pragma unroll
+    for (int c = 0; c < NL; c++) {
+        const u64 msk = __ballot(cls == c);
+        if (cls == c) mine = msk;
+        if (lane == 0) wc[c][w] = (int)__popcll(msk);
+    }
+    __syncthreads();
+    if (threadIdx.x < NL) {
+        int tot = 0;
+        for (int q = 0; q < 256 / GLT_WAVE; q++) tot += wc[threadIdx.x][q];
+        base[threadIdx.x] = tot ? atomicAdd(&counters[threadIdx.x], tot) : 0;
+    }
+    __syncthreads();
+    if (cls >= 0 && cls < NL) {
+        int off = base[cls];
+        for (int q = 0; q < w; q++) off += wc[cls][q];
+        lists[(int64_t)cls * stride + off + (int)__popcll(mine & lt)] = value;
+    }
+}
+
 static inline unsigned nblk(int64_t items, int per) { return (unsigned)((items + per - 1) / per); }
 
 // ---------------------------------------------------------------------------------------
@@ -42,6 +73,18 @@ __global__ __launch_bounds__(256) void k_check_rows(const RP* __restrict__ rp, i
     }
     const int bad = wave_or((x < n && !ok) ? ERR_RANGE : 0);
     if (glt_lane() == 0 && bad) atomicOr(err, bad);
+    // rows per sort class of P2, summed per workgroup before one atomic per class
+    __shared__ int cls_cnt[RS_N];
+    if (threadIdx.x < RS_N) cls_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int cls = (x < n && ok) ? row_class(deg[x]) : -1;
+#pragma unroll
+    for (int c = 0; c < RS_N; c++) {
+        const u64 msk = __ballot(cls == c);
+        if (glt_lane() == 0 && msk) atomicAdd(&cls_cnt[c], (int)__popcll(msk));
+    }
+    __syncthreads();
+    if (threadIdx.x < RS_N && cls_cnt[threadIdx.x]) atomicAdd(&err[2 + threadIdx.x], cls_cnt[threadIdx.x]);
     // rows of a wavefront start at non-decreasing offsets: count each offset once per run
     bool last;
     const int key = ok ? (int)b : 0x7fffffff;
@@ -139,7 +182,7 @@ __global__ __launch_bounds__(256) void k_union_cols(const int64_t* __restrict__ 
 
 int glt_union_build(const Dev& d, int* urp, int* ucol, hipStream_t st) {
     (void)ucol;
-    (void)hipMemsetAsync(d.err, 0, 4 * sizeof(int), st);
+    (void)hipMemsetAsync(d.err, 0, ERR_WORDS * sizeof(int), st);
     if (d.ngraphs <= 0) return 0;
     hipLaunchKernelGGL(k_union_rows, dim3(d.ngraphs), dim3(256), 0, st, d.gvb, d.gsb, d.glrp, urp, d.gid, d.err);
     launch_fill<int>(urp + d.n, 1, d.S, st);
@@ -149,48 +192,227 @@ int glt_union_build(const Dev& d, int* urp, int* ucol, hipStream_t st) {
 // ---------------------------------------------------------------------------------------
 // P1 / P2 / P3
 // ---------------------------------------------------------------------------------------
-__global__ void k_iota_keys(const int* __restrict__ deg, int n, u64* __restrict__ keys, u32* __restrict__ vals) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) { keys[i] = (u64)(u32)deg[i]; vals[i] = (u32)i; }
-}
-
-__global__ void k_apply_order(const u32* __restrict__ sorted_ids, const int* __restrict__ deg, int n,
-                              int* __restrict__ order, int* __restrict__ rank, int* __restrict__ ndeg,
-                              const int* __restrict__ gid, int* __restrict__ ngid) {
+// P1 sort keys: the degree; in a batch (graph, degree), so that every graph's vertices keep
+// the contiguous rank range of their union ids, degree-ordered inside it.
+__global__ void k_iota_keys(const int* __restrict__ deg, const int* __restrict__ gid, int degbits, int n,
+                            u64* __restrict__ keys, u32* __restrict__ vals) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
-        int x = (int)sorted_ids[i];
+        keys[i] = (gid ? ((u64)(u32)gid[i] << degbits) : 0ull) | (u64)(u32)deg[i];
+        vals[i] = (u32)i;
+    }
+}
+
+// Rank i -> original id; also appends i to the list of its row's sort class.
+__global__ __launch_bounds__(256) void k_apply_order(const u32* __restrict__ sorted_ids, const int* __restrict__ deg,
+                                                     int n, int* __restrict__ order, int* __restrict__ rank,
+                                                     int* __restrict__ ndeg, const int* __restrict__ gid,
+                                                     int* __restrict__ ngid, int* __restrict__ rlist,
+                                                     int* __restrict__ rcnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int cls = -1;
+    if (i < n) {
+        const int x = (int)sorted_ids[i];
         order[i] = x;
         rank[x] = i;
         ndeg[i] = deg[x];
         if (ngid) ngid[i] = gid[x];
+        cls = row_class(deg[x]);
     }
+    block_append<RS_N>(rcnt, rlist, n, cls, i);
 }
 
-// One thread per entry of the caller's CSR: the relabelled (src, dst) key, the caller's
-// entry index as payload, and the "upward in caller ids" flag whose prefix sum numbers the
-// caller's edges.
-__global__ __launch_bounds__(256) void k_emit(const u32* __restrict__ rowx, const int* __restrict__ col, int64_t S,
-                                              const int* __restrict__ rank, int B, u64* __restrict__ keys,
-                                              u32* __restrict__ vals, u32* __restrict__ upflag) {
+// P2 without a global sort: row x of the caller's CSR becomes row rank[x] with the same
+// length, so every entry goes straight to nrp[rank[x]] + (its offset within the row), keyed by
+// its neighbour's rank and carrying its caller index; then each row is sorted on its own.
+// Also sets the "upward in caller ids" flag whose prefix sum numbers the caller's edges.
+template <typename RP>
+__global__ __launch_bounds__(256) void k_place(const RP* __restrict__ rp, const u32* __restrict__ rowx,
+                                               const int* __restrict__ col, int64_t S, const int* __restrict__ rank,
+                                               const int* __restrict__ nrp, u32* __restrict__ key,
+                                               u32* __restrict__ val, int* __restrict__ nsrow,
+                                               u32* __restrict__ upflag) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S) return;
     const int x = (int)rowx[s + 1] - 1;
     const int y = col[s];
-    keys[s] = ((u64)(u32)rank[x] << B) | (u64)(u32)rank[y];
-    vals[s] = (u32)s;
+    const int r = rank[x];
+    const int64_t pos = (int64_t)nrp[r] + (s - (int64_t)rp[x]);
+    key[pos] = (u32)rank[y];
+    val[pos] = (u32)s;
+    nsrow[pos] = r;
     upflag[s] = (y > x) ? 1u : 0u;
 }
 
-// Sorted keys -> relabelled rows and columns; adjacent equal keys are duplicate entries.
-__global__ void k_unpack_cols(const u64* __restrict__ keys, int64_t S, int B, int* __restrict__ ncol,
-                              int* __restrict__ nsrow, int* __restrict__ err) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
-    const u64 k = keys[s];
-    ncol[s] = (int)(k & ((1ull << B) - 1));
-    nsrow[s] = (int)(k >> B);
-    if (s > 0 && keys[s - 1] == k) atomicOr(err, ERR_DUP);
+#define PAD_KEY 0xffffffffu   // sorts after every rank (ranks are < 2^31)
+
+// Rows of 2..RT_MAX entries: one thread per row, bitonic network over RT_MAX registers.
+__global__ __launch_bounds__(256) void k_sort_tiny(const int* __restrict__ list, int cnt, const int* __restrict__ nrp,
+                                                   u32* __restrict__ key, u32* __restrict__ val) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const int r = list[i];
+    const int b = nrp[r], len = nrp[r + 1] - b;
+    u32 k[RT_MAX], v[RT_MAX];
+#pragma unroll
+    for (int j = 0; j < RT_MAX; j++) {
+        k[j] = (j < len) ? key[b + j] : PAD_KEY;
+        v[j] = (j < len) ? val[b + j] : 0u;
+    }
+#pragma unroll
+    for (int kk = 2; kk <= RT_MAX; kk <<= 1) {
+#pragma unroll
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+#pragma unroll
+            for (int a = 0; a < RT_MAX; a++) {
+                const int c = a ^ jj;
+                if (c > a) {
+                    const bool up = (a & kk) == 0;
+                    if ((k[a] > k[c]) == up) {
+                        const u32 tk = k[a]; k[a] = k[c]; k[c] = tk;
+                        const u32 tv = v[a]; v[a] = v[c]; v[c] = tv;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < RT_MAX; j++)
+        if (j < len) { key[b + j] = k[j]; val[b + j] = v[j]; }
+}
+
+// Rows of RT_MAX+1..RW_MAX entries: one wavefront per row, bitonic over the lanes.
+__global__ __launch_bounds__(256) void k_sort_wave(const int* __restrict__ list, int cnt, const int* __restrict__ nrp,
+                                                   u32* __restrict__ key, u32* __restrict__ val) {
+    const int i = blockIdx.x * (256 / GLT_WAVE) + threadIdx.x / GLT_WAVE;
+    if (i >= cnt) return;   // whole wavefronts
+    const int l = glt_lane();
+    const int r = list[i];
+    const int b = nrp[r], len = nrp[r + 1] - b;
+    u32 k = (l < len) ? key[b + l] : PAD_KEY;
+    u32 v = (l < len) ? val[b + l] : 0u;
+#pragma unroll
+    for (int kk = 2; kk <= GLT_WAVE; kk <<= 1) {
+#pragma unroll
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            const u32 ok = __shfl_xor(k, jj, GLT_WAVE);
+            const u32 ov = __shfl_xor(v, jj, GLT_WAVE);
+            const bool up = (l & kk) == 0;
+            const bool lower = (l & jj) == 0;
+            // lower lane of an ascending pair keeps the minimum, upper the maximum
+            const bool take = lower ? ((k > ok) == up) : ((k < ok) == up);
+            if (take) { k = ok; v = ov; }
+        }
+    }
+    if (l < len) { key[b + l] = k; val[b + l] = v; }
+}
+
+// Rows of RW_MAX+1..RB_MAX entries: one workgroup per row, bitonic in LDS.
+__global__ __launch_bounds__(256) void k_sort_blk(const int* __restrict__ list, int cnt, const int* __restrict__ nrp,
+                                                  u32* __restrict__ key, u32* __restrict__ val) {
+    __shared__ u32 sk[RB_MAX], sv[RB_MAX];
+    const int t = threadIdx.x;
+    const int r = list[blockIdx.x];
+    const int b = nrp[r], len = nrp[r + 1] - b;
+    int P = 2 * RW_MAX;
+    while (P < len) P <<= 1;   // <= RB_MAX
+    for (int j = t; j < P; j += 256) {
+        sk[j] = (j < len) ? key[b + j] : PAD_KEY;
+        sv[j] = (j < len) ? val[b + j] : 0u;
+    }
+    __syncthreads();
+    for (int kk = 2; kk <= P; kk <<= 1) {
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            for (int q = t; q < P / 2; q += 256) {
+                const int lo = ((q & ~(jj - 1)) << 1) | (q & (jj - 1));
+                const int hi = lo + jj;
+                const bool up = (lo & kk) == 0;
+                const u32 a = sk[lo], c = sk[hi];
+                if ((a > c) == up) {
+                    sk[lo] = c; sk[hi] = a;
+                    const u32 tv = sv[lo]; sv[lo] = sv[hi]; sv[hi] = tv;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int j = t; j < len; j += 256) { key[b + j] = sk[j]; val[b + j] = sv[j]; }
+}
+
+// Rows longer than RB_MAX: one workgroup per row, stable LSD radix passes of 8 bits over
+// `bits` key bits, ping-ponging between (kA, vA) and (kB, vB) at the row's own positions;
+// the result ends in (kA, vA).
+__global__ __launch_bounds__(256) void k_sort_big(const int* __restrict__ list, int cnt, const int* __restrict__ nrp,
+                                                  u32* __restrict__ kA, u32* __restrict__ vA, u32* __restrict__ kB,
+                                                  u32* __restrict__ vB, int bits) {
+    __shared__ u32 base[256];
+    __shared__ u32 wcnt[256 / GLT_WAVE][256];
+    __shared__ u32 sscan[256 / GLT_WAVE];
+    const int t = threadIdx.x, lane = glt_lane(), w = t / GLT_WAVE;
+    const int r = list[blockIdx.x];
+    const int64_t b = nrp[r];
+    const int len = nrp[r + 1] - (int)b;
+    u32* ki = kA + b; u32* vi = vA + b;
+    u32* ko = kB + b; u32* vo = vB + b;
+    const u64 lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (GLT_WAVE - lane));
+    int npass = 0;
+    for (int shift = 0; shift < bits; shift += 8, npass++) {
+        base[t] = 0;
+        for (int q = 0; q < 256 / GLT_WAVE; q++) wcnt[q][t] = 0;
+        __syncthreads();
+        for (int j = t; j < len; j += 256) atomicAdd(&base[(ki[j] >> shift) & 255u], 1u);
+        __syncthreads();
+        u32 tot;
+        const u32 ex = block_excl_scan<u32, 256>(base[t], sscan, tot);
+        base[t] = ex;
+        __syncthreads();
+        for (int j0 = 0; j0 < len; j0 += 256) {
+            const int j = j0 + t;
+            const bool valid = j < len;
+            const u32 k = valid ? ki[j] : 0u;
+            const u32 v = valid ? vi[j] : 0u;
+            const u32 d = (k >> shift) & 255u;
+            u64 peers = __ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < 8; bit++) {
+                const u64 bb = __ballot((d >> bit) & 1u);
+                peers &= ((d >> bit) & 1u) ? bb : ~bb;
+            }
+            const u32 rk = (u32)__popcll(peers & lt_mask);
+            if (valid && rk == 0) wcnt[w][d] = (u32)__popcll(peers);
+            __syncthreads();
+            if (valid) {
+                u32 off = base[d];
+                for (int q = 0; q < w; q++) off += wcnt[q][d];
+                ko[off + rk] = k;
+                vo[off + rk] = v;
+            }
+            __syncthreads();
+            u32 add = 0;
+            for (int q = 0; q < 256 / GLT_WAVE; q++) { add += wcnt[q][t]; wcnt[q][t] = 0; }
+            base[t] += add;
+            __syncthreads();
+        }
+        u32* tk = ki; ki = ko; ko = tk;
+        u32* tv = vi; vi = vo; vo = tv;
+    }
+    if (npass & 1)
+        for (int j = t; j < len; j += 256) { kA[b + j] = kB[b + j]; vA[b + j] = vB[b + j]; }
+}
+
+// Sorted rows -> relabelled columns; equal neighbours side by side in a row are duplicates.
+__global__ __launch_bounds__(256) void k_unpack_cols(const u32* __restrict__ key, int64_t S,
+                                                     const int* __restrict__ nsrow, const int* __restrict__ nrp,
+                                                     int* __restrict__ ncol, int* __restrict__ err) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int bad = 0;
+    if (s < S) {
+        const u32 k = key[s];
+        ncol[s] = (int)k;
+        if (s > nrp[nsrow[s]] && key[s - 1] == k) bad = ERR_DUP;
+    }
+    bad = wave_or(bad);
+    if (glt_lane() == 0 && bad) atomicOr(err, bad);
 }
 
 // dlo[x] = number of neighbours ranked below x (the row is ascending, binary search).
@@ -255,67 +477,85 @@ __device__ __forceinline__ int tbucket(int s) {
     return TB_GLOBAL;
 }
 
-__device__ __forceinline__ void wave_append(int* counter, int* list, bool pred, int value) {
-    const int lane = glt_lane();
-    u64 mask = __ballot(pred);
-    if (mask == 0) return;
-    int leader = __ffsll((long long)mask) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(counter, __popcll(mask));
-    base = __shfl(base, leader, GLT_WAVE);
-    u64 lt = (lane == 0) ? 0ull : ((~0ull) >> (GLT_WAVE - lane));
-    if (pred) list[base + __popcll(mask & lt)] = value;
-}
 
+// Triangle-pass lists by out-degree; toff[x] = C(|N+(x)|, 2), the most triangles x can be
+// the lowest vertex of (its prefix sum places x's triangle records).
 __global__ __launch_bounds__(256) void k_tbuckets(const int* __restrict__ optr, int n, int* __restrict__ tlist,
-                                                  int* __restrict__ counts, int* __restrict__ tmax) {
+                                                  int* __restrict__ counts, int* __restrict__ tmax,
+                                                  u64* __restrict__ toff) {
+    __shared__ int bmax[TB_N];
+    if (threadIdx.x < TB_N) bmax[threadIdx.x] = 0;
     int x = blockIdx.x * blockDim.x + threadIdx.x;
     int s = (x < n) ? optr[x + 1] - optr[x] : 0;
     int b = (x < n) ? tbucket(s) : -1;
+    if (x < n) toff[x] = (u64)s * (u64)(s > 0 ? s - 1 : 0) / 2;
+    block_append<TB_N>(counts, tlist, n, b, x);   // (its barriers also order bmax's clearing)
     for (int q = 0; q < TB_N; q++) {
-        wave_append(&counts[q], tlist + (int64_t)q * n, b == q, x);
         const int mx = wave_max(b == q ? s : 0);
-        if (glt_lane() == 0 && mx) atomicMax(&tmax[q], mx);
+        if (glt_lane() == 0 && mx) atomicMax(&bmax[q], mx);
     }
+    __syncthreads();
+    if (threadIdx.x < TB_N && bmax[threadIdx.x]) atomicMax(&tmax[threadIdx.x], bmax[threadIdx.x]);
 }
 
 // Wedge pass work: per relabelled entry (y -> w) the wedges y - w - x with x above both y
 // and w (x in N+(w), x > y), summed per y; and the triangle pass's list lengths |N+(w)|
-// over upward entries.  One thread per entry, runs of one row summed in the wavefront.
+// over upward entries, totalled by the triangle-pass path of y (work[2] wave, work[3]
+// workgroup).  One thread per entry, runs of one row summed in the wavefront.
 __global__ __launch_bounds__(256) void k_wcount(const int* __restrict__ ncol, const int* __restrict__ nsrow,
                                                 const int* __restrict__ optr, const int* __restrict__ s2k, int64_t S,
-                                                u64* __restrict__ wcnt, u64* __restrict__ work) {
+                                                u64* __restrict__ wcnt, u64* __restrict__ wspread) {
     __shared__ u64 red[2][256 / GLT_WAVE];
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    u64 wc = 0, ls = 0;
+    u64 wc = 0, lw = 0, lb = 0;
     int y = 0x7fffffff;
     if (s < S) {
         y = nsrow[s];
         const int w = ncol[s];
         const int dpw = optr[w + 1] - optr[w];
         wc = (u64)((w > y) ? dpw : (optr[w + 1] - s2k[s] - 1));
-        ls = (u64)((w > y) ? dpw : 0);
+        if (w > y) {
+            const int dpy = optr[y + 1] - optr[y];
+            if (dpy >= 2 && dpy <= 64) lw = (u64)dpw;
+            else if (dpy > 64) lb = (u64)dpw;
+        }
     }
     bool last;
     const u64 run = seg_sum_last(wc, y, last);
     if (last && run && y != 0x7fffffff) atomicAdd(&wcnt[y], run);
-    const u64 a = wave_sum(wc), b = wave_sum(ls);
+    const u64 a = wave_sum(lw), b = wave_sum(lb);
     if (glt_lane() == 0) { red[0][threadIdx.x / GLT_WAVE] = a; red[1][threadIdx.x / GLT_WAVE] = b; }
     __syncthreads();
     if (threadIdx.x == 0) {
         u64 ta = 0, tb = 0;
         for (int q = 0; q < 256 / GLT_WAVE; q++) { ta += red[0][q]; tb += red[1][q]; }
-        if (ta) atomicAdd(&work[0], ta);
-        if (tb) atomicAdd(&work[1], tb);
+        u64* line = wspread + (blockIdx.x & (GSPREAD - 1)) * WSPREAD_WORDS;
+        if (ta) atomicAdd(&line[2], ta);
+        if (tb) atomicAdd(&line[3], tb);
     }
 }
 
-__global__ __launch_bounds__(256) void k_wappend(const u64* __restrict__ wcnt, int n, int wave_max,
-                                                 int* __restrict__ wlist, int* __restrict__ counts) {
+// Bucket the wedge pass by wedges per vertex; totals go to work[0] (wave and mid classes,
+// one wavefront per vertex) and work[1] (workgroup class).
+__global__ __launch_bounds__(256) void k_wappend(const u64* __restrict__ wcnt, int n, int wave_max, int mid_max,
+                                                 int* __restrict__ wlist, int* __restrict__ counts,
+                                                 u64* __restrict__ wspread) {
+    __shared__ u64 red[2][256 / GLT_WAVE];
     const int y = blockIdx.x * blockDim.x + threadIdx.x;
     const u64 wc = (y < n) ? wcnt[y] : 0;
-    const int q = (wc == 0) ? -1 : (wc <= (u64)wave_max ? WB_WAVE : WB_BLK);
-    for (int b = 0; b < WB_N; b++) wave_append(&counts[b], wlist + (int64_t)b * n, q == b, y);
+    const int q = (wc == 0) ? -1
+                            : (wc <= (u64)wave_max ? WB_WAVE : (wc <= (u64)mid_max ? WB_MID : WB_BLK));
+    block_append<WB_N>(counts, wlist, n, q, y);
+    const u64 a = wave_sum((q == WB_WAVE || q == WB_MID) ? wc : 0ull), bb = wave_sum(q == WB_BLK ? wc : 0ull);
+    if (glt_lane() == 0) { red[0][threadIdx.x / GLT_WAVE] = a; red[1][threadIdx.x / GLT_WAVE] = bb; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 ta = 0, tb = 0;
+        for (int k = 0; k < 256 / GLT_WAVE; k++) { ta += red[0][k]; tb += red[1][k]; }
+        u64* line = wspread + (blockIdx.x & (GSPREAD - 1)) * WSPREAD_WORDS;
+        if (ta) atomicAdd(&line[0], ta);
+        if (tb) atomicAdd(&line[1], tb);
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -323,7 +563,7 @@ __global__ __launch_bounds__(256) void k_wappend(const u64* __restrict__ wcnt, i
 // ---------------------------------------------------------------------------------------
 int glt_prep_validate(const Dev& d, const void* rp, int rp64, const int* col, hipStream_t st) {
     // err[0] error bits (kept from the union build in batched mode), err[1] max degree
-    if (d.ngraphs <= 0) (void)hipMemsetAsync(d.err, 0, 4 * sizeof(int), st);
+    if (d.ngraphs <= 0) (void)hipMemsetAsync(d.err, 0, ERR_WORDS * sizeof(int), st);
     if (d.n <= 0) return 0;
     const int64_t S = d.S;
     launch_fill<u32>(d.rowx, S + 1, 0u, st);
@@ -348,33 +588,55 @@ int glt_prep_validate(const Dev& d, const void* rp, int rp64, const int* col, hi
 
 static inline int bitlen(u64 x) { int b = 0; while (x) { b++; x >>= 1; } return b; }
 
-int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipStream_t st, int* host_counts) {
-    (void)rp;
-    (void)rp64;
+int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipStream_t st, const int* vinfo) {
+    static_assert(RS_N <= TB_N, "row-sort lists live in the triangle-pass list area");
     const int n = d.n;
     const int64_t S = d.S;
-    int maxdeg = host_counts[0];
+    const int maxdeg = vinfo[0];
+    const int* rows = vinfo + 1;   // rows per sort class
     (void)hipMemsetAsync(d.counts, 0, sizeof(int) * (TB_N + WB_N + TB_N), st);
-    (void)hipMemsetAsync(d.work, 0, sizeof(u64) * 2, st);
+    launch_fill<u64>(d.work, NWORK, 0ull, st);
+    launch_fill<u64>(d.wspread, (int64_t)GSPREAD * WSPREAD_WORDS, 0ull, st);
     if (n == 0) return 0;
-    // P1: stable sort of vertices by degree (ties keep id order)
-    hipLaunchKernelGGL(k_iota_keys, dim3(nblk(n, 256)), dim3(256), 0, st, d.deg, n, d.key0, d.val0);
-    int cur = launch_radix_sort(d.key0, d.val0, d.key1, d.val1, n, bitlen((u64)maxdeg), d.rs_counts, d.rs_tmp, st);
+    // P1: stable sort of vertices by degree (ties keep id order); rows listed by sort class
+    const int degbits = bitlen((u64)maxdeg);
+    const int keybits = degbits + (d.ngraphs > 0 ? bitlen((u64)(d.ngraphs - 1)) : 0);
+    hipLaunchKernelGGL(k_iota_keys, dim3(nblk(n, 256)), dim3(256), 0, st, d.deg, d.ngraphs > 0 ? d.gid : nullptr,
+                       degbits, n, d.key0, d.val0);
+    const int cur = launch_radix_sort(d.key0, d.val0, d.key1, d.val1, n, keybits, d.rs_counts, d.rs_tmp, st);
+    int* rlist = d.tlist;
+    int* rcnt = d.err + 2 + RS_N;
     hipLaunchKernelGGL(k_apply_order, dim3(nblk(n, 256)), dim3(256), 0, st, cur ? d.val1 : d.val0, d.deg, n,
-                       d.order, d.rank, d.ndeg, d.gid, d.ngid);
+                       d.order, d.rank, d.ndeg, d.gid, d.ngid, rlist, rcnt);
     // relabelled CSR offsets
     launch_excl_scan<int, int>(d.ndeg, d.nrp, n, d.itmp, d.nrp + n, st);
-    // P2: sort every entry by (relabelled src, relabelled dst)
-    const int B = bitlen((u64)(n > 1 ? n - 1 : 1));
+    // P2: entries placed in their relabelled rows, then every row sorted by neighbour rank
+    u32* key = (u32*)d.key0;
+    u32* val = d.val0;
     if (S > 0) {
-        hipLaunchKernelGGL(k_emit, dim3(nblk(S, 256)), dim3(256), 0, st, d.rowx, col, S, d.rank, B, d.key0, d.val0,
-                           d.upx);
+        if (rp64)
+            hipLaunchKernelGGL(k_place<int64_t>, dim3(nblk(S, 256)), dim3(256), 0, st, (const int64_t*)rp, d.rowx, col,
+                               S, d.rank, d.nrp, key, val, d.nsrow, d.upx);
+        else
+            hipLaunchKernelGGL(k_place<int32_t>, dim3(nblk(S, 256)), dim3(256), 0, st, (const int32_t*)rp, d.rowx, col,
+                               S, d.rank, d.nrp, key, val, d.nsrow, d.upx);
         launch_excl_scan<u32, u32>(d.upx, d.upx, S, d.rs_tmp, (u32*)nullptr, st);
-        cur = launch_radix_sort(d.key0, d.val0, d.key1, d.val1, S, 2 * B, d.rs_counts, d.rs_tmp, st);
-        u64* ks = cur ? d.key1 : d.key0;
-        hipLaunchKernelGGL(k_unpack_cols, dim3(nblk(S, 256)), dim3(256), 0, st, ks, S, B, d.ncol, d.nsrow, d.err);
+        if (rows[RS_TINY] > 0)
+            hipLaunchKernelGGL(k_sort_tiny, dim3(nblk(rows[RS_TINY], 256)), dim3(256), 0, st,
+                               rlist + (int64_t)RS_TINY * n, rows[RS_TINY], d.nrp, key, val);
+        if (rows[RS_WAVE] > 0)
+            hipLaunchKernelGGL(k_sort_wave, dim3(nblk(rows[RS_WAVE], 256 / GLT_WAVE)), dim3(256), 0, st,
+                               rlist + (int64_t)RS_WAVE * n, rows[RS_WAVE], d.nrp, key, val);
+        if (rows[RS_BLK] > 0)
+            hipLaunchKernelGGL(k_sort_blk, dim3(rows[RS_BLK]), dim3(256), 0, st, rlist + (int64_t)RS_BLK * n,
+                               rows[RS_BLK], d.nrp, key, val);
+        if (rows[RS_BIG] > 0)
+            hipLaunchKernelGGL(k_sort_big, dim3(rows[RS_BIG]), dim3(256), 0, st, rlist + (int64_t)RS_BIG * n,
+                               rows[RS_BIG], d.nrp, key, val, (u32*)d.key1, d.val1,
+                               bitlen((u64)(n > 1 ? n - 1 : 1)));
+        hipLaunchKernelGGL(k_unpack_cols, dim3(nblk(S, 256)), dim3(256), 0, st, key, S, d.nsrow, d.nrp, d.ncol, d.err);
     }
-    const u32* oslot = cur ? d.val1 : d.val0;
+    const u32* oslot = val;
     // P3: orientation
     int* dplus = d.itmp + scan_tmp_elems(S + n + 1);  // past the scan scratch
     hipLaunchKernelGGL(k_dlo, dim3(nblk(n, 256)), dim3(256), 0, st, d.nrp, d.ncol, n, d.dlo, dplus);
@@ -384,12 +646,13 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
                            d.order, oslot, d.upx, S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.err);
     // work lists
     hipLaunchKernelGGL(k_tbuckets, dim3(nblk(n, 256)), dim3(256), 0, st, d.optr, n, d.tlist, d.counts,
-                       d.counts + TB_N + WB_N);
+                       d.counts + TB_N + WB_N, d.toff);
+    launch_excl_scan<u64, u64>(d.toff, d.toff, n, d.tmp64, d.toff + n, st);
     launch_fill<u64>(d.wcnt, n, 0ull, st);
     if (S > 0)
         hipLaunchKernelGGL(k_wcount, dim3(nblk(S, 256)), dim3(256), 0, st, d.ncol, d.nsrow, d.optr, d.s2k, S, d.wcnt,
-                           d.work);
-    hipLaunchKernelGGL(k_wappend, dim3(nblk(n, 256)), dim3(256), 0, st, d.wcnt, n, d.wedge_wave_max, d.wlist,
-                       d.counts + TB_N);
+                           d.wspread);
+    hipLaunchKernelGGL(k_wappend, dim3(nblk(n, 256)), dim3(256), 0, st, d.wcnt, n, d.wedge_wave_max, d.wedge_mid_max, d.wlist,
+                       d.counts + TB_N, d.wspread);
     return 0;
 }

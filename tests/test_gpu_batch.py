@@ -97,3 +97,36 @@ def test_batch_invalid_graph_rejected(ctx):
     assert ei.value.status == -1
     # the handle still works
     assert ctx.count_batch(gg.pack_batch([good]))[0][0] == 6
+
+
+def test_schedule_api_and_autotuner():
+    """The schedule setters reject out-of-range fields; the autotuner returns a schedule from
+    its grid, installs it, and the counts under it equal the oracle's."""
+    import paper_1608_05138_amd as glt
+    c = glt.Context(0)
+    try:
+        base = c.schedule()
+        assert base["tri_records"] in (0, 1) and base["wedge_range_limit"] >= 1
+        for bad in ({"wedge_wave_max": 100000}, {"wedge_dense": -1}, {"wedge_range_limit": 0},
+                    {"tri_records": 2}):
+            with pytest.raises(glt.GltError):
+                c.set_schedule(**bad)
+            assert c.schedule() == base
+        c.set_schedule(wedge_mid_max=0, wedge_dense=7, tri_records=0)
+        specs = gg.batch_spec(24, base=gg.BASE_SEED + 77)
+        graphs = [gg.batch_graph((m_, min(n, 1200), min(m, 9000), s)) for (m_, n, m, s) in specs]
+        packed = _to_device(gg.pack_batch(graphs))
+        expect = [oracle.count(n, rp, col)["X"] for n, (rp, col) in graphs]
+        say("schedule-fixed")
+        assert ctx_counts(c, packed) == expect
+        say("autotune")
+        best, ms = c.autotune_batch(packed)
+        assert ms > 0 and best["wedge_wave_max"] in (128, 256) and best["wedge_mid_max"] in (1024, 2048, 4096)
+        assert c.schedule() == best
+        assert ctx_counts(c, packed) == expect
+    finally:
+        c.close()
+
+
+def ctx_counts(c, packed):
+    return c.count_batch(packed)

@@ -164,24 +164,67 @@ def test_complete_bipartite(ctx):
     np.testing.assert_array_equal(pe, want)
 
 
-@pytest.mark.parametrize("dense", ["0", "7"])
-def test_forced_workgroup_path_and_range_splitting(monkeypatch, dense):
-    """Wedge pass with every vertex on the workgroup path, a tiny distinct-top limit (hash
-    ranges split many times) and no or a tiny dense window of top counters; results must
-    not change."""
+SPLIT_CASES = {
+    # name: (wave-class max, mid-class max, dense window)
+    "wg-nodense": ("0", "0", "0"),
+    "wg-dense7": ("0", "0", "7"),
+    "mid-nodense": ("0", "1000000000", "0"),
+    "mid-dense7": ("0", "1000000000", "7"),
+    "wave+wg": ("256", "256", "5"),
+}
+
+
+@pytest.mark.parametrize("case", list(SPLIT_CASES))
+def test_forced_classes_and_range_splitting(monkeypatch, case):
+    """Wedge pass with every bottom vertex forced into one size class (workgroup, mid
+    wavefront, or wave + workgroup), a tiny distinct-top limit (hash ranges split many
+    times) and no or a tiny dense window of top counters; results must not change."""
     import paper_1608_05138_amd as glt
-    monkeypatch.setenv("GLT_WEDGE_WAVE_MAX", "0")
+    wave_max, mid_max, dense = SPLIT_CASES[case]
+    monkeypatch.setenv("GLT_WEDGE_WAVE_MAX", wave_max)
+    monkeypatch.setenv("GLT_WEDGE_MID_MAX", mid_max)
     monkeypatch.setenv("GLT_WEDGE_RANGE_LIMIT", "3")
     monkeypatch.setenv("GLT_WEDGE_DENSE", dense)
     c = glt.Context(0)
     try:
         for n, m, seed in ((3000, 30000, 31), (800, 24000, 32)):
             rp, col = gg.chung_lu(n, m, 2.1, float(n - 1), seed)
-            check_vs_oracle(c, f"forced-split-{n}-{m}-dense{dense}", n, rp, col)
+            check_vs_oracle(c, f"forced-{case}-{n}-{m}", n, rp, col)
         N, (rp, col) = gg.complete_bipartite(40, 47)
-        check_vs_oracle(c, f"forced-split-K40,47-dense{dense}", N, rp, col)
+        check_vs_oracle(c, f"forced-{case}-K40,47", N, rp, col)
     finally:
         c.close()
+
+
+def test_triangle_records_on_and_off(monkeypatch, ctx):
+    """The triangle and gather passes walk stored triangle records when the record buffer
+    fits, and re-scan the out-lists when records are switched off; both must agree with each
+    other and with the oracle on the wave, LDS-bitmap and global-bitmap paths."""
+    import paper_1608_05138_amd as glt
+    monkeypatch.setenv("GLT_TRI_RECORD_BYTES", "0")
+    off = glt.Context(0)
+    try:
+        rng = np.random.default_rng(5)
+        n = 2300
+        lo, hi = gg.er_pairs(n, 6000, rng)
+        iu = np.triu_indices(700, 1)   # out-degrees up to 699: global-bitmap rows
+        a = np.concatenate([lo, iu[0]]); b = np.concatenate([hi, iu[1]])
+        key = np.unique(np.minimum(a, b) * n + np.maximum(a, b))
+        perm = rng.permutation(n)
+        cases = [("clique700-noise", n, gg.csr_from_pairs(n, perm[key // n], perm[key % n]))]
+        cases.append(("chung-lu-4000", 4000, gg.chung_lu(4000, 60000, 2.1, 3999.0, 77)))
+        for name, nn, (rp, col) in cases:
+            say(f"records {name}")
+            X1, pe1 = gpu(ctx, nn, rp, col)
+            X0, pe0 = gpu(off, nn, rp, col)
+            assert X0 == X1, name
+            np.testing.assert_array_equal(pe0, pe1)
+            assert X1 == oracle.count(nn, rp, col)["X"], name
+            G1, _ = gpu(ctx, nn, rp, col, per_edge=False)
+            G0, _ = gpu(off, nn, rp, col, per_edge=False)
+            assert G0 == G1 == X1, name
+    finally:
+        off.close()
 
 
 def test_modes_and_layouts_agree(ctx):
@@ -224,6 +267,54 @@ def test_invalid_inputs_rejected(ctx):
     n, (rp, col) = gg.cycle(7)
     X, _ = gpu(ctx, n, rp, col, per_edge=False)
     assert X[0] == 7
+
+
+def _row_class_graph(seed):
+    """Rows of every length class of the per-row sort (a 5000-leaf star, a 1000-leaf star,
+    vertices of degree ~40 and ~10) over sparse noise, ids and row order shuffled."""
+    rng = np.random.default_rng(seed)
+    n = 7000
+    lo, hi = gg.er_pairs(n, 9000, rng)
+    a = [lo, np.zeros(5000, np.int64), np.full(1000, 5001, np.int64)]
+    b = [hi, np.arange(1, 5001), np.arange(5002, 6002)]
+    for v in range(6100, 6140):
+        a.append(np.full(40, v, np.int64)); b.append(rng.choice(6000, 40, replace=False) + 1)
+    a = np.concatenate(a); b = np.concatenate(b)
+    keep = a != b
+    a, b = a[keep], b[keep]
+    key = np.unique(np.minimum(a, b) * n + np.maximum(a, b))
+    perm = rng.permutation(n)
+    rp, col = gg.csr_from_pairs(n, perm[key // n], perm[key % n])
+    return n, rp, gg.shuffle_rows(rp, col, seed + 1)
+
+
+def test_row_sort_classes(ctx):
+    n, rp, col = _row_class_graph(41)
+    d = np.diff(rp)
+    assert d.max() > 2048 and ((d > 64) & (d <= 2048)).any() and ((d > 16) & (d <= 64)).any()
+    check_vs_oracle(ctx, "row-sort-classes", n, rp, col)
+
+
+@pytest.mark.parametrize("length_class", ["tiny", "wave", "wg", "big"])
+def test_duplicate_in_each_row_class(ctx, length_class):
+    """A duplicated neighbour is found whichever per-row sort handled the row."""
+    import paper_1608_05138_amd as glt
+    n, rp, col = _row_class_graph(43)
+    d = np.diff(rp)
+    lo, hi = {"tiny": (2, 16), "wave": (17, 64), "wg": (65, 2048), "big": (2049, 1 << 30)}[length_class]
+    r = int(np.flatnonzero((d >= lo) & (d <= hi - 2))[0])
+    c = int(col[rp[r]])
+    rows = [list(col[rp[i]:rp[i + 1]]) for i in range(n)]
+    # c three times in row r only (the entry count stays even; the row stays in its class)
+    rows[r].insert(len(rows[r]) // 2, c)
+    rows[r].append(c)
+    rp2 = np.zeros(n + 1, np.int64)
+    rp2[1:] = np.cumsum([len(x) for x in rows])
+    col2 = np.concatenate([np.asarray(x, np.int32) for x in rows])
+    say(f"duplicate-{length_class}")
+    with pytest.raises(glt.GltError) as ei:
+        ctx.count(rp2.astype(np.int32), col2, n=n)
+    assert ei.value.status == -2, str(ei.value)
 
 
 def test_budget_is_enforced():
@@ -299,8 +390,11 @@ def test_config_chung_lu_1m(ctx):
     path = os.path.join(os.path.dirname(__file__), "golden", "chung_lu_1m_global.json")
     golden = None
     if os.path.exists(path):
+        import hashlib
         with open(path) as f:
-            golden = [int(x) for x in json.load(f)["X"]]
+            g = json.load(f)
+        assert hashlib.sha256(np.ascontiguousarray(col).tobytes()).hexdigest()[:16] == g["col_sha256_prefix"]
+        golden = [int(x) for x in g["X"]]
     _full_size(ctx, "chung-lu-1m-10m", n, rp, col, golden)
 
 
