@@ -65,12 +65,12 @@ def _gen_batch_graph(spec):
     return gg.batch_graph(spec)
 
 
-def gen_batch(num_graphs):
+def gen_batch(num_graphs, base=None):
     """The mixed batch, generated in parallel host processes (not timed)."""
     import multiprocessing as mp
 
     import graphgen as gg
-    specs = gg.batch_spec(num_graphs)
+    specs = gg.batch_spec(num_graphs) if base is None else gg.batch_spec(num_graphs, base=base)
     procs = max(1, min(16, len(os.sched_getaffinity(0))))
     with mp.get_context("fork").Pool(procs) as pool:
         graphs = pool.map(_gen_batch_graph, specs, chunksize=16)
@@ -206,6 +206,19 @@ def bench_batch(args):
     dpk["col"] = torch.from_numpy(packed["col"]).to(dev)
     ctx = glt.Context(0)
     stream = torch.cuda.current_stream(dev).cuda_stream
+    tuned = None
+    if not args.no_autotune:
+        # the schedule is picked on a separate draw of the same mix (other seeds), not on the
+        # timed graphs
+        _, tgraphs = gen_batch(args.tune_graphs, base=gg.BASE_SEED + 1003)
+        tpk = gg.pack_batch(tgraphs)
+        tpk["row_ptr"] = torch.from_numpy(tpk["row_ptr"]).to(dev)
+        tpk["col"] = torch.from_numpy(tpk["col"]).to(dev)
+        best, best_ms = ctx.autotune_batch(tpk, stream=stream)
+        tuned = {"schedule": best, "tuned_on": f"{len(tgraphs)} graphs of the same mix drawn with other seeds",
+                 "tuned_device_ms": round(best_ms, 3)}
+        print(f"[bench] autotuned schedule {best} ({best_ms:.2f} ms on the tuning batch)", file=sys.stderr, flush=True)
+        del tpk
     print(f"[bench] batch: {len(graphs)} graphs, {m_total} edges; warmup {args.warmup}", file=sys.stderr,
           flush=True)
     for _ in range(args.warmup):
@@ -252,6 +265,8 @@ def bench_batch(args):
             "ms": round(per_graph_ms, 1), "graphs_per_s": len(graphs) / (per_graph_ms * 1e-3)},
         "kernel_groups_ms": {k: round(float(v), 4) for k, v in timing.items()},
         "work": work,
+        "autotune": tuned,
+        "schedule": ctx.schedule(),
         "roofline": roofline(timing, work, False, acc_width(maxdeg)),
     }
     ctx.close()
@@ -330,10 +345,12 @@ def main():
     ap.add_argument("--workload", default="chung_lu_1m", choices=sorted(WORKLOADS) + ["batch_10k", "served"])
     ap.add_argument("--batch-graphs", type=int, default=10_000)
     ap.add_argument("--no-per-graph", action="store_true", help="batch/served: skip the per-graph comparison")
+    ap.add_argument("--no-autotune", action="store_true", help="batch: keep the default schedule")
+    ap.add_argument("--tune-graphs", type=int, default=1000, help="batch: graphs in the autotuning draw")
     ap.add_argument("--rate", type=float, default=2000.0, help="served: arrivals per second")
-    ap.add_argument("--serve-seconds", type=float, default=20.0, help="served: length of the arrival stream")
-    ap.add_argument("--pool-small", type=int, default=2000, help="served: pool of small request graphs")
-    ap.add_argument("--pool-large", type=int, default=16, help="served: pool of large request graphs")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="served: length of the arrival stream")
+    ap.add_argument("--pool-small", type=int, default=10000, help="served: pool of small request graphs")
+    ap.add_argument("--pool-large", type=int, default=64, help="served: pool of large request graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--global-only", action="store_true", help="skip per-edge output")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",

@@ -157,18 +157,22 @@ int glt_last_work(const glt_ctx* ctx, uint64_t* out, int cap);
  * Work schedule of a handle: how the counting passes split their work among size classes
  * (Section 4.3 splits edges by cost between workers; here vertices are split by their work
  * between wavefront and workgroup kernels).  Every schedule yields the same counts; only
- * the speed differs.  Defaults: 256, 2048, 4096, 1024, 1.
+ * the speed differs.  Defaults: 256, 2048, 16384, 4096, 1, 65536.
  */
 typedef struct {
     int32_t wedge_wave_max;    /* 4-cycle pass: bottom vertices with at most this many wedges
                                   run one per wavefront with an LDS hash only (0..256)        */
     int32_t wedge_mid_max;     /* up to this many: one per wavefront with a dense window of
-                                  top counters and a hash; more: one per workgroup (>= 0)     */
-    int32_t wedge_dense;       /* width of the dense window of highest-ranked tops (0..4096)  */
-    int32_t wedge_range_limit; /* distinct hashed tops per range before it is halved (1..1024) */
+                                  top counters and a hash (>= 0)                               */
+    int32_t wedge_dense;       /* width of the dense window of highest-ranked tops (0..16384;
+                                  each class caps it at its own table: 1024, 4096, 16384)     */
+    int32_t wedge_range_limit; /* distinct hashed tops per range before it is halved (1..4096;
+                                  each class caps it at half its hash: 256, 512, 1024, 4096)  */
     int32_t tri_records;       /* 1: store each triangle once for the 4-clique sweep and the
                                   gather pass when the record buffer fits; 0: re-scan lists  */
-    int32_t reserved[3];       /* must be 0                                                  */
+    int32_t wedge_wg_max;      /* up to this many: one per 256-thread workgroup; more: one per
+                                  1024-thread workgroup with the largest tables (>= 0)        */
+    int32_t reserved[2];       /* must be 0                                                  */
 } glt_schedule;
 
 /* The handle's current schedule. */
@@ -207,7 +211,9 @@ typedef struct {
     size_t resident_bytes;     /* device pool for admitted graphs (the admission budget); 0 = 4 GiB */
     size_t workspace_bytes;    /* cap of the counting workspace (0 = none)                      */
     int32_t max_pending;       /* queued, not yet admitted requests before GLT_E_BUSY; 0 = 2^20 */
-    int32_t reserved;
+    int32_t large_edges;       /* requests with more edges run on a second compute lane (its own
+                                  stream and workspace), overlapping the small-request batches
+                                  instead of holding them up; 0 = 262,144, -1 = one lane       */
 } glt_server_opts;
 
 typedef struct {

@@ -67,17 +67,19 @@ class glt_batch(ctypes.Structure):
 class glt_schedule(ctypes.Structure):
     _fields_ = [("wedge_wave_max", ctypes.c_int32), ("wedge_mid_max", ctypes.c_int32),
                 ("wedge_dense", ctypes.c_int32), ("wedge_range_limit", ctypes.c_int32),
-                ("tri_records", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("tri_records", ctypes.c_int32), ("wedge_wg_max", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
-SCHEDULE_KEYS = ["wedge_wave_max", "wedge_mid_max", "wedge_dense", "wedge_range_limit", "tri_records"]
+SCHEDULE_KEYS = ["wedge_wave_max", "wedge_mid_max", "wedge_dense", "wedge_range_limit", "tri_records",
+                 "wedge_wg_max"]
 
 
 class glt_server_opts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_batch_graphs", ctypes.c_int32),
                 ("max_batch_edges", ctypes.c_int64), ("resident_bytes", ctypes.c_size_t),
                 ("workspace_bytes", ctypes.c_size_t), ("max_pending", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("large_edges", ctypes.c_int32)]
 
 
 class glt_result(ctypes.Structure):
@@ -319,10 +321,10 @@ class Server:
     """Continuous-batching request server (glt_server_*)."""
 
     def __init__(self, device=0, max_batch_graphs=0, max_batch_edges=0, resident_bytes=0,
-                 workspace_bytes=0, max_pending=0):
+                 workspace_bytes=0, max_pending=0, large_edges=0):
         self._lib = load_library()
         o = glt_server_opts(device, max_batch_graphs, max_batch_edges, resident_bytes,
-                            workspace_bytes, max_pending, 0)
+                            workspace_bytes, max_pending, large_edges)
         h = ctypes.c_void_p()
         rc = self._lib.glt_server_create(ctypes.byref(o), ctypes.byref(h))
         if rc != 0:

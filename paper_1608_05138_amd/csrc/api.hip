@@ -34,6 +34,7 @@ struct glt_ctx {
     u64* hbuf = nullptr;   // pinned host buffer for small read-backs (4 KiB)
     int wedge_wave_max = 0;
     int wedge_mid_max = 0;
+    int wedge_wg_max = 0;
     int wedge_limit = 0;
     int wedge_dense = 0;
     uint64_t work[2 + NWORK] = {};     // n, m, then the device work counters
@@ -274,6 +275,7 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
     const int n = d.n, m = d.m;
     d.wedge_wave_max = ctx->wedge_wave_max;
     d.wedge_mid_max = ctx->wedge_mid_max;
+    d.wedge_wg_max = ctx->wedge_wg_max;
     d.wedge_limit = ctx->wedge_limit;
     d.wedge_dense = ctx->wedge_dense;
     HIPCHK(hipEventRecord(ctx->ev[0], st));
@@ -405,6 +407,11 @@ glt_status glt_create(int device, size_t hbm_budget_bytes, glt_ctx** out) {
     if (const char* e = getenv("GLT_WEDGE_MID_MAX")) {
         int v = atoi(e);
         if (v >= 0) ctx->wedge_mid_max = v;
+    }
+    ctx->wedge_wg_max = 65536;
+    if (const char* e = getenv("GLT_WEDGE_WG_MAX")) {
+        int v = atoi(e);
+        if (v >= 0) ctx->wedge_wg_max = v;
     }
     if (const char* e = getenv("GLT_WEDGE_RANGE_LIMIT")) {
         int v = atoi(e);
@@ -601,6 +608,7 @@ glt_status glt_get_schedule(const glt_ctx* ctx, glt_schedule* out) {
     memset(out, 0, sizeof(*out));
     out->wedge_wave_max = ctx->wedge_wave_max;
     out->wedge_mid_max = ctx->wedge_mid_max;
+    out->wedge_wg_max = ctx->wedge_wg_max;
     out->wedge_dense = ctx->wedge_dense;
     out->wedge_range_limit = ctx->wedge_limit;
     out->tri_records = ctx->tri_records;
@@ -614,15 +622,17 @@ glt_status glt_set_schedule(glt_ctx* ctx, const glt_schedule* s) {
     if (s->wedge_wave_max < 0 || s->wedge_wave_max > glt_wave_table() / 2)
         return fail(ctx, GLT_E_INVALID_ARG, "wedge_wave_max must be in [0, %d]", glt_wave_table() / 2);
     if (s->wedge_mid_max < 0) return fail(ctx, GLT_E_INVALID_ARG, "wedge_mid_max must be >= 0");
+    if (s->wedge_wg_max < 0) return fail(ctx, GLT_E_INVALID_ARG, "wedge_wg_max must be >= 0");
     if (s->wedge_dense < 0 || s->wedge_dense > glt_wedge_dense())
         return fail(ctx, GLT_E_INVALID_ARG, "wedge_dense must be in [0, %d]", glt_wedge_dense());
     if (s->wedge_range_limit < 1 || s->wedge_range_limit > glt_wedge_table() / 2)
         return fail(ctx, GLT_E_INVALID_ARG, "wedge_range_limit must be in [1, %d]", glt_wedge_table() / 2);
     if (s->tri_records != 0 && s->tri_records != 1) return fail(ctx, GLT_E_INVALID_ARG, "tri_records must be 0 or 1");
-    for (int i = 0; i < 3; i++)
+    for (int i = 0; i < 2; i++)
         if (s->reserved[i]) return fail(ctx, GLT_E_INVALID_ARG, "reserved fields must be 0");
     ctx->wedge_wave_max = s->wedge_wave_max;
     ctx->wedge_mid_max = s->wedge_mid_max;
+    ctx->wedge_wg_max = s->wedge_wg_max;
     ctx->wedge_dense = s->wedge_dense;
     ctx->wedge_limit = s->wedge_range_limit;
     ctx->tri_records = s->tri_records;
@@ -643,7 +653,7 @@ glt_status glt_autotune_batch(glt_ctx* ctx, const glt_batch* b, glt_schedule* be
     // candidate grid: wedge class bounds x dense window
     static const int wave_c[2] = {128, 256};
     static const int mid_c[3] = {1024, 2048, 4096};
-    static const int dense_c[2] = {1024, 4096};
+    static const int dense_c[2] = {4096, 16384};
     glt_schedule win = base;
     float win_ms = -1.f;
     for (int a = 0; a < 2; a++)

@@ -66,6 +66,26 @@ __device__ __forceinline__ int sh_find(const int* hk, const unsigned char* hv, i
     }
 }
 
+// Entries of the LDS hash over S = N+(a) in the workgroup triangle pass: a power of two
+// >= 2 |S| (load <= 1/2).
+__host__ __device__ inline int tri_blk_ht(int smax) {
+    int h = 64;
+    while (h < 2 * smax) h <<= 1;
+    return h;
+}
+
+// Membership of S = N+(a) for the workgroup triangle pass: LDS open addressing, id -> position.
+__device__ __forceinline__ u32 bhash(int x, u32 mask) { return ((u32)x * 2654435761u >> 7) & mask; }
+__device__ __forceinline__ int bh_find(const int* hk, const unsigned short* hp, u32 mask, int x) {
+    u32 h = bhash(x, mask);
+    while (true) {
+        const int k = hk[h];
+        if (k == x) return (int)hp[h];
+        if (k == -1) return -1;
+        h = (h + 1) & mask;
+    }
+}
+
 // Triangle records (REC): every triangle (a, b_i, b_j) found while the rows are built is
 // written as (k << 32 | j << 16 | i), k the oriented index of (b_i, b_j), into a's slots
 // [toff[a], toff[a] + C(|N+(a)|, 2)) (each pair i < j at most once), and tcnt[a] holds
@@ -222,12 +242,18 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
     int* sPre = sOb + smax;
     const int Wmax = (smax + 31) / 32;
     u32* M = GM ? gscratch + (int64_t)blockIdx.x * smax * Wmax : (u32*)(sPre + smax);
+    const int HT = tri_blk_ht(smax);
+    const u32 hmask = (u32)HT - 1;
+    int* hk = GM ? (sPre + smax) : (int*)(M + (int64_t)smax * Wmax);
+    unsigned short* hp = (unsigned short*)(hk + HT);
     const int tid = threadIdx.x;
     const int a = list[blockIdx.x];
     const int o0 = optr[a];
     const int s = optr[a + 1] - o0;
     const int W = (s + 31) / 32;
-    // S, its out-list offsets and the exclusive prefix of their lengths
+    for (int q = tid; q < HT; q += TB_THREADS) hk[q] = -1;
+    __syncthreads();
+    // S, its out-list offsets and the exclusive prefix of their lengths; S into the hash
     int carry = 0;
     for (int c0 = 0; c0 < s; c0 += TB_THREADS) {
         const int i = c0 + tid;
@@ -237,6 +263,9 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
             const int ob = optr[b];
             db = optr[b + 1] - ob;
             sS[i] = b; sOb[i] = ob; sK[i] = 0;
+            u32 h = bhash(b, hmask);
+            while (atomicCAS(&hk[h], -1, b) != -1) h = (h + 1) & hmask;
+            hp[h] = (unsigned short)i;
         }
         int tot;
         const int ex = block_excl_scan<int, TB_THREADS>(db, sScan, tot);
@@ -256,13 +285,11 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
         if (q < total) {
             i = ii = advance_idx(sPre, s, q, ii);
             k = sOb[i] + (q - sPre[i]);
-            const int x = ocol[k];
-            j = lower_bound_i32(sS, i + 1, s, x);
-            if (j < s && sS[j] == x) {
+            const int jj = bh_find(hk, hp, hmask, ocol[k]);   // x in S lies above b_i: jj > i
+            if (jj >= 0) {
+                j = jj;
                 atomicOr(&M[i * W + (j >> 5)], 1u << (j & 31));
                 atomicOr(&M[j * W + (i >> 5)], 1u << (i & 31));
-            } else {
-                j = s;
             }
         }
         if (REC) {   // one slot reservation per wavefront and round
@@ -303,9 +330,8 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
         if (q < total) {
             i = ii = advance_idx(sPre, s, q, ii);
             const int k = sOb[i] + (q - sPre[i]);
-            const int x = ocol[k];
-            const int j = lower_bound_i32(sS, i + 1, s, x);
-            if (j < s && sS[j] == x) {
+            const int j = bh_find(hk, hp, hmask, ocol[k]);
+            if (j >= 0) {
                 for (int wd = 0; wd < W; wd++) tk += (u64)__popc(M[i * W + wd] & M[j * W + wd]);
                 atomicAdd(&e.t[k], 1u);
                 if (PE && tk) {
@@ -349,6 +375,7 @@ static inline size_t tri_blk_lds(int smax, bool gm) {
     const int Wmax = (smax + 31) / 32;
     size_t b = (size_t)smax * (8 + 4 + 4 + 4);
     if (!gm) b += (size_t)smax * Wmax * 4;
+    b += (size_t)tri_blk_ht(smax) * (4 + 2);
     return b;
 }
 
@@ -584,6 +611,9 @@ __device__ __forceinline__ int grp_excl_scan(int v, int* lds, int& tot) {
 #define WB_T 256
 #define WB_HT 2048
 #define WB_DW 4096
+#define WH_T 1024        // huge class: a whole CU's LDS for bottom vertices with the most wedges
+#define WH_HT 8192
+#define WH_DW 16384
 
 // One group of T threads per bottom vertex y (G groups per block).  For every wedge
 // y - w - x with x above y the group counts c(y, x) = number of such w in LDS: tops x in
@@ -1138,7 +1168,7 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
     const int* cnt = hc;                  // TB_N counts, WB_N counts, TB_N maxima
     const EdgeArrays e = d.e;
     for (int bkt = TB_BLK1; bkt <= TB_GLOBAL; bkt++) sort_heaviest_first(d, d.tlist + (int64_t)bkt * n, cnt[bkt], 1, st);
-    for (int bkt = WB_MID; bkt <= WB_BLK; bkt++) sort_heaviest_first(d, d.wlist + (int64_t)bkt * n, hc[TB_N + bkt], 0, st);
+    for (int bkt = WB_MID; bkt <= WB_HUGE; bkt++) sort_heaviest_first(d, d.wlist + (int64_t)bkt * n, hc[TB_N + bkt], 0, st);
     if (ev) (void)hipEventRecord(ev[0], st);
     // triangle / 4-clique pass
     if (cnt[TB_WAVE] > 0) {
@@ -1214,10 +1244,13 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
         launch_wedge<false, AT, WM_T, WM_G, WM_HT, WM_DW>(d, WB_MID, wc[WB_MID], st);
     }
     if (ev) (void)hipEventRecord(ev[5], st);
-    if (per_edge)
+    if (per_edge) {
+        launch_wedge<true, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], st);
         launch_wedge<true, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], st);
-    else
+    } else {
+        launch_wedge<false, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], st);
         launch_wedge<false, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], st);
+    }
     if (ev) (void)hipEventRecord(ev[6], st);
     // vertex pass + combine
     if (per_edge && n > 0 && m > 0) {
@@ -1255,6 +1288,6 @@ void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hi
 int glt_combine_blocks(int m) { return combine_blocks(m); }
 // largest out-degree the block passes accept (LDS holds 5 ints per neighbour of a)
 int glt_max_out_degree() { return 3200; }
-int glt_wedge_table() { return WB_HT; }
-int glt_wedge_dense() { return WB_DW; }
+int glt_wedge_table() { return WH_HT; }
+int glt_wedge_dense() { return WH_DW; }
 int glt_wave_table() { return WW_HT; }

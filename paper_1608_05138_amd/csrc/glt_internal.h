@@ -61,7 +61,7 @@ __device__ __forceinline__ int64_t gslot(const int* ngid, int v) {
 
 // Bucket ids for the vertex work lists.
 enum { TB_WAVE = 0, TB_BLK1, TB_BLK2, TB_GLOBAL, TB_N };   // triangle / gather passes
-enum { WB_WAVE = 0, WB_MID, WB_BLK, WB_N };                 // wedge pass
+enum { WB_WAVE = 0, WB_MID, WB_BLK, WB_HUGE, WB_N };        // wedge pass
 
 // Device pointers of one graph's workspace.
 struct Dev {
@@ -119,6 +119,7 @@ struct Dev {
     // tuning (defaults; overridable per handle for testing)
     int wedge_wave_max;   // wedge-pass vertices with at most this many wedges: wave class (hash only)
     int wedge_mid_max;    // up to this many: mid class (one wavefront, dense window + hash)
+    int wedge_wg_max;     // up to this many: workgroup class; more: huge class (1024 threads, big tables)
     int wedge_limit;      // distinct hashed tops per range before the range is split
     int wedge_dense;      // width of the dense window of highest-ranked tops
     int acc32;            // per-edge accumulators fit 32 bits (maximum degree <= 46340)

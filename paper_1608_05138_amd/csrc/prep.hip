@@ -426,9 +426,10 @@ __global__ void k_dlo(const int* __restrict__ nrp, const int* __restrict__ ncol,
     dplus[x] = e - p;
 }
 
-// One thread per relabelled entry; upward entries (x -> y, y > x) copy themselves into the
-// oriented CSR at index k, map both their own entry and the matching downward entry of y
-// (binary search) to k, name the caller's edge id of k and clear the edge's accumulators.
+// One thread per relabelled entry.  Upward entries (x -> y, y > x) copy themselves into the
+// oriented CSR at index k and clear the edge's accumulators; downward entries find their
+// edge's k by binary search of x in N+(y), map themselves to k and name the caller's edge
+// id of k.
 __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ nrp, const int* __restrict__ ncol,
                                                     const int* __restrict__ nsrow, const int* __restrict__ dlo,
                                                     const int* __restrict__ optr, const int* __restrict__ order,
@@ -443,6 +444,7 @@ __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ nrp,
         const int ub = nrp[x] + dlo[x];
         const int y = ncol[s];
         if (s >= ub) {
+            // upward x -> y: its own oriented slot
             const int k = optr[x] + (s - ub);
             if (k >= m) {
                 bad = ERR_ASYM;   // more upward than downward entries
@@ -450,17 +452,21 @@ __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ nrp,
                 ocol[k] = y;
                 s2k[s] = k;
                 ea.t[k] = 0; ea.K[k] = 0; ea.P[k] = 0; ea.g[k] = 0; ea.sig[k] = 0; ea.u[k] = x;
-                const int yb = nrp[y], ye = yb + dlo[y];
-                const int sp = lower_bound_i32(ncol, yb, ye, x);
-                if (sp >= ye || ncol[sp] != x) {
-                    bad = ERR_ASYM;
-                } else {
-                    s2k[sp] = k;
-                    const u32 j = (order[x] < order[y]) ? oslot[s] : oslot[sp];
-                    const u32 eid = upx[j];
-                    if (eid >= (u32)m) bad = ERR_ASYM;
-                    else eid2k[eid] = k;
-                }
+            }
+        } else {
+            // downward x -> y (y ranked below x): the edge's slot is x's place in N+(y), a short
+            // list (out-degrees are bounded by sqrt(2m) in the degree order)
+            const int yb = nrp[y] + dlo[y], ye = nrp[y + 1];
+            const int sp = lower_bound_i32(ncol, yb, ye, x);
+            const int k = optr[y] + (sp - yb);
+            if (sp >= ye || ncol[sp] != x || k >= m) {
+                bad = ERR_ASYM;
+            } else {
+                s2k[s] = k;
+                const u32 j = (order[x] < order[y]) ? oslot[s] : oslot[sp];
+                const u32 eid = upx[j];
+                if (eid >= (u32)m) bad = ERR_ASYM;
+                else eid2k[eid] = k;
             }
         }
     }
@@ -536,17 +542,21 @@ __global__ __launch_bounds__(256) void k_wcount(const int* __restrict__ ncol, co
 }
 
 // Bucket the wedge pass by wedges per vertex; totals go to work[0] (wave and mid classes,
-// one wavefront per vertex) and work[1] (workgroup class).
+// one wavefront per vertex) and work[1] (workgroup and huge classes).
 __global__ __launch_bounds__(256) void k_wappend(const u64* __restrict__ wcnt, int n, int wave_max, int mid_max,
-                                                 int* __restrict__ wlist, int* __restrict__ counts,
+                                                 int wg_max, int* __restrict__ wlist, int* __restrict__ counts,
                                                  u64* __restrict__ wspread) {
     __shared__ u64 red[2][256 / GLT_WAVE];
     const int y = blockIdx.x * blockDim.x + threadIdx.x;
     const u64 wc = (y < n) ? wcnt[y] : 0;
-    const int q = (wc == 0) ? -1
-                            : (wc <= (u64)wave_max ? WB_WAVE : (wc <= (u64)mid_max ? WB_MID : WB_BLK));
+    const int q = (wc == 0)                 ? -1
+                  : (wc <= (u64)wave_max)   ? WB_WAVE
+                  : (wc <= (u64)mid_max)    ? WB_MID
+                  : (wc <= (u64)wg_max)     ? WB_BLK
+                                            : WB_HUGE;
     block_append<WB_N>(counts, wlist, n, q, y);
-    const u64 a = wave_sum((q == WB_WAVE || q == WB_MID) ? wc : 0ull), bb = wave_sum(q == WB_BLK ? wc : 0ull);
+    const u64 a = wave_sum((q == WB_WAVE || q == WB_MID) ? wc : 0ull);
+    const u64 bb = wave_sum((q == WB_BLK || q == WB_HUGE) ? wc : 0ull);
     if (glt_lane() == 0) { red[0][threadIdx.x / GLT_WAVE] = a; red[1][threadIdx.x / GLT_WAVE] = bb; }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -652,7 +662,7 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
     if (S > 0)
         hipLaunchKernelGGL(k_wcount, dim3(nblk(S, 256)), dim3(256), 0, st, d.ncol, d.nsrow, d.optr, d.s2k, S, d.wcnt,
                            d.wspread);
-    hipLaunchKernelGGL(k_wappend, dim3(nblk(n, 256)), dim3(256), 0, st, d.wcnt, n, d.wedge_wave_max, d.wedge_mid_max, d.wlist,
+    hipLaunchKernelGGL(k_wappend, dim3(nblk(n, 256)), dim3(256), 0, st, d.wcnt, n, d.wedge_wave_max, d.wedge_mid_max, d.wedge_wg_max, d.wlist,
                        d.counts + TB_N, d.wspread);
     return 0;
 }

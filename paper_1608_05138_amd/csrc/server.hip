@@ -2,12 +2,15 @@
 //
 // Requests (host CSR graphs) are queued on submit.  An admission thread moves them, in
 // arrival order, into a device-resident pool when the pool's budget has room, copying them
-// on a copy stream.  A compute thread repeatedly takes every admitted request whose copy has
-// finished (up to an edge budget per launch) and counts the whole group with one batched
-// call on its own stream; requests that arrive while a batch runs are admitted and copied
-// meanwhile and join the next batch.  Each request's result (17 global counts) is queued
-// with its timestamps for poll().  A request whose graph is invalid fails alone: when a
-// batch reports a validation error, its requests are re-run one by one.
+// on a copy stream.  Two compute lanes (each a thread with its own handle, workspace and
+// stream) repeatedly take every admitted request of their size class whose copy has
+// finished (up to an edge budget per launch) and count the group with one batched call;
+// requests that arrive while a batch runs are admitted and copied meanwhile and join the
+// next batch of their lane.  Large requests (more than large_edges edges) have a lane of
+// their own, so their launches overlap on the device with the small-request batches
+// instead of delaying them.  Each request's result (17 global counts) is queued with its
+// timestamps for poll().  A request whose graph is invalid fails alone: when a batch
+// reports a validation error, its requests are re-run one by one.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -80,20 +83,36 @@ constexpr size_t kSlotAlign = 256;
 
 }  // namespace
 
+struct glt_server;
+
+// One compute lane: a handle (workspace), a stream, a thread and its admitted queue.
+struct Lane {
+    glt_ctx* ctx = nullptr;
+    hipStream_t stream = nullptr;
+    std::deque<Request*> admitted;
+    std::condition_variable cv;
+    std::thread thr;
+};
+
 struct glt_server {
     glt_server_opts opts{};
-    glt_ctx* ctx = nullptr;
-    hipStream_t copy_stream = nullptr, compute_stream = nullptr;
+    int nlanes = 2;
+    Lane lanes[2];
+    hipStream_t copy_stream = nullptr;
     char* pool_base = nullptr;
     Pool pool;
     std::mutex mu;
-    std::condition_variable cv_admit, cv_compute, cv_done;
-    std::deque<Request*> pending, admitted;
+    std::condition_variable cv_admit, cv_done;
+    std::deque<Request*> pending;
     std::deque<glt_result> done;
     std::vector<hipEvent_t> spare_events;
     bool stop = false;
     int64_t inflight = 0;           // submitted and not yet completed
-    std::thread admit_thr, compute_thr;
+    std::thread admit_thr;
+
+    int lane_of(const Request* r) const {
+        return (nlanes > 1 && (int64_t)r->m > (int64_t)opts.large_edges) ? 1 : 0;
+    }
 
     hipEvent_t get_event() {
         if (!spare_events.empty()) {
@@ -158,14 +177,15 @@ struct glt_server {
                 cv_done.notify_all();
                 continue;
             }
-            admitted.push_back(r);
-            cv_compute.notify_one();
+            Lane& ln = lanes[lane_of(r)];
+            ln.admitted.push_back(r);
+            ln.cv.notify_one();
         }
     }
 
     // Runs one group; on a validation error, re-runs its requests one by one so that only
     // the invalid ones fail.
-    void run_group(std::vector<Request*>& grp, std::vector<int>& status, std::vector<glt_u128>& X) {
+    void run_group(Lane& ln, std::vector<Request*>& grp, std::vector<int>& status, std::vector<glt_u128>& X) {
         const int64_t B = (int64_t)grp.size();
         std::vector<int64_t> vb(B + 1), sb(B + 1);
         std::vector<const int*> rps(B), cols(B);
@@ -179,29 +199,30 @@ struct glt_server {
         }
         X.assign((size_t)B * 17, glt_u128{0, 0});
         status.assign(B, GLT_OK);
-        glt_status rc = glt_run_batch_ptrs(ctx, B, vb.data(), sb.data(), rps.data(), cols.data(), X.data(),
-                                           compute_stream);
+        glt_status rc = glt_run_batch_ptrs(ln.ctx, B, vb.data(), sb.data(), rps.data(), cols.data(), X.data(),
+                                           ln.stream);
         if (rc == GLT_OK) return;
         const bool input_error = rc == GLT_E_INVALID_ARG || rc == GLT_E_NOT_SIMPLE || rc == GLT_E_NOT_SYMMETRIC ||
                                  rc == GLT_E_UNSUPPORTED;
         if (!input_error || B == 1) {
-            for (auto& s : status) s = rc;
+            for (auto& st : status) st = rc;
             return;
         }
         for (int64_t g = 0; g < B; g++) {
             int64_t v1[2] = {0, grp[g]->n}, s1[2] = {0, 2 * (int64_t)grp[g]->m};
-            status[g] = glt_run_batch_ptrs(ctx, 1, v1, s1, &rps[g], &cols[g], &X[(size_t)g * 17], compute_stream);
+            status[g] = glt_run_batch_ptrs(ln.ctx, 1, v1, s1, &rps[g], &cols[g], &X[(size_t)g * 17], ln.stream);
         }
     }
 
-    void compute_loop() {
+    void compute_loop(int li) {
         (void)hipSetDevice(opts.device);
+        Lane& ln = lanes[li];
         std::unique_lock<std::mutex> lk(mu);
         while (true) {
-            cv_compute.wait(lk, [&] { return stop || !admitted.empty(); });
+            ln.cv.wait(lk, [&] { return stop || !ln.admitted.empty(); });
             if (stop) return;
-            // the oldest admitted request goes first; wait for its copy if needed
-            Request* head = admitted.front();
+            // the oldest admitted request of the lane goes first; wait for its copy if needed
+            Request* head = ln.admitted.front();
             if (hipEventQuery(head->ev) != hipSuccess) {
                 lk.unlock();
                 (void)hipEventSynchronize(head->ev);
@@ -210,11 +231,11 @@ struct glt_server {
             std::vector<Request*> grp;
             int64_t edges = 0;
             const int64_t maxg = opts.max_batch_graphs > 0 ? opts.max_batch_graphs : INT64_MAX;
-            while (!admitted.empty() && (int64_t)grp.size() < maxg) {
-                Request* r = admitted.front();
+            while (!ln.admitted.empty() && (int64_t)grp.size() < maxg) {
+                Request* r = ln.admitted.front();
                 if (!grp.empty() && edges + r->m > opts.max_batch_edges) break;
                 if (hipEventQuery(r->ev) != hipSuccess) break;
-                admitted.pop_front();
+                ln.admitted.pop_front();
                 grp.push_back(r);
                 edges += r->m;
             }
@@ -222,7 +243,7 @@ struct glt_server {
             const double t_start = now_s();
             std::vector<int> status;
             std::vector<glt_u128> X;
-            run_group(grp, status, X);
+            run_group(ln, grp, status, X);
             const double t_done = now_s();
             lk.lock();
             for (size_t g = 0; g < grp.size(); g++) {
@@ -251,14 +272,22 @@ glt_status glt_server_create(const glt_server_opts* opts, glt_server** out) {
     if (s->opts.max_batch_edges <= 0) s->opts.max_batch_edges = 8 << 20;
     if (s->opts.resident_bytes == 0) s->opts.resident_bytes = (size_t)4 << 30;
     if (s->opts.max_pending <= 0) s->opts.max_pending = 1 << 20;
-    glt_status rc = glt_create(s->opts.device, s->opts.workspace_bytes, &s->ctx);
-    if (rc != GLT_OK) { delete s; return rc; }
+    if (s->opts.large_edges == 0) s->opts.large_edges = 1 << 18;
+    s->nlanes = s->opts.large_edges < 0 ? 1 : 2;
+    for (int i = 0; i < s->nlanes; i++) {
+        glt_status rc = glt_create(s->opts.device, s->opts.workspace_bytes, &s->lanes[i].ctx);
+        if (rc != GLT_OK) { glt_server_destroy(s); return rc; }
+    }
     if (hipSetDevice(s->opts.device) != hipSuccess ||
-        hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&s->compute_stream, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) != hipSuccess) {
         glt_server_destroy(s);
         return GLT_E_DEVICE;
     }
+    for (int i = 0; i < s->nlanes; i++)
+        if (hipStreamCreateWithFlags(&s->lanes[i].stream, hipStreamNonBlocking) != hipSuccess) {
+            glt_server_destroy(s);
+            return GLT_E_DEVICE;
+        }
     if (hipMalloc((void**)&s->pool_base, s->opts.resident_bytes) != hipSuccess) {
         (void)hipGetLastError();
         s->pool_base = nullptr;
@@ -267,7 +296,7 @@ glt_status glt_server_create(const glt_server_opts* opts, glt_server** out) {
     }
     s->pool.init(s->opts.resident_bytes);
     s->admit_thr = std::thread([s] { s->admit_loop(); });
-    s->compute_thr = std::thread([s] { s->compute_loop(); });
+    for (int i = 0; i < s->nlanes; i++) s->lanes[i].thr = std::thread([s, i] { s->compute_loop(i); });
     *out = s;
     return GLT_OK;
 }
@@ -335,23 +364,28 @@ void glt_server_destroy(glt_server* s) {
         s->stop = true;
     }
     s->cv_admit.notify_all();
-    s->cv_compute.notify_all();
+    for (Lane& ln : s->lanes) ln.cv.notify_all();
     s->cv_done.notify_all();
     if (s->admit_thr.joinable()) s->admit_thr.join();
-    if (s->compute_thr.joinable()) s->compute_thr.join();
+    for (Lane& ln : s->lanes)
+        if (ln.thr.joinable()) ln.thr.join();
     (void)hipSetDevice(s->opts.device);
     if (s->copy_stream) (void)hipStreamSynchronize(s->copy_stream);
-    if (s->compute_stream) (void)hipStreamSynchronize(s->compute_stream);
+    for (Lane& ln : s->lanes)
+        if (ln.stream) (void)hipStreamSynchronize(ln.stream);
     for (Request* r : s->pending) delete r;
-    for (Request* r : s->admitted) {
-        if (r->ev) s->spare_events.push_back(r->ev);
-        delete r;
-    }
+    for (Lane& ln : s->lanes)
+        for (Request* r : ln.admitted) {
+            if (r->ev) s->spare_events.push_back(r->ev);
+            delete r;
+        }
     for (hipEvent_t e : s->spare_events) (void)hipEventDestroy(e);
     if (s->pool_base) (void)hipFree(s->pool_base);
     if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
-    if (s->compute_stream) (void)hipStreamDestroy(s->compute_stream);
-    glt_destroy(s->ctx);
+    for (Lane& ln : s->lanes) {
+        if (ln.stream) (void)hipStreamDestroy(ln.stream);
+        glt_destroy(ln.ctx);
+    }
     delete s;
 }
 

@@ -165,24 +165,28 @@ def test_complete_bipartite(ctx):
 
 
 SPLIT_CASES = {
-    # name: (wave-class max, mid-class max, dense window)
-    "wg-nodense": ("0", "0", "0"),
-    "wg-dense7": ("0", "0", "7"),
-    "mid-nodense": ("0", "1000000000", "0"),
-    "mid-dense7": ("0", "1000000000", "7"),
-    "wave+wg": ("256", "256", "5"),
+    # name: (wave-class max, mid-class max, dense window, workgroup-class max)
+    "wg-nodense": ("0", "0", "0", "1000000000"),
+    "wg-dense7": ("0", "0", "7", "1000000000"),
+    "mid-nodense": ("0", "1000000000", "0", "1000000000"),
+    "mid-dense7": ("0", "1000000000", "7", "1000000000"),
+    "wave+wg": ("256", "256", "5", "1000000000"),
+    "huge-nodense": ("0", "0", "0", "0"),
+    "huge-dense9": ("0", "0", "9", "0"),
 }
 
 
 @pytest.mark.parametrize("case", list(SPLIT_CASES))
 def test_forced_classes_and_range_splitting(monkeypatch, case):
     """Wedge pass with every bottom vertex forced into one size class (workgroup, mid
-    wavefront, or wave + workgroup), a tiny distinct-top limit (hash ranges split many
-    times) and no or a tiny dense window of top counters; results must not change."""
+    wavefront, huge workgroup, or wave + workgroup), a tiny distinct-top limit (hash ranges
+    split many times) and no or a tiny dense window of top counters; results must not
+    change."""
     import paper_1608_05138_amd as glt
-    wave_max, mid_max, dense = SPLIT_CASES[case]
+    wave_max, mid_max, dense, wg_max = SPLIT_CASES[case]
     monkeypatch.setenv("GLT_WEDGE_WAVE_MAX", wave_max)
     monkeypatch.setenv("GLT_WEDGE_MID_MAX", mid_max)
+    monkeypatch.setenv("GLT_WEDGE_WG_MAX", wg_max)
     monkeypatch.setenv("GLT_WEDGE_RANGE_LIMIT", "3")
     monkeypatch.setenv("GLT_WEDGE_DENSE", dense)
     c = glt.Context(0)

@@ -107,3 +107,29 @@ def test_small_admission_budget_and_per_graph_mode():
         else:
             assert got[1000]["status"] == 0
             assert max(r["batch_graphs"] for r in got.values()) == 1
+
+
+def test_large_requests_run_on_their_own_lane():
+    """A large request runs on the second compute lane: small requests submitted right after
+    it finish before it does (they are not queued behind it), and every result equals the
+    graph counted alone."""
+    import paper_1608_05138_amd as glt
+    n_big = 200_000
+    big_rp, big_col = gg.chung_lu(n_big, 2_000_000, 2.5, float(n_big - 1), 11)
+    graphs = _requests(40, 515)
+    ctx = glt.Context(0)
+    alone = [ctx.count(rp, col, n=n)[0] for n, (rp, col) in graphs]
+    alone_big = ctx.count(big_rp, big_col, n=n_big)[0]
+    ctx.close()
+    srv = glt.Server(0, large_edges=100_000)
+    say("server-lanes")
+    assert srv.submit(big_rp, big_col, 10_000, n=n_big) == 0
+    for i, (n, (rp, col)) in enumerate(graphs):
+        assert srv.submit(rp, col, i, n=n) == 0
+    got = _collect(srv, len(graphs) + 1)
+    srv.close()
+    assert got[10_000]["status"] == 0 and got[10_000]["X"] == alone_big
+    for i in range(len(graphs)):
+        assert got[i]["status"] == 0 and got[i]["X"] == alone[i], i
+    early = sum(1 for i in range(len(graphs)) if got[i]["t_done"] < got[10_000]["t_done"])
+    assert early > 0, "every small request waited for the large one"
