@@ -156,13 +156,17 @@ def bench_served(args):
         if len(got) < len(arrivals):
             raise RuntimeError(f"only {len(got)} of {len(arrivals)} requests completed")
         lat = np.array([got[i]["t_done"] - sched[i] for i in range(len(arrivals))]) * 1e3
+        kinds = np.array([kind for (_, kind, _) in arrivals])
         bad = sum(1 for i, (ta, kind, idx) in enumerate(arrivals)
                   if got[i]["status"] != 0 or got[i]["X"] != (alone_large if kind else alone_small)[idx])
         span = max(got[i]["t_done"] for i in got) - t0
         sizes = [got[i]["batch_graphs"] for i in got]
-        return {"completed": len(got), "req_per_s": len(got) / span,
-                "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                               "max": float(lat.max())},
+
+        def pct(x):
+            return None if x.size == 0 else {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99)),
+                                             "max": float(x.max())}
+        return {"completed": len(got), "req_per_s": len(got) / span, "latency_ms": pct(lat),
+                "latency_ms_small": pct(lat[kinds == 0]), "latency_ms_large": pct(lat[kinds == 1]),
                 "mean_batch": float(np.mean(sizes)), "mismatches_vs_alone": bad}
 
     print(f"[bench] serving {len(arrivals)} requests over {args.serve_seconds} s (continuous batching)",

@@ -133,12 +133,14 @@ glt_status glt_count_batch(glt_ctx* ctx, const glt_batch* b, uint32_t flags, glt
 
 /*
  * Timing breakdown of the last successful glt_count or glt_count_batch on this handle, in
- * milliseconds measured with HIP events on the call's stream, one entry per kernel group:
+ * milliseconds measured with HIP events, one entry per kernel group:
  * [0] validation + preprocessing (degree order, sorted oriented CSR, work lists),
  * [1] triangle / 4-clique pass, one wavefront per vertex, [2] the same, one workgroup per
  * vertex, [3] per-edge gather pass, wavefront path, [4] the same, workgroup path,
- * [5] 4-cycle wedge pass, wavefront path, [6] the same, workgroup path, [7] vertex sums,
- * combine and reduction.  Returns the number of entries written (<= cap, at most 8).
+ * [5] 4-cycle wedge pass, wavefront classes, [6] the same, workgroup classes, [7] vertex
+ * sums, combine and reduction, [8] the whole call.  The wedge pass runs on a second stream
+ * beside entries [1]-[4], so the entries do not add up to [8].  Returns the number of
+ * entries written (<= cap, at most 9).
  */
 int glt_last_timing(const glt_ctx* ctx, float* ms, int cap);
 
@@ -163,7 +165,7 @@ typedef struct {
     int32_t wedge_wave_max;    /* 4-cycle pass: bottom vertices with at most this many wedges
                                   run one per wavefront with an LDS hash only (0..256)        */
     int32_t wedge_mid_max;     /* up to this many: one per wavefront with a dense window of
-                                  top counters and a hash (>= 0)                               */
+                                  16-bit top counters and a hash (>= 0; at most 65,535 apply) */
     int32_t wedge_dense;       /* width of the dense window of highest-ranked tops (0..16384;
                                   each class caps it at its own table: 1024, 4096, 16384)     */
     int32_t wedge_range_limit; /* distinct hashed tops per range before it is halved (1..4096;

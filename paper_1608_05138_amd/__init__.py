@@ -174,14 +174,15 @@ class Context:
         return self._lib.glt_last_error(self._h).decode()
 
     TIMING_KEYS = ["prep", "tri_wave", "tri_wg", "gather_wave", "gather_wg", "wedge_wave", "wedge_wg",
-                   "combine"]
+                   "combine", "total"]
     WORK_KEYS = ["n", "m", "wedges_wave", "wedges_wg", "tri_list_wave", "tri_list_wg", "triangles_wave",
                  "triangles_wg"]
 
     def last_timing(self):
-        """dict of kernel-group times (ms) of the last count (HIP events on its stream)."""
-        buf = (ctypes.c_float * 8)()
-        k = self._lib.glt_last_timing(self._h, buf, 8)
+        """dict of kernel-group times (ms) of the last count (HIP events; the wedge groups run
+        on a second stream beside the triangle groups, "total" is the whole call)."""
+        buf = (ctypes.c_float * len(self.TIMING_KEYS))()
+        k = self._lib.glt_last_timing(self._h, buf, len(self.TIMING_KEYS))
         return {name: float(buf[i]) for i, name in enumerate(self.TIMING_KEYS[:k])}
 
     def last_work(self):

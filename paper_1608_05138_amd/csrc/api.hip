@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -30,7 +31,8 @@ struct glt_ctx {
     size_t ws_bytes = 0;
     std::string err;
     float timing[NSEG] = {};
-    hipEvent_t ev[NSEG + 1] = {};
+    hipEvent_t ev[NEV] = {};
+    hipStream_t side = nullptr;       // second stream: the wedge pass runs beside the triangle passes
     u64* hbuf = nullptr;   // pinned host buffer for small read-backs (4 KiB)
     int wedge_wave_max = 0;
     int wedge_mid_max = 0;
@@ -44,6 +46,8 @@ struct glt_ctx {
     size_t trec_bytes = 0;
     size_t trec_cap = 0;               // largest record buffer the handle allocates
     int tri_records = 1;               // schedule: use triangle records when they fit
+    void* slab = nullptr;              // larger global slab for the highest out-degrees (grown on demand)
+    size_t slab_bytes = 0;
 };
 
 #define GLT_VERSION "glt 0.2 (gfx950)"
@@ -251,6 +255,32 @@ glt_status ensure_ws(glt_ctx* ctx, size_t need, hipStream_t st) {
 // Triangle records need 8 bytes per slot (sum over vertices of C(out-degree, 2)).  They are
 // used when that fits the handle's record cap and budget; otherwise the passes re-scan the
 // out-lists, with the same results.
+// The workgroup passes for out-degrees above the LDS limit keep their rows (or accumulators)
+// in a global slab, one region per workgroup, launched in groups that fit it.  The built-in
+// 32 MiB slab is replaced by one that holds every such workgroup at once when that fits
+// 1 GiB and the budget (one launch instead of dozens on heavy-tailed graphs).
+void grow_slab(glt_ctx* ctx, Dev& d, int count, int smax, hipStream_t st) {
+    if (count <= 0 || smax <= 0) return;
+    const int64_t W = (smax + 31) / 32;
+    const int64_t per = std::max<int64_t>((int64_t)smax * W, 4 * (int64_t)smax);   // tri rows, gather sums
+    const int64_t want = std::min<int64_t>(per * count, (int64_t)1 << 28);          // words (1 GiB)
+    if (want <= d.gscratch_words) return;
+    const size_t need = (size_t)want * 4;
+    if (need > ctx->slab_bytes) {
+        if (ctx->budget && ctx->ws_bytes + ctx->trec_bytes + need > ctx->budget) return;
+        if (hipStreamSynchronize(st) != hipSuccess) return;
+        if (ctx->slab) { (void)hipFree(ctx->slab); ctx->slab = nullptr; ctx->slab_bytes = 0; }
+        if (hipMalloc(&ctx->slab, need) != hipSuccess) {
+            ctx->slab = nullptr;
+            (void)hipGetLastError();
+            return;
+        }
+        ctx->slab_bytes = need;
+    }
+    d.gscratch = (u32*)ctx->slab;
+    d.gscratch_words = (int64_t)(ctx->slab_bytes / 4);
+}
+
 u64* ensure_trec(glt_ctx* ctx, u64 slots, hipStream_t st) {
     if (slots == 0 || ctx->trec_cap == 0 || !ctx->tri_records) return nullptr;
     if (slots > (u64)(ctx->trec_cap / 8)) return nullptr;
@@ -311,15 +341,19 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
                         hc[TB_N + WB_N + TB_GLOBAL], glt_max_out_degree());
     }
     d.trec = ensure_trec(ctx, n > 0 ? *(u64*)((char*)ctx->hbuf + 64) : 0, st);
-    glt_count_passes(d, per_edge ? 1 : 0, hc, pe_dev, st, ctx->ev + 1);
+    grow_slab(ctx, d, hc[TB_GLOBAL], hc[TB_N + WB_N + TB_GLOBAL], st);
+    glt_count_passes(d, per_edge ? 1 : 0, hc, pe_dev, st, ctx->side, ctx->ev);
     HIPCHK(hipGetLastError());
     return GLT_OK;
 }
 
+// Kernel groups as (begin, end) events; the wedge groups (side stream) overlap the
+// triangle and gather groups, so the groups do not add up to the total.
 void record_timing(glt_ctx* ctx) {
+    static const int be[NSEG][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {1, 6}, {6, 7}, {8, 9}, {0, 9}};
     for (int i = 0; i < NSEG; i++) {
         float ms = 0;
-        (void)hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]);
+        (void)hipEventElapsedTime(&ms, ctx->ev[be[i][0]], ctx->ev[be[i][1]]);
         ctx->timing[i] = ms;
     }
 }
@@ -432,8 +466,12 @@ glt_status glt_create(int device, size_t hbm_budget_bytes, glt_ctx** out) {
         if (hipMemGetInfo(&fr, &total) == hipSuccess) ctx->trec_cap = total / 4;
         if (const char* e = getenv("GLT_TRI_RECORD_BYTES")) ctx->trec_cap = (size_t)strtoull(e, nullptr, 10);
     }
-    for (int i = 0; i <= NSEG; i++)
+    for (int i = 0; i < NEV; i++)
         if (hipEventCreate(&ctx->ev[i]) != hipSuccess) { glt_destroy(ctx); return GLT_E_DEVICE; }
+    if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess) {
+        glt_destroy(ctx);
+        return GLT_E_DEVICE;
+    }
     if (hipHostMalloc((void**)&ctx->hbuf, 4096, hipHostMallocDefault) != hipSuccess) {
         glt_destroy(ctx);
         return GLT_E_DEVICE;
@@ -449,7 +487,12 @@ void glt_destroy(glt_ctx* ctx) {
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->stage) (void)hipFree(ctx->stage);
     if (ctx->trec) (void)hipFree(ctx->trec);
-    for (int i = 0; i <= NSEG; i++)
+    if (ctx->slab) (void)hipFree(ctx->slab);
+    if (ctx->side) {
+        (void)hipStreamSynchronize(ctx->side);
+        (void)hipStreamDestroy(ctx->side);
+    }
+    for (int i = 0; i < NEV; i++)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     if (ctx->hbuf) (void)hipHostFree(ctx->hbuf);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -672,8 +715,7 @@ glt_status glt_autotune_batch(glt_ctx* ctx, const glt_batch* b, glt_schedule* be
                     return fail(ctx, GLT_E_INTERNAL, "schedule (%d, %d, %d) changed the counts", wave_c[a], mid_c[c],
                                 dense_c[e]);
                 }
-                float ms = 0;
-                for (int i = 0; i < NSEG; i++) ms += ctx->timing[i];
+                const float ms = ctx->timing[NSEG - 1];   // the whole call
                 if (win_ms < 0 || ms < win_ms) { win_ms = ms; win = cand; }
             }
     glt_set_schedule(ctx, &win);

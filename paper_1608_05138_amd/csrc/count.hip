@@ -41,6 +41,7 @@ __device__ __forceinline__ u64 acc_get(const u64* base, int64_t k) {
 }
 
 #define TB_THREADS 256
+#define TRI_ILP 4      // out-list entries per lane in flight in the triangle passes
 
 // ---------------------------------------------------------------------------------------
 // triangle / 4-clique pass, out-degree 2..64: one wavefront per vertex, M rows in one word
@@ -112,9 +113,11 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__
     __shared__ u64 sK[4][GLT_WAVE];
     __shared__ int hk[4][SH_SIZE];
     __shared__ unsigned char hv[4][SH_SIZE];
+    // every LDS array is per wavefront: wavefronts synchronise only with themselves
     const int w = threadIdx.x / GLT_WAVE, l = glt_lane();
     const int idx = blockIdx.x * 4 + w;
-    const bool active = idx < nlist;
+    if (idx >= nlist) return;
+    const bool active = true;
     const int a = active ? list[idx] : 0;
     const int o0 = active ? optr[a] : 0;
     const int s = active ? optr[a + 1] - o0 : 0;
@@ -124,33 +127,45 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__
     const int total = __shfl(inc, GLT_WAVE - 1, GLT_WAVE);
     sOb[w][l] = ob; sPre[w][l] = inc - db; sM[w][l] = 0; sK[w][l] = 0;
     hk[w][l] = -1; hk[w][l + GLT_WAVE] = -1;
-    __syncthreads();
+    wave_sync();
     if (l < s) sh_insert(hk[w], hv[w], b, l);
-    __syncthreads();
+    wave_sync();
     // build the adjacency rows among S (and record the triangles)
     u64* rec = (REC && active) ? trec + toff[a] : nullptr;
     const u64 lt = (l == 0) ? 0ull : ((~0ull) >> (GLT_WAVE - l));
     int nh = 0;   // records so far (wave-uniform)
     int i = 0;
-    for (int q0 = 0; q0 < total; q0 += GLT_WAVE) {
-        const int q = q0 + l;
-        int j = -1, k = 0;
-        if (q < total) {
-            i = advance_idx(sPre[w], s, q, i);
-            k = sOb[w][i] + (q - sPre[w][i]);
-            j = sh_find(hk[w], hv[w], ocol[k]);
-            if (j >= 0) {
-                atomicOr(&sM[w][i], 1ull << j);
-                atomicOr(&sM[w][j], 1ull << i);
+    for (int q0 = 0; q0 < total; q0 += TRI_ILP * GLT_WAVE) {
+        // TRI_ILP entries per lane in flight: indices and loads first, then the probes
+        int is[TRI_ILP], ks[TRI_ILP], xs[TRI_ILP];
+#pragma unroll
+        for (int u = 0; u < TRI_ILP; u++) {
+            const int q = q0 + u * GLT_WAVE + l;
+            xs[u] = -1;
+            is[u] = 0;
+            ks[u] = 0;
+            if (q < total) {
+                i = advance_idx(sPre[w], s, q, i);
+                is[u] = i;
+                ks[u] = sOb[w][i] + (q - sPre[w][i]);
+                xs[u] = ocol[ks[u]];
             }
         }
-        if (REC) {
-            const u64 hm = __ballot(j >= 0);
-            if (j >= 0) rec[nh + __popcll(hm & lt)] = tri_rec(i, j, k);
-            nh += __popcll(hm);
+#pragma unroll
+        for (int u = 0; u < TRI_ILP; u++) {
+            const int j = (xs[u] >= 0) ? sh_find(hk[w], hv[w], xs[u]) : -1;
+            if (j >= 0) {
+                atomicOr(&sM[w][is[u]], 1ull << j);
+                atomicOr(&sM[w][j], 1ull << is[u]);
+            }
+            if (REC) {   // entries in scan order: records stay sorted by i
+                const u64 hm = __ballot(j >= 0);
+                if (j >= 0) rec[nh + __popcll(hm & lt)] = tri_rec(is[u], j, ks[u]);
+                nh += __popcll(hm);
+            }
         }
     }
-    __syncthreads();
+    wave_sync();
     u64 k4 = 0;
     if (REC) {
         for (int r0 = 0; r0 < nh; r0 += GLT_WAVE) {
@@ -203,7 +218,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__
             if (last && ssum) atomicAdd(&sK[w][key], ssum);
         }
     }
-    __syncthreads();
+    wave_sync();
     if (l < s) {
         const u32 tl = (u32)__popcll(sM[w][l]);
         if (tl) atomicAdd(&e.t[o0 + l], tl);
@@ -279,44 +294,67 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
     u64* rec = REC ? trec + toff[a] : nullptr;
     const u64 lt = (glt_lane() == 0) ? 0ull : ((~0ull) >> (GLT_WAVE - glt_lane()));
     int ii = 0;
-    for (int q0 = 0; q0 < total; q0 += TB_THREADS) {
-        const int q = q0 + tid;
-        int j = s, k = 0, i = 0;
-        if (q < total) {
-            i = ii = advance_idx(sPre, s, q, ii);
-            k = sOb[i] + (q - sPre[i]);
-            const int jj = bh_find(hk, hp, hmask, ocol[k]);   // x in S lies above b_i: jj > i
-            if (jj >= 0) {
-                j = jj;
-                atomicOr(&M[i * W + (j >> 5)], 1u << (j & 31));
-                atomicOr(&M[j * W + (i >> 5)], 1u << (i & 31));
+    for (int q0 = 0; q0 < total; q0 += TRI_ILP * TB_THREADS) {
+        int is[TRI_ILP], ks[TRI_ILP], xs[TRI_ILP];
+#pragma unroll
+        for (int u = 0; u < TRI_ILP; u++) {
+            const int q = q0 + u * TB_THREADS + tid;
+            xs[u] = -1;
+            is[u] = 0;
+            ks[u] = 0;
+            if (q < total) {
+                is[u] = ii = advance_idx(sPre, s, q, ii);
+                ks[u] = sOb[ii] + (q - sPre[ii]);
+                xs[u] = ocol[ks[u]];
             }
         }
-        if (REC) {   // one slot reservation per wavefront and round
-            const u64 hm = __ballot(j < s);
-            int base = 0;
-            if (glt_lane() == 0 && hm) base = atomicAdd(&sNrec, __popcll(hm));
-            base = __shfl(base, 0, GLT_WAVE);
-            if (j < s) rec[base + __popcll(hm & lt)] = tri_rec(i, j, k);
+#pragma unroll
+        for (int u = 0; u < TRI_ILP; u++) {
+            const int i = is[u];
+            int j = s;
+            if (xs[u] >= 0) {
+                const int jj = bh_find(hk, hp, hmask, xs[u]);   // x in S lies above b_i: jj > i
+                if (jj >= 0) {
+                    j = jj;
+                    atomicOr(&M[i * W + (j >> 5)], 1u << (j & 31));
+                    atomicOr(&M[j * W + (i >> 5)], 1u << (i & 31));
+                }
+            }
+            if (REC) {   // one slot reservation per wavefront and entry batch
+                const u64 hm = __ballot(j < s);
+                int base = 0;
+                if (glt_lane() == 0 && hm) base = atomicAdd(&sNrec, __popcll(hm));
+                base = __shfl(base, 0, GLT_WAVE);
+                if (j < s) rec[base + __popcll(hm & lt)] = tri_rec(i, j, ks[u]);
+            }
         }
     }
     __syncthreads();
     u64 k4 = 0;
     if (REC) {
-        // records of different wavefronts interleave: per-source sums go straight to LDS
+        // records come in runs of equal i (per writing wavefront): per-source sums by run
         const int nrec = sNrec;
-        for (int r = tid; r < nrec; r += TB_THREADS) {
-            int ri, rj, k;
-            tri_unrec(rec[r], ri, rj, k);
+        for (int r0 = 0; r0 < nrec; r0 += TB_THREADS) {
+            const int r = r0 + tid;
+            int key = 0x7fffffff;
             u64 tk = 0;
-            for (int wd = 0; wd < W; wd++) tk += (u64)__popc(M[ri * W + wd] & M[rj * W + wd]);
-            atomicAdd(&e.t[k], 1u);
-            if (PE && tk) {
-                acc_add<AT>(e.K, k, tk);
-                atomicAdd(&sK[rj], tk);
-                atomicAdd(&sK[ri], tk);
+            if (r < nrec) {
+                int ri, rj, k;
+                tri_unrec(rec[r], ri, rj, k);
+                key = ri;
+                for (int wd = 0; wd < W; wd++) tk += (u64)__popc(M[ri * W + wd] & M[rj * W + wd]);
+                atomicAdd(&e.t[k], 1u);
+                if (PE && tk) {
+                    acc_add<AT>(e.K, k, tk);
+                    atomicAdd(&sK[rj], tk);
+                }
+                k4 += tk;
             }
-            k4 += tk;
+            if (PE) {
+                bool last;
+                const u64 ssum = seg_run_sum_last(tk, key, last);
+                if (last && ssum) atomicAdd(&sK[key], ssum);
+            }
         }
         if (tid == 0) tcnt[a] = nrec;
     }
@@ -400,10 +438,10 @@ __device__ __forceinline__ void gather_credit(bool found, int i, int j, int k, c
         acc_add<AT>(e.g, k, tai + taj);
         acc_add<AT>(e.sig, k, (u64)da);
     }
-    // lanes of a wavefront hold non-decreasing i (idle lanes a larger sentinel, zero values)
+    // runs of equal i in the wavefront are summed first (idle lanes: a sentinel key, zero values)
     bool last;
-    const u64 a1 = seg_sum_last(gi, i, last);
-    const u64 a3 = seg_sum_last(di, i, last);
+    const u64 a1 = seg_run_sum_last(gi, i, last);
+    const u64 a3 = seg_run_sum_last(di, i, last);
     if (last) {
         if (a1) atomicAdd(&sG[i], a1);
         if (a3) atomicAdd(&sSg[i], a3);
@@ -426,31 +464,31 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
     __shared__ u64 sSg[4][GLT_WAVE];
     __shared__ int hk[4][SH_SIZE];
     __shared__ unsigned char hv[4][SH_SIZE];
+    // every LDS array is per wavefront: wavefronts synchronise only with themselves and leave
+    // as soon as their vertex is done
     const int w = threadIdx.x / GLT_WAVE, l = glt_lane();
     const int idx = blockIdx.x * 4 + w;
-    const bool active = idx < nlist;
-    const int a = active ? list[idx] : 0;
-    const int o0 = active ? optr[a] : 0;
-    const int s = active ? optr[a + 1] - o0 : 0;
-    const int da = active ? ndeg[a] : 0;
+    if (idx >= nlist) return;
+    const int a = list[idx];
+    const int nh = REC ? tcnt[a] : 0;
+    if (REC && nh == 0) return;   // no triangle has a as its lowest vertex
+    const int o0 = optr[a];
+    const int s = optr[a + 1] - o0;
+    const int da = ndeg[a];
     int b = 0, ob = 0, db = 0;
     u32 tb = 0;
     int degb = 0;
     if (l < s) {
-        b = ocol[o0 + l]; ob = optr[b]; db = optr[b + 1] - ob;
-        tb = e.t[o0 + l]; degb = ndeg[b];
+        b = ocol[o0 + l];
+        tb = e.t[o0 + l];
+        degb = ndeg[b];
+        if (!REC) { ob = optr[b]; db = optr[b + 1] - ob; }
     }
-    const int inc = wave_incl_scan(db);
-    const int total = __shfl(inc, GLT_WAVE - 1, GLT_WAVE);
-    sOb[w][l] = ob; sPre[w][l] = inc - db; sT[w][l] = tb; sD[w][l] = degb;
+    sT[w][l] = tb; sD[w][l] = degb;
     sG[w][l] = 0; sSg[w][l] = 0;
-    hk[w][l] = -1; hk[w][l + GLT_WAVE] = -1;
-    __syncthreads();
-    if (l < s) sh_insert(hk[w], hv[w], b, l);
-    __syncthreads();
     if (REC) {
-        const int nh = active ? tcnt[a] : 0;
-        const u64* rec = trec + (active ? toff[a] : 0);
+        wave_sync();
+        const u64* rec = trec + toff[a];
         for (int r0 = 0; r0 < nh; r0 += GLT_WAVE) {
             const int r = r0 + l;
             int key = 0x3fffffff, j = -1, k = 0;
@@ -458,6 +496,13 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
             gather_credit<AT>(r < nh, key, j, k, sT[w], sD[w], da, e, sG[w], sSg[w]);
         }
     } else {
+        const int inc = wave_incl_scan(db);
+        const int total = __shfl(inc, GLT_WAVE - 1, GLT_WAVE);
+        sOb[w][l] = ob; sPre[w][l] = inc - db;
+        hk[w][l] = -1; hk[w][l + GLT_WAVE] = -1;
+        wave_sync();
+        if (l < s) sh_insert(hk[w], hv[w], b, l);
+        wave_sync();
         int i = 0;
         for (int q0 = 0; q0 < total; q0 += GLT_WAVE) {
             const int q = q0 + l;
@@ -471,7 +516,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
             gather_credit<AT>(j >= 0, key, j, k, sT[w], sD[w], da, e, sG[w], sSg[w]);
         }
     }
-    __syncthreads();
+    wave_sync();
     if (l < s) {
         if (sG[w][l]) acc_add<AT>(e.g, o0 + l, sG[w][l]);
         if (sSg[w][l]) acc_add<AT>(e.sig, o0 + l, sSg[w][l]);
@@ -519,20 +564,14 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict
     const int total = carry;
     __syncthreads();
     if (REC) {
-        // records of different wavefronts interleave: the source's sums go straight to LDS
+        // records come in runs of equal i (per writing wavefront), summed per run
         const int nh = tcnt[a];
         const u64* rec = trec + toff[a];
-        for (int r = tid; r < nh; r += TB_THREADS) {
-            int i, j, k;
-            tri_unrec(rec[r], i, j, k);
-            const u64 tij = e.t[k];
-            const u64 tai = sT[i], taj = sT[j];
-            atomicAdd(&sG[i], taj + tij);
-            atomicAdd(&sSg[i], (u64)sD[j]);
-            atomicAdd(&sG[j], tai + tij);
-            atomicAdd(&sSg[j], (u64)sD[i]);
-            acc_add<AT>(e.g, k, tai + taj);
-            acc_add<AT>(e.sig, k, (u64)da);
+        for (int r0 = 0; r0 < nh; r0 += TB_THREADS) {
+            const int r = r0 + tid;
+            int i = 0x3fffffff, j = -1, k = 0;
+            if (r < nh) tri_unrec(rec[r], i, j, k);
+            gather_credit<AT>(r < nh, i, j, k, sT, sD, da, e, sG, sSg);
         }
     }
     const int rounds = REC ? 0 : (total + TB_THREADS - 1) / TB_THREADS;
@@ -605,7 +644,7 @@ __device__ __forceinline__ int grp_excl_scan(int v, int* lds, int& tot) {
 #define WW_G 4
 #define WW_HT 512        // wave class: <= WW_HT / 2 wedges, so the hash never overflows
 #define WM_T 64
-#define WM_G 2
+#define WM_G 2       // mid class: 16-bit counters (its bottoms have at most 65,535 wedges)
 #define WM_HT 1024
 #define WM_DW 1024
 #define WB_T 256
@@ -625,7 +664,24 @@ __device__ __forceinline__ int grp_excl_scan(int v, int* lds, int& tot) {
 // bottom edge (y, w) summed per source first).  Whenever more than `limit` distinct hashed
 // tops appear, the x-range [lo, hi) is halved and redone; a range is credited only after its
 // count sweep completed without overflow, so no wedge is credited twice.
-template <bool PE, typename AT, int T, int G, int HT, int DW>
+// Top counters: u32 each, or (P16) two 16-bit counters per u32 word when every count is
+// known to stay below 2^16 (the count of a top never exceeds the bottom vertex's wedges).
+template <bool P16>
+__device__ __forceinline__ u32 cnt_inc(u32* a, int i) {
+    if constexpr (P16) {
+        const u32 sh = (u32)(i & 1) << 4;
+        return (atomicAdd(&a[i >> 1], 1u << sh) >> sh) & 0xffffu;
+    } else {
+        return atomicAdd(&a[i], 1u);
+    }
+}
+template <bool P16>
+__device__ __forceinline__ u32 cnt_get(const u32* a, int i) {
+    if constexpr (P16) return (a[i >> 1] >> ((u32)(i & 1) << 4)) & 0xffffu;
+    else return a[i];
+}
+
+template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16>
 __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, int nlist, int n, int limit,
                                                  int dense, const int* __restrict__ nrp,
                                                  const int* __restrict__ ncol, const int* __restrict__ optr,
@@ -634,11 +690,13 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                                                  const int64_t* __restrict__ gvb, int* __restrict__ err) {
     static_assert(T == GLT_WAVE || G == 1, "multi-wave groups own the whole block");
     static_assert(HT % 4 == 0 && DW % 4 == 0 && (HT & (HT - 1)) == 0, "table sizes");
-    constexpr int DWA = DW > 0 ? DW : 4;
+    constexpr int DWA = DW > 0 ? DW : 8;
+    constexpr int DCW = P16 ? DWA / 2 : DWA;   // u32 words of dense counters
+    constexpr int HCW = P16 ? HT / 2 : HT;     // u32 words of hash counters
     constexpr u32 mask = HT - 1;
-    __shared__ __align__(16) u32 s_dc[G][DWA];
+    __shared__ __align__(16) u32 s_dc[G][DCW];
     __shared__ __align__(16) int s_hk[G][HT];
-    __shared__ __align__(16) u32 s_hc[G][HT];
+    __shared__ __align__(16) u32 s_hc[G][HCW];
     __shared__ int s_k0[G][T], s_pre[G][T];
     __shared__ AT s_b[G][T];
     __shared__ int s_scan[G][T / GLT_WAVE];
@@ -669,11 +727,10 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
         const bool full = (lo == y + 1) && (hi == top);
         grp_sync<T>();
         if (tid == 0) { s_sp[g] = sp - 1; s_dist[g] = 0; s_ovf[g] = 0; }
-        for (int q = tid; q < HT / 4; q += T) {
-            reinterpret_cast<int4*>(hk)[q] = make_int4(-1, -1, -1, -1);
-            reinterpret_cast<int4*>(hc)[q] = make_int4(0, 0, 0, 0);
-        }
-        for (int q = tid; q < (nd + 3) / 4; q += T) reinterpret_cast<int4*>(dc)[q] = make_int4(0, 0, 0, 0);
+        for (int q = tid; q < HT / 4; q += T) reinterpret_cast<int4*>(hk)[q] = make_int4(-1, -1, -1, -1);
+        for (int q = tid; q < HCW / 4; q += T) reinterpret_cast<int4*>(hc)[q] = make_int4(0, 0, 0, 0);
+        const int ndw = P16 ? (nd + 1) / 2 : nd;   // dense counter words in use
+        for (int q = tid; q < (ndw + 3) / 4; q += T) reinterpret_cast<int4*>(dc)[q] = make_int4(0, 0, 0, 0);
         grp_sync<T>();
         // count sweep
         u64 c4r = 0;
@@ -705,7 +762,7 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                     const int x = xs[j];
                     if (x < 0) continue;
                     if (x >= base) {
-                        c4r += atomicAdd(&dc[x - base], 1u);
+                        c4r += cnt_inc<P16>(dc, x - base);
                         continue;
                     }
                     u32 h = hslot(x, mask);
@@ -715,14 +772,14 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                         if (cur == -1) {
                             cur = atomicCAS(&hk[h], -1, x);
                             if (cur == -1) {
-                                c4r += atomicAdd(&hc[h], 1u);
+                                c4r += cnt_inc<P16>(hc, (int)h);
                                 if (atomicAdd(&s_dist[g], 1) >= limit) s_ovf[g] = 1;
                                 placed = true;
                                 break;
                             }
                         }
                         if (cur == x) {
-                            c4r += atomicAdd(&hc[h], 1u);
+                            c4r += cnt_inc<P16>(hc, (int)h);
                             placed = true;
                             break;
                         }
@@ -784,12 +841,12 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                         if (x >= 0) {
                             u32 cnt = 1;
                             if (x >= base) {
-                                cnt = dc[x - base];
+                                cnt = cnt_get<P16>(dc, x - base);
                             } else {
                                 u32 h = hslot(x, mask);
                                 int p = 0;
                                 while (p < HT && hk[h] != x) { h = (h + 1) & mask; p++; }
-                                if (p < HT) cnt = hc[h];
+                                if (p < HT) cnt = cnt_get<P16>(hc, (int)h);
                                 else atomicOr(err, ERR_CAP);
                             }
                             c = (AT)(cnt - 1);
@@ -1150,17 +1207,24 @@ static void launch_gather_blk(const Dev& d, const int* lst, int c, int smax, hip
                            d.ocol, d.ndeg, d.e, (u64*)d.gscratch, d.trec, d.toff, d.tcnt);
 }
 
-template <bool PE, typename AT, int T, int G, int HT, int DW>
+template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16 = false>
 static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st) {
     if (cnt <= 0) return;
     const int limit = d.wedge_limit < HT / 2 ? d.wedge_limit : HT / 2;
-    hipLaunchKernelGGL((k_wedge<PE, AT, T, G, HT, DW>), dim3(cdiv(cnt, G)), dim3(T * G), 0, st,
+    hipLaunchKernelGGL((k_wedge<PE, AT, T, G, HT, DW, P16>), dim3(cdiv(cnt, G)), dim3(T * G), 0, st,
                        d.wlist + (int64_t)bkt * d.n, cnt, d.n, limit, d.wedge_dense, d.nrp, d.ncol, d.optr, d.ocol,
                        d.s2k, d.e, d.gsum, d.ngid, d.gvb, d.err);
 }
 
+// The wedge pass runs on a side stream, concurrently with the triangle and gather passes
+// (they share only read-only inputs and distinct accumulators); both join before the vertex
+// pass and the combine.  Events (all recorded, also used to fork and join):
+//   ev[1] end of preprocessing (fork)     ev[2..5] after tri wave / tri wg / gather wave / gather wg
+//   ev[6] after the wedge wave+mid classes, ev[7] after the workgroup classes (side stream)
+//   ev[8] after the join                  ev[9] after the combine
 template <typename AT>
-static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st, hipEvent_t* ev) {
+static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st, hipStream_t side,
+                         hipEvent_t* ev) {
     const int n = d.n, m = d.m;
     u64* gsum = d.gsum;                   // [graph][NSUMS]: 3 x 4-cliques and non-induced 4-cycles
     launch_fill<u64>(gsum, (int64_t)(d.ngraphs > 0 ? d.ngraphs : GSPREAD) * NSUMS, 0ull, st);
@@ -1169,13 +1233,33 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
     const EdgeArrays e = d.e;
     for (int bkt = TB_BLK1; bkt <= TB_GLOBAL; bkt++) sort_heaviest_first(d, d.tlist + (int64_t)bkt * n, cnt[bkt], 1, st);
     for (int bkt = WB_MID; bkt <= WB_HUGE; bkt++) sort_heaviest_first(d, d.wlist + (int64_t)bkt * n, hc[TB_N + bkt], 0, st);
-    if (ev) (void)hipEventRecord(ev[0], st);
+    (void)hipEventRecord(ev[1], st);
+    // wedge pass (side stream): wave and mid classes (one wavefront per bottom vertex), then
+    // the huge and workgroup classes
+    (void)hipStreamWaitEvent(side, ev[1], 0);
+    const int* wc = hc + TB_N;
+    if (per_edge) {
+        launch_wedge<true, AT, WW_T, WW_G, WW_HT, 0>(d, WB_WAVE, wc[WB_WAVE], side);
+        launch_wedge<true, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, WB_MID, wc[WB_MID], side);
+    } else {
+        launch_wedge<false, AT, WW_T, WW_G, WW_HT, 0>(d, WB_WAVE, wc[WB_WAVE], side);
+        launch_wedge<false, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, WB_MID, wc[WB_MID], side);
+    }
+    (void)hipEventRecord(ev[6], side);
+    if (per_edge) {
+        launch_wedge<true, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], side);
+        launch_wedge<true, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], side);
+    } else {
+        launch_wedge<false, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], side);
+        launch_wedge<false, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], side);
+    }
+    (void)hipEventRecord(ev[7], side);
     // triangle / 4-clique pass
     if (cnt[TB_WAVE] > 0) {
         if (per_edge) launch_tri_wave<true, AT>(d, tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], st);
         else launch_tri_wave<false, AT>(d, tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], st);
     }
-    if (ev) (void)hipEventRecord(ev[1], st);
+    (void)hipEventRecord(ev[2], st);
     for (int bkt = TB_BLK1; bkt <= TB_GLOBAL; bkt++) {
         const int c = cnt[bkt];
         if (c <= 0) continue;
@@ -1200,7 +1284,7 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
             }
         }
     }
-    if (ev) (void)hipEventRecord(ev[2], st);
+    (void)hipEventRecord(ev[3], st);
     // gather pass
     if (per_edge && cnt[TB_WAVE] > 0) {
         if (d.trec)
@@ -1212,7 +1296,7 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
                                tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, d.ndeg, e, d.trec, d.toff,
                                d.tcnt);
     }
-    if (ev) (void)hipEventRecord(ev[3], st);
+    (void)hipEventRecord(ev[4], st);
     if (per_edge) {
         for (int bkt = TB_BLK1; bkt <= TB_GLOBAL; bkt++) {
             const int c = cnt[bkt];
@@ -1233,25 +1317,10 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
             }
         }
     }
-    if (ev) (void)hipEventRecord(ev[4], st);
-    // wedge pass: wave and mid classes (one wavefront per bottom vertex), then workgroups
-    const int* wc = hc + TB_N;
-    if (per_edge) {
-        launch_wedge<true, AT, WW_T, WW_G, WW_HT, 0>(d, WB_WAVE, wc[WB_WAVE], st);
-        launch_wedge<true, AT, WM_T, WM_G, WM_HT, WM_DW>(d, WB_MID, wc[WB_MID], st);
-    } else {
-        launch_wedge<false, AT, WW_T, WW_G, WW_HT, 0>(d, WB_WAVE, wc[WB_WAVE], st);
-        launch_wedge<false, AT, WM_T, WM_G, WM_HT, WM_DW>(d, WB_MID, wc[WB_MID], st);
-    }
-    if (ev) (void)hipEventRecord(ev[5], st);
-    if (per_edge) {
-        launch_wedge<true, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], st);
-        launch_wedge<true, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], st);
-    } else {
-        launch_wedge<false, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], st);
-        launch_wedge<false, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], st);
-    }
-    if (ev) (void)hipEventRecord(ev[6], st);
+    (void)hipEventRecord(ev[5], st);
+    // join the wedge pass
+    (void)hipStreamWaitEvent(st, ev[7], 0);
+    (void)hipEventRecord(ev[8], st);
     // vertex pass + combine
     if (per_edge && n > 0 && m > 0) {
         launch_fill<u64>(d.tri, n, 0ull, st);
@@ -1274,15 +1343,16 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
     } else {
         launch_fill<u64>(d.final_sums, 2 * NCS, 0ull, st);
     }
-    if (ev) (void)hipEventRecord(ev[7], st);
+    (void)hipEventRecord(ev[9], st);
     hipLaunchKernelGGL(k_fold_gsum, dim3(1), dim3(256), 0, st, gsum, d.ngraphs, d.work, d.wspread);
 }
 
-void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st, hipEvent_t* ev) {
+void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st, hipStream_t side,
+                      hipEvent_t* ev) {
     if (d.acc32)
-        count_passes<u32>(d, per_edge, hc, out_pe, st, ev);
+        count_passes<u32>(d, per_edge, hc, out_pe, st, side, ev);
     else
-        count_passes<u64>(d, per_edge, hc, out_pe, st, ev);
+        count_passes<u64>(d, per_edge, hc, out_pe, st, side, ev);
 }
 
 int glt_combine_blocks(int m) { return combine_blocks(m); }

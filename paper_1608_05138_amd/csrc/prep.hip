@@ -339,15 +339,18 @@ __global__ __launch_bounds__(256) void k_sort_blk(const int* __restrict__ list, 
     for (int j = t; j < len; j += 256) { key[b + j] = sk[j]; val[b + j] = sv[j]; }
 }
 
-// Rows longer than RB_MAX: one workgroup per row, stable LSD radix passes of 8 bits over
-// `bits` key bits, ping-ponging between (kA, vA) and (kB, vB) at the row's own positions;
-// the result ends in (kA, vA).
-__global__ __launch_bounds__(256) void k_sort_big(const int* __restrict__ list, int cnt, const int* __restrict__ nrp,
-                                                  u32* __restrict__ kA, u32* __restrict__ vA, u32* __restrict__ kB,
-                                                  u32* __restrict__ vB, int bits) {
+// Rows longer than RB_MAX: one 1024-thread workgroup per row, stable LSD radix passes of 8
+// bits over `bits` key bits, ping-ponging between (kA, vA) and (kB, vB) at the row's own
+// positions; the result ends in (kA, vA).  Each pass: a digit histogram, its exclusive
+// scan, then tiles of 1024 entries in order, ranked within each wavefront by ballots and
+// across wavefronts by per-wavefront digit counts.
+#define SB_T 1024
+__global__ __launch_bounds__(SB_T) void k_sort_big(const int* __restrict__ list, int cnt, const int* __restrict__ nrp,
+                                                   u32* __restrict__ kA, u32* __restrict__ vA, u32* __restrict__ kB,
+                                                   u32* __restrict__ vB, int bits) {
     __shared__ u32 base[256];
-    __shared__ u32 wcnt[256 / GLT_WAVE][256];
-    __shared__ u32 sscan[256 / GLT_WAVE];
+    __shared__ u32 wcnt[SB_T / GLT_WAVE][256];
+    __shared__ u32 sscan[SB_T / GLT_WAVE];
     const int t = threadIdx.x, lane = glt_lane(), w = t / GLT_WAVE;
     const int r = list[blockIdx.x];
     const int64_t b = nrp[r];
@@ -357,16 +360,18 @@ __global__ __launch_bounds__(256) void k_sort_big(const int* __restrict__ list, 
     const u64 lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (GLT_WAVE - lane));
     int npass = 0;
     for (int shift = 0; shift < bits; shift += 8, npass++) {
-        base[t] = 0;
-        for (int q = 0; q < 256 / GLT_WAVE; q++) wcnt[q][t] = 0;
+        if (t < 256) {
+            base[t] = 0;
+            for (int q = 0; q < SB_T / GLT_WAVE; q++) wcnt[q][t] = 0;
+        }
         __syncthreads();
-        for (int j = t; j < len; j += 256) atomicAdd(&base[(ki[j] >> shift) & 255u], 1u);
+        for (int j = t; j < len; j += SB_T) atomicAdd(&base[(ki[j] >> shift) & 255u], 1u);
         __syncthreads();
         u32 tot;
-        const u32 ex = block_excl_scan<u32, 256>(base[t], sscan, tot);
-        base[t] = ex;
+        const u32 ex = block_excl_scan<u32, SB_T>(t < 256 ? base[t] : 0u, sscan, tot);
+        if (t < 256) base[t] = ex;
         __syncthreads();
-        for (int j0 = 0; j0 < len; j0 += 256) {
+        for (int j0 = 0; j0 < len; j0 += SB_T) {
             const int j = j0 + t;
             const bool valid = j < len;
             const u32 k = valid ? ki[j] : 0u;
@@ -388,16 +393,18 @@ __global__ __launch_bounds__(256) void k_sort_big(const int* __restrict__ list, 
                 vo[off + rk] = v;
             }
             __syncthreads();
-            u32 add = 0;
-            for (int q = 0; q < 256 / GLT_WAVE; q++) { add += wcnt[q][t]; wcnt[q][t] = 0; }
-            base[t] += add;
+            if (t < 256) {
+                u32 add = 0;
+                for (int q = 0; q < SB_T / GLT_WAVE; q++) { add += wcnt[q][t]; wcnt[q][t] = 0; }
+                base[t] += add;
+            }
             __syncthreads();
         }
         u32* tk = ki; ki = ko; ko = tk;
         u32* tv = vi; vi = vo; vo = tv;
     }
     if (npass & 1)
-        for (int j = t; j < len; j += 256) { kA[b + j] = kB[b + j]; vA[b + j] = vB[b + j]; }
+        for (int j = t; j < len; j += SB_T) { kA[b + j] = kB[b + j]; vA[b + j] = vB[b + j]; }
 }
 
 // Sorted rows -> relabelled columns; equal neighbours side by side in a row are duplicates.
@@ -641,7 +648,7 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
             hipLaunchKernelGGL(k_sort_blk, dim3(rows[RS_BLK]), dim3(256), 0, st, rlist + (int64_t)RS_BLK * n,
                                rows[RS_BLK], d.nrp, key, val);
         if (rows[RS_BIG] > 0)
-            hipLaunchKernelGGL(k_sort_big, dim3(rows[RS_BIG]), dim3(256), 0, st, rlist + (int64_t)RS_BIG * n,
+            hipLaunchKernelGGL(k_sort_big, dim3(rows[RS_BIG]), dim3(SB_T), 0, st, rlist + (int64_t)RS_BIG * n,
                                rows[RS_BIG], d.nrp, key, val, (u32*)d.key1, d.val1,
                                bitlen((u64)(n > 1 ? n - 1 : 1)));
         hipLaunchKernelGGL(k_unpack_cols, dim3(nblk(S, 256)), dim3(256), 0, st, key, S, d.nsrow, d.nrp, d.ncol, d.err);
@@ -662,7 +669,7 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
     if (S > 0)
         hipLaunchKernelGGL(k_wcount, dim3(nblk(S, 256)), dim3(256), 0, st, d.ncol, d.nsrow, d.optr, d.s2k, S, d.wcnt,
                            d.wspread);
-    hipLaunchKernelGGL(k_wappend, dim3(nblk(n, 256)), dim3(256), 0, st, d.wcnt, n, d.wedge_wave_max, d.wedge_mid_max, d.wedge_wg_max, d.wlist,
+    hipLaunchKernelGGL(k_wappend, dim3(nblk(n, 256)), dim3(256), 0, st, d.wcnt, n, d.wedge_wave_max, d.wedge_mid_max < 65535 ? d.wedge_mid_max : 65535, d.wedge_wg_max, d.wlist,
                        d.counts + TB_N, d.wspread);
     return 0;
 }

@@ -64,6 +64,28 @@ __device__ __forceinline__ T seg_sum_last(T v, int key, bool& is_last) {
     return v;
 }
 
+// Segmented inclusive sum over maximal runs of equal consecutive keys in a wavefront; a key
+// may recur in separate runs (each run is summed on its own).  is_last marks the last lane of
+// each run, which holds the run's total.
+template <typename T>
+__device__ __forceinline__ T seg_run_sum_last(T v, int key, bool& is_last) {
+    const int l = glt_lane();
+    const int kp = __shfl_up(key, 1, GLT_WAVE);
+    int f = (l == 0 || kp != key) ? 1 : 0;   // a run starts at or below this lane's span
+#pragma unroll
+    for (int d = 1; d < GLT_WAVE; d <<= 1) {
+        const T o = __shfl_up(v, d, GLT_WAVE);
+        const int of = __shfl_up(f, d, GLT_WAVE);
+        if (l >= d && !f) {
+            v += o;
+            f = of;
+        }
+    }
+    const int kn = __shfl_down(key, 1, GLT_WAVE);
+    is_last = (l == GLT_WAVE - 1) || (kn != key);
+    return v;
+}
+
 // Exclusive scan over a block of BLOCK threads.  lds must hold BLOCK/64 elements.  All
 // threads of the block must call it (contains __syncthreads).
 template <typename T, int BLOCK>

@@ -405,3 +405,22 @@ def test_config_chung_lu_1m(ctx):
 def test_config_rmat_s22(ctx):
     n, (rp, col) = gg.config_rmat_s22()
     _full_size(ctx, "rmat-s22-ef16", n, rp, col)
+
+
+def test_out_degree_limit(ctx):
+    """The largest supported out-degree in the degree order is 3200: K_3201 (out-degrees up to
+    3200, every vertex on the global-bitmap path above 640) counts exactly; K_3202 is refused
+    with GLT_E_UNSUPPORTED before any count is produced."""
+    import paper_1608_05138_amd as glt
+    n = 3201
+    N, (rp, col) = gg.complete(n)
+    say(f"complete-{n} (limit)")
+    X, _ = gpu(ctx, N, rp, col, per_edge=False)
+    assert X == _closed_complete(n)
+    N2, (rp2, col2) = gg.complete(n + 1)
+    say(f"complete-{n + 1} (refused)")
+    with pytest.raises(glt.GltError) as ei:
+        ctx.count(rp2, col2, n=N2)
+    assert ei.value.status == -6, str(ei.value)
+    X, _ = gpu(ctx, N, rp, col, per_edge=False)   # the handle still works
+    assert X == _closed_complete(n)
