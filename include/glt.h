@@ -159,7 +159,7 @@ int glt_last_work(const glt_ctx* ctx, uint64_t* out, int cap);
  * Work schedule of a handle: how the counting passes split their work among size classes
  * (Section 4.3 splits edges by cost between workers; here vertices are split by their work
  * between wavefront and workgroup kernels).  Every schedule yields the same counts; only
- * the speed differs.  Defaults: 256, 2048, 16384, 4096, 1, 65536.
+ * the speed differs.  Defaults: 256, 2048, 16384, 4096, 1, 65536, 1.
  */
 typedef struct {
     int32_t wedge_wave_max;    /* 4-cycle pass: bottom vertices with at most this many wedges
@@ -174,7 +174,9 @@ typedef struct {
                                   gather pass when the record buffer fits; 0: re-scan lists  */
     int32_t wedge_wg_max;      /* up to this many: one per 256-thread workgroup; more: one per
                                   1024-thread workgroup with the largest tables (>= 0)        */
-    int32_t reserved[2];       /* must be 0                                                  */
+    int32_t wedge_stream;      /* 1: the 4-cycle pass runs on a second stream beside the
+                                  triangle and gather passes; 0: after them on one stream     */
+    int32_t reserved;          /* must be 0                                                  */
 } glt_schedule;
 
 /* The handle's current schedule. */
@@ -185,8 +187,9 @@ glt_status glt_get_schedule(const glt_ctx* ctx, glt_schedule* out);
 glt_status glt_set_schedule(glt_ctx* ctx, const glt_schedule* s);
 
 /*
- * Autotuner for batches: counts the batch once per candidate schedule (a fixed grid over
- * the wedge class bounds and the dense window, after one warm-up call), checks that all
+ * Autotuner for batches: counts the batch once per candidate schedule (a fixed 24-point grid
+ * over the wedge class bounds, the dense window and wedge_stream, after one warm-up call),
+ * checks that all
  * candidates give identical counts (GLT_E_INTERNAL otherwise), installs the candidate with
  * the least device time (sum of the glt_last_timing groups) on the handle and returns it.
  *   best     out: the chosen schedule

@@ -68,11 +68,11 @@ class glt_schedule(ctypes.Structure):
     _fields_ = [("wedge_wave_max", ctypes.c_int32), ("wedge_mid_max", ctypes.c_int32),
                 ("wedge_dense", ctypes.c_int32), ("wedge_range_limit", ctypes.c_int32),
                 ("tri_records", ctypes.c_int32), ("wedge_wg_max", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("wedge_stream", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 SCHEDULE_KEYS = ["wedge_wave_max", "wedge_mid_max", "wedge_dense", "wedge_range_limit", "tri_records",
-                 "wedge_wg_max"]
+                 "wedge_wg_max", "wedge_stream"]
 
 
 class glt_server_opts(ctypes.Structure):

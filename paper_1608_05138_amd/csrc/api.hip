@@ -46,6 +46,8 @@ struct glt_ctx {
     size_t trec_bytes = 0;
     size_t trec_cap = 0;               // largest record buffer the handle allocates
     int tri_records = 1;               // schedule: use triangle records when they fit
+    int wedge_stream = 1;              // schedule: wedge pass on the side stream
+    int last_overlap = 1;              // the mode the last call's timing was taken in
     void* slab = nullptr;              // larger global slab for the highest out-degrees (grown on demand)
     size_t slab_bytes = 0;
 };
@@ -342,7 +344,8 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
     }
     d.trec = ensure_trec(ctx, n > 0 ? *(u64*)((char*)ctx->hbuf + 64) : 0, st);
     grow_slab(ctx, d, hc[TB_GLOBAL], hc[TB_N + WB_N + TB_GLOBAL], st);
-    glt_count_passes(d, per_edge ? 1 : 0, hc, pe_dev, st, ctx->side, ctx->ev);
+    ctx->last_overlap = ctx->wedge_stream;
+    glt_count_passes(d, per_edge ? 1 : 0, hc, pe_dev, st, ctx->side, ctx->ev, ctx->wedge_stream);
     HIPCHK(hipGetLastError());
     return GLT_OK;
 }
@@ -352,8 +355,10 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
 void record_timing(glt_ctx* ctx) {
     static const int be[NSEG][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {1, 6}, {6, 7}, {8, 9}, {0, 9}};
     for (int i = 0; i < NSEG; i++) {
+        int b0 = be[i][0];
+        if (i == 5 && !ctx->last_overlap) b0 = 5;   // one stream: the wedge pass follows the gather pass
         float ms = 0;
-        (void)hipEventElapsedTime(&ms, ctx->ev[be[i][0]], ctx->ev[be[i][1]]);
+        (void)hipEventElapsedTime(&ms, ctx->ev[b0], ctx->ev[be[i][1]]);
         ctx->timing[i] = ms;
     }
 }
@@ -447,6 +452,7 @@ glt_status glt_create(int device, size_t hbm_budget_bytes, glt_ctx** out) {
         int v = atoi(e);
         if (v >= 0) ctx->wedge_wg_max = v;
     }
+    if (const char* e = getenv("GLT_WEDGE_STREAM")) ctx->wedge_stream = atoi(e) ? 1 : 0;
     if (const char* e = getenv("GLT_WEDGE_RANGE_LIMIT")) {
         int v = atoi(e);
         if (v >= 1 && v < ctx->wedge_limit) ctx->wedge_limit = v;
@@ -652,6 +658,7 @@ glt_status glt_get_schedule(const glt_ctx* ctx, glt_schedule* out) {
     out->wedge_wave_max = ctx->wedge_wave_max;
     out->wedge_mid_max = ctx->wedge_mid_max;
     out->wedge_wg_max = ctx->wedge_wg_max;
+    out->wedge_stream = ctx->wedge_stream;
     out->wedge_dense = ctx->wedge_dense;
     out->wedge_range_limit = ctx->wedge_limit;
     out->tri_records = ctx->tri_records;
@@ -671,14 +678,15 @@ glt_status glt_set_schedule(glt_ctx* ctx, const glt_schedule* s) {
     if (s->wedge_range_limit < 1 || s->wedge_range_limit > glt_wedge_table() / 2)
         return fail(ctx, GLT_E_INVALID_ARG, "wedge_range_limit must be in [1, %d]", glt_wedge_table() / 2);
     if (s->tri_records != 0 && s->tri_records != 1) return fail(ctx, GLT_E_INVALID_ARG, "tri_records must be 0 or 1");
-    for (int i = 0; i < 2; i++)
-        if (s->reserved[i]) return fail(ctx, GLT_E_INVALID_ARG, "reserved fields must be 0");
+    if (s->wedge_stream != 0 && s->wedge_stream != 1) return fail(ctx, GLT_E_INVALID_ARG, "wedge_stream must be 0 or 1");
+    if (s->reserved) return fail(ctx, GLT_E_INVALID_ARG, "reserved field must be 0");
     ctx->wedge_wave_max = s->wedge_wave_max;
     ctx->wedge_mid_max = s->wedge_mid_max;
     ctx->wedge_wg_max = s->wedge_wg_max;
     ctx->wedge_dense = s->wedge_dense;
     ctx->wedge_limit = s->wedge_range_limit;
     ctx->tri_records = s->tri_records;
+    ctx->wedge_stream = s->wedge_stream;
     return GLT_OK;
 }
 
@@ -701,19 +709,20 @@ glt_status glt_autotune_batch(glt_ctx* ctx, const glt_batch* b, glt_schedule* be
     float win_ms = -1.f;
     for (int a = 0; a < 2; a++)
         for (int c = 0; c < 3; c++)
-            for (int e = 0; e < 2; e++) {
+            for (int e = 0; e < 4; e++) {
                 glt_schedule cand = base;
                 cand.wedge_wave_max = wave_c[a];
                 cand.wedge_mid_max = mid_c[c];
-                cand.wedge_dense = dense_c[e];
+                cand.wedge_dense = dense_c[e & 1];
+                cand.wedge_stream = e >> 1;
                 rc = glt_set_schedule(ctx, &cand);
                 if (rc) { glt_set_schedule(ctx, &base); return rc; }
                 rc = glt_count_batch(ctx, b, GLT_GLOBAL, got.data(), stream);
                 if (rc) { glt_set_schedule(ctx, &base); return rc; }
                 if (memcmp(got.data(), ref.data(), got.size() * sizeof(glt_u128)) != 0) {
                     glt_set_schedule(ctx, &base);
-                    return fail(ctx, GLT_E_INTERNAL, "schedule (%d, %d, %d) changed the counts", wave_c[a], mid_c[c],
-                                dense_c[e]);
+                    return fail(ctx, GLT_E_INTERNAL, "schedule (%d, %d, %d, %d) changed the counts", wave_c[a], mid_c[c],
+                                dense_c[e & 1], e >> 1);
                 }
                 const float ms = ctx->timing[NSEG - 1];   // the whole call
                 if (win_ms < 0 || ms < win_ms) { win_ms = ms; win = cand; }

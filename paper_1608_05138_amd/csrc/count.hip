@@ -41,7 +41,9 @@ __device__ __forceinline__ u64 acc_get(const u64* base, int64_t k) {
 }
 
 #define TB_THREADS 256
-#define TRI_ILP 4      // out-list entries per lane in flight in the triangle passes
+#ifndef TRI_ILP
+#define TRI_ILP 8      // out-list entries per lane in flight in the triangle passes
+#endif
 
 // ---------------------------------------------------------------------------------------
 // triangle / 4-clique pass, out-degree 2..64: one wavefront per vertex, M rows in one word
@@ -636,7 +638,9 @@ __device__ __forceinline__ int grp_excl_scan(int v, int* lds, int& tot) {
 }
 
 #define WEDGE_STACK 40   // x-range stack per group (halving depth <= 32 for 31-bit ids)
-#define WEDGE_ILP 4      // wedges in flight per lane
+#ifndef WEDGE_ILP
+#define WEDGE_ILP 4      // wedges in flight per lane (8 measured slower: registers)
+#endif
 
 // Size classes of the wedge pass (wedges per bottom vertex y): threads per group, groups per
 // block, hash entries, dense top counters.
@@ -647,6 +651,15 @@ __device__ __forceinline__ int grp_excl_scan(int v, int* lds, int& tot) {
 #define WM_G 2       // mid class: 16-bit counters (its bottoms have at most 65,535 wedges)
 #define WM_HT 1024
 #define WM_DW 1024
+// Remembering each wedge's counter slot in LDS (CAP > 0) spares the credit sweep the top's
+// load and hash probe, but the extra LDS lowers occupancy; measured slower on the Chung-Lu
+// and R-MAT graphs, so both classes run without it by default.
+#ifndef WW_CAP
+#define WW_CAP 0
+#endif
+#ifndef WM_CAP
+#define WM_CAP 0
+#endif
 #define WB_T 256
 #define WB_HT 2048
 #define WB_DW 4096
@@ -681,22 +694,26 @@ __device__ __forceinline__ u32 cnt_get(const u32* a, int i) {
     else return a[i];
 }
 
-template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16>
+template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16, int CAP>
 __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, int nlist, int n, int limit,
                                                  int dense, const int* __restrict__ nrp,
                                                  const int* __restrict__ ncol, const int* __restrict__ optr,
                                                  const int* __restrict__ ocol, const int* __restrict__ s2k,
-                                                 EdgeArrays e, u64* __restrict__ gsum, const int* __restrict__ ngid,
+                                                 const u64* __restrict__ wcnt, EdgeArrays e,
+                                                 u64* __restrict__ gsum, const int* __restrict__ ngid,
                                                  const int64_t* __restrict__ gvb, int* __restrict__ err) {
     static_assert(T == GLT_WAVE || G == 1, "multi-wave groups own the whole block");
     static_assert(HT % 4 == 0 && DW % 4 == 0 && (HT & (HT - 1)) == 0, "table sizes");
+    static_assert(DW + HT <= 65536, "table slots fit 16 bits");
     constexpr int DWA = DW > 0 ? DW : 8;
     constexpr int DCW = P16 ? DWA / 2 : DWA;   // u32 words of dense counters
     constexpr int HCW = P16 ? HT / 2 : HT;     // u32 words of hash counters
+    constexpr int CAPA = CAP > 0 ? CAP : 2;
     constexpr u32 mask = HT - 1;
     __shared__ __align__(16) u32 s_dc[G][DCW];
     __shared__ __align__(16) int s_hk[G][HT];
     __shared__ __align__(16) u32 s_hc[G][HCW];
+    __shared__ unsigned short s_slot[G][CAPA];   // per wedge: its counter (dense index or DW + hash slot)
     __shared__ int s_k0[G][T], s_pre[G][T];
     __shared__ AT s_b[G][T];
     __shared__ int s_scan[G][T / GLT_WAVE];
@@ -711,9 +728,14 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
     const int top = ngid ? (int)gvb[ngid[y] + 1] : n;
     const int base = max(top - min(dense, DW), y + 1);   // tops >= base are counted densely
     const int nd = top - base;                            // dense counters in use, <= DW
+    // with at most CAP wedges, the count sweep remembers each wedge's counter so that the
+    // credit sweep needs neither the top's id nor a hash probe
+    const bool cached = CAP > 0 && PE && wcnt[y] <= (u64)CAP;
+    const bool one = (re - rb) <= T;   // one chunk of sources: its bounds stay in LDS
     u32* dc = s_dc[g];
     int* hk = s_hk[g];
     u32* hc = s_hc[g];
+    unsigned short* slot = s_slot[g];
     int* k0s = s_k0[g];
     int* pre = s_pre[g];
     AT* sb = s_b[g];
@@ -734,6 +756,7 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
         grp_sync<T>();
         // count sweep
         u64 c4r = 0;
+        int qb = 0, tot1 = 0;   // wedges of earlier chunks; wedges of the last chunk
         for (int c0 = rb; c0 < re; c0 += T) {
             const int s = c0 + tid;
             int k0 = 0, k1 = 0;
@@ -761,33 +784,38 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                 for (int j = 0; j < WEDGE_ILP; j++) {
                     const int x = xs[j];
                     if (x < 0) continue;
+                    int sl;
                     if (x >= base) {
-                        c4r += cnt_inc<P16>(dc, x - base);
-                        continue;
-                    }
-                    u32 h = hslot(x, mask);
-                    bool placed = false;
-                    for (int p = 0; p < HT; p++) {   // bounded probe: a full table is an overflow
-                        int cur = hk[h];
-                        if (cur == -1) {
-                            cur = atomicCAS(&hk[h], -1, x);
+                        sl = x - base;
+                        c4r += cnt_inc<P16>(dc, sl);
+                    } else {
+                        u32 h = hslot(x, mask);
+                        sl = -1;
+                        for (int p = 0; p < HT; p++) {   // bounded probe: a full table is an overflow
+                            int cur = hk[h];
                             if (cur == -1) {
+                                cur = atomicCAS(&hk[h], -1, x);
+                                if (cur == -1) {
+                                    c4r += cnt_inc<P16>(hc, (int)h);
+                                    if (atomicAdd(&s_dist[g], 1) >= limit) s_ovf[g] = 1;
+                                    sl = DW + (int)h;
+                                    break;
+                                }
+                            }
+                            if (cur == x) {
                                 c4r += cnt_inc<P16>(hc, (int)h);
-                                if (atomicAdd(&s_dist[g], 1) >= limit) s_ovf[g] = 1;
-                                placed = true;
+                                sl = DW + (int)h;
                                 break;
                             }
+                            h = (h + 1) & mask;
                         }
-                        if (cur == x) {
-                            c4r += cnt_inc<P16>(hc, (int)h);
-                            placed = true;
-                            break;
-                        }
-                        h = (h + 1) & mask;
+                        if (sl < 0) { s_ovf[g] = 1; continue; }
                     }
-                    if (!placed) s_ovf[g] = 1;
+                    if (CAP > 0 && cached) slot[qb + q0 + j * T + tid] = (unsigned short)sl;
                 }
             }
+            qb += tot;
+            tot1 = tot;
             grp_sync<T>();
         }
         if (s_ovf[g]) {
@@ -807,59 +835,81 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
         c4 += c4r;
         if (PE) {
             // credit sweep: the counts of this range are final
+            qb = 0;
             for (int c0 = rb; c0 < re; c0 += T) {
                 const int s = c0 + tid;
-                int k0 = 0, k1 = 0;
-                if (s < re) wedge_bounds(y, s, lo, hi, full, ncol, optr, ocol, s2k, k0, k1);
-                int tot;
-                const int ex = grp_excl_scan<T>(k1 - k0, s_scan[g], tot);
+                int tot = tot1;
+                if (!one) {
+                    int k0 = 0, k1 = 0;
+                    if (s < re) wedge_bounds(y, s, lo, hi, full, ncol, optr, ocol, s2k, k0, k1);
+                    const int ex = grp_excl_scan<T>(k1 - k0, s_scan[g], tot);
+                    k0s[tid] = k0;
+                    pre[tid] = ex;
+                }
                 const int nsrc = min(T, re - c0);
-                k0s[tid] = k0;
-                pre[tid] = ex;
                 sb[tid] = 0;
                 grp_sync<T>();
                 int ii = 0;
-                for (int q0 = 0; q0 < tot; q0 += WEDGE_ILP * T) {
-                    int xs[WEDGE_ILP], ks[WEDGE_ILP], is[WEDGE_ILP];
-#pragma unroll
-                    for (int j = 0; j < WEDGE_ILP; j++) {
-                        const int q = q0 + j * T + tid;
-                        is[j] = 0x7fffffff;
-                        ks[j] = 0;
-                        xs[j] = -1;
-                        if (q < tot) {
-                            ii = advance_idx(pre, nsrc, q, ii);
-                            is[j] = ii;
-                            ks[j] = k0s[ii] + (q - pre[ii]);
-                            xs[j] = ocol[ks[j]];
-                        }
-                    }
-#pragma unroll
-                    for (int j = 0; j < WEDGE_ILP; j++) {
+                if (CAP > 0 && cached) {
+                    for (int q0 = 0; q0 < tot; q0 += T) {
+                        const int q = q0 + tid;
+                        int i = 0x7fffffff;
                         AT c = 0;
-                        const int x = xs[j];
-                        if (x >= 0) {
-                            u32 cnt = 1;
-                            if (x >= base) {
-                                cnt = cnt_get<P16>(dc, x - base);
-                            } else {
-                                u32 h = hslot(x, mask);
-                                int p = 0;
-                                while (p < HT && hk[h] != x) { h = (h + 1) & mask; p++; }
-                                if (p < HT) cnt = cnt_get<P16>(hc, (int)h);
-                                else atomicOr(err, ERR_CAP);
-                            }
+                        if (q < tot) {
+                            i = ii = advance_idx(pre, nsrc, q, ii);
+                            const int sl = slot[qb + q];
+                            const u32 cnt = (sl < DW) ? cnt_get<P16>(dc, sl) : cnt_get<P16>(hc, sl - DW);
                             c = (AT)(cnt - 1);
-                            if (c) acc_add<AT>(e.P, ks[j], (u64)c);
+                            if (c) acc_add<AT>(e.P, k0s[i] + (q - pre[i]), (u64)c);
                         }
                         bool last;
-                        const AT ssum = seg_sum_last(c, is[j], last);
-                        if (last && ssum) atomicAdd(&sb[is[j]], ssum);
+                        const AT ssum = seg_sum_last(c, i, last);
+                        if (last && ssum) atomicAdd(&sb[i], ssum);
+                    }
+                } else {
+                    for (int q0 = 0; q0 < tot; q0 += WEDGE_ILP * T) {
+                        int xs[WEDGE_ILP], ks[WEDGE_ILP], is[WEDGE_ILP];
+#pragma unroll
+                        for (int j = 0; j < WEDGE_ILP; j++) {
+                            const int q = q0 + j * T + tid;
+                            is[j] = 0x7fffffff;
+                            ks[j] = 0;
+                            xs[j] = -1;
+                            if (q < tot) {
+                                ii = advance_idx(pre, nsrc, q, ii);
+                                is[j] = ii;
+                                ks[j] = k0s[ii] + (q - pre[ii]);
+                                xs[j] = ocol[ks[j]];
+                            }
+                        }
+#pragma unroll
+                        for (int j = 0; j < WEDGE_ILP; j++) {
+                            AT c = 0;
+                            const int x = xs[j];
+                            if (x >= 0) {
+                                u32 cnt = 1;
+                                if (x >= base) {
+                                    cnt = cnt_get<P16>(dc, x - base);
+                                } else {
+                                    u32 h = hslot(x, mask);
+                                    int p = 0;
+                                    while (p < HT && hk[h] != x) { h = (h + 1) & mask; p++; }
+                                    if (p < HT) cnt = cnt_get<P16>(hc, (int)h);
+                                    else atomicOr(err, ERR_CAP);
+                                }
+                                c = (AT)(cnt - 1);
+                                if (c) acc_add<AT>(e.P, ks[j], (u64)c);
+                            }
+                            bool last;
+                            const AT ssum = seg_sum_last(c, is[j], last);
+                            if (last && ssum) atomicAdd(&sb[is[j]], ssum);
+                        }
                     }
                 }
                 grp_sync<T>();
                 if (s < re && sb[tid]) acc_add<AT>(e.P, s2k[s], (u64)sb[tid]);
                 grp_sync<T>();
+                qb += tot;
             }
         }
         grp_sync<T>();
@@ -1207,24 +1257,48 @@ static void launch_gather_blk(const Dev& d, const int* lst, int c, int smax, hip
                            d.ocol, d.ndeg, d.e, (u64*)d.gscratch, d.trec, d.toff, d.tcnt);
 }
 
-template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16 = false>
+template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16 = false, int CAP = 0>
 static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st) {
     if (cnt <= 0) return;
     const int limit = d.wedge_limit < HT / 2 ? d.wedge_limit : HT / 2;
-    hipLaunchKernelGGL((k_wedge<PE, AT, T, G, HT, DW, P16>), dim3(cdiv(cnt, G)), dim3(T * G), 0, st,
+    hipLaunchKernelGGL((k_wedge<PE, AT, T, G, HT, DW, P16, CAP>), dim3(cdiv(cnt, G)), dim3(T * G), 0, st,
                        d.wlist + (int64_t)bkt * d.n, cnt, d.n, limit, d.wedge_dense, d.nrp, d.ncol, d.optr, d.ocol,
-                       d.s2k, d.e, d.gsum, d.ngid, d.gvb, d.err);
+                       d.s2k, d.wcnt, d.e, d.gsum, d.ngid, d.gvb, d.err);
 }
 
-// The wedge pass runs on a side stream, concurrently with the triangle and gather passes
-// (they share only read-only inputs and distinct accumulators); both join before the vertex
-// pass and the combine.  Events (all recorded, also used to fork and join):
+// With `overlap` the wedge pass runs on a side stream, concurrently with the triangle and
+// gather passes (they share only read-only inputs and distinct accumulators); both join
+// before the vertex pass and the combine.  Otherwise it follows the gather pass on the same
+// stream.  Events (all recorded, also used to fork and join):
 //   ev[1] end of preprocessing (fork)     ev[2..5] after tri wave / tri wg / gather wave / gather wg
 //   ev[6] after the wedge wave+mid classes, ev[7] after the workgroup classes (side stream)
 //   ev[8] after the join                  ev[9] after the combine
+// Wedge pass: wave and mid classes (one wavefront per bottom vertex), then the huge and
+// workgroup classes; ev[6] and ev[7] mark the two halves on stream s.
+template <typename AT>
+static void wedge_pass(const Dev& d, int per_edge, const int* hc, hipStream_t s, hipEvent_t* ev) {
+    const int* wc = hc + TB_N;
+    if (per_edge) {
+        launch_wedge<true, AT, WW_T, WW_G, WW_HT, 0, false, WW_CAP>(d, WB_WAVE, wc[WB_WAVE], s);
+        launch_wedge<true, AT, WM_T, WM_G, WM_HT, WM_DW, true, WM_CAP>(d, WB_MID, wc[WB_MID], s);
+    } else {
+        launch_wedge<false, AT, WW_T, WW_G, WW_HT, 0>(d, WB_WAVE, wc[WB_WAVE], s);
+        launch_wedge<false, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, WB_MID, wc[WB_MID], s);
+    }
+    (void)hipEventRecord(ev[6], s);
+    if (per_edge) {
+        launch_wedge<true, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], s);
+        launch_wedge<true, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s);
+    } else {
+        launch_wedge<false, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], s);
+        launch_wedge<false, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s);
+    }
+    (void)hipEventRecord(ev[7], s);
+}
+
 template <typename AT>
 static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st, hipStream_t side,
-                         hipEvent_t* ev) {
+                         hipEvent_t* ev, bool overlap) {
     const int n = d.n, m = d.m;
     u64* gsum = d.gsum;                   // [graph][NSUMS]: 3 x 4-cliques and non-induced 4-cycles
     launch_fill<u64>(gsum, (int64_t)(d.ngraphs > 0 ? d.ngraphs : GSPREAD) * NSUMS, 0ull, st);
@@ -1234,26 +1308,11 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
     for (int bkt = TB_BLK1; bkt <= TB_GLOBAL; bkt++) sort_heaviest_first(d, d.tlist + (int64_t)bkt * n, cnt[bkt], 1, st);
     for (int bkt = WB_MID; bkt <= WB_HUGE; bkt++) sort_heaviest_first(d, d.wlist + (int64_t)bkt * n, hc[TB_N + bkt], 0, st);
     (void)hipEventRecord(ev[1], st);
-    // wedge pass (side stream): wave and mid classes (one wavefront per bottom vertex), then
-    // the huge and workgroup classes
-    (void)hipStreamWaitEvent(side, ev[1], 0);
-    const int* wc = hc + TB_N;
-    if (per_edge) {
-        launch_wedge<true, AT, WW_T, WW_G, WW_HT, 0>(d, WB_WAVE, wc[WB_WAVE], side);
-        launch_wedge<true, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, WB_MID, wc[WB_MID], side);
-    } else {
-        launch_wedge<false, AT, WW_T, WW_G, WW_HT, 0>(d, WB_WAVE, wc[WB_WAVE], side);
-        launch_wedge<false, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, WB_MID, wc[WB_MID], side);
+    if (overlap) {
+        // the wedge pass on the side stream, beside the triangle and gather passes
+        (void)hipStreamWaitEvent(side, ev[1], 0);
+        wedge_pass<AT>(d, per_edge, hc, side, ev);
     }
-    (void)hipEventRecord(ev[6], side);
-    if (per_edge) {
-        launch_wedge<true, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], side);
-        launch_wedge<true, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], side);
-    } else {
-        launch_wedge<false, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], side);
-        launch_wedge<false, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], side);
-    }
-    (void)hipEventRecord(ev[7], side);
     // triangle / 4-clique pass
     if (cnt[TB_WAVE] > 0) {
         if (per_edge) launch_tri_wave<true, AT>(d, tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], st);
@@ -1318,8 +1377,8 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
         }
     }
     (void)hipEventRecord(ev[5], st);
-    // join the wedge pass
-    (void)hipStreamWaitEvent(st, ev[7], 0);
+    if (overlap) (void)hipStreamWaitEvent(st, ev[7], 0);   // join the wedge pass
+    else wedge_pass<AT>(d, per_edge, hc, st, ev);
     (void)hipEventRecord(ev[8], st);
     // vertex pass + combine
     if (per_edge && n > 0 && m > 0) {
@@ -1348,11 +1407,11 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
 }
 
 void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st, hipStream_t side,
-                      hipEvent_t* ev) {
+                      hipEvent_t* ev, int overlap) {
     if (d.acc32)
-        count_passes<u32>(d, per_edge, hc, out_pe, st, side, ev);
+        count_passes<u32>(d, per_edge, hc, out_pe, st, side, ev, overlap != 0);
     else
-        count_passes<u64>(d, per_edge, hc, out_pe, st, side, ev);
+        count_passes<u64>(d, per_edge, hc, out_pe, st, side, ev, overlap != 0);
 }
 
 int glt_combine_blocks(int m) { return combine_blocks(m); }

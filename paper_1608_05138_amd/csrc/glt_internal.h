@@ -134,4 +134,5 @@ int glt_prep_validate(const Dev& d, const void* rp, int rp64, const int* col, hi
 int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipStream_t st,
                    const int* vinfo /* max degree, then RS_N row-class counts */);
 void glt_count_passes(const Dev& d, int per_edge, const int* host_counts, u64* out_pe,
-                      hipStream_t st, hipStream_t side, hipEvent_t* ev /* NEV events, ev[0] recorded by the caller */);
+                      hipStream_t st, hipStream_t side, hipEvent_t* ev /* NEV events, ev[0] recorded by the caller */,
+                      int overlap /* wedge pass on `side`, beside the triangle passes */);

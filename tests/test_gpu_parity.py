@@ -202,11 +202,13 @@ def test_forced_classes_and_range_splitting(monkeypatch, case):
 
 def test_triangle_records_on_and_off(monkeypatch, ctx):
     """The triangle and gather passes walk stored triangle records when the record buffer
-    fits, and re-scan the out-lists when records are switched off; both must agree with each
-    other and with the oracle on the wave, LDS-bitmap and global-bitmap paths."""
+    fits, and re-scan the out-lists when records are switched off (here also with the 4-cycle
+    pass on one stream instead of beside them); both must agree with each other and with the
+    oracle on the wave, LDS-bitmap and global-bitmap paths."""
     import paper_1608_05138_amd as glt
     monkeypatch.setenv("GLT_TRI_RECORD_BYTES", "0")
     off = glt.Context(0)
+    off.set_schedule(wedge_stream=0)   # and the 4-cycle pass on the same stream
     try:
         rng = np.random.default_rng(5)
         n = 2300
