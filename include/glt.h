@@ -159,7 +159,7 @@ int glt_last_work(const glt_ctx* ctx, uint64_t* out, int cap);
  * Work schedule of a handle: how the counting passes split their work among size classes
  * (Section 4.3 splits edges by cost between workers; here vertices are split by their work
  * between wavefront and workgroup kernels).  Every schedule yields the same counts; only
- * the speed differs.  Defaults: 256, 2048, 16384, 4096, 1, 65536, 1.
+ * the speed differs.  Defaults: 128, 2048, 16384, 4096, 1, 2^30, 1.
  */
 typedef struct {
     int32_t wedge_wave_max;    /* 4-cycle pass: bottom vertices with at most this many wedges
@@ -172,8 +172,9 @@ typedef struct {
                                   each class caps it at half its hash: 256, 512, 1024, 4096)  */
     int32_t tri_records;       /* 1: store each triangle once for the 4-clique sweep and the
                                   gather pass when the record buffer fits; 0: re-scan lists  */
-    int32_t wedge_wg_max;      /* up to this many: one per 256-thread workgroup; more: one per
-                                  1024-thread workgroup with the largest tables (>= 0)        */
+    int32_t wedge_wg_max;      /* up to this many: one per 256-thread workgroup, moving to the
+                                  1024-thread class with the largest tables if its distinct
+                                  tops overflow the workgroup's tables; more: straight there */
     int32_t wedge_stream;      /* 1: the 4-cycle pass runs on a second stream beside the
                                   triangle and gather passes; 0: after them on one stream     */
     int32_t reserved;          /* must be 0                                                  */

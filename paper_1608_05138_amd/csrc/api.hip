@@ -37,6 +37,7 @@ struct glt_ctx {
     int wedge_wave_max = 0;
     int wedge_mid_max = 0;
     int wedge_wg_max = 0;
+    int num_cu = 256;
     int wedge_limit = 0;
     int wedge_dense = 0;
     uint64_t work[2 + NWORK] = {};     // n, m, then the device work counters
@@ -308,6 +309,7 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
     d.wedge_wave_max = ctx->wedge_wave_max;
     d.wedge_mid_max = ctx->wedge_mid_max;
     d.wedge_wg_max = ctx->wedge_wg_max;
+    d.num_cu = ctx->num_cu;
     d.wedge_limit = ctx->wedge_limit;
     d.wedge_dense = ctx->wedge_dense;
     HIPCHK(hipEventRecord(ctx->ev[0], st));
@@ -434,20 +436,20 @@ glt_status glt_create(int device, size_t hbm_budget_bytes, glt_ctx** out) {
     if (!ctx) return GLT_E_OOM;
     ctx->device = device;
     ctx->budget = hbm_budget_bytes;
-    // work-split thresholds; the environment may lower them (used by tests to force the
-    // workgroup path and range splitting on small graphs)
-    ctx->wedge_wave_max = glt_wave_table() / 2;
+    // default schedule; the environment may change it within the same ranges as
+    // glt_set_schedule (used by tests to force classes and range splitting on small graphs)
+    ctx->wedge_wave_max = 128;   // (<= glt_wave_table() / 2; 128 measured best on the Chung-Lu graph)
     ctx->wedge_limit = glt_wedge_table() / 2;
     if (const char* e = getenv("GLT_WEDGE_WAVE_MAX")) {
         int v = atoi(e);
-        if (v >= 0 && v < ctx->wedge_wave_max) ctx->wedge_wave_max = v;
+        if (v >= 0 && v <= glt_wave_table() / 2) ctx->wedge_wave_max = v;
     }
     ctx->wedge_mid_max = 2048;
     if (const char* e = getenv("GLT_WEDGE_MID_MAX")) {
         int v = atoi(e);
         if (v >= 0) ctx->wedge_mid_max = v;
     }
-    ctx->wedge_wg_max = 65536;
+    ctx->wedge_wg_max = 1 << 30;   // bottoms move to the huge class when their tops overflow
     if (const char* e = getenv("GLT_WEDGE_WG_MAX")) {
         int v = atoi(e);
         if (v >= 0) ctx->wedge_wg_max = v;
@@ -465,6 +467,11 @@ glt_status glt_create(int device, size_t hbm_budget_bytes, glt_ctx** out) {
     if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
         delete ctx;
         return GLT_E_DEVICE;
+    }
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+            ctx->num_cu = cus;
     }
     {
         // triangle records may take up to a quarter of the device's memory (0 disables them)

@@ -701,7 +701,9 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                                                  const int* __restrict__ ocol, const int* __restrict__ s2k,
                                                  const u64* __restrict__ wcnt, EdgeArrays e,
                                                  u64* __restrict__ gsum, const int* __restrict__ ngid,
-                                                 const int64_t* __restrict__ gvb, int* __restrict__ err) {
+                                                 const int64_t* __restrict__ gvb, int* __restrict__ err,
+                                                 const int* __restrict__ dcount, int* __restrict__ defer_list,
+                                                 int* __restrict__ defer_cnt) {
     static_assert(T == GLT_WAVE || G == 1, "multi-wave groups own the whole block");
     static_assert(HT % 4 == 0 && DW % 4 == 0 && (HT & (HT - 1)) == 0, "table sizes");
     static_assert(DW + HT <= 65536, "table slots fit 16 bits");
@@ -720,9 +722,15 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
     __shared__ int s_lo[G][WEDGE_STACK], s_hi[G][WEDGE_STACK];
     __shared__ int s_sp[G], s_dist[G], s_ovf[G];
     const int g = threadIdx.x / T, tid = threadIdx.x % T;
-    const int idx = blockIdx.x * G + g;
-    if (idx >= nlist) return;   // whole groups leave together (G == 1 when T > one wave)
-    const int y = list[idx];
+    // one list entry per group, or (dcount given) a resident grid walking a list whose length
+    // a previous launch settled on the device
+    const int first = blockIdx.x * G + g;
+    const int count = dcount ? *dcount : nlist;
+    const int stride = dcount ? (int)gridDim.x * G : count;
+    if (first >= count) return;   // whole groups leave together (G == 1 when T > one wave)
+    for (int item = first; item < count; item += stride) {
+    grp_sync<T>();   // the previous entry's last reads of the group's LDS are done
+    const int y = list[item];
     const int rb = nrp[y], re = nrp[y + 1];
     // tops lie above y inside y's graph: a batch keeps each graph's ranks contiguous
     const int top = ngid ? (int)gvb[ngid[y] + 1] : n;
@@ -819,6 +827,13 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
             grp_sync<T>();
         }
         if (s_ovf[g]) {
+            if (defer_cnt && full) {
+                // too many distinct tops for this class: y moves, uncredited, to the list of
+                // the class with the largest tables
+                if (tid == 0) defer_list[atomicAdd(defer_cnt, 1)] = y;
+                grp_sync<T>();
+                break;
+            }
             if (tid == 0) {
                 if (sp + 1 <= WEDGE_STACK && hi - lo >= 2) {
                     const int mid = lo + (hi - lo) / 2;
@@ -916,6 +931,7 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
     }
     c4 = wave_sum(c4);
     if (glt_lane() == 0 && c4) atomicAdd(&gsum[gslot(ngid, y) * NSUMS + S_NC4], c4);
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1257,13 +1273,19 @@ static void launch_gather_blk(const Dev& d, const int* lst, int c, int smax, hip
                            d.ocol, d.ndeg, d.e, (u64*)d.gscratch, d.trec, d.toff, d.tcnt);
 }
 
+// One group per list entry (grid from the host's count), or, with `resident` blocks, a grid
+// that walks the list up to the device count at `dcount`; `defer` > 0 lets overflowing
+// entries move to the list of class `defer`.
 template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16 = false, int CAP = 0>
-static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st) {
-    if (cnt <= 0) return;
+static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st, int resident = 0, int defer = -1) {
+    if (cnt <= 0 && resident <= 0) return;
     const int limit = d.wedge_limit < HT / 2 ? d.wedge_limit : HT / 2;
-    hipLaunchKernelGGL((k_wedge<PE, AT, T, G, HT, DW, P16, CAP>), dim3(cdiv(cnt, G)), dim3(T * G), 0, st,
+    int* counts = d.counts + TB_N;
+    const unsigned grid = resident > 0 ? (unsigned)resident : cdiv(cnt, G);
+    hipLaunchKernelGGL((k_wedge<PE, AT, T, G, HT, DW, P16, CAP>), dim3(grid), dim3(T * G), 0, st,
                        d.wlist + (int64_t)bkt * d.n, cnt, d.n, limit, d.wedge_dense, d.nrp, d.ncol, d.optr, d.ocol,
-                       d.s2k, d.wcnt, d.e, d.gsum, d.ngid, d.gvb, d.err);
+                       d.s2k, d.wcnt, d.e, d.gsum, d.ngid, d.gvb, d.err, resident > 0 ? counts + bkt : nullptr,
+                       defer >= 0 ? d.wlist + (int64_t)defer * d.n : nullptr, defer >= 0 ? counts + defer : nullptr);
 }
 
 // With `overlap` the wedge pass runs on a side stream, concurrently with the triangle and
@@ -1286,12 +1308,15 @@ static void wedge_pass(const Dev& d, int per_edge, const int* hc, hipStream_t s,
         launch_wedge<false, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, WB_MID, wc[WB_MID], s);
     }
     (void)hipEventRecord(ev[6], s);
+    // workgroup class first: its bottoms whose tops overflow its tables join the huge list,
+    // which one resident workgroup per CU then walks
+    const int huge_grid = (wc[WB_BLK] + wc[WB_HUGE] > 0) ? d.num_cu : 0;
     if (per_edge) {
-        launch_wedge<true, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], s);
-        launch_wedge<true, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s);
+        launch_wedge<true, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
+        launch_wedge<true, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], s, huge_grid);
     } else {
-        launch_wedge<false, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], s);
-        launch_wedge<false, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s);
+        launch_wedge<false, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
+        launch_wedge<false, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], s, huge_grid);
     }
     (void)hipEventRecord(ev[7], s);
 }

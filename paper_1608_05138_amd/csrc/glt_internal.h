@@ -121,6 +121,7 @@ struct Dev {
     int wedge_wave_max;   // wedge-pass vertices with at most this many wedges: wave class (hash only)
     int wedge_mid_max;    // up to this many: mid class (one wavefront, dense window + hash)
     int wedge_wg_max;     // up to this many: workgroup class; more: huge class (1024 threads, big tables)
+    int num_cu;           // compute units (resident grid of the huge class)
     int wedge_limit;      // distinct hashed tops per range before the range is split
     int wedge_dense;      // width of the dense window of highest-ranked tops
     int acc32;            // per-edge accumulators fit 32 bits (maximum degree <= 46340)
