@@ -28,10 +28,11 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # source with the hash below and are reported only while it is unchanged.
 TRAFFIC = {
     "source": "paper_1608_05138_amd/csrc/count.hip",
-    "sha256": "a351f08c094660544f995729ea601d74cc711d1c7d6725863fd0b4e4dbe3d59e",
+    "sha256": "7944400a8cc737fd1c130540f05f3560d02bdc2307f6728633d89ce49950bbd8",
     "workload": "chung_lu_1m", "per_edge": True,
-    "bytes": {"tri_wave": 3676166496, "tri_wg": 4328773920, "gather_wave": 2080813952,
-              "gather_wg": 3374473216, "wedge_wave": 3967000032, "wedge_wg": 10492788064},
+    "bytes": {"tri_wave": 3670049408, "tri_wg": 4390950784, "gather_wave": 1886630784,
+              "gather_wg": 3390846464, "wedge_wave": 99581376, "wedge_mid": 3898080288,
+              "wedge_wg": 10287631712, "wedge_huge": 38912},
 }
 
 
@@ -56,8 +57,10 @@ WORKLOADS = {
 
 # kernel groups timed by the library (HIP events on the call's stream) and their kernels
 GROUPS = {"tri_wave": "k_tri_wave", "tri_wg": "k_tri_blk", "gather_wave": "k_gather_wave",
-          "gather_wg": "k_gather_blk", "wedge_wave": "k_wedge (wave and mid classes, 64-thread groups)",
-          "wedge_wg": "k_wedge (workgroup class, 256-thread groups)"}
+          "gather_wg": "k_gather_blk", "wedge_wave": "k_wedge (wave class: 64 threads, 4 per block)",
+          "wedge_mid": "k_wedge (mid class: 64 threads, 2 per block)",
+          "wedge_wg": "k_wedge (workgroup class: 256 threads)",
+          "wedge_huge": "k_wedge (huge class: 1024 threads, one resident per CU)"}
 
 
 def _gen_batch_graph(spec):
@@ -277,26 +280,35 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
-def group_bytes(work, per_edge, acc_bytes):
-    """Algorithmic bytes of each counting kernel group (section Measurement):
-    per triangle-pass list entry one 4 B id; per triangle a 4 B triangle credit plus (per-edge
-    mode) one 4-clique credit; per triangle in the gather pass two credits; per wedge one 4 B
-    top id plus (per-edge mode) one 4-cycle credit.  Credits are acc_bytes wide."""
+def group_bytes(work, per_edge, acc_bytes, records=True):
+    """Algorithmic bytes of each counting kernel group (section Measurement).
+    Triangle pass: one 4 B id per out-list entry scanned, and per triangle its 4 B triangle
+    credit plus (per-edge mode) one 4-clique credit, plus, with triangle records, the 8 B
+    record written and read back.  Gather pass: per triangle its record (or, without records,
+    the re-scanned list entries), the three 4 B triangle counts and two credits.  Wedge pass:
+    per wedge one 4 B top id plus (per-edge mode) one 4-cycle credit.  Credits are acc_bytes
+    wide."""
     ab = acc_bytes
+    rec = 16 if records else 0
+    wb = 4 + (ab if per_edge else 0)
+    tb = 4 + (ab if per_edge else 0) + rec
     out = {
-        "tri_wave": 4 * work["tri_list_wave"] + (4 + (ab if per_edge else 0)) * work["triangles_wave"],
-        "tri_wg": 4 * work["tri_list_wg"] + (4 + (ab if per_edge else 0)) * work["triangles_wg"],
-        "wedge_wave": (4 + (ab if per_edge else 0)) * work["wedges_wave"],
-        "wedge_wg": (4 + (ab if per_edge else 0)) * work["wedges_wg"],
+        "tri_wave": 4 * work["tri_list_wave"] + tb * work["triangles_wave"],
+        "tri_wg": 4 * work["tri_list_wg"] + tb * work["triangles_wg"],
+        "wedge_wave": wb * work["wedges_wave"],
+        "wedge_mid": wb * work["wedges_mid"],
+        "wedge_wg": wb * work["wedges_wg"],
+        "wedge_huge": wb * work["wedges_huge"],
     }
     if per_edge:
-        out["gather_wave"] = 4 * work["tri_list_wave"] + 2 * ab * work["triangles_wave"]
-        out["gather_wg"] = 4 * work["tri_list_wg"] + 2 * ab * work["triangles_wg"]
+        for path in ("wave", "wg"):
+            scan = 8 * work["triangles_" + path] if records else 4 * work["tri_list_" + path]
+            out["gather_" + path] = scan + (12 + 2 * ab) * work["triangles_" + path]
     return out
 
 
-def roofline(timing, work, per_edge, acc_bytes, workload=None):
-    gb = group_bytes(work, per_edge, acc_bytes)
+def roofline(timing, work, per_edge, acc_bytes, workload=None, records=True):
+    gb = group_bytes(work, per_edge, acc_bytes, records)
     dom = max(gb, key=lambda g: timing[g])
     achieved = gb[dom] / (timing[dom] * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": GROUPS[dom], "group": dom, "achieved": round(achieved, 1),
@@ -357,6 +369,8 @@ def main():
     ap.add_argument("--pool-large", type=int, default=64, help="served: pool of large request graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--global-only", action="store_true", help="skip per-edge output")
+    ap.add_argument("--order-study", action="store_true",
+                    help="also time each order of the workgroup work lists (reported as order_study)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES, 3 times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters against a known traffic)")
@@ -417,7 +431,25 @@ def main():
           ", ".join(f"{k}={v:.3f}" for k, v in timing.items()), file=sys.stderr, flush=True)
 
     maxdeg = int(np.diff(rp.astype(np.int64)).max()) if n else 0
-    roof = roofline(timing, work, per_edge, acc_width(maxdeg), args.workload)
+    roof = roofline(timing, work, per_edge, acc_width(maxdeg), args.workload, bool(ctx.schedule()["tri_records"]))
+    study = None
+    if args.order_study:
+        # the ordering study (Section 4.3, Table 4) on the same graph: step time per order of the
+        # workgroup work lists, each after one warm-up step
+        names = ["largest work first", "largest degree first", "ascending rank", "pseudo-random"]
+        study = {}
+        for order, name in enumerate(names):
+            ctx.set_schedule(list_order=order)
+            ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                Xo, _ = ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
+            torch.cuda.synchronize()
+            study[name] = round((time.perf_counter() - t0) * 1e3 / args.steps, 3)
+            assert Xo == X, "list order changed the counts"
+        ctx.set_schedule(list_order=0)
+        print(f"[bench] ordering study (ms/step): {study}", file=sys.stderr, flush=True)
     line = {
         "metric": "edges/sec for exact 4-node motif counts (1 GPU)",
         "value": m / (ms_per_step * 1e-3),
@@ -432,6 +464,7 @@ def main():
         "kernel_groups_ms": {k: round(float(v), 4) for k, v in timing.items()},
         "work": work,
         "roofline": roof,
+        **({"order_study_ms_per_step": study} if study else {}),
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on a bounded sample", file=sys.stderr, flush=True)

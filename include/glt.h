@@ -133,25 +133,26 @@ glt_status glt_count_batch(glt_ctx* ctx, const glt_batch* b, uint32_t flags, glt
 
 /*
  * Timing breakdown of the last successful glt_count or glt_count_batch on this handle, in
- * milliseconds measured with HIP events, one entry per kernel group:
+ * milliseconds measured with HIP events, one entry per kernel group (each one kernel, the
+ * workgroup triangle and gather groups one kernel per out-degree bucket):
  * [0] validation + preprocessing (degree order, sorted oriented CSR, work lists),
  * [1] triangle / 4-clique pass, one wavefront per vertex, [2] the same, one workgroup per
  * vertex, [3] per-edge gather pass, wavefront path, [4] the same, workgroup path,
- * [5] 4-cycle wedge pass, wavefront classes, [6] the same, workgroup classes, [7] vertex
- * sums, combine and reduction, [8] the whole call.  The wedge pass runs on a second stream
- * beside entries [1]-[4], so the entries do not add up to [8].  Returns the number of
- * entries written (<= cap, at most 9).
+ * [5]-[8] 4-cycle wedge pass, wave / mid / workgroup / huge class, [9] vertex sums, combine
+ * and reduction, [10] the whole call.  With the schedule's wedge_stream = 1 the wedge pass
+ * runs on a second stream beside entries [1]-[4], and the entries then overlap.  Returns the number of
+ * entries written (<= cap, at most 11).
  */
 int glt_last_timing(const glt_ctx* ctx, float* ms, int cap);
 
 /*
  * Work counters of the last successful glt_count or glt_count_batch on this handle:
  * [0] n, [1] m, [2] wedges y - w - x (x ranked above y and w; the 4-cycle pass's unit of
- * work) handled by the wavefront path, [3] the same by the workgroup path, [4] out-list
- * entries scanned by the triangle pass (sum over oriented edges (a,b) of |N+(b)|), wavefront
- * path, [5] the same, workgroup path, [6] triangles found by the wavefront path, [7] by the
- * workgroup path.  Returns the number of entries written (<= cap, at most 8).  Used to state
- * the algorithmic bytes of each kernel group.
+ * work) counted by the wave class, [3] by the workgroup class, [4] out-list entries scanned
+ * by the triangle pass (sum over oriented edges (a,b) of |N+(b)|), wavefront path, [5] the
+ * same, workgroup path, [6] triangles found by the wavefront path, [7] by the workgroup
+ * path, [8] wedges of the mid class, [9] of the huge class.  Returns the number of entries
+ * written (<= cap, at most 10).  Used to state the algorithmic bytes of each kernel group.
  */
 int glt_last_work(const glt_ctx* ctx, uint64_t* out, int cap);
 
@@ -159,7 +160,7 @@ int glt_last_work(const glt_ctx* ctx, uint64_t* out, int cap);
  * Work schedule of a handle: how the counting passes split their work among size classes
  * (Section 4.3 splits edges by cost between workers; here vertices are split by their work
  * between wavefront and workgroup kernels).  Every schedule yields the same counts; only
- * the speed differs.  Defaults: 128, 2048, 16384, 4096, 1, 2^30, 1.
+ * the speed differs.  Defaults: 128, 2048, 16384, 4096, 1, 2^30, 0, 0.
  */
 typedef struct {
     int32_t wedge_wave_max;    /* 4-cycle pass: bottom vertices with at most this many wedges
@@ -177,7 +178,9 @@ typedef struct {
                                   tops overflow the workgroup's tables; more: straight there */
     int32_t wedge_stream;      /* 1: the 4-cycle pass runs on a second stream beside the
                                   triangle and gather passes; 0: after them on one stream     */
-    int32_t reserved;          /* must be 0                                                  */
+    int32_t list_order;        /* order of the workgroup work lists (Section 4.3's edge order,
+                                  Table 4's ordering study): 0 largest work first, 1 largest
+                                  degree first, 2 ascending rank, 3 pseudo-random            */
 } glt_schedule;
 
 /* The handle's current schedule. */

@@ -68,11 +68,11 @@ class glt_schedule(ctypes.Structure):
     _fields_ = [("wedge_wave_max", ctypes.c_int32), ("wedge_mid_max", ctypes.c_int32),
                 ("wedge_dense", ctypes.c_int32), ("wedge_range_limit", ctypes.c_int32),
                 ("tri_records", ctypes.c_int32), ("wedge_wg_max", ctypes.c_int32),
-                ("wedge_stream", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("wedge_stream", ctypes.c_int32), ("list_order", ctypes.c_int32)]
 
 
 SCHEDULE_KEYS = ["wedge_wave_max", "wedge_mid_max", "wedge_dense", "wedge_range_limit", "tri_records",
-                 "wedge_wg_max", "wedge_stream"]
+                 "wedge_wg_max", "wedge_stream", "list_order"]
 
 
 class glt_server_opts(ctypes.Structure):
@@ -173,10 +173,10 @@ class Context:
     def last_error(self) -> str:
         return self._lib.glt_last_error(self._h).decode()
 
-    TIMING_KEYS = ["prep", "tri_wave", "tri_wg", "gather_wave", "gather_wg", "wedge_wave", "wedge_wg",
-                   "combine", "total"]
+    TIMING_KEYS = ["prep", "tri_wave", "tri_wg", "gather_wave", "gather_wg", "wedge_wave", "wedge_mid",
+                   "wedge_wg", "wedge_huge", "combine", "total"]
     WORK_KEYS = ["n", "m", "wedges_wave", "wedges_wg", "tri_list_wave", "tri_list_wg", "triangles_wave",
-                 "triangles_wg"]
+                 "triangles_wg", "wedges_mid", "wedges_huge"]
 
     def last_timing(self):
         """dict of kernel-group times (ms) of the last count (HIP events; the wedge groups run
@@ -187,8 +187,8 @@ class Context:
 
     def last_work(self):
         """dict of work counters of the last count."""
-        buf = (ctypes.c_uint64 * 8)()
-        k = self._lib.glt_last_work(self._h, buf, 8)
+        buf = (ctypes.c_uint64 * len(self.WORK_KEYS))()
+        k = self._lib.glt_last_work(self._h, buf, len(self.WORK_KEYS))
         return {name: int(buf[i]) for i, name in enumerate(self.WORK_KEYS[:k])}
 
     def count(self, row_ptr, col, n: int | None = None, per_edge: bool = False, out=None,

@@ -47,8 +47,10 @@ struct glt_ctx {
     size_t trec_bytes = 0;
     size_t trec_cap = 0;               // largest record buffer the handle allocates
     int tri_records = 1;               // schedule: use triangle records when they fit
-    int wedge_stream = 1;              // schedule: wedge pass on the side stream
-    int last_overlap = 1;              // the mode the last call's timing was taken in
+    int wedge_stream = 0;              // schedule: wedge pass on the side stream (off: each kernel
+                                       // group then has the chip alone and is timed cleanly)
+    int list_order = 0;                // schedule: order of the workgroup work lists (LO_*)
+    int last_overlap = 0;              // the mode the last call's timing was taken in
     void* slab = nullptr;              // larger global slab for the highest out-degrees (grown on demand)
     size_t slab_bytes = 0;
 };
@@ -310,6 +312,7 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
     d.wedge_mid_max = ctx->wedge_mid_max;
     d.wedge_wg_max = ctx->wedge_wg_max;
     d.num_cu = ctx->num_cu;
+    d.list_order = ctx->list_order;
     d.wedge_limit = ctx->wedge_limit;
     d.wedge_dense = ctx->wedge_dense;
     HIPCHK(hipEventRecord(ctx->ev[0], st));
@@ -355,7 +358,8 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
 // Kernel groups as (begin, end) events; the wedge groups (side stream) overlap the
 // triangle and gather groups, so the groups do not add up to the total.
 void record_timing(glt_ctx* ctx) {
-    static const int be[NSEG][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {1, 6}, {6, 7}, {8, 9}, {0, 9}};
+    static const int be[NSEG][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {1, 6},
+                                    {6, 7}, {7, 8}, {8, 9}, {10, 11}, {0, 11}};
     for (int i = 0; i < NSEG; i++) {
         int b0 = be[i][0];
         if (i == 5 && !ctx->last_overlap) b0 = 5;   // one stream: the wedge pass follows the gather pass
@@ -666,6 +670,7 @@ glt_status glt_get_schedule(const glt_ctx* ctx, glt_schedule* out) {
     out->wedge_mid_max = ctx->wedge_mid_max;
     out->wedge_wg_max = ctx->wedge_wg_max;
     out->wedge_stream = ctx->wedge_stream;
+    out->list_order = ctx->list_order;
     out->wedge_dense = ctx->wedge_dense;
     out->wedge_range_limit = ctx->wedge_limit;
     out->tri_records = ctx->tri_records;
@@ -686,7 +691,7 @@ glt_status glt_set_schedule(glt_ctx* ctx, const glt_schedule* s) {
         return fail(ctx, GLT_E_INVALID_ARG, "wedge_range_limit must be in [1, %d]", glt_wedge_table() / 2);
     if (s->tri_records != 0 && s->tri_records != 1) return fail(ctx, GLT_E_INVALID_ARG, "tri_records must be 0 or 1");
     if (s->wedge_stream != 0 && s->wedge_stream != 1) return fail(ctx, GLT_E_INVALID_ARG, "wedge_stream must be 0 or 1");
-    if (s->reserved) return fail(ctx, GLT_E_INVALID_ARG, "reserved field must be 0");
+    if (s->list_order < 0 || s->list_order > 3) return fail(ctx, GLT_E_INVALID_ARG, "list_order must be in [0, 3]");
     ctx->wedge_wave_max = s->wedge_wave_max;
     ctx->wedge_mid_max = s->wedge_mid_max;
     ctx->wedge_wg_max = s->wedge_wg_max;
@@ -694,6 +699,7 @@ glt_status glt_set_schedule(glt_ctx* ctx, const glt_schedule* s) {
     ctx->wedge_limit = s->wedge_range_limit;
     ctx->tri_records = s->tri_records;
     ctx->wedge_stream = s->wedge_stream;
+    ctx->list_order = s->list_order;
     return GLT_OK;
 }
 

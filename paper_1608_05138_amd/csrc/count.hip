@@ -703,7 +703,7 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                                                  u64* __restrict__ gsum, const int* __restrict__ ngid,
                                                  const int64_t* __restrict__ gvb, int* __restrict__ err,
                                                  const int* __restrict__ dcount, int* __restrict__ defer_list,
-                                                 int* __restrict__ defer_cnt) {
+                                                 int* __restrict__ defer_cnt, u64* __restrict__ defer_work) {
     static_assert(T == GLT_WAVE || G == 1, "multi-wave groups own the whole block");
     static_assert(HT % 4 == 0 && DW % 4 == 0 && (HT & (HT - 1)) == 0, "table sizes");
     static_assert(DW + HT <= 65536, "table slots fit 16 bits");
@@ -830,7 +830,10 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
             if (defer_cnt && full) {
                 // too many distinct tops for this class: y moves, uncredited, to the list of
                 // the class with the largest tables
-                if (tid == 0) defer_list[atomicAdd(defer_cnt, 1)] = y;
+                if (tid == 0) {
+                    defer_list[atomicAdd(defer_cnt, 1)] = y;
+                    if (defer_work) atomicAdd(defer_work, wcnt[y]);   // wedges that changed class
+                }
                 grp_sync<T>();
                 break;
             }
@@ -1172,13 +1175,22 @@ __device__ __forceinline__ u32 work_code(u64 w) {
     return 256u + (u32)(ex - 8) * 128u + (top - 128u);  // < 7424
 }
 
-__global__ void k_work_keys(const int* __restrict__ list, int nlist, int mode, const u64* __restrict__ wcnt,
-                            const int* __restrict__ optr, u64* __restrict__ keys, u32* __restrict__ vals) {
+// order: LO_WORK sorts by the work (mode 0: wedges of y, mode 1: out-degree of x), LO_DEGREE
+// by the vertex's degree, both largest first; LO_RANDOM by a hash of the vertex.
+__global__ void k_work_keys(const int* __restrict__ list, int nlist, int mode, int order,
+                            const u64* __restrict__ wcnt, const int* __restrict__ optr,
+                            const int* __restrict__ ndeg, u64* __restrict__ keys, u32* __restrict__ vals) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nlist) return;
     const int x = list[i];
-    const u64 w = mode == 0 ? wcnt[x] : (u64)(optr[x + 1] - optr[x]);
-    keys[i] = (u64)(0xffffu - work_code(w));   // ascending sort = heaviest first
+    u32 key;
+    if (order == LO_RANDOM) {
+        key = ((u32)x * 2654435761u) >> 16;
+    } else {
+        const u64 w = order == LO_DEGREE ? (u64)ndeg[x] : mode == 0 ? wcnt[x] : (u64)(optr[x + 1] - optr[x]);
+        key = 0xffffu - work_code(w);   // ascending sort = largest first
+    }
+    keys[i] = (u64)key;
     vals[i] = (u32)x;
 }
 
@@ -1188,9 +1200,10 @@ __global__ void k_copy_list(const u32* __restrict__ vals, int nlist, int* __rest
 }
 
 static void sort_heaviest_first(const Dev& d, int* list, int nlist, int mode, hipStream_t st) {
-    if (nlist < 2) return;
+    if (nlist < 2 || d.list_order == LO_NONE) return;   // LO_NONE: the bucketing order (ascending rank)
     const unsigned g = (unsigned)((nlist + 255) / 256);
-    hipLaunchKernelGGL(k_work_keys, dim3(g), dim3(256), 0, st, list, nlist, mode, d.wcnt, d.optr, d.key0, d.val0);
+    hipLaunchKernelGGL(k_work_keys, dim3(g), dim3(256), 0, st, list, nlist, mode, d.list_order, d.wcnt, d.optr,
+                       d.ndeg, d.key0, d.val0);
     const int cur = launch_radix_sort(d.key0, d.val0, d.key1, d.val1, nlist, 16, d.rs_counts, d.rs_tmp, st);
     hipLaunchKernelGGL(k_copy_list, dim3(g), dim3(256), 0, st, cur ? d.val1 : d.val0, nlist, list);
 }
@@ -1199,16 +1212,28 @@ static void sort_heaviest_first(const Dev& d, int* list, int nlist, int mode, hi
 // per group into GSPREAD cache lines (single graph) or one line per graph (batch), so that
 // hundreds of thousands of groups do not contend on one address.  One workgroup folds the
 // lines: the single-graph sums land in line 0; the triangle totals go to work[4], work[5],
-// and the preprocessing counters (spread the same way) to work[0..3].
+// and the other work counters (spread the same way) to work[0..3], work[6], work[7].
 __global__ __launch_bounds__(256) void k_fold_gsum(u64* __restrict__ gsum, int ngraphs, u64* __restrict__ work,
                                                    const u64* __restrict__ wspread) {
     __shared__ u64 red[2][256 / GLT_WAVE];
     const int t = threadIdx.x;
-    // preprocessing work counters (wedges per path, triangle-pass list entries per path)
-    if (t < 4) {
+    // spread work counters: words 0, 1, 4, 5 wedges of the wave, workgroup, mid and huge
+    // classes as bucketed, 2, 3 triangle-pass list entries per path, 6 wedges of bottoms that
+    // moved from the workgroup to the huge class
+    __shared__ u64 wsum[WSPREAD_WORDS];
+    if (t < WSPREAD_WORDS) {
         u64 v = 0;
         for (int q = 0; q < GSPREAD; q++) v += wspread[q * WSPREAD_WORDS + t];
-        work[t] = v;
+        wsum[t] = v;
+    }
+    __syncthreads();
+    if (t == 0) {
+        work[0] = wsum[0];
+        work[1] = wsum[1] - wsum[6];
+        work[2] = wsum[2];
+        work[3] = wsum[3];
+        work[6] = wsum[4];
+        work[7] = wsum[5] + wsum[6];
     }
     if (ngraphs <= 0) {
         u64 v = 0;
@@ -1285,7 +1310,8 @@ static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st, int res
     hipLaunchKernelGGL((k_wedge<PE, AT, T, G, HT, DW, P16, CAP>), dim3(grid), dim3(T * G), 0, st,
                        d.wlist + (int64_t)bkt * d.n, cnt, d.n, limit, d.wedge_dense, d.nrp, d.ncol, d.optr, d.ocol,
                        d.s2k, d.wcnt, d.e, d.gsum, d.ngid, d.gvb, d.err, resident > 0 ? counts + bkt : nullptr,
-                       defer >= 0 ? d.wlist + (int64_t)defer * d.n : nullptr, defer >= 0 ? counts + defer : nullptr);
+                       defer >= 0 ? d.wlist + (int64_t)defer * d.n : nullptr, defer >= 0 ? counts + defer : nullptr,
+                       defer >= 0 ? d.wspread + 6 : nullptr);
 }
 
 // With `overlap` the wedge pass runs on a side stream, concurrently with the triangle and
@@ -1293,32 +1319,28 @@ static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st, int res
 // before the vertex pass and the combine.  Otherwise it follows the gather pass on the same
 // stream.  Events (all recorded, also used to fork and join):
 //   ev[1] end of preprocessing (fork)     ev[2..5] after tri wave / tri wg / gather wave / gather wg
-//   ev[6] after the wedge wave+mid classes, ev[7] after the workgroup classes (side stream)
-//   ev[8] after the join                  ev[9] after the combine
+//   ev[6..9] after the wedge wave / mid / workgroup / huge classes (side stream with overlap)
+//   ev[10] after the join                 ev[11] after the combine
 // Wedge pass: wave and mid classes (one wavefront per bottom vertex), then the huge and
 // workgroup classes; ev[6] and ev[7] mark the two halves on stream s.
 template <typename AT>
 static void wedge_pass(const Dev& d, int per_edge, const int* hc, hipStream_t s, hipEvent_t* ev) {
     const int* wc = hc + TB_N;
-    if (per_edge) {
-        launch_wedge<true, AT, WW_T, WW_G, WW_HT, 0, false, WW_CAP>(d, WB_WAVE, wc[WB_WAVE], s);
-        launch_wedge<true, AT, WM_T, WM_G, WM_HT, WM_DW, true, WM_CAP>(d, WB_MID, wc[WB_MID], s);
-    } else {
-        launch_wedge<false, AT, WW_T, WW_G, WW_HT, 0>(d, WB_WAVE, wc[WB_WAVE], s);
-        launch_wedge<false, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, WB_MID, wc[WB_MID], s);
-    }
+    if (per_edge) launch_wedge<true, AT, WW_T, WW_G, WW_HT, 0, false, WW_CAP>(d, WB_WAVE, wc[WB_WAVE], s);
+    else launch_wedge<false, AT, WW_T, WW_G, WW_HT, 0>(d, WB_WAVE, wc[WB_WAVE], s);
     (void)hipEventRecord(ev[6], s);
+    if (per_edge) launch_wedge<true, AT, WM_T, WM_G, WM_HT, WM_DW, true, WM_CAP>(d, WB_MID, wc[WB_MID], s);
+    else launch_wedge<false, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, WB_MID, wc[WB_MID], s);
+    (void)hipEventRecord(ev[7], s);
     // workgroup class first: its bottoms whose tops overflow its tables join the huge list,
     // which one resident workgroup per CU then walks
     const int huge_grid = (wc[WB_BLK] + wc[WB_HUGE] > 0) ? d.num_cu : 0;
-    if (per_edge) {
-        launch_wedge<true, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
-        launch_wedge<true, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], s, huge_grid);
-    } else {
-        launch_wedge<false, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
-        launch_wedge<false, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], s, huge_grid);
-    }
-    (void)hipEventRecord(ev[7], s);
+    if (per_edge) launch_wedge<true, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
+    else launch_wedge<false, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
+    (void)hipEventRecord(ev[8], s);
+    if (per_edge) launch_wedge<true, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], s, huge_grid);
+    else launch_wedge<false, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], s, huge_grid);
+    (void)hipEventRecord(ev[9], s);
 }
 
 template <typename AT>
@@ -1402,9 +1424,9 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
         }
     }
     (void)hipEventRecord(ev[5], st);
-    if (overlap) (void)hipStreamWaitEvent(st, ev[7], 0);   // join the wedge pass
+    if (overlap) (void)hipStreamWaitEvent(st, ev[9], 0);   // join the wedge pass
     else wedge_pass<AT>(d, per_edge, hc, st, ev);
-    (void)hipEventRecord(ev[8], st);
+    (void)hipEventRecord(ev[10], st);
     // vertex pass + combine
     if (per_edge && n > 0 && m > 0) {
         launch_fill<u64>(d.tri, n, 0ull, st);
@@ -1427,7 +1449,7 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
     } else {
         launch_fill<u64>(d.final_sums, 2 * NCS, 0ull, st);
     }
-    (void)hipEventRecord(ev[9], st);
+    (void)hipEventRecord(ev[11], st);
     hipLaunchKernelGGL(k_fold_gsum, dim3(1), dim3(256), 0, st, gsum, d.ngraphs, d.work, d.wspread);
 }
 

@@ -45,20 +45,25 @@ struct EdgeArrays {
 //   14     : 3 x (number of 4-cliques), from the triangle pass
 //   15     : number of non-induced 4-cycles, from the wedge pass
 #define NSUMS 16
-#define NWORK 6
-#define NSEG 9      // timed groups: prep, tri wave, tri wg, gather wave, gather wg, wedge wave, wedge wg, combine, total
-#define NEV 10      // events of one call (see count_passes)
+#define NWORK 8
+#define NSEG 11     // timed groups: prep, tri wave, tri wg, gather wave, gather wg, wedge wave, wedge mid,
+                    // wedge wg, wedge huge, combine, total
+#define NEV 12      // events of one call (see count_passes)
 enum { S_C3 = 0, S_C4, S_C5, S_C7, S_C8, S_C9, S_C10, S_C11, S_C12, S_C13, S_C14, S_C15, S_C16,
        S_SPARE, S_K4x3, S_NC4 };
 // The per-group totals array (gsum) holds NSUMS words per line and uses S_K4x3, S_NC4 and
 // the triangle counts of the two triangle-pass paths (measurement only).
 enum { GS_TRI_WAVE = 0, GS_TRI_WG = 1 };
 #define GSPREAD 64   // lines of gsum a single graph's groups spread their atomics over
-#define WSPREAD_WORDS 8   // u64 per line of the spread work counters (work[0..3] before folding)
+#define WSPREAD_WORDS 8   // u64 per line of the spread work counters (folded into work[])
 // gsum line of a group: its graph in a batch, else spread by workgroup index
 __device__ __forceinline__ int64_t gslot(const int* ngid, int v) {
     return ngid ? (int64_t)ngid[v] : (int64_t)(blockIdx.x & (GSPREAD - 1));
 }
+
+// Orders of the workgroup work lists (the paper's study of edge orderings, Section 4.3 and
+// Table 4, applied to vertex work lists).
+enum { LO_WORK = 0, LO_DEGREE = 1, LO_NONE = 2, LO_RANDOM = 3 };
 
 // Bucket ids for the vertex work lists.
 enum { TB_WAVE = 0, TB_BLK1, TB_BLK2, TB_GLOBAL, TB_N };   // triangle / gather passes
@@ -88,12 +93,13 @@ struct Dev {
     u64* toff;        // [n+1] triangle-record slots before vertex a: prefix of C(|N+(a)|, 2)
     int* tcnt;        // [n] triangle records written for lowest vertex a
     u64* tmp64;       // scan scratch for toff
-    u64* wspread;     // [GSPREAD][WSPREAD_WORDS] preprocessing work counters, folded into work[0..3]
+    u64* wspread;     // [GSPREAD][WSPREAD_WORDS] work counters, folded into work[] after the passes
     u64* trec;        // triangle records (null: the passes re-scan the out-lists instead)
     int* wlist;       // wedge-pass vertex lists, WB_N segments of n
     int* counts;      // bucket counts and maxima (TB_N + WB_N + TB_N)
-    u64* work;        // work counters [NWORK]: wedges (wave / workgroup path), triangle-pass list
-                      // entries (wave / workgroup path), triangles found (wave / workgroup path)
+    u64* work;        // work counters [NWORK]: wedges (wave / workgroup class), triangle-pass list
+                      // entries (wave / workgroup path), triangles found (wave / workgroup path),
+                      // wedges (mid / huge class)
     u64* wcnt;        // wedges per vertex [n] (wedge-pass bucketing)
     u32* rowx;        // [S+1] exclusive prefix of row starts of the input CSR: row of entry s = rowx[s+1]-1
     int* nsrow;       // [S] row of each relabelled CSR entry
@@ -122,6 +128,7 @@ struct Dev {
     int wedge_mid_max;    // up to this many: mid class (one wavefront, dense window + hash)
     int wedge_wg_max;     // up to this many: workgroup class; more: huge class (1024 threads, big tables)
     int num_cu;           // compute units (resident grid of the huge class)
+    int list_order;       // LO_*: order of the workgroup work lists
     int wedge_limit;      // distinct hashed tops per range before the range is split
     int wedge_dense;      // width of the dense window of highest-ranked tops
     int acc32;            // per-edge accumulators fit 32 bits (maximum degree <= 46340)

@@ -548,12 +548,11 @@ __global__ __launch_bounds__(256) void k_wcount(const int* __restrict__ ncol, co
     }
 }
 
-// Bucket the wedge pass by wedges per vertex; totals go to work[0] (wave and mid classes,
-// one wavefront per vertex) and work[1] (workgroup and huge classes).
+// Bucket the wedge pass by wedges per vertex; per-class wedge totals go to the spread work
+// counters.
 __global__ __launch_bounds__(256) void k_wappend(const u64* __restrict__ wcnt, int n, int wave_max, int mid_max,
                                                  int wg_max, int* __restrict__ wlist, int* __restrict__ counts,
                                                  u64* __restrict__ wspread) {
-    __shared__ u64 red[2][256 / GLT_WAVE];
     const int y = blockIdx.x * blockDim.x + threadIdx.x;
     const u64 wc = (y < n) ? wcnt[y] : 0;
     const int q = (wc == 0)                 ? -1
@@ -562,16 +561,20 @@ __global__ __launch_bounds__(256) void k_wappend(const u64* __restrict__ wcnt, i
                   : (wc <= (u64)wg_max)     ? WB_BLK
                                             : WB_HUGE;
     block_append<WB_N>(counts, wlist, n, q, y);
-    const u64 a = wave_sum((q == WB_WAVE || q == WB_MID) ? wc : 0ull);
-    const u64 bb = wave_sum((q == WB_BLK || q == WB_HUGE) ? wc : 0ull);
-    if (glt_lane() == 0) { red[0][threadIdx.x / GLT_WAVE] = a; red[1][threadIdx.x / GLT_WAVE] = bb; }
+    // wedges per class, summed per workgroup: wspread words 0 (wave), 1 (workgroup), 4 (mid),
+    // 5 (huge)
+    __shared__ u64 cred[WB_N][256 / GLT_WAVE];
+#pragma unroll
+    for (int c = 0; c < WB_N; c++) {
+        const u64 v = wave_sum(q == c ? wc : 0ull);
+        if (glt_lane() == 0) cred[c][threadIdx.x / GLT_WAVE] = v;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        u64 ta = 0, tb = 0;
-        for (int k = 0; k < 256 / GLT_WAVE; k++) { ta += red[0][k]; tb += red[1][k]; }
-        u64* line = wspread + (blockIdx.x & (GSPREAD - 1)) * WSPREAD_WORDS;
-        if (ta) atomicAdd(&line[0], ta);
-        if (tb) atomicAdd(&line[1], tb);
+    if (threadIdx.x < WB_N) {
+        u64 t = 0;
+        for (int k = 0; k < 256 / GLT_WAVE; k++) t += cred[threadIdx.x][k];
+        const int wd = threadIdx.x == WB_WAVE ? 0 : threadIdx.x == WB_MID ? 4 : threadIdx.x == WB_BLK ? 1 : 5;
+        if (t) atomicAdd(&wspread[(blockIdx.x & (GSPREAD - 1)) * WSPREAD_WORDS + wd], t);
     }
 }
 

@@ -203,12 +203,12 @@ def test_forced_classes_and_range_splitting(monkeypatch, case):
 def test_triangle_records_on_and_off(monkeypatch, ctx):
     """The triangle and gather passes walk stored triangle records when the record buffer
     fits, and re-scan the out-lists when records are switched off (here also with the 4-cycle
-    pass on one stream instead of beside them); both must agree with each other and with the
-    oracle on the wave, LDS-bitmap and global-bitmap paths."""
+    pass on a second stream beside them); both must agree with each other and with the oracle
+    on the wave, LDS-bitmap and global-bitmap paths."""
     import paper_1608_05138_amd as glt
     monkeypatch.setenv("GLT_TRI_RECORD_BYTES", "0")
     off = glt.Context(0)
-    off.set_schedule(wedge_stream=0)   # and the 4-cycle pass on the same stream
+    off.set_schedule(wedge_stream=1)   # and the 4-cycle pass on a second stream beside them
     try:
         rng = np.random.default_rng(5)
         n = 2300
@@ -426,3 +426,27 @@ def test_out_degree_limit(ctx):
     assert ei.value.status == -6, str(ei.value)
     X, _ = gpu(ctx, N, rp, col, per_edge=False)   # the handle still works
     assert X == _closed_complete(n)
+
+
+def test_list_orders_agree():
+    """The order of the workgroup work lists (largest work, largest degree, ascending rank,
+    pseudo-random: the ordering study of Section 4.3 / Table 4) changes only the schedule: all
+    four give the oracle's counts, global and per edge."""
+    import paper_1608_05138_amd as glt
+    n = 20000
+    rp, col = gg.chung_lu(n, 200000, 2.1, float(n - 1), 8)
+    ref = oracle.count(n, rp, col)["X"]
+    c = glt.Context(0)
+    try:
+        base = None
+        for order in range(4):
+            c.set_schedule(list_order=order)
+            say(f"list-order {order}")
+            X, pe = gpu(c, n, rp, col)
+            assert X == ref, order
+            if base is None:
+                base = pe
+            else:
+                np.testing.assert_array_equal(pe, base)
+    finally:
+        c.close()
