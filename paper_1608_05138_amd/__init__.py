@@ -179,8 +179,9 @@ class Context:
                  "triangles_wg", "wedges_mid", "wedges_huge"]
 
     def last_timing(self):
-        """dict of kernel-group times (ms) of the last count (HIP events; the wedge groups run
-        on a second stream beside the triangle groups, "total" is the whole call)."""
+        """dict of kernel-group times (ms) of the last count (HIP events on the stream each
+        group runs on; with wedge_stream = 1 the wedge groups share the chip with the triangle
+        groups; "total" is the whole call)."""
         buf = (ctypes.c_float * len(self.TIMING_KEYS))()
         k = self._lib.glt_last_timing(self._h, buf, len(self.TIMING_KEYS))
         return {name: float(buf[i]) for i, name in enumerate(self.TIMING_KEYS[:k])}

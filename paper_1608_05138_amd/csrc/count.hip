@@ -642,6 +642,84 @@ __device__ __forceinline__ int grp_excl_scan(int v, int* lds, int& tot) {
 #define WEDGE_ILP 4      // wedges in flight per lane (8 measured slower: registers)
 #endif
 
+// Flattened enumeration of the entries of up to T runs (sources) by a group of T threads,
+// with consecutive threads on consecutive positions.  Thread i of the group owns run i of
+// the current chunk (len_i entries starting at column offset k0_i); positions are
+// numbered 0 .. sum(len) - 1 in run order.  For every super-tile of SPOS = 64 T positions
+// the group marks the first position of each non-empty run in a bit mask (one 64-bit word
+// per thread) and keeps the number of runs begun before each word; the run of a position
+// is then (runs begun before its word) + popcount(earlier bits of its word) - 1, found with
+// two broadcast LDS reads and one lookup, instead of a search over the run prefix sums.
+template <int T>
+struct RunTables {
+    static constexpr int SPOS = 64 * T;
+    u64 msk[T];        // bit p of word w: a non-empty run begins at super-tile position 64 w + p
+    int pc[T];         // non-empty runs begun before word w (including earlier super-tiles)
+    int2 nz[T];        // per non-empty run in order: (column offset - position, run index)
+    u64 scan[T / GLT_WAVE > 0 ? T / GLT_WAVE : 1];
+};
+
+template <int T, typename V>
+__device__ __forceinline__ V grp_excl_scan_t(V v, V* lds, V& tot) {
+    if constexpr (T == GLT_WAVE) {
+        const V inc = wave_incl_scan(v);
+        tot = __shfl(inc, GLT_WAVE - 1, GLT_WAVE);
+        return inc - v;
+    } else {
+        return block_excl_scan<V, T>(v, lds, tot);
+    }
+}
+
+// Group-cooperative (every thread of the group calls it, uniformly): sets up a chunk whose
+// run tid has `len` entries at column offset k0; returns the chunk's total entries and
+// this thread's first position `pre`; the tables describe super-tile 0 and `carry` counts
+// the non-empty runs begun in it.  The caller has passed a group barrier since the tables
+// were last read.
+template <int T>
+__device__ __forceinline__ int runs_begin(RunTables<T>& rt, int len, int k0, int& pre, int& carry) {
+    const int tid = threadIdx.x % T;
+    rt.msk[tid] = 0;
+    u64 tot2;
+    // run lengths (<= the out-degree limit) and non-empty flags, one packed scan
+    const u64 ex = grp_excl_scan_t<T, u64>(((u64)(u32)len << 32) | (u64)(len > 0), rt.scan, tot2);
+    grp_sync<T>();   // the cleared words are visible before any bit is set
+    pre = (int)(ex >> 32);
+    if (len > 0) {
+        rt.nz[(int)(u32)ex] = make_int2(k0 - pre, tid);
+        if (pre < RunTables<T>::SPOS) atomicOr(&rt.msk[pre >> 6], 1ull << (pre & 63));
+    }
+    grp_sync<T>();
+    u64 ptot;
+    rt.pc[tid] = (int)grp_excl_scan_t<T, u64>((u64)__popcll(rt.msk[tid]), rt.scan, ptot);
+    carry = (int)ptot;
+    grp_sync<T>();
+    return (int)(tot2 >> 32);
+}
+
+// Group-cooperative: moves the tables to the super-tile starting at position sb0.
+template <int T>
+__device__ __forceinline__ void runs_next(RunTables<T>& rt, int sb0, int len, int pre, int& carry) {
+    const int tid = threadIdx.x % T;
+    grp_sync<T>();   // readers of the previous super-tile are done
+    rt.msk[tid] = 0;
+    grp_sync<T>();
+    const int p = pre - sb0;
+    if (len > 0 && p >= 0 && p < RunTables<T>::SPOS) atomicOr(&rt.msk[p >> 6], 1ull << (p & 63));
+    grp_sync<T>();
+    u64 ptot;
+    rt.pc[tid] = carry + (int)grp_excl_scan_t<T, u64>((u64)__popcll(rt.msk[tid]), rt.scan, ptot);
+    carry += (int)ptot;
+    grp_sync<T>();
+}
+
+// (column offset - position, run index) of super-tile position p
+template <int T>
+__device__ __forceinline__ int2 runs_at(const RunTables<T>& rt, int p) {
+    const int w = p >> 6;
+    const u64 m = rt.msk[w] & ((2ull << (p & 63)) - 1ull);
+    return rt.nz[rt.pc[w] + __popcll(m) - 1];
+}
+
 // Size classes of the wedge pass (wedges per bottom vertex y): threads per group, groups per
 // block, hash entries, dense top counters.
 #define WW_T 64
@@ -651,15 +729,6 @@ __device__ __forceinline__ int grp_excl_scan(int v, int* lds, int& tot) {
 #define WM_G 2       // mid class: 16-bit counters (its bottoms have at most 65,535 wedges)
 #define WM_HT 1024
 #define WM_DW 1024
-// Remembering each wedge's counter slot in LDS (CAP > 0) spares the credit sweep the top's
-// load and hash probe, but the extra LDS lowers occupancy; measured slower on the Chung-Lu
-// and R-MAT graphs, so both classes run without it by default.
-#ifndef WW_CAP
-#define WW_CAP 0
-#endif
-#ifndef WM_CAP
-#define WM_CAP 0
-#endif
 #define WB_T 256
 #define WB_HT 2048
 #define WB_DW 4096
@@ -694,7 +763,7 @@ __device__ __forceinline__ u32 cnt_get(const u32* a, int i) {
     else return a[i];
 }
 
-template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16, int CAP>
+template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16>
 __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, int nlist, int n, int limit,
                                                  int dense, const int* __restrict__ nrp,
                                                  const int* __restrict__ ncol, const int* __restrict__ optr,
@@ -706,19 +775,16 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                                                  int* __restrict__ defer_cnt, u64* __restrict__ defer_work) {
     static_assert(T == GLT_WAVE || G == 1, "multi-wave groups own the whole block");
     static_assert(HT % 4 == 0 && DW % 4 == 0 && (HT & (HT - 1)) == 0, "table sizes");
-    static_assert(DW + HT <= 65536, "table slots fit 16 bits");
     constexpr int DWA = DW > 0 ? DW : 8;
     constexpr int DCW = P16 ? DWA / 2 : DWA;   // u32 words of dense counters
     constexpr int HCW = P16 ? HT / 2 : HT;     // u32 words of hash counters
-    constexpr int CAPA = CAP > 0 ? CAP : 2;
+    constexpr int SPOS = RunTables<T>::SPOS;
     constexpr u32 mask = HT - 1;
     __shared__ __align__(16) u32 s_dc[G][DCW];
     __shared__ __align__(16) int s_hk[G][HT];
     __shared__ __align__(16) u32 s_hc[G][HCW];
-    __shared__ unsigned short s_slot[G][CAPA];   // per wedge: its counter (dense index or DW + hash slot)
-    __shared__ int s_k0[G][T], s_pre[G][T];
+    __shared__ RunTables<T> s_rt[G];
     __shared__ AT s_b[G][T];
-    __shared__ int s_scan[G][T / GLT_WAVE];
     __shared__ int s_lo[G][WEDGE_STACK], s_hi[G][WEDGE_STACK];
     __shared__ int s_sp[G], s_dist[G], s_ovf[G];
     const int g = threadIdx.x / T, tid = threadIdx.x % T;
@@ -728,6 +794,11 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
     const int count = dcount ? *dcount : nlist;
     const int stride = dcount ? (int)gridDim.x * G : count;
     if (first >= count) return;   // whole groups leave together (G == 1 when T > one wave)
+    RunTables<T>& rt = s_rt[g];
+    u32* dc = s_dc[g];
+    int* hk = s_hk[g];
+    u32* hc = s_hc[g];
+    AT* sb = s_b[g];
     for (int item = first; item < count; item += stride) {
     grp_sync<T>();   // the previous entry's last reads of the group's LDS are done
     const int y = list[item];
@@ -736,17 +807,6 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
     const int top = ngid ? (int)gvb[ngid[y] + 1] : n;
     const int base = max(top - min(dense, DW), y + 1);   // tops >= base are counted densely
     const int nd = top - base;                            // dense counters in use, <= DW
-    // with at most CAP wedges, the count sweep remembers each wedge's counter so that the
-    // credit sweep needs neither the top's id nor a hash probe
-    const bool cached = CAP > 0 && PE && wcnt[y] <= (u64)CAP;
-    const bool one = (re - rb) <= T;   // one chunk of sources: its bounds stay in LDS
-    u32* dc = s_dc[g];
-    int* hk = s_hk[g];
-    u32* hc = s_hc[g];
-    unsigned short* slot = s_slot[g];
-    int* k0s = s_k0[g];
-    int* pre = s_pre[g];
-    AT* sb = s_b[g];
     if (tid == 0) { s_lo[g][0] = y + 1; s_hi[g][0] = top; s_sp[g] = 1; }
     u64 c4 = 0;
     grp_sync<T>();
@@ -762,67 +822,59 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
         const int ndw = P16 ? (nd + 1) / 2 : nd;   // dense counter words in use
         for (int q = tid; q < (ndw + 3) / 4; q += T) reinterpret_cast<int4*>(dc)[q] = make_int4(0, 0, 0, 0);
         grp_sync<T>();
-        // count sweep
+        // count sweep, over chunks of T sources; source tid of a chunk has `len` wedges
         u64 c4r = 0;
-        int qb = 0, tot1 = 0;   // wedges of earlier chunks; wedges of the last chunk
+        int tot1 = 0, len = 0, pre = 0;
         for (int c0 = rb; c0 < re; c0 += T) {
             const int s = c0 + tid;
             int k0 = 0, k1 = 0;
             if (s < re) wedge_bounds(y, s, lo, hi, full, ncol, optr, ocol, s2k, k0, k1);
-            int tot;
-            const int ex = grp_excl_scan<T>(k1 - k0, s_scan[g], tot);
-            const int nsrc = min(T, re - c0);
-            k0s[tid] = k0;
-            pre[tid] = ex;
-            grp_sync<T>();
-            int ii = 0;
-            for (int q0 = 0; q0 < tot; q0 += WEDGE_ILP * T) {
-                if (*(volatile int*)&s_ovf[g]) break;
-                int xs[WEDGE_ILP];
+            len = k1 - k0;
+            int carry;
+            const int tot = runs_begin<T>(rt, len, k0, pre, carry);
+            for (int sb0 = 0; sb0 < tot; sb0 += SPOS) {
+                if (sb0 > 0) runs_next<T>(rt, sb0, len, pre, carry);
+                const int se = min(tot, sb0 + SPOS);
+                for (int q0 = sb0; q0 < se; q0 += WEDGE_ILP * T) {
+                    if (*(volatile int*)&s_ovf[g]) break;
+                    int xs[WEDGE_ILP];
 #pragma unroll
-                for (int j = 0; j < WEDGE_ILP; j++) {
-                    const int q = q0 + j * T + tid;
-                    xs[j] = -1;
-                    if (q < tot) {
-                        ii = advance_idx(pre, nsrc, q, ii);
-                        xs[j] = ocol[k0s[ii] + (q - pre[ii])];
+                    for (int j = 0; j < WEDGE_ILP; j++) {
+                        const int q = q0 + j * T + tid;
+                        xs[j] = (q < se) ? ocol[q + runs_at(rt, q - sb0).x] : -1;
                     }
-                }
 #pragma unroll
-                for (int j = 0; j < WEDGE_ILP; j++) {
-                    const int x = xs[j];
-                    if (x < 0) continue;
-                    int sl;
-                    if (x >= base) {
-                        sl = x - base;
-                        c4r += cnt_inc<P16>(dc, sl);
-                    } else {
-                        u32 h = hslot(x, mask);
-                        sl = -1;
-                        for (int p = 0; p < HT; p++) {   // bounded probe: a full table is an overflow
-                            int cur = hk[h];
-                            if (cur == -1) {
-                                cur = atomicCAS(&hk[h], -1, x);
+                    for (int j = 0; j < WEDGE_ILP; j++) {
+                        const int x = xs[j];
+                        if (x < 0) continue;
+                        if (x >= base) {
+                            c4r += cnt_inc<P16>(dc, x - base);
+                        } else {
+                            u32 h = hslot(x, mask);
+                            bool done = false;
+                            for (int p = 0; p < HT; p++) {   // bounded probe: a full table is an overflow
+                                int cur = hk[h];
                                 if (cur == -1) {
+                                    cur = atomicCAS(&hk[h], -1, x);
+                                    if (cur == -1) {
+                                        c4r += cnt_inc<P16>(hc, (int)h);
+                                        if (atomicAdd(&s_dist[g], 1) >= limit) s_ovf[g] = 1;
+                                        done = true;
+                                        break;
+                                    }
+                                }
+                                if (cur == x) {
                                     c4r += cnt_inc<P16>(hc, (int)h);
-                                    if (atomicAdd(&s_dist[g], 1) >= limit) s_ovf[g] = 1;
-                                    sl = DW + (int)h;
+                                    done = true;
                                     break;
                                 }
+                                h = (h + 1) & mask;
                             }
-                            if (cur == x) {
-                                c4r += cnt_inc<P16>(hc, (int)h);
-                                sl = DW + (int)h;
-                                break;
-                            }
-                            h = (h + 1) & mask;
+                            if (!done) s_ovf[g] = 1;
                         }
-                        if (sl < 0) { s_ovf[g] = 1; continue; }
                     }
-                    if (CAP > 0 && cached) slot[qb + q0 + j * T + tid] = (unsigned short)sl;
                 }
             }
-            qb += tot;
             tot1 = tot;
             grp_sync<T>();
         }
@@ -852,82 +904,63 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
         }
         c4 += c4r;
         if (PE) {
-            // credit sweep: the counts of this range are final
-            qb = 0;
+            // credit sweep: the counts of this range are final.  With one chunk of sources in
+            // one super-tile the count sweep's run tables are still in place.
+            const bool one = (re - rb) <= T && tot1 <= SPOS;
             for (int c0 = rb; c0 < re; c0 += T) {
                 const int s = c0 + tid;
-                int tot = tot1;
+                int tot = tot1, carry = 0;
                 if (!one) {
                     int k0 = 0, k1 = 0;
                     if (s < re) wedge_bounds(y, s, lo, hi, full, ncol, optr, ocol, s2k, k0, k1);
-                    const int ex = grp_excl_scan<T>(k1 - k0, s_scan[g], tot);
-                    k0s[tid] = k0;
-                    pre[tid] = ex;
+                    len = k1 - k0;
+                    tot = runs_begin<T>(rt, len, k0, pre, carry);
                 }
-                const int nsrc = min(T, re - c0);
                 sb[tid] = 0;
                 grp_sync<T>();
-                int ii = 0;
-                if (CAP > 0 && cached) {
-                    for (int q0 = 0; q0 < tot; q0 += T) {
-                        const int q = q0 + tid;
-                        int i = 0x7fffffff;
-                        AT c = 0;
-                        if (q < tot) {
-                            i = ii = advance_idx(pre, nsrc, q, ii);
-                            const int sl = slot[qb + q];
-                            const u32 cnt = (sl < DW) ? cnt_get<P16>(dc, sl) : cnt_get<P16>(hc, sl - DW);
-                            c = (AT)(cnt - 1);
-                            if (c) acc_add<AT>(e.P, k0s[i] + (q - pre[i]), (u64)c);
-                        }
-                        bool last;
-                        const AT ssum = seg_sum_last(c, i, last);
-                        if (last && ssum) atomicAdd(&sb[i], ssum);
-                    }
-                } else {
-                    for (int q0 = 0; q0 < tot; q0 += WEDGE_ILP * T) {
+                for (int sb0 = 0; sb0 < tot; sb0 += SPOS) {
+                    if (sb0 > 0) runs_next<T>(rt, sb0, len, pre, carry);
+                    const int se = min(tot, sb0 + SPOS);
+                    for (int q0 = sb0; q0 < se; q0 += WEDGE_ILP * T) {
                         int xs[WEDGE_ILP], ks[WEDGE_ILP], is[WEDGE_ILP];
 #pragma unroll
                         for (int j = 0; j < WEDGE_ILP; j++) {
                             const int q = q0 + j * T + tid;
-                            is[j] = 0x7fffffff;
-                            ks[j] = 0;
                             xs[j] = -1;
-                            if (q < tot) {
-                                ii = advance_idx(pre, nsrc, q, ii);
-                                is[j] = ii;
-                                ks[j] = k0s[ii] + (q - pre[ii]);
+                            is[j] = 0;
+                            ks[j] = 0;
+                            if (q < se) {
+                                const int2 r = runs_at(rt, q - sb0);
+                                ks[j] = q + r.x;
+                                is[j] = r.y;
                                 xs[j] = ocol[ks[j]];
                             }
                         }
 #pragma unroll
                         for (int j = 0; j < WEDGE_ILP; j++) {
-                            AT c = 0;
                             const int x = xs[j];
-                            if (x >= 0) {
-                                u32 cnt = 1;
-                                if (x >= base) {
-                                    cnt = cnt_get<P16>(dc, x - base);
-                                } else {
-                                    u32 h = hslot(x, mask);
-                                    int p = 0;
-                                    while (p < HT && hk[h] != x) { h = (h + 1) & mask; p++; }
-                                    if (p < HT) cnt = cnt_get<P16>(hc, (int)h);
-                                    else atomicOr(err, ERR_CAP);
-                                }
-                                c = (AT)(cnt - 1);
-                                if (c) acc_add<AT>(e.P, ks[j], (u64)c);
+                            if (x < 0) continue;
+                            u32 cnt = 1;
+                            if (x >= base) {
+                                cnt = cnt_get<P16>(dc, x - base);
+                            } else {
+                                u32 h = hslot(x, mask);
+                                int p = 0;
+                                while (p < HT && hk[h] != x) { h = (h + 1) & mask; p++; }
+                                if (p < HT) cnt = cnt_get<P16>(hc, (int)h);
+                                else atomicOr(err, ERR_CAP);
                             }
-                            bool last;
-                            const AT ssum = seg_sum_last(c, is[j], last);
-                            if (last && ssum) atomicAdd(&sb[is[j]], ssum);
+                            const AT c = (AT)(cnt - 1);
+                            if (c) {
+                                acc_add<AT>(e.P, ks[j], (u64)c);   // top edge (w, x)
+                                atomicAdd(&sb[is[j]], c);          // bottom edge (y, w), per source
+                            }
                         }
                     }
                 }
                 grp_sync<T>();
                 if (s < re && sb[tid]) acc_add<AT>(e.P, s2k[s], (u64)sb[tid]);
                 grp_sync<T>();
-                qb += tot;
             }
         }
         grp_sync<T>();
@@ -1301,13 +1334,13 @@ static void launch_gather_blk(const Dev& d, const int* lst, int c, int smax, hip
 // One group per list entry (grid from the host's count), or, with `resident` blocks, a grid
 // that walks the list up to the device count at `dcount`; `defer` > 0 lets overflowing
 // entries move to the list of class `defer`.
-template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16 = false, int CAP = 0>
+template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16 = false>
 static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st, int resident = 0, int defer = -1) {
     if (cnt <= 0 && resident <= 0) return;
     const int limit = d.wedge_limit < HT / 2 ? d.wedge_limit : HT / 2;
     int* counts = d.counts + TB_N;
     const unsigned grid = resident > 0 ? (unsigned)resident : cdiv(cnt, G);
-    hipLaunchKernelGGL((k_wedge<PE, AT, T, G, HT, DW, P16, CAP>), dim3(grid), dim3(T * G), 0, st,
+    hipLaunchKernelGGL((k_wedge<PE, AT, T, G, HT, DW, P16>), dim3(grid), dim3(T * G), 0, st,
                        d.wlist + (int64_t)bkt * d.n, cnt, d.n, limit, d.wedge_dense, d.nrp, d.ncol, d.optr, d.ocol,
                        d.s2k, d.wcnt, d.e, d.gsum, d.ngid, d.gvb, d.err, resident > 0 ? counts + bkt : nullptr,
                        defer >= 0 ? d.wlist + (int64_t)defer * d.n : nullptr, defer >= 0 ? counts + defer : nullptr,
@@ -1326,10 +1359,10 @@ static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st, int res
 template <typename AT>
 static void wedge_pass(const Dev& d, int per_edge, const int* hc, hipStream_t s, hipEvent_t* ev) {
     const int* wc = hc + TB_N;
-    if (per_edge) launch_wedge<true, AT, WW_T, WW_G, WW_HT, 0, false, WW_CAP>(d, WB_WAVE, wc[WB_WAVE], s);
+    if (per_edge) launch_wedge<true, AT, WW_T, WW_G, WW_HT, 0, false>(d, WB_WAVE, wc[WB_WAVE], s);
     else launch_wedge<false, AT, WW_T, WW_G, WW_HT, 0>(d, WB_WAVE, wc[WB_WAVE], s);
     (void)hipEventRecord(ev[6], s);
-    if (per_edge) launch_wedge<true, AT, WM_T, WM_G, WM_HT, WM_DW, true, WM_CAP>(d, WB_MID, wc[WB_MID], s);
+    if (per_edge) launch_wedge<true, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, WB_MID, wc[WB_MID], s);
     else launch_wedge<false, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, WB_MID, wc[WB_MID], s);
     (void)hipEventRecord(ev[7], s);
     // workgroup class first: its bottoms whose tops overflow its tables join the huge list,
