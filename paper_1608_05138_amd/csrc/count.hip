@@ -42,605 +42,13 @@ __device__ __forceinline__ u64 acc_get(const u64* base, int64_t k) {
 
 #define TB_THREADS 256
 #ifndef TRI_ILP
-#define TRI_ILP 8      // out-list entries per lane in flight in the triangle passes
+#define TRI_ILP 4      // out-list entries per lane in flight in the triangle passes (8: more registers, slower)
 #endif
-
-// ---------------------------------------------------------------------------------------
-// triangle / 4-clique pass, out-degree 2..64: one wavefront per vertex, M rows in one word
-// ---------------------------------------------------------------------------------------
-// Membership of a vertex id in S = N+(a) (s <= 64) through a 128-entry LDS hash per
-// wavefront mapping id -> position in S.
-#define SH_SIZE 128
-__device__ __forceinline__ u32 shash(int x) { return ((u32)x * 2654435761u >> 9) & (SH_SIZE - 1); }
-
-__device__ __forceinline__ void sh_insert(int* hk, unsigned char* hv, int x, int pos) {
-    u32 h = shash(x);
-    while (atomicCAS(&hk[h], -1, x) != -1) h = (h + 1) & (SH_SIZE - 1);
-    hv[h] = (unsigned char)pos;
-}
-
-__device__ __forceinline__ int sh_find(const int* hk, const unsigned char* hv, int x) {
-    u32 h = shash(x);
-    while (true) {
-        const int k = hk[h];
-        if (k == x) return hv[h];
-        if (k == -1) return -1;
-        h = (h + 1) & (SH_SIZE - 1);
-    }
-}
-
-// Entries of the LDS hash over S = N+(a) in the workgroup triangle pass: a power of two
-// >= 2 |S| (load <= 1/2).
-__host__ __device__ inline int tri_blk_ht(int smax) {
-    int h = 64;
-    while (h < 2 * smax) h <<= 1;
-    return h;
-}
-
-// Membership of S = N+(a) for the workgroup triangle pass: LDS open addressing, id -> position.
-__device__ __forceinline__ u32 bhash(int x, u32 mask) { return ((u32)x * 2654435761u >> 7) & mask; }
-__device__ __forceinline__ int bh_find(const int* hk, const unsigned short* hp, u32 mask, int x) {
-    u32 h = bhash(x, mask);
-    while (true) {
-        const int k = hk[h];
-        if (k == x) return (int)hp[h];
-        if (k == -1) return -1;
-        h = (h + 1) & mask;
-    }
-}
-
-// Triangle records (REC): every triangle (a, b_i, b_j) found while the rows are built is
-// written as (k << 32 | j << 16 | i), k the oriented index of (b_i, b_j), into a's slots
-// [toff[a], toff[a] + C(|N+(a)|, 2)) (each pair i < j at most once), and tcnt[a] holds
-// their number.  The 4-clique sweep and the gather pass then walk the records instead of
-// re-scanning every out-list of N+(a).
-__device__ __forceinline__ u64 tri_rec(int i, int j, int k) {
-    return ((u64)(u32)k << 32) | (u64)(u32)(i | (j << 16));
-}
-__device__ __forceinline__ void tri_unrec(u64 v, int& i, int& j, int& k) {
-    i = (int)(v & 0xffffu);
-    j = (int)((v >> 16) & 0xffffu);
-    k = (int)(v >> 32);
-}
-
-template <bool PE, bool REC, typename AT>
-__global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__ list, int nlist,
-                                                        const int* __restrict__ optr, const int* __restrict__ ocol,
-                                                        EdgeArrays e, u64* __restrict__ gsum,
-                                                        const int* __restrict__ ngid, u64* __restrict__ trec,
-                                                        const u64* __restrict__ toff, int* __restrict__ tcnt) {
-    __shared__ int sOb[4][GLT_WAVE];
-    __shared__ int sPre[4][GLT_WAVE];
-    __shared__ u64 sM[4][GLT_WAVE];
-    __shared__ u64 sK[4][GLT_WAVE];
-    __shared__ int hk[4][SH_SIZE];
-    __shared__ unsigned char hv[4][SH_SIZE];
-    // every LDS array is per wavefront: wavefronts synchronise only with themselves
-    const int w = threadIdx.x / GLT_WAVE, l = glt_lane();
-    const int idx = blockIdx.x * 4 + w;
-    if (idx >= nlist) return;
-    const bool active = true;
-    const int a = active ? list[idx] : 0;
-    const int o0 = active ? optr[a] : 0;
-    const int s = active ? optr[a + 1] - o0 : 0;
-    int b = 0, ob = 0, db = 0;
-    if (l < s) { b = ocol[o0 + l]; ob = optr[b]; db = optr[b + 1] - ob; }
-    const int inc = wave_incl_scan(db);
-    const int total = __shfl(inc, GLT_WAVE - 1, GLT_WAVE);
-    sOb[w][l] = ob; sPre[w][l] = inc - db; sM[w][l] = 0; sK[w][l] = 0;
-    hk[w][l] = -1; hk[w][l + GLT_WAVE] = -1;
-    wave_sync();
-    if (l < s) sh_insert(hk[w], hv[w], b, l);
-    wave_sync();
-    // build the adjacency rows among S (and record the triangles)
-    u64* rec = (REC && active) ? trec + toff[a] : nullptr;
-    const u64 lt = (l == 0) ? 0ull : ((~0ull) >> (GLT_WAVE - l));
-    int nh = 0;   // records so far (wave-uniform)
-    int i = 0;
-    for (int q0 = 0; q0 < total; q0 += TRI_ILP * GLT_WAVE) {
-        // TRI_ILP entries per lane in flight: indices and loads first, then the probes
-        int is[TRI_ILP], ks[TRI_ILP], xs[TRI_ILP];
-#pragma unroll
-        for (int u = 0; u < TRI_ILP; u++) {
-            const int q = q0 + u * GLT_WAVE + l;
-            xs[u] = -1;
-            is[u] = 0;
-            ks[u] = 0;
-            if (q < total) {
-                i = advance_idx(sPre[w], s, q, i);
-                is[u] = i;
-                ks[u] = sOb[w][i] + (q - sPre[w][i]);
-                xs[u] = ocol[ks[u]];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < TRI_ILP; u++) {
-            const int j = (xs[u] >= 0) ? sh_find(hk[w], hv[w], xs[u]) : -1;
-            if (j >= 0) {
-                atomicOr(&sM[w][is[u]], 1ull << j);
-                atomicOr(&sM[w][j], 1ull << is[u]);
-            }
-            if (REC) {   // entries in scan order: records stay sorted by i
-                const u64 hm = __ballot(j >= 0);
-                if (j >= 0) rec[nh + __popcll(hm & lt)] = tri_rec(is[u], j, ks[u]);
-                nh += __popcll(hm);
-            }
-        }
-    }
-    wave_sync();
-    u64 k4 = 0;
-    if (REC) {
-        for (int r0 = 0; r0 < nh; r0 += GLT_WAVE) {
-            const int r = r0 + l;
-            int key = 0x7fffffff;
-            u64 tk = 0;
-            if (r < nh) {
-                int ri, rj, k;
-                tri_unrec(rec[r], ri, rj, k);
-                key = ri;
-                tk = (u64)__popcll(sM[w][ri] & sM[w][rj]);
-                atomicAdd(&e.t[k], 1u);
-                if (PE && tk) {
-                    acc_add<AT>(e.K, k, tk);
-                    atomicAdd(&sK[w][rj], tk);
-                }
-                k4 += tk;
-            }
-            if (PE) {   // records are in scan order: i non-decreasing across the lanes
-                bool last;
-                const u64 ssum = seg_sum_last(tk, key, last);
-                if (last && ssum) atomicAdd(&sK[w][key], ssum);
-            }
-        }
-        if (l == 0 && active) tcnt[a] = nh;
-    }
-    i = 0;
-    for (int q0 = 0; !REC && q0 < total; q0 += GLT_WAVE) {
-        const int q = q0 + l;
-        int key = 0x7fffffff;
-        u64 tk = 0;
-        if (q < total) {
-            i = advance_idx(sPre[w], s, q, i);
-            key = i;
-            const int k = sOb[w][i] + (q - sPre[w][i]);
-            const int j = sh_find(hk[w], hv[w], ocol[k]);
-            if (j >= 0) {
-                tk = (u64)__popcll(sM[w][i] & sM[w][j]);
-                atomicAdd(&e.t[k], 1u);
-                if (PE && tk) {
-                    acc_add<AT>(e.K, k, tk);
-                    atomicAdd(&sK[w][j], tk);
-                }
-                k4 += tk;
-            }
-        }
-        if (PE) {
-            bool last;
-            const u64 ssum = seg_sum_last(tk, key, last);
-            if (last && ssum) atomicAdd(&sK[w][key], ssum);
-        }
-    }
-    wave_sync();
-    if (l < s) {
-        const u32 tl = (u32)__popcll(sM[w][l]);
-        if (tl) atomicAdd(&e.t[o0 + l], tl);
-        if (PE) {
-            const u64 kl = sK[w][l] >> 1;
-            if (kl) acc_add<AT>(e.K, o0 + l, kl);
-        }
-    }
-    k4 = wave_sum(k4);
-    const u64 ntri = wave_sum((l < s) ? (u64)__popcll(sM[w][l]) : 0ull) / 2;
-    if (l == 0 && active) {
-        u64* gs = gsum + gslot(ngid, a) * NSUMS;
-        if (k4) atomicAdd(&gs[S_K4x3], k4);
-        if (ntri) atomicAdd(&gs[GS_TRI_WAVE], ntri);
-    }
-}
-
-// ---------------------------------------------------------------------------------------
-// triangle / 4-clique pass, out-degree > 64: one workgroup per vertex, M rows of W words
-// in LDS (GM = false) or in a per-workgroup global slab (GM = true)
-// ---------------------------------------------------------------------------------------
-template <bool PE, bool GM, bool REC, typename AT>
-__global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ list, int nlist, int smax,
-                                                       const int* __restrict__ optr, const int* __restrict__ ocol,
-                                                       EdgeArrays e, u64* __restrict__ gsum,
-                                                       u32* __restrict__ gscratch, const int* __restrict__ ngid,
-                                                       u64* __restrict__ trec, const u64* __restrict__ toff,
-                                                       int* __restrict__ tcnt) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
-    __shared__ int sScan[TB_THREADS / GLT_WAVE];
-    __shared__ u64 sRed[TB_THREADS / GLT_WAVE];
-    __shared__ int sNrec;
-    u64* sK = (u64*)dyn;
-    int* sS = (int*)(sK + smax);
-    int* sOb = sS + smax;
-    int* sPre = sOb + smax;
-    const int Wmax = (smax + 31) / 32;
-    u32* M = GM ? gscratch + (int64_t)blockIdx.x * smax * Wmax : (u32*)(sPre + smax);
-    const int HT = tri_blk_ht(smax);
-    const u32 hmask = (u32)HT - 1;
-    int* hk = GM ? (sPre + smax) : (int*)(M + (int64_t)smax * Wmax);
-    unsigned short* hp = (unsigned short*)(hk + HT);
-    const int tid = threadIdx.x;
-    const int a = list[blockIdx.x];
-    const int o0 = optr[a];
-    const int s = optr[a + 1] - o0;
-    const int W = (s + 31) / 32;
-    for (int q = tid; q < HT; q += TB_THREADS) hk[q] = -1;
-    __syncthreads();
-    // S, its out-list offsets and the exclusive prefix of their lengths; S into the hash
-    int carry = 0;
-    for (int c0 = 0; c0 < s; c0 += TB_THREADS) {
-        const int i = c0 + tid;
-        int db = 0;
-        if (i < s) {
-            const int b = ocol[o0 + i];
-            const int ob = optr[b];
-            db = optr[b + 1] - ob;
-            sS[i] = b; sOb[i] = ob; sK[i] = 0;
-            u32 h = bhash(b, hmask);
-            while (atomicCAS(&hk[h], -1, b) != -1) h = (h + 1) & hmask;
-            hp[h] = (unsigned short)i;
-        }
-        int tot;
-        const int ex = block_excl_scan<int, TB_THREADS>(db, sScan, tot);
-        if (i < s) sPre[i] = carry + ex;
-        carry += tot;
-    }
-    const int total = carry;
-    for (int q = tid; q < s * W; q += TB_THREADS) M[q] = 0;
-    if (tid == 0) sNrec = 0;
-    __syncthreads();
-    u64* rec = REC ? trec + toff[a] : nullptr;
-    const u64 lt = (glt_lane() == 0) ? 0ull : ((~0ull) >> (GLT_WAVE - glt_lane()));
-    int ii = 0;
-    for (int q0 = 0; q0 < total; q0 += TRI_ILP * TB_THREADS) {
-        int is[TRI_ILP], ks[TRI_ILP], xs[TRI_ILP];
-#pragma unroll
-        for (int u = 0; u < TRI_ILP; u++) {
-            const int q = q0 + u * TB_THREADS + tid;
-            xs[u] = -1;
-            is[u] = 0;
-            ks[u] = 0;
-            if (q < total) {
-                is[u] = ii = advance_idx(sPre, s, q, ii);
-                ks[u] = sOb[ii] + (q - sPre[ii]);
-                xs[u] = ocol[ks[u]];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < TRI_ILP; u++) {
-            const int i = is[u];
-            int j = s;
-            if (xs[u] >= 0) {
-                const int jj = bh_find(hk, hp, hmask, xs[u]);   // x in S lies above b_i: jj > i
-                if (jj >= 0) {
-                    j = jj;
-                    atomicOr(&M[i * W + (j >> 5)], 1u << (j & 31));
-                    atomicOr(&M[j * W + (i >> 5)], 1u << (i & 31));
-                }
-            }
-            if (REC) {   // one slot reservation per wavefront and entry batch
-                const u64 hm = __ballot(j < s);
-                int base = 0;
-                if (glt_lane() == 0 && hm) base = atomicAdd(&sNrec, __popcll(hm));
-                base = __shfl(base, 0, GLT_WAVE);
-                if (j < s) rec[base + __popcll(hm & lt)] = tri_rec(i, j, ks[u]);
-            }
-        }
-    }
-    __syncthreads();
-    u64 k4 = 0;
-    if (REC) {
-        // records come in runs of equal i (per writing wavefront): per-source sums by run
-        const int nrec = sNrec;
-        for (int r0 = 0; r0 < nrec; r0 += TB_THREADS) {
-            const int r = r0 + tid;
-            int key = 0x7fffffff;
-            u64 tk = 0;
-            if (r < nrec) {
-                int ri, rj, k;
-                tri_unrec(rec[r], ri, rj, k);
-                key = ri;
-                for (int wd = 0; wd < W; wd++) tk += (u64)__popc(M[ri * W + wd] & M[rj * W + wd]);
-                atomicAdd(&e.t[k], 1u);
-                if (PE && tk) {
-                    acc_add<AT>(e.K, k, tk);
-                    atomicAdd(&sK[rj], tk);
-                }
-                k4 += tk;
-            }
-            if (PE) {
-                bool last;
-                const u64 ssum = seg_run_sum_last(tk, key, last);
-                if (last && ssum) atomicAdd(&sK[key], ssum);
-            }
-        }
-        if (tid == 0) tcnt[a] = nrec;
-    }
-    // every thread runs the same number of iterations so the wave reductions see full waves
-    const int rounds = REC ? 0 : (total + TB_THREADS - 1) / TB_THREADS;
-    ii = 0;
-    for (int r = 0; r < rounds; r++) {
-        const int q = r * TB_THREADS + tid;
-        int i = 0x7fffffff;
-        u64 tk = 0;
-        if (q < total) {
-            i = ii = advance_idx(sPre, s, q, ii);
-            const int k = sOb[i] + (q - sPre[i]);
-            const int j = bh_find(hk, hp, hmask, ocol[k]);
-            if (j >= 0) {
-                for (int wd = 0; wd < W; wd++) tk += (u64)__popc(M[i * W + wd] & M[j * W + wd]);
-                atomicAdd(&e.t[k], 1u);
-                if (PE && tk) {
-                    acc_add<AT>(e.K, k, tk);
-                    atomicAdd(&sK[j], tk);
-                }
-                k4 += tk;
-            }
-        }
-        if (PE) {
-            bool last;
-            const u64 ssum = seg_sum_last(tk, i, last);
-            if (last && ssum) atomicAdd(&sK[i], ssum);
-        }
-    }
-    __syncthreads();
-    u64 ntri = 0;
-    for (int i = tid; i < s; i += TB_THREADS) {
-        u32 tl = 0;
-        for (int wd = 0; wd < W; wd++) tl += (u32)__popc(M[i * W + wd]);
-        ntri += tl;
-        if (tl) atomicAdd(&e.t[o0 + i], tl);
-        if (PE) {
-            const u64 kl = sK[i] >> 1;
-            if (kl) acc_add<AT>(e.K, o0 + i, kl);
-        }
-    }
-    k4 = wave_sum(k4);
-    if (glt_lane() == 0) sRed[tid / GLT_WAVE] = k4;
-    __syncthreads();
-    if (tid == 0) {
-        u64 tot = 0;
-        for (int q = 0; q < TB_THREADS / GLT_WAVE; q++) tot += sRed[q];
-        if (tot) atomicAdd(&gsum[gslot(ngid, a) * NSUMS + S_K4x3], tot);
-    }
-    ntri = wave_sum(ntri) / 2;
-    if (glt_lane() == 0 && ntri) atomicAdd(&gsum[gslot(ngid, a) * NSUMS + GS_TRI_WG], ntri);
-}
-
-static inline size_t tri_blk_lds(int smax, bool gm) {
-    const int Wmax = (smax + 31) / 32;
-    size_t b = (size_t)smax * (8 + 4 + 4 + 4);
-    if (!gm) b += (size_t)smax * Wmax * 4;
-    b += (size_t)tri_blk_ht(smax) * (4 + 2);
-    return b;
-}
-
-// ---------------------------------------------------------------------------------------
-// gather pass (per-edge mode): for every triangle (a, b_i, b_j), a lowest
-// ---------------------------------------------------------------------------------------
-// Credits of one triangle found at (i, j, edge k = (b_i, b_j)):
-//   edge (a, b_i): g += t(a, b_j) + t(b_i, b_j), sig += d(b_j)   [local, run-summed]
-//   edge (a, b_j): g += t(a, b_i) + t(b_i, b_j), sig += d(b_i)   [local]
-//   edge (b_i, b_j): g += t(a, b_i) + t(a, b_j), sig += d(a)     [global, coalesced]
-template <typename AT>
-__device__ __forceinline__ void gather_credit(bool found, int i, int j, int k, const u32* sT, const int* sD, int da,
-                                              EdgeArrays& e, u64* sG, u64* sSg) {
-    u64 gi = 0, di = 0;
-    if (found) {
-        const u64 tij = e.t[k];
-        const u64 tai = sT[i], taj = sT[j];
-        gi = taj + tij;
-        di = (u64)sD[j];
-        atomicAdd(&sG[j], tai + tij);
-        atomicAdd(&sSg[j], (u64)sD[i]);
-        acc_add<AT>(e.g, k, tai + taj);
-        acc_add<AT>(e.sig, k, (u64)da);
-    }
-    // runs of equal i in the wavefront are summed first (idle lanes: a sentinel key, zero values)
-    bool last;
-    const u64 a1 = seg_run_sum_last(gi, i, last);
-    const u64 a3 = seg_run_sum_last(di, i, last);
-    if (last) {
-        if (a1) atomicAdd(&sG[i], a1);
-        if (a3) atomicAdd(&sSg[i], a3);
-    }
-}
-
-template <bool REC, typename AT>
-__global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restrict__ list, int nlist,
-                                                           const int* __restrict__ optr,
-                                                           const int* __restrict__ ocol,
-                                                           const int* __restrict__ ndeg, EdgeArrays e,
-                                                           const u64* __restrict__ trec,
-                                                           const u64* __restrict__ toff,
-                                                           const int* __restrict__ tcnt) {
-    __shared__ int sOb[4][GLT_WAVE];
-    __shared__ int sPre[4][GLT_WAVE];
-    __shared__ u32 sT[4][GLT_WAVE];
-    __shared__ int sD[4][GLT_WAVE];
-    __shared__ u64 sG[4][GLT_WAVE];
-    __shared__ u64 sSg[4][GLT_WAVE];
-    __shared__ int hk[4][SH_SIZE];
-    __shared__ unsigned char hv[4][SH_SIZE];
-    // every LDS array is per wavefront: wavefronts synchronise only with themselves and leave
-    // as soon as their vertex is done
-    const int w = threadIdx.x / GLT_WAVE, l = glt_lane();
-    const int idx = blockIdx.x * 4 + w;
-    if (idx >= nlist) return;
-    const int a = list[idx];
-    const int nh = REC ? tcnt[a] : 0;
-    if (REC && nh == 0) return;   // no triangle has a as its lowest vertex
-    const int o0 = optr[a];
-    const int s = optr[a + 1] - o0;
-    const int da = ndeg[a];
-    int b = 0, ob = 0, db = 0;
-    u32 tb = 0;
-    int degb = 0;
-    if (l < s) {
-        b = ocol[o0 + l];
-        tb = e.t[o0 + l];
-        degb = ndeg[b];
-        if (!REC) { ob = optr[b]; db = optr[b + 1] - ob; }
-    }
-    sT[w][l] = tb; sD[w][l] = degb;
-    sG[w][l] = 0; sSg[w][l] = 0;
-    if (REC) {
-        wave_sync();
-        const u64* rec = trec + toff[a];
-        for (int r0 = 0; r0 < nh; r0 += GLT_WAVE) {
-            const int r = r0 + l;
-            int key = 0x3fffffff, j = -1, k = 0;
-            if (r < nh) tri_unrec(rec[r], key, j, k);
-            gather_credit<AT>(r < nh, key, j, k, sT[w], sD[w], da, e, sG[w], sSg[w]);
-        }
-    } else {
-        const int inc = wave_incl_scan(db);
-        const int total = __shfl(inc, GLT_WAVE - 1, GLT_WAVE);
-        sOb[w][l] = ob; sPre[w][l] = inc - db;
-        hk[w][l] = -1; hk[w][l + GLT_WAVE] = -1;
-        wave_sync();
-        if (l < s) sh_insert(hk[w], hv[w], b, l);
-        wave_sync();
-        int i = 0;
-        for (int q0 = 0; q0 < total; q0 += GLT_WAVE) {
-            const int q = q0 + l;
-            int key = 0x3fffffff, j = -1, k = 0;
-            if (q < total) {
-                i = advance_idx(sPre[w], s, q, i);
-                key = i;
-                k = sOb[w][i] + (q - sPre[w][i]);
-                j = sh_find(hk[w], hv[w], ocol[k]);
-            }
-            gather_credit<AT>(j >= 0, key, j, k, sT[w], sD[w], da, e, sG[w], sSg[w]);
-        }
-    }
-    wave_sync();
-    if (l < s) {
-        if (sG[w][l]) acc_add<AT>(e.g, o0 + l, sG[w][l]);
-        if (sSg[w][l]) acc_add<AT>(e.sig, o0 + l, sSg[w][l]);
-    }
-}
-
-template <bool GM, bool REC, typename AT>
-__global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict__ list, int nlist, int smax,
-                                                          const int* __restrict__ optr,
-                                                          const int* __restrict__ ocol,
-                                                          const int* __restrict__ ndeg, EdgeArrays e,
-                                                          u64* __restrict__ gslab, const u64* __restrict__ trec,
-                                                          const u64* __restrict__ toff,
-                                                          const int* __restrict__ tcnt) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
-    __shared__ int sScan[TB_THREADS / GLT_WAVE];
-    int* sS = (int*)dyn;
-    int* sOb = sS + smax;
-    int* sPre = sOb + smax;
-    u32* sT = (u32*)(sPre + smax);
-    int* sD = (int*)(sT + smax);
-    u64* sG = GM ? gslab + (int64_t)blockIdx.x * 2 * smax : (u64*)(sD + smax + (smax & 1));
-    u64* sSg = sG + smax;
-    const int tid = threadIdx.x;
-    const int a = list[blockIdx.x];
-    const int o0 = optr[a];
-    const int s = optr[a + 1] - o0;
-    const int da = ndeg[a];
-    int carry = 0;
-    for (int c0 = 0; c0 < s; c0 += TB_THREADS) {
-        const int i = c0 + tid;
-        int db = 0;
-        if (i < s) {
-            const int b = ocol[o0 + i];
-            const int ob = optr[b];
-            db = optr[b + 1] - ob;
-            sS[i] = b; sOb[i] = ob; sT[i] = e.t[o0 + i]; sD[i] = ndeg[b];
-            sG[i] = 0; sSg[i] = 0;
-        }
-        int tot;
-        const int ex = block_excl_scan<int, TB_THREADS>(db, sScan, tot);
-        if (i < s) sPre[i] = carry + ex;
-        carry += tot;
-    }
-    const int total = carry;
-    __syncthreads();
-    if (REC) {
-        // records come in runs of equal i (per writing wavefront), summed per run
-        const int nh = tcnt[a];
-        const u64* rec = trec + toff[a];
-        for (int r0 = 0; r0 < nh; r0 += TB_THREADS) {
-            const int r = r0 + tid;
-            int i = 0x3fffffff, j = -1, k = 0;
-            if (r < nh) tri_unrec(rec[r], i, j, k);
-            gather_credit<AT>(r < nh, i, j, k, sT, sD, da, e, sG, sSg);
-        }
-    }
-    const int rounds = REC ? 0 : (total + TB_THREADS - 1) / TB_THREADS;
-    int ii = 0;
-    for (int r = 0; r < rounds; r++) {
-        const int q = r * TB_THREADS + tid;
-        int i = 0x3fffffff, j = 0, k = 0;
-        bool found = false;
-        if (q < total) {
-            i = ii = advance_idx(sPre, s, q, ii);
-            k = sOb[i] + (q - sPre[i]);
-            const int x = ocol[k];
-            j = lower_bound_i32(sS, i + 1, s, x);
-            found = (j < s && sS[j] == x);
-        }
-        gather_credit<AT>(found, i, j, k, sT, sD, da, e, sG, sSg);
-    }
-    __syncthreads();
-    for (int i = tid; i < s; i += TB_THREADS) {
-        if (sG[i]) acc_add<AT>(e.g, o0 + i, sG[i]);
-        if (sSg[i]) acc_add<AT>(e.sig, o0 + i, sSg[i]);
-    }
-}
-
-static inline size_t gather_blk_lds(int smax, bool gm) {
-    return (size_t)(smax + 1) * 4 * 5 + (gm ? 0 : (size_t)smax * 8 * 2);
-}
-
-// ---------------------------------------------------------------------------------------
-// wedge / 4-cycle pass
-// ---------------------------------------------------------------------------------------
-__device__ __forceinline__ u32 hslot(int x, u32 mask) { return ((u32)x * 2654435761u >> 7) & mask; }
-
-// Oriented index range [k0, k1) of the wedges y - w - x for CSR slot s of row y (w = ncol[s]),
-// restricted to tops x in [lo, hi) unless the range is the full [y + 1, n).
-__device__ __forceinline__ void wedge_bounds(int y, int s, int lo, int hi, bool full, const int* __restrict__ ncol,
-                                             const int* __restrict__ optr, const int* __restrict__ ocol,
-                                             const int* __restrict__ s2k, int& k0, int& k1) {
-    const int w = ncol[s];
-    k1 = optr[w + 1];
-    k0 = (w > y) ? optr[w] : s2k[s] + 1;
-    if (!full) {
-        k0 = lower_bound_i32(ocol, k0, k1, lo);
-        k1 = lower_bound_i32(ocol, k0, k1, hi);
-    }
-}
 
 template <int T>
 __device__ __forceinline__ void grp_sync() {
     if constexpr (T == GLT_WAVE) wave_sync(); else __syncthreads();
 }
-
-template <int T>
-__device__ __forceinline__ int grp_excl_scan(int v, int* lds, int& tot) {
-    if constexpr (T == GLT_WAVE) {
-        const int inc = wave_incl_scan(v);
-        tot = __shfl(inc, GLT_WAVE - 1, GLT_WAVE);
-        return inc - v;
-    } else {
-        return block_excl_scan<int, T>(v, lds, tot);
-    }
-}
-
-#define WEDGE_STACK 40   // x-range stack per group (halving depth <= 32 for 31-bit ids)
-#ifndef WEDGE_ILP
-#define WEDGE_ILP 4      // wedges in flight per lane (8 measured slower: registers)
-#endif
 
 // Flattened enumeration of the entries of up to T runs (sources) by a group of T threads,
 // with consecutive threads on consecutive positions.  Thread i of the group owns run i of
@@ -720,6 +128,599 @@ __device__ __forceinline__ int2 runs_at(const RunTables<T>& rt, int p) {
     return rt.nz[rt.pc[w] + __popcll(m) - 1];
 }
 
+
+// ---------------------------------------------------------------------------------------
+// triangle / 4-clique pass, out-degree 2..64: one wavefront per vertex, M rows in one word
+// ---------------------------------------------------------------------------------------
+// Membership of a vertex id in S = N+(a) (s <= 64) through a 128-entry LDS hash per
+// wavefront mapping id -> position in S.
+#define SH_SIZE 128
+__device__ __forceinline__ u32 shash(int x) { return ((u32)x * 2654435761u >> 9) & (SH_SIZE - 1); }
+
+__device__ __forceinline__ void sh_insert(int* hk, unsigned char* hv, int x, int pos) {
+    u32 h = shash(x);
+    while (atomicCAS(&hk[h], -1, x) != -1) h = (h + 1) & (SH_SIZE - 1);
+    hv[h] = (unsigned char)pos;
+}
+
+__device__ __forceinline__ int sh_find(const int* hk, const unsigned char* hv, int x) {
+    u32 h = shash(x);
+    while (true) {
+        const int k = hk[h];
+        if (k == x) return hv[h];
+        if (k == -1) return -1;
+        h = (h + 1) & (SH_SIZE - 1);
+    }
+}
+
+// Entries of the LDS hash over S = N+(a) in the workgroup triangle pass: a power of two
+// >= 2 |S| (load <= 1/2).
+__host__ __device__ inline int tri_blk_ht(int smax) {
+    int h = 64;
+    while (h < 2 * smax) h <<= 1;
+    return h;
+}
+
+// Membership of S = N+(a) for the workgroup triangle pass: LDS open addressing, id -> position.
+__device__ __forceinline__ u32 bhash(int x, u32 mask) { return ((u32)x * 2654435761u >> 7) & mask; }
+__device__ __forceinline__ int bh_find(const int* hk, const unsigned short* hp, u32 mask, int x) {
+    u32 h = bhash(x, mask);
+    while (true) {
+        const int k = hk[h];
+        if (k == x) return (int)hp[h];
+        if (k == -1) return -1;
+        h = (h + 1) & mask;
+    }
+}
+
+// Triangle records (REC): every triangle (a, b_i, b_j) found while the rows are built is
+// written as (k << 32 | j << 16 | i), k the oriented index of (b_i, b_j), into a's slots
+// [toff[a], toff[a] + C(|N+(a)|, 2)) (each pair i < j at most once), and tcnt[a] holds
+// their number.  The 4-clique sweep and the gather pass then walk the records instead of
+// re-scanning every out-list of N+(a).
+__device__ __forceinline__ u64 tri_rec(int i, int j, int k) {
+    return ((u64)(u32)k << 32) | (u64)(u32)(i | (j << 16));
+}
+__device__ __forceinline__ void tri_unrec(u64 v, int& i, int& j, int& k) {
+    i = (int)(v & 0xffffu);
+    j = (int)((v >> 16) & 0xffffu);
+    k = (int)(v >> 32);
+}
+
+template <bool PE, bool REC, typename AT>
+__global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__ list, int nlist,
+                                                        const int* __restrict__ optr, const int* __restrict__ ocol,
+                                                        EdgeArrays e, u64* __restrict__ gsum,
+                                                        const int* __restrict__ ngid, u64* __restrict__ trec,
+                                                        const u64* __restrict__ toff, int* __restrict__ tcnt) {
+    constexpr int SPOS = RunTables<GLT_WAVE>::SPOS;
+    __shared__ RunTables<GLT_WAVE> sRT[4];
+    __shared__ u64 sM[4][GLT_WAVE];
+    __shared__ u64 sK[4][GLT_WAVE];
+    __shared__ int hk[4][SH_SIZE];
+    __shared__ unsigned char hv[4][SH_SIZE];
+    // every LDS array is per wavefront: wavefronts synchronise only with themselves
+    const int w = threadIdx.x / GLT_WAVE, l = glt_lane();
+    const int idx = blockIdx.x * 4 + w;
+    if (idx >= nlist) return;
+    const int a = list[idx];
+    const int o0 = optr[a];
+    const int s = optr[a + 1] - o0;
+    int b = 0, ob = 0, db = 0;
+    if (l < s) { b = ocol[o0 + l]; ob = optr[b]; db = optr[b + 1] - ob; }
+    RunTables<GLT_WAVE>& rt = sRT[w];
+    sM[w][l] = 0; sK[w][l] = 0;
+    hk[w][l] = -1; hk[w][l + GLT_WAVE] = -1;
+    // runs: the out-list of b_l for every l; positions enumerate N+(b_0), N+(b_1), ...
+    int pre, carry;
+    const int total = runs_begin<GLT_WAVE>(rt, db, ob, pre, carry);
+    if (l < s) sh_insert(hk[w], hv[w], b, l);
+    wave_sync();
+    // build the adjacency rows among S (and record the triangles)
+    u64* rec = REC ? trec + toff[a] : nullptr;
+    const u64 lt = (l == 0) ? 0ull : ((~0ull) >> (GLT_WAVE - l));
+    int nh = 0;   // records so far (wave-uniform)
+    for (int sb0 = 0; sb0 < total; sb0 += SPOS) {
+        if (sb0 > 0) runs_next<GLT_WAVE>(rt, sb0, db, pre, carry);
+        const int se = min(total, sb0 + SPOS);
+        for (int q0 = sb0; q0 < se; q0 += TRI_ILP * GLT_WAVE) {
+            // TRI_ILP entries per lane in flight: indices and loads first, then the probes
+            int is[TRI_ILP], ks[TRI_ILP], xs[TRI_ILP];
+#pragma unroll
+            for (int u = 0; u < TRI_ILP; u++) {
+                const int q = q0 + u * GLT_WAVE + l;
+                xs[u] = -1;
+                is[u] = 0;
+                ks[u] = 0;
+                if (q < se) {
+                    const int2 r = runs_at(rt, q - sb0);
+                    is[u] = r.y;
+                    ks[u] = q + r.x;
+                    xs[u] = ocol[ks[u]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < TRI_ILP; u++) {
+                const int j = (xs[u] >= 0) ? sh_find(hk[w], hv[w], xs[u]) : -1;
+                if (j >= 0) {
+                    atomicOr(&sM[w][is[u]], 1ull << j);
+                    atomicOr(&sM[w][j], 1ull << is[u]);
+                }
+                if (REC) {   // entries in scan order: records stay sorted by i
+                    const u64 hm = __ballot(j >= 0);
+                    if (j >= 0) rec[nh + __popcll(hm & lt)] = tri_rec(is[u], j, ks[u]);
+                    nh += __popcll(hm);
+                }
+            }
+        }
+    }
+    wave_sync();
+    // 4-cliques of every triangle (a, b_i, b_j): popcount(M_i & M_j); each credits the
+    // triangle's three edges (the two at a are summed per source in LDS)
+    u64 k4 = 0;
+    if (REC) {
+        for (int r0 = 0; r0 < nh; r0 += GLT_WAVE) {
+            const int r = r0 + l;
+            int ri = 0x7fffffff;
+            u64 tk = 0;
+            if (r < nh) {
+                int rj, k;
+                tri_unrec(rec[r], ri, rj, k);
+                tk = (u64)__popcll(sM[w][ri] & sM[w][rj]);
+                atomicAdd(&e.t[k], 1u);
+                if (PE && tk) {
+                    acc_add<AT>(e.K, k, tk);
+                    atomicAdd(&sK[w][rj], tk);
+                }
+                k4 += tk;
+            }
+            if (PE) {   // records are in scan order: runs of equal i summed first
+                bool last;
+                const u64 ssum = seg_sum_last(tk, ri, last);
+                if (last && ssum) atomicAdd(&sK[w][ri], ssum);
+            }
+        }
+        if (l == 0) tcnt[a] = nh;
+    } else {
+        runs_begin<GLT_WAVE>(rt, db, ob, pre, carry);
+        for (int sb0 = 0; sb0 < total; sb0 += SPOS) {
+            if (sb0 > 0) runs_next<GLT_WAVE>(rt, sb0, db, pre, carry);
+            const int se = min(total, sb0 + SPOS);
+            for (int q0 = sb0; q0 < se; q0 += GLT_WAVE) {
+                const int q = q0 + l;
+                if (q < se) {
+                    const int2 r = runs_at(rt, q - sb0);
+                    const int i = r.y, k = q + r.x;
+                    const int j = sh_find(hk[w], hv[w], ocol[k]);
+                    if (j >= 0) {
+                        const u64 tk = (u64)__popcll(sM[w][i] & sM[w][j]);
+                        atomicAdd(&e.t[k], 1u);
+                        if (PE && tk) {
+                            acc_add<AT>(e.K, k, tk);
+                            atomicAdd(&sK[w][i], tk);
+                            atomicAdd(&sK[w][j], tk);
+                        }
+                        k4 += tk;
+                    }
+                }
+            }
+        }
+    }
+    wave_sync();
+    if (l < s) {
+        const u32 tl = (u32)__popcll(sM[w][l]);
+        if (tl) atomicAdd(&e.t[o0 + l], tl);
+        if (PE) {
+            const u64 kl = sK[w][l] >> 1;
+            if (kl) acc_add<AT>(e.K, o0 + l, kl);
+        }
+    }
+    k4 = wave_sum(k4);
+    const u64 ntri = wave_sum((l < s) ? (u64)__popcll(sM[w][l]) : 0ull) / 2;
+    if (l == 0) {
+        u64* gs = gsum + gslot(ngid, a) * NSUMS;
+        if (k4) atomicAdd(&gs[S_K4x3], k4);
+        if (ntri) atomicAdd(&gs[GS_TRI_WAVE], ntri);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// triangle / 4-clique pass, out-degree > 64: one workgroup per vertex, M rows of W words
+// in LDS (GM = false) or in a per-workgroup global slab (GM = true)
+// ---------------------------------------------------------------------------------------
+template <bool PE, bool GM, bool REC, typename AT>
+__global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ list, int nlist, int smax,
+                                                       const int* __restrict__ optr, const int* __restrict__ ocol,
+                                                       EdgeArrays e, u64* __restrict__ gsum,
+                                                       u32* __restrict__ gscratch, const int* __restrict__ ngid,
+                                                       u64* __restrict__ trec, const u64* __restrict__ toff,
+                                                       int* __restrict__ tcnt) {
+    constexpr int SPOS = RunTables<TB_THREADS>::SPOS;
+    extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
+    __shared__ RunTables<TB_THREADS> rt;
+    __shared__ u64 sRed[TB_THREADS / GLT_WAVE];
+    __shared__ int sNrec;
+    u64* sK = (u64*)dyn;
+    int* sS = (int*)(sK + smax);
+    int* sOb = sS + smax;
+    int* sLen = sOb + smax;
+    const int Wmax = (smax + 31) / 32;
+    u32* M = GM ? gscratch + (int64_t)blockIdx.x * smax * Wmax : (u32*)(sLen + smax);
+    const int HT = tri_blk_ht(smax);
+    const u32 hmask = (u32)HT - 1;
+    int* hk = GM ? (sLen + smax) : (int*)(M + (int64_t)smax * Wmax);
+    unsigned short* hp = (unsigned short*)(hk + HT);
+    const int tid = threadIdx.x;
+    const int a = list[blockIdx.x];
+    const int o0 = optr[a];
+    const int s = optr[a + 1] - o0;
+    const int W = (s + 31) / 32;
+    for (int q = tid; q < HT; q += TB_THREADS) hk[q] = -1;
+    __syncthreads();
+    // S, its out-list offsets and lengths; S into the hash
+    for (int i = tid; i < s; i += TB_THREADS) {
+        const int b = ocol[o0 + i];
+        const int ob = optr[b];
+        sS[i] = b; sOb[i] = ob; sLen[i] = optr[b + 1] - ob; sK[i] = 0;
+        u32 h = bhash(b, hmask);
+        while (atomicCAS(&hk[h], -1, b) != -1) h = (h + 1) & hmask;
+        hp[h] = (unsigned short)i;
+    }
+    for (int q = tid; q < s * W; q += TB_THREADS) M[q] = 0;
+    if (tid == 0) sNrec = 0;
+    __syncthreads();
+    u64* rec = REC ? trec + toff[a] : nullptr;
+    const u64 lt = (glt_lane() == 0) ? 0ull : ((~0ull) >> (GLT_WAVE - glt_lane()));
+    // scan the out-lists of b_c0 .. b_{c0+255}, one chunk of runs at a time
+    for (int c0 = 0; c0 < s; c0 += TB_THREADS) {
+        const int len = (c0 + tid < s) ? sLen[c0 + tid] : 0;
+        const int ob = (c0 + tid < s) ? sOb[c0 + tid] : 0;
+        int pre, carry;
+        const int total = runs_begin<TB_THREADS>(rt, len, ob, pre, carry);
+        for (int sb0 = 0; sb0 < total; sb0 += SPOS) {
+            if (sb0 > 0) runs_next<TB_THREADS>(rt, sb0, len, pre, carry);
+            const int se = min(total, sb0 + SPOS);
+            for (int q0 = sb0; q0 < se; q0 += TRI_ILP * TB_THREADS) {
+                int is[TRI_ILP], ks[TRI_ILP], xs[TRI_ILP];
+#pragma unroll
+                for (int u = 0; u < TRI_ILP; u++) {
+                    const int q = q0 + u * TB_THREADS + tid;
+                    xs[u] = -1;
+                    is[u] = 0;
+                    ks[u] = 0;
+                    if (q < se) {
+                        const int2 r = runs_at(rt, q - sb0);
+                        is[u] = c0 + r.y;
+                        ks[u] = q + r.x;
+                        xs[u] = ocol[ks[u]];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < TRI_ILP; u++) {
+                    const int i = is[u];
+                    int j = s;
+                    if (xs[u] >= 0) {
+                        const int jj = bh_find(hk, hp, hmask, xs[u]);   // x in S lies above b_i: jj > i
+                        if (jj >= 0) {
+                            j = jj;
+                            atomicOr(&M[i * W + (j >> 5)], 1u << (j & 31));
+                            atomicOr(&M[j * W + (i >> 5)], 1u << (i & 31));
+                        }
+                    }
+                    if (REC) {   // one slot reservation per wavefront and entry batch
+                        const u64 hm = __ballot(j < s);
+                        int base = 0;
+                        if (glt_lane() == 0 && hm) base = atomicAdd(&sNrec, __popcll(hm));
+                        base = __shfl(base, 0, GLT_WAVE);
+                        if (j < s) rec[base + __popcll(hm & lt)] = tri_rec(i, j, ks[u]);
+                    }
+                }
+            }
+        }
+        __syncthreads();   // the run tables are rebuilt for the next chunk
+    }
+    u64 k4 = 0;
+    // 4-cliques of every triangle (a, b_i, b_j): popcount(M_i & M_j); each credits the
+    // triangle's three edges (the two at a are summed per source in LDS)
+    if (REC) {
+        const int nrec = sNrec;
+        for (int r0 = 0; r0 < nrec; r0 += TB_THREADS) {
+            const int r = r0 + tid;
+            int ri = 0x7fffffff;
+            u64 tk = 0;
+            if (r < nrec) {
+                int rj, k;
+                tri_unrec(rec[r], ri, rj, k);
+                for (int wd = 0; wd < W; wd++) tk += (u64)__popc(M[ri * W + wd] & M[rj * W + wd]);
+                atomicAdd(&e.t[k], 1u);
+                if (PE && tk) {
+                    acc_add<AT>(e.K, k, tk);
+                    atomicAdd(&sK[rj], tk);
+                }
+                k4 += tk;
+            }
+            if (PE) {   // records come in runs of equal i (per writing wavefront)
+                bool last;
+                const u64 ssum = seg_run_sum_last(tk, ri, last);
+                if (last && ssum) atomicAdd(&sK[ri], ssum);
+            }
+        }
+        if (tid == 0) tcnt[a] = nrec;
+    } else {
+        for (int c0 = 0; c0 < s; c0 += TB_THREADS) {
+            const int len = (c0 + tid < s) ? sLen[c0 + tid] : 0;
+            const int ob = (c0 + tid < s) ? sOb[c0 + tid] : 0;
+            int pre, carry;
+            const int total = runs_begin<TB_THREADS>(rt, len, ob, pre, carry);
+            for (int sb0 = 0; sb0 < total; sb0 += SPOS) {
+                if (sb0 > 0) runs_next<TB_THREADS>(rt, sb0, len, pre, carry);
+                const int se = min(total, sb0 + SPOS);
+                for (int q = sb0 + tid; q < se; q += TB_THREADS) {
+                    const int2 r = runs_at(rt, q - sb0);
+                    const int i = c0 + r.y, k = q + r.x;
+                    const int j = bh_find(hk, hp, hmask, ocol[k]);
+                    if (j >= 0) {
+                        u64 tk = 0;
+                        for (int wd = 0; wd < W; wd++) tk += (u64)__popc(M[i * W + wd] & M[j * W + wd]);
+                        atomicAdd(&e.t[k], 1u);
+                        if (PE && tk) {
+                            acc_add<AT>(e.K, k, tk);
+                            atomicAdd(&sK[i], tk);
+                            atomicAdd(&sK[j], tk);
+                        }
+                        k4 += tk;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    u64 ntri = 0;
+    for (int i = tid; i < s; i += TB_THREADS) {
+        u32 tl = 0;
+        for (int wd = 0; wd < W; wd++) tl += (u32)__popc(M[i * W + wd]);
+        ntri += tl;
+        if (tl) atomicAdd(&e.t[o0 + i], tl);
+        if (PE) {
+            const u64 kl = sK[i] >> 1;
+            if (kl) acc_add<AT>(e.K, o0 + i, kl);
+        }
+    }
+    k4 = wave_sum(k4);
+    if (glt_lane() == 0) sRed[tid / GLT_WAVE] = k4;
+    __syncthreads();
+    if (tid == 0) {
+        u64 tot = 0;
+        for (int q = 0; q < TB_THREADS / GLT_WAVE; q++) tot += sRed[q];
+        if (tot) atomicAdd(&gsum[gslot(ngid, a) * NSUMS + S_K4x3], tot);
+    }
+    ntri = wave_sum(ntri) / 2;
+    if (glt_lane() == 0 && ntri) atomicAdd(&gsum[gslot(ngid, a) * NSUMS + GS_TRI_WG], ntri);
+}
+
+static inline size_t tri_blk_lds(int smax, bool gm) {
+    const int Wmax = (smax + 31) / 32;
+    size_t b = (size_t)smax * (8 + 4 + 4 + 4);
+    if (!gm) b += (size_t)smax * Wmax * 4;
+    b += (size_t)tri_blk_ht(smax) * (4 + 2);
+    return b;
+}
+
+// ---------------------------------------------------------------------------------------
+// gather pass (per-edge mode): for every triangle (a, b_i, b_j), a lowest
+// ---------------------------------------------------------------------------------------
+// Credits of one triangle found at (i, j, edge k = (b_i, b_j)):
+//   edge (a, b_i): g += t(a, b_j) + t(b_i, b_j), sig += d(b_j)   [local, run-summed]
+//   edge (a, b_j): g += t(a, b_i) + t(b_i, b_j), sig += d(b_i)   [local]
+//   edge (b_i, b_j): g += t(a, b_i) + t(a, b_j), sig += d(a)     [global, coalesced]
+// Runs of equal i in the wavefront are summed first (every lane must call; idle lanes pass
+// a sentinel key and found = false).
+template <typename AT>
+__device__ __forceinline__ void gather_credit(bool found, int i, int j, int k, const u32* sT, const int* sD, int da,
+                                              EdgeArrays& e, u64* sG, u64* sSg) {
+    u64 gi = 0, di = 0;
+    if (found) {
+        const u64 tij = e.t[k];
+        const u64 tai = sT[i], taj = sT[j];
+        gi = taj + tij;
+        di = (u64)sD[j];
+        atomicAdd(&sG[j], tai + tij);
+        atomicAdd(&sSg[j], (u64)sD[i]);
+        acc_add<AT>(e.g, k, tai + taj);
+        acc_add<AT>(e.sig, k, (u64)da);
+    }
+    bool last;
+    const u64 a1 = seg_run_sum_last(gi, i, last);
+    const u64 a3 = seg_run_sum_last(di, i, last);
+    if (last) {
+        if (a1) atomicAdd(&sG[i], a1);
+        if (a3) atomicAdd(&sSg[i], a3);
+    }
+}
+
+template <bool REC, typename AT>
+__global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restrict__ list, int nlist,
+                                                           const int* __restrict__ optr,
+                                                           const int* __restrict__ ocol,
+                                                           const int* __restrict__ ndeg, EdgeArrays e,
+                                                           const u64* __restrict__ trec,
+                                                           const u64* __restrict__ toff,
+                                                           const int* __restrict__ tcnt) {
+    constexpr int SPOS = RunTables<GLT_WAVE>::SPOS;
+    __shared__ RunTables<GLT_WAVE> sRT[REC ? 1 : 4];
+    __shared__ u32 sT[4][GLT_WAVE];
+    __shared__ int sD[4][GLT_WAVE];
+    __shared__ u64 sG[4][GLT_WAVE];
+    __shared__ u64 sSg[4][GLT_WAVE];
+    __shared__ int hk[4][SH_SIZE];
+    __shared__ unsigned char hv[4][SH_SIZE];
+    // every LDS array is per wavefront: wavefronts synchronise only with themselves and leave
+    // as soon as their vertex is done
+    const int w = threadIdx.x / GLT_WAVE, l = glt_lane();
+    const int idx = blockIdx.x * 4 + w;
+    if (idx >= nlist) return;
+    const int a = list[idx];
+    const int nh = REC ? tcnt[a] : 0;
+    if (REC && nh == 0) return;   // no triangle has a as its lowest vertex
+    const int o0 = optr[a];
+    const int s = optr[a + 1] - o0;
+    const int da = ndeg[a];
+    int b = 0, ob = 0, db = 0;
+    u32 tb = 0;
+    int degb = 0;
+    if (l < s) {
+        b = ocol[o0 + l];
+        tb = e.t[o0 + l];
+        degb = ndeg[b];
+        if (!REC) { ob = optr[b]; db = optr[b + 1] - ob; }
+    }
+    sT[w][l] = tb; sD[w][l] = degb;
+    sG[w][l] = 0; sSg[w][l] = 0;
+    if (REC) {
+        wave_sync();
+        const u64* rec = trec + toff[a];
+        for (int r0 = 0; r0 < nh; r0 += GLT_WAVE) {
+            const int r = r0 + l;
+            int i = 0x3fffffff, j = -1, k = 0;
+            if (r < nh) tri_unrec(rec[r], i, j, k);
+            gather_credit<AT>(r < nh, i, j, k, sT[w], sD[w], da, e, sG[w], sSg[w]);
+        }
+    } else {
+        RunTables<GLT_WAVE>& rt = sRT[REC ? 0 : w];
+        hk[w][l] = -1; hk[w][l + GLT_WAVE] = -1;
+        int pre, carry;
+        const int total = runs_begin<GLT_WAVE>(rt, db, ob, pre, carry);
+        if (l < s) sh_insert(hk[w], hv[w], b, l);
+        wave_sync();
+        for (int sb0 = 0; sb0 < total; sb0 += SPOS) {
+            if (sb0 > 0) runs_next<GLT_WAVE>(rt, sb0, db, pre, carry);
+            const int se = min(total, sb0 + SPOS);
+            for (int q0 = sb0; q0 < se; q0 += GLT_WAVE) {
+                const int q = q0 + l;
+                int i = 0x3fffffff, j = -1, k = 0;
+                if (q < se) {
+                    const int2 r = runs_at(rt, q - sb0);
+                    i = r.y;
+                    k = q + r.x;
+                    j = sh_find(hk[w], hv[w], ocol[k]);
+                }
+                gather_credit<AT>(j >= 0, i, j, k, sT[w], sD[w], da, e, sG[w], sSg[w]);
+            }
+        }
+    }
+    wave_sync();
+    if (l < s) {
+        if (sG[w][l]) acc_add<AT>(e.g, o0 + l, sG[w][l]);
+        if (sSg[w][l]) acc_add<AT>(e.sig, o0 + l, sSg[w][l]);
+    }
+}
+
+template <bool GM, bool REC, typename AT>
+__global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict__ list, int nlist, int smax,
+                                                          const int* __restrict__ optr,
+                                                          const int* __restrict__ ocol,
+                                                          const int* __restrict__ ndeg, EdgeArrays e,
+                                                          u64* __restrict__ gslab, const u64* __restrict__ trec,
+                                                          const u64* __restrict__ toff,
+                                                          const int* __restrict__ tcnt) {
+    constexpr int SPOS = RunTables<TB_THREADS>::SPOS;
+    extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
+    __shared__ RunTables<REC ? GLT_WAVE : TB_THREADS> rt;
+    int* sS = (int*)dyn;
+    int* sOb = sS + smax;
+    int* sLen = sOb + smax;
+    u32* sT = (u32*)(sLen + smax);
+    int* sD = (int*)(sT + smax);
+    u64* sG = GM ? gslab + (int64_t)blockIdx.x * 2 * smax : (u64*)(sD + smax + (smax & 1));
+    u64* sSg = sG + smax;
+    const int tid = threadIdx.x;
+    const int a = list[blockIdx.x];
+    const int o0 = optr[a];
+    const int s = optr[a + 1] - o0;
+    const int da = ndeg[a];
+    for (int i = tid; i < s; i += TB_THREADS) {
+        const int b = ocol[o0 + i];
+        const int ob = optr[b];
+        sS[i] = b; sOb[i] = ob; sLen[i] = optr[b + 1] - ob; sT[i] = e.t[o0 + i]; sD[i] = ndeg[b];
+        sG[i] = 0; sSg[i] = 0;
+    }
+    __syncthreads();
+    if (REC) {
+        // records come in runs of equal i (per writing wavefront), summed per run
+        const int nh = tcnt[a];
+        const u64* rec = trec + toff[a];
+        for (int r0 = 0; r0 < nh; r0 += TB_THREADS) {
+            const int r = r0 + tid;
+            int i = 0x3fffffff, j = -1, k = 0;
+            if (r < nh) tri_unrec(rec[r], i, j, k);
+            gather_credit<AT>(r < nh, i, j, k, sT, sD, da, e, sG, sSg);
+        }
+    } else {
+        if constexpr (!REC) {
+            for (int c0 = 0; c0 < s; c0 += TB_THREADS) {
+                const int len = (c0 + tid < s) ? sLen[c0 + tid] : 0;
+                const int ob = (c0 + tid < s) ? sOb[c0 + tid] : 0;
+                int pre, carry;
+                const int total = runs_begin<TB_THREADS>(rt, len, ob, pre, carry);
+                for (int sb0 = 0; sb0 < total; sb0 += SPOS) {
+                    if (sb0 > 0) runs_next<TB_THREADS>(rt, sb0, len, pre, carry);
+                    const int se = min(total, sb0 + SPOS);
+                    // every thread runs the same number of rounds (runs are summed across the wave)
+                    for (int q0 = sb0; q0 < se; q0 += TB_THREADS) {
+                        const int q = q0 + tid;
+                        int i = 0x3fffffff, j = 0, k = 0;
+                        bool found = false;
+                        if (q < se) {
+                            const int2 r = runs_at(rt, q - sb0);
+                            i = c0 + r.y;
+                            k = q + r.x;
+                            const int x = ocol[k];
+                            j = lower_bound_i32(sS, i + 1, s, x);
+                            found = (j < s && sS[j] == x);
+                        }
+                        gather_credit<AT>(found, i, j, k, sT, sD, da, e, sG, sSg);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < s; i += TB_THREADS) {
+        if (sG[i]) acc_add<AT>(e.g, o0 + i, sG[i]);
+        if (sSg[i]) acc_add<AT>(e.sig, o0 + i, sSg[i]);
+    }
+}
+
+static inline size_t gather_blk_lds(int smax, bool gm) {
+    return (size_t)(smax + 1) * 4 * 5 + (gm ? 0 : (size_t)smax * 8 * 2);
+}
+
+// ---------------------------------------------------------------------------------------
+// wedge / 4-cycle pass
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ u32 hslot(int x, u32 mask) { return ((u32)x * 2654435761u >> 7) & mask; }
+
+// Oriented index range [k0, k1) of the wedges y - w - x for CSR slot s of row y (w = ncol[s]),
+// restricted to tops x in [lo, hi) unless the range is the full [y + 1, n).
+__device__ __forceinline__ void wedge_bounds(int y, int s, int lo, int hi, bool full, const int* __restrict__ ncol,
+                                             const int* __restrict__ optr, const int* __restrict__ ocol,
+                                             const int* __restrict__ s2k, int& k0, int& k1) {
+    const int w = ncol[s];
+    k1 = optr[w + 1];
+    k0 = (w > y) ? optr[w] : s2k[s] + 1;
+    if (!full) {
+        k0 = lower_bound_i32(ocol, k0, k1, lo);
+        k1 = lower_bound_i32(ocol, k0, k1, hi);
+    }
+}
+
+#define WEDGE_STACK 40   // x-range stack per group (halving depth <= 32 for 31-bit ids)
+#ifndef WEDGE_ILP
+#define WEDGE_ILP 4      // wedges in flight per lane (8 measured slower: registers)
+#endif
+
 // Size classes of the wedge pass (wedges per bottom vertex y): threads per group, groups per
 // block, hash entries, dense top counters.
 #define WW_T 64
@@ -727,11 +728,19 @@ __device__ __forceinline__ int2 runs_at(const RunTables<T>& rt, int p) {
 #define WW_HT 512        // wave class: <= WW_HT / 2 wedges, so the hash never overflows
 #define WM_T 64
 #define WM_G 2       // mid class: 16-bit counters (its bottoms have at most 65,535 wedges)
+#ifndef WM_HT
 #define WM_HT 1024
+#endif
+#ifndef WM_DW
 #define WM_DW 1024
+#endif
 #define WB_T 256
+#ifndef WB_HT
 #define WB_HT 2048
+#endif
+#ifndef WB_DW
 #define WB_DW 4096
+#endif
 #define WH_T 1024        // huge class: a whole CU's LDS for bottom vertices with the most wedges
 #define WH_HT 8192
 #define WH_DW 16384
@@ -939,22 +948,38 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
 #pragma unroll
                         for (int j = 0; j < WEDGE_ILP; j++) {
                             const int x = xs[j];
-                            if (x < 0) continue;
-                            u32 cnt = 1;
-                            if (x >= base) {
-                                cnt = cnt_get<P16>(dc, x - base);
-                            } else {
-                                u32 h = hslot(x, mask);
-                                int p = 0;
-                                while (p < HT && hk[h] != x) { h = (h + 1) & mask; p++; }
-                                if (p < HT) cnt = cnt_get<P16>(hc, (int)h);
-                                else atomicOr(err, ERR_CAP);
+                            AT c = 0;
+                            if (x >= 0) {
+                                u32 cnt = 1;
+                                if (x >= base) {
+                                    cnt = cnt_get<P16>(dc, x - base);
+                                } else {
+                                    u32 h = hslot(x, mask);
+                                    int p = 0;
+                                    while (p < HT && hk[h] != x) { h = (h + 1) & mask; p++; }
+                                    if (p < HT) cnt = cnt_get<P16>(hc, (int)h);
+                                    else atomicOr(err, ERR_CAP);
+                                }
+                                c = (AT)(cnt - 1);
+                                if (c) acc_add<AT>(e.P, ks[j], (u64)c);   // top edge (w, x)
                             }
-                            const AT c = (AT)(cnt - 1);
-                            if (c) {
-                                acc_add<AT>(e.P, ks[j], (u64)c);   // top edge (w, x)
-                                atomicAdd(&sb[is[j]], c);          // bottom edge (y, w), per source
-                            }
+                            // bottom edge (y, w): the wavefront's lanes cover one word of the
+                            // run tables, whose start bits (and every idle lane) delimit the
+                            // sources.  With P the wave's inclusive prefix of c, a source's sum
+                            // is P(last lane) - P(first lane - 1): its first lane subtracts its
+                            // exclusive prefix and its last lane adds its inclusive one
+                            // (modular arithmetic, exact once both have landed).
+                            const int qw = q0 + j * T + (tid & ~(GLT_WAVE - 1));
+                            const int idle = se - qw;   // lanes >= idle have no wedge
+                            u64 F = rt.msk[(qw - sb0) >> 6] | 1ull;
+                            if (idle <= 0) F = ~0ull;
+                            else if (idle < GLT_WAVE) F |= ~0ull << idle;
+                            const int l = glt_lane();
+                            const AT P = wave_incl_scan<AT>(c);
+                            const bool first = (F >> l) & 1;
+                            const bool last = (l == GLT_WAVE - 1) || (((F >> l) >> 1) & 1);
+                            const AT v = (last ? P : (AT)0) - (first ? (AT)(P - c) : (AT)0);
+                            if (v) atomicAdd(&sb[is[j]], v);
                         }
                     }
                 }

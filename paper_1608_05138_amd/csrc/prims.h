@@ -20,14 +20,39 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Cross-lane moves by DPP (GFX9 data-parallel primitives; no LDS traffic).  Lanes whose
+// source is outside the row (row_shr), in a row not named by the row mask (row_bcast), or
+// off the wave's ends (wave_shr / wave_shl) read 0.  Every lane of the wave must be active.
+#define GLT_DPP_ROW_SHR(n) (0x110 + (n))
+#define GLT_DPP_ROW_BCAST15 0x142
+#define GLT_DPP_ROW_BCAST31 0x143
+#define GLT_DPP_WAVE_SHL1 0x130
+#define GLT_DPP_WAVE_SHR1 0x138
+template <int CTRL, int ROWM, bool BC>
+__device__ __forceinline__ u32 dpp_u32(u32 v) {
+    return (u32)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWM, 0xf, BC);
+}
+template <typename T, int CTRL, int ROWM, bool BC>
+__device__ __forceinline__ T dpp_move(T v) {
+    if constexpr (sizeof(T) == 8) {
+        const u32 lo = dpp_u32<CTRL, ROWM, BC>((u32)(u64)v);
+        const u32 hi = dpp_u32<CTRL, ROWM, BC>((u32)((u64)v >> 32));
+        return (T)(((u64)hi << 32) | lo);
+    } else {
+        return (T)dpp_u32<CTRL, ROWM, BC>((u32)v);
+    }
+}
+// Inclusive sum over the lanes of a wavefront (every lane active): shifts by 1, 2, 4, 8
+// inside rows of 16 lanes, then the last lane of row 0 / row 2 into rows 1 / 3 and of row 1
+// into rows 2 and 3.
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
-    const int l = glt_lane();
-#pragma unroll
-    for (int d = 1; d < GLT_WAVE; d <<= 1) {
-        T o = __shfl_up(v, d, GLT_WAVE);
-        if (l >= d) v += o;
-    }
+    v += dpp_move<T, GLT_DPP_ROW_SHR(1), 0xf, true>(v);
+    v += dpp_move<T, GLT_DPP_ROW_SHR(2), 0xf, true>(v);
+    v += dpp_move<T, GLT_DPP_ROW_SHR(4), 0xf, true>(v);
+    v += dpp_move<T, GLT_DPP_ROW_SHR(8), 0xf, true>(v);
+    v += dpp_move<T, GLT_DPP_ROW_BCAST15, 0xa, false>(v);
+    v += dpp_move<T, GLT_DPP_ROW_BCAST31, 0xc, false>(v);
     return v;
 }
 
@@ -48,42 +73,45 @@ __device__ __forceinline__ T wave_max(T v) {
     return v;
 }
 
-// Segmented sum over the lanes of a wavefront whose keys are non-decreasing in lane order:
-// the last lane of each run of equal keys receives the run's sum (is_last is set there).
+// one step of the segmented scan: (v, f) := (v_src, f_src) (+) (v, f), where
+// (a, fa) (+) (b, fb) = (fb ? b : a + b, fa | fb)
+template <typename T, int CTRL, int ROWM, bool BC>
+__device__ __forceinline__ void seg_step(T& v, u32& f) {
+    const T o = dpp_move<T, CTRL, ROWM, BC>(v);
+    const u32 of = dpp_u32<CTRL, ROWM, BC>(f);
+    if (!f) v += o;
+    f |= of;
+}
+// Segmented inclusive sum over the lanes of a wavefront (the moves of wave_incl_scan):
+// `start` marks the first lane of a segment (lane 0 always begins one).
 template <typename T>
-__device__ __forceinline__ T seg_sum_last(T v, int key, bool& is_last) {
-    const int l = glt_lane();
-#pragma unroll
-    for (int d = 1; d < GLT_WAVE; d <<= 1) {
-        const T o = __shfl_up(v, d, GLT_WAVE);
-        const int ko = __shfl_up(key, d, GLT_WAVE);
-        if (l >= d && ko == key) v += o;
-    }
-    const int kn = __shfl_down(key, 1, GLT_WAVE);
-    is_last = (l == GLT_WAVE - 1) || (kn != key);
+__device__ __forceinline__ T wave_seg_sum(T v, bool start) {
+    u32 f = start ? 1u : 0u;
+    seg_step<T, GLT_DPP_ROW_SHR(1), 0xf, true>(v, f);
+    seg_step<T, GLT_DPP_ROW_SHR(2), 0xf, true>(v, f);
+    seg_step<T, GLT_DPP_ROW_SHR(4), 0xf, true>(v, f);
+    seg_step<T, GLT_DPP_ROW_SHR(8), 0xf, true>(v, f);
+    seg_step<T, GLT_DPP_ROW_BCAST15, 0xa, false>(v, f);
+    seg_step<T, GLT_DPP_ROW_BCAST31, 0xc, false>(v, f);
     return v;
 }
 
-// Segmented inclusive sum over maximal runs of equal consecutive keys in a wavefront; a key
-// may recur in separate runs (each run is summed on its own).  is_last marks the last lane of
-// each run, which holds the run's total.
+// Segmented sum over maximal runs of equal consecutive keys in a wavefront (a key may recur
+// in separate runs; each run is summed on its own).  is_last marks the last lane of each
+// run, which holds the run's total.  Every lane must call it (idle lanes: a sentinel key).
 template <typename T>
 __device__ __forceinline__ T seg_run_sum_last(T v, int key, bool& is_last) {
     const int l = glt_lane();
-    const int kp = __shfl_up(key, 1, GLT_WAVE);
-    int f = (l == 0 || kp != key) ? 1 : 0;   // a run starts at or below this lane's span
-#pragma unroll
-    for (int d = 1; d < GLT_WAVE; d <<= 1) {
-        const T o = __shfl_up(v, d, GLT_WAVE);
-        const int of = __shfl_up(f, d, GLT_WAVE);
-        if (l >= d && !f) {
-            v += o;
-            f = of;
-        }
-    }
-    const int kn = __shfl_down(key, 1, GLT_WAVE);
+    const int kp = (int)dpp_u32<GLT_DPP_WAVE_SHR1, 0xf, true>((u32)key);
+    const int kn = (int)dpp_u32<GLT_DPP_WAVE_SHL1, 0xf, true>((u32)key);
     is_last = (l == GLT_WAVE - 1) || (kn != key);
-    return v;
+    return wave_seg_sum(v, l == 0 || kp != key);
+}
+
+// The same for keys that are non-decreasing in lane order.
+template <typename T>
+__device__ __forceinline__ T seg_sum_last(T v, int key, bool& is_last) {
+    return seg_run_sum_last(v, key, is_last);
 }
 
 // Exclusive scan over a block of BLOCK threads.  lds must hold BLOCK/64 elements.  All
