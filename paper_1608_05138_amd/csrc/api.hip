@@ -107,6 +107,7 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
     d.ocol = c.take<int>(m);
     d.s2k = c.take<int>(S);
     d.eid2k = c.take<int>(m);
+    d.wb = c.take<int2>(S);
     d.e.t = c.take<u32>(m);
     d.e.K = c.take<u64>(m);
     d.e.P = c.take<u64>(m);

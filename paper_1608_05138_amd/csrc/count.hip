@@ -704,12 +704,11 @@ __device__ __forceinline__ u32 hslot(int x, u32 mask) { return ((u32)x * 2654435
 
 // Oriented index range [k0, k1) of the wedges y - w - x for CSR slot s of row y (w = ncol[s]),
 // restricted to tops x in [lo, hi) unless the range is the full [y + 1, n).
-__device__ __forceinline__ void wedge_bounds(int y, int s, int lo, int hi, bool full, const int* __restrict__ ncol,
-                                             const int* __restrict__ optr, const int* __restrict__ ocol,
-                                             const int* __restrict__ s2k, int& k0, int& k1) {
-    const int w = ncol[s];
-    k1 = optr[w + 1];
-    k0 = (w > y) ? optr[w] : s2k[s] + 1;
+__device__ __forceinline__ void wedge_bounds(int s, int lo, int hi, bool full, const int2* __restrict__ wb,
+                                             const int* __restrict__ ocol, int& k0, int& k1) {
+    const int2 r = wb[s];
+    k0 = r.x;
+    k1 = r.y;
     if (!full) {
         k0 = lower_bound_i32(ocol, k0, k1, lo);
         k1 = lower_bound_i32(ocol, k0, k1, hi);
@@ -775,7 +774,7 @@ __device__ __forceinline__ u32 cnt_get(const u32* a, int i) {
 template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16>
 __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, int nlist, int n, int limit,
                                                  int dense, const int* __restrict__ nrp,
-                                                 const int* __restrict__ ncol, const int* __restrict__ optr,
+                                                 const int2* __restrict__ wb,
                                                  const int* __restrict__ ocol, const int* __restrict__ s2k,
                                                  const u64* __restrict__ wcnt, EdgeArrays e,
                                                  u64* __restrict__ gsum, const int* __restrict__ ngid,
@@ -837,7 +836,7 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
         for (int c0 = rb; c0 < re; c0 += T) {
             const int s = c0 + tid;
             int k0 = 0, k1 = 0;
-            if (s < re) wedge_bounds(y, s, lo, hi, full, ncol, optr, ocol, s2k, k0, k1);
+            if (s < re) wedge_bounds(s, lo, hi, full, wb, ocol, k0, k1);
             len = k1 - k0;
             int carry;
             const int tot = runs_begin<T>(rt, len, k0, pre, carry);
@@ -921,7 +920,7 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                 int tot = tot1, carry = 0;
                 if (!one) {
                     int k0 = 0, k1 = 0;
-                    if (s < re) wedge_bounds(y, s, lo, hi, full, ncol, optr, ocol, s2k, k0, k1);
+                    if (s < re) wedge_bounds(s, lo, hi, full, wb, ocol, k0, k1);
                     len = k1 - k0;
                     tot = runs_begin<T>(rt, len, k0, pre, carry);
                 }
@@ -1366,7 +1365,7 @@ static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st, int res
     int* counts = d.counts + TB_N;
     const unsigned grid = resident > 0 ? (unsigned)resident : cdiv(cnt, G);
     hipLaunchKernelGGL((k_wedge<PE, AT, T, G, HT, DW, P16>), dim3(grid), dim3(T * G), 0, st,
-                       d.wlist + (int64_t)bkt * d.n, cnt, d.n, limit, d.wedge_dense, d.nrp, d.ncol, d.optr, d.ocol,
+                       d.wlist + (int64_t)bkt * d.n, cnt, d.n, limit, d.wedge_dense, d.nrp, d.wb, d.ocol,
                        d.s2k, d.wcnt, d.e, d.gsum, d.ngid, d.gvb, d.err, resident > 0 ? counts + bkt : nullptr,
                        defer >= 0 ? d.wlist + (int64_t)defer * d.n : nullptr, defer >= 0 ? counts + defer : nullptr,
                        defer >= 0 ? d.wspread + 6 : nullptr);

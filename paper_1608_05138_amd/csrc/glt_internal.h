@@ -86,6 +86,8 @@ struct Dev {
     int* ocol;        // oriented CSR columns [m], ascending
     int* s2k;         // CSR slot -> oriented edge index [S]
     int* eid2k;       // caller edge id -> oriented edge index [m]
+    int2* wb;         // CSR slot s of row y (w = ncol[s]) -> oriented range [k0, k1) of the tops x > y of
+                      // the wedges y - w - x: N+(w), or its part after y when w < y [S]
     EdgeArrays e;     // per-edge accumulators [m] each
     u64* tri;         // twice the triangles at each relabelled vertex [n]
     u64* sdeg;        // sum of neighbour degrees [n]

@@ -517,7 +517,8 @@ __global__ __launch_bounds__(256) void k_tbuckets(const int* __restrict__ optr, 
 // workgroup).  One thread per entry, runs of one row summed in the wavefront.
 __global__ __launch_bounds__(256) void k_wcount(const int* __restrict__ ncol, const int* __restrict__ nsrow,
                                                 const int* __restrict__ optr, const int* __restrict__ s2k, int64_t S,
-                                                u64* __restrict__ wcnt, u64* __restrict__ wspread) {
+                                                u64* __restrict__ wcnt, u64* __restrict__ wspread,
+                                                int2* __restrict__ wb) {
     __shared__ u64 red[2][256 / GLT_WAVE];
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     u64 wc = 0, lw = 0, lb = 0;
@@ -525,8 +526,11 @@ __global__ __launch_bounds__(256) void k_wcount(const int* __restrict__ ncol, co
     if (s < S) {
         y = nsrow[s];
         const int w = ncol[s];
-        const int dpw = optr[w + 1] - optr[w];
-        wc = (u64)((w > y) ? dpw : (optr[w + 1] - s2k[s] - 1));
+        const int w0 = optr[w], w1 = optr[w + 1];
+        const int dpw = w1 - w0;
+        const int k0 = (w > y) ? w0 : s2k[s] + 1;   // the tops of y - w - x lie above y
+        wb[s] = make_int2(k0, w1);
+        wc = (u64)(w1 - k0);
         if (w > y) {
             const int dpy = optr[y + 1] - optr[y];
             if (dpy >= 2 && dpy <= 64) lw = (u64)dpw;
@@ -671,7 +675,7 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
     launch_fill<u64>(d.wcnt, n, 0ull, st);
     if (S > 0)
         hipLaunchKernelGGL(k_wcount, dim3(nblk(S, 256)), dim3(256), 0, st, d.ncol, d.nsrow, d.optr, d.s2k, S, d.wcnt,
-                           d.wspread);
+                           d.wspread, d.wb);
     hipLaunchKernelGGL(k_wappend, dim3(nblk(n, 256)), dim3(256), 0, st, d.wcnt, n, d.wedge_wave_max, d.wedge_mid_max < 65535 ? d.wedge_mid_max : 65535, d.wedge_wg_max, d.wlist,
                        d.counts + TB_N, d.wspread);
     return 0;
