@@ -40,6 +40,32 @@ __device__ __forceinline__ u64 acc_get(const u64* base, int64_t k) {
     return (u64)((const AT*)base)[k];
 }
 
+// g and sigma of an edge: with 32-bit accumulators the pair shares one 64-bit word of the g
+// buffer (g low, sigma high), so both move with one atomic; each half stays below 2^32 (the
+// host picks 32 bits only when every such count does), so no carry crosses the halves.
+// With 64-bit accumulators they are separate arrays.
+template <typename AT>
+__device__ __forceinline__ void gsig_add(EdgeArrays& e, int64_t k, u64 g, u64 sig) {
+    if constexpr (sizeof(AT) == 4) {
+        const u64 v = (sig << 32) | g;
+        if (v) atomicAdd(&e.g[k], v);
+    } else {
+        if (g) atomicAdd(&e.g[k], g);
+        if (sig) atomicAdd(&e.sig[k], sig);
+    }
+}
+template <typename AT>
+__device__ __forceinline__ void gsig_get(const EdgeArrays& e, int64_t k, u64& g, u64& sig) {
+    if constexpr (sizeof(AT) == 4) {
+        const u64 v = e.g[k];
+        g = v & 0xffffffffull;
+        sig = v >> 32;
+    } else {
+        g = e.g[k];
+        sig = e.sig[k];
+    }
+}
+
 #define TB_THREADS 256
 #ifndef TRI_ILP
 #define TRI_ILP 4      // out-list entries per lane in flight in the triangle passes (8: more registers, slower)
@@ -424,25 +450,32 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
     // triangle's three edges (the two at a are summed per source in LDS)
     if (REC) {
         const int nrec = sNrec;
-        for (int r0 = 0; r0 < nrec; r0 += TB_THREADS) {
-            const int r = r0 + tid;
-            int ri = 0x7fffffff;
-            u64 tk = 0;
-            if (r < nrec) {
-                int rj, k;
-                tri_unrec(rec[r], ri, rj, k);
-                for (int wd = 0; wd < W; wd++) tk += (u64)__popc(M[ri * W + wd] & M[rj * W + wd]);
-                atomicAdd(&e.t[k], 1u);
-                if (PE && tk) {
-                    acc_add<AT>(e.K, k, tk);
-                    atomicAdd(&sK[rj], tk);
-                }
-                k4 += tk;
+        constexpr int CR = 4;   // records per thread and round, loaded together
+        for (int r0 = 0; r0 < nrec; r0 += CR * TB_THREADS) {
+            int ri[CR], rj[CR], rk[CR];
+#pragma unroll
+            for (int u = 0; u < CR; u++) {
+                const int r = r0 + u * TB_THREADS + tid;
+                ri[u] = 0x7fffffff; rj[u] = 0; rk[u] = -1;
+                if (r < nrec) tri_unrec(rec[r], ri[u], rj[u], rk[u]);
             }
-            if (PE) {   // records come in runs of equal i (per writing wavefront)
-                bool last;
-                const u64 ssum = seg_run_sum_last(tk, ri, last);
-                if (last && ssum) atomicAdd(&sK[ri], ssum);
+#pragma unroll
+            for (int u = 0; u < CR; u++) {
+                u64 tk = 0;
+                if (rk[u] >= 0) {
+                    for (int wd = 0; wd < W; wd++) tk += (u64)__popc(M[ri[u] * W + wd] & M[rj[u] * W + wd]);
+                    atomicAdd(&e.t[rk[u]], 1u);
+                    if (PE && tk) {
+                        acc_add<AT>(e.K, rk[u], tk);
+                        atomicAdd(&sK[rj[u]], tk);
+                    }
+                    k4 += tk;
+                }
+                if (PE) {   // records come in runs of equal i (per writing wavefront)
+                    bool last;
+                    const u64 ssum = seg_run_sum_last(tk, ri[u], last);
+                    if (last && ssum) atomicAdd(&sK[ri[u]], ssum);
+                }
             }
         }
         if (tid == 0) tcnt[a] = nrec;
@@ -514,21 +547,19 @@ static inline size_t tri_blk_lds(int smax, bool gm) {
 //   edge (a, b_i): g += t(a, b_j) + t(b_i, b_j), sig += d(b_j)   [local, run-summed]
 //   edge (a, b_j): g += t(a, b_i) + t(b_i, b_j), sig += d(b_i)   [local]
 //   edge (b_i, b_j): g += t(a, b_i) + t(a, b_j), sig += d(a)     [global, coalesced]
-// Runs of equal i in the wavefront are summed first (every lane must call; idle lanes pass
-// a sentinel key and found = false).
+// tij = t of edge k = (b_i, b_j).  Runs of equal i in the wavefront are summed first (every
+// lane must call; idle lanes pass a sentinel key and found = false).
 template <typename AT>
-__device__ __forceinline__ void gather_credit(bool found, int i, int j, int k, const u32* sT, const int* sD, int da,
-                                              EdgeArrays& e, u64* sG, u64* sSg) {
+__device__ __forceinline__ void gather_credit(bool found, int i, int j, int k, u64 tij, const u32* sT, const int* sD,
+                                              int da, EdgeArrays& e, u64* sG, u64* sSg) {
     u64 gi = 0, di = 0;
     if (found) {
-        const u64 tij = e.t[k];
         const u64 tai = sT[i], taj = sT[j];
         gi = taj + tij;
         di = (u64)sD[j];
         atomicAdd(&sG[j], tai + tij);
         atomicAdd(&sSg[j], (u64)sD[i]);
-        acc_add<AT>(e.g, k, tai + taj);
-        acc_add<AT>(e.sig, k, (u64)da);
+        gsig_add<AT>(e, k, tai + taj, (u64)da);
     }
     bool last;
     const u64 a1 = seg_run_sum_last(gi, i, last);
@@ -566,6 +597,22 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
     const int o0 = optr[a];
     const int s = optr[a + 1] - o0;
     const int da = ndeg[a];
+    // REC: GR rounds of records (and the t of each triangle's third edge) are loaded before
+    // the setup, so that both chains of loads are in flight together
+    constexpr int GR = 2;
+    int ri[GR], rj[GR], rk[GR];
+    u32 rt3[GR];
+    const u64* rec = REC ? trec + toff[a] : nullptr;
+    if (REC) {
+#pragma unroll
+        for (int u = 0; u < GR; u++) {
+            const int r = u * GLT_WAVE + l;
+            ri[u] = 0x3fffffff; rj[u] = -1; rk[u] = 0;
+            if (r < nh) tri_unrec(rec[r], ri[u], rj[u], rk[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < GR; u++) rt3[u] = (u * GLT_WAVE + l < nh) ? e.t[rk[u]] : 0u;
+    }
     int b = 0, ob = 0, db = 0;
     u32 tb = 0;
     int degb = 0;
@@ -579,12 +626,15 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
     sG[w][l] = 0; sSg[w][l] = 0;
     if (REC) {
         wave_sync();
-        const u64* rec = trec + toff[a];
-        for (int r0 = 0; r0 < nh; r0 += GLT_WAVE) {
+#pragma unroll
+        for (int u = 0; u < GR; u++)
+            gather_credit<AT>(u * GLT_WAVE + l < nh, ri[u], rj[u], rk[u], rt3[u], sT[w], sD[w], da, e, sG[w],
+                              sSg[w]);
+        for (int r0 = GR * GLT_WAVE; r0 < nh; r0 += GLT_WAVE) {
             const int r = r0 + l;
             int i = 0x3fffffff, j = -1, k = 0;
             if (r < nh) tri_unrec(rec[r], i, j, k);
-            gather_credit<AT>(r < nh, i, j, k, sT[w], sD[w], da, e, sG[w], sSg[w]);
+            gather_credit<AT>(r < nh, i, j, k, r < nh ? (u64)e.t[k] : 0ull, sT[w], sD[w], da, e, sG[w], sSg[w]);
         }
     } else {
         RunTables<GLT_WAVE>& rt = sRT[REC ? 0 : w];
@@ -605,14 +655,13 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
                     k = q + r.x;
                     j = sh_find(hk[w], hv[w], ocol[k]);
                 }
-                gather_credit<AT>(j >= 0, i, j, k, sT[w], sD[w], da, e, sG[w], sSg[w]);
+                gather_credit<AT>(j >= 0, i, j, k, j >= 0 ? (u64)e.t[k] : 0ull, sT[w], sD[w], da, e, sG[w], sSg[w]);
             }
         }
     }
     wave_sync();
     if (l < s) {
-        if (sG[w][l]) acc_add<AT>(e.g, o0 + l, sG[w][l]);
-        if (sSg[w][l]) acc_add<AT>(e.sig, o0 + l, sSg[w][l]);
+        gsig_add<AT>(e, o0 + l, sG[w][l], sSg[w][l]);
     }
 }
 
@@ -636,9 +685,28 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict
     u64* sSg = sG + smax;
     const int tid = threadIdx.x;
     const int a = list[blockIdx.x];
+    const int nh = REC ? tcnt[a] : 0;
+    if (REC && nh == 0) return;   // no triangle has a as its lowest vertex (uniform per block)
     const int o0 = optr[a];
     const int s = optr[a + 1] - o0;
     const int da = ndeg[a];
+    // REC: GR records per thread and round, each with the t of its third edge; the first
+    // round's loads go out before the setup
+    constexpr int GR = 4;
+    const u64* rec = REC ? trec + toff[a] : nullptr;
+    int ri[GR], rj[GR], rk[GR];
+    u32 rt3[GR];
+    auto load_round = [&](int r0) {
+#pragma unroll
+        for (int u = 0; u < GR; u++) {
+            const int r = r0 + u * TB_THREADS + tid;
+            ri[u] = 0x3fffffff; rj[u] = -1; rk[u] = 0;
+            if (r < nh) tri_unrec(rec[r], ri[u], rj[u], rk[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < GR; u++) rt3[u] = (r0 + u * TB_THREADS + tid < nh) ? e.t[rk[u]] : 0u;
+    };
+    if (REC) load_round(0);
     for (int i = tid; i < s; i += TB_THREADS) {
         const int b = ocol[o0 + i];
         const int ob = optr[b];
@@ -648,13 +716,12 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict
     __syncthreads();
     if (REC) {
         // records come in runs of equal i (per writing wavefront), summed per run
-        const int nh = tcnt[a];
-        const u64* rec = trec + toff[a];
-        for (int r0 = 0; r0 < nh; r0 += TB_THREADS) {
-            const int r = r0 + tid;
-            int i = 0x3fffffff, j = -1, k = 0;
-            if (r < nh) tri_unrec(rec[r], i, j, k);
-            gather_credit<AT>(r < nh, i, j, k, sT, sD, da, e, sG, sSg);
+        for (int r0 = 0; r0 < nh; r0 += GR * TB_THREADS) {
+            if (r0 > 0) load_round(r0);
+#pragma unroll
+            for (int u = 0; u < GR; u++)
+                gather_credit<AT>(r0 + u * TB_THREADS + tid < nh, ri[u], rj[u], rk[u], rt3[u], sT, sD, da, e, sG,
+                                  sSg);
         }
     } else {
         if constexpr (!REC) {
@@ -679,7 +746,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict
                             j = lower_bound_i32(sS, i + 1, s, x);
                             found = (j < s && sS[j] == x);
                         }
-                        gather_credit<AT>(found, i, j, k, sT, sD, da, e, sG, sSg);
+                        gather_credit<AT>(found, i, j, k, found ? (u64)e.t[k] : 0ull, sT, sD, da, e, sG, sSg);
                     }
                 }
                 __syncthreads();
@@ -688,8 +755,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict
     }
     __syncthreads();
     for (int i = tid; i < s; i += TB_THREADS) {
-        if (sG[i]) acc_add<AT>(e.g, o0 + i, sG[i]);
-        if (sSg[i]) acc_add<AT>(e.sig, o0 + i, sSg[i]);
+        gsig_add<AT>(e, o0 + i, sG[i], sSg[i]);
     }
 }
 
@@ -1070,9 +1136,11 @@ __global__ __launch_bounds__(CB_THREADS) void k_combine(const int* __restrict__ 
         if (PE) {
             K = (int64_t)acc_get<AT>(e.K, k);
             const int64_t P = (int64_t)acc_get<AT>(e.P, k);
-            const int64_t A = (int64_t)acc_get<AT>(e.g, k) - 2 * t - 4 * K;     // edges T-S_u plus T-S_v
+            u64 gk, sk;
+            gsig_get<AT>(e, k, gk, sk);
+            const int64_t A = (int64_t)gk - 2 * t - 4 * K;     // edges T-S_u plus T-S_v
             Q = P - 2 * K - A;                                      // edges S_u-S_v
-            const int64_t sigT = (int64_t)acc_get<AT>(e.sig, k);
+            const int64_t sigT = (int64_t)sk;
             const int64_t E2 = (int64_t)((tri[u] + tri[v]) >> 1) - 2 * t - 2 * K - A;   // inside S_u plus inside S_v
             const int64_t ETD = sigT - 2 * t - 2 * K - A;           // edges T-D
             const int64_t ESD = ((int64_t)sdeg[u] - dv - sigT) + ((int64_t)sdeg[v] - du - sigT) - su - sv - 2 * E2 - A -

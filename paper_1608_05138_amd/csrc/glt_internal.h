@@ -34,8 +34,9 @@ struct EdgeArrays {
     u32* t;      // triangles on the edge
     u64* K;      // 4-cliques on the edge (edges inside T)
     u64* P;      // non-induced 4-cycles through the edge
-    u64* g;      // sum over w in T of t(w,u) + t(w,v)
-    u64* sig;    // sum over w in T of d_w
+    u64* g;      // sum over w in T of t(w,u) + t(w,v); with 32-bit accumulators each word holds
+                 // g (low half) and sig (high half) of its edge
+    u64* sig;    // sum over w in T of d_w (64-bit accumulators only)
     int* u;      // lower-ranked endpoint (relabelled id); the other one is ocol[k]
 };
 
