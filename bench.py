@@ -28,11 +28,11 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # source with the hash below and are reported only while it is unchanged.
 TRAFFIC = {
     "source": "paper_1608_05138_amd/csrc/count.hip",
-    "sha256": "7944400a8cc737fd1c130540f05f3560d02bdc2307f6728633d89ce49950bbd8",
+    "sha256": "b1020b16e085dd9fbe53eb53c98c809a4c786a9b97dc9ac5437ade9efb6e56b0",
     "workload": "chung_lu_1m", "per_edge": True,
-    "bytes": {"tri_wave": 3670049408, "tri_wg": 4390950784, "gather_wave": 1886630784,
-              "gather_wg": 3390846464, "wedge_wave": 99581376, "wedge_mid": 3898080288,
-              "wedge_wg": 10287631712, "wedge_huge": 38912},
+    "bytes": {"tri_wave": 3672835264, "tri_wg": 4390485376, "gather_wave": 1485096192,
+              "gather_wg": 2861392544, "wedge_wave": 82168384, "wedge_mid": 3570422304,
+              "wedge_wg": 9070377312, "wedge_huge": 40960},
 }
 
 

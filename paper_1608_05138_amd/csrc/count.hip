@@ -1026,23 +1026,23 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                                     else atomicOr(err, ERR_CAP);
                                 }
                                 c = (AT)(cnt - 1);
-                                if (c) acc_add<AT>(e.P, ks[j], (u64)c);   // top edge (w, x)
                             }
-                            // bottom edge (y, w): the wavefront's lanes cover one word of the
-                            // run tables, whose start bits (and every idle lane) delimit the
-                            // sources.  With P the wave's inclusive prefix of c, a source's sum
-                            // is P(last lane) - P(first lane - 1): its first lane subtracts its
-                            // exclusive prefix and its last lane adds its inclusive one
-                            // (modular arithmetic, exact once both have landed).
+                            // the wavefront's lanes cover one word of the run tables, whose start
+                            // bits (and every idle lane) delimit the sources
                             const int qw = q0 + j * T + (tid & ~(GLT_WAVE - 1));
                             const int idle = se - qw;   // lanes >= idle have no wedge
                             u64 F = rt.msk[(qw - sb0) >> 6] | 1ull;
                             if (idle <= 0) F = ~0ull;
                             else if (idle < GLT_WAVE) F |= ~0ull << idle;
                             const int l = glt_lane();
-                            const AT P = wave_incl_scan<AT>(c);
                             const bool first = (F >> l) & 1;
                             const bool last = (l == GLT_WAVE - 1) || (((F >> l) >> 1) & 1);
+                            if (c) acc_add<AT>(e.P, ks[j], (u64)c);   // top edge (w, x)
+                            // bottom edge (y, w): with P the wave's inclusive prefix of c, a
+                            // source's sum is P(last lane) - P(first lane - 1): its first lane
+                            // subtracts its exclusive prefix and its last lane adds its inclusive
+                            // one (modular arithmetic, exact once both have landed)
+                            const AT P = wave_incl_scan<AT>(c);
                             const AT v = (last ? P : (AT)0) - (first ? (AT)(P - c) : (AT)0);
                             if (v) atomicAdd(&sb[is[j]], v);
                         }
