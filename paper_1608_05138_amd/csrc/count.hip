@@ -158,9 +158,12 @@ __device__ __forceinline__ int2 runs_at(const RunTables<T>& rt, int p) {
 // ---------------------------------------------------------------------------------------
 // triangle / 4-clique pass, out-degree 2..64: one wavefront per vertex, M rows in one word
 // ---------------------------------------------------------------------------------------
-// Membership of a vertex id in S = N+(a) (s <= 64) through a 128-entry LDS hash per
-// wavefront mapping id -> position in S.
-#define SH_SIZE 128
+// Membership of a vertex id in S = N+(a) (s <= 64) through an LDS hash per wavefront mapping
+// id -> position in S.  Most probes miss, so the table is kept sparse (a miss usually costs
+// one read).
+#ifndef SH_SIZE
+#define SH_SIZE 256
+#endif
 __device__ __forceinline__ u32 shash(int x) { return ((u32)x * 2654435761u >> 9) & (SH_SIZE - 1); }
 
 __device__ __forceinline__ void sh_insert(int* hk, unsigned char* hv, int x, int pos) {
@@ -180,10 +183,17 @@ __device__ __forceinline__ int sh_find(const int* hk, const unsigned char* hv, i
 }
 
 // Entries of the LDS hash over S = N+(a) in the workgroup triangle pass: a power of two
-// >= 2 |S| (load <= 1/2).
+// >= F |S| (load <= 1/F), sparser for the smaller buckets where LDS allows.
+#ifndef TRI_HT_F
+#define TRI_HT_F 2
+#endif
+#ifndef TRI_HT_F2
+#define TRI_HT_F2 2
+#endif
 __host__ __device__ inline int tri_blk_ht(int smax) {
+    const int f = smax <= 256 ? TRI_HT_F : smax <= 640 ? TRI_HT_F2 : 2;
     int h = 64;
-    while (h < 2 * smax) h <<= 1;
+    while (h < f * smax) h <<= 1;
     return h;
 }
 
@@ -236,7 +246,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__
     if (l < s) { b = ocol[o0 + l]; ob = optr[b]; db = optr[b + 1] - ob; }
     RunTables<GLT_WAVE>& rt = sRT[w];
     sM[w][l] = 0; sK[w][l] = 0;
-    hk[w][l] = -1; hk[w][l + GLT_WAVE] = -1;
+    for (int q = l; q < SH_SIZE; q += GLT_WAVE) hk[w][q] = -1;
     // runs: the out-list of b_l for every l; positions enumerate N+(b_0), N+(b_1), ...
     int pre, carry;
     const int total = runs_begin<GLT_WAVE>(rt, db, ob, pre, carry);
@@ -638,7 +648,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
         }
     } else {
         RunTables<GLT_WAVE>& rt = sRT[REC ? 0 : w];
-        hk[w][l] = -1; hk[w][l + GLT_WAVE] = -1;
+        for (int q = l; q < SH_SIZE; q += GLT_WAVE) hk[w][q] = -1;
         int pre, carry;
         const int total = runs_begin<GLT_WAVE>(rt, db, ob, pre, carry);
         if (l < s) sh_insert(hk[w], hv[w], b, l);
