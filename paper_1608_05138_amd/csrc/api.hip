@@ -103,6 +103,7 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
     d.nrp = c.take<int>(n + 1);
     d.dlo = c.take<int>(n);
     d.optr = c.take<int>(n + 1);
+    d.vinf = c.take<int4>(n);
     d.ncol = c.take<int>(S);
     d.ocol = c.take<int>(m);
     d.s2k = c.take<int>(S);
@@ -155,7 +156,10 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
         sg.out = nullptr;
         (void)host_in;
         (void)local_rp_len;
+        d.erec = d.vrec = nullptr;
     } else {
+        d.erec = c.take<u64>(4 * (int64_t)m);
+        d.vrec = c.take<u64>(4 * (int64_t)n);
         d.gid = d.ngid = nullptr;
         d.gvb = d.gsb = nullptr;
         d.gparts = nullptr;

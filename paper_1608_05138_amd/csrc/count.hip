@@ -1120,13 +1120,57 @@ __device__ __forceinline__ void wave_sum128(u64& lo, u64& hi) {
 #define CB_EPT 4
 #define NCS 13
 
-template <bool PE, typename AT>
+// The combine walks the edges in the caller's order, so its reads of the edge and vertex
+// arrays are scattered.  With 32-bit accumulators they are first packed, in oriented-edge
+// and vertex order (coalesced), into one 32-byte record per edge and per vertex: the
+// combine then gathers three records per edge instead of a dozen scattered words.
+struct __align__(32) ERec {
+    int u, v;
+    u32 t, K, P, pad;
+    u64 gsig;   // g (low half), sigma (high half)
+};
+struct __align__(32) VRec {
+    u64 tri, sdeg;
+    int deg, pad[3];
+};
+
+__global__ __launch_bounds__(256) void k_pack_edges(EdgeArrays e, const int* __restrict__ ocol, int m,
+                                                    ERec* __restrict__ er) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    ERec r;
+    r.u = e.u[k];
+    r.v = ocol[k];
+    r.t = e.t[k];
+    r.K = ((const u32*)e.K)[k];
+    r.P = ((const u32*)e.P)[k];
+    r.pad = 0;
+    r.gsig = e.g[k];
+    er[k] = r;
+}
+
+__global__ __launch_bounds__(256) void k_pack_vertices(const u64* __restrict__ tri, const u64* __restrict__ sdeg,
+                                                       const int* __restrict__ ndeg, int n, VRec* __restrict__ vr) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    VRec r;
+    r.tri = tri[x];
+    r.sdeg = sdeg[x];
+    r.deg = ndeg[x];
+    r.pad[0] = r.pad[1] = r.pad[2] = 0;
+    vr[x] = r;
+}
+
+// PK: per-edge inputs from the packed records (per-edge mode with 32-bit accumulators).
+template <bool PE, typename AT, bool PK>
 __global__ __launch_bounds__(CB_THREADS) void k_combine(const int* __restrict__ eid2k, EdgeArrays e,
                                                         const int* __restrict__ ocol,
                                                         const int* __restrict__ ndeg, const u64* __restrict__ tri,
-                                                        const u64* __restrict__ sdeg, int n, int m,
+                                                        const u64* __restrict__ sdeg, const ERec* __restrict__ er,
+                                                        const VRec* __restrict__ vr, int n, int m,
                                                         u64* __restrict__ out, u64* __restrict__ part,
                                                         int* __restrict__ err) {
+    static_assert(!PK || (PE && sizeof(AT) == 4), "packed records hold 32-bit accumulators");
     __shared__ u64 red[CB_THREADS / GLT_WAVE][NCS][2];
     u64 lo[NCS], hi[NCS];
 #pragma unroll
@@ -1137,23 +1181,40 @@ __global__ __launch_bounds__(CB_THREADS) void k_combine(const int* __restrict__ 
         const int64_t eid = e0 + (int64_t)r * CB_THREADS + threadIdx.x;
         if (eid >= m) break;
         const int k = eid2k[eid];
-        const int u = e.u[k], v = ocol[k];
-        const int64_t du = ndeg[u], dv = ndeg[v];
-        const int64_t t = e.t[k];
+        int u, v;
+        int64_t du, dv, t, Kk = 0, Pk = 0, triu = 0, triv = 0, sdu = 0, sdv = 0;
+        u64 gk = 0, sk = 0;
+        if constexpr (PK) {
+            const ERec r = er[k];
+            u = r.u; v = r.v;
+            const VRec a = vr[u], b = vr[v];
+            du = a.deg; dv = b.deg;
+            t = r.t; Kk = r.K; Pk = r.P;
+            gk = r.gsig & 0xffffffffull; sk = r.gsig >> 32;
+            triu = (int64_t)a.tri; triv = (int64_t)b.tri; sdu = (int64_t)a.sdeg; sdv = (int64_t)b.sdeg;
+        } else {
+            u = e.u[k]; v = ocol[k];
+            du = ndeg[u]; dv = ndeg[v];
+            t = e.t[k];
+            if (PE) {
+                Kk = (int64_t)acc_get<AT>(e.K, k);
+                Pk = (int64_t)acc_get<AT>(e.P, k);
+                gsig_get<AT>(e, k, gk, sk);
+                triu = (int64_t)tri[u]; triv = (int64_t)tri[v]; sdu = (int64_t)sdeg[u]; sdv = (int64_t)sdeg[v];
+            }
+        }
         const int64_t su = du - 1 - t, sv = dv - 1 - t;
         const int64_t D = (int64_t)n - 2 - t - su - sv;
         int64_t K = 0, Q = 0;
         if (PE) {
-            K = (int64_t)acc_get<AT>(e.K, k);
-            const int64_t P = (int64_t)acc_get<AT>(e.P, k);
-            u64 gk, sk;
-            gsig_get<AT>(e, k, gk, sk);
+            K = Kk;
+            const int64_t P = Pk;
             const int64_t A = (int64_t)gk - 2 * t - 4 * K;     // edges T-S_u plus T-S_v
             Q = P - 2 * K - A;                                      // edges S_u-S_v
             const int64_t sigT = (int64_t)sk;
-            const int64_t E2 = (int64_t)((tri[u] + tri[v]) >> 1) - 2 * t - 2 * K - A;   // inside S_u plus inside S_v
+            const int64_t E2 = ((triu + triv) >> 1) - 2 * t - 2 * K - A;   // inside S_u plus inside S_v
             const int64_t ETD = sigT - 2 * t - 2 * K - A;           // edges T-D
-            const int64_t ESD = ((int64_t)sdeg[u] - dv - sigT) + ((int64_t)sdeg[v] - du - sigT) - su - sv - 2 * E2 - A -
+            const int64_t ESD = (sdu - dv - sigT) + (sdv - du - sigT) - su - sv - 2 * E2 - A -
                                 2 * Q;                              // edges S_u-D plus S_v-D
             const int64_t EDD = (int64_t)m - 1 - 2 * t - su - sv - (K + E2 + A + Q + ETD + ESD);
             int64_t x[13];
@@ -1574,12 +1635,21 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
         hipLaunchKernelGGL(k_combine_graphs, dim3(d.ngraphs), dim3(CB_THREADS), 0, st, d.gvb, d.gsb, d.eid2k, e,
                            d.ocol, d.ndeg, d.gparts);
     } else if (m > 0) {
-        if (per_edge)
-            hipLaunchKernelGGL((k_combine<true, AT>), dim3(nb), dim3(CB_THREADS), 0, st, d.eid2k, e, d.ocol, d.ndeg, d.tri,
-                               d.sdeg, n, m, out_pe, d.sums, d.err);
-        else
-            hipLaunchKernelGGL((k_combine<false, AT>), dim3(nb), dim3(CB_THREADS), 0, st, d.eid2k, e, d.ocol, d.ndeg, d.tri,
-                               d.sdeg, n, m, out_pe, d.sums, d.err);
+        ERec* er = (ERec*)d.erec;
+        VRec* vr = (VRec*)d.vrec;
+        if (per_edge && sizeof(AT) == 4 && er && vr) {
+            hipLaunchKernelGGL(k_pack_edges, dim3(cdiv(m, 256)), dim3(256), 0, st, e, d.ocol, m, er);
+            hipLaunchKernelGGL(k_pack_vertices, dim3(cdiv(n, 256)), dim3(256), 0, st, d.tri, d.sdeg, d.ndeg, n, vr);
+            if constexpr (sizeof(AT) == 4)
+                hipLaunchKernelGGL((k_combine<true, AT, true>), dim3(nb), dim3(CB_THREADS), 0, st, d.eid2k, e, d.ocol,
+                                   d.ndeg, d.tri, d.sdeg, er, vr, n, m, out_pe, d.sums, d.err);
+        } else if (per_edge) {
+            hipLaunchKernelGGL((k_combine<true, AT, false>), dim3(nb), dim3(CB_THREADS), 0, st, d.eid2k, e, d.ocol,
+                               d.ndeg, d.tri, d.sdeg, er, vr, n, m, out_pe, d.sums, d.err);
+        } else {
+            hipLaunchKernelGGL((k_combine<false, AT, false>), dim3(nb), dim3(CB_THREADS), 0, st, d.eid2k, e, d.ocol,
+                               d.ndeg, d.tri, d.sdeg, er, vr, n, m, out_pe, d.sums, d.err);
+        }
         hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, d.sums, nb, d.final_sums);
     } else {
         launch_fill<u64>(d.final_sums, 2 * NCS, 0ull, st);

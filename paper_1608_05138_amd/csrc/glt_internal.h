@@ -84,6 +84,7 @@ struct Dev {
     int* ncol;        // relabelled CSR columns [S], ascending within a row
     int* dlo;         // number of lower-ranked neighbours of each vertex
     int* optr;        // oriented (upward) CSR offsets [n+1]
+    int4* vinf;       // per vertex: first upward slot, row end, optr, original id [n]
     int* ocol;        // oriented CSR columns [m], ascending
     int* s2k;         // CSR slot -> oriented edge index [S]
     int* eid2k;       // caller edge id -> oriented edge index [m]
@@ -91,6 +92,8 @@ struct Dev {
                       // the wedges y - w - x: N+(w), or its part after y when w < y [S]
     EdgeArrays e;     // per-edge accumulators [m] each
     u64* tri;         // twice the triangles at each relabelled vertex [n]
+    u64* erec;        // per-edge combine records, 32 bytes per oriented edge [4m] (single graphs)
+    u64* vrec;        // per-vertex combine records, 32 bytes per vertex [4n] (single graphs)
     u64* sdeg;        // sum of neighbour degrees [n]
     int* tlist;       // triangle-pass vertex lists, TB_N segments of n
     u64* toff;        // [n+1] triangle-record slots before vertex a: prefix of C(|N+(a)|, 2)

@@ -433,26 +433,36 @@ __global__ void k_dlo(const int* __restrict__ nrp, const int* __restrict__ ncol,
     dplus[x] = e - p;
 }
 
+// Per vertex x: (first upward slot nrp[x] + dlo[x], row end nrp[x + 1], optr[x], order[x]),
+// one 16-byte record, so that an entry's scattered look-up of its other endpoint reads one
+// line instead of four arrays.
+__global__ __launch_bounds__(256) void k_vinfo(const int* __restrict__ nrp, const int* __restrict__ dlo,
+                                               const int* __restrict__ optr, const int* __restrict__ order, int n,
+                                               int4* __restrict__ vinf) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) vinf[x] = make_int4(nrp[x] + dlo[x], nrp[x + 1], optr[x], order[x]);
+}
+
 // One thread per relabelled entry.  Upward entries (x -> y, y > x) copy themselves into the
 // oriented CSR at index k and clear the edge's accumulators; downward entries find their
 // edge's k by binary search of x in N+(y), map themselves to k and name the caller's edge
 // id of k.
-__global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ nrp, const int* __restrict__ ncol,
-                                                    const int* __restrict__ nsrow, const int* __restrict__ dlo,
-                                                    const int* __restrict__ optr, const int* __restrict__ order,
-                                                    const u32* __restrict__ oslot, const u32* __restrict__ upx,
-                                                    int64_t S, int m, int* __restrict__ ocol, int* __restrict__ s2k,
+__global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ ncol, const int* __restrict__ nsrow,
+                                                    const int4* __restrict__ vinf, const u32* __restrict__ oslot,
+                                                    const u32* __restrict__ upx, int64_t S, int m,
+                                                    int* __restrict__ ocol, int* __restrict__ s2k,
                                                     int* __restrict__ eid2k, EdgeArrays ea, int* __restrict__ err) {
     const int64_t s64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int bad = 0;
     if (s64 < S) {
         const int s = (int)s64;
         const int x = nsrow[s];
-        const int ub = nrp[x] + dlo[x];
+        const int4 vx = vinf[x];
+        const int ub = vx.x;
         const int y = ncol[s];
         if (s >= ub) {
             // upward x -> y: its own oriented slot
-            const int k = optr[x] + (s - ub);
+            const int k = vx.z + (s - ub);
             if (k >= m) {
                 bad = ERR_ASYM;   // more upward than downward entries
             } else {
@@ -463,14 +473,15 @@ __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ nrp,
         } else {
             // downward x -> y (y ranked below x): the edge's slot is x's place in N+(y), a short
             // list (out-degrees are bounded by sqrt(2m) in the degree order)
-            const int yb = nrp[y] + dlo[y], ye = nrp[y + 1];
+            const int4 vy = vinf[y];
+            const int yb = vy.x, ye = vy.y;
             const int sp = lower_bound_i32(ncol, yb, ye, x);
-            const int k = optr[y] + (sp - yb);
+            const int k = vy.z + (sp - yb);
             if (sp >= ye || ncol[sp] != x || k >= m) {
                 bad = ERR_ASYM;
             } else {
                 s2k[s] = k;
-                const u32 j = (order[x] < order[y]) ? oslot[s] : oslot[sp];
+                const u32 j = (vx.w < vy.w) ? oslot[s] : oslot[sp];
                 const u32 eid = upx[j];
                 if (eid >= (u32)m) bad = ERR_ASYM;
                 else eid2k[eid] = k;
@@ -665,9 +676,11 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
     int* dplus = d.itmp + scan_tmp_elems(S + n + 1);  // past the scan scratch
     hipLaunchKernelGGL(k_dlo, dim3(nblk(n, 256)), dim3(256), 0, st, d.nrp, d.ncol, n, d.dlo, dplus);
     launch_excl_scan<int, int>(dplus, d.optr, n, d.itmp, d.optr + n, st);
-    if (S > 0)
-        hipLaunchKernelGGL(k_edge_index, dim3(nblk(S, 256)), dim3(256), 0, st, d.nrp, d.ncol, d.nsrow, d.dlo, d.optr,
-                           d.order, oslot, d.upx, S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.err);
+    if (S > 0) {
+        hipLaunchKernelGGL(k_vinfo, dim3(nblk(n, 256)), dim3(256), 0, st, d.nrp, d.dlo, d.optr, d.order, n, d.vinf);
+        hipLaunchKernelGGL(k_edge_index, dim3(nblk(S, 256)), dim3(256), 0, st, d.ncol, d.nsrow, d.vinf, oslot, d.upx,
+                           S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.err);
+    }
     // work lists
     hipLaunchKernelGGL(k_tbuckets, dim3(nblk(n, 256)), dim3(256), 0, st, d.optr, n, d.tlist, d.counts,
                        d.counts + TB_N + WB_N, d.toff);
