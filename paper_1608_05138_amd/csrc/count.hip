@@ -1276,30 +1276,39 @@ __global__ __launch_bounds__(CB_THREADS) void k_combine(const int* __restrict__ 
 }
 
 // one workgroup: final 128-bit reduction of the per-block partials
-__global__ __launch_bounds__(256) void k_reduce_parts(const u64* __restrict__ part, int nparts,
-                                                      u64* __restrict__ fin) {
-    __shared__ u64 red[256 / GLT_WAVE][2];
+__global__ __launch_bounds__(1024) void k_reduce_parts(const u64* __restrict__ part, int nparts,
+                                                       u64* __restrict__ fin) {
+    __shared__ u64 red[1024 / GLT_WAVE][NCS][2];
+    u64 lo[NCS], hi[NCS];
+#pragma unroll
+    for (int c = 0; c < NCS; c++) { lo[c] = 0; hi[c] = 0; }
+    // each thread sums whole partial records (all NCS sums of one block are contiguous)
+    for (int b = threadIdx.x; b < nparts; b += 1024) {
+        const u64* p = part + (int64_t)b * NCS * 2;
+#pragma unroll
+        for (int c = 0; c < NCS; c++) {
+            const u64 o = lo[c];
+            lo[c] += p[2 * c];
+            hi[c] += p[2 * c + 1] + ((lo[c] < o) ? 1ull : 0ull);
+        }
+    }
+    const int w = threadIdx.x / GLT_WAVE;
+#pragma unroll
     for (int c = 0; c < NCS; c++) {
-        u64 lo = 0, hi = 0;
-        for (int b = threadIdx.x; b < nparts; b += 256) {
-            const u64 o = lo;
-            lo += part[((int64_t)b * NCS + c) * 2];
-            hi += part[((int64_t)b * NCS + c) * 2 + 1] + ((lo < o) ? 1ull : 0ull);
+        wave_sum128(lo[c], hi[c]);
+        if (glt_lane() == 0) { red[w][c][0] = lo[c]; red[w][c][1] = hi[c]; }
+    }
+    __syncthreads();
+    if (threadIdx.x < NCS) {
+        const int c = threadIdx.x;
+        u64 L = 0, H = 0;
+        for (int q = 0; q < 1024 / GLT_WAVE; q++) {
+            const u64 o = L;
+            L += red[q][c][0];
+            H += red[q][c][1] + ((L < o) ? 1ull : 0ull);
         }
-        wave_sum128(lo, hi);
-        if (glt_lane() == 0) { red[threadIdx.x / GLT_WAVE][0] = lo; red[threadIdx.x / GLT_WAVE][1] = hi; }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            u64 L = 0, H = 0;
-            for (int q = 0; q < 256 / GLT_WAVE; q++) {
-                const u64 o = L;
-                L += red[q][0];
-                H += red[q][1] + ((L < o) ? 1ull : 0ull);
-            }
-            fin[2 * c] = L;
-            fin[2 * c + 1] = H;
-        }
-        __syncthreads();
+        fin[2 * c] = L;
+        fin[2 * c + 1] = H;
     }
 }
 
@@ -1650,7 +1659,7 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
             hipLaunchKernelGGL((k_combine<false, AT, false>), dim3(nb), dim3(CB_THREADS), 0, st, d.eid2k, e, d.ocol,
                                d.ndeg, d.tri, d.sdeg, er, vr, n, m, out_pe, d.sums, d.err);
         }
-        hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, d.sums, nb, d.final_sums);
+        hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(1024), 0, st, d.sums, nb, d.final_sums);
     } else {
         launch_fill<u64>(d.final_sums, 2 * NCS, 0ull, st);
     }
