@@ -368,10 +368,9 @@ def main():
     ap.add_argument("--pool-small", type=int, default=10000, help="served: pool of small request graphs")
     ap.add_argument("--pool-large", type=int, default=64, help="served: pool of large request graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--two-stream", action="store_true",
-                    help="single graph: time the wedge pass on the handle's second stream, beside the "
-                         "triangle and gather passes (kernels then share the chip, so per-kernel times "
-                         "and the roofline describe shared execution)")
+    ap.add_argument("--stream-mode", type=int, default=None, choices=[0, 1, 2],
+                    help="single graph: the schedule's stream mode (default: the library's, 2 = workgroup "
+                         "triangle/gather paths beside the wavefront paths, 4-cycle pass alone)")
     ap.add_argument("--global-only", action="store_true", help="skip per-edge output")
     ap.add_argument("--order-study", action="store_true",
                     help="also time each order of the workgroup work lists (reported as order_study)")
@@ -416,10 +415,9 @@ def main():
     per_edge = not args.global_only
     out = torch.empty((13, m), dtype=torch.int64, device=dev) if per_edge else None
     ctx = glt.Context(0)
-    if args.two_stream:
-        # the wedge pass on the handle's second stream, concurrent with the triangle and
-        # gather passes; each kernel group is still timed by events on its own stream
-        ctx.set_schedule(wedge_stream=1)
+    if args.stream_mode is not None:
+        ctx.set_schedule(wedge_stream=args.stream_mode)
+    mode = ctx.schedule()["wedge_stream"]
     stream = torch.cuda.current_stream(dev)
     print(f"[bench] n={n} m={m}; warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -458,21 +456,23 @@ def main():
             assert Xo == X, "list order changed the counts"
         ctx.set_schedule(list_order=0)
         print(f"[bench] ordering study (ms/step): {study}", file=sys.stderr, flush=True)
-    other = None
-    if not args.two_stream and args.steps > 0:
-        # the same step with the wedge pass on the second stream (reported beside the line;
-        # the headline keeps one stream so that every kernel's time is its own)
-        ctx.set_schedule(wedge_stream=1)
-        ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            X2, _ = ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
-        torch.cuda.synchronize()
-        other = round((time.perf_counter() - t0) * 1e3 / args.steps, 3)
-        assert X2 == X, "the two-stream schedule changed the counts"
-        ctx.set_schedule(wedge_stream=0)
-        print(f"[bench] two-stream schedule: {other} ms/step", file=sys.stderr, flush=True)
+    other = {}
+    if args.steps > 0:
+        # the same step under the other stream modes, reported beside the line
+        for om in (0, 1, 2):
+            if om == mode:
+                continue
+            ctx.set_schedule(wedge_stream=om)
+            ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                X2, _ = ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
+            torch.cuda.synchronize()
+            other[str(om)] = round((time.perf_counter() - t0) * 1e3 / args.steps, 3)
+            assert X2 == X, "the stream mode changed the counts"
+        ctx.set_schedule(wedge_stream=mode)
+        print(f"[bench] other stream modes (ms/step): {other}", file=sys.stderr, flush=True)
     line = {
         "metric": "edges/sec for exact 4-node motif counts (1 GPU)",
         "value": m / (ms_per_step * 1e-3),
@@ -489,7 +489,7 @@ def main():
         "work": work,
         "roofline": roof,
         **({"order_study_ms_per_step": study} if study else {}),
-        **({"two_stream_ms_per_step": other} if other else {}),
+        **({"other_stream_modes_ms_per_step": other} if other else {}),
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on a bounded sample", file=sys.stderr, flush=True)

@@ -140,7 +140,8 @@ glt_status glt_count_batch(glt_ctx* ctx, const glt_batch* b, uint32_t flags, glt
  * vertex, [3] per-edge gather pass, wavefront path, [4] the same, workgroup path,
  * [5]-[8] 4-cycle wedge pass, wave / mid / workgroup / huge class, [9] vertex sums, combine
  * and reduction, [10] the whole call.  With the schedule's wedge_stream = 1 the wedge pass
- * runs on a second stream beside entries [1]-[4], and the entries then overlap.  Returns the number of
+ * runs on a second stream beside entries [1]-[4]; with wedge_stream = 2 entries [2] and [4]
+ * run beside [1] and [3]; overlapping entries share the chip.  Returns the number of
  * entries written (<= cap, at most 11).
  */
 int glt_last_timing(const glt_ctx* ctx, float* ms, int cap);
@@ -176,8 +177,11 @@ typedef struct {
     int32_t wedge_wg_max;      /* up to this many: one per 256-thread workgroup, moving to the
                                   1024-thread class with the largest tables if its distinct
                                   tops overflow the workgroup's tables; more: straight there */
-    int32_t wedge_stream;      /* 1: the 4-cycle pass runs on a second stream beside the
-                                  triangle and gather passes; 0: after them on one stream     */
+    int32_t wedge_stream;      /* streams: 0 all passes on the call's stream; 1 the 4-cycle
+                                  pass on a second stream beside the triangle and gather
+                                  passes; 2 the workgroup paths of the triangle and gather
+                                  passes on a second stream beside their wavefront paths,
+                                  the 4-cycle pass alone after both                          */
     int32_t list_order;        /* order of the workgroup work lists (Section 4.3's edge order,
                                   Table 4's ordering study): 0 largest work first, 1 largest
                                   degree first, 2 ascending rank, 3 pseudo-random            */
@@ -191,11 +195,11 @@ glt_status glt_get_schedule(const glt_ctx* ctx, glt_schedule* out);
 glt_status glt_set_schedule(glt_ctx* ctx, const glt_schedule* s);
 
 /*
- * Autotuner for batches: counts the batch once per candidate schedule (a fixed 24-point grid
- * over the wedge class bounds, the dense window and wedge_stream, after one warm-up call),
- * checks that all
- * candidates give identical counts (GLT_E_INTERNAL otherwise), installs the candidate with
- * the least device time (sum of the glt_last_timing groups) on the handle and returns it.
+ * Autotuner for batches: counts the batch once per candidate schedule (a fixed 36-point grid
+ * over the wedge class bounds, the dense window and the stream mode wedge_stream, after one
+ * warm-up call), checks that all candidates give identical counts (GLT_E_INTERNAL
+ * otherwise), installs the candidate with the least device time (the whole call,
+ * glt_last_timing's last entry) on the handle and returns it.
  *   best     out: the chosen schedule
  *   best_ms  out (may be NULL): its device time in milliseconds
  * Errors as glt_count_batch.

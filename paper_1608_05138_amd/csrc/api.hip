@@ -47,10 +47,12 @@ struct glt_ctx {
     size_t trec_bytes = 0;
     size_t trec_cap = 0;               // largest record buffer the handle allocates
     int tri_records = 1;               // schedule: use triangle records when they fit
-    int wedge_stream = 0;              // schedule: wedge pass on the side stream (off: each kernel
-                                       // group then has the chip alone and is timed cleanly)
+    int wedge_stream = 2;              // schedule: stream mode (0 one stream: each kernel group has
+                                       // the chip alone; 1 wedge pass on the side stream; 2 the
+                                       // workgroup triangle / gather paths on the side stream, the
+                                       // wedge pass alone)
     int list_order = 0;                // schedule: order of the workgroup work lists (LO_*)
-    int last_overlap = 0;              // the mode the last call's timing was taken in
+    int last_mode = 0;                 // the stream mode the last call's timing was taken in
     void* slab = nullptr;              // larger global slab for the highest out-degrees (grown on demand)
     size_t slab_bytes = 0;
 };
@@ -354,7 +356,7 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
     }
     d.trec = ensure_trec(ctx, n > 0 ? *(u64*)((char*)ctx->hbuf + 64) : 0, st);
     grow_slab(ctx, d, hc[TB_GLOBAL], hc[TB_N + WB_N + TB_GLOBAL], st);
-    ctx->last_overlap = ctx->wedge_stream;
+    ctx->last_mode = ctx->wedge_stream;
     glt_count_passes(d, per_edge ? 1 : 0, hc, pe_dev, st, ctx->side, ctx->ev, ctx->wedge_stream);
     HIPCHK(hipGetLastError());
     return GLT_OK;
@@ -363,11 +365,16 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
 // Kernel groups as (begin, end) events; the wedge groups (side stream) overlap the
 // triangle and gather groups, so the groups do not add up to the total.
 void record_timing(glt_ctx* ctx) {
-    static const int be[NSEG][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {1, 6},
-                                    {6, 7}, {7, 8}, {8, 9}, {10, 11}, {0, 11}};
+    // group i runs from event be[i][0] to event be[i][1] (events as in count_passes)
+    int be[NSEG][2] = {{0, 1}, {1, 2}, {2, 3}, {12, 4}, {4, 5}, {14, 6},
+                       {6, 7}, {7, 8}, {8, 9}, {10, 11}, {0, 11}};
+    if (ctx->last_mode == 1) be[5][0] = 1;   // the wedge pass starts at the fork, beside the others
+    if (ctx->last_mode == 2) {               // workgroup paths on the second stream from the fork
+        be[2][0] = 1;
+        be[4][0] = 13;
+    }
     for (int i = 0; i < NSEG; i++) {
-        int b0 = be[i][0];
-        if (i == 5 && !ctx->last_overlap) b0 = 5;   // one stream: the wedge pass follows the gather pass
+        const int b0 = be[i][0];
         float ms = 0;
         (void)hipEventElapsedTime(&ms, ctx->ev[b0], ctx->ev[be[i][1]]);
         ctx->timing[i] = ms;
@@ -463,7 +470,10 @@ glt_status glt_create(int device, size_t hbm_budget_bytes, glt_ctx** out) {
         int v = atoi(e);
         if (v >= 0) ctx->wedge_wg_max = v;
     }
-    if (const char* e = getenv("GLT_WEDGE_STREAM")) ctx->wedge_stream = atoi(e) ? 1 : 0;
+    if (const char* e = getenv("GLT_WEDGE_STREAM")) {
+        const int v = atoi(e);
+        ctx->wedge_stream = (v >= 0 && v <= 2) ? v : 0;
+    }
     if (const char* e = getenv("GLT_WEDGE_RANGE_LIMIT")) {
         int v = atoi(e);
         if (v >= 1 && v < ctx->wedge_limit) ctx->wedge_limit = v;
@@ -695,7 +705,7 @@ glt_status glt_set_schedule(glt_ctx* ctx, const glt_schedule* s) {
     if (s->wedge_range_limit < 1 || s->wedge_range_limit > glt_wedge_table() / 2)
         return fail(ctx, GLT_E_INVALID_ARG, "wedge_range_limit must be in [1, %d]", glt_wedge_table() / 2);
     if (s->tri_records != 0 && s->tri_records != 1) return fail(ctx, GLT_E_INVALID_ARG, "tri_records must be 0 or 1");
-    if (s->wedge_stream != 0 && s->wedge_stream != 1) return fail(ctx, GLT_E_INVALID_ARG, "wedge_stream must be 0 or 1");
+    if (s->wedge_stream < 0 || s->wedge_stream > 2) return fail(ctx, GLT_E_INVALID_ARG, "wedge_stream must be 0, 1 or 2");
     if (s->list_order < 0 || s->list_order > 3) return fail(ctx, GLT_E_INVALID_ARG, "list_order must be in [0, 3]");
     ctx->wedge_wave_max = s->wedge_wave_max;
     ctx->wedge_mid_max = s->wedge_mid_max;
@@ -719,7 +729,7 @@ glt_status glt_autotune_batch(glt_ctx* ctx, const glt_batch* b, glt_schedule* be
     std::vector<glt_u128> ref((size_t)B * 17), got((size_t)B * 17);
     glt_status rc = glt_count_batch(ctx, b, GLT_GLOBAL, ref.data(), stream);   // warm-up, reference counts
     if (rc) return rc;
-    // candidate grid: wedge class bounds x dense window
+    // candidate grid: wedge class bounds x dense window x stream mode
     static const int wave_c[2] = {128, 256};
     static const int mid_c[3] = {1024, 2048, 4096};
     static const int dense_c[2] = {4096, 16384};
@@ -727,7 +737,7 @@ glt_status glt_autotune_batch(glt_ctx* ctx, const glt_batch* b, glt_schedule* be
     float win_ms = -1.f;
     for (int a = 0; a < 2; a++)
         for (int c = 0; c < 3; c++)
-            for (int e = 0; e < 4; e++) {
+            for (int e = 0; e < 6; e++) {
                 glt_schedule cand = base;
                 cand.wedge_wave_max = wave_c[a];
                 cand.wedge_mid_max = mid_c[c];

@@ -1548,9 +1548,15 @@ static void wedge_pass(const Dev& d, int per_edge, const int* hc, hipStream_t s,
     (void)hipEventRecord(ev[9], s);
 }
 
+// Stream modes: 0 everything on st; 1 the wedge pass on `side`, beside the triangle and
+// gather passes on st; 2 the workgroup paths of the triangle and gather passes on `side`,
+// beside their wavefront paths on st (each gather path starts once both triangle paths
+// are done), and the wedge pass alone on st after both.
 template <typename AT>
 static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st, hipStream_t side,
-                         hipEvent_t* ev, bool overlap) {
+                         hipEvent_t* ev, int mode) {
+    const bool overlap = mode == 1, split = mode == 2;
+    const hipStream_t sw = split ? side : st;   // stream of the workgroup paths
     const int n = d.n, m = d.m;
     u64* gsum = d.gsum;                   // [graph][NSUMS]: 3 x 4-cliques and non-induced 4-cycles
     launch_fill<u64>(gsum, (int64_t)(d.ngraphs > 0 ? d.ngraphs : GSPREAD) * NSUMS, 0ull, st);
@@ -1560,6 +1566,7 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
     for (int bkt = TB_BLK1; bkt <= TB_GLOBAL; bkt++) sort_heaviest_first(d, d.tlist + (int64_t)bkt * n, cnt[bkt], 1, st);
     for (int bkt = WB_MID; bkt <= WB_HUGE; bkt++) sort_heaviest_first(d, d.wlist + (int64_t)bkt * n, hc[TB_N + bkt], 0, st);
     (void)hipEventRecord(ev[1], st);
+    if (split) (void)hipStreamWaitEvent(side, ev[1], 0);
     if (overlap) {
         // the wedge pass on the side stream, beside the triangle and gather passes
         (void)hipStreamWaitEvent(side, ev[1], 0);
@@ -1587,15 +1594,23 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
         for (int64_t off = 0; off < c; off += grp) {
             const int cc = (int)((c - off < grp) ? (c - off) : grp);
             if (per_edge) {
-                if (gm) launch_tri_blk<true, true, AT>(d, lst + off, cc, smax, st);
-                else launch_tri_blk<true, false, AT>(d, lst + off, cc, smax, st);
+                if (gm) launch_tri_blk<true, true, AT>(d, lst + off, cc, smax, sw);
+                else launch_tri_blk<true, false, AT>(d, lst + off, cc, smax, sw);
             } else {
-                if (gm) launch_tri_blk<false, true, AT>(d, lst + off, cc, smax, st);
-                else launch_tri_blk<false, false, AT>(d, lst + off, cc, smax, st);
+                if (gm) launch_tri_blk<false, true, AT>(d, lst + off, cc, smax, sw);
+                else launch_tri_blk<false, false, AT>(d, lst + off, cc, smax, sw);
             }
         }
     }
-    (void)hipEventRecord(ev[3], st);
+    (void)hipEventRecord(ev[3], sw);
+    if (split) {
+        // the gather passes need every triangle's t: each stream waits for the other's
+        // triangle path
+        (void)hipStreamWaitEvent(st, ev[3], 0);
+        (void)hipStreamWaitEvent(side, ev[2], 0);
+    }
+    (void)hipEventRecord(ev[12], st);
+    (void)hipEventRecord(ev[13], sw);
     // gather pass
     if (per_edge && cnt[TB_WAVE] > 0) {
         if (d.trec)
@@ -1623,12 +1638,14 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
             }
             for (int64_t off = 0; off < c; off += grp) {
                 const int cc = (int)((c - off < grp) ? (c - off) : grp);
-                if (gm) launch_gather_blk<true, AT>(d, lst + off, cc, smax, st);
-                else launch_gather_blk<false, AT>(d, lst + off, cc, smax, st);
+                if (gm) launch_gather_blk<true, AT>(d, lst + off, cc, smax, sw);
+                else launch_gather_blk<false, AT>(d, lst + off, cc, smax, sw);
             }
         }
     }
-    (void)hipEventRecord(ev[5], st);
+    (void)hipEventRecord(ev[5], sw);
+    if (split) (void)hipStreamWaitEvent(st, ev[5], 0);     // join the workgroup paths
+    (void)hipEventRecord(ev[14], st);
     if (overlap) (void)hipStreamWaitEvent(st, ev[9], 0);   // join the wedge pass
     else wedge_pass<AT>(d, per_edge, hc, st, ev);
     (void)hipEventRecord(ev[10], st);
@@ -1668,11 +1685,11 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
 }
 
 void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st, hipStream_t side,
-                      hipEvent_t* ev, int overlap) {
+                      hipEvent_t* ev, int mode) {
     if (d.acc32)
-        count_passes<u32>(d, per_edge, hc, out_pe, st, side, ev, overlap != 0);
+        count_passes<u32>(d, per_edge, hc, out_pe, st, side, ev, mode);
     else
-        count_passes<u64>(d, per_edge, hc, out_pe, st, side, ev, overlap != 0);
+        count_passes<u64>(d, per_edge, hc, out_pe, st, side, ev, mode);
 }
 
 int glt_combine_blocks(int m) { return combine_blocks(m); }

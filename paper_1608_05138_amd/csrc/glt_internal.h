@@ -49,7 +49,7 @@ struct EdgeArrays {
 #define NWORK 8
 #define NSEG 11     // timed groups: prep, tri wave, tri wg, gather wave, gather wg, wedge wave, wedge mid,
                     // wedge wg, wedge huge, combine, total
-#define NEV 12      // events of one call (see count_passes)
+#define NEV 15      // events of one call (see count_passes)
 enum { S_C3 = 0, S_C4, S_C5, S_C7, S_C8, S_C9, S_C10, S_C11, S_C12, S_C13, S_C14, S_C15, S_C16,
        S_SPARE, S_K4x3, S_NC4 };
 // The per-group totals array (gsum) holds NSUMS words per line and uses S_K4x3, S_NC4 and
@@ -149,4 +149,4 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
                    const int* vinfo /* max degree, then RS_N row-class counts */);
 void glt_count_passes(const Dev& d, int per_edge, const int* host_counts, u64* out_pe,
                       hipStream_t st, hipStream_t side, hipEvent_t* ev /* NEV events, ev[0] recorded by the caller */,
-                      int overlap /* wedge pass on `side`, beside the triangle passes */);
+                      int mode /* streams: 0 one, 1 wedge pass on `side`, 2 workgroup paths on `side` */);

@@ -233,6 +233,45 @@ def test_triangle_records_on_and_off(monkeypatch, ctx):
         off.close()
 
 
+@pytest.mark.parametrize("records", ["on", "off"])
+def test_stream_modes_agree(monkeypatch, ctx, records):
+    """Stream mode 2 runs the workgroup triangle and gather paths on a second stream beside
+    the wavefront paths (each gather path waiting for both triangle paths) and mode 1 the
+    4-cycle pass beside them; per-edge and global counts must equal one-stream's, with and
+    without triangle records, on graphs that reach the wave, LDS-bitmap and global-bitmap
+    paths."""
+    import paper_1608_05138_amd as glt
+    if records == "off":
+        monkeypatch.setenv("GLT_TRI_RECORD_BYTES", "0")
+    handles = {}
+    try:
+        for mode in (0, 1, 2):
+            handles[mode] = glt.Context(0)
+            handles[mode].set_schedule(wedge_stream=mode)
+        rng = np.random.default_rng(9)
+        n = 3000
+        lo, hi = gg.er_pairs(n, 9000, rng)
+        iu = np.triu_indices(760, 1)   # out-degrees up to 759: global-bitmap rows
+        a = np.concatenate([lo, iu[0]]); b = np.concatenate([hi, iu[1]])
+        key = np.unique(np.minimum(a, b) * n + np.maximum(a, b))
+        perm = rng.permutation(n)
+        cases = [("clique760-noise", n, gg.csr_from_pairs(n, perm[key // n], perm[key % n])),
+                 ("chung-lu-6000", 6000, gg.chung_lu(6000, 90000, 2.1, 5999.0, 78))]
+        for name, nn, (rp, col) in cases:
+            say(f"stream modes {records} {name}")
+            X0, pe0 = gpu(handles[0], nn, rp, col)
+            for mode in (1, 2):
+                X, pe = gpu(handles[mode], nn, rp, col)
+                assert X == X0, (name, mode)
+                np.testing.assert_array_equal(pe, pe0)
+                G, _ = gpu(handles[mode], nn, rp, col, per_edge=False)
+                assert G == X0, (name, mode)
+        assert X0 == oracle.count(nn, rp, col)["X"]
+    finally:
+        for h in handles.values():
+            h.close()
+
+
 def test_modes_and_layouts_agree(ctx):
     n = 4000
     rp, col = gg.chung_lu(n, 40000, 2.3, float(n - 1), 21)
