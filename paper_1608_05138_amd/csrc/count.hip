@@ -67,6 +67,10 @@ __device__ __forceinline__ void gsig_get(const EdgeArrays& e, int64_t k, u64& g,
 }
 
 #define TB_THREADS 256
+#ifndef TW_G
+#define TW_G 4         // wavefronts per block in the wavefront triangle and gather passes
+#endif
+#define TW_THREADS (TW_G * GLT_WAVE)
 #ifndef TRI_ILP
 #define TRI_ILP 4      // out-list entries per lane in flight in the triangle passes (8: more registers, slower)
 #endif
@@ -224,20 +228,20 @@ __device__ __forceinline__ void tri_unrec(u64 v, int& i, int& j, int& k) {
 }
 
 template <bool PE, bool REC, typename AT>
-__global__ __launch_bounds__(TB_THREADS) void k_tri_wave(const int* __restrict__ list, int nlist,
+__global__ __launch_bounds__(TW_THREADS) void k_tri_wave(const int* __restrict__ list, int nlist,
                                                         const int* __restrict__ optr, const int* __restrict__ ocol,
                                                         EdgeArrays e, u64* __restrict__ gsum,
                                                         const int* __restrict__ ngid, u64* __restrict__ trec,
                                                         const u64* __restrict__ toff, int* __restrict__ tcnt) {
     constexpr int SPOS = RunTables<GLT_WAVE>::SPOS;
-    __shared__ RunTables<GLT_WAVE> sRT[4];
-    __shared__ u64 sM[4][GLT_WAVE];
-    __shared__ u64 sK[4][GLT_WAVE];
-    __shared__ int hk[4][SH_SIZE];
-    __shared__ unsigned char hv[4][SH_SIZE];
+    __shared__ RunTables<GLT_WAVE> sRT[TW_G];
+    __shared__ u64 sM[TW_G][GLT_WAVE];
+    __shared__ u64 sK[TW_G][GLT_WAVE];
+    __shared__ int hk[TW_G][SH_SIZE];
+    __shared__ unsigned char hv[TW_G][SH_SIZE];
     // every LDS array is per wavefront: wavefronts synchronise only with themselves
     const int w = threadIdx.x / GLT_WAVE, l = glt_lane();
-    const int idx = blockIdx.x * 4 + w;
+    const int idx = blockIdx.x * TW_G + w;
     if (idx >= nlist) return;
     const int a = list[idx];
     const int o0 = optr[a];
@@ -581,7 +585,7 @@ __device__ __forceinline__ void gather_credit(bool found, int i, int j, int k, u
 }
 
 template <bool REC, typename AT>
-__global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restrict__ list, int nlist,
+__global__ __launch_bounds__(TW_THREADS) void k_gather_wave(const int* __restrict__ list, int nlist,
                                                            const int* __restrict__ optr,
                                                            const int* __restrict__ ocol,
                                                            const int* __restrict__ ndeg, EdgeArrays e,
@@ -589,17 +593,17 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_wave(const int* __restric
                                                            const u64* __restrict__ toff,
                                                            const int* __restrict__ tcnt) {
     constexpr int SPOS = RunTables<GLT_WAVE>::SPOS;
-    __shared__ RunTables<GLT_WAVE> sRT[REC ? 1 : 4];
-    __shared__ u32 sT[4][GLT_WAVE];
-    __shared__ int sD[4][GLT_WAVE];
-    __shared__ u64 sG[4][GLT_WAVE];
-    __shared__ u64 sSg[4][GLT_WAVE];
-    __shared__ int hk[4][SH_SIZE];
-    __shared__ unsigned char hv[4][SH_SIZE];
+    __shared__ RunTables<GLT_WAVE> sRT[REC ? 1 : TW_G];
+    __shared__ u32 sT[TW_G][GLT_WAVE];
+    __shared__ int sD[TW_G][GLT_WAVE];
+    __shared__ u64 sG[TW_G][GLT_WAVE];
+    __shared__ u64 sSg[TW_G][GLT_WAVE];
+    __shared__ int hk[TW_G][SH_SIZE];
+    __shared__ unsigned char hv[TW_G][SH_SIZE];
     // every LDS array is per wavefront: wavefronts synchronise only with themselves and leave
     // as soon as their vertex is done
     const int w = threadIdx.x / GLT_WAVE, l = glt_lane();
-    const int idx = blockIdx.x * 4 + w;
+    const int idx = blockIdx.x * TW_G + w;
     if (idx >= nlist) return;
     const int a = list[idx];
     const int nh = REC ? tcnt[a] : 0;
@@ -799,10 +803,14 @@ __device__ __forceinline__ void wedge_bounds(int s, int lo, int hi, bool full, c
 // Size classes of the wedge pass (wedges per bottom vertex y): threads per group, groups per
 // block, hash entries, dense top counters.
 #define WW_T 64
+#ifndef WW_G
 #define WW_G 4
+#endif
 #define WW_HT 512        // wave class: <= WW_HT / 2 wedges, so the hash never overflows
 #define WM_T 64
-#define WM_G 2       // mid class: 16-bit counters (its bottoms have at most 65,535 wedges)
+#ifndef WM_G
+#define WM_G 1       // mid class: 16-bit counters (its bottoms have at most 65,535 wedges)
+#endif
 #ifndef WM_HT
 #define WM_HT 1024
 #endif
@@ -1474,10 +1482,10 @@ static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1
 template <bool PE, typename AT>
 static void launch_tri_wave(const Dev& d, const int* lst, int c, hipStream_t st) {
     if (d.trec)
-        hipLaunchKernelGGL((k_tri_wave<PE, true, AT>), dim3(cdiv(c, 4)), dim3(TB_THREADS), 0, st, lst, c, d.optr, d.ocol,
+        hipLaunchKernelGGL((k_tri_wave<PE, true, AT>), dim3(cdiv(c, TW_G)), dim3(TW_THREADS), 0, st, lst, c, d.optr, d.ocol,
                            d.e, d.gsum, d.ngid, d.trec, d.toff, d.tcnt);
     else
-        hipLaunchKernelGGL((k_tri_wave<PE, false, AT>), dim3(cdiv(c, 4)), dim3(TB_THREADS), 0, st, lst, c, d.optr,
+        hipLaunchKernelGGL((k_tri_wave<PE, false, AT>), dim3(cdiv(c, TW_G)), dim3(TW_THREADS), 0, st, lst, c, d.optr,
                            d.ocol, d.e, d.gsum, d.ngid, d.trec, d.toff, d.tcnt);
 }
 
@@ -1614,11 +1622,11 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
     // gather pass
     if (per_edge && cnt[TB_WAVE] > 0) {
         if (d.trec)
-            hipLaunchKernelGGL((k_gather_wave<true, AT>), dim3(cdiv(cnt[TB_WAVE], 4)), dim3(TB_THREADS), 0, st,
+            hipLaunchKernelGGL((k_gather_wave<true, AT>), dim3(cdiv(cnt[TB_WAVE], TW_G)), dim3(TW_THREADS), 0, st,
                                tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, d.ndeg, e, d.trec, d.toff,
                                d.tcnt);
         else
-            hipLaunchKernelGGL((k_gather_wave<false, AT>), dim3(cdiv(cnt[TB_WAVE], 4)), dim3(TB_THREADS), 0, st,
+            hipLaunchKernelGGL((k_gather_wave<false, AT>), dim3(cdiv(cnt[TB_WAVE], TW_G)), dim3(TW_THREADS), 0, st,
                                tl + (int64_t)TB_WAVE * n, cnt[TB_WAVE], d.optr, d.ocol, d.ndeg, e, d.trec, d.toff,
                                d.tcnt);
     }
