@@ -795,6 +795,9 @@ __device__ __forceinline__ void wedge_bounds(int s, int lo, int hi, bool full, c
     }
 }
 
+#ifndef WEDGE_NORET
+#define WEDGE_NORET 1
+#endif
 #define WEDGE_STACK 40   // x-range stack per group (halving depth <= 32 for 31-bit ids)
 #ifndef WEDGE_ILP
 #define WEDGE_ILP 4      // wedges in flight per lane (8 measured slower: registers)
@@ -850,6 +853,11 @@ __device__ __forceinline__ u32 cnt_inc(u32* a, int i) {
     }
 }
 template <bool P16>
+__device__ __forceinline__ void cnt_add(u32* a, int i) {
+    if constexpr (P16) atomicAdd(&a[i >> 1], 1u << ((u32)(i & 1) << 4));
+    else atomicAdd(&a[i], 1u);
+}
+template <bool P16>
 __device__ __forceinline__ u32 cnt_get(const u32* a, int i) {
     if constexpr (P16) return (a[i >> 1] >> ((u32)(i & 1) << 4)) & 0xffffu;
     else return a[i];
@@ -872,6 +880,9 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
     constexpr int HCW = P16 ? HT / 2 : HT;     // u32 words of hash counters
     constexpr int SPOS = RunTables<T>::SPOS;
     constexpr u32 mask = HT - 1;
+    // NR: with per-edge credits the counting sweep increments without reading back (the
+    // credit sweep sees every final count and sums the 4-cycles there)
+    constexpr bool NR = PE && WEDGE_NORET;
     __shared__ __align__(16) u32 s_dc[G][DCW];
     __shared__ __align__(16) int s_hk[G][HT];
     __shared__ __align__(16) u32 s_hc[G][HCW];
@@ -940,7 +951,8 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                         const int x = xs[j];
                         if (x < 0) continue;
                         if (x >= base) {
-                            c4r += cnt_inc<P16>(dc, x - base);
+                            if (NR) cnt_add<P16>(dc, x - base);
+                            else c4r += cnt_inc<P16>(dc, x - base);
                         } else {
                             u32 h = hslot(x, mask);
                             bool done = false;
@@ -949,14 +961,16 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                                 if (cur == -1) {
                                     cur = atomicCAS(&hk[h], -1, x);
                                     if (cur == -1) {
-                                        c4r += cnt_inc<P16>(hc, (int)h);
+                                        if (NR) cnt_add<P16>(hc, (int)h);
+                                        else c4r += cnt_inc<P16>(hc, (int)h);
                                         if (atomicAdd(&s_dist[g], 1) >= limit) s_ovf[g] = 1;
                                         done = true;
                                         break;
                                     }
                                 }
                                 if (cur == x) {
-                                    c4r += cnt_inc<P16>(hc, (int)h);
+                                    if (NR) cnt_add<P16>(hc, (int)h);
+                                    else c4r += cnt_inc<P16>(hc, (int)h);
                                     done = true;
                                     break;
                                 }
@@ -1044,6 +1058,7 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                                     else atomicOr(err, ERR_CAP);
                                 }
                                 c = (AT)(cnt - 1);
+                                if (NR) c4 += (u64)c;   // sums to 2 x sum over tops of C(c, 2)
                             }
                             // the wavefront's lanes cover one word of the run tables, whose start
                             // bits (and every idle lane) delimit the sources
@@ -1073,8 +1088,17 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
         }
         grp_sync<T>();
     }
+    // the group's total (with NR twice the 4-cycles of y, even), added once
     c4 = wave_sum(c4);
-    if (glt_lane() == 0 && c4) atomicAdd(&gsum[gslot(ngid, y) * NSUMS + S_NC4], c4);
+    if constexpr (T > GLT_WAVE) {
+        grp_sync<T>();
+        if (glt_lane() == 0) rt.scan[tid / GLT_WAVE] = c4;
+        grp_sync<T>();
+        c4 = 0;
+        for (int q = 0; q < T / GLT_WAVE; q++) c4 += rt.scan[q];
+    }
+    if (NR) c4 >>= 1;
+    if (tid == 0 && c4) atomicAdd(&gsum[gslot(ngid, y) * NSUMS + S_NC4], c4);
     }
 }
 
