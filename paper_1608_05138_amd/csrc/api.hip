@@ -367,7 +367,7 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
 void record_timing(glt_ctx* ctx) {
     // group i runs from event be[i][0] to event be[i][1] (events as in count_passes)
     int be[NSEG][2] = {{0, 1}, {1, 2}, {2, 3}, {12, 4}, {4, 5}, {14, 6},
-                       {6, 7}, {7, 8}, {8, 9}, {10, 11}, {0, 11}};
+                       {6, 7}, {15, 8}, {8, 9}, {10, 11}, {0, 11}};
     if (ctx->last_mode == 1) be[5][0] = 1;   // the wedge pass starts at the fork, beside the others
     if (ctx->last_mode == 2) {               // workgroup paths on the second stream from the fork
         be[2][0] = 1;

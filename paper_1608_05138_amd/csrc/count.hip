@@ -1551,17 +1551,19 @@ static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st, int res
                        defer >= 0 ? d.wspread + 6 : nullptr);
 }
 
-// With `overlap` the wedge pass runs on a side stream, concurrently with the triangle and
-// gather passes (they share only read-only inputs and distinct accumulators); both join
-// before the vertex pass and the combine.  Otherwise it follows the gather pass on the same
-// stream.  Events (all recorded, also used to fork and join):
-//   ev[1] end of preprocessing (fork)     ev[2..5] after tri wave / tri wg / gather wave / gather wg
-//   ev[6..9] after the wedge wave / mid / workgroup / huge classes (side stream with overlap)
-//   ev[10] after the join                 ev[11] after the combine
-// Wedge pass: wave and mid classes (one wavefront per bottom vertex), then the huge and
-// workgroup classes; ev[6] and ev[7] mark the two halves on stream s.
+// Events of one call (all recorded, also used to fork and join; the stream modes are
+// described at count_passes):
+//   ev[0] start                            ev[1] end of preprocessing (fork)
+//   ev[2..5] after tri wave / tri wg / gather wave / gather wg
+//   ev[12], ev[13] start of the gather wavefront / workgroup path (after their joins)
+//   ev[14] start of the wedge pass          ev[6], ev[7] after the wave / mid classes
+//   ev[15] start of the workgroup class     ev[8], ev[9] after the workgroup / huge classes
+//   ev[10] after the last join              ev[11] after the combine
+// The passes share only read-only inputs and write distinct accumulators, so the streams
+// join only where a pass needs another's final values (the gather pass needs every t).
+// Wave and mid classes on stream s (ev[6], ev[7] after each).
 template <typename AT>
-static void wedge_pass(const Dev& d, int per_edge, const int* hc, hipStream_t s, hipEvent_t* ev) {
+static void wedge_small(const Dev& d, int per_edge, const int* hc, hipStream_t s, hipEvent_t* ev) {
     const int* wc = hc + TB_N;
     if (per_edge) launch_wedge<true, AT, WW_T, WW_G, WW_HT, 0, false>(d, WB_WAVE, wc[WB_WAVE], s);
     else launch_wedge<false, AT, WW_T, WW_G, WW_HT, 0>(d, WB_WAVE, wc[WB_WAVE], s);
@@ -1569,9 +1571,15 @@ static void wedge_pass(const Dev& d, int per_edge, const int* hc, hipStream_t s,
     if (per_edge) launch_wedge<true, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, WB_MID, wc[WB_MID], s);
     else launch_wedge<false, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, WB_MID, wc[WB_MID], s);
     (void)hipEventRecord(ev[7], s);
-    // workgroup class first: its bottoms whose tops overflow its tables join the huge list,
-    // which one resident workgroup per CU then walks
+}
+
+// Workgroup class first: its bottoms whose tops overflow its tables join the huge list,
+// which one resident workgroup per CU then walks (ev[15] before, ev[8], ev[9] after each).
+template <typename AT>
+static void wedge_large(const Dev& d, int per_edge, const int* hc, hipStream_t s, hipEvent_t* ev) {
+    const int* wc = hc + TB_N;
     const int huge_grid = (wc[WB_BLK] + wc[WB_HUGE] > 0) ? d.num_cu : 0;
+    (void)hipEventRecord(ev[15], s);
     if (per_edge) launch_wedge<true, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
     else launch_wedge<false, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
     (void)hipEventRecord(ev[8], s);
@@ -1580,10 +1588,17 @@ static void wedge_pass(const Dev& d, int per_edge, const int* hc, hipStream_t s,
     (void)hipEventRecord(ev[9], s);
 }
 
+template <typename AT>
+static void wedge_pass(const Dev& d, int per_edge, const int* hc, hipStream_t s, hipEvent_t* ev) {
+    wedge_small<AT>(d, per_edge, hc, s, ev);
+    wedge_large<AT>(d, per_edge, hc, s, ev);
+}
+
 // Stream modes: 0 everything on st; 1 the wedge pass on `side`, beside the triangle and
 // gather passes on st; 2 the workgroup paths of the triangle and gather passes on `side`,
 // beside their wavefront paths on st (each gather path starts once both triangle paths
-// are done), and the wedge pass alone on st after both.
+// are done), then the wave and mid wedge classes on `side` beside the gather pass's
+// wavefront path, and the workgroup and huge wedge classes alone on st after both.
 template <typename AT>
 static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st, hipStream_t side,
                          hipEvent_t* ev, int mode) {
@@ -1676,10 +1691,16 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
         }
     }
     (void)hipEventRecord(ev[5], sw);
-    if (split) (void)hipStreamWaitEvent(st, ev[5], 0);     // join the workgroup paths
-    (void)hipEventRecord(ev[14], st);
-    if (overlap) (void)hipStreamWaitEvent(st, ev[9], 0);   // join the wedge pass
-    else wedge_pass<AT>(d, per_edge, hc, st, ev);
+    (void)hipEventRecord(ev[14], sw);
+    if (split) {
+        wedge_small<AT>(d, per_edge, hc, side, ev);
+        (void)hipStreamWaitEvent(st, ev[7], 0);   // join: the large classes run alone
+        wedge_large<AT>(d, per_edge, hc, st, ev);
+    } else if (overlap) {
+        (void)hipStreamWaitEvent(st, ev[9], 0);   // join the wedge pass
+    } else {
+        wedge_pass<AT>(d, per_edge, hc, st, ev);
+    }
     (void)hipEventRecord(ev[10], st);
     // vertex pass + combine
     if (per_edge && n > 0 && m > 0) {
