@@ -28,11 +28,11 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # source with the hash below and are reported only while it is unchanged.
 TRAFFIC = {
     "source": "paper_1608_05138_amd/csrc/count.hip",
-    "sha256": "b1020b16e085dd9fbe53eb53c98c809a4c786a9b97dc9ac5437ade9efb6e56b0",
+    "sha256": "897d112b0863ece86e6455716fa9d61fc162ffa84985a063a79fd61be386610f",
     "workload": "chung_lu_1m", "per_edge": True,
-    "bytes": {"tri_wave": 3672835264, "tri_wg": 4390485376, "gather_wave": 1485096192,
-              "gather_wg": 2861392544, "wedge_wave": 82168384, "wedge_mid": 3570422304,
-              "wedge_wg": 9070377312, "wedge_huge": 40960},
+    "bytes": {"tri_wave": 3672528320, "tri_wg": 4389171456, "gather_wave": 1484752512,
+              "gather_wg": 2861106560, "wedge_wave": 82174144, "wedge_mid": 3577801248,
+              "wedge_wg": 9052424928, "wedge_huge": 40960},
 }
 
 
@@ -58,7 +58,7 @@ WORKLOADS = {
 # kernel groups timed by the library (HIP events on the call's stream) and their kernels
 GROUPS = {"tri_wave": "k_tri_wave", "tri_wg": "k_tri_blk", "gather_wave": "k_gather_wave",
           "gather_wg": "k_gather_blk", "wedge_wave": "k_wedge (wave class: 64 threads, 4 per block)",
-          "wedge_mid": "k_wedge (mid class: 64 threads, 2 per block)",
+          "wedge_mid": "k_wedge (mid class: 64 threads, one per block)",
           "wedge_wg": "k_wedge (workgroup class: 256 threads)",
           "wedge_huge": "k_wedge (huge class: 1024 threads, one resident per CU)"}
 
@@ -368,6 +368,8 @@ def main():
     ap.add_argument("--pool-small", type=int, default=10000, help="served: pool of small request graphs")
     ap.add_argument("--pool-large", type=int, default=64, help="served: pool of large request graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare-modes", action="store_true",
+                    help="single graph: also time the other stream modes (reported beside the line)")
     ap.add_argument("--stream-mode", type=int, default=None, choices=[0, 1, 2],
                     help="single graph: the schedule's stream mode (default: the library's, 2 = workgroup "
                          "triangle/gather paths beside the wavefront paths, 4-cycle pass alone)")
@@ -457,7 +459,7 @@ def main():
         ctx.set_schedule(list_order=0)
         print(f"[bench] ordering study (ms/step): {study}", file=sys.stderr, flush=True)
     other = {}
-    if args.steps > 0:
+    if args.compare_modes and args.steps > 0:
         # the same step under the other stream modes, reported beside the line
         for om in (0, 1, 2):
             if om == mode:
