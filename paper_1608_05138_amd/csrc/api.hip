@@ -322,6 +322,7 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
     d.list_order = ctx->list_order;
     d.wedge_limit = ctx->wedge_limit;
     d.wedge_dense = ctx->wedge_dense;
+    d.per_edge = per_edge ? 1 : 0;
     HIPCHK(hipEventRecord(ctx->ev[0], st));
     glt_prep_validate(d, rp, rp64, col, st);
     HIPCHK(hipGetLastError());

@@ -1212,7 +1212,7 @@ __global__ __launch_bounds__(CB_THREADS) void k_combine(const int* __restrict__ 
     for (int r = 0; r < CB_EPT; r++) {
         const int64_t eid = e0 + (int64_t)r * CB_THREADS + threadIdx.x;
         if (eid >= m) break;
-        const int k = eid2k[eid];
+        const int k = PE ? eid2k[eid] : (int)eid;   // global sums: any edge order, here oriented
         int u, v;
         int64_t du, dv, t, Kk = 0, Pk = 0, triu = 0, triv = 0, sdu = 0, sdv = 0;
         u64 gk = 0, sk = 0;
@@ -1344,24 +1344,23 @@ __global__ __launch_bounds__(1024) void k_reduce_parts(const u64* __restrict__ p
     }
 }
 
-// Batched global mode: one workgroup per graph over its edges (edge ids of graph g are
-// [slot_base[g]/2, slot_base[g+1]/2) in the packed numbering), unrestricted sums with the
-// graph's own n and m.
+// Batched global mode: one workgroup per graph over its oriented edges, unrestricted sums
+// with the graph's own n and m.
 __global__ __launch_bounds__(CB_THREADS) void k_combine_graphs(const int64_t* __restrict__ vb,
-                                                               const int64_t* __restrict__ sb,
-                                                               const int* __restrict__ eid2k, EdgeArrays e,
+                                                               const int* __restrict__ optr, EdgeArrays e,
                                                                const int* __restrict__ ocol,
                                                                const int* __restrict__ ndeg,
                                                                u64* __restrict__ gparts) {
     __shared__ u64 red[CB_THREADS / GLT_WAVE][NCS][2];
     const int g = blockIdx.x;
     const int64_t ng = vb[g + 1] - vb[g];
-    const int64_t e0 = sb[g] / 2, e1 = sb[g + 1] / 2, mg = e1 - e0;
+    // graph g's vertices hold the ranks [vb[g], vb[g + 1]), so its oriented edges are the
+    // contiguous range below (the sums do not depend on the edge order)
+    const int64_t e0 = optr[vb[g]], e1 = optr[vb[g + 1]], mg = e1 - e0;
     u64 lo[NCS], hi[NCS];
 #pragma unroll
     for (int c = 0; c < NCS; c++) { lo[c] = 0; hi[c] = 0; }
-    for (int64_t eid = e0 + threadIdx.x; eid < e1; eid += CB_THREADS) {
-        const int k = eid2k[eid];
+    for (int64_t k = e0 + threadIdx.x; k < e1; k += CB_THREADS) {
         const int64_t du = ndeg[e.u[k]], dv = ndeg[ocol[k]];
         const int64_t t = e.t[k];
         const int64_t su = du - 1 - t, sv = dv - 1 - t;
@@ -1711,8 +1710,8 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
     }
     const int nb = combine_blocks(m);
     if (d.ngraphs > 0) {
-        hipLaunchKernelGGL(k_combine_graphs, dim3(d.ngraphs), dim3(CB_THREADS), 0, st, d.gvb, d.gsb, d.eid2k, e,
-                           d.ocol, d.ndeg, d.gparts);
+        hipLaunchKernelGGL(k_combine_graphs, dim3(d.ngraphs), dim3(CB_THREADS), 0, st, d.gvb, d.optr, e, d.ocol,
+                           d.ndeg, d.gparts);
     } else if (m > 0) {
         ERec* er = (ERec*)d.erec;
         VRec* vr = (VRec*)d.vrec;

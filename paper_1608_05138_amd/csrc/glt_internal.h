@@ -138,6 +138,8 @@ struct Dev {
     int wedge_limit;      // distinct hashed tops per range before the range is split
     int wedge_dense;      // width of the dense window of highest-ranked tops
     int acc32;            // per-edge accumulators fit 32 bits (maximum degree <= 46340)
+    int per_edge;         // per-edge output requested (global counts need neither caller edge
+                          // ids nor the K, P, g, sigma accumulators)
 };
 
 // Host-side entry points of the device pipeline (count.hip).

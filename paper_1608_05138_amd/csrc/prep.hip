@@ -445,8 +445,10 @@ __global__ __launch_bounds__(256) void k_vinfo(const int* __restrict__ nrp, cons
 
 // One thread per relabelled entry.  Upward entries (x -> y, y > x) copy themselves into the
 // oriented CSR at index k and clear the edge's accumulators; downward entries find their
-// edge's k by binary search of x in N+(y), map themselves to k and name the caller's edge
-// id of k.
+// edge's k by binary search of x in N+(y), map themselves to k and (PE: per-edge output)
+// name the caller's edge id of k.  Global counts need only t and u of an edge, and no
+// caller edge ids.
+template <bool PE>
 __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ ncol, const int* __restrict__ nsrow,
                                                     const int4* __restrict__ vinf, const u32* __restrict__ oslot,
                                                     const u32* __restrict__ upx, int64_t S, int m,
@@ -468,7 +470,8 @@ __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ ncol
             } else {
                 ocol[k] = y;
                 s2k[s] = k;
-                ea.t[k] = 0; ea.K[k] = 0; ea.P[k] = 0; ea.g[k] = 0; ea.sig[k] = 0; ea.u[k] = x;
+                ea.t[k] = 0; ea.u[k] = x;
+                if (PE) { ea.K[k] = 0; ea.P[k] = 0; ea.g[k] = 0; ea.sig[k] = 0; }
             }
         } else {
             // downward x -> y (y ranked below x): the edge's slot is x's place in N+(y), a short
@@ -481,10 +484,12 @@ __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ ncol
                 bad = ERR_ASYM;
             } else {
                 s2k[s] = k;
-                const u32 j = (vx.w < vy.w) ? oslot[s] : oslot[sp];
-                const u32 eid = upx[j];
-                if (eid >= (u32)m) bad = ERR_ASYM;
-                else eid2k[eid] = k;
+                if (PE) {
+                    const u32 j = (vx.w < vy.w) ? oslot[s] : oslot[sp];
+                    const u32 eid = upx[j];
+                    if (eid >= (u32)m) bad = ERR_ASYM;
+                    else eid2k[eid] = k;
+                }
             }
         }
     }
@@ -678,8 +683,12 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
     launch_excl_scan<int, int>(dplus, d.optr, n, d.itmp, d.optr + n, st);
     if (S > 0) {
         hipLaunchKernelGGL(k_vinfo, dim3(nblk(n, 256)), dim3(256), 0, st, d.nrp, d.dlo, d.optr, d.order, n, d.vinf);
-        hipLaunchKernelGGL(k_edge_index, dim3(nblk(S, 256)), dim3(256), 0, st, d.ncol, d.nsrow, d.vinf, oslot, d.upx,
-                           S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.err);
+        if (d.per_edge)
+            hipLaunchKernelGGL(k_edge_index<true>, dim3(nblk(S, 256)), dim3(256), 0, st, d.ncol, d.nsrow, d.vinf,
+                               oslot, d.upx, S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.err);
+        else
+            hipLaunchKernelGGL(k_edge_index<false>, dim3(nblk(S, 256)), dim3(256), 0, st, d.ncol, d.nsrow, d.vinf,
+                               oslot, d.upx, S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.err);
     }
     // work lists
     hipLaunchKernelGGL(k_tbuckets, dim3(nblk(n, 256)), dim3(256), 0, st, d.optr, n, d.tlist, d.counts,
