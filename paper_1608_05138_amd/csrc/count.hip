@@ -802,6 +802,9 @@ __device__ __forceinline__ void wedge_bounds(int s, int lo, int hi, bool full, c
 #ifndef WEDGE_ILP
 #define WEDGE_ILP 4      // wedges in flight per lane (8 measured slower: registers)
 #endif
+#ifndef WEDGE_ILP_HUGE
+#define WEDGE_ILP_HUGE 4 // the same for the 1024-thread class (at most 128 registers per lane)
+#endif
 
 // Size classes of the wedge pass (wedges per bottom vertex y): threads per group, groups per
 // block, hash entries, dense top counters.
@@ -863,7 +866,7 @@ __device__ __forceinline__ u32 cnt_get(const u32* a, int i) {
     else return a[i];
 }
 
-template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16>
+template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16, int IL>
 __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, int nlist, int n, int limit,
                                                  int dense, const int* __restrict__ nrp,
                                                  const int2* __restrict__ wb,
@@ -938,16 +941,16 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
             for (int sb0 = 0; sb0 < tot; sb0 += SPOS) {
                 if (sb0 > 0) runs_next<T>(rt, sb0, len, pre, carry);
                 const int se = min(tot, sb0 + SPOS);
-                for (int q0 = sb0; q0 < se; q0 += WEDGE_ILP * T) {
+                for (int q0 = sb0; q0 < se; q0 += IL * T) {
                     if (*(volatile int*)&s_ovf[g]) break;
-                    int xs[WEDGE_ILP];
+                    int xs[IL];
 #pragma unroll
-                    for (int j = 0; j < WEDGE_ILP; j++) {
+                    for (int j = 0; j < IL; j++) {
                         const int q = q0 + j * T + tid;
                         xs[j] = (q < se) ? ocol[q + runs_at(rt, q - sb0).x] : -1;
                     }
 #pragma unroll
-                    for (int j = 0; j < WEDGE_ILP; j++) {
+                    for (int j = 0; j < IL; j++) {
                         const int x = xs[j];
                         if (x < 0) continue;
                         if (x >= base) {
@@ -1027,10 +1030,10 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                 for (int sb0 = 0; sb0 < tot; sb0 += SPOS) {
                     if (sb0 > 0) runs_next<T>(rt, sb0, len, pre, carry);
                     const int se = min(tot, sb0 + SPOS);
-                    for (int q0 = sb0; q0 < se; q0 += WEDGE_ILP * T) {
-                        int xs[WEDGE_ILP], ks[WEDGE_ILP], is[WEDGE_ILP];
+                    for (int q0 = sb0; q0 < se; q0 += IL * T) {
+                        int xs[IL], ks[IL], is[IL];
 #pragma unroll
-                        for (int j = 0; j < WEDGE_ILP; j++) {
+                        for (int j = 0; j < IL; j++) {
                             const int q = q0 + j * T + tid;
                             xs[j] = -1;
                             is[j] = 0;
@@ -1043,7 +1046,7 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                             }
                         }
 #pragma unroll
-                        for (int j = 0; j < WEDGE_ILP; j++) {
+                        for (int j = 0; j < IL; j++) {
                             const int x = xs[j];
                             AT c = 0;
                             if (x >= 0) {
@@ -1537,13 +1540,13 @@ static void launch_gather_blk(const Dev& d, const int* lst, int c, int smax, hip
 // One group per list entry (grid from the host's count), or, with `resident` blocks, a grid
 // that walks the list up to the device count at `dcount`; `defer` > 0 lets overflowing
 // entries move to the list of class `defer`.
-template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16 = false>
+template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16 = false, int IL = WEDGE_ILP>
 static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st, int resident = 0, int defer = -1) {
     if (cnt <= 0 && resident <= 0) return;
     const int limit = d.wedge_limit < HT / 2 ? d.wedge_limit : HT / 2;
     int* counts = d.counts + TB_N;
     const unsigned grid = resident > 0 ? (unsigned)resident : cdiv(cnt, G);
-    hipLaunchKernelGGL((k_wedge<PE, AT, T, G, HT, DW, P16>), dim3(grid), dim3(T * G), 0, st,
+    hipLaunchKernelGGL((k_wedge<PE, AT, T, G, HT, DW, P16, IL>), dim3(grid), dim3(T * G), 0, st,
                        d.wlist + (int64_t)bkt * d.n, cnt, d.n, limit, d.wedge_dense, d.nrp, d.wb, d.ocol,
                        d.s2k, d.wcnt, d.e, d.gsum, d.ngid, d.gvb, d.err, resident > 0 ? counts + bkt : nullptr,
                        defer >= 0 ? d.wlist + (int64_t)defer * d.n : nullptr, defer >= 0 ? counts + defer : nullptr,
@@ -1582,8 +1585,8 @@ static void wedge_large(const Dev& d, int per_edge, const int* hc, hipStream_t s
     if (per_edge) launch_wedge<true, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
     else launch_wedge<false, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
     (void)hipEventRecord(ev[8], s);
-    if (per_edge) launch_wedge<true, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], s, huge_grid);
-    else launch_wedge<false, AT, WH_T, 1, WH_HT, WH_DW>(d, WB_HUGE, wc[WB_HUGE], s, huge_grid);
+    if (per_edge) launch_wedge<true, AT, WH_T, 1, WH_HT, WH_DW, false, WEDGE_ILP_HUGE>(d, WB_HUGE, wc[WB_HUGE], s, huge_grid);
+    else launch_wedge<false, AT, WH_T, 1, WH_HT, WH_DW, false, WEDGE_ILP_HUGE>(d, WB_HUGE, wc[WB_HUGE], s, huge_grid);
     (void)hipEventRecord(ev[9], s);
 }
 
