@@ -446,6 +446,7 @@ def main():
         # workgroup work lists, each after one warm-up step
         names = ["largest work first", "largest degree first", "ascending rank", "pseudo-random"]
         study = {}
+        default_order = ctx.schedule()["list_order"]
         for order, name in enumerate(names):
             ctx.set_schedule(list_order=order)
             ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
@@ -456,7 +457,7 @@ def main():
             torch.cuda.synchronize()
             study[name] = round((time.perf_counter() - t0) * 1e3 / args.steps, 3)
             assert Xo == X, "list order changed the counts"
-        ctx.set_schedule(list_order=0)
+        ctx.set_schedule(list_order=default_order)
         print(f"[bench] ordering study (ms/step): {study}", file=sys.stderr, flush=True)
     other = {}
     if args.compare_modes and args.steps > 0:

@@ -184,7 +184,8 @@ typedef struct {
                                   the 4-cycle pass alone after both                          */
     int32_t list_order;        /* order of the workgroup work lists (Section 4.3's edge order,
                                   Table 4's ordering study): 0 largest work first, 1 largest
-                                  degree first, 2 ascending rank, 3 pseudo-random            */
+                                  degree first, 2 ascending rank (no sort; the default),
+                                  3 pseudo-random                                             */
 } glt_schedule;
 
 /* The handle's current schedule. */

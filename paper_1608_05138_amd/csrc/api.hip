@@ -51,7 +51,9 @@ struct glt_ctx {
                                        // the chip alone; 1 wedge pass on the side stream; 2 the
                                        // workgroup triangle / gather paths on the side stream, the
                                        // wedge pass alone)
-    int list_order = 0;                // schedule: order of the workgroup work lists (LO_*)
+    int list_order = LO_NONE;          // schedule: order of the workgroup work lists (LO_*); with the
+                                       // second stream filling idle CUs, skipping the sort measured
+                                       // fastest (Chung-Lu 18.40 vs 18.67 ms, R-MAT 678 vs 688 ms)
     int last_mode = 0;                 // the stream mode the last call's timing was taken in
     void* slab = nullptr;              // larger global slab for the highest out-degrees (grown on demand)
     size_t slab_bytes = 0;
