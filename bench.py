@@ -28,11 +28,11 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # source with the hash below and are reported only while it is unchanged.
 TRAFFIC = {
     "source": "paper_1608_05138_amd/csrc/count.hip",
-    "sha256": "897d112b0863ece86e6455716fa9d61fc162ffa84985a063a79fd61be386610f",
+    "sha256": "3790ee74656af7ce4ed1c1119d85c57bc5913b264dc263ba07cd5f198dddbb3c",
     "workload": "chung_lu_1m", "per_edge": True,
-    "bytes": {"tri_wave": 3672528320, "tri_wg": 4389171456, "gather_wave": 1484752512,
-              "gather_wg": 2861106560, "wedge_wave": 82174144, "wedge_mid": 3577801248,
-              "wedge_wg": 9052424928, "wedge_huge": 40960},
+    "bytes": {"tri_wave": 3673902176, "tri_wg": 4442267296, "gather_wave": 1485006720,
+              "gather_wg": 2895340128, "wedge_wave": 82191552, "wedge_mid": 3529322272,
+              "wedge_wg": 9122681184, "wedge_huge": 38912},
 }
 
 
