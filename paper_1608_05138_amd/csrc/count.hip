@@ -23,10 +23,11 @@
 //  * combine: the 13 per-edge counts and the unrestricted sums C3..C16 (Section 4.5),
 //    reduced exactly in 128 bits; the global frequencies (Section 4.6) follow on the host.
 //
-// Work items inside a wavefront are enumerated as flattened (source, offset) pairs with
-// consecutive lanes on consecutive entries of one out-list, so credits to the edges of one
-// list are coalesced atomics to consecutive oriented indices, and credits that all lanes of
-// a run send to the same source are first summed with a segmented wave reduction.
+// Work items inside a group are enumerated as flattened (source, offset) pairs with
+// consecutive lanes on consecutive entries of one out-list (run tables map a position to
+// its source in O(1)), so credits to the edges of one list are coalesced atomics to
+// consecutive oriented indices, and credits that all lanes of a run send to the same source
+// are first summed across the wavefront (DPP) before one atomic per run.
 #include "glt_internal.h"
 
 // Per-edge accumulators K, P, g, sig are 64-bit, or 32-bit when the maximum degree bounds

@@ -1,6 +1,7 @@
-// prims.h -- device primitives for gfx950 (wave64): wave/block scans and reductions,
-// a device-wide exclusive scan, a stable LSD radix sort of (u64 key, u32 value) pairs,
-// and fill kernels.  Used by the graph preprocessing (degree order, sorted CSR).
+// prims.h -- device primitives for gfx950 (wave64): wave scans and segmented sums by DPP,
+// block scans and reductions, a device-wide exclusive scan, a stable LSD radix sort of
+// (u64 key, u32 value) pairs, and fill kernels.  Used by the graph preprocessing (degree
+// order, sorted CSR) and the counting passes.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -132,32 +133,6 @@ __device__ __forceinline__ T block_excl_scan(T v, T* lds, T& total) {
     __syncthreads();
     total = tot;
     return off + inc - v;
-}
-
-// largest i in [0, n) with a[i] <= q, assuming a[0] <= q and a ascending
-template <typename T>
-__device__ __forceinline__ int upper_idx(const T* a, int n, T q) {
-    int lo = 0, hi = n;  // invariant: a[lo] <= q, answer in [lo, hi)
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (a[mid] <= q) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
-// Like upper_idx, starting from a previous answer i for a smaller q: gallops forward, then
-// bisects.  Cheap when consecutive queries of a lane move across few entries.
-template <typename T>
-__device__ __forceinline__ int advance_idx(const T* a, int n, T q, int i) {
-    if (i + 1 >= n || a[i + 1] > q) return i;
-    int step = 1, lo = i + 1;
-    while (lo + step < n && a[lo + step] <= q) { lo += step; step <<= 1; }
-    int hi = min(lo + step, n);   // a[lo] <= q, answer in [lo, hi)
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (a[mid] <= q) lo = mid; else hi = mid;
-    }
-    return lo;
 }
 
 // first index in [lo, hi) with a[idx] >= x (hi if none)
