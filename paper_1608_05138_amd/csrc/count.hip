@@ -1597,6 +1597,20 @@ static void wedge_pass(const Dev& d, int per_edge, const int* hc, hipStream_t s,
     wedge_large<AT>(d, per_edge, hc, s, ev);
 }
 
+// Vertex pass (needs final t only): triangles and neighbour-degree sums per vertex, and with
+// packed combine records (per-edge mode, 32-bit accumulators) the per-vertex records.
+template <typename AT>
+static void vertex_sums(const Dev& d, hipStream_t s) {
+    const int n = d.n, m = d.m;
+    launch_fill<u64>(d.tri, n, 0ull, s);
+    launch_fill<u64>(d.sdeg, n, 0ull, s);
+    hipLaunchKernelGGL(k_vertex, dim3(cdiv(2 * (int64_t)m, 256)), dim3(256), 0, s, d.nsrow, d.ncol, d.s2k, d.ndeg,
+                       d.e.t, 2 * (int64_t)m, d.tri, d.sdeg);
+    if (sizeof(AT) == 4 && d.erec && d.vrec)
+        hipLaunchKernelGGL(k_pack_vertices, dim3(cdiv(n, 256)), dim3(256), 0, s, d.tri, d.sdeg, d.ndeg, n,
+                           (VRec*)d.vrec);
+}
+
 // Stream modes: 0 everything on st; 1 the wedge pass on `side`, beside the triangle and
 // gather passes on st; 2 the workgroup paths of the triangle and gather passes on `side`,
 // beside their wavefront paths on st (each gather path starts once both triangle paths
@@ -1694,6 +1708,10 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
         }
     }
     (void)hipEventRecord(ev[5], sw);
+    // mode 2: the vertex pass follows the gather workgroup path on the second stream (t is
+    // final there), beside the gather wavefront path; it is in no timed group then
+    const bool vside = split && per_edge && n > 0 && m > 0;
+    if (vside) vertex_sums<AT>(d, side);
     (void)hipEventRecord(ev[14], sw);
     if (split) {
         wedge_small<AT>(d, per_edge, hc, side, ev);
@@ -1705,13 +1723,8 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
         wedge_pass<AT>(d, per_edge, hc, st, ev);
     }
     (void)hipEventRecord(ev[10], st);
-    // vertex pass + combine
-    if (per_edge && n > 0 && m > 0) {
-        launch_fill<u64>(d.tri, n, 0ull, st);
-        launch_fill<u64>(d.sdeg, n, 0ull, st);
-        hipLaunchKernelGGL(k_vertex, dim3(cdiv(2 * (int64_t)m, 256)), dim3(256), 0, st, d.nsrow, d.ncol, d.s2k,
-                           d.ndeg, e.t, 2 * (int64_t)m, d.tri, d.sdeg);
-    }
+    // vertex pass (unless done beside the gather pass) + combine
+    if (per_edge && n > 0 && m > 0 && !vside) vertex_sums<AT>(d, st);
     const int nb = combine_blocks(m);
     if (d.ngraphs > 0) {
         hipLaunchKernelGGL(k_combine_graphs, dim3(d.ngraphs), dim3(CB_THREADS), 0, st, d.gvb, d.optr, e, d.ocol,
@@ -1721,7 +1734,6 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
         VRec* vr = (VRec*)d.vrec;
         if (per_edge && sizeof(AT) == 4 && er && vr) {
             hipLaunchKernelGGL(k_pack_edges, dim3(cdiv(m, 256)), dim3(256), 0, st, e, d.ocol, m, er);
-            hipLaunchKernelGGL(k_pack_vertices, dim3(cdiv(n, 256)), dim3(256), 0, st, d.tri, d.sdeg, d.ndeg, n, vr);
             if constexpr (sizeof(AT) == 4)
                 hipLaunchKernelGGL((k_combine<true, AT, true>), dim3(nb), dim3(CB_THREADS), 0, st, d.eid2k, e, d.ocol,
                                    d.ndeg, d.tri, d.sdeg, er, vr, n, m, out_pe, d.sums, d.err);
