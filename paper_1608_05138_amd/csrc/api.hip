@@ -275,7 +275,7 @@ glt_status ensure_ws(glt_ctx* ctx, size_t need, hipStream_t st) {
 // 1 GiB and the budget (one launch instead of dozens on heavy-tailed graphs).
 void grow_slab(glt_ctx* ctx, Dev& d, int count, int smax, hipStream_t st) {
     if (count <= 0 || smax <= 0) return;
-    const int64_t W = (smax + 31) / 32;
+    const int64_t W = ((smax + 31) / 32 + 3) & ~3;   // row words as the triangle pass pads them
     const int64_t per = std::max<int64_t>((int64_t)smax * W, 4 * (int64_t)smax);   // tri rows, gather sums
     const int64_t want = std::min<int64_t>(per * count, (int64_t)1 << 28);          // words (1 GiB)
     if (want <= d.gscratch_words) return;

@@ -195,6 +195,15 @@ __device__ __forceinline__ int sh_find(const int* hk, const unsigned char* hv, i
 #ifndef TRI_HT_F2
 #define TRI_HT_F2 2
 #endif
+// Words per adjacency row M_i in the workgroup triangle pass.  Rows in the global slab are
+// padded to a multiple of four words, so they are 16-byte aligned and the 4-clique sweep
+// reads them in 16-byte loads (the padding words stay zero); rows in LDS are not (16-byte LDS
+// reads at scattered rows measured slower there).
+__host__ __device__ inline int tri_row_words(int s, bool gm) {
+    const int w = (s + 31) / 32;
+    return gm ? ((w + 3) & ~3) : w;
+}
+
 __host__ __device__ inline int tri_blk_ht(int smax) {
     const int f = smax <= 256 ? TRI_HT_F : smax <= 640 ? TRI_HT_F2 : 2;
     int h = 64;
@@ -369,6 +378,23 @@ __global__ __launch_bounds__(TW_THREADS) void k_tri_wave(const int* __restrict__
 // triangle / 4-clique pass, out-degree > 64: one workgroup per vertex, M rows of W words
 // in LDS (GM = false) or in a per-workgroup global slab (GM = true)
 // ---------------------------------------------------------------------------------------
+// popcount(M_i & M_j) over W words (GM: 16-byte loads of padded rows)
+template <bool GM>
+__device__ __forceinline__ u64 row_and_count(const u32* M, int W, int i, int j) {
+    u64 c = 0;
+    if constexpr (GM) {
+        const uint4* mi = reinterpret_cast<const uint4*>(M + (int64_t)i * W);
+        const uint4* mj = reinterpret_cast<const uint4*>(M + (int64_t)j * W);
+        for (int wd = 0; wd < W / 4; wd++) {
+            const uint4 x = mi[wd], y = mj[wd];
+            c += (u64)(__popc(x.x & y.x) + __popc(x.y & y.y) + __popc(x.z & y.z) + __popc(x.w & y.w));
+        }
+    } else {
+        for (int wd = 0; wd < W; wd++) c += (u64)__popc(M[i * W + wd] & M[j * W + wd]);
+    }
+    return c;
+}
+
 template <bool PE, bool GM, bool REC, typename AT>
 __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ list, int nlist, int smax,
                                                        const int* __restrict__ optr, const int* __restrict__ ocol,
@@ -385,7 +411,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
     int* sS = (int*)(sK + smax);
     int* sOb = sS + smax;
     int* sLen = sOb + smax;
-    const int Wmax = (smax + 31) / 32;
+    const int Wmax = tri_row_words(smax, GM);
     u32* M = GM ? gscratch + (int64_t)blockIdx.x * smax * Wmax : (u32*)(sLen + smax);
     const int HT = tri_blk_ht(smax);
     const u32 hmask = (u32)HT - 1;
@@ -395,7 +421,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
     const int a = list[blockIdx.x];
     const int o0 = optr[a];
     const int s = optr[a + 1] - o0;
-    const int W = (s + 31) / 32;
+    const int W = tri_row_words(s, GM);
     for (int q = tid; q < HT; q += TB_THREADS) hk[q] = -1;
     __syncthreads();
     // S, its out-list offsets and lengths; S into the hash
@@ -478,7 +504,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
             for (int u = 0; u < CR; u++) {
                 u64 tk = 0;
                 if (rk[u] >= 0) {
-                    for (int wd = 0; wd < W; wd++) tk += (u64)__popc(M[ri[u] * W + wd] & M[rj[u] * W + wd]);
+                    tk = row_and_count<GM>(M, W, ri[u], rj[u]);
                     atomicAdd(&e.t[rk[u]], 1u);
                     if (PE && tk) {
                         acc_add<AT>(e.K, rk[u], tk);
@@ -508,8 +534,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
                     const int i = c0 + r.y, k = q + r.x;
                     const int j = bh_find(hk, hp, hmask, ocol[k]);
                     if (j >= 0) {
-                        u64 tk = 0;
-                        for (int wd = 0; wd < W; wd++) tk += (u64)__popc(M[i * W + wd] & M[j * W + wd]);
+                        const u64 tk = row_and_count<GM>(M, W, i, j);
                         atomicAdd(&e.t[k], 1u);
                         if (PE && tk) {
                             acc_add<AT>(e.K, k, tk);
@@ -548,9 +573,8 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
 }
 
 static inline size_t tri_blk_lds(int smax, bool gm) {
-    const int Wmax = (smax + 31) / 32;
     size_t b = (size_t)smax * (8 + 4 + 4 + 4);
-    if (!gm) b += (size_t)smax * Wmax * 4;
+    if (!gm) b += (size_t)smax * tri_row_words(smax, false) * 4;
     b += (size_t)tri_blk_ht(smax) * (4 + 2);
     return b;
 }
@@ -1651,7 +1675,7 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
         // the global slab holds one M per workgroup: launch in groups that fit it
         int64_t grp = c;
         if (gm) {
-            const int64_t per = (int64_t)smax * ((smax + 31) / 32);
+            const int64_t per = (int64_t)smax * tri_row_words(smax, true);
             grp = d.gscratch_words / per;
             if (grp < 1) grp = 1;
         }
