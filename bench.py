@@ -28,11 +28,11 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # source with the hash below and are reported only while it is unchanged.
 TRAFFIC = {
     "source": "paper_1608_05138_amd/csrc/count.hip",
-    "sha256": "6f901e7d79dc595d20bfe207be4c0bc79b36a4cae2fb92603971cfe7d8b4b7af",
+    "sha256": "37f059036e1d4e2fb2707da5cb914f861df862a12e93c1ae89fd402e2642b872",
     "workload": "chung_lu_1m", "per_edge": True,
-    "bytes": {"tri_wave": 3673902176, "tri_wg": 4442267296, "gather_wave": 1485006720,
-              "gather_wg": 2895340128, "wedge_wave": 82191552, "wedge_mid": 3529322272,
-              "wedge_wg": 9122681184, "wedge_huge": 38912},
+    "bytes": {"tri_wave": 3667971872, "tri_wg": 4452787744, "gather_wave": 1482366464,
+              "gather_wg": 2903822176, "wedge_wave": 82187840, "wedge_mid": 3527885856,
+              "wedge_wg": 9086386400, "wedge_huge": 38912},
 }
 
 
