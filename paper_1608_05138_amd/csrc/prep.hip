@@ -443,25 +443,36 @@ __global__ __launch_bounds__(256) void k_vinfo(const int* __restrict__ nrp, cons
     if (x < n) vinf[x] = make_int4(nrp[x] + dlo[x], nrp[x + 1], optr[x], order[x]);
 }
 
-// One thread per relabelled entry.  Upward entries (x -> y, y > x) copy themselves into the
-// oriented CSR at index k and clear the edge's accumulators; downward entries find their
-// edge's k by binary search of x in N+(y), map themselves to k and (PE: per-edge output)
-// name the caller's edge id of k.  Global counts need only t and u of an edge, and no
-// caller edge ids.
+// One thread per relabelled entry s of row x (y = ncol[s]).  Upward entries (y > x) copy
+// themselves into the oriented CSR at index k and clear the edge's accumulators; downward
+// entries find their edge's k by binary search of x in N+(y), map themselves to k and (PE:
+// per-edge output) name the caller's edge id of k.  Global counts need only t and u of an
+// edge, and no caller edge ids.  Every entry also records, for the wedge pass, the oriented
+// range [k0, k1) of the tops of the wedges x - y - top (top above x: all of N+(y) when y > x,
+// the part after x when y < x) and adds its length to wcnt[x] (runs of one row summed in the
+// wavefront first); upward entries add |N+(y)| to the triangle-list totals of x's path.
 template <bool PE>
 __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ ncol, const int* __restrict__ nsrow,
                                                     const int4* __restrict__ vinf, const u32* __restrict__ oslot,
                                                     const u32* __restrict__ upx, int64_t S, int m,
                                                     int* __restrict__ ocol, int* __restrict__ s2k,
-                                                    int* __restrict__ eid2k, EdgeArrays ea, int* __restrict__ err) {
+                                                    int* __restrict__ eid2k, EdgeArrays ea, int2* __restrict__ wb,
+                                                    u64* __restrict__ wcnt, u64* __restrict__ wspread,
+                                                    int* __restrict__ err) {
+    __shared__ u64 red[2][256 / GLT_WAVE];
     const int64_t s64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int bad = 0;
+    u64 wc = 0, lw = 0, lb = 0;
+    int x = 0x7fffffff;
     if (s64 < S) {
         const int s = (int)s64;
-        const int x = nsrow[s];
+        x = nsrow[s];
         const int4 vx = vinf[x];
         const int ub = vx.x;
         const int y = ncol[s];
+        const int4 vy = vinf[y];
+        const int y1 = vy.z + (vy.y - vy.x);   // optr[y + 1]
+        int2 r = make_int2(0, 0);
         if (s >= ub) {
             // upward x -> y: its own oriented slot
             const int k = vx.z + (s - ub);
@@ -472,11 +483,14 @@ __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ ncol
                 s2k[s] = k;
                 ea.t[k] = 0; ea.u[k] = x;
                 if (PE) { ea.K[k] = 0; ea.P[k] = 0; ea.g[k] = 0; ea.sig[k] = 0; }
+                r = make_int2(vy.z, y1);
+                const int dpx = vx.y - vx.x;   // |N+(x)|: the triangle-pass path of x
+                if (dpx >= 2 && dpx <= 64) lw = (u64)(y1 - vy.z);
+                else if (dpx > 64) lb = (u64)(y1 - vy.z);
             }
         } else {
             // downward x -> y (y ranked below x): the edge's slot is x's place in N+(y), a short
             // list (out-degrees are bounded by sqrt(2m) in the degree order)
-            const int4 vy = vinf[y];
             const int yb = vy.x, ye = vy.y;
             const int sp = lower_bound_i32(ncol, yb, ye, x);
             const int k = vy.z + (sp - yb);
@@ -484,6 +498,7 @@ __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ ncol
                 bad = ERR_ASYM;
             } else {
                 s2k[s] = k;
+                r = make_int2(k + 1, y1);
                 if (PE) {
                     const u32 j = (vx.w < vy.w) ? oslot[s] : oslot[sp];
                     const u32 eid = upx[j];
@@ -492,9 +507,24 @@ __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ ncol
                 }
             }
         }
+        wb[s] = r;
+        wc = (u64)(r.y - r.x);
     }
+    bool last;
+    const u64 run = seg_sum_last(wc, x, last);
+    if (last && run && x != 0x7fffffff) atomicAdd(&wcnt[x], run);
+    const u64 ta = wave_sum(lw), tb = wave_sum(lb);
+    if (glt_lane() == 0) { red[0][threadIdx.x / GLT_WAVE] = ta; red[1][threadIdx.x / GLT_WAVE] = tb; }
     bad = wave_or(bad);
     if (glt_lane() == 0 && bad) atomicOr(err, bad);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 sa = 0, sb = 0;
+        for (int q = 0; q < 256 / GLT_WAVE; q++) { sa += red[0][q]; sb += red[1][q]; }
+        u64* line = wspread + (blockIdx.x & (GSPREAD - 1)) * WSPREAD_WORDS;
+        if (sa) atomicAdd(&line[2], sa);
+        if (sb) atomicAdd(&line[3], sb);
+    }
 }
 
 // Triangle / gather pass buckets by out-degree s = |N+(x)|.
@@ -525,47 +555,6 @@ __global__ __launch_bounds__(256) void k_tbuckets(const int* __restrict__ optr, 
     }
     __syncthreads();
     if (threadIdx.x < TB_N && bmax[threadIdx.x]) atomicMax(&tmax[threadIdx.x], bmax[threadIdx.x]);
-}
-
-// Wedge pass work: per relabelled entry (y -> w) the wedges y - w - x with x above both y
-// and w (x in N+(w), x > y), summed per y; and the triangle pass's list lengths |N+(w)|
-// over upward entries, totalled by the triangle-pass path of y (work[2] wave, work[3]
-// workgroup).  One thread per entry, runs of one row summed in the wavefront.
-__global__ __launch_bounds__(256) void k_wcount(const int* __restrict__ ncol, const int* __restrict__ nsrow,
-                                                const int* __restrict__ optr, const int* __restrict__ s2k, int64_t S,
-                                                u64* __restrict__ wcnt, u64* __restrict__ wspread,
-                                                int2* __restrict__ wb) {
-    __shared__ u64 red[2][256 / GLT_WAVE];
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    u64 wc = 0, lw = 0, lb = 0;
-    int y = 0x7fffffff;
-    if (s < S) {
-        y = nsrow[s];
-        const int w = ncol[s];
-        const int w0 = optr[w], w1 = optr[w + 1];
-        const int dpw = w1 - w0;
-        const int k0 = (w > y) ? w0 : s2k[s] + 1;   // the tops of y - w - x lie above y
-        wb[s] = make_int2(k0, w1);
-        wc = (u64)(w1 - k0);
-        if (w > y) {
-            const int dpy = optr[y + 1] - optr[y];
-            if (dpy >= 2 && dpy <= 64) lw = (u64)dpw;
-            else if (dpy > 64) lb = (u64)dpw;
-        }
-    }
-    bool last;
-    const u64 run = seg_sum_last(wc, y, last);
-    if (last && run && y != 0x7fffffff) atomicAdd(&wcnt[y], run);
-    const u64 a = wave_sum(lw), b = wave_sum(lb);
-    if (glt_lane() == 0) { red[0][threadIdx.x / GLT_WAVE] = a; red[1][threadIdx.x / GLT_WAVE] = b; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        u64 ta = 0, tb = 0;
-        for (int q = 0; q < 256 / GLT_WAVE; q++) { ta += red[0][q]; tb += red[1][q]; }
-        u64* line = wspread + (blockIdx.x & (GSPREAD - 1)) * WSPREAD_WORDS;
-        if (ta) atomicAdd(&line[2], ta);
-        if (tb) atomicAdd(&line[3], tb);
-    }
 }
 
 // Bucket the wedge pass by wedges per vertex; per-class wedge totals go to the spread work
@@ -681,23 +670,20 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
     int* dplus = d.itmp + scan_tmp_elems(S + n + 1);  // past the scan scratch
     hipLaunchKernelGGL(k_dlo, dim3(nblk(n, 256)), dim3(256), 0, st, d.nrp, d.ncol, n, d.dlo, dplus);
     launch_excl_scan<int, int>(dplus, d.optr, n, d.itmp, d.optr + n, st);
+    launch_fill<u64>(d.wcnt, n, 0ull, st);
     if (S > 0) {
         hipLaunchKernelGGL(k_vinfo, dim3(nblk(n, 256)), dim3(256), 0, st, d.nrp, d.dlo, d.optr, d.order, n, d.vinf);
         if (d.per_edge)
             hipLaunchKernelGGL(k_edge_index<true>, dim3(nblk(S, 256)), dim3(256), 0, st, d.ncol, d.nsrow, d.vinf,
-                               oslot, d.upx, S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.err);
+                               oslot, d.upx, S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.wb, d.wcnt, d.wspread, d.err);
         else
             hipLaunchKernelGGL(k_edge_index<false>, dim3(nblk(S, 256)), dim3(256), 0, st, d.ncol, d.nsrow, d.vinf,
-                               oslot, d.upx, S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.err);
+                               oslot, d.upx, S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.wb, d.wcnt, d.wspread, d.err);
     }
     // work lists
     hipLaunchKernelGGL(k_tbuckets, dim3(nblk(n, 256)), dim3(256), 0, st, d.optr, n, d.tlist, d.counts,
                        d.counts + TB_N + WB_N, d.toff);
     launch_excl_scan<u64, u64>(d.toff, d.toff, n, d.tmp64, d.toff + n, st);
-    launch_fill<u64>(d.wcnt, n, 0ull, st);
-    if (S > 0)
-        hipLaunchKernelGGL(k_wcount, dim3(nblk(S, 256)), dim3(256), 0, st, d.ncol, d.nsrow, d.optr, d.s2k, S, d.wcnt,
-                           d.wspread, d.wb);
     hipLaunchKernelGGL(k_wappend, dim3(nblk(n, 256)), dim3(256), 0, st, d.wcnt, n, d.wedge_wave_max, d.wedge_mid_max < 65535 ? d.wedge_mid_max : 65535, d.wedge_wg_max, d.wlist,
                        d.counts + TB_N, d.wspread);
     return 0;
