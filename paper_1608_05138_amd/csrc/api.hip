@@ -131,7 +131,7 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
     d.tlist = c.take<int>((int64_t)TB_N * n);
     d.wlist = c.take<int>((int64_t)WB_N * n);
     d.nsum_slots = glt_combine_blocks(m > 0 ? m : 1);
-    d.sums = c.take<u64>((int64_t)d.nsum_slots * 13 * 2);
+    d.sums = c.take<u64>((int64_t)(d.nsum_slots + GLT_REDUCE_BLOCKS) * 13 * 2);   // + reduction stage
     d.gscratch_words = kGScratchWords;
     d.gscratch = c.take<u32>(kGScratchWords);
     d.key0 = c.take<u64>(big);
@@ -375,6 +375,7 @@ void record_timing(glt_ctx* ctx) {
     if (ctx->last_mode == 2) {               // workgroup paths on the second stream from the fork
         be[2][0] = 1;
         be[4][0] = 13;
+        be[6][0] = 5;                        // the mid class follows the gather workgroup path
     }
     for (int i = 0; i < NSEG; i++) {
         const int b0 = be[i][0];

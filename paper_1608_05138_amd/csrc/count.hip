@@ -1335,41 +1335,53 @@ __global__ __launch_bounds__(CB_THREADS) void k_combine(const int* __restrict__ 
     }
 }
 
-// one workgroup: final 128-bit reduction of the per-block partials
+// 128-bit reduction of per-block partial records (NCS (lo, hi) pairs each) into one record
+// per workgroup at out.  The records are read as 16-byte (lo, hi) items in address order;
+// a workgroup's 1014 = 78 x NCS active threads step by a multiple of NCS items, so every
+// thread keeps to one column (its index mod NCS) and the loads stay coalesced.
+#define RP_ACT ((1024 / NCS) * NCS)
 __global__ __launch_bounds__(1024) void k_reduce_parts(const u64* __restrict__ part, int nparts,
-                                                       u64* __restrict__ fin) {
-    __shared__ u64 red[1024 / GLT_WAVE][NCS][2];
-    u64 lo[NCS], hi[NCS];
-#pragma unroll
-    for (int c = 0; c < NCS; c++) { lo[c] = 0; hi[c] = 0; }
-    // each thread sums whole partial records (all NCS sums of one block are contiguous)
-    for (int b = threadIdx.x; b < nparts; b += 1024) {
-        const u64* p = part + (int64_t)b * NCS * 2;
-#pragma unroll
-        for (int c = 0; c < NCS; c++) {
-            const u64 o = lo[c];
-            lo[c] += p[2 * c];
-            hi[c] += p[2 * c + 1] + ((lo[c] < o) ? 1ull : 0ull);
+                                                       u64* __restrict__ out) {
+    __shared__ u64 red[RP_ACT][2];
+    const int t = threadIdx.x;
+    if (t < RP_ACT) {
+        u64 lo = 0, hi = 0;
+        const int64_t items = (int64_t)nparts * NCS;
+        const int64_t stride = (int64_t)gridDim.x * RP_ACT;
+        const ulonglong2* p = reinterpret_cast<const ulonglong2*>(part);
+        for (int64_t q = (int64_t)blockIdx.x * RP_ACT + t; q < items; q += stride) {
+            const ulonglong2 v = p[q];
+            add128(lo, hi, v.x);
+            hi += v.y;
         }
-    }
-    const int w = threadIdx.x / GLT_WAVE;
-#pragma unroll
-    for (int c = 0; c < NCS; c++) {
-        wave_sum128(lo[c], hi[c]);
-        if (glt_lane() == 0) { red[w][c][0] = lo[c]; red[w][c][1] = hi[c]; }
+        red[t][0] = lo;
+        red[t][1] = hi;
     }
     __syncthreads();
-    if (threadIdx.x < NCS) {
-        const int c = threadIdx.x;
+    if (t < NCS) {
         u64 L = 0, H = 0;
-        for (int q = 0; q < 1024 / GLT_WAVE; q++) {
-            const u64 o = L;
-            L += red[q][c][0];
-            H += red[q][c][1] + ((L < o) ? 1ull : 0ull);
+        for (int q = t; q < RP_ACT; q += NCS) {
+            add128(L, H, red[q][0]);
+            H += red[q][1];
         }
-        fin[2 * c] = L;
-        fin[2 * c + 1] = H;
+        out[((int64_t)blockIdx.x * NCS + t) * 2] = L;
+        out[((int64_t)blockIdx.x * NCS + t) * 2 + 1] = H;
     }
+}
+
+// Partial records of nb combine blocks -> final_sums: one workgroup per RP_ACT x 2 items
+// (at most GLT_REDUCE_BLOCKS) writing records behind the partials, then one workgroup.
+static void reduce_parts(const Dev& d, int nb, hipStream_t st) {
+    const int64_t items = (int64_t)nb * NCS;
+    int r = (int)((items + 2 * RP_ACT - 1) / (2 * RP_ACT));
+    if (r > GLT_REDUCE_BLOCKS) r = GLT_REDUCE_BLOCKS;
+    if (r <= 1) {
+        hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(1024), 0, st, d.sums, nb, d.final_sums);
+        return;
+    }
+    u64* mid = d.sums + (int64_t)d.nsum_slots * NCS * 2;
+    hipLaunchKernelGGL(k_reduce_parts, dim3(r), dim3(1024), 0, st, d.sums, nb, mid);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(1024), 0, st, mid, r, d.final_sums);
 }
 
 // Batched global mode: one workgroup per graph over its oriented edges, unrestricted sums
@@ -1583,18 +1595,23 @@ static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st, int res
 //   ev[0] start                            ev[1] end of preprocessing (fork)
 //   ev[2..5] after tri wave / tri wg / gather wave / gather wg
 //   ev[12], ev[13] start of the gather wavefront / workgroup path (after their joins)
-//   ev[14] start of the wedge pass          ev[6], ev[7] after the wave / mid classes
+//   ev[14] start of the wave class          ev[6], ev[7] after the wave / mid classes
 //   ev[15] start of the workgroup class     ev[8], ev[9] after the workgroup / huge classes
 //   ev[10] after the last join              ev[11] after the combine
 // The passes share only read-only inputs and write distinct accumulators, so the streams
 // join only where a pass needs another's final values (the gather pass needs every t).
-// Wave and mid classes on stream s (ev[6], ev[7] after each).
+// Wave class, and mid class, on stream s (ev[6], ev[7] after each).
 template <typename AT>
-static void wedge_small(const Dev& d, int per_edge, const int* hc, hipStream_t s, hipEvent_t* ev) {
+static void wedge_wave_class(const Dev& d, int per_edge, const int* hc, hipStream_t s, hipEvent_t* ev) {
     const int* wc = hc + TB_N;
     if (per_edge) launch_wedge<true, AT, WW_T, WW_G, WW_HT, 0, false>(d, WB_WAVE, wc[WB_WAVE], s);
     else launch_wedge<false, AT, WW_T, WW_G, WW_HT, 0>(d, WB_WAVE, wc[WB_WAVE], s);
     (void)hipEventRecord(ev[6], s);
+}
+
+template <typename AT>
+static void wedge_mid_class(const Dev& d, int per_edge, const int* hc, hipStream_t s, hipEvent_t* ev) {
+    const int* wc = hc + TB_N;
     if (per_edge) launch_wedge<true, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, WB_MID, wc[WB_MID], s);
     else launch_wedge<false, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, WB_MID, wc[WB_MID], s);
     (void)hipEventRecord(ev[7], s);
@@ -1617,7 +1634,8 @@ static void wedge_large(const Dev& d, int per_edge, const int* hc, hipStream_t s
 
 template <typename AT>
 static void wedge_pass(const Dev& d, int per_edge, const int* hc, hipStream_t s, hipEvent_t* ev) {
-    wedge_small<AT>(d, per_edge, hc, s, ev);
+    wedge_wave_class<AT>(d, per_edge, hc, s, ev);
+    wedge_mid_class<AT>(d, per_edge, hc, s, ev);
     wedge_large<AT>(d, per_edge, hc, s, ev);
 }
 
@@ -1638,8 +1656,8 @@ static void vertex_sums(const Dev& d, hipStream_t s) {
 // Stream modes: 0 everything on st; 1 the wedge pass on `side`, beside the triangle and
 // gather passes on st; 2 the workgroup paths of the triangle and gather passes on `side`,
 // beside their wavefront paths on st (each gather path starts once both triangle paths
-// are done), then the wave and mid wedge classes on `side` beside the gather pass's
-// wavefront path, and the workgroup and huge wedge classes alone on st after both.
+// are done), then the mid wedge class on `side` and the vertex pass and wave wedge class on
+// st, and the workgroup and huge wedge classes alone on st after both.
 template <typename AT>
 static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hipStream_t st, hipStream_t side,
                          hipEvent_t* ev, int mode) {
@@ -1658,6 +1676,7 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
     if (overlap) {
         // the wedge pass on the side stream, beside the triangle and gather passes
         (void)hipStreamWaitEvent(side, ev[1], 0);
+        (void)hipEventRecord(ev[14], side);
         wedge_pass<AT>(d, per_edge, hc, side, ev);
     }
     // triangle / 4-clique pass
@@ -1732,23 +1751,26 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
         }
     }
     (void)hipEventRecord(ev[5], sw);
-    // mode 2: the vertex pass follows the gather workgroup path on the second stream (t is
-    // final there), beside the gather wavefront path; it is in no timed group then
-    const bool vside = split && per_edge && n > 0 && m > 0;
-    if (vside) vertex_sums<AT>(d, side);
-    (void)hipEventRecord(ev[14], sw);
+    // mode 2: the mid wedge class follows the gather workgroup path on the second stream;
+    // the vertex pass (t is final once st waited for both triangle paths; in no timed group)
+    // and the wave wedge class follow the gather wavefront path on st
+    const bool vsplit = split && per_edge && n > 0 && m > 0;
     if (split) {
-        wedge_small<AT>(d, per_edge, hc, side, ev);
+        wedge_mid_class<AT>(d, per_edge, hc, side, ev);
+        if (vsplit) vertex_sums<AT>(d, st);
+        (void)hipEventRecord(ev[14], st);
+        wedge_wave_class<AT>(d, per_edge, hc, st, ev);
         (void)hipStreamWaitEvent(st, ev[7], 0);   // join: the large classes run alone
         wedge_large<AT>(d, per_edge, hc, st, ev);
     } else if (overlap) {
         (void)hipStreamWaitEvent(st, ev[9], 0);   // join the wedge pass
     } else {
+        (void)hipEventRecord(ev[14], st);
         wedge_pass<AT>(d, per_edge, hc, st, ev);
     }
     (void)hipEventRecord(ev[10], st);
     // vertex pass (unless done beside the gather pass) + combine
-    if (per_edge && n > 0 && m > 0 && !vside) vertex_sums<AT>(d, st);
+    if (per_edge && n > 0 && m > 0 && !vsplit) vertex_sums<AT>(d, st);
     const int nb = combine_blocks(m);
     if (d.ngraphs > 0) {
         hipLaunchKernelGGL(k_combine_graphs, dim3(d.ngraphs), dim3(CB_THREADS), 0, st, d.gvb, d.optr, e, d.ocol,
@@ -1768,7 +1790,7 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
             hipLaunchKernelGGL((k_combine<false, AT, false>), dim3(nb), dim3(CB_THREADS), 0, st, d.eid2k, e, d.ocol,
                                d.ndeg, d.tri, d.sdeg, er, vr, n, m, out_pe, d.sums, d.err);
         }
-        hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(1024), 0, st, d.sums, nb, d.final_sums);
+        reduce_parts(d, nb, st);
     } else {
         launch_fill<u64>(d.final_sums, 2 * NCS, 0ull, st);
     }

@@ -55,6 +55,7 @@ enum { S_C3 = 0, S_C4, S_C5, S_C7, S_C8, S_C9, S_C10, S_C11, S_C12, S_C13, S_C14
 // The per-group totals array (gsum) holds NSUMS words per line and uses S_K4x3, S_NC4 and
 // the triangle counts of the two triangle-pass paths (measurement only).
 enum { GS_TRI_WAVE = 0, GS_TRI_WG = 1 };
+#define GLT_REDUCE_BLOCKS 256   // first-stage workgroups of the 128-bit partial-sum reduction
 #define GSPREAD 64   // lines of gsum a single graph's groups spread their atomics over
 #define WSPREAD_WORDS 8   // u64 per line of the spread work counters (folded into work[])
 // gsum line of a group: its graph in a batch, else spread by workgroup index
@@ -109,8 +110,8 @@ struct Dev {
     u64* wcnt;        // wedges per vertex [n] (wedge-pass bucketing)
     u32* rowx;        // [S+1] exclusive prefix of row starts of the input CSR: row of entry s = rowx[s+1]-1
     int* nsrow;       // [S] row of each relabelled CSR entry
-    u64* sums;        // per-block partial sums, NSUMS per entry
-    int nsum_slots;   // capacity of sums (entries)
+    u64* sums;        // per-block partial sums, 13 (lo, hi) pairs per entry, then GLT_REDUCE_BLOCKS entries
+    int nsum_slots;   // combine blocks' entries of sums (the reduction stage's follow)
     u64* final_sums;  // 2*NSUMS u64 (lo,hi) reduced 128-bit sums
     u32* gscratch;    // global-memory adjacency bitmaps for very high out-degree
     int64_t gscratch_words;
