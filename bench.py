@@ -28,11 +28,11 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # source with the hash below and are reported only while it is unchanged.
 TRAFFIC = {
     "source": "paper_1608_05138_amd/csrc/count.hip",
-    "sha256": "37f059036e1d4e2fb2707da5cb914f861df862a12e93c1ae89fd402e2642b872",
+    "sha256": "a9293444c1ee3b234d89349cc324099b433eebb64779af3523c9ce5380518a19",
     "workload": "chung_lu_1m", "per_edge": True,
-    "bytes": {"tri_wave": 3667971872, "tri_wg": 4452787744, "gather_wave": 1482366464,
-              "gather_wg": 2903822176, "wedge_wave": 82187840, "wedge_mid": 3527885856,
-              "wedge_wg": 9086386400, "wedge_huge": 38912},
+    "bytes": {"tri_wave": 3672354432, "tri_wg": 4451754720, "gather_wave": 1482230400,
+              "gather_wg": 2900660448, "wedge_wave": 82265536, "wedge_mid": 3528601760,
+              "wedge_wg": 9050081632, "wedge_huge": 38912},
 }
 
 
