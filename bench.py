@@ -281,7 +281,8 @@ def bench_batch(args):
 
 
 def group_bytes(work, per_edge, acc_bytes, records=True):
-    """Algorithmic bytes of each counting kernel group (section Measurement).
+    """Algorithmic bytes of each counting kernel group: the bytes the method must move per
+    unit of work (list entry, triangle, wedge), times the units the call counted.
     Triangle pass: one 4 B id per out-list entry scanned, and per triangle its 4 B triangle
     credit plus (per-edge mode) one 4-clique credit, plus, with triangle records, the 8 B
     record written and read back.  Gather pass: per triangle its record (or, without records,
@@ -390,8 +391,8 @@ def main():
         print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md but not implemented", file=sys.stderr)
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is not implemented", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch_10k":
