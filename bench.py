@@ -226,6 +226,8 @@ def bench_batch(args):
                  "tuned_device_ms": round(best_ms, 3)}
         print(f"[bench] autotuned schedule {best} ({best_ms:.2f} ms on the tuning batch)", file=sys.stderr, flush=True)
         del tpk
+    if args.stream_mode is not None:
+        ctx.set_schedule(wedge_stream=args.stream_mode)
     print(f"[bench] batch: {len(graphs)} graphs, {m_total} edges; warmup {args.warmup}", file=sys.stderr,
           flush=True)
     for _ in range(args.warmup):
