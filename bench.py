@@ -137,7 +137,15 @@ def bench_served(args):
         th.start()
         t0 = srv.clock() + 0.2
         sched = np.empty(len(arrivals))
+        next_note = time.time() + 10.0
+
+        def note(what):
+            print(f"[bench] {what}: {len(got)} of {len(arrivals)} requests done", file=sys.stderr, flush=True)
+
         for i, (ta, kind, idx) in enumerate(arrivals):
+            if time.time() >= next_note:
+                note(f"submitted {i}")
+                next_note += 10.0
             target = t0 + ta
             while True:
                 d = target - srv.clock()
@@ -154,6 +162,9 @@ def bench_served(args):
         deadline = time.time() + 600
         while len(got) < len(arrivals) and time.time() < deadline:
             time.sleep(0.01)
+            if time.time() >= next_note:
+                note("all submitted")
+                next_note += 10.0
         th.join(timeout=5)
         srv.close()
         if len(got) < len(arrivals):
