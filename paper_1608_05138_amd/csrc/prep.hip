@@ -456,9 +456,9 @@ __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ ncol
                                                     const int4* __restrict__ vinf, const u32* __restrict__ oslot,
                                                     const u32* __restrict__ upx, int64_t S, int m,
                                                     int* __restrict__ ocol, int* __restrict__ s2k,
-                                                    int* __restrict__ eid2k, EdgeArrays ea, int2* __restrict__ wb,
-                                                    u64* __restrict__ wcnt, u64* __restrict__ wspread,
-                                                    int* __restrict__ err) {
+                                                    int* __restrict__ eid2k, EdgeArrays ea, int acc32,
+                                                    int2* __restrict__ wb, u64* __restrict__ wcnt,
+                                                    u64* __restrict__ wspread, int* __restrict__ err) {
     __shared__ u64 red[2][256 / GLT_WAVE];
     const int64_t s64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int bad = 0;
@@ -482,7 +482,16 @@ __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ ncol
                 ocol[k] = y;
                 s2k[s] = k;
                 ea.t[k] = 0; ea.u[k] = x;
-                if (PE) { ea.K[k] = 0; ea.P[k] = 0; ea.g[k] = 0; ea.sig[k] = 0; }
+                if (PE) {
+                    // 32-bit accumulators: K and P are u32 arrays and one word of g holds g and sigma
+                    if (acc32) {
+                        reinterpret_cast<u32*>(ea.K)[k] = 0;
+                        reinterpret_cast<u32*>(ea.P)[k] = 0;
+                        ea.g[k] = 0;
+                    } else {
+                        ea.K[k] = 0; ea.P[k] = 0; ea.g[k] = 0; ea.sig[k] = 0;
+                    }
+                }
                 r = make_int2(vy.z, y1);
                 const int dpx = vx.y - vx.x;   // |N+(x)|: the triangle-pass path of x
                 if (dpx >= 2 && dpx <= 64) lw = (u64)(y1 - vy.z);
@@ -675,10 +684,12 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
         hipLaunchKernelGGL(k_vinfo, dim3(nblk(n, 256)), dim3(256), 0, st, d.nrp, d.dlo, d.optr, d.order, n, d.vinf);
         if (d.per_edge)
             hipLaunchKernelGGL(k_edge_index<true>, dim3(nblk(S, 256)), dim3(256), 0, st, d.ncol, d.nsrow, d.vinf,
-                               oslot, d.upx, S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.wb, d.wcnt, d.wspread, d.err);
+                               oslot, d.upx, S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.acc32, d.wb, d.wcnt, d.wspread,
+                               d.err);
         else
             hipLaunchKernelGGL(k_edge_index<false>, dim3(nblk(S, 256)), dim3(256), 0, st, d.ncol, d.nsrow, d.vinf,
-                               oslot, d.upx, S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.wb, d.wcnt, d.wspread, d.err);
+                               oslot, d.upx, S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.acc32, d.wb, d.wcnt, d.wspread,
+                               d.err);
     }
     // work lists
     hipLaunchKernelGGL(k_tbuckets, dim3(nblk(n, 256)), dim3(256), 0, st, d.optr, n, d.tlist, d.counts,
