@@ -141,8 +141,9 @@ glt_status glt_count_batch(glt_ctx* ctx, const glt_batch* b, uint32_t flags, glt
  * [5]-[8] 4-cycle wedge pass, wave / mid / workgroup / huge class, [9] vertex sums, combine
  * and reduction, [10] the whole call.  With the schedule's wedge_stream = 1 the wedge pass
  * runs on a second stream beside entries [1]-[4]; with wedge_stream = 2 entries [2] and [4]
- * run beside [1] and [3]; overlapping entries share the chip.  Returns the number of
- * entries written (<= cap, at most 11).
+ * run beside [1] and [3], and [6] (mid class, second stream) beside [5] (wave class, after
+ * the vertex sums on the call's stream); overlapping entries share the chip.  Returns the
+ * number of entries written (<= cap, at most 11).
  */
 int glt_last_timing(const glt_ctx* ctx, float* ms, int cap);
 
@@ -181,7 +182,8 @@ typedef struct {
                                   pass on a second stream beside the triangle and gather
                                   passes; 2 the workgroup paths of the triangle and gather
                                   passes on a second stream beside their wavefront paths,
-                                  the 4-cycle pass alone after both                          */
+                                  then the mid 4-cycle class there beside the vertex sums
+                                  and the wave class, the larger classes alone after both   */
     int32_t list_order;        /* order of the workgroup work lists (Section 4.3's edge order,
                                   Table 4's ordering study): 0 largest work first, 1 largest
                                   degree first, 2 ascending rank (no sort; the default),

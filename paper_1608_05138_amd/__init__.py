@@ -182,7 +182,8 @@ class Context:
         """dict of kernel-group times (ms) of the last count (HIP events on the stream each
         group runs on; with wedge_stream = 1 the wedge groups share the chip with the triangle
         and gather groups, with wedge_stream = 2 the workgroup groups share it with the
-        wavefront groups; "total" is the whole call)."""
+        wavefront groups and the mid wedge class with the wave class; "total" is the whole
+        call)."""
         buf = (ctypes.c_float * len(self.TIMING_KEYS))()
         k = self._lib.glt_last_timing(self._h, buf, len(self.TIMING_KEYS))
         return {name: float(buf[i]) for i, name in enumerate(self.TIMING_KEYS[:k])}
