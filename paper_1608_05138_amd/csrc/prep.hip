@@ -339,17 +339,21 @@ __global__ __launch_bounds__(256) void k_sort_blk(const int* __restrict__ list, 
     for (int j = t; j < len; j += 256) { key[b + j] = sk[j]; val[b + j] = sv[j]; }
 }
 
-// Rows longer than RB_MAX: one 1024-thread workgroup per row, stable LSD radix passes of 8
-// bits over `bits` key bits, ping-ponging between (kA, vA) and (kB, vB) at the row's own
-// positions; the result ends in (kA, vA).  Each pass: a digit histogram, its exclusive
-// scan, then tiles of 1024 entries in order, ranked within each wavefront by ballots and
-// across wavefronts by per-wavefront digit counts.
+// Rows longer than RB_MAX: one 1024-thread workgroup per row, stable LSD radix passes over
+// `bits` key bits, ping-ponging between (kA, vA) and (kB, vB) at the row's own positions;
+// the result ends in (kA, vA).  The passes are as few as digits of at most SB_DMAX bits
+// allow (20-bit ranks: two passes of 10 bits), the digits as even as possible.  Each pass:
+// a digit histogram, its exclusive scan, then tiles of 1024 entries in order, ranked
+// within each wavefront by ballots and across wavefronts by per-wavefront digit counts.
 #define SB_T 1024
+#define SB_DMAX 10
+#define SB_NB (1 << SB_DMAX)
 __global__ __launch_bounds__(SB_T) void k_sort_big(const int* __restrict__ list, int cnt, const int* __restrict__ nrp,
                                                    u32* __restrict__ kA, u32* __restrict__ vA, u32* __restrict__ kB,
                                                    u32* __restrict__ vB, int bits) {
-    __shared__ u32 base[256];
-    __shared__ u32 wcnt[SB_T / GLT_WAVE][256];
+    static_assert(SB_NB <= SB_T, "one bucket per thread in the bucket loops");
+    __shared__ u32 base[SB_NB];
+    __shared__ u32 wcnt[SB_T / GLT_WAVE][SB_NB];
     __shared__ u32 sscan[SB_T / GLT_WAVE];
     const int t = threadIdx.x, lane = glt_lane(), w = t / GLT_WAVE;
     const int r = list[blockIdx.x];
@@ -358,28 +362,31 @@ __global__ __launch_bounds__(SB_T) void k_sort_big(const int* __restrict__ list,
     u32* ki = kA + b; u32* vi = vA + b;
     u32* ko = kB + b; u32* vo = vB + b;
     const u64 lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (GLT_WAVE - lane));
+    const int npass_all = (bits + SB_DMAX - 1) / SB_DMAX;
+    const int dbits = npass_all > 0 ? (bits + npass_all - 1) / npass_all : 0;   // <= SB_DMAX
+    const u32 dmask = (1u << dbits) - 1u;
+    const int nb = 1 << dbits;                                                   // buckets in use
     int npass = 0;
-    for (int shift = 0; shift < bits; shift += 8, npass++) {
-        if (t < 256) {
+    for (int shift = 0; shift < bits; shift += dbits, npass++) {
+        if (t < nb) {
             base[t] = 0;
             for (int q = 0; q < SB_T / GLT_WAVE; q++) wcnt[q][t] = 0;
         }
         __syncthreads();
-        for (int j = t; j < len; j += SB_T) atomicAdd(&base[(ki[j] >> shift) & 255u], 1u);
+        for (int j = t; j < len; j += SB_T) atomicAdd(&base[(ki[j] >> shift) & dmask], 1u);
         __syncthreads();
         u32 tot;
-        const u32 ex = block_excl_scan<u32, SB_T>(t < 256 ? base[t] : 0u, sscan, tot);
-        if (t < 256) base[t] = ex;
+        const u32 ex = block_excl_scan<u32, SB_T>(t < nb ? base[t] : 0u, sscan, tot);
+        if (t < nb) base[t] = ex;
         __syncthreads();
         for (int j0 = 0; j0 < len; j0 += SB_T) {
             const int j = j0 + t;
             const bool valid = j < len;
             const u32 k = valid ? ki[j] : 0u;
             const u32 v = valid ? vi[j] : 0u;
-            const u32 d = (k >> shift) & 255u;
+            const u32 d = (k >> shift) & dmask;
             u64 peers = __ballot(valid);
-#pragma unroll
-            for (int bit = 0; bit < 8; bit++) {
+            for (int bit = 0; bit < dbits; bit++) {
                 const u64 bb = __ballot((d >> bit) & 1u);
                 peers &= ((d >> bit) & 1u) ? bb : ~bb;
             }
@@ -393,7 +400,7 @@ __global__ __launch_bounds__(SB_T) void k_sort_big(const int* __restrict__ list,
                 vo[off + rk] = v;
             }
             __syncthreads();
-            if (t < 256) {
+            if (t < nb) {
                 u32 add = 0;
                 for (int q = 0; q < SB_T / GLT_WAVE; q++) { add += wcnt[q][t]; wcnt[q][t] = 0; }
                 base[t] += add;
