@@ -30,9 +30,9 @@ TRAFFIC = {
     "source": "paper_1608_05138_amd/csrc/count.hip",
     "sha256": "a9293444c1ee3b234d89349cc324099b433eebb64779af3523c9ce5380518a19",
     "workload": "chung_lu_1m", "per_edge": True,
-    "bytes": {"tri_wave": 3673977056, "tri_wg": 4443510528, "gather_wave": 1485745664,
-              "gather_wg": 2894722976, "wedge_wave": 82243264, "wedge_mid": 3528251168,
-              "wedge_wg": 9009525344, "wedge_huge": 38912},
+    "bytes": {"tri_wave": 3673907104, "tri_wg": 4449845568, "gather_wave": 1483612160,
+              "gather_wg": 2898601408, "wedge_wave": 82198464, "wedge_mid": 3529524128,
+              "wedge_wg": 8973273696, "wedge_huge": 38912},
 }
 
 
