@@ -9,6 +9,11 @@ Contents
   subset, Section 3, Definitions 1-3 and Problem 1) and the paper's edge-centric method
   (Section 4: hash Psi with per-edge tags, clique and cycle neighbour iteration, local and
   unrestricted counts of Section 4.5, global frequencies of Section 4.6).
+  ``count_range`` runs that method over a block of edges (partial unrestricted sums and the
+  block's per-edge counts), so that long runs proceed block by block.
+* ``global_substructures``: global counts of graphs far too large for the edge-centric method,
+  from the triangles on every edge (by definition), the 4-cliques and the 4-cycles, each
+  counted once at its lowest vertex, through Sections 4.5-4.6.
 * ``brute_py``: a pure-Python enumeration for tiny graphs that pins the C brute force.
 
 Global counts are returned as Python ints (exact, they exceed 64 bits for large n).
@@ -58,7 +63,11 @@ def _load():
         lib.brute_count.argtypes = [ctypes.c_int64, P, P, P, P]
         lib.glo_count.argtypes = [ctypes.c_int64, P, P, ctypes.c_int, P, P, P]
         lib.glo_count_edges.argtypes = [ctypes.c_int64, P, P, ctypes.c_int, P, ctypes.c_int64, P]
-        for f in (lib.brute_count, lib.glo_count, lib.glo_count_edges):
+        lib.glo_count_range.argtypes = [ctypes.c_int64, P, P, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, P, P]
+        lib.glo_global_from_c.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P]
+        lib.glo_global_substructures.argtypes = [ctypes.c_int64, P, P, ctypes.c_int, P, P, P]
+        for f in (lib.brute_count, lib.glo_count, lib.glo_count_edges, lib.glo_count_range,
+                  lib.glo_global_from_c, lib.glo_global_substructures):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -116,6 +125,54 @@ def count_edges(n, row_ptr, col, eids, nthreads: int | None = None):
     if rc != 0:
         raise RuntimeError(f"oracle glo_count_edges failed: {rc}")
     return out
+
+
+def count_range(n, row_ptr, col, k0: int, k1: int, per_edge: bool = False,
+                nthreads: int | None = None):
+    """The paper's method over edges [k0, k1) only.  Returns dict(C=[17 ints], the block's
+    terms of the unrestricted sums; per_edge=[13, k1-k0] or None)."""
+    lib = _load()
+    rp, c = _prep(n, row_ptr, col)
+    C = np.zeros(34, dtype=np.uint64)
+    pe = np.zeros((13, max(0, k1 - k0)), dtype=np.uint64) if per_edge else None
+    rc = lib.glo_count_range(n, _ptr(rp), _ptr(c), nthreads or default_threads(), k0, k1, _ptr(C),
+                             _ptr(pe) if pe is not None else None)
+    if rc != 0:
+        raise RuntimeError(f"oracle glo_count_range failed: {rc}")
+    return {"C": _u128(C), "per_edge": pe}
+
+
+def global_from_c(n: int, m: int, C):
+    """Global counts X1..X17 (Section 4.6) from unrestricted sums C (17 Python ints, as
+    count_range returns them, summed over a partition of the edges)."""
+    lib = _load()
+    words = np.zeros(34, dtype=np.uint64)
+    for i, v in enumerate(C):
+        v = int(v) % (1 << 128)
+        words[2 * i] = v & ((1 << 64) - 1)
+        words[2 * i + 1] = v >> 64
+    X = np.zeros(34, dtype=np.uint64)
+    rc = lib.glo_global_from_c(n, m, _ptr(words), _ptr(X))
+    if rc != 0:
+        raise RuntimeError(f"oracle glo_global_from_c failed: {rc}")
+    return _u128(X)
+
+
+def global_substructures(n, row_ptr, col, per_edge3: bool = False, nthreads: int | None = None):
+    """Global counts from per-edge triangles, 4-cliques and 4-cycles.  Returns dict(X=[17 ints],
+    k4, c4, per_edge3=[3, m] (triangles, 2-stars, H5 per edge) or None)."""
+    lib = _load()
+    rp, c = _prep(n, row_ptr, col)
+    m = num_edges(n, rp, c)
+    X = np.zeros(34, dtype=np.uint64)
+    W = np.zeros(4, dtype=np.uint64)
+    pe = np.zeros((3, m), dtype=np.uint64) if per_edge3 else None
+    rc = lib.glo_global_substructures(n, _ptr(rp), _ptr(c), nthreads or default_threads(), _ptr(X),
+                                      _ptr(pe) if pe is not None else None, _ptr(W))
+    if rc != 0:
+        raise RuntimeError(f"oracle glo_global_substructures failed: {rc}")
+    return {"X": _u128(X), "k4": int(W[0]) | (int(W[1]) << 64), "c4": int(W[2]) | (int(W[3]) << 64),
+            "per_edge3": pe}
 
 
 def brute(n, row_ptr, col, per_edge: bool = False):

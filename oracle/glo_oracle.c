@@ -5,7 +5,7 @@
  * baseline may load this code.  It shares nothing with the GPU library: no headers, no
  * helpers, no tables.  It is deliberately plain and slow.
  *
- * Two independent methods live here:
+ * Three methods live here:
  *
  *  (1) brute_*  -- the definition (Section 3, Definitions 1-3 and Problem 1): every 3- and
  *      4-vertex subset is classified by the induced subgraph it spans.  Per-edge counts
@@ -28,7 +28,14 @@
  *      4-path and the disconnected ones) follow from a partition of V \ {u,v} into
  *      T, S_u, S_v and D (neither endpoint) and the edge counts between those classes,
  *      derived from |T|, the clique and cycle counts, three extra scan counters and
- *      vertex triangle / neighbour-degree sums.
+ *      vertex triangle / neighbour-degree sums.  glo_count_range runs the same pass over a
+ *      block of edges, so that a long run can proceed (and be checked) block by block.
+ *
+ *  (3) glo_global_substructures -- global counts only, for graphs far too large for (2):
+ *      every unrestricted count of Section 4.5 follows from the triangles on each edge
+ *      (by definition, |N(u) & N(v)|), the number of 4-cliques and the number of 4-cycles,
+ *      each counted once at its lowest vertex in the order of P1; Section 4.6 then gives
+ *      X1..X17.  Pinned against (1) and (2) on every graph the tests draw.
  *
  * Edge numbering (shared convention of the C interface, re-implemented here): edge k is
  * the k-th CSR entry (i, col[j]) with i < col[j] in row-major order.
@@ -325,6 +332,91 @@ static int global_from_unrestricted(int64_t n, int64_t m, const i128 C[17], i128
 #undef EXACT
 }
 
+/* Edge order Pi (Section 4.3): heaviest edges first, by d_u + d_v, ties by id, over the
+ * caller's edges [k0, k1); workers take one edge at a time (chunk b = 1, the paper's CPU
+ * setting). */
+static int heaviest_first(const int32_t* eu, const int32_t* ev, const int64_t* deg,
+                          int64_t k0, int64_t k1, int64_t* order) {
+    int64_t maxkey = 0;
+    for (int64_t k = k0; k < k1; k++) {
+        int64_t key = deg[eu[k]] + deg[ev[k]];
+        if (key > maxkey) maxkey = key;
+    }
+    int64_t* bucket = (int64_t*)calloc((size_t)(maxkey + 2), sizeof(int64_t));
+    if (!bucket) return ORC_E_NOMEM;
+    for (int64_t k = k0; k < k1; k++) bucket[maxkey - (deg[eu[k]] + deg[ev[k]])]++;
+    int64_t acc = 0;
+    for (int64_t b = 0; b <= maxkey; b++) { int64_t c = bucket[b]; bucket[b] = acc; acc += c; }
+    for (int64_t k = k0; k < k1; k++) order[bucket[maxkey - (deg[eu[k]] + deg[ev[k]])]++] = k;
+    free(bucket);
+    return ORC_OK;
+}
+
+/* The edge-centric pass over the caller's edges [k0, k1) in the order Pi: per edge its
+ * neighbourhood (Alg. "3-Graphlets", "Clique", "Cycle"), its 13 local counts (written to
+ * per_edge[i * stride + k - k0] when per_edge is given) and its terms of the unrestricted
+ * counts C3..C16 (Section 4.5), summed into Csum. */
+static int edge_pass(int64_t n, int64_t m, const int64_t* rp, const int32_t* col, const int64_t* deg,
+                     const int32_t* eu, const int32_t* ev, const int64_t* tri, const int64_t* sdeg,
+                     int64_t k0, int64_t k1, int nthreads, i128 Csum[17], uint64_t* per_edge,
+                     int64_t stride) {
+    memset(Csum, 0, sizeof(i128) * 17);
+    if (k1 <= k0) return ORC_OK;
+    int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(k1 - k0));
+    if (!order) return ORC_E_NOMEM;
+    int rc = heaviest_first(eu, ev, deg, k0, k1, order);
+    if (rc) { free(order); return rc; }
+    int fail = 0;
+#pragma omp parallel num_threads(nthreads)
+    {
+        int64_t* psi = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+        int64_t* Tb = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+        int64_t* Sb = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+        i128 loc[17];
+        memset(loc, 0, sizeof(loc));
+        int64_t serial = 0;
+        int lfail = (!psi || !Tb || !Sb) ? ORC_E_NOMEM : 0;
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t q = 0; q < k1 - k0; q++) {
+            if (lfail) continue;
+            int64_t k = order[q];
+            int64_t a = eu[k], b = ev[k];
+            int64_t v = ranks_above(deg, a, b) ? a : b;
+            int64_t u = (v == a) ? b : a;
+            edge_terms e;
+            edge_neighbourhood(u, v, rp, col, deg, psi, Tb, Sb, serial++, &e);
+            int64_t x[13];
+            int r = local_counts(&e, n, m, deg[u], deg[v], tri[u], tri[v], sdeg[u], sdeg[v], x);
+            if (r) { lfail = r; continue; }
+            if (per_edge)
+                for (int i = 0; i < 13; i++) per_edge[(size_t)i * stride + (k - k0)] = (uint64_t)x[i];
+            /* unrestricted counts (Section 4.5) */
+            i128 t = e.t, s = e.su + e.sv, D = x[2];
+            loc[3] += t;
+            loc[4] += s;
+            loc[5] += D;
+            loc[7] += e.K;
+            loc[8] += choose2(t);
+            loc[9] += t * s;
+            loc[10] += e.Q;
+            loc[11] += choose2(e.su) + choose2(e.sv);
+            loc[12] += (i128)e.su * e.sv;
+            loc[13] += t * D;
+            loc[14] += (i128)(m - deg[u] - deg[v] + 1);
+            loc[15] += s * D;
+            loc[16] += choose2(D);
+        }
+#pragma omp critical
+        {
+            for (int i = 0; i < 17; i++) Csum[i] += loc[i];
+            if (lfail) fail = lfail;
+        }
+        free(psi); free(Tb); free(Sb);
+    }
+    free(order);
+    return fail;
+}
+
 /* Full count: global X1..X17 (as 17 x (lo,hi)), optional unrestricted sums C (index 3..16
  * meaningful, same layout), optional per-edge counts [13][m]. */
 int glo_count(int64_t n, const int64_t* rp, const int32_t* col, int nthreads,
@@ -336,80 +428,16 @@ int glo_count(int64_t n, const int64_t* rp, const int32_t* col, int nthreads,
     int64_t* deg = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
     int64_t* tri = (int64_t*)calloc((size_t)(n + 1), sizeof(int64_t));
     int64_t* sdeg = (int64_t*)calloc((size_t)(n + 1), sizeof(int64_t));
-    int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m + 1));
     int rc = ORC_OK;
-    if (!eu || !ev || !deg || !tri || !sdeg || !order) { rc = ORC_E_NOMEM; goto done; }
+    if (!eu || !ev || !deg || !tri || !sdeg) { rc = ORC_E_NOMEM; goto done; }
     build_edges(n, rp, col, eu, ev);
     for (int64_t x = 0; x < n; x++) deg[x] = rp[x + 1] - rp[x];
     rc = vertex_terms(n, rp, col, deg, NULL, tri, sdeg, nthreads);
     if (rc) goto done;
-    /* Edge order Pi (Section 4.3): heaviest edges first, by d_u + d_v, ties by id; workers
-     * take one edge at a time (chunk b = 1, the paper's CPU setting). */
-    {
-        int64_t maxkey = 0;
-        for (int64_t k = 0; k < m; k++) {
-            int64_t key = deg[eu[k]] + deg[ev[k]];
-            if (key > maxkey) maxkey = key;
-        }
-        int64_t* bucket = (int64_t*)calloc((size_t)(maxkey + 2), sizeof(int64_t));
-        if (!bucket) { rc = ORC_E_NOMEM; goto done; }
-        for (int64_t k = 0; k < m; k++) bucket[maxkey - (deg[eu[k]] + deg[ev[k]])]++;
-        int64_t acc = 0;
-        for (int64_t b = 0; b <= maxkey; b++) { int64_t c = bucket[b]; bucket[b] = acc; acc += c; }
-        for (int64_t k = 0; k < m; k++) order[bucket[maxkey - (deg[eu[k]] + deg[ev[k]])]++] = k;
-        free(bucket);
-    }
     {
         i128 Csum[17];
-        memset(Csum, 0, sizeof(Csum));
-        int fail = 0;
-#pragma omp parallel num_threads(nthreads)
-        {
-            int64_t* psi = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
-            int64_t* Tb = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
-            int64_t* Sb = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
-            i128 loc[17];
-            memset(loc, 0, sizeof(loc));
-            int64_t serial = 0;
-            int lfail = (!psi || !Tb || !Sb) ? ORC_E_NOMEM : 0;
-#pragma omp for schedule(dynamic, 1)
-            for (int64_t q = 0; q < m; q++) {
-                if (lfail) continue;
-                int64_t k = order[q];
-                int64_t a = eu[k], b = ev[k];
-                int64_t v = ranks_above(deg, a, b) ? a : b;
-                int64_t u = (v == a) ? b : a;
-                edge_terms e;
-                edge_neighbourhood(u, v, rp, col, deg, psi, Tb, Sb, serial++, &e);
-                int64_t x[13];
-                int r = local_counts(&e, n, m, deg[u], deg[v], tri[u], tri[v], sdeg[u], sdeg[v], x);
-                if (r) { lfail = r; continue; }
-                if (per_edge)
-                    for (int i = 0; i < 13; i++) per_edge[(size_t)i * m + k] = (uint64_t)x[i];
-                /* unrestricted counts (Section 4.5) */
-                i128 t = e.t, s = e.su + e.sv, D = x[2];
-                loc[3] += t;
-                loc[4] += s;
-                loc[5] += D;
-                loc[7] += e.K;
-                loc[8] += choose2(t);
-                loc[9] += t * s;
-                loc[10] += e.Q;
-                loc[11] += choose2(e.su) + choose2(e.sv);
-                loc[12] += (i128)e.su * e.sv;
-                loc[13] += t * D;
-                loc[14] += (i128)(m - deg[u] - deg[v] + 1);
-                loc[15] += s * D;
-                loc[16] += choose2(D);
-            }
-#pragma omp critical
-            {
-                for (int i = 0; i < 17; i++) Csum[i] += loc[i];
-                if (lfail) fail = lfail;
-            }
-            free(psi); free(Tb); free(Sb);
-        }
-        if (fail) { rc = fail; goto done; }
+        rc = edge_pass(n, m, rp, col, deg, eu, ev, tri, sdeg, 0, m, nthreads, Csum, per_edge, m);
+        if (rc) goto done;
         i128 X[18];
         rc = global_from_unrestricted(n, m, Csum, X);
         if (rc) goto done;
@@ -418,8 +446,53 @@ int glo_count(int64_t n, const int64_t* rp, const int32_t* col, int nthreads,
             for (int i = 0; i < 17; i++) put128(Cout, i, Csum[i]);
     }
 done:
-    free(eu); free(ev); free(deg); free(tri); free(sdeg); free(order);
+    free(eu); free(ev); free(deg); free(tri); free(sdeg);
     return rc;
+}
+
+/* The same pass restricted to the caller's edges [k0, k1): their terms of the unrestricted
+ * counts (C3..C16, as 17 x (lo,hi), index 3..16 meaningful; the sums over a partition of
+ * [0, m) add up to glo_count's) and, when per_edge is given, their 13 local counts
+ * ([13][k1 - k0], slot-major).  Lets a long run proceed block by block. */
+int glo_count_range(int64_t n, const int64_t* rp, const int32_t* col, int nthreads,
+                    int64_t k0, int64_t k1, uint64_t* Cout, uint64_t* per_edge) {
+    if (n < 0 || !rp || !Cout || nthreads < 1) return ORC_E_ARG;
+    int64_t m = build_edges(n, rp, col, NULL, NULL);
+    if (k0 < 0 || k1 < k0 || k1 > m) return ORC_E_ARG;
+    int32_t* eu = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
+    int32_t* ev = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
+    int64_t* deg = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t* tri = (int64_t*)calloc((size_t)(n + 1), sizeof(int64_t));
+    int64_t* sdeg = (int64_t*)calloc((size_t)(n + 1), sizeof(int64_t));
+    uint8_t* want = (uint8_t*)calloc((size_t)(n + 1), 1);
+    int rc = ORC_OK;
+    if (!eu || !ev || !deg || !tri || !sdeg || !want) { rc = ORC_E_NOMEM; goto done; }
+    build_edges(n, rp, col, eu, ev);
+    for (int64_t x = 0; x < n; x++) deg[x] = rp[x + 1] - rp[x];
+    for (int64_t k = k0; k < k1; k++) { want[eu[k]] = 1; want[ev[k]] = 1; }
+    rc = vertex_terms(n, rp, col, deg, want, tri, sdeg, nthreads);
+    if (rc) goto done;
+    {
+        i128 Csum[17];
+        rc = edge_pass(n, m, rp, col, deg, eu, ev, tri, sdeg, k0, k1, nthreads, Csum, per_edge, k1 - k0);
+        if (rc) goto done;
+        for (int i = 0; i < 17; i++) put128(Cout, i, Csum[i]);
+    }
+done:
+    free(eu); free(ev); free(deg); free(tri); free(sdeg); free(want);
+    return rc;
+}
+
+/* Global counts X1..X17 from unrestricted sums C (17 x (lo,hi) as glo_count_range returns
+ * them, summed over a partition of the edges), Section 4.6. */
+int glo_global_from_c(int64_t n, int64_t m, const uint64_t* Cin, uint64_t* Xout) {
+    if (n < 0 || m < 0 || !Cin || !Xout) return ORC_E_ARG;
+    i128 C[17], X[18];
+    for (int i = 0; i < 17; i++) C[i] = (i128)(((u128)Cin[2 * i + 1] << 64) | (u128)Cin[2 * i]);
+    int rc = global_from_unrestricted(n, m, C, X);
+    if (rc) return rc;
+    for (int i = 0; i < 17; i++) put128(Xout, i, X[i + 1]);
+    return ORC_OK;
 }
 
 /* Per-edge counts for selected edges only (no global sums).  Vertex terms are computed
@@ -473,5 +546,179 @@ int glo_count_edges(int64_t n, const int64_t* rp, const int32_t* col, int nthrea
     }
 done:
     free(eu); free(ev); free(deg); free(tri); free(sdeg); free(want);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* (3) global counts from three plainly defined sub-counts, for graphs too large for (2)  */
+/* ------------------------------------------------------------------------------------ */
+/*
+ * Every count of Sections 4.5-4.6 follows from the triangles on each edge, the number of
+ * 4-cliques and the number of (not necessarily induced) 4-cycles, besides n, m and the
+ * degrees:
+ *   - t_e = |N(u) & N(v)|, the triangles on edge e = (u, v), by definition;
+ *   - a 4-clique has one lowest vertex a in the order of P1 (degree, then id), and its other
+ *     three vertices form a triangle among the neighbours of a ranked above a;
+ *   - a 4-cycle has one lowest vertex y; its opposite vertex x and both middle vertices rank
+ *     above y, so with c(y, x) = the common neighbours of y and x ranked above y, the
+ *     4-cycles number the sum over pairs y < x (in rank) of C(c(y, x), 2).
+ * Per edge, s_u = d_u - 1 - t, s_v = d_v - 1 - t and D = n - 2 - t - s_u - s_v give every
+ * unrestricted count except C7 and C10; C7 = 6 #K4 (each 4-clique holds 6 edges, each with
+ * the other two vertices in T and adjacent), X8 = C8 - C7 (Section 4.6), and since an
+ * induced 4-cycle holds one 4-cycle, a chordal cycle one and a 4-clique three,
+ * X10 = #C4 - X8 - 3 X7 and C10 = 4 X10.  The rest is Section 4.6 as in (2).
+ * per_edge3, when given, receives the three per-edge counts of Section 4.5 that depend on
+ * t and the degrees alone: [0] triangles (H3) t, [1] 2-stars (H4) s_u + s_v, [2] H5 = D,
+ * slot-major [3][m] in the shared numbering.  work, when given, receives #K4 and #C4 as two
+ * (lo, hi) pairs.
+ */
+static int rank_less(const int64_t* deg, int64_t a, int64_t b) { return ranks_above(deg, b, a); }
+
+int glo_global_substructures(int64_t n, const int64_t* rp, const int32_t* col, int nthreads,
+                             uint64_t* Xout, uint64_t* per_edge3, uint64_t* work) {
+    if (n < 0 || !rp || !Xout || nthreads < 1) return ORC_E_ARG;
+    int64_t m = build_edges(n, rp, col, NULL, NULL);
+    int32_t* eu = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
+    int32_t* ev = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
+    int64_t* deg = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t* hstart = (int64_t*)calloc((size_t)(n + 2), sizeof(int64_t));   /* edges by higher end */
+    int64_t* hedge = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m + 1));
+    int64_t* ustart = (int64_t*)calloc((size_t)(n + 2), sizeof(int64_t));   /* upward neighbours */
+    int32_t* up = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
+    uint32_t* tcnt = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(m + 1));
+    int rc = ORC_OK;
+    if (!eu || !ev || !deg || !hstart || !hedge || !ustart || !up || !tcnt) { rc = ORC_E_NOMEM; goto done; }
+    build_edges(n, rp, col, eu, ev);
+    for (int64_t x = 0; x < n; x++) deg[x] = rp[x + 1] - rp[x];
+    /* each edge listed at its higher-ranked endpoint; N+(x) = neighbours ranked above x */
+    for (int64_t k = 0; k < m; k++) {
+        int64_t hi = ranks_above(deg, eu[k], ev[k]) ? eu[k] : ev[k];
+        int64_t lo = (hi == eu[k]) ? ev[k] : eu[k];
+        hstart[hi + 1]++;
+        ustart[lo + 1]++;
+    }
+    for (int64_t x = 0; x < n; x++) { hstart[x + 1] += hstart[x]; ustart[x + 1] += ustart[x]; }
+    {
+        int64_t* fh = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+        int64_t* fu = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+        if (!fh || !fu) { free(fh); free(fu); rc = ORC_E_NOMEM; goto done; }
+        memcpy(fh, hstart, sizeof(int64_t) * (size_t)n);
+        memcpy(fu, ustart, sizeof(int64_t) * (size_t)n);
+        for (int64_t k = 0; k < m; k++) {
+            int64_t hi = ranks_above(deg, eu[k], ev[k]) ? eu[k] : ev[k];
+            int64_t lo = (hi == eu[k]) ? ev[k] : eu[k];
+            hedge[fh[hi]++] = k;
+            up[fu[lo]++] = (int32_t)hi;
+        }
+        free(fh); free(fu);
+    }
+    i128 k4 = 0, c4 = 0;
+    int fail = 0;
+#pragma omp parallel num_threads(nthreads)
+    {
+        int64_t* mark = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+        int64_t* mark2 = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+        uint32_t* cnt = (uint32_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(uint32_t));
+        int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+        int32_t* L = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+        i128 lk4 = 0, lc4 = 0;
+        int lfail = (!mark || !mark2 || !cnt || !touched || !L) ? ORC_E_NOMEM : 0;
+        if (!lfail)
+            for (int64_t x = 0; x < n; x++) { mark[x] = -1; mark2[x] = -1; }
+        int64_t serial = 0;
+        /* triangles on every edge: N(v) marked once per higher endpoint v, N(u) probed */
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t v = 0; v < n; v++) {
+            if (lfail || hstart[v] == hstart[v + 1]) continue;
+            for (int64_t j = rp[v]; j < rp[v + 1]; j++) mark[col[j]] = v;
+            for (int64_t q = hstart[v]; q < hstart[v + 1]; q++) {
+                int64_t k = hedge[q];
+                int64_t u = (eu[k] == v) ? ev[k] : eu[k];
+                uint32_t c = 0;
+                for (int64_t j = rp[u]; j < rp[u + 1]; j++) c += (mark[col[j]] == v);
+                tcnt[k] = c;
+            }
+        }
+        /* 4-cliques at their lowest vertex a: triangles b < c < d inside N+(a) */
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t a = 0; a < n; a++) {
+            if (lfail) continue;
+            for (int64_t j = ustart[a]; j < ustart[a + 1]; j++) mark[up[j]] = n + a;
+            for (int64_t j = ustart[a]; j < ustart[a + 1]; j++) {
+                int64_t b = up[j];
+                int64_t nl = 0;
+                serial++;
+                for (int64_t q = ustart[b]; q < ustart[b + 1]; q++)
+                    if (mark[up[q]] == n + a) { L[nl++] = up[q]; mark2[up[q]] = serial; }
+                for (int64_t i = 0; i < nl; i++) {
+                    int64_t c = L[i];
+                    for (int64_t q = ustart[c]; q < ustart[c + 1]; q++) lk4 += (mark2[up[q]] == serial);
+                }
+            }
+        }
+        /* 4-cycles at their lowest vertex y: wedges y - w - x with w and x ranked above y */
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t y = 0; y < n; y++) {
+            if (lfail) continue;
+            int64_t nt = 0;
+            for (int64_t j = ustart[y]; j < ustart[y + 1]; j++) {
+                int64_t w = up[j];
+                for (int64_t q = rp[w]; q < rp[w + 1]; q++) {
+                    int64_t x = col[q];
+                    if (x == y || !rank_less(deg, y, x)) continue;
+                    if (cnt[x]++ == 0) touched[nt++] = (int32_t)x;
+                }
+            }
+            for (int64_t i = 0; i < nt; i++) { lc4 += choose2(cnt[touched[i]]); cnt[touched[i]] = 0; }
+        }
+#pragma omp critical
+        {
+            k4 += lk4;
+            c4 += lc4;
+            if (lfail) fail = lfail;
+        }
+        free(mark); free(mark2); free(cnt); free(touched); free(L);
+    }
+    if (fail) { rc = fail; goto done; }
+    {
+        i128 C[17], X[18];
+        memset(C, 0, sizeof(C));
+        for (int64_t k = 0; k < m; k++) {
+            const int64_t du = deg[eu[k]], dv = deg[ev[k]];
+            const i128 t = tcnt[k], su = du - 1 - (int64_t)tcnt[k], sv = dv - 1 - (int64_t)tcnt[k];
+            const i128 D = (i128)n - 2 - t - su - sv;
+            if (su < 0 || sv < 0 || D < 0) { rc = ORC_E_NEGATIVE; goto done; }
+            C[3] += t;
+            C[4] += su + sv;
+            C[5] += D;
+            C[8] += choose2(t);
+            C[9] += t * (su + sv);
+            C[11] += choose2(su) + choose2(sv);
+            C[12] += su * sv;
+            C[13] += t * D;
+            C[14] += (i128)(m - du - dv + 1);
+            C[15] += (su + sv) * D;
+            C[16] += choose2(D);
+            if (per_edge3) {
+                per_edge3[k] = (uint64_t)t;
+                per_edge3[(size_t)m + k] = (uint64_t)(su + sv);
+                per_edge3[2 * (size_t)m + k] = (uint64_t)D;
+            }
+        }
+        C[7] = 6 * k4;
+        const i128 x8 = C[8] - C[7];
+        const i128 x10 = c4 - x8 - 3 * k4;
+        if (x8 < 0 || x10 < 0) { rc = ORC_E_NEGATIVE; goto done; }
+        C[10] = 4 * x10;
+        rc = global_from_unrestricted(n, m, C, X);
+        if (rc) goto done;
+        for (int i = 0; i < 17; i++) put128(Xout, i, X[i + 1]);
+        if (work) {
+            put128(work, 0, k4);
+            put128(work, 1, c4);
+        }
+    }
+done:
+    free(eu); free(ev); free(deg); free(hstart); free(hedge); free(ustart); free(up); free(tcnt);
     return rc;
 }

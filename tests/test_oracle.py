@@ -374,3 +374,98 @@ def test_stored_chung_lu_1m_counts_consistent():
     n2, (rp, col) = gg.config_chung_lu_1m()
     assert n2 == n and col.size == 2 * m
     assert hashlib.sha256(np.ascontiguousarray(col).tobytes()).hexdigest()[:16] == g["col_sha256_prefix"]
+
+
+# --------------------------------------------------------------------------------------
+# block-wise runs and the sub-structure method for large graphs
+# --------------------------------------------------------------------------------------
+
+def test_range_blocks_add_up_to_full_count():
+    """The edge-centric pass over a partition of the edges into blocks gives, summed, the
+    unrestricted counts of the full run, the same per-edge counts block by block and, through
+    Section 4.6, the same global counts."""
+    for n, m, seed, cuts in ((300, 2500, 5, (0, 1, 700, 1300, 2500)), (1000, 10000, 6, (0, 5000, 10000)),
+                             (60, 400, 7, (0, 400))):
+        rp, col = gg.chung_lu(n, m, 2.2, float(n - 1), seed)
+        full = oracle.count(n, rp, col, per_edge=True)
+        mm = col.size // 2
+        cuts = [min(c, mm) for c in cuts]
+        parts = [oracle.count_range(n, rp, col, a, b, per_edge=True, nthreads=3) for a, b in zip(cuts, cuts[1:])]
+        C = [sum(p["C"][i] for p in parts) for i in range(17)]
+        assert C == full["C"]
+        np.testing.assert_array_equal(np.concatenate([p["per_edge"] for p in parts], axis=1), full["per_edge"])
+        assert oracle.global_from_c(n, mm, C) == full["X"]
+    # an empty block contributes nothing; a block outside [0, m) is refused
+    rp, col = gg.er(50, 200, 1)
+    assert oracle.count_range(50, rp, col, 100, 100)["C"] == [0] * 17
+    with pytest.raises(RuntimeError):
+        oracle.count_range(50, rp, col, 150, 201)
+
+
+def test_substructures_match_brute_random():
+    """Global counts and the per-edge triangle, 2-star and H5 counts of the sub-structure
+    method equal the brute-force definition on random graphs of every density, including
+    equal-degree ties and isolated vertices."""
+    rng = np.random.default_rng(31)
+    for trial in range(120):
+        n = int(rng.integers(1, 36))
+        pairs = _random_pairs(n, float(rng.choice([0.05, 0.2, 0.4, 0.6, 0.8, 0.97])), rng)
+        rp, col = _csr(n, pairs)
+        col = gg.shuffle_rows(rp, col, trial)
+        b = oracle.brute(n, rp, col, per_edge=True)
+        s = oracle.global_substructures(n, rp, col, per_edge3=True, nthreads=1 + trial % 3)
+        assert s["X"] == b["X"], trial
+        np.testing.assert_array_equal(s["per_edge3"], b["per_edge"][:3])
+
+
+def test_substructures_match_method_powerlaw():
+    """Against the edge-centric method on power-law and ER graphs large enough for hubs,
+    4-cliques and many 4-cycles; the 4-clique and 4-cycle totals also equal the ones implied
+    by that method's per-edge counts (sum of K_e / 6; X10 + X8 + 3 X7)."""
+    for n, m, gamma, seed in ((2000, 30000, 2.1, 41), (5000, 60000, 2.5, 42), (800, 40000, 2.1, 43)):
+        rp, col = gg.chung_lu(n, m, gamma, float(n - 1), seed)
+        r = oracle.count(n, rp, col, per_edge=True)
+        s = oracle.global_substructures(n, rp, col, per_edge3=True)
+        assert s["X"] == r["X"]
+        np.testing.assert_array_equal(s["per_edge3"], r["per_edge"][:3])
+        assert 6 * s["k4"] == int(r["per_edge"][3].sum())
+        X = r["X"]
+        assert s["c4"] == X[9] + X[7] + 3 * X[6]
+    n, (rp, col) = gg.config_er_1k()
+    assert oracle.global_substructures(n, rp, col)["X"] == oracle.count(n, rp, col)["X"]
+
+
+def test_substructures_closed_forms():
+    """4-clique and 4-cycle totals of complete, cycle and complete bipartite graphs, and the
+    full closed forms, including sizes where X17 exceeds 64 bits."""
+    for n in (4, 5, 9, 40):
+        N, (rp, col) = gg.complete(n)
+        s = oracle.global_substructures(N, rp, col)
+        assert s["k4"] == comb(n, 4) and s["c4"] == 3 * comb(n, 4)
+        assert s["X"] == closed_complete(n)
+    for a, b in ((2, 2), (3, 5), (7, 9)):
+        N, (rp, col) = gg.complete_bipartite(a, b)
+        s = oracle.global_substructures(N, rp, col)
+        assert s["k4"] == 0 and s["c4"] == comb(a, 2) * comb(b, 2)
+        assert s["X"] == closed_bipartite(a, b)
+    N, (rp, col) = gg.cycle(4)
+    assert oracle.global_substructures(N, rp, col)["c4"] == 1
+    N, (rp, col) = gg.cycle(3_000_000)
+    assert oracle.global_substructures(N, rp, col)["X"] == closed_cycle(3_000_000)
+    N, (rp, col) = gg.star(5000)
+    assert oracle.global_substructures(N, rp, col)["X"] == closed_star(5000)
+    N, (rp, col) = gg.path(200_000)
+    assert oracle.global_substructures(N, rp, col)["X"] == closed_path(200_000)
+
+
+def test_substructures_complement_identity():
+    rng = np.random.default_rng(8)
+    for trial in range(15):
+        n = int(rng.integers(6, 50))
+        rp, col = _csr(n, _random_pairs(n, float(rng.uniform(0.1, 0.9)), rng))
+        X = oracle.global_substructures(n, rp, col)["X"]
+        cn, (crp, ccol) = gg.complement(n, rp, col)
+        Xc = oracle.global_substructures(cn, crp, ccol)["X"]
+        for i in range(1, 18):
+            assert X[i - 1] == Xc[COMPLEMENT[i] - 1], (trial, i)
+        assert sum(X[6:16]) + Xc[6] == comb(n, 4)
