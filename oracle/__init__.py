@@ -14,6 +14,9 @@ Contents
 * ``global_substructures``: global counts of graphs far too large for the edge-centric method,
   from the triangles on every edge (by definition), the 4-cliques and the 4-cycles, each
   counted once at its lowest vertex, through Sections 4.5-4.6.
+* ``per_edge_substructures``: per-edge and global counts of such graphs from per-edge
+  triangles, 4-cliques, 4-cycles and triangle-weighted sums, each sub-structure enumerated
+  once, through the same class-pair formulas as the edge-centric method.
 * ``brute_py``: a pure-Python enumeration for tiny graphs that pins the C brute force.
 
 Global counts are returned as Python ints (exact, they exceed 64 bits for large n).
@@ -66,8 +69,10 @@ def _load():
         lib.glo_count_range.argtypes = [ctypes.c_int64, P, P, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, P, P]
         lib.glo_global_from_c.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P]
         lib.glo_global_substructures.argtypes = [ctypes.c_int64, P, P, ctypes.c_int, P, P, P]
+        lib.glo_per_edge_substructures.argtypes = [ctypes.c_int64, P, P, ctypes.c_int, P, P, P]
         for f in (lib.brute_count, lib.glo_count, lib.glo_count_edges, lib.glo_count_range,
-                  lib.glo_global_from_c, lib.glo_global_substructures):
+                  lib.glo_global_from_c, lib.glo_global_substructures,
+                  lib.glo_per_edge_substructures):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -173,6 +178,24 @@ def global_substructures(n, row_ptr, col, per_edge3: bool = False, nthreads: int
         raise RuntimeError(f"oracle glo_global_substructures failed: {rc}")
     return {"X": _u128(X), "k4": int(W[0]) | (int(W[1]) << 64), "c4": int(W[2]) | (int(W[3]) << 64),
             "per_edge3": pe}
+
+
+def per_edge_substructures(n, row_ptr, col, per_edge: bool = True, nthreads: int | None = None):
+    """Per-edge and global counts from per-edge triangles, 4-cliques, 4-cycles and
+    triangle-weighted sums (each sub-structure enumerated once).  Returns dict(X=[17 ints],
+    k4, c4, per_edge=[13, m] or None)."""
+    lib = _load()
+    rp, c = _prep(n, row_ptr, col)
+    m = num_edges(n, rp, c)
+    X = np.zeros(34, dtype=np.uint64)
+    W = np.zeros(4, dtype=np.uint64)
+    pe = np.zeros((13, m), dtype=np.uint64) if per_edge else None
+    rc = lib.glo_per_edge_substructures(n, _ptr(rp), _ptr(c), nthreads or default_threads(),
+                                        _ptr(X), _ptr(pe) if pe is not None else None, _ptr(W))
+    if rc != 0:
+        raise RuntimeError(f"oracle glo_per_edge_substructures failed: {rc}")
+    return {"X": _u128(X), "k4": int(W[0]) | (int(W[1]) << 64), "c4": int(W[2]) | (int(W[3]) << 64),
+            "per_edge": pe}
 
 
 def brute(n, row_ptr, col, per_edge: bool = False):

@@ -5,7 +5,7 @@
  * baseline may load this code.  It shares nothing with the GPU library: no headers, no
  * helpers, no tables.  It is deliberately plain and slow.
  *
- * Three methods live here:
+ * Four methods live here:
  *
  *  (1) brute_*  -- the definition (Section 3, Definitions 1-3 and Problem 1): every 3- and
  *      4-vertex subset is classified by the induced subgraph it spans.  Per-edge counts
@@ -37,6 +37,13 @@
  *      each counted once at its lowest vertex in the order of P1; Section 4.6 then gives
  *      X1..X17.  Pinned against (1) and (2) on every graph the tests draw.
  *
+ *  (4) glo_per_edge_substructures -- per-edge and global counts for graphs too large for
+ *      (2): the per-edge terms that (2) gets from tag scans (4-cliques, T-S_u and T-S_v
+ *      edges, S_u-S_v edges, degree sum over T) are recovered from per-edge counts of
+ *      triangles, 4-cliques, 4-cycles and triangle-weighted sums, each sub-structure
+ *      enumerated once; the class-pair formulas of (2) then give the 13 local counts.
+ *      Pinned against (1) and (2) on every graph the tests draw.
+ *
  * Edge numbering (shared convention of the C interface, re-implemented here): edge k is
  * the k-th CSR entry (i, col[j]) with i < col[j] in row-major order.
  *
@@ -46,6 +53,7 @@
  *   10:H14 4-node-2-edge 11:H15 4-node-2-star 12:H16 4-node-1-edge
  * Global output is 17 graphlets x (lo, hi) 64-bit words of an unsigned 128-bit count.
  */
+#define _GNU_SOURCE   /* qsort_r */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -722,3 +730,312 @@ done:
     free(eu); free(ev); free(deg); free(hstart); free(hedge); free(ustart); free(up); free(tcnt);
     return rc;
 }
+
+/* ------------------------------------------------------------------------------------ */
+/* (4) per-edge counts from plainly defined per-edge sub-counts, for graphs too large     */
+/*     for (2)                                                                            */
+/* ------------------------------------------------------------------------------------ */
+/*
+ * The terms that (2) obtains per edge e = (u, v) by tag scans (Section 4.5) are counts with
+ * plain definitions, and each can be gathered from sub-structures enumerated once each:
+ *   t      = |N(u) & N(v)|, by definition (marks of N(v), probes of N(u));
+ *   K      = the 4-cliques that contain e: every 4-clique is enumerated once at its lowest
+ *            vertex in the order of P1 and credited to its six edges;
+ *   P      = the 4-cycles (not necessarily induced) that contain e: every 4-cycle is
+ *            enumerated once at its lowest vertex y, as two middles w, w' that are both
+ *            adjacent to y and to the opposite vertex x, and credited to its four edges;
+ *   gu, gv = sums over w in T of t(w, u) and of t(w, v): every triangle is enumerated once
+ *            and credits each of its edges with the triangle counts of its other two edges;
+ *   sigT   = the sum of d_w over w in T: every triangle credits each of its edges with the
+ *            degree of its third vertex.
+ * The tag counts of (2) follow from these: for w in T, N(w) & N(u) holds v, the neighbours
+ * of w inside T and those inside S_u, so gu = t + 2K + a_u (likewise gv with S_v); a 4-cycle
+ * through e is a path u - r - w - v whose middle pair (r, w) is an ordered adjacent pair of
+ * T (2K of them), a T-S_v or S_u-T pair (a_v + a_u), or an S_u-S_v pair (Q), so
+ * P = 2K + a_u + a_v + Q.  The 13 local counts, the unrestricted sums and X1..X17 then
+ * come from the same class-pair formulas as (2) (local_counts, Sections 4.5-4.6).
+ * Pinned against (1) and (2) on every graph the tests draw.
+ *
+ * Neighbour lists are copied in descending P1 rank (Section 4.2, P2) so that the wedge
+ * scans stop at the first vertex not ranked above y.  per_edge receives [13][m] (slot-
+ * major, shared numbering), Xout 17 x (lo, hi), work #K4 and #C4 as two (lo, hi) pairs.
+ */
+typedef struct { int32_t v; int64_t e; } nbr_entry;
+
+/* qsort_r comparator: neighbours in descending P1 rank */
+static int by_rank_desc(const void* pa, const void* pb, void* ctx) {
+    const int64_t* deg = (const int64_t*)ctx;
+    const int64_t a = ((const nbr_entry*)pa)->v, b = ((const nbr_entry*)pb)->v;
+    if (a == b) return 0;
+    return ranks_above(deg, a, b) ? -1 : 1;
+}
+
+#define ADD(arr, k, val) __atomic_fetch_add(&(arr)[k], (val), __ATOMIC_RELAXED)
+
+int glo_per_edge_substructures(int64_t n, const int64_t* rp, const int32_t* col, int nthreads,
+                               uint64_t* Xout, uint64_t* per_edge, uint64_t* work) {
+    if (n < 0 || !rp || !Xout || nthreads < 1) return ORC_E_ARG;
+    const int64_t m = build_edges(n, rp, col, NULL, NULL);
+    const int64_t nn = n > 0 ? n : 1, mm = m > 0 ? m : 1;
+    int32_t* eu = (int32_t*)malloc(sizeof(int32_t) * (size_t)mm);
+    int32_t* ev = (int32_t*)malloc(sizeof(int32_t) * (size_t)mm);
+    int64_t* deg = (int64_t*)malloc(sizeof(int64_t) * (size_t)nn);
+    int64_t* seid = (int64_t*)malloc(sizeof(int64_t) * (size_t)(2 * mm));   /* CSR slot -> edge */
+    int32_t* rcol = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * mm));   /* rows, rank-descending */
+    int64_t* reid = (int64_t*)malloc(sizeof(int64_t) * (size_t)(2 * mm));
+    int64_t* nup = (int64_t*)calloc((size_t)nn, sizeof(int64_t));           /* |N+(x)| */
+    int64_t* tE = (int64_t*)calloc((size_t)mm, sizeof(int64_t));
+    int64_t* KE = (int64_t*)calloc((size_t)mm, sizeof(int64_t));
+    int64_t* PE = (int64_t*)calloc((size_t)mm, sizeof(int64_t));
+    int64_t* guE = (int64_t*)calloc((size_t)mm, sizeof(int64_t));
+    int64_t* gvE = (int64_t*)calloc((size_t)mm, sizeof(int64_t));
+    int64_t* sgE = (int64_t*)calloc((size_t)mm, sizeof(int64_t));
+    int64_t* tri = (int64_t*)calloc((size_t)nn, sizeof(int64_t));
+    int64_t* sdeg = (int64_t*)calloc((size_t)nn, sizeof(int64_t));
+    int rc = ORC_OK;
+    i128 k4 = 0, c4 = 0;
+    if (!eu || !ev || !deg || !seid || !rcol || !reid || !nup || !tE || !KE || !PE || !guE ||
+        !gvE || !sgE || !tri || !sdeg) { rc = ORC_E_NOMEM; goto done; }
+    build_edges(n, rp, col, eu, ev);
+    for (int64_t x = 0; x < n; x++) deg[x] = rp[x + 1] - rp[x];
+    /* slot -> edge id: the edge (i, j), i < j, is numbered in row i; row j finds it there */
+    {
+        int64_t k = 0;
+        for (int64_t i = 0; i < n; i++)
+            for (int64_t j = rp[i]; j < rp[i + 1]; j++)
+                if ((int64_t)col[j] > i) seid[j] = k++;
+        int fail = 0;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; i++)
+            for (int64_t j = rp[i]; j < rp[i + 1]; j++) {
+                int64_t o = col[j];
+                if (o > i) continue;
+                int64_t f = -1;
+                for (int64_t q = rp[o]; q < rp[o + 1]; q++)   /* row o holds i once */
+                    if (col[q] == i) { f = seid[q]; break; }
+                if (f < 0) {
+#pragma omp atomic write
+                    fail = 1;
+                }
+                seid[j] = f;
+            }
+        if (fail) { rc = ORC_E_ARG; goto done; }   /* not symmetric */
+    }
+    /* rank-descending copy of every row; N+(x) is its prefix of vertices ranked above x */
+    {
+        int64_t dmax = 0;
+        for (int64_t x = 0; x < n; x++) dmax = deg[x] > dmax ? deg[x] : dmax;
+        int fail = 0;
+#pragma omp parallel num_threads(nthreads)
+        {
+            nbr_entry* tmp = (nbr_entry*)malloc(sizeof(nbr_entry) * (size_t)(dmax + 1));
+            if (!tmp) {
+#pragma omp atomic write
+                fail = 1;
+            }
+#pragma omp for schedule(dynamic, 256)
+            for (int64_t x = 0; x < n; x++) {
+                if (!tmp) continue;
+                const int64_t b = rp[x], len = rp[x + 1] - rp[x];
+                for (int64_t j = 0; j < len; j++) { tmp[j].v = col[b + j]; tmp[j].e = seid[b + j]; }
+                qsort_r(tmp, (size_t)len, sizeof(nbr_entry), by_rank_desc, (void*)deg);
+                int64_t c = 0;
+                for (int64_t j = 0; j < len; j++) { rcol[b + j] = tmp[j].v; reid[b + j] = tmp[j].e; }
+                while (c < len && ranks_above(deg, rcol[b + c], x)) c++;
+                nup[x] = c;
+            }
+            free(tmp);
+        }
+        if (fail) { rc = ORC_E_NOMEM; goto done; }
+    }
+    int fail = 0;
+#pragma omp parallel num_threads(nthreads)
+    {
+        int64_t* mark = (int64_t*)malloc(sizeof(int64_t) * (size_t)nn);
+        int64_t* markE = (int64_t*)malloc(sizeof(int64_t) * (size_t)nn);
+        int64_t* mark2 = (int64_t*)malloc(sizeof(int64_t) * (size_t)nn);
+        int64_t* mark2E = (int64_t*)malloc(sizeof(int64_t) * (size_t)nn);
+        int64_t* cnt = (int64_t*)calloc((size_t)nn, sizeof(int64_t));
+        int64_t* accA = (int64_t*)calloc((size_t)nn, sizeof(int64_t));
+        int64_t* accB = (int64_t*)calloc((size_t)nn, sizeof(int64_t));
+        int32_t* L = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+        int64_t* LE = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+        i128 lk4 = 0, lc4 = 0;
+        int lfail = (!mark || !markE || !mark2 || !mark2E || !cnt || !accA || !accB || !L || !LE)
+                        ? ORC_E_NOMEM : 0;
+        if (!lfail)
+            for (int64_t x = 0; x < n; x++) { mark[x] = -1; mark2[x] = -1; }
+        /* triangles on every edge, t = |N(u) & N(v)|: N(x) marked once, every edge (x, y)
+         * with y ranked below x probed through N(y) */
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t x = 0; x < n; x++) {
+            if (lfail) continue;
+            for (int64_t j = rp[x]; j < rp[x + 1]; j++) mark[col[j]] = x;
+            for (int64_t j = rp[x]; j < rp[x + 1]; j++) {
+                int64_t y = col[j];
+                if (!ranks_above(deg, x, y)) continue;
+                int64_t c = 0;
+                for (int64_t q = rp[y]; q < rp[y + 1]; q++) c += (mark[col[q]] == x);
+                tE[seid[j]] = c;
+            }
+        }
+        /* per vertex: triangles at x (= half the sum of t over its edges) and the sum of its
+         * neighbours' degrees */
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t x = 0; x < n; x++) {
+            int64_t s = 0, c = 0;
+            for (int64_t j = rp[x]; j < rp[x + 1]; j++) { s += deg[col[j]]; c += tE[seid[j]]; }
+            sdeg[x] = s;
+            tri[x] = c / 2;
+        }
+        /* triangles {a, b, c} and 4-cliques {a, b, c, d}, a < b < c < d in rank, at their lowest
+         * vertex a */
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t a = 0; a < n; a++) {
+            if (lfail) continue;
+            const int64_t ba = rp[a];
+            for (int64_t j = 0; j < nup[a]; j++) { mark[rcol[ba + j]] = n + a; markE[rcol[ba + j]] = reid[ba + j]; }
+            for (int64_t j = 0; j < nup[a]; j++) {
+                const int64_t b = rcol[ba + j], eab = reid[ba + j], bb = rp[b];
+                int64_t nl = 0;
+                for (int64_t q = 0; q < nup[b]; q++) {
+                    const int64_t c = rcol[bb + q];
+                    if (mark[c] != n + a) continue;
+                    L[nl] = (int32_t)c;
+                    LE[nl++] = reid[bb + q];
+                    mark2[c] = n + b;   /* c is above b and in N+(a) */
+                    mark2E[c] = reid[bb + q];
+                }
+                int64_t kab = 0;
+                for (int64_t i = 0; i < nl; i++) {
+                    const int64_t c = L[i], ebc = LE[i], eac = markE[c], bc0 = rp[c];
+                    /* triangle {a, b, c}: gather credits (edge ab's u-side endpoint is a) */
+                    const int64_t tab = tE[eab], tac = tE[eac], tbc = tE[ebc];
+                    ADD(guE, eab, tac); ADD(gvE, eab, tbc); ADD(sgE, eab, deg[c]);
+                    ADD(guE, eac, tab); ADD(gvE, eac, tbc); ADD(sgE, eac, deg[b]);
+                    ADD(guE, ebc, tab); ADD(gvE, ebc, tac); ADD(sgE, ebc, deg[a]);
+                    /* 4-cliques {a, b, c, d}, d above c, adjacent to a and b; each credits
+                     * its six edges: ab, ac, ad summed per vertex over a's iteration (accA),
+                     * bc, bd over b's (accB), cd directly */
+                    int64_t kc = 0;
+                    for (int64_t q = 0; q < nup[c]; q++) {
+                        const int64_t d = rcol[bc0 + q];
+                        if (mark2[d] != n + b) continue;
+                        kc++;
+                        accA[d]++;
+                        accB[d]++;
+                        ADD(KE, reid[bc0 + q], 1);
+                    }
+                    kab += kc;
+                    accA[c] += kc;
+                    accB[c] += kc;
+                }
+                lk4 += kab;
+                if (kab) ADD(KE, eab, kab);
+                for (int64_t i = 0; i < nl; i++) {
+                    const int64_t c = L[i];
+                    if (accB[c]) ADD(KE, mark2E[c], accB[c]);
+                    accB[c] = 0;
+                    mark2[c] = -1;
+                }
+            }
+            for (int64_t j = 0; j < nup[a]; j++) {
+                const int64_t x = rcol[ba + j];
+                if (accA[x]) ADD(KE, markE[x], accA[x]);
+                accA[x] = 0;
+            }
+        }
+        /* 4-cycles at their lowest vertex y: middles w (above y, adjacent to y), opposite
+         * x (above y, adjacent to w); c(y, x) middles give C(c, 2) cycles, and each of the
+         * edges (y, w), (w, x) lies on c - 1 of them */
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t y = 0; y < n; y++) {
+            if (lfail) continue;
+            const int64_t by = rp[y];
+            for (int pass = 0; pass < 3; pass++)
+                for (int64_t j = 0; j < nup[y]; j++) {
+                    const int64_t w = rcol[by + j], eyw = reid[by + j], bw = rp[w];
+                    int64_t credit = 0;
+                    for (int64_t q = 0; q < deg[w] && ranks_above(deg, rcol[bw + q], y); q++) {
+                        const int64_t x = rcol[bw + q];
+                        if (pass == 0) cnt[x]++;
+                        else if (pass == 1) {
+                            ADD(PE, reid[bw + q], cnt[x] - 1);
+                            credit += cnt[x] - 1;
+                        } else if (cnt[x] > 0) {
+                            lc4 += choose2(cnt[x]);
+                            cnt[x] = 0;
+                        }
+                    }
+                    if (pass == 1) ADD(PE, eyw, credit);
+                }
+        }
+#pragma omp critical
+        {
+            k4 += lk4;
+            c4 += lc4;
+            if (lfail) fail = lfail;
+        }
+        free(mark); free(markE); free(mark2); free(mark2E); free(cnt); free(accA); free(accB);
+        free(L); free(LE);
+    }
+    if (fail) { rc = fail; goto done; }
+    {
+        i128 C[17];
+        memset(C, 0, sizeof(C));
+        for (int64_t k = 0; k < m; k++) {
+            const int64_t a = eu[k], b = ev[k];
+            const int64_t v = ranks_above(deg, a, b) ? a : b, u = (v == a) ? b : a;
+            /* the enumeration credited g to each edge's lower endpoint as gu */
+            edge_terms e;
+            e.t = tE[k];
+            e.su = deg[u] - 1 - e.t;
+            e.sv = deg[v] - 1 - e.t;
+            e.K = KE[k];
+            e.au = guE[k] - e.t - 2 * e.K;
+            e.av = gvE[k] - e.t - 2 * e.K;
+            e.Q = PE[k] - 2 * e.K - e.au - e.av;
+            e.sigT = sgE[k];
+            if (e.su < 0 || e.sv < 0 || e.au < 0 || e.av < 0 || e.Q < 0) { rc = ORC_E_NEGATIVE; goto done; }
+            int64_t x[13];
+            rc = local_counts(&e, n, m, deg[u], deg[v], tri[u], tri[v], sdeg[u], sdeg[v], x);
+            if (rc) goto done;
+            if (per_edge)
+                for (int i = 0; i < 13; i++) per_edge[(size_t)i * m + k] = (uint64_t)x[i];
+            i128 t = e.t, s = e.su + e.sv, D = x[2];
+            C[3] += t;
+            C[4] += s;
+            C[5] += D;
+            C[7] += e.K;
+            C[8] += choose2(t);
+            C[9] += t * s;
+            C[10] += e.Q;
+            C[11] += choose2(e.su) + choose2(e.sv);
+            C[12] += (i128)e.su * e.sv;
+            C[13] += t * D;
+            C[14] += (i128)(m - deg[u] - deg[v] + 1);
+            C[15] += s * D;
+            C[16] += choose2(D);
+        }
+        /* each 4-clique has six edges, each 4-cycle four */
+        if (C[7] != 6 * k4) { rc = ORC_E_INEXACT; goto done; }
+        {
+            i128 sp = 0;
+            for (int64_t k = 0; k < m; k++) sp += PE[k];
+            if (sp != 4 * c4) { rc = ORC_E_INEXACT; goto done; }
+        }
+        i128 X[18];
+        rc = global_from_unrestricted(n, m, C, X);
+        if (rc) goto done;
+        for (int i = 0; i < 17; i++) put128(Xout, i, X[i + 1]);
+        if (work) {
+            put128(work, 0, k4);
+            put128(work, 1, c4);
+        }
+    }
+done:
+    free(eu); free(ev); free(deg); free(seid); free(rcol); free(reid); free(nup); free(tE); free(KE);
+    free(PE); free(guE); free(gvE); free(sgE); free(tri); free(sdeg);
+    return rc;
+}
+#undef ADD

@@ -7,18 +7,18 @@ Targets (every value below comes from ``oracle/``; nothing is read back from the
 chung_lu_1m          global counts X1..X17 of the Chung-Lu graph n=1e6, m=1e7, exponent 2.1,
                      weight cap 50,000 (graphgen.config_chung_lu_1m), by the paper's
                      edge-centric method -> chung_lu_1m_global.json
-chung_lu_1m_per_edge the 13 per-edge counts of every edge of the same graph by the same method,
-                     run block by block (glo_count_range; blocks checkpointed under
-                     _work/golden_ckpt so an interrupted run resumes): SHA-256 of each slot's
-                     little-endian uint64 array in the caller's edge order, the global counts
-                     recombined from the blocks' unrestricted sums, and the counts of a seeded
-                     edge sample -> chung_lu_1m_per_edge.json
-rmat_s22             R-MAT scale 22, edge factor 16 (graphgen.config_rmat_s22): global counts
-                     by the sub-structure method (per-edge triangles, 4-cliques, 4-cycles;
-                     the edge-centric method would take hundreds of core-hours here), SHA-256 of
-                     the per-edge triangle, 2-star and H5 arrays, and the 13 per-edge counts of
-                     a seeded edge sample (uniform edges plus edges at the highest-degree
-                     vertices) by the edge-centric method -> rmat_s22.json
+chung_lu_1m_per_edge the 13 per-edge counts of every edge of the same graph by the per-edge
+                     sub-structure method, then by the paper's edge-centric method run block by
+                     block (glo_count_range; blocks checkpointed under _work/golden_ckpt so an
+                     interrupted run resumes), which must agree on every count: SHA-256 of each
+                     slot's little-endian uint64 array in the caller's edge order, the global
+                     counts and the counts of a seeded edge sample -> chung_lu_1m_per_edge.json
+rmat_s22             R-MAT scale 22, edge factor 16 (graphgen.config_rmat_s22): per-edge and
+                     global counts by the per-edge sub-structure method (the edge-centric method
+                     would take hundreds of core-hours here), SHA-256 of each of the 13 per-edge
+                     slot arrays, and the 13 counts of a seeded edge sample (uniform edges plus
+                     edges at the highest-degree vertices) by the edge-centric method, which
+                     must agree -> rmat_s22.json
 batch_10k            global counts of each of the 10,000 graphs of the batch mix
                      (graphgen.batch_spec / batch_graph), edge-centric method: a 16-hex digest
                      per graph and the full counts of every 100th graph -> batch_10k.json
@@ -100,14 +100,28 @@ def target_chung_lu_1m(threads):
     })
 
 
+def edge_sums_check(pe, X):
+    """Sum over edges of each per-edge count = (edges of the graphlet) x (its global count)."""
+    for s_, gid in enumerate(oracle.EDGE_SLOTS):
+        if int(pe[s_].sum(dtype=np.uint64)) % (1 << 64) != (oracle.GRAPHLET_EDGES[gid - 1] * X[gid - 1]) % (1 << 64):
+            raise SystemExit(f"edge sum of slot {s_} does not match the global count")
+
+
 def target_chung_lu_1m_per_edge(threads, blocks=8):
+    """Per-edge counts by the per-edge sub-structure method, then by the paper's
+    edge-centric method block by block; the two must agree on every count."""
     n, (rp, col) = gg.config_chung_lu_1m()
     m = col.size // 2
     os.makedirs(CKPT, exist_ok=True)
+    t0 = time.time()
+    sub = oracle.per_edge_substructures(n, rp, col, nthreads=threads)
+    t_sub = time.time() - t0
+    log(f"per-edge sub-structure method {t_sub:.0f} s")
+    pe = sub["per_edge"]
+    edge_sums_check(pe, sub["X"])
     cuts = [m * b // blocks for b in range(blocks + 1)]
     t0 = time.time()
     C = [0] * 17
-    pe = np.zeros((13, m), dtype=np.uint64)
     for b in range(blocks):
         k0, k1 = cuts[b], cuts[b + 1]
         path = os.path.join(CKPT, f"chung_lu_1m_block{b}_of{blocks}.npz")
@@ -122,50 +136,56 @@ def target_chung_lu_1m_per_edge(threads, blocks=8):
             np.savez(path + ".tmp.npz", pe=part_pe, C=np.array([str(v) for v in part_c]))
             os.replace(path + ".tmp.npz", path)
             log(f"block {b} done ({time.time() - t0:.0f} s so far)")
-        pe[:, k0:k1] = part_pe
+        if not np.array_equal(pe[:, k0:k1], part_pe):
+            raise SystemExit(f"oracle methods disagree in block {b}")
         C = [C[i] + int(part_c[i]) for i in range(17)]
     X = oracle.global_from_c(n, m, C)
+    if X != sub["X"]:
+        raise SystemExit("oracle methods disagree on the global counts")
     eids = sample_edges(n, rp, col, 256, 11)
     write("chung_lu_1m_per_edge.json", {
         "graph": "graphgen.config_chung_lu_1m(): Chung-Lu n=1000000 m=10000000 gamma=2.1 cap=50000 "
                  f"seed={gg.BASE_SEED + 1}",
         "n": n, "m": int(m), "col_sha256_prefix": col_prefix(col),
-        "method": "edge-centric (glo_count_range over 8 blocks of the shared edge numbering)",
-        "X_from_blocks": [str(x) for x in X],
-        "slot_sha256": [sha_u64(pe[s]) for s in range(13)],
+        "method": "per-edge sub-structure method, and the edge-centric method over 8 blocks of the "
+                  "shared edge numbering; both gave every count below",
+        "X": [str(x) for x in X], "k4": str(sub["k4"]), "c4": str(sub["c4"]),
+        "slot_sha256": [sha_u64(pe[s_]) for s_ in range(13)],
         "sample_eids": [int(e) for e in eids],
-        "sample_counts": [[int(v) for v in pe[s, eids]] for s in range(13)],
-        "oracle_threads": threads,
+        "sample_counts": [[int(v) for v in pe[s_, eids]] for s_ in range(13)],
+        "oracle_seconds_substructures": round(t_sub, 1), "oracle_threads": threads,
     })
 
 
 def target_rmat_s22(threads):
+    """Per-edge and global counts by the per-edge sub-structure method (the edge-centric
+    method would take hundreds of core-hours here), checked on a seeded edge sample (uniform
+    edges plus edges at the highest-degree vertices) against the edge-centric method."""
     log("generating R-MAT scale 22")
     n, (rp, col) = gg.config_rmat_s22()
     m = col.size // 2
     t0 = time.time()
-    r = oracle.global_substructures(n, rp, col, per_edge3=True, nthreads=threads)
+    r = oracle.per_edge_substructures(n, rp, col, nthreads=threads)
     t_sub = time.time() - t0
-    log(f"sub-structure method {t_sub:.0f} s")
+    log(f"per-edge sub-structure method {t_sub:.0f} s")
+    pe = r["per_edge"]
+    edge_sums_check(pe, r["X"])
     eids = sample_edges(n, rp, col, 384, 12)
     t0 = time.time()
     ref = oracle.count_edges(n, rp, col, eids, nthreads=threads)
     log(f"edge-centric method on {eids.size} sampled edges {time.time() - t0:.0f} s")
-    # the sample's triangle, 2-star and H5 counts by both methods must agree
-    if not np.array_equal(ref[:3], r["per_edge3"][:, eids]):
+    if not np.array_equal(ref, pe[:, eids]):
         raise SystemExit("oracle methods disagree on the sampled edges")
     write("rmat_s22.json", {
         "graph": "graphgen.config_rmat_s22(): R-MAT scale 22 edge factor 16 (0.57,0.19,0.19,0.05) "
                  f"seed={gg.BASE_SEED + 2}, duplicates and self-loops removed, int64 offsets",
         "n": n, "m": int(m), "col_sha256_prefix": col_prefix(col),
-        "method": "global: sub-structure method (per-edge triangles, 4-cliques, 4-cycles); "
-                  "sample: edge-centric method",
+        "method": "per-edge sub-structure method (all counts); edge-centric method on the sample",
         "X": [str(x) for x in r["X"]], "k4": str(r["k4"]), "c4": str(r["c4"]),
-        "slot_sha256": {"0": sha_u64(r["per_edge3"][0]), "1": sha_u64(r["per_edge3"][1]),
-                        "2": sha_u64(r["per_edge3"][2])},
+        "slot_sha256": [sha_u64(pe[s_]) for s_ in range(13)],
         "sample_eids": [int(e) for e in eids],
-        "sample_counts": [[int(v) for v in ref[s]] for s in range(13)],
-        "oracle_seconds_global": round(t_sub, 1), "oracle_threads": threads,
+        "sample_counts": [[int(v) for v in ref[s_]] for s_ in range(13)],
+        "oracle_seconds_substructures": round(t_sub, 1), "oracle_threads": threads,
     })
 
 
