@@ -1,11 +1,13 @@
 """Benchmark: exact 4-node graphlet counts (global + per-edge) on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload chung_lu_1m]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat_s22]
 
 One step is one full glt_count call (validation, degree-order relabel, sorted oriented CSR,
 triangle / 4-clique pass, per-edge gather pass, 4-cycle wedge pass, combine and 128-bit
 reduction) producing all 17 global counts and the 13 per-edge counts of every edge, with
-the input CSR already resident in HBM.  Prints one JSON line.
+the input CSR already resident in HBM.  The default workload is the largest single-graph
+one, R-MAT scale 22 (edge factor 16, 64.2M edges); the Chung-Lu graph (10^6 vertices, 10^7
+edges) is timed in the same run and reported beside it.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -21,32 +23,37 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 
-# Measured HBM traffic (bytes per execution of each kernel group) of the per-edge run on
-# chung_lu_1m: rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, each a separate run of
-# `python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline`, scaled by the copy calibration
-# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0; see --copy-probe).  The figures belong to the kernel
-# source with the hash below and are reported only while it is unchanged.
+# Measured HBM traffic (bytes per execution of each kernel group) per workload, per-edge run:
+# rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, each a separate run of
+# `python3 bench.py --workload W --steps 1 --warmup 0 --no-cpu-baseline --no-side-workload
+# --no-probe`, scaled by the copy calibration (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0; see
+# --copy-probe).  The figures belong to the kernel sources with the hash below and are
+# reported only while they are unchanged.
+TRAFFIC_SOURCES = ["paper_1608_05138_amd/csrc/count.hip", "paper_1608_05138_amd/csrc/prep.hip"]
 TRAFFIC = {
-    "source": "paper_1608_05138_amd/csrc/count.hip",
-    "sha256": "a9293444c1ee3b234d89349cc324099b433eebb64779af3523c9ce5380518a19",
-    "workload": "chung_lu_1m", "per_edge": True,
-    "bytes": {"tri_wave": 3673907104, "tri_wg": 4449845568, "gather_wave": 1483612160,
-              "gather_wg": 2898601408, "wedge_wave": 82198464, "wedge_mid": 3529524128,
-              "wedge_wg": 8973273696, "wedge_huge": 38912},
+    "sha256": None,
+    "workloads": {},
 }
 
 
-def measured_traffic(workload, per_edge, group):
+def sources_sha256():
     import hashlib
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), TRAFFIC["source"])
-    try:
-        with open(src, "rb") as f:
-            ok = hashlib.sha256(f.read()).hexdigest() == TRAFFIC["sha256"]
-    except OSError:
-        ok = False
-    if not ok or workload != TRAFFIC["workload"] or bool(per_edge) != TRAFFIC["per_edge"]:
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        try:
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                h.update(f.read())
+        except OSError:
+            return None
+    return h.hexdigest()
+
+
+def measured_traffic(workload, per_edge, group):
+    rec = TRAFFIC["workloads"].get(workload)
+    if rec is None or not per_edge or TRAFFIC["sha256"] is None or sources_sha256() != TRAFFIC["sha256"]:
         return None
-    return TRAFFIC["bytes"].get(group)
+    return rec.get(group)
+
 
 WORKLOADS = {
     "chung_lu_1m": ("Chung-Lu n=1,000,000 m=10,000,000 exponent 2.1 weight cap 50,000, int32 CSR",
@@ -321,14 +328,56 @@ def group_bytes(work, per_edge, acc_bytes, records=True):
     return out
 
 
-def roofline(timing, work, per_edge, acc_bytes, workload=None, records=True):
+def prep_bytes(n, m, rp_width):
+    """Algorithmic bytes of preprocessing (validation, degree order, sorted and oriented
+    CSR): the input CSR read once (4 B per column entry, rp_width B per offset), the
+    relabelled, row-sorted CSR written once (4 B per entry and per offset) and the oriented
+    CSR written once (4 B per oriented edge and per offset)."""
+    return (8 * m + rp_width * (n + 1)) + (8 * m + 4 * (n + 1)) + (4 * m + 4 * (n + 1))
+
+
+def group_atomics(work, per_edge):
+    """Global atomic credits the 4-cycle wedge classes issue per launch: one per wedge (its
+    4-cycle credit to the top edge w - x) in per-edge mode; global-only counting credits in
+    LDS and adds one total per group."""
+    if not per_edge:
+        return {}
+    return {"wedge_" + c: work["wedges_" + c] for c in ("wave", "mid", "wg", "huge")}
+
+
+def roofline(timing, work, per_edge, acc_bytes, workload=None, records=True, prep=None, atomic_rate=None):
+    """The roofline record of the kernel group with the largest HIP-event time (counting
+    groups and, when prep is given, preprocessing): its algorithmic bytes over its time
+    against HBM's peak and, for a wedge class in per-edge mode, its global atomic credits
+    over its time against the measured rate of such atomics (atomic_rate, atomics/s)."""
     gb = group_bytes(work, per_edge, acc_bytes, records)
+    if prep is not None:
+        gb["prep"] = prep
     dom = max(gb, key=lambda g: timing[g])
     achieved = gb[dom] / (timing[dom] * 1e-3) / 1e9
-    return {"bound": "hbm", "kernel": GROUPS[dom], "group": dom, "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(workload, per_edge, dom),
-            "alg_bytes": int(gb[dom]), "kernel_ms": round(float(timing[dom]), 4)}
+    rec = {"bound": "hbm", "kernel": GROUPS.get(dom, dom), "group": dom, "achieved": round(achieved, 1),
+           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": measured_traffic(workload, per_edge, dom),
+           "alg_bytes": int(gb[dom]), "kernel_ms": round(float(timing[dom]), 4)}
+    atoms = group_atomics(work, per_edge)
+    if dom in atoms and atomic_rate:
+        a = atoms[dom] / (timing[dom] * 1e-3)
+        rec["atomic_roof"] = {"achieved": round(a / 1e9, 3), "peak": round(atomic_rate["rate"] / 1e9, 3),
+                              "unit": "Gatomics/s", "frac": round(a / atomic_rate["rate"], 4),
+                              "atomics": int(atoms[dom]), "peak_from": atomic_rate["what"]}
+        rec["closest_roof"] = "atomics" if rec["atomic_roof"]["frac"] > rec["frac"] else "hbm"
+    return rec
+
+
+def atomic_rate(nbytes, wide):
+    """Measured rate of global atomic adds in runs of 64 consecutive words per wavefront over
+    an array of nbytes (the pattern of the wedge pass's credits to one vertex's out-edges)."""
+    import paper_1608_05138_amd as glt
+    kind = "atomic_runs64" if wide else "atomic_runs"
+    ms, ops = glt.probe(kind, max(int(nbytes), 1 << 20), reps=5)
+    return {"rate": ops / (ms * 1e-3),
+            "what": f"glt_probe {kind}: {ops} atomic adds of {'64' if wide else '32'}-bit words in runs of 64 per "
+                    f"wavefront over {max(int(nbytes), 1 << 20)} bytes, {ms:.3f} ms per launch"}
 
 
 def mean_timing(samples):
@@ -341,13 +390,29 @@ def acc_width(max_degree):
     return 4 if max_degree <= 46340 else 8
 
 
+def host_cpu():
+    """CPU model name and the counts of logical CPUs on the host and available to us."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(n, rp, col, budget_s=15.0):
-    """The oracle (paper's method), per-edge counts of a uniform random edge sample."""
+    """The oracle (paper's method), per-edge counts of a uniform random edge sample, on the
+    host threads available to this process (at most 16: the host's share per GPU here)."""
     import numpy as np
 
     import oracle
     oracle.build(force=False)
-    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    cpu = host_cpu()
+    threads = max(1, min(16, cpu["affinity"]))
     m = col.size // 2
     rng = np.random.default_rng(2024)
     k = 256
@@ -364,15 +429,34 @@ def cpu_baseline(n, rp, col, budget_s=15.0):
     return {"value": done / spent, "unit": "edges/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} uniformly drawn edges of the same graph, per-edge counts by the "
                       f"paper's edge-centric method (vertex terms for their endpoints included), "
-                      f"{spent:.1f} s"}
+                      f"{spent:.1f} s on {threads} threads",
+            "host": cpu}
+
+
+def time_graph(ctx, rpt, ct, n, per_edge, out, stream, steps, warmup):
+    """Warm-up calls, then `steps` timed glt_count calls (host clock around them, the
+    library's HIP-event kernel-group times per call)."""
+    import torch
+    X = None
+    for _ in range(warmup):
+        X, _ = ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    timings = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        X, _ = ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
+        timings.append(ctx.last_timing())
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+    return ms, mean_timing(timings), X
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="chung_lu_1m", choices=sorted(WORKLOADS) + ["batch_10k", "served"])
+    ap.add_argument("--workload", default="rmat_s22", choices=sorted(WORKLOADS) + ["batch_10k", "served"])
     ap.add_argument("--batch-graphs", type=int, default=10_000)
     ap.add_argument("--no-per-graph", action="store_true", help="batch/served: skip the per-graph comparison")
     ap.add_argument("--no-autotune", action="store_true", help="batch: keep the default schedule")
@@ -382,6 +466,10 @@ def main():
     ap.add_argument("--pool-small", type=int, default=10000, help="served: pool of small request graphs")
     ap.add_argument("--pool-large", type=int, default=64, help="served: pool of large request graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-side-workload", action="store_true",
+                    help="single graph: skip the second workload timed beside the line (the Chung-Lu "
+                         "graph beside R-MAT)")
+    ap.add_argument("--no-probe", action="store_true", help="skip the atomic-rate calibration of the roofline")
     ap.add_argument("--compare-modes", action="store_true",
                     help="single graph: also time the other stream modes (reported beside the line)")
     ap.add_argument("--stream-mode", type=int, default=None, choices=[0, 1, 2],
@@ -435,25 +523,20 @@ def main():
         ctx.set_schedule(wedge_stream=args.stream_mode)
     mode = ctx.schedule()["wedge_stream"]
     stream = torch.cuda.current_stream(dev)
-    print(f"[bench] n={n} m={m}; warmup {args.warmup}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        X, _ = ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
-    torch.cuda.synchronize()
-    timings = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        X, _ = ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
-        timings.append(ctx.last_timing())
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    timing = mean_timing(timings)
+    print(f"[bench] n={n} m={m}; warmup {args.warmup}, {args.steps} timed steps", file=sys.stderr, flush=True)
+    ms_per_step, timing, X = time_graph(ctx, rpt, ct, n, per_edge, out, stream, args.steps, args.warmup)
     work = ctx.last_work()
     print(f"[bench] {ms_per_step:.3f} ms/step; kernel groups " +
           ", ".join(f"{k}={v:.3f}" for k, v in timing.items()), file=sys.stderr, flush=True)
 
     maxdeg = int(np.diff(rp.astype(np.int64)).max()) if n else 0
-    roof = roofline(timing, work, per_edge, acc_width(maxdeg), args.workload, bool(ctx.schedule()["tri_records"]))
+    acc = acc_width(maxdeg)
+    arate = None
+    if not args.no_probe and per_edge:
+        arate = atomic_rate(acc * m, acc == 8)
+        print(f"[bench] atomic calibration: {arate['what']}", file=sys.stderr, flush=True)
+    roof = roofline(timing, work, per_edge, acc, args.workload, bool(ctx.schedule()["tri_records"]),
+                    prep=prep_bytes(n, m, rp.dtype.itemsize), atomic_rate=arate)
     study = None
     if args.order_study:
         # the ordering study (Section 4.3, Table 4) on the same graph: step time per order of the
@@ -463,13 +546,8 @@ def main():
         default_order = ctx.schedule()["list_order"]
         for order, name in enumerate(names):
             ctx.set_schedule(list_order=order)
-            ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                Xo, _ = ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
-            torch.cuda.synchronize()
-            study[name] = round((time.perf_counter() - t0) * 1e3 / args.steps, 3)
+            oms, _, Xo = time_graph(ctx, rpt, ct, n, per_edge, out, stream, args.steps, 1)
+            study[name] = round(oms, 3)
             assert Xo == X, "list order changed the counts"
         ctx.set_schedule(list_order=default_order)
         print(f"[bench] ordering study (ms/step): {study}", file=sys.stderr, flush=True)
@@ -480,16 +558,35 @@ def main():
             if om == mode:
                 continue
             ctx.set_schedule(wedge_stream=om)
-            ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                X2, _ = ctx.count(rpt, ct, n=n, per_edge=per_edge, out=out, stream=stream.cuda_stream)
-            torch.cuda.synchronize()
-            other[str(om)] = round((time.perf_counter() - t0) * 1e3 / args.steps, 3)
+            oms, _, X2 = time_graph(ctx, rpt, ct, n, per_edge, out, stream, args.steps, 1)
+            other[str(om)] = round(oms, 3)
             assert X2 == X, "the stream mode changed the counts"
         ctx.set_schedule(wedge_stream=mode)
         print(f"[bench] other stream modes (ms/step): {other}", file=sys.stderr, flush=True)
+    side = None
+    if args.workload == "rmat_s22" and not args.no_side_workload:
+        # the Chung-Lu graph, timed in the same run and reported beside the line
+        del out
+        torch.cuda.empty_cache()
+        sdesc, sfn = WORKLOADS["chung_lu_1m"]
+        print(f"[bench] side workload: generating {sdesc}", file=sys.stderr, flush=True)
+        sn, (srp, scol) = getattr(gg, sfn)()
+        sm = scol.size // 2
+        srpt = torch.from_numpy(srp).to(dev)
+        sct = torch.from_numpy(scol).to(dev)
+        sout = torch.empty((13, sm), dtype=torch.int64, device=dev) if per_edge else None
+        sms, stiming, _ = time_graph(ctx, srpt, sct, sn, per_edge, sout, stream, 20, 5)
+        swork = ctx.last_work()
+        sacc = acc_width(int(np.diff(srp.astype(np.int64)).max()))
+        sarate = atomic_rate(sacc * sm, sacc == 8) if (not args.no_probe and per_edge) else None
+        side = {"workload": "chung_lu_1m", "graph": sdesc, "n": sn, "m": sm, "steps": 20, "warmup": 5,
+                "ms_per_step": round(sms, 4), "edges_per_s": sm / (sms * 1e-3),
+                "kernel_groups_ms": {k: round(float(v), 4) for k, v in stiming.items()},
+                "roofline": roofline(stiming, swork, per_edge, sacc, "chung_lu_1m",
+                                     bool(ctx.schedule()["tri_records"]), prep=prep_bytes(sn, sm, srp.dtype.itemsize),
+                                     atomic_rate=sarate)}
+        print(f"[bench] side workload: {sms:.3f} ms/step", file=sys.stderr, flush=True)
+        del sout, srpt, sct
     line = {
         "metric": "edges/sec for exact 4-node motif counts (1 GPU)",
         "value": m / (ms_per_step * 1e-3),
@@ -505,6 +602,7 @@ def main():
         "kernel_groups_ms": {k: round(float(v), 4) for k, v in timing.items()},
         "work": work,
         "roofline": roof,
+        **({"side_workload": side} if side else {}),
         **({"order_study_ms_per_step": study} if study else {}),
         **({"other_stream_modes_ms_per_step": other} if other else {}),
     }

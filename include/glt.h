@@ -33,9 +33,12 @@
  * message is available from glt_last_error() until the next call on the same handle.
  * On error, outputs are unspecified.  No C++ exception crosses this interface.
  *
- * Streams: "stream" is a hipStream_t (passed as void*); NULL selects the handle's own
- * stream.  Every call in this header returns only after its results are complete and
- * visible to the host (global counts) and on the device (per-edge counts).
+ * Streams: "stream" is a hipStream_t (passed as void*).  A call's device work is ordered
+ * after the work already queued on that stream.  NULL selects the handle's own stream,
+ * which is then made to wait for the work already queued on the device's legacy default
+ * (NULL) stream, so inputs written there (e.g. by PyTorch's default stream) are complete
+ * before they are read.  Every call in this header returns only after its results are
+ * complete and visible to the host (global counts) and on the device (per-edge counts).
  */
 #ifndef GLT_H
 #define GLT_H
@@ -208,6 +211,24 @@ glt_status glt_set_schedule(glt_ctx* ctx, const glt_schedule* s);
  * Errors as glt_count_batch.
  */
 glt_status glt_autotune_batch(glt_ctx* ctx, const glt_batch* b, glt_schedule* best, float* best_ms, void* stream);
+
+/*
+ * Calibration of the roofline (measurement only; counts nothing).  Allocates `bytes` of
+ * device memory on `device`, runs one untimed and `reps` timed launches of a probe kernel
+ * over it and frees it:
+ *   kind 0  global atomic adds, each wavefront to a run of 64 consecutive 32-bit words at a
+ *           pseudo-random 256-byte-aligned place (the pattern of the counting passes' credits
+ *           to the out-edges of one vertex)
+ *   kind 1  global atomic adds, each lane to a pseudo-random 32-bit word
+ *   kind 2  one read of every byte (16-byte loads, grid-stride), no stores besides one
+ *           word per workgroup
+ *   kind 3, 4  as 0 and 1 with 64-bit words (runs of 64 words are 512 bytes)
+ *   ms   out: average time of one launch in milliseconds (HIP events)
+ *   ops  out: atomic adds (kinds 0, 1, 3, 4) or bytes read (kind 2) per launch
+ * Errors: GLT_E_INVALID_ARG (null output, reps < 1, unknown kind, bytes outside
+ * [16 KiB, 16 GiB)), GLT_E_OOM, GLT_E_DEVICE.
+ */
+glt_status glt_probe(int device, int kind, size_t bytes, int reps, float* ms, uint64_t* ops);
 
 /* ------------------------------------------------------------------------------------ */
 /* Request server: continuous batching of graph-count requests on one device.            */

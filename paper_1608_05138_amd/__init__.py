@@ -39,7 +39,8 @@ STATUS = {0: "GLT_OK", -1: "GLT_E_INVALID_ARG", -2: "GLT_E_NOT_SIMPLE", -3: "GLT
 EXPORTS = ["glt_create", "glt_destroy", "glt_last_error", "glt_version", "glt_count",
            "glt_last_timing", "glt_last_work", "glt_count_batch", "glt_server_create",
            "glt_server_submit", "glt_server_poll", "glt_server_inflight", "glt_server_clock",
-           "glt_server_destroy", "glt_get_schedule", "glt_set_schedule", "glt_autotune_batch"]
+           "glt_server_destroy", "glt_get_schedule", "glt_set_schedule", "glt_autotune_batch",
+           "glt_probe"]
 
 
 class GltError(RuntimeError):
@@ -139,6 +140,9 @@ def load_library(path: str = LIB_PATH):
     lib.glt_autotune_batch.argtypes = [P, ctypes.POINTER(glt_batch), ctypes.POINTER(glt_schedule),
                                        ctypes.POINTER(ctypes.c_float), P]
     lib.glt_autotune_batch.restype = ctypes.c_int
+    lib.glt_probe.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t, ctypes.c_int,
+                              ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint64)]
+    lib.glt_probe.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -389,6 +393,19 @@ def count(row_ptr, col, n=None, per_edge=False, device=0):
     if ctx is None:
         ctx = _default[device] = Context(device)
     return ctx.count(row_ptr, col, n=n, per_edge=per_edge)
+
+
+PROBE_KINDS = {"atomic_runs": 0, "atomic_scatter": 1, "read": 2, "atomic_runs64": 3, "atomic_scatter64": 4}
+
+
+def probe(kind: str, nbytes: int, reps: int = 5, device: int = 0):
+    """Roofline calibration (glt_probe): (ms per launch, atomics or bytes per launch)."""
+    ms = ctypes.c_float(0)
+    ops = ctypes.c_uint64(0)
+    rc = load_library().glt_probe(device, PROBE_KINDS[kind], nbytes, reps, ctypes.byref(ms), ctypes.byref(ops))
+    if rc != 0:
+        raise GltError(rc, f"glt_probe({kind}) failed")
+    return float(ms.value), int(ops.value)
 
 
 def version() -> str:

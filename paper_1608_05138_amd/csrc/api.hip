@@ -57,6 +57,7 @@ struct glt_ctx {
     int last_mode = 0;                 // the stream mode the last call's timing was taken in
     void* slab = nullptr;              // larger global slab for the highest out-degrees (grown on demand)
     size_t slab_bytes = 0;
+    hipEvent_t ev_null = nullptr;      // orders the handle's stream after the legacy default stream
 };
 
 #define GLT_VERSION "glt 0.2 (gfx950)"
@@ -385,6 +386,20 @@ void record_timing(glt_ctx* ctx) {
     }
 }
 
+// The stream a call runs on.  With no stream given, the handle's own (non-blocking) stream,
+// made to wait for the work already queued on the device's legacy default stream: device
+// inputs (and the per-edge output buffer) may come from work still pending there.
+glt_status call_stream(glt_ctx* ctx, void* stream_, hipStream_t& st) {
+    if (stream_) {
+        st = (hipStream_t)stream_;
+        return GLT_OK;
+    }
+    st = ctx->stream;
+    HIPCHK(hipEventRecord(ctx->ev_null, nullptr));
+    HIPCHK(hipStreamWaitEvent(st, ctx->ev_null, 0));
+    return GLT_OK;
+}
+
 }  // namespace
 
 // Global counts of B graphs given per-graph device pointers to their local offsets
@@ -504,6 +519,10 @@ glt_status glt_create(int device, size_t hbm_budget_bytes, glt_ctx** out) {
     }
     for (int i = 0; i < NEV; i++)
         if (hipEventCreate(&ctx->ev[i]) != hipSuccess) { glt_destroy(ctx); return GLT_E_DEVICE; }
+    if (hipEventCreateWithFlags(&ctx->ev_null, hipEventDisableTiming) != hipSuccess) {
+        glt_destroy(ctx);
+        return GLT_E_DEVICE;
+    }
     if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess) {
         glt_destroy(ctx);
         return GLT_E_DEVICE;
@@ -530,6 +549,7 @@ void glt_destroy(glt_ctx* ctx) {
     }
     for (int i = 0; i < NEV; i++)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    if (ctx->ev_null) (void)hipEventDestroy(ctx->ev_null);
     if (ctx->hbuf) (void)hipHostFree(ctx->hbuf);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -569,12 +589,14 @@ glt_status glt_count(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 ou
     const bool host_in = !g->on_device;
     const bool host_out = per_edge && !g->on_device && m > 0;
     HIPCHK(hipSetDevice(ctx->device));
-    hipStream_t st = stream_ ? (hipStream_t)stream_ : ctx->stream;
+    hipStream_t st = nullptr;
+    glt_status rc = call_stream(ctx, stream_, st);
+    if (rc) return rc;
 
     Dev d;
     Staging sg;
     const size_t need = carve(nullptr, n, m, rp64, host_in, host_out, 0, 0, d, sg);
-    glt_status rc = ensure_ws(ctx, need, st);
+    rc = ensure_ws(ctx, need, st);
     if (rc) return rc;
     carve(ctx->ws, n, m, rp64, host_in, host_out, 0, 0, d, sg);
 
@@ -650,7 +672,9 @@ glt_status glt_count_batch(glt_ctx* ctx, const glt_batch* b, uint32_t flags, glt
         return fail(ctx, GLT_E_UNSUPPORTED, "packed vertices or slots do not fit 31 bits");
     if (!b->row_ptr || (S > 0 && !b->col)) return fail(ctx, GLT_E_INVALID_ARG, "null row_ptr or col");
     HIPCHK(hipSetDevice(ctx->device));
-    hipStream_t st = stream_ ? (hipStream_t)stream_ : ctx->stream;
+    hipStream_t st = nullptr;
+    glt_status rc0 = call_stream(ctx, stream_, st);
+    if (rc0) return rc0;
     const int* rp = b->row_ptr;
     const int* col = b->col;
     if (!b->on_device) {

@@ -183,6 +183,19 @@ struct glt_server {
         }
     }
 
+    // A request whose copy to the device reported an error (its event's query or wait did not
+    // return success) fails alone with GLT_E_DEVICE; its slot is released and its event, in
+    // an unknown state, destroyed.  Called with the lock held.
+    void fail_copy(Request* r) {
+        const double t = now_s();
+        finish(r, GLT_E_DEVICE, nullptr, t, t, 0);
+        pool.release(r->off, r->bytes);
+        (void)hipEventDestroy(r->ev);
+        delete r;
+        cv_admit.notify_all();
+        cv_done.notify_all();
+    }
+
     // Runs one group; on a validation error, re-runs its requests one by one so that only
     // the invalid ones fail.
     void run_group(Lane& ln, std::vector<Request*>& grp, std::vector<int>& status, std::vector<glt_u128>& X) {
@@ -222,11 +235,18 @@ struct glt_server {
             ln.cv.wait(lk, [&] { return stop || !ln.admitted.empty(); });
             if (stop) return;
             // the oldest admitted request of the lane goes first; wait for its copy if needed
+            // (only this thread removes entries of ln.admitted, so it stays at the front)
             Request* head = ln.admitted.front();
-            if (hipEventQuery(head->ev) != hipSuccess) {
+            hipError_t q = hipEventQuery(head->ev);
+            if (q == hipErrorNotReady) {
                 lk.unlock();
-                (void)hipEventSynchronize(head->ev);
+                q = hipEventSynchronize(head->ev);
                 lk.lock();
+            }
+            if (q != hipSuccess) {
+                ln.admitted.pop_front();
+                fail_copy(head);
+                continue;
             }
             std::vector<Request*> grp;
             int64_t edges = 0;
@@ -234,11 +254,17 @@ struct glt_server {
             while (!ln.admitted.empty() && (int64_t)grp.size() < maxg) {
                 Request* r = ln.admitted.front();
                 if (!grp.empty() && edges + r->m > opts.max_batch_edges) break;
-                if (hipEventQuery(r->ev) != hipSuccess) break;
+                const hipError_t qr = hipEventQuery(r->ev);
+                if (qr == hipErrorNotReady) break;
                 ln.admitted.pop_front();
+                if (qr != hipSuccess) {   // its copy failed: it fails alone
+                    fail_copy(r);
+                    continue;
+                }
                 grp.push_back(r);
                 edges += r->m;
             }
+            if (grp.empty()) continue;
             lk.unlock();
             const double t_start = now_s();
             std::vector<int> status;

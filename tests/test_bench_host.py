@@ -50,8 +50,30 @@ def test_roofline_takes_the_longest_group():
 def test_traffic_only_for_its_workload_and_mode():
     assert bench.measured_traffic("er_1k", True, "wedge_wg") is None
     assert bench.measured_traffic("chung_lu_1m", False, "wedge_wg") is None
-    v = bench.measured_traffic("chung_lu_1m", True, "wedge_wg")
-    assert v is None or v == bench.TRAFFIC["bytes"]["wedge_wg"]
+    for wl, rec in bench.TRAFFIC["workloads"].items():
+        v = bench.measured_traffic(wl, True, "wedge_wg")
+        assert v is None or v == rec["wedge_wg"]
+
+
+def test_prep_competes_and_atomic_roof():
+    timing = {"tri_wave": 1.0, "tri_wg": 0.5, "gather_wave": 0.1, "gather_wg": 0.1,
+              "wedge_wave": 0.2, "wedge_mid": 0.3, "wedge_wg": 2.0, "wedge_huge": 0.0, "prep": 3.0}
+    pb = bench.prep_bytes(100, 1000, 8)
+    assert pb == (8 * 1000 + 8 * 101) + (8 * 1000 + 4 * 101) + (4 * 1000 + 4 * 101)
+    r = bench.roofline(timing, WORK, per_edge=True, acc_bytes=4, prep=pb,
+                       atomic_rate={"rate": 1e9, "what": "test"})
+    assert r["group"] == "prep" and r["alg_bytes"] == pb and "atomic_roof" not in r
+    timing["prep"] = 0.1
+    r = bench.roofline(timing, WORK, per_edge=True, acc_bytes=4, prep=pb,
+                       atomic_rate={"rate": 1e9, "what": "test"})
+    assert r["group"] == "wedge_wg"
+    a = r["atomic_roof"]
+    assert a["atomics"] == 300 and a["frac"] == pytest.approx(300 / 2.0e-3 / 1e9, abs=1e-4)
+    assert r["closest_roof"] in ("hbm", "atomics")
+    # global counts only: the wedge pass issues no per-wedge global atomics
+    r = bench.roofline(timing, WORK, per_edge=False, acc_bytes=4, prep=pb,
+                       atomic_rate={"rate": 1e9, "what": "test"})
+    assert "atomic_roof" not in r
 
 
 def test_more_than_one_gpu_is_refused():

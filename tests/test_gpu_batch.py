@@ -130,3 +130,37 @@ def test_schedule_api_and_autotuner():
 
 def ctx_counts(c, packed):
     return c.count_batch(packed)
+
+
+def _gen(spec):
+    return gg.batch_graph(spec)
+
+
+def test_batch_10k_vs_stored_oracle(ctx):
+    """All 10,000 graphs of the batch mix (n ~ U{50..5000}, ER or Chung-Lu(2.5), mean degree
+    ~ U[4, 64]) in one glt_count_batch call: every graph's 17 counts equal the stored
+    oracle counts (digest of each graph's counts; full counts of every 100th graph)."""
+    import hashlib
+    import json
+    import multiprocessing as mp
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "batch_10k.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored counts")
+    with open(path) as f:
+        golden = json.load(f)
+    specs = gg.batch_spec(golden["num_graphs"])
+    say("batch-10k generating graphs")
+    procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    with mp.get_context("fork").Pool(procs) as pool:
+        graphs = pool.map(_gen, specs, chunksize=16)
+    packed = gg.pack_batch(graphs)
+    del graphs
+    say(f"batch-10k counting ({packed['col'].size // 2} edges)")
+    res = ctx.count_batch(_to_device(packed))
+    assert len(res) == len(specs)
+    for key, Xs in golden["X_every_100"].items():
+        assert res[int(key)] == [int(x) for x in Xs], int(key)
+    bad = [g for g, X in enumerate(res)
+           if hashlib.sha256(",".join(str(v) for v in X).encode()).hexdigest()[:16] != golden["X_digest"][g]]
+    assert not bad, f"{len(bad)} graphs differ from the stored oracle counts, first {bad[:10]}"

@@ -410,7 +410,30 @@ def _sampled_edges(n, rp, col, k, seed):
     return np.array(sorted(ids), dtype=np.int64)
 
 
-def _full_size(ctx, name, n, rp, col, golden=None):
+def _load_golden(name, col):
+    """Stored oracle results (tests/golden/<name>), checked to belong to this graph."""
+    import hashlib
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    assert hashlib.sha256(np.ascontiguousarray(col).tobytes()).hexdigest()[:16] == g["col_sha256_prefix"]
+    return g
+
+
+def _slot_digests(pe):
+    import hashlib
+    return [hashlib.sha256(np.ascontiguousarray(pe[s], dtype="<u8").tobytes()).hexdigest() for s in range(13)]
+
+
+def _full_size(ctx, name, n, rp, col, golden_X=None, golden_pe=None):
+    """Full-size graph: global counts against the stored oracle counts; per-edge counts
+    against the stored oracle's SHA-256 of every slot array (all edges) and its counts of a
+    seeded edge sample (element by element, to name a failing edge); identities that hold
+    at any size; and the oracle itself on a few sampled edges."""
     say(f"{name} per-edge")
     X, pe = gpu(ctx, n, rp, col, per_edge=True)
     say(f"{name} global")
@@ -419,9 +442,14 @@ def _full_size(ctx, name, n, rp, col, golden=None):
     _edge_sum_identity(X, pe)
     assert X[0] == col.size // 2
     assert sum(X[2:6]) == comb(n, 3)
-    if golden is not None:
-        assert X == golden, name + " vs stored oracle counts"
-    eids = _sampled_edges(n, rp, col, 96, 7)
+    if golden_X is not None:
+        assert X == golden_X, name + " vs stored oracle counts"
+    if golden_pe is not None:
+        eids = np.asarray(golden_pe["sample_eids"], dtype=np.int64)
+        np.testing.assert_array_equal(pe[:, eids], np.asarray(golden_pe["sample_counts"], dtype=np.uint64))
+        say(f"{name} per-edge digests of all {col.size // 2} edges")
+        assert _slot_digests(pe) == golden_pe["slot_sha256"], name + " per-edge arrays vs stored oracle digests"
+    eids = _sampled_edges(n, rp, col, 48, 7)
     say(f"{name} oracle on {eids.size} sampled edges")
     ref = oracle.count_edges(n, rp, col, eids)
     np.testing.assert_array_equal(pe[:, eids], ref)
@@ -429,23 +457,71 @@ def _full_size(ctx, name, n, rp, col, golden=None):
 
 
 def test_config_chung_lu_1m(ctx):
-    import json
-    import os
     n, (rp, col) = gg.config_chung_lu_1m()
-    path = os.path.join(os.path.dirname(__file__), "golden", "chung_lu_1m_global.json")
-    golden = None
-    if os.path.exists(path):
-        import hashlib
-        with open(path) as f:
-            g = json.load(f)
-        assert hashlib.sha256(np.ascontiguousarray(col).tobytes()).hexdigest()[:16] == g["col_sha256_prefix"]
-        golden = [int(x) for x in g["X"]]
-    _full_size(ctx, "chung-lu-1m-10m", n, rp, col, golden)
+    g = _load_golden("chung_lu_1m_global.json", col)
+    gpe = _load_golden("chung_lu_1m_per_edge.json", col)
+    _full_size(ctx, "chung-lu-1m-10m", n, rp, col, [int(x) for x in g["X"]] if g else None, gpe)
+    if gpe is not None:
+        assert [int(x) for x in gpe["X"]] == [int(x) for x in g["X"]]
 
 
 def test_config_rmat_s22(ctx):
     n, (rp, col) = gg.config_rmat_s22()
-    _full_size(ctx, "rmat-s22-ef16", n, rp, col)
+    g = _load_golden("rmat_s22.json", col)
+    _full_size(ctx, "rmat-s22-ef16", n, rp, col, [int(x) for x in g["X"]] if g else None, g)
+
+
+def test_hub_above_46340_all_stream_modes():
+    """A 50,000-leaf star over sparse ER noise: the maximum degree exceeds 46,340, so every
+    per-edge accumulator is 64-bit; all 13 per-edge counts of every edge and the global
+    counts must equal the oracle's in each stream mode."""
+    import paper_1608_05138_amd as glt
+    rng = np.random.default_rng(46341)
+    n = 60000
+    lo, hi = gg.er_pairs(n, 100000, rng)
+    a = np.concatenate([lo, np.zeros(50000, np.int64)])
+    b = np.concatenate([hi, np.arange(1, 50001)])
+    key = np.unique(np.minimum(a, b) * n + np.maximum(a, b))
+    perm = rng.permutation(n)
+    rp, col = gg.csr_from_pairs(n, perm[key // n], perm[key % n])
+    assert np.diff(rp).max() > 46340
+    ref = oracle.count(n, rp, col, per_edge=True)
+    for mode in (0, 1, 2):
+        c = glt.Context(0)
+        try:
+            c.set_schedule(wedge_stream=mode)
+            say(f"hub-50000-star mode {mode}")
+            X, pe = gpu(c, n, rp, col)
+            assert X == ref["X"], mode
+            np.testing.assert_array_equal(pe, ref["per_edge"], err_msg=f"mode {mode}")
+            G, _ = gpu(c, n, rp, col, per_edge=False)
+            assert G == ref["X"], mode
+        finally:
+            c.close()
+
+
+def test_inputs_pending_on_default_stream(ctx):
+    """Device inputs still being written by work queued on the default stream (a
+    non-blocking copy from pinned memory behind a long kernel) are read only after that
+    work: the call made with no stream waits for the default stream."""
+    import torch
+    n = 20000
+    rp, col = gg.chung_lu(n, 200000, 2.1, float(n - 1), 12)
+    ref = oracle.count(n, rp, col, per_edge=True)
+    say("inputs pending on the default stream")
+    for trial in range(3):
+        a = torch.randn(4096, 4096, device="cuda")
+        b = a
+        for _ in range(8):          # keeps the default stream busy for a while
+            b = b @ a
+        rpt = torch.from_numpy(np.ascontiguousarray(rp)).pin_memory().cuda(non_blocking=True)
+        ct = torch.from_numpy(np.ascontiguousarray(col, dtype=np.int32)).pin_memory().cuda(non_blocking=True)
+        out = torch.full((13, col.size // 2), -1, dtype=torch.int64, device="cuda")
+        X, pe = ctx.count(rpt, ct, n=n, per_edge=True, out=out)
+        torch.cuda.synchronize()
+        assert X == ref["X"], trial
+        np.testing.assert_array_equal(pe.cpu().numpy().view(np.uint64), ref["per_edge"])
+        del b
 
 
 def test_out_degree_limit(ctx):
