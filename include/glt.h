@@ -110,6 +110,24 @@ glt_status glt_count(glt_ctx* ctx, const glt_csr* g, uint32_t flags,
                      glt_u128 out_global[17], uint64_t* out_per_edge, void* stream);
 
 /*
+ * glt_count for callers that cannot allocate device memory during the call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same counts
+ * as glt_count, computed with no hipMalloc, hipFree or other allocating call.  Its
+ * workspace is one fixed array of GLT_NOALLOC_MAX_BYTES per device, reserved when the
+ * library is loaded on that device and held until the process ends; every call on a device
+ * shares it (calls that overlap on one device, on any handles or streams, race and must be
+ * serialised by the caller), and each call clears what it needs before use.  Arguments as
+ * glt_count, except that g->on_device must be 1 (inputs and out_per_edge in device memory).
+ * The triangle passes re-scan out-lists instead of storing triangle records.
+ * Errors as glt_count; GLT_E_INVALID_ARG for host inputs; GLT_E_UNSUPPORTED when the graph's
+ * workspace exceeds GLT_NOALLOC_MAX_BYTES (roughly 400,000 edges), with the size needed in
+ * the message.
+ */
+#define GLT_NOALLOC_MAX_BYTES ((size_t)128 << 20)
+glt_status glt_count_noalloc(glt_ctx* ctx, const glt_csr* g, uint32_t flags,
+                             glt_u128 out_global[17], uint64_t* out_per_edge, void* stream);
+
+/*
  * A batch of independent graphs packed back to back.  Graph g owns packed vertices
  * [vtx_base[g], vtx_base[g+1]) and packed column entries [slot_base[g], slot_base[g+1]);
  * its n_g + 1 local row offsets start at row_ptr[vtx_base[g] + g] and count from 0 to

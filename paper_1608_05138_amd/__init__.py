@@ -40,7 +40,7 @@ EXPORTS = ["glt_create", "glt_destroy", "glt_last_error", "glt_version", "glt_co
            "glt_last_timing", "glt_last_work", "glt_count_batch", "glt_server_create",
            "glt_server_submit", "glt_server_poll", "glt_server_inflight", "glt_server_clock",
            "glt_server_destroy", "glt_get_schedule", "glt_set_schedule", "glt_autotune_batch",
-           "glt_probe"]
+           "glt_probe", "glt_count_noalloc"]
 
 
 class GltError(RuntimeError):
@@ -143,6 +143,9 @@ def load_library(path: str = LIB_PATH):
     lib.glt_probe.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t, ctypes.c_int,
                               ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint64)]
     lib.glt_probe.restype = ctypes.c_int
+    lib.glt_count_noalloc.argtypes = [P, ctypes.POINTER(glt_csr), ctypes.c_uint32,
+                                      ctypes.POINTER(glt_u128), P, P]
+    lib.glt_count_noalloc.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -198,8 +201,17 @@ class Context:
         k = self._lib.glt_last_work(self._h, buf, len(self.WORK_KEYS))
         return {name: int(buf[i]) for i, name in enumerate(self.WORK_KEYS[:k])}
 
+    def count_noalloc(self, row_ptr, col, n: int | None = None, per_edge: bool = False, out=None,
+                      stream=None):
+        """glt_count_noalloc: as count() with device tensors only; the library allocates no
+        device memory during the call (its fixed per-device scratch array serves as the
+        workspace; overlapping calls on one device race)."""
+        if not (_is_torch(row_ptr) and row_ptr.is_cuda):
+            raise ValueError("count_noalloc takes device tensors only")
+        return self.count(row_ptr, col, n=n, per_edge=per_edge, out=out, stream=stream, _noalloc=True)
+
     def count(self, row_ptr, col, n: int | None = None, per_edge: bool = False, out=None,
-              stream=None):
+              stream=None, _noalloc: bool = False):
         """Count graphlets of the CSR graph (row_ptr, col).
 
         Device inputs: torch CUDA tensors (int32/int64 row_ptr, int32 col); per-edge output
@@ -246,9 +258,9 @@ class Context:
         g = glt_csr(nn, m, rp_ptr, col_ptr, 1 if rp64 else 0, 1 if dev else 0)
         X = (glt_u128 * 17)()
         flags = GLT_GLOBAL | (GLT_PER_EDGE if per_edge else 0)
-        rc = self._lib.glt_count(self._h, ctypes.byref(g), flags, X,
-                                 ctypes.c_void_p(out_ptr) if out_ptr else None,
-                                 ctypes.c_void_p(stream) if stream else None)
+        fn = self._lib.glt_count_noalloc if _noalloc else self._lib.glt_count
+        rc = fn(self._h, ctypes.byref(g), flags, X, ctypes.c_void_p(out_ptr) if out_ptr else None,
+                ctypes.c_void_p(stream) if stream else None)
         if rc != 0:
             raise GltError(rc, self.last_error())
         return [int(x.lo) | (int(x.hi) << 64) for x in X], (out if per_edge else None)

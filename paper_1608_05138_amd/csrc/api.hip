@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -58,11 +59,38 @@ struct glt_ctx {
     void* slab = nullptr;              // larger global slab for the highest out-degrees (grown on demand)
     size_t slab_bytes = 0;
     hipEvent_t ev_null = nullptr;      // orders the handle's stream after the legacy default stream
+    void* scratch = nullptr;           // device address of this device's glt_count_noalloc workspace
 };
 
 #define GLT_VERSION "glt 0.2 (gfx950)"
 
+// Workspace of glt_count_noalloc: one fixed array per device (each device that loads the
+// library holds its own copy until the process ends).  Host code never uses its name as an
+// address: the device address comes from hipGetSymbolAddress, once per device, at handle
+// creation (scratch_address).
+#define GLT_SCRATCH_BYTES GLT_NOALLOC_MAX_BYTES
+static __device__ __align__(256) unsigned char scratch[GLT_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the current device), looked up once per device.
+hipError_t scratch_address(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 constexpr size_t kAlign = 256;
 constexpr int64_t kGScratchWords = 8 << 20;   // 32 MiB of global bitmap rows / accumulators
@@ -316,7 +344,7 @@ u64* ensure_trec(glt_ctx* ctx, u64 slots, hipStream_t st) {
 // Validation, preprocessing and the counting passes on a prepared CSR (rp, col) on the
 // device.  Host read-backs: validation flags after the row check and after the build.
 glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const int* col, bool per_edge,
-                        u64* pe_dev, hipStream_t st) {
+                        u64* pe_dev, hipStream_t st, bool noalloc = false) {
     const int n = d.n, m = d.m;
     d.wedge_wave_max = ctx->wedge_wave_max;
     d.wedge_mid_max = ctx->wedge_mid_max;
@@ -358,8 +386,12 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
             return fail(ctx, GLT_E_UNSUPPORTED, "out-degree %d in the degree order exceeds %d",
                         hc[TB_N + WB_N + TB_GLOBAL], glt_max_out_degree());
     }
-    d.trec = ensure_trec(ctx, n > 0 ? *(u64*)((char*)ctx->hbuf + 64) : 0, st);
-    grow_slab(ctx, d, hc[TB_GLOBAL], hc[TB_N + WB_N + TB_GLOBAL], st);
+    if (noalloc) {
+        d.trec = nullptr;   // the passes re-scan the out-lists; the carved 32 MiB slab serves
+    } else {
+        d.trec = ensure_trec(ctx, n > 0 ? *(u64*)((char*)ctx->hbuf + 64) : 0, st);
+        grow_slab(ctx, d, hc[TB_GLOBAL], hc[TB_N + WB_N + TB_GLOBAL], st);
+    }
     ctx->last_mode = ctx->wedge_stream;
     glt_count_passes(d, per_edge ? 1 : 0, hc, pe_dev, st, ctx->side, ctx->ev, ctx->wedge_stream);
     HIPCHK(hipGetLastError());
@@ -523,6 +555,12 @@ glt_status glt_create(int device, size_t hbm_budget_bytes, glt_ctx** out) {
         glt_destroy(ctx);
         return GLT_E_DEVICE;
     }
+    // the device's glt_count_noalloc workspace (device current); a failure here only
+    // disables that entry point
+    if (scratch_address(device, &ctx->scratch) != hipSuccess) {
+        ctx->scratch = nullptr;
+        (void)hipGetLastError();
+    }
     if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess) {
         glt_destroy(ctx);
         return GLT_E_DEVICE;
@@ -571,8 +609,14 @@ int glt_last_timing(const glt_ctx* ctx, float* ms, int cap) {
     return k;
 }
 
-glt_status glt_count(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 out_global[17],
-                     uint64_t* out_per_edge, void* stream_) {
+}  // extern "C"
+
+namespace {
+
+// One graph: glt_count, or with noalloc glt_count_noalloc (device inputs only, the
+// workspace carved from the device's scratch array, no triangle records, no slab growth).
+glt_status count_one(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 out_global[17],
+                     uint64_t* out_per_edge, void* stream_, bool noalloc) {
     if (!ctx) return GLT_E_INVALID_ARG;
     ctx->err.clear();
     if (!g || !out_global) return fail(ctx, GLT_E_INVALID_ARG, "null graph or output");
@@ -596,9 +640,18 @@ glt_status glt_count(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 ou
     Dev d;
     Staging sg;
     const size_t need = carve(nullptr, n, m, rp64, host_in, host_out, 0, 0, d, sg);
-    rc = ensure_ws(ctx, need, st);
-    if (rc) return rc;
-    carve(ctx->ws, n, m, rp64, host_in, host_out, 0, 0, d, sg);
+    if (noalloc) {
+        if (host_in) return fail(ctx, GLT_E_INVALID_ARG, "glt_count_noalloc takes device inputs only");
+        if (!ctx->scratch) return fail(ctx, GLT_E_DEVICE, "no scratch address for device %d", ctx->device);
+        if (need > GLT_SCRATCH_BYTES)
+            return fail(ctx, GLT_E_UNSUPPORTED, "graph needs %zu bytes of workspace, the fixed scratch holds %zu",
+                        need, (size_t)GLT_SCRATCH_BYTES);
+        carve(ctx->scratch, n, m, rp64, false, false, 0, 0, d, sg);
+    } else {
+        rc = ensure_ws(ctx, need, st);
+        if (rc) return rc;
+        carve(ctx->ws, n, m, rp64, host_in, host_out, 0, 0, d, sg);
+    }
 
     const void* rp = g->row_ptr;
     const int* col = g->col;
@@ -621,7 +674,7 @@ glt_status glt_count(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 ou
             return fail(ctx, GLT_E_INVALID_ARG, "row_ptr[0]=%lld, row_ptr[n]=%lld, expected 0 and 2m=%lld",
                         (long long)r0, (long long)rn, (long long)S);
     }
-    rc = run_pipeline(ctx, d, rp, rp64, col, per_edge, pe_dev, st);
+    rc = run_pipeline(ctx, d, rp, rp64, col, per_edge, pe_dev, st, noalloc);
     if (rc) return rc;
     if (host_out)
         HIPCHK(hipMemcpyAsync(out_per_edge, sg.out, (size_t)13 * m * 8, hipMemcpyDeviceToHost, st));
@@ -649,6 +702,20 @@ glt_status glt_count(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 ou
         return fail(ctx, GLT_E_INTERNAL, "global combination failed: %s", why.c_str());
     store_x(X, out_global);
     return GLT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+glt_status glt_count(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 out_global[17],
+                     uint64_t* out_per_edge, void* stream) {
+    return count_one(ctx, g, flags, out_global, out_per_edge, stream, false);
+}
+
+glt_status glt_count_noalloc(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 out_global[17],
+                             uint64_t* out_per_edge, void* stream) {
+    return count_one(ctx, g, flags, out_global, out_per_edge, stream, true);
 }
 
 glt_status glt_count_batch(glt_ctx* ctx, const glt_batch* b, uint32_t flags, glt_u128* out, void* stream_) {
