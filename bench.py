@@ -541,15 +541,22 @@ def main():
     if args.order_study:
         # the ordering study (Section 4.3, Table 4) on the same graph: step time per order of the
         # workgroup work lists, each after one warm-up step
-        names = ["largest work first", "largest degree first", "ascending rank", "pseudo-random"]
+        names = ["largest work first", "largest degree first", "ascending rank", "pseudo-random",
+                 "largest volume first", "smallest degree first", "smallest volume first"]
         study = {}
         default_order = ctx.schedule()["list_order"]
         for order, name in enumerate(names):
-            ctx.set_schedule(list_order=order)
-            oms, _, Xo = time_graph(ctx, rpt, ct, n, per_edge, out, stream, args.steps, 1)
-            study[name] = round(oms, 3)
+            ctx.set_schedule(list_order=order, record_balance=0)
+            oms, otiming, Xo = time_graph(ctx, rpt, ct, n, per_edge, out, stream, args.steps, 1)
             assert Xo == X, "list order changed the counts"
-        ctx.set_schedule(list_order=default_order)
+            # one more step with the workgroup wedge class's entries timed (load balance)
+            ctx.set_schedule(record_balance=1)
+            time_graph(ctx, rpt, ct, n, per_edge, out, stream, 1, 0)
+            w = ctx.last_work()
+            study[name] = {"ms_per_step": round(oms, 3), "wedge_wg_ms": round(otiming["wedge_wg"], 3),
+                           "wedge_wg_tail_ms": round(w.get("wg_tail_ns", 0) / 1e6, 3),
+                           "wedge_wg_span_ms": round(w.get("wg_span_ns", 0) / 1e6, 3)}
+        ctx.set_schedule(list_order=default_order, record_balance=0)
         print(f"[bench] ordering study (ms/step): {study}", file=sys.stderr, flush=True)
     other = {}
     if args.compare_modes and args.steps > 0:

@@ -174,8 +174,12 @@ int glt_last_timing(const glt_ctx* ctx, float* ms, int cap);
  * work) counted by the wave class, [3] by the workgroup class, [4] out-list entries scanned
  * by the triangle pass (sum over oriented edges (a,b) of |N+(b)|), wavefront path, [5] the
  * same, workgroup path, [6] triangles found by the wavefront path, [7] by the workgroup
- * path, [8] wedges of the mid class, [9] of the huge class.  Returns the number of entries
- * written (<= cap, at most 10).  Used to state the algorithmic bytes of each kernel group.
+ * path, [8] wedges of the mid class, [9] of the huge class; with the schedule's
+ * record_balance, [10] the tail of the 4-cycle pass's workgroup class in nanoseconds (from
+ * the time 95 % of its list entries were done to the time the last one was) and [11] the
+ * span from the first entry done to the last (0 otherwise).  Returns the number of entries
+ * written (<= cap, at most 12).  Used to state the algorithmic bytes of each kernel group
+ * and the balance of the work lists (Section 4.3, Table 4's orderings).
  */
 int glt_last_work(const glt_ctx* ctx, uint64_t* out, int cap);
 
@@ -183,7 +187,7 @@ int glt_last_work(const glt_ctx* ctx, uint64_t* out, int cap);
  * Work schedule of a handle: how the counting passes split their work among size classes
  * (Section 4.3 splits edges by cost between workers; here vertices are split by their work
  * between wavefront and workgroup kernels).  Every schedule yields the same counts; only
- * the speed differs.  Defaults: 128, 2048, 16384, 4096, 1, 2^30, 0, 0.
+ * the speed differs.  Defaults: 128, 2048, 16384, 4096, 1, 2^30, 2, 2, 0.
  */
 typedef struct {
     int32_t wedge_wave_max;    /* 4-cycle pass: bottom vertices with at most this many wedges
@@ -208,7 +212,12 @@ typedef struct {
     int32_t list_order;        /* order of the workgroup work lists (Section 4.3's edge order,
                                   Table 4's ordering study): 0 largest work first, 1 largest
                                   degree first, 2 ascending rank (no sort; the default),
-                                  3 pseudo-random                                             */
+                                  3 pseudo-random, 4 largest volume first (volume: the sum
+                                  of the neighbours' degrees), 5 smallest degree first,
+                                  6 smallest volume first                                     */
+    int32_t record_balance;    /* 1: time when each entry of the 4-cycle pass's workgroup-class
+                                  list is done (one clock read per entry) and report the
+                                  spread in glt_last_work entries [10], [11]; 0: off         */
 } glt_schedule;
 
 /* The handle's current schedule. */

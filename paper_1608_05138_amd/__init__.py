@@ -69,11 +69,12 @@ class glt_schedule(ctypes.Structure):
     _fields_ = [("wedge_wave_max", ctypes.c_int32), ("wedge_mid_max", ctypes.c_int32),
                 ("wedge_dense", ctypes.c_int32), ("wedge_range_limit", ctypes.c_int32),
                 ("tri_records", ctypes.c_int32), ("wedge_wg_max", ctypes.c_int32),
-                ("wedge_stream", ctypes.c_int32), ("list_order", ctypes.c_int32)]
+                ("wedge_stream", ctypes.c_int32), ("list_order", ctypes.c_int32),
+                ("record_balance", ctypes.c_int32)]
 
 
 SCHEDULE_KEYS = ["wedge_wave_max", "wedge_mid_max", "wedge_dense", "wedge_range_limit", "tri_records",
-                 "wedge_wg_max", "wedge_stream", "list_order"]
+                 "wedge_wg_max", "wedge_stream", "list_order", "record_balance"]
 
 
 class glt_server_opts(ctypes.Structure):
@@ -183,7 +184,7 @@ class Context:
     TIMING_KEYS = ["prep", "tri_wave", "tri_wg", "gather_wave", "gather_wg", "wedge_wave", "wedge_mid",
                    "wedge_wg", "wedge_huge", "combine", "total"]
     WORK_KEYS = ["n", "m", "wedges_wave", "wedges_wg", "tri_list_wave", "tri_list_wg", "triangles_wave",
-                 "triangles_wg", "wedges_mid", "wedges_huge"]
+                 "triangles_wg", "wedges_mid", "wedges_huge", "wg_tail_ns", "wg_span_ns"]
 
     def last_timing(self):
         """dict of kernel-group times (ms) of the last count (HIP events on the stream each

@@ -41,7 +41,10 @@ struct glt_ctx {
     int num_cu = 256;
     int wedge_limit = 0;
     int wedge_dense = 0;
-    uint64_t work[2 + NWORK] = {};     // n, m, then the device work counters
+    uint64_t work[2 + NWORK + 2] = {}; // n, m, the device work counters, the workgroup class's tail and span
+    int record_balance = 0;            // schedule: time the entries of the workgroup wedge class
+    int bal_count = 0;                 // entries of that list in the last call
+    int clock_khz = 100000;            // device wall-clock rate
     void* stage = nullptr;             // device staging of host batch inputs
     size_t stage_bytes = 0;
     void* trec = nullptr;              // triangle records (grown on demand)
@@ -56,6 +59,7 @@ struct glt_ctx {
                                        // second stream filling idle CUs, skipping the sort measured
                                        // fastest (Chung-Lu 18.40 vs 18.67 ms, R-MAT 678 vs 688 ms)
     int last_mode = 0;                 // the stream mode the last call's timing was taken in
+    int wide_degree = 0;               // GLT_WIDE_DEGREE (tests): widen edges from this lower-endpoint degree
     void* slab = nullptr;              // larger global slab for the highest out-degrees (grown on demand)
     size_t slab_bytes = 0;
     hipEvent_t ev_null = nullptr;      // orders the handle's stream after the legacy default stream
@@ -126,7 +130,7 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
     const int64_t big = S > n ? S : n;
     d.n = n; d.m = m; d.S = (int)S;
     d.err = c.take<int>(ERR_WORDS);
-    d.counts = c.take<int>(TB_N + WB_N + TB_N);
+    d.counts = c.take<int>(CNT_WORDS);
     d.work = c.take<u64>(NWORK);
     d.final_sums = c.take<u64>(2 * 13);
     d.deg = c.take<int>(n);
@@ -353,35 +357,35 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
     d.list_order = ctx->list_order;
     d.wedge_limit = ctx->wedge_limit;
     d.wedge_dense = ctx->wedge_dense;
+    d.wide_degree = ctx->wide_degree;
+    d.tstamp = ctx->record_balance ? d.key1 : nullptr;   // key1 is free once preprocessing is done
     d.per_edge = per_edge ? 1 : 0;
     HIPCHK(hipEventRecord(ctx->ev[0], st));
     glt_prep_validate(d, rp, rp64, col, st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(ctx->hbuf, d.err, (2 + RS_N) * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    int hc[TB_N + WB_N + TB_N + 1];
+    int hc[CNT_WORDS];
     int vinfo[1 + RS_N];
     {
         const int e = ((int*)ctx->hbuf)[0];
         if (e & ERR_RANGE) return fail(ctx, GLT_E_INVALID_ARG, "row offsets not monotone or neighbour id out of range");
         if (e & ERR_SELF) return fail(ctx, GLT_E_NOT_SIMPLE, "self-loop");
         for (int i = 0; i < 1 + RS_N; i++) vinfo[i] = ((int*)ctx->hbuf)[1 + i];   // max degree, row classes
-        // K <= C(dmax,2), P <= dmax^2, sum over T of t(w,u)+t(w,v) <= 2 dmax^2, sum of d_w <= dmax^2
-        d.acc32 = (vinfo[0] <= 46340) ? 1 : 0;
     }
     glt_prep_build(d, rp, rp64, col, st, vinfo);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(ctx->hbuf, d.err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 8, d.optr + n, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 16, d.counts, sizeof(int) * (TB_N + WB_N + TB_N), hipMemcpyDeviceToHost, st));
-    if (n > 0) HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 64, d.toff + n, sizeof(u64), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 16, d.counts, sizeof(int) * CNT_WORDS, hipMemcpyDeviceToHost, st));
+    if (n > 0) HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 128, d.toff + n, sizeof(u64), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     {
         const int e = ((int*)ctx->hbuf)[0];
         const int up = n > 0 ? ((int*)ctx->hbuf)[2] : 0;
         if (e & ERR_DUP) return fail(ctx, GLT_E_NOT_SIMPLE, "duplicate entry");
         if ((e & ERR_ASYM) || up != m) return fail(ctx, GLT_E_NOT_SYMMETRIC, "adjacency is not symmetric");
-        memcpy(hc, (char*)ctx->hbuf + 16, sizeof(int) * (TB_N + WB_N + TB_N));
+        memcpy(hc, (char*)ctx->hbuf + 16, sizeof(int) * CNT_WORDS);
         if (hc[TB_N + WB_N + TB_GLOBAL] > glt_max_out_degree())
             return fail(ctx, GLT_E_UNSUPPORTED, "out-degree %d in the degree order exceeds %d",
                         hc[TB_N + WB_N + TB_GLOBAL], glt_max_out_degree());
@@ -389,9 +393,14 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
     if (noalloc) {
         d.trec = nullptr;   // the passes re-scan the out-lists; the carved 32 MiB slab serves
     } else {
-        d.trec = ensure_trec(ctx, n > 0 ? *(u64*)((char*)ctx->hbuf + 64) : 0, st);
+        d.trec = ensure_trec(ctx, n > 0 ? *(u64*)((char*)ctx->hbuf + 128) : 0, st);
         grow_slab(ctx, d, hc[TB_GLOBAL], hc[TB_N + WB_N + TB_GLOBAL], st);
     }
+    // per-edge accumulators: 32-bit kernels when no edge is wide (or no per-edge output),
+    // else 64-bit in-kernel sums with the narrow / wide storage split at kw (EdgeArrays)
+    ctx->bal_count = ctx->record_balance ? hc[TB_N + WB_BLK] : 0;
+    wide_arrays(d.e, m, hc[CNT_KW]);
+    d.acc32 = (!per_edge || hc[CNT_KW] >= m) ? 1 : 0;
     ctx->last_mode = ctx->wedge_stream;
     glt_count_passes(d, per_edge ? 1 : 0, hc, pe_dev, st, ctx->side, ctx->ev, ctx->wedge_stream);
     HIPCHK(hipGetLastError());
@@ -416,6 +425,24 @@ void record_timing(glt_ctx* ctx) {
         (void)hipEventElapsedTime(&ms, ctx->ev[b0], ctx->ev[be[i][1]]);
         ctx->timing[i] = ms;
     }
+}
+
+// Load-balance summary of the last call's workgroup wedge class (record_balance): from the
+// wall-clock times at which its list entries were done, the tail (95th percentile to the
+// last) and the span (first to last), in nanoseconds, into work[2 + NWORK], work[3 + NWORK].
+glt_status balance_summary(glt_ctx* ctx, const u64* tstamp, hipStream_t st) {
+    ctx->work[2 + NWORK] = ctx->work[3 + NWORK] = 0;
+    const int c = ctx->bal_count;
+    if (c <= 0 || !tstamp) return GLT_OK;
+    std::vector<u64> t((size_t)c);
+    HIPCHK(hipMemcpyAsync(t.data(), tstamp, (size_t)c * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::sort(t.begin(), t.end());
+    const double ns = 1e6 / (double)ctx->clock_khz;
+    const u64 p95 = t[(size_t)((int64_t)(c - 1) * 95 / 100)];
+    ctx->work[2 + NWORK] = (uint64_t)((double)(t.back() - p95) * ns);
+    ctx->work[3 + NWORK] = (uint64_t)((double)(t.back() - t.front()) * ns);
+    return GLT_OK;
 }
 
 // The stream a call runs on.  With no stream given, the handle's own (non-blocking) stream,
@@ -474,6 +501,8 @@ glt_status glt_run_batch_ptrs(glt_ctx* ctx, int64_t B, const int64_t* vb, const 
     ctx->work[1] = (uint64_t)m;
     for (int i = 0; i < NWORK; i++) ctx->work[2 + i] = ((u64*)((char*)ctx->hbuf + 1032))[i];
     record_timing(ctx);
+    rc = balance_summary(ctx, d.tstamp, st);
+    if (rc) return rc;
     for (int64_t g = 0; g < B; g++) {
         i128 C[17];
         unpack_c(&parts[(size_t)g * 26], C);
@@ -529,6 +558,7 @@ glt_status glt_create(int device, size_t hbm_budget_bytes, glt_ctx** out) {
         int v = atoi(e);
         if (v >= 1 && v < ctx->wedge_limit) ctx->wedge_limit = v;
     }
+    if (const char* e = getenv("GLT_WIDE_DEGREE")) ctx->wide_degree = atoi(e) > 0 ? atoi(e) : 0;
     ctx->wedge_dense = glt_wedge_dense();
     if (const char* e = getenv("GLT_WEDGE_DENSE")) {
         int v = atoi(e);
@@ -542,6 +572,9 @@ glt_status glt_create(int device, size_t hbm_budget_bytes, glt_ctx** out) {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
             ctx->num_cu = cus;
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+            ctx->clock_khz = khz;
     }
     {
         // triangle records may take up to a quarter of the device's memory (0 disables them)
@@ -597,7 +630,7 @@ const char* glt_last_error(const glt_ctx* ctx) { return ctx ? ctx->err.c_str() :
 
 int glt_last_work(const glt_ctx* ctx, uint64_t* out, int cap) {
     if (!ctx || !out) return 0;
-    int k = cap < 2 + NWORK ? cap : 2 + NWORK;
+    int k = cap < 4 + NWORK ? cap : 4 + NWORK;
     for (int i = 0; i < k; i++) out[i] = ctx->work[i];
     return k;
 }
@@ -691,6 +724,8 @@ glt_status count_one(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 ou
     ctx->work[1] = (uint64_t)m;
     for (int i = 0; i < NWORK; i++) ctx->work[2 + i] = n > 0 ? ((u64*)((char*)ctx->hbuf + 1032))[i] : 0;
     record_timing(ctx);
+    rc = balance_summary(ctx, d.tstamp, st);
+    if (rc) return rc;
     i128 C[17];
     unpack_c(ctx->hbuf, C);
     const u64* gs = (const u64*)((char*)ctx->hbuf + 512);
@@ -784,6 +819,7 @@ glt_status glt_get_schedule(const glt_ctx* ctx, glt_schedule* out) {
     out->wedge_dense = ctx->wedge_dense;
     out->wedge_range_limit = ctx->wedge_limit;
     out->tri_records = ctx->tri_records;
+    out->record_balance = ctx->record_balance;
     return GLT_OK;
 }
 
@@ -801,7 +837,10 @@ glt_status glt_set_schedule(glt_ctx* ctx, const glt_schedule* s) {
         return fail(ctx, GLT_E_INVALID_ARG, "wedge_range_limit must be in [1, %d]", glt_wedge_table() / 2);
     if (s->tri_records != 0 && s->tri_records != 1) return fail(ctx, GLT_E_INVALID_ARG, "tri_records must be 0 or 1");
     if (s->wedge_stream < 0 || s->wedge_stream > 2) return fail(ctx, GLT_E_INVALID_ARG, "wedge_stream must be 0, 1 or 2");
-    if (s->list_order < 0 || s->list_order > 3) return fail(ctx, GLT_E_INVALID_ARG, "list_order must be in [0, 3]");
+    if (s->record_balance != 0 && s->record_balance != 1)
+        return fail(ctx, GLT_E_INVALID_ARG, "record_balance must be 0 or 1");
+    if (s->list_order < 0 || s->list_order >= LO_N)
+        return fail(ctx, GLT_E_INVALID_ARG, "list_order must be in [0, %d]", LO_N - 1);
     ctx->wedge_wave_max = s->wedge_wave_max;
     ctx->wedge_mid_max = s->wedge_mid_max;
     ctx->wedge_wg_max = s->wedge_wg_max;
@@ -810,6 +849,7 @@ glt_status glt_set_schedule(glt_ctx* ctx, const glt_schedule* s) {
     ctx->tri_records = s->tri_records;
     ctx->wedge_stream = s->wedge_stream;
     ctx->list_order = s->list_order;
+    ctx->record_balance = s->record_balance;
     return GLT_OK;
 }
 

@@ -30,40 +30,44 @@
 // are first summed across the wavefront (DPP) before one atomic per run.
 #include "glt_internal.h"
 
-// Per-edge accumulators K, P, g, sig are 64-bit, or 32-bit when the maximum degree bounds
-// every value below 2^32 (the host picks AT); the buffers are sized for 64-bit either way.
-template <typename AT>
-__device__ __forceinline__ void acc_add(u64* base, int64_t k, u64 v) {
-    atomicAdd(&((AT*)base)[k], (AT)v);
+// Per-edge accumulators (EdgeArrays): 32-bit words for narrow edges (k < kw), 64-bit words
+// for wide ones.  With AT = u32 (no wide edge) the 64-bit side is compiled out.  Every credit
+// of a narrow edge is at most its final value, so it fits 32 bits; sums that kernels form
+// in AT before crediting are exact modulo 2^32, and so is the narrow word they land in.
+enum { ACC_K = 0, ACC_P = 1 };
+template <typename AT, int WHICH>
+__device__ __forceinline__ void acc_add(const EdgeArrays& e, int64_t k, u64 v) {
+    if (sizeof(AT) == 8 && k >= e.kw) atomicAdd(&(WHICH == ACC_K ? e.Kw : e.Pw)[k - e.kw], v);
+    else atomicAdd(&((u32*)(WHICH == ACC_K ? e.K : e.P))[k], (u32)v);
 }
-template <typename AT>
-__device__ __forceinline__ u64 acc_get(const u64* base, int64_t k) {
-    return (u64)((const AT*)base)[k];
+template <typename AT, int WHICH>
+__device__ __forceinline__ u64 acc_get(const EdgeArrays& e, int64_t k) {
+    if (sizeof(AT) == 8 && k >= e.kw) return (WHICH == ACC_K ? e.Kw : e.Pw)[k - e.kw];
+    return (u64)((const u32*)(WHICH == ACC_K ? e.K : e.P))[k];
 }
 
-// g and sigma of an edge: with 32-bit accumulators the pair shares one 64-bit word of the g
-// buffer (g low, sigma high), so both move with one atomic; each half stays below 2^32 (the
-// host picks 32 bits only when every such count does), so no carry crosses the halves.
-// With 64-bit accumulators they are separate arrays.
+// g and sigma of an edge: for a narrow edge the pair shares one 64-bit word of the g buffer
+// (g low, sigma high), so both move with one atomic; each half stays below 2^32, so no carry
+// crosses the halves.  A wide edge has them in separate 64-bit words.
 template <typename AT>
-__device__ __forceinline__ void gsig_add(EdgeArrays& e, int64_t k, u64 g, u64 sig) {
-    if constexpr (sizeof(AT) == 4) {
-        const u64 v = (sig << 32) | g;
-        if (v) atomicAdd(&e.g[k], v);
+__device__ __forceinline__ void gsig_add(const EdgeArrays& e, int64_t k, u64 g, u64 sig) {
+    if (sizeof(AT) == 8 && k >= e.kw) {
+        if (g) atomicAdd(&e.gw[k - e.kw], g);
+        if (sig) atomicAdd(&e.sw[k - e.kw], sig);
     } else {
-        if (g) atomicAdd(&e.g[k], g);
-        if (sig) atomicAdd(&e.sig[k], sig);
+        const u64 v = (sig << 32) | (g & 0xffffffffull);
+        if (v) atomicAdd(&e.g[k], v);
     }
 }
 template <typename AT>
 __device__ __forceinline__ void gsig_get(const EdgeArrays& e, int64_t k, u64& g, u64& sig) {
-    if constexpr (sizeof(AT) == 4) {
+    if (sizeof(AT) == 8 && k >= e.kw) {
+        g = e.gw[k - e.kw];
+        sig = e.sw[k - e.kw];
+    } else {
         const u64 v = e.g[k];
         g = v & 0xffffffffull;
         sig = v >> 32;
-    } else {
-        g = e.g[k];
-        sig = e.sig[k];
     }
 }
 
@@ -319,7 +323,7 @@ __global__ __launch_bounds__(TW_THREADS) void k_tri_wave(const int* __restrict__
                 tk = (u64)__popcll(sM[w][ri] & sM[w][rj]);
                 atomicAdd(&e.t[k], 1u);
                 if (PE && tk) {
-                    acc_add<AT>(e.K, k, tk);
+                    acc_add<AT, ACC_K>(e, k, tk);
                     atomicAdd(&sK[w][rj], tk);
                 }
                 k4 += tk;
@@ -346,7 +350,7 @@ __global__ __launch_bounds__(TW_THREADS) void k_tri_wave(const int* __restrict__
                         const u64 tk = (u64)__popcll(sM[w][i] & sM[w][j]);
                         atomicAdd(&e.t[k], 1u);
                         if (PE && tk) {
-                            acc_add<AT>(e.K, k, tk);
+                            acc_add<AT, ACC_K>(e, k, tk);
                             atomicAdd(&sK[w][i], tk);
                             atomicAdd(&sK[w][j], tk);
                         }
@@ -362,7 +366,7 @@ __global__ __launch_bounds__(TW_THREADS) void k_tri_wave(const int* __restrict__
         if (tl) atomicAdd(&e.t[o0 + l], tl);
         if (PE) {
             const u64 kl = sK[w][l] >> 1;
-            if (kl) acc_add<AT>(e.K, o0 + l, kl);
+            if (kl) acc_add<AT, ACC_K>(e, o0 + l, kl);
         }
     }
     k4 = wave_sum(k4);
@@ -395,17 +399,17 @@ __device__ __forceinline__ u64 row_and_count(const u32* M, int W, int i, int j) 
     return c;
 }
 
-template <bool PE, bool GM, bool REC, typename AT>
-__global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ list, int nlist, int smax,
+template <bool PE, bool GM, bool REC, typename AT, int NT>
+__global__ __launch_bounds__(NT, 8) void k_tri_blk(const int* __restrict__ list, int nlist, int smax,
                                                        const int* __restrict__ optr, const int* __restrict__ ocol,
                                                        EdgeArrays e, u64* __restrict__ gsum,
                                                        u32* __restrict__ gscratch, const int* __restrict__ ngid,
                                                        u64* __restrict__ trec, const u64* __restrict__ toff,
                                                        int* __restrict__ tcnt) {
-    constexpr int SPOS = RunTables<TB_THREADS>::SPOS;
+    constexpr int SPOS = RunTables<NT>::SPOS;
     extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
-    __shared__ RunTables<TB_THREADS> rt;
-    __shared__ u64 sRed[TB_THREADS / GLT_WAVE];
+    __shared__ RunTables<NT> rt;
+    __shared__ u64 sRed[NT / GLT_WAVE];
     __shared__ int sNrec;
     u64* sK = (u64*)dyn;
     int* sS = (int*)(sK + smax);
@@ -422,10 +426,10 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
     const int o0 = optr[a];
     const int s = optr[a + 1] - o0;
     const int W = tri_row_words(s, GM);
-    for (int q = tid; q < HT; q += TB_THREADS) hk[q] = -1;
+    for (int q = tid; q < HT; q += NT) hk[q] = -1;
     __syncthreads();
     // S, its out-list offsets and lengths; S into the hash
-    for (int i = tid; i < s; i += TB_THREADS) {
+    for (int i = tid; i < s; i += NT) {
         const int b = ocol[o0 + i];
         const int ob = optr[b];
         sS[i] = b; sOb[i] = ob; sLen[i] = optr[b + 1] - ob; sK[i] = 0;
@@ -433,25 +437,25 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
         while (atomicCAS(&hk[h], -1, b) != -1) h = (h + 1) & hmask;
         hp[h] = (unsigned short)i;
     }
-    for (int q = tid; q < s * W; q += TB_THREADS) M[q] = 0;
+    for (int q = tid; q < s * W; q += NT) M[q] = 0;
     if (tid == 0) sNrec = 0;
     __syncthreads();
     u64* rec = REC ? trec + toff[a] : nullptr;
     const u64 lt = (glt_lane() == 0) ? 0ull : ((~0ull) >> (GLT_WAVE - glt_lane()));
     // scan the out-lists of b_c0 .. b_{c0+255}, one chunk of runs at a time
-    for (int c0 = 0; c0 < s; c0 += TB_THREADS) {
+    for (int c0 = 0; c0 < s; c0 += NT) {
         const int len = (c0 + tid < s) ? sLen[c0 + tid] : 0;
         const int ob = (c0 + tid < s) ? sOb[c0 + tid] : 0;
         int pre, carry;
-        const int total = runs_begin<TB_THREADS>(rt, len, ob, pre, carry);
+        const int total = runs_begin<NT>(rt, len, ob, pre, carry);
         for (int sb0 = 0; sb0 < total; sb0 += SPOS) {
-            if (sb0 > 0) runs_next<TB_THREADS>(rt, sb0, len, pre, carry);
+            if (sb0 > 0) runs_next<NT>(rt, sb0, len, pre, carry);
             const int se = min(total, sb0 + SPOS);
-            for (int q0 = sb0; q0 < se; q0 += TRI_ILP * TB_THREADS) {
+            for (int q0 = sb0; q0 < se; q0 += TRI_ILP * NT) {
                 int is[TRI_ILP], ks[TRI_ILP], xs[TRI_ILP];
 #pragma unroll
                 for (int u = 0; u < TRI_ILP; u++) {
-                    const int q = q0 + u * TB_THREADS + tid;
+                    const int q = q0 + u * NT + tid;
                     xs[u] = -1;
                     is[u] = 0;
                     ks[u] = 0;
@@ -492,11 +496,11 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
     if (REC) {
         const int nrec = sNrec;
         constexpr int CR = 4;   // records per thread and round, loaded together
-        for (int r0 = 0; r0 < nrec; r0 += CR * TB_THREADS) {
+        for (int r0 = 0; r0 < nrec; r0 += CR * NT) {
             int ri[CR], rj[CR], rk[CR];
 #pragma unroll
             for (int u = 0; u < CR; u++) {
-                const int r = r0 + u * TB_THREADS + tid;
+                const int r = r0 + u * NT + tid;
                 ri[u] = 0x7fffffff; rj[u] = 0; rk[u] = -1;
                 if (r < nrec) tri_unrec(rec[r], ri[u], rj[u], rk[u]);
             }
@@ -507,7 +511,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
                     tk = row_and_count<GM>(M, W, ri[u], rj[u]);
                     atomicAdd(&e.t[rk[u]], 1u);
                     if (PE && tk) {
-                        acc_add<AT>(e.K, rk[u], tk);
+                        acc_add<AT, ACC_K>(e, rk[u], tk);
                         atomicAdd(&sK[rj[u]], tk);
                     }
                     k4 += tk;
@@ -521,15 +525,15 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
         }
         if (tid == 0) tcnt[a] = nrec;
     } else {
-        for (int c0 = 0; c0 < s; c0 += TB_THREADS) {
+        for (int c0 = 0; c0 < s; c0 += NT) {
             const int len = (c0 + tid < s) ? sLen[c0 + tid] : 0;
             const int ob = (c0 + tid < s) ? sOb[c0 + tid] : 0;
             int pre, carry;
-            const int total = runs_begin<TB_THREADS>(rt, len, ob, pre, carry);
+            const int total = runs_begin<NT>(rt, len, ob, pre, carry);
             for (int sb0 = 0; sb0 < total; sb0 += SPOS) {
-                if (sb0 > 0) runs_next<TB_THREADS>(rt, sb0, len, pre, carry);
+                if (sb0 > 0) runs_next<NT>(rt, sb0, len, pre, carry);
                 const int se = min(total, sb0 + SPOS);
-                for (int q = sb0 + tid; q < se; q += TB_THREADS) {
+                for (int q = sb0 + tid; q < se; q += NT) {
                     const int2 r = runs_at(rt, q - sb0);
                     const int i = c0 + r.y, k = q + r.x;
                     const int j = bh_find(hk, hp, hmask, ocol[k]);
@@ -537,7 +541,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
                         const u64 tk = row_and_count<GM>(M, W, i, j);
                         atomicAdd(&e.t[k], 1u);
                         if (PE && tk) {
-                            acc_add<AT>(e.K, k, tk);
+                            acc_add<AT, ACC_K>(e, k, tk);
                             atomicAdd(&sK[i], tk);
                             atomicAdd(&sK[j], tk);
                         }
@@ -550,14 +554,14 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
     }
     __syncthreads();
     u64 ntri = 0;
-    for (int i = tid; i < s; i += TB_THREADS) {
+    for (int i = tid; i < s; i += NT) {
         u32 tl = 0;
         for (int wd = 0; wd < W; wd++) tl += (u32)__popc(M[i * W + wd]);
         ntri += tl;
         if (tl) atomicAdd(&e.t[o0 + i], tl);
         if (PE) {
             const u64 kl = sK[i] >> 1;
-            if (kl) acc_add<AT>(e.K, o0 + i, kl);
+            if (kl) acc_add<AT, ACC_K>(e, o0 + i, kl);
         }
     }
     k4 = wave_sum(k4);
@@ -565,7 +569,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tri_blk(const int* __restrict__ 
     __syncthreads();
     if (tid == 0) {
         u64 tot = 0;
-        for (int q = 0; q < TB_THREADS / GLT_WAVE; q++) tot += sRed[q];
+        for (int q = 0; q < NT / GLT_WAVE; q++) tot += sRed[q];
         if (tot) atomicAdd(&gsum[gslot(ngid, a) * NSUMS + S_K4x3], tot);
     }
     ntri = wave_sum(ntri) / 2;
@@ -900,7 +904,8 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                                                  u64* __restrict__ gsum, const int* __restrict__ ngid,
                                                  const int64_t* __restrict__ gvb, int* __restrict__ err,
                                                  const int* __restrict__ dcount, int* __restrict__ defer_list,
-                                                 int* __restrict__ defer_cnt, u64* __restrict__ defer_work) {
+                                                 int* __restrict__ defer_cnt, u64* __restrict__ defer_work,
+                                                 u64* __restrict__ tstamp) {
     static_assert(T == GLT_WAVE || G == 1, "multi-wave groups own the whole block");
     static_assert(HT % 4 == 0 && DW % 4 == 0 && (HT & (HT - 1)) == 0, "table sizes");
     constexpr int DWA = DW > 0 ? DW : 8;
@@ -1098,7 +1103,7 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                             const int l = glt_lane();
                             const bool first = (F >> l) & 1;
                             const bool last = (l == GLT_WAVE - 1) || (((F >> l) >> 1) & 1);
-                            if (c) acc_add<AT>(e.P, ks[j], (u64)c);   // top edge (w, x)
+                            if (c) acc_add<AT, ACC_P>(e, ks[j], (u64)c);   // top edge (w, x)
                             // bottom edge (y, w): with P the wave's inclusive prefix of c, a
                             // source's sum is P(last lane) - P(first lane - 1): its first lane
                             // subtracts its exclusive prefix and its last lane adds its inclusive
@@ -1110,7 +1115,7 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                     }
                 }
                 grp_sync<T>();
-                if (s < re && sb[tid]) acc_add<AT>(e.P, s2k[s], (u64)sb[tid]);
+                if (s < re && sb[tid]) acc_add<AT, ACC_P>(e, s2k[s], (u64)sb[tid]);
                 grp_sync<T>();
             }
         }
@@ -1127,6 +1132,8 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
     }
     if (NR) c4 >>= 1;
     if (tid == 0 && c4) atomicAdd(&gsum[gslot(ngid, y) * NSUMS + S_NC4], c4);
+    // load-balance measurement (when asked): the wall clock at which this list entry is done
+    if (tstamp && tid == 0) tstamp[item] = (u64)wall_clock64();
     }
 }
 
@@ -1257,8 +1264,8 @@ __global__ __launch_bounds__(CB_THREADS) void k_combine(const int* __restrict__ 
             du = ndeg[u]; dv = ndeg[v];
             t = e.t[k];
             if (PE) {
-                Kk = (int64_t)acc_get<AT>(e.K, k);
-                Pk = (int64_t)acc_get<AT>(e.P, k);
+                Kk = (int64_t)acc_get<AT, ACC_K>(e, k);
+                Pk = (int64_t)acc_get<AT, ACC_P>(e, k);
                 gsig_get<AT>(e, k, gk, sk);
                 triu = (int64_t)tri[u]; triv = (int64_t)tri[v]; sdu = (int64_t)sdeg[u]; sdv = (int64_t)sdeg[v];
             }
@@ -1452,10 +1459,12 @@ __device__ __forceinline__ u32 work_code(u64 w) {
 }
 
 // order: LO_WORK sorts by the work (mode 0: wedges of y, mode 1: out-degree of x), LO_DEGREE
-// by the vertex's degree, both largest first; LO_RANDOM by a hash of the vertex.
+// by the vertex's degree, LO_VOLUME by its volume (vol), all largest first; LO_DEGREE_INV and
+// LO_VOLUME_INV smallest first; LO_RANDOM by a hash of the vertex.
 __global__ void k_work_keys(const int* __restrict__ list, int nlist, int mode, int order,
                             const u64* __restrict__ wcnt, const int* __restrict__ optr,
-                            const int* __restrict__ ndeg, u64* __restrict__ keys, u32* __restrict__ vals) {
+                            const int* __restrict__ ndeg, const u64* __restrict__ vol,
+                            u64* __restrict__ keys, u32* __restrict__ vals) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nlist) return;
     const int x = list[i];
@@ -1463,11 +1472,22 @@ __global__ void k_work_keys(const int* __restrict__ list, int nlist, int mode, i
     if (order == LO_RANDOM) {
         key = ((u32)x * 2654435761u) >> 16;
     } else {
-        const u64 w = order == LO_DEGREE ? (u64)ndeg[x] : mode == 0 ? wcnt[x] : (u64)(optr[x + 1] - optr[x]);
-        key = 0xffffu - work_code(w);   // ascending sort = largest first
+        const bool deg = order == LO_DEGREE || order == LO_DEGREE_INV;
+        const bool vl = order == LO_VOLUME || order == LO_VOLUME_INV;
+        const u64 w = deg ? (u64)ndeg[x] : vl ? vol[x] : mode == 0 ? wcnt[x] : (u64)(optr[x + 1] - optr[x]);
+        const bool inv = order == LO_DEGREE_INV || order == LO_VOLUME_INV;
+        key = inv ? work_code(w) : 0xffffu - work_code(w);   // ascending sort
     }
     keys[i] = (u64)key;
     vals[i] = (u32)x;
+}
+
+// Volume of every relabelled vertex, vol(x) = sum of its neighbours' degrees (the vertex form
+// of Table 4's vol(e)), for the volume orders of the work lists.
+__global__ __launch_bounds__(256) void k_volume(const int* __restrict__ nsrow, const int* __restrict__ ncol,
+                                                const int* __restrict__ ndeg, int64_t S, u64* __restrict__ vol) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s < S) atomicAdd(&vol[nsrow[s]], (u64)ndeg[ncol[s]]);
 }
 
 __global__ void k_copy_list(const u32* __restrict__ vals, int nlist, int* __restrict__ list) {
@@ -1479,7 +1499,7 @@ static void sort_heaviest_first(const Dev& d, int* list, int nlist, int mode, hi
     if (nlist < 2 || d.list_order == LO_NONE) return;   // LO_NONE: the bucketing order (ascending rank)
     const unsigned g = (unsigned)((nlist + 255) / 256);
     hipLaunchKernelGGL(k_work_keys, dim3(g), dim3(256), 0, st, list, nlist, mode, d.list_order, d.wcnt, d.optr,
-                       d.ndeg, d.key0, d.val0);
+                       d.ndeg, d.sdeg, d.key0, d.val0);
     const int cur = launch_radix_sort(d.key0, d.val0, d.key1, d.val1, nlist, 16, d.rs_counts, d.rs_tmp, st);
     hipLaunchKernelGGL(k_copy_list, dim3(g), dim3(256), 0, st, cur ? d.val1 : d.val0, nlist, list);
 }
@@ -1552,15 +1572,26 @@ static void launch_tri_wave(const Dev& d, const int* lst, int c, hipStream_t st)
                            d.ocol, d.e, d.gsum, d.ngid, d.trec, d.toff, d.tcnt);
 }
 
-template <bool PE, bool GM, typename AT>
-static void launch_tri_blk(const Dev& d, const int* lst, int c, int smax, hipStream_t st) {
+// Threads per workgroup of the triangle pass: 256 for out-degrees up to 256 (small LDS
+// tables, many workgroups per CU), TB_BIG_THREADS above, where the rows' LDS allows only a
+// few workgroups per CU and larger groups keep more out-list loads in flight.
+#ifndef TB_BIG_THREADS
+#define TB_BIG_THREADS 1024
+#endif
+template <bool PE, bool GM, typename AT, int NT>
+static void launch_tri_blk_nt(const Dev& d, const int* lst, int c, int smax, hipStream_t st) {
     const size_t lds = tri_blk_lds(smax, GM);
     if (d.trec)
-        hipLaunchKernelGGL((k_tri_blk<PE, GM, true, AT>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax, d.optr,
+        hipLaunchKernelGGL((k_tri_blk<PE, GM, true, AT, NT>), dim3(c), dim3(NT), lds, st, lst, c, smax, d.optr,
                            d.ocol, d.e, d.gsum, d.gscratch, d.ngid, d.trec, d.toff, d.tcnt);
     else
-        hipLaunchKernelGGL((k_tri_blk<PE, GM, false, AT>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax, d.optr,
+        hipLaunchKernelGGL((k_tri_blk<PE, GM, false, AT, NT>), dim3(c), dim3(NT), lds, st, lst, c, smax, d.optr,
                            d.ocol, d.e, d.gsum, d.gscratch, d.ngid, d.trec, d.toff, d.tcnt);
+}
+template <bool PE, bool GM, typename AT>
+static void launch_tri_blk(const Dev& d, const int* lst, int c, int smax, hipStream_t st) {
+    if (smax <= 256) launch_tri_blk_nt<PE, GM, AT, TB_THREADS>(d, lst, c, smax, st);
+    else launch_tri_blk_nt<PE, GM, AT, TB_BIG_THREADS>(d, lst, c, smax, st);
 }
 
 template <bool GM, typename AT>
@@ -1587,7 +1618,7 @@ static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st, int res
                        d.wlist + (int64_t)bkt * d.n, cnt, d.n, limit, d.wedge_dense, d.nrp, d.wb, d.ocol,
                        d.s2k, d.wcnt, d.e, d.gsum, d.ngid, d.gvb, d.err, resident > 0 ? counts + bkt : nullptr,
                        defer >= 0 ? d.wlist + (int64_t)defer * d.n : nullptr, defer >= 0 ? counts + defer : nullptr,
-                       defer >= 0 ? d.wspread + 6 : nullptr);
+                       defer >= 0 ? d.wspread + 6 : nullptr, bkt == WB_BLK ? d.tstamp : nullptr);
 }
 
 // Events of one call (all recorded, also used to fork and join; the stream modes are
@@ -1669,6 +1700,13 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
     const int* tl = d.tlist;
     const int* cnt = hc;                  // TB_N counts, WB_N counts, TB_N maxima
     const EdgeArrays e = d.e;
+    if (d.list_order == LO_VOLUME || d.list_order == LO_VOLUME_INV) {
+        // volumes for the sort keys (sdeg is recomputed by the vertex pass later)
+        launch_fill<u64>(d.sdeg, n, 0ull, st);
+        if (m > 0)
+            hipLaunchKernelGGL(k_volume, dim3(cdiv(2 * (int64_t)m, 256)), dim3(256), 0, st, d.nsrow, d.ncol, d.ndeg,
+                               2 * (int64_t)m, d.sdeg);
+    }
     for (int bkt = TB_BLK1; bkt <= TB_GLOBAL; bkt++) sort_heaviest_first(d, d.tlist + (int64_t)bkt * n, cnt[bkt], 1, st);
     for (int bkt = WB_MID; bkt <= WB_HUGE; bkt++) sort_heaviest_first(d, d.wlist + (int64_t)bkt * n, hc[TB_N + bkt], 0, st);
     (void)hipEventRecord(ev[1], st);

@@ -30,15 +30,35 @@ __host__ __device__ inline int row_class(int64_t len) {
 // Per oriented edge (u -> v, u before v in the degree order) accumulators, one dense
 // array per quantity indexed by the oriented index k.  Credits to the out-edges of one
 // vertex land on consecutive k, so a wavefront's atomics coalesce into few cache lines.
+// Widths: an edge u -> v (d_u <= d_v <= dmax) has K < d_u^2 / 2, P < d_u d_v, g < 2 d_u d_v and
+// sig < d_u dmax, so every value stays below 2^32 when d_u dmax < 2^31.  Such "narrow" edges
+// keep K and P as 32-bit words and g, sig packed in one 64-bit word (g low, sig high).  In
+// the degree order the other, "wide" edges are a suffix [kw, m) of the oriented index (their
+// lower endpoint has degree >= 2^31 / dmax); they keep four 64-bit words each in the arrays
+// Kw, Pw, gw, sw indexed by k - kw.  kw is settled during preprocessing: m when no edge is wide
+// (32-bit kernels), the first wide edge when the wide suffix is at most m / 4 (its arrays then
+// live in the sig buffer), else 0 (every edge wide; Kw..sw are K, P, g, sig themselves).
 struct EdgeArrays {
     u32* t;      // triangles on the edge
-    u64* K;      // 4-cliques on the edge (edges inside T)
-    u64* P;      // non-induced 4-cycles through the edge
-    u64* g;      // sum over w in T of t(w,u) + t(w,v); with 32-bit accumulators each word holds
-                 // g (low half) and sig (high half) of its edge
-    u64* sig;    // sum over w in T of d_w (64-bit accumulators only)
+    u64* K;      // 4-cliques on the edge (edges inside T): u32 words below kw
+    u64* P;      // non-induced 4-cycles through the edge: u32 words below kw
+    u64* g;      // below kw: sum over w in T of t(w,u) + t(w,v) (low half) and of d_w (high half)
+    u64* sig;    // storage of the wide arrays (see above)
     int* u;      // lower-ranked endpoint (relabelled id); the other one is ocol[k]
+    int kw;      // first wide edge (m: none)
+    u64* Kw; u64* Pw; u64* gw; u64* sw;   // wide edges' K, P, g, sig at k - kw
 };
+
+// Wide-edge storage for a given split point (the same on host and device).
+__host__ __device__ inline void wide_arrays(EdgeArrays& e, int m, int kw) {
+    e.kw = kw;
+    if (kw <= 0) {
+        e.Kw = e.K; e.Pw = e.P; e.gw = e.g; e.sw = e.sig;
+    } else {
+        const int64_t nw = (int64_t)m - kw;
+        e.Kw = e.sig; e.Pw = e.sig + nw; e.gw = e.sig + 2 * nw; e.sw = e.sig + 3 * nw;
+    }
+}
 
 // Sums produced by the counting passes, all reduced to 128 bits at the end.
 // Index layout of the per-block partials and of the final reduction:
@@ -64,12 +84,19 @@ __device__ __forceinline__ int64_t gslot(const int* ngid, int v) {
 }
 
 // Orders of the workgroup work lists (the paper's study of edge orderings, Section 4.3 and
-// Table 4, applied to vertex work lists).
-enum { LO_WORK = 0, LO_DEGREE = 1, LO_NONE = 2, LO_RANDOM = 3 };
+// Table 4, applied to vertex work lists): largest work, degree or volume (sum of the
+// neighbours' degrees) first, their inverses (smallest first), ascending rank (the bucketing
+// order, no sort) and pseudo-random.
+enum { LO_WORK = 0, LO_DEGREE = 1, LO_NONE = 2, LO_RANDOM = 3, LO_VOLUME = 4, LO_DEGREE_INV = 5,
+       LO_VOLUME_INV = 6, LO_N = 7 };
 
 // Bucket ids for the vertex work lists.
 enum { TB_WAVE = 0, TB_BLK1, TB_BLK2, TB_GLOBAL, TB_N };   // triangle / gather passes
 enum { WB_WAVE = 0, WB_MID, WB_BLK, WB_HUGE, WB_N };        // wedge pass
+// d.counts words: TB_N triangle-list counts, WB_N wedge-list counts, TB_N largest out-degrees
+// per triangle list, then the accumulator split point kw (EdgeArrays).
+#define CNT_KW (TB_N + WB_N + TB_N)
+#define CNT_WORDS (CNT_KW + 1)
 
 // Device pointers of one graph's workspace.
 struct Dev {
@@ -138,7 +165,10 @@ struct Dev {
     int list_order;       // LO_*: order of the workgroup work lists
     int wedge_limit;      // distinct hashed tops per range before the range is split
     int wedge_dense;      // width of the dense window of highest-ranked tops
-    int acc32;            // per-edge accumulators fit 32 bits (maximum degree <= 46340)
+    int acc32;            // 32-bit accumulator kernels: no wide edge (EdgeArrays), or global counts only
+    int wide_degree;      // > 0: lower endpoint degree from which edges are wide, if below the bound (tests)
+    u64* tstamp;          // null, or per workgroup-class wedge list entry the wall clock when it was done
+                          // (load-balance measurement; the preprocessing scratch key1 is reused)
     int per_edge;         // per-edge output requested (global counts need neither caller edge
                           // ids nor the K, P, g, sigma accumulators)
 };

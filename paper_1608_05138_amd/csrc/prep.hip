@@ -463,7 +463,8 @@ __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ ncol
                                                     const int4* __restrict__ vinf, const u32* __restrict__ oslot,
                                                     const u32* __restrict__ upx, int64_t S, int m,
                                                     int* __restrict__ ocol, int* __restrict__ s2k,
-                                                    int* __restrict__ eid2k, EdgeArrays ea, int acc32,
+                                                    int* __restrict__ eid2k, EdgeArrays ea,
+                                                    const int* __restrict__ kwp,
                                                     int2* __restrict__ wb, u64* __restrict__ wcnt,
                                                     u64* __restrict__ wspread, int* __restrict__ err) {
     __shared__ u64 red[2][256 / GLT_WAVE];
@@ -490,13 +491,16 @@ __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ ncol
                 s2k[s] = k;
                 ea.t[k] = 0; ea.u[k] = x;
                 if (PE) {
-                    // 32-bit accumulators: K and P are u32 arrays and one word of g holds g and sigma
-                    if (acc32) {
+                    // narrow edges: K and P are u32 words and one word of g holds g and sigma;
+                    // wide edges: four u64 words (EdgeArrays)
+                    const int kw = *kwp;
+                    if (k < kw) {
                         reinterpret_cast<u32*>(ea.K)[k] = 0;
                         reinterpret_cast<u32*>(ea.P)[k] = 0;
                         ea.g[k] = 0;
                     } else {
-                        ea.K[k] = 0; ea.P[k] = 0; ea.g[k] = 0; ea.sig[k] = 0;
+                        wide_arrays(ea, m, kw);
+                        ea.Kw[k - kw] = 0; ea.Pw[k - kw] = 0; ea.gw[k - kw] = 0; ea.sw[k - kw] = 0;
                     }
                 }
                 r = make_int2(vy.z, y1);
@@ -603,6 +607,34 @@ __global__ __launch_bounds__(256) void k_wappend(const u64* __restrict__ wcnt, i
     }
 }
 
+// Split point kw of the per-edge accumulators (EdgeArrays): the first oriented edge whose
+// lower endpoint u has d_u dmax >= 2^31 (a suffix in the degree order); m if there is none;
+// 0 (every edge wide) when that suffix holds more than m / 4 edges, too many for the wide
+// arrays' place in the sig buffer.  Batches (global counts only) use no accumulator: m.
+// wide_degree > 0 lowers the threshold to that degree (tests: more edges take the wide path;
+// a lower threshold only widens edges, which is always exact).
+__global__ void k_wide_split(const int* __restrict__ ndeg, const int* __restrict__ optr, int n, int m,
+                             int batched, int wide_degree, int* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int kw = m;
+    if (!batched && n > 0) {
+        const int64_t dmax = ndeg[n - 1];   // ranks ascend by degree
+        if (dmax > 0) {
+            int64_t dw = ((int64_t)1 << 31) / dmax + ((((int64_t)1 << 31) % dmax) ? 1 : 0);   // ceil
+            if (wide_degree > 0 && wide_degree < dw) dw = wide_degree;
+            int lo = 0, hi = n;               // first rank with degree >= dw
+            while (lo < hi) {
+                const int mid = lo + (hi - lo) / 2;
+                if ((int64_t)ndeg[mid] < dw) lo = mid + 1;
+                else hi = mid;
+            }
+            kw = optr[lo];
+            if ((int64_t)(m - kw) * 4 > (int64_t)m) kw = 0;
+        }
+    }
+    *out = kw;
+}
+
 // ---------------------------------------------------------------------------------------
 // host orchestration
 // ---------------------------------------------------------------------------------------
@@ -639,7 +671,7 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
     const int64_t S = d.S;
     const int maxdeg = vinfo[0];
     const int* rows = vinfo + 1;   // rows per sort class
-    (void)hipMemsetAsync(d.counts, 0, sizeof(int) * (TB_N + WB_N + TB_N), st);
+    (void)hipMemsetAsync(d.counts, 0, sizeof(int) * CNT_WORDS, st);
     launch_fill<u64>(d.work, NWORK, 0ull, st);
     launch_fill<u64>(d.wspread, (int64_t)GSPREAD * WSPREAD_WORDS, 0ull, st);
     if (n == 0) return 0;
@@ -686,16 +718,20 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
     int* dplus = d.itmp + scan_tmp_elems(S + n + 1);  // past the scan scratch
     hipLaunchKernelGGL(k_dlo, dim3(nblk(n, 256)), dim3(256), 0, st, d.nrp, d.ncol, n, d.dlo, dplus);
     launch_excl_scan<int, int>(dplus, d.optr, n, d.itmp, d.optr + n, st);
+    hipLaunchKernelGGL(k_wide_split, dim3(1), dim3(64), 0, st, d.ndeg, d.optr, n, d.m, d.ngraphs > 0 ? 1 : 0,
+                       d.wide_degree, d.counts + CNT_KW);
     launch_fill<u64>(d.wcnt, n, 0ull, st);
     if (S > 0) {
         hipLaunchKernelGGL(k_vinfo, dim3(nblk(n, 256)), dim3(256), 0, st, d.nrp, d.dlo, d.optr, d.order, n, d.vinf);
         if (d.per_edge)
             hipLaunchKernelGGL(k_edge_index<true>, dim3(nblk(S, 256)), dim3(256), 0, st, d.ncol, d.nsrow, d.vinf,
-                               oslot, d.upx, S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.acc32, d.wb, d.wcnt, d.wspread,
+                               oslot, d.upx, S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.counts + CNT_KW, d.wb, d.wcnt,
+                               d.wspread,
                                d.err);
         else
             hipLaunchKernelGGL(k_edge_index<false>, dim3(nblk(S, 256)), dim3(256), 0, st, d.ncol, d.nsrow, d.vinf,
-                               oslot, d.upx, S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.acc32, d.wb, d.wcnt, d.wspread,
+                               oslot, d.upx, S, d.m, d.ocol, d.s2k, d.eid2k, d.e, d.counts + CNT_KW, d.wb, d.wcnt,
+                               d.wspread,
                                d.err);
     }
     // work lists

@@ -544,9 +544,10 @@ def test_out_degree_limit(ctx):
 
 
 def test_list_orders_agree():
-    """The order of the workgroup work lists (largest work, largest degree, ascending rank,
-    pseudo-random: the ordering study of Section 4.3 / Table 4) changes only the schedule: all
-    four give the oracle's counts, global and per edge."""
+    """The order of the workgroup work lists (largest work, degree or volume first, smallest
+    degree or volume first, ascending rank, pseudo-random: the ordering study of Section 4.3
+    / Table 4) changes only the schedule: all seven give the oracle's counts, global and per
+    edge."""
     import paper_1608_05138_amd as glt
     n = 20000
     rp, col = gg.chung_lu(n, 200000, 2.1, float(n - 1), 8)
@@ -554,7 +555,7 @@ def test_list_orders_agree():
     c = glt.Context(0)
     try:
         base = None
-        for order in range(4):
+        for order in range(7):
             c.set_schedule(list_order=order)
             say(f"list-order {order}")
             X, pe = gpu(c, n, rp, col)
@@ -563,5 +564,63 @@ def test_list_orders_agree():
                 base = pe
             else:
                 np.testing.assert_array_equal(pe, base)
+    finally:
+        c.close()
+
+
+def test_wide_edges_two_hubs_all_stream_modes():
+    """Two adjacent hubs sharing 50,000 leaves, over sparse ER noise: the edge between them
+    has endpoint degrees above 2^31 / dmax, so it takes the 64-bit (wide) accumulators while
+    every other edge keeps 32-bit ones; all 13 per-edge counts of every edge must equal the
+    oracle's in each stream mode."""
+    import paper_1608_05138_amd as glt
+    rng = np.random.default_rng(2031)
+    n = 70000
+    lo, hi = gg.er_pairs(n, 80000, rng)
+    leaves = np.arange(2, 50002)
+    a = np.concatenate([lo, [0], np.zeros(50000, np.int64), np.ones(50000, np.int64)])
+    b = np.concatenate([hi, [1], leaves, leaves])
+    keep = a != b
+    a, b = a[keep], b[keep]
+    key = np.unique(np.minimum(a, b) * n + np.maximum(a, b))
+    perm = rng.permutation(n)
+    rp, col = gg.csr_from_pairs(n, perm[key // n], perm[key % n])
+    d = np.diff(rp)
+    assert int(np.sort(d)[-2]) * int(d.max()) >= 2 ** 31
+    ref = oracle.count(n, rp, col, per_edge=True)
+    for mode in (0, 1, 2):
+        c = glt.Context(0)
+        try:
+            c.set_schedule(wedge_stream=mode)
+            say(f"two-hubs mode {mode}")
+            X, pe = gpu(c, n, rp, col)
+            assert X == ref["X"], mode
+            np.testing.assert_array_equal(pe, ref["per_edge"], err_msg=f"mode {mode}")
+        finally:
+            c.close()
+
+
+@pytest.mark.parametrize("wide_degree", ["60", "3"])
+def test_forced_wide_edges(monkeypatch, wide_degree):
+    """Edges whose lower endpoint has degree >= GLT_WIDE_DEGREE forced onto the 64-bit
+    accumulators: with 60 a suffix of the oriented edges (at most a quarter) is wide and the
+    rest narrow; with 3 more than a quarter would be, so every edge is wide.  Per-edge and
+    global counts must equal the oracle's on graphs that reach every triangle and wedge
+    path."""
+    import paper_1608_05138_amd as glt
+    monkeypatch.setenv("GLT_WIDE_DEGREE", wide_degree)
+    c = glt.Context(0)
+    try:
+        cases = [("chung-lu-6000", 6000, gg.chung_lu(6000, 90000, 2.1, 5999.0, 78))]
+        rng = np.random.default_rng(9)
+        nn = 3000
+        lo, hi = gg.er_pairs(nn, 9000, rng)
+        iu = np.triu_indices(760, 1)   # out-degrees up to 759: global-bitmap rows
+        a = np.concatenate([lo, iu[0]]); b = np.concatenate([hi, iu[1]])
+        key = np.unique(np.minimum(a, b) * nn + np.maximum(a, b))
+        perm = rng.permutation(nn)
+        cases.append(("clique760-noise", nn, gg.csr_from_pairs(nn, perm[key // nn], perm[key % nn])))
+        for name, n, (rp, col) in cases:
+            check_vs_oracle(c, f"wide-{wide_degree}-{name}", n, rp, col)
     finally:
         c.close()
