@@ -19,7 +19,7 @@ typedef __int128 i128;
 typedef unsigned __int128 u128;
 
 int glt_combine_blocks(int m);
-int glt_max_out_degree();
+int64_t glt_slab_words(int smax);
 int glt_wedge_table();
 int glt_wave_table();
 int glt_wedge_dense();
@@ -308,9 +308,8 @@ glt_status ensure_ws(glt_ctx* ctx, size_t need, hipStream_t st) {
 // 1 GiB and the budget (one launch instead of dozens on heavy-tailed graphs).
 void grow_slab(glt_ctx* ctx, Dev& d, int count, int smax, hipStream_t st) {
     if (count <= 0 || smax <= 0) return;
-    const int64_t W = ((smax + 31) / 32 + 3) & ~3;   // row words as the triangle pass pads them
-    const int64_t per = std::max<int64_t>((int64_t)smax * W, 4 * (int64_t)smax);   // tri rows, gather sums
-    const int64_t want = std::min<int64_t>(per * count, (int64_t)1 << 28);          // words (1 GiB)
+    const int64_t per = glt_slab_words(smax);   // one workgroup's region (triangle and gather passes)
+    const int64_t want = std::min<int64_t>(std::max<int64_t>(per * count, per), (int64_t)1 << 28);   // words (1 GiB)
     if (want <= d.gscratch_words) return;
     const size_t need = (size_t)want * 4;
     if (need > ctx->slab_bytes) {
@@ -386,9 +385,6 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
         if (e & ERR_DUP) return fail(ctx, GLT_E_NOT_SIMPLE, "duplicate entry");
         if ((e & ERR_ASYM) || up != m) return fail(ctx, GLT_E_NOT_SYMMETRIC, "adjacency is not symmetric");
         memcpy(hc, (char*)ctx->hbuf + 16, sizeof(int) * CNT_WORDS);
-        if (hc[TB_N + WB_N + TB_GLOBAL] > glt_max_out_degree())
-            return fail(ctx, GLT_E_UNSUPPORTED, "out-degree %d in the degree order exceeds %d",
-                        hc[TB_N + WB_N + TB_GLOBAL], glt_max_out_degree());
     }
     if (noalloc) {
         d.trec = nullptr;   // the passes re-scan the out-lists; the carved 32 MiB slab serves
@@ -396,6 +392,10 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
         d.trec = ensure_trec(ctx, n > 0 ? *(u64*)((char*)ctx->hbuf + 128) : 0, st);
         grow_slab(ctx, d, hc[TB_GLOBAL], hc[TB_N + WB_N + TB_GLOBAL], st);
     }
+    // the workgroup passes above the LDS rows need at least one slab region
+    if (hc[TB_GLOBAL] > 0 && glt_slab_words(hc[TB_N + WB_N + TB_GLOBAL]) > d.gscratch_words)
+        return fail(ctx, GLT_E_OOM, "out-degree %d needs %lld bytes of slab per workgroup, more than available",
+                    hc[TB_N + WB_N + TB_GLOBAL], (long long)glt_slab_words(hc[TB_N + WB_N + TB_GLOBAL]) * 4);
     // per-edge accumulators: 32-bit kernels when no edge is wide (or no per-edge output),
     // else 64-bit in-kernel sums with the narrow / wide storage split at kw (EdgeArrays)
     ctx->bal_count = ctx->record_balance ? hc[TB_N + WB_BLK] : 0;

@@ -71,6 +71,31 @@ __device__ __forceinline__ void gsig_get(const EdgeArrays& e, int64_t k, u64& g,
     }
 }
 
+// Triangle and 4-clique credits of one edge.  In per-edge mode a narrow edge accumulates
+// (K << 32 | t) in its g word during the triangle pass, one atomic for both (t and K stay
+// below 2^32, so the halves never carry into each other); k_unpack_tk then moves them to t
+// and K and clears g before the gather pass.  Wide edges, and global counting (no K), credit
+// t and K separately.
+template <bool PE, typename AT>
+__device__ __forceinline__ void tk_add(const EdgeArrays& e, int64_t k, u32 dt, u64 dk) {
+    if (PE && !(sizeof(AT) == 8 && k >= e.kw)) {
+        const u64 v = (dk << 32) | (u64)dt;
+        if (v) atomicAdd(&e.g[k], v);
+    } else {
+        if (dt) atomicAdd(&e.t[k], dt);
+        if (PE && dk) acc_add<AT, ACC_K>(e, k, dk);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_unpack_tk(EdgeArrays e, int m) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= m || k >= e.kw) return;
+    const u64 v = e.g[k];
+    e.t[k] = (u32)v;
+    reinterpret_cast<u32*>(e.K)[k] = (u32)(v >> 32);
+    e.g[k] = 0;
+}
+
 #define TB_THREADS 256
 #ifndef TW_G
 #define TW_G 4         // wavefronts per block in the wavefront triangle and gather passes
@@ -215,6 +240,24 @@ __host__ __device__ inline int tri_blk_ht(int smax) {
     return h;
 }
 
+// Out-degrees above TB_LDS_SMAX (rare: the degree order bounds them by sqrt(2m)) keep the
+// workgroup passes' per-neighbour arrays and membership hash in the workgroup's region of
+// the global slab too (GX), besides the rows.  Positions in N+(a) are 16-bit fields of the
+// triangle records and of the hash; 2m < 2^31 keeps every out-degree below 46,341.
+#define TB_LDS_SMAX 3200
+// u32 words of one workgroup's slab region: triangle pass (rows; GX: sK, sS, sOb, sLen, hash)
+__host__ __device__ inline int64_t tri_slab_words(int smax, bool gx) {
+    int64_t w = (int64_t)smax * tri_row_words(smax, true);
+    if (gx) w += 5 * (int64_t)smax + tri_blk_ht(smax) + (tri_blk_ht(smax) + 1) / 2;
+    return (w + 3) & ~(int64_t)3;
+}
+// gather pass (sG, sSg; GX: sS, sOb, sLen, sT, sD)
+__host__ __device__ inline int64_t gather_slab_words(int smax, bool gx) {
+    int64_t w = 4 * (int64_t)smax;
+    if (gx) w += 5 * (int64_t)(smax + 1);
+    return (w + 3) & ~(int64_t)3;
+}
+
 // Membership of S = N+(a) for the workgroup triangle pass: LDS open addressing, id -> position.
 __device__ __forceinline__ u32 bhash(int x, u32 mask) { return ((u32)x * 2654435761u >> 7) & mask; }
 __device__ __forceinline__ int bh_find(const int* hk, const unsigned short* hp, u32 mask, int x) {
@@ -321,11 +364,8 @@ __global__ __launch_bounds__(TW_THREADS) void k_tri_wave(const int* __restrict__
                 int rj, k;
                 tri_unrec(rec[r], ri, rj, k);
                 tk = (u64)__popcll(sM[w][ri] & sM[w][rj]);
-                atomicAdd(&e.t[k], 1u);
-                if (PE && tk) {
-                    acc_add<AT, ACC_K>(e, k, tk);
-                    atomicAdd(&sK[w][rj], tk);
-                }
+                tk_add<PE, AT>(e, k, 1u, PE ? tk : 0ull);
+                if (PE && tk) atomicAdd(&sK[w][rj], tk);
                 k4 += tk;
             }
             if (PE) {   // records are in scan order: runs of equal i summed first
@@ -348,9 +388,8 @@ __global__ __launch_bounds__(TW_THREADS) void k_tri_wave(const int* __restrict__
                     const int j = sh_find(hk[w], hv[w], ocol[k]);
                     if (j >= 0) {
                         const u64 tk = (u64)__popcll(sM[w][i] & sM[w][j]);
-                        atomicAdd(&e.t[k], 1u);
+                        tk_add<PE, AT>(e, k, 1u, PE ? tk : 0ull);
                         if (PE && tk) {
-                            acc_add<AT, ACC_K>(e, k, tk);
                             atomicAdd(&sK[w][i], tk);
                             atomicAdd(&sK[w][j], tk);
                         }
@@ -361,14 +400,7 @@ __global__ __launch_bounds__(TW_THREADS) void k_tri_wave(const int* __restrict__
         }
     }
     wave_sync();
-    if (l < s) {
-        const u32 tl = (u32)__popcll(sM[w][l]);
-        if (tl) atomicAdd(&e.t[o0 + l], tl);
-        if (PE) {
-            const u64 kl = sK[w][l] >> 1;
-            if (kl) acc_add<AT, ACC_K>(e, o0 + l, kl);
-        }
-    }
+    if (l < s) tk_add<PE, AT>(e, o0 + l, (u32)__popcll(sM[w][l]), PE ? (sK[w][l] >> 1) : 0ull);
     k4 = wave_sum(k4);
     const u64 ntri = wave_sum((l < s) ? (u64)__popcll(sM[w][l]) : 0ull) / 2;
     if (l == 0) {
@@ -399,32 +431,40 @@ __device__ __forceinline__ u64 row_and_count(const u32* M, int W, int i, int j) 
     return c;
 }
 
-template <bool PE, bool GM, bool REC, typename AT, int NT>
+// GM: rows M in the workgroup's slab region (gstride u32 words per workgroup); GX (with GM):
+// also the per-neighbour arrays and the hash there.  A launch takes the list entries with
+// out-degree <= smax, or with GX those above TB_LDS_SMAX (each group skips the rest).
+template <bool PE, bool GM, bool REC, typename AT, int NT, bool GX>
 __global__ __launch_bounds__(NT, 8) void k_tri_blk(const int* __restrict__ list, int nlist, int smax,
                                                        const int* __restrict__ optr, const int* __restrict__ ocol,
                                                        EdgeArrays e, u64* __restrict__ gsum,
-                                                       u32* __restrict__ gscratch, const int* __restrict__ ngid,
+                                                       u32* __restrict__ gscratch, int64_t gstride,
+                                                       const int* __restrict__ ngid,
                                                        u64* __restrict__ trec, const u64* __restrict__ toff,
                                                        int* __restrict__ tcnt) {
+    static_assert(GM || !GX, "global per-neighbour arrays only on the global-row path");
     constexpr int SPOS = RunTables<NT>::SPOS;
     extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
     __shared__ RunTables<NT> rt;
     __shared__ u64 sRed[NT / GLT_WAVE];
     __shared__ int sNrec;
-    u64* sK = (u64*)dyn;
+    const int a = list[blockIdx.x];
+    const int o0 = optr[a];
+    const int s = optr[a + 1] - o0;
+    if (GX ? (s <= TB_LDS_SMAX) : (s > smax)) return;   // not this launch's entry (uniform per workgroup)
+    const int Wmax = tri_row_words(smax, GM);
+    u32* gb = GM ? gscratch + (int64_t)blockIdx.x * gstride : nullptr;
+    unsigned char* xb = GX ? (unsigned char*)(gb + (int64_t)smax * Wmax) : dyn;
+    u64* sK = (u64*)xb;
     int* sS = (int*)(sK + smax);
     int* sOb = sS + smax;
     int* sLen = sOb + smax;
-    const int Wmax = tri_row_words(smax, GM);
-    u32* M = GM ? gscratch + (int64_t)blockIdx.x * smax * Wmax : (u32*)(sLen + smax);
+    u32* M = GM ? gb : (u32*)(sLen + smax);
     const int HT = tri_blk_ht(smax);
     const u32 hmask = (u32)HT - 1;
     int* hk = GM ? (sLen + smax) : (int*)(M + (int64_t)smax * Wmax);
     unsigned short* hp = (unsigned short*)(hk + HT);
     const int tid = threadIdx.x;
-    const int a = list[blockIdx.x];
-    const int o0 = optr[a];
-    const int s = optr[a + 1] - o0;
     const int W = tri_row_words(s, GM);
     for (int q = tid; q < HT; q += NT) hk[q] = -1;
     __syncthreads();
@@ -509,11 +549,8 @@ __global__ __launch_bounds__(NT, 8) void k_tri_blk(const int* __restrict__ list,
                 u64 tk = 0;
                 if (rk[u] >= 0) {
                     tk = row_and_count<GM>(M, W, ri[u], rj[u]);
-                    atomicAdd(&e.t[rk[u]], 1u);
-                    if (PE && tk) {
-                        acc_add<AT, ACC_K>(e, rk[u], tk);
-                        atomicAdd(&sK[rj[u]], tk);
-                    }
+                    tk_add<PE, AT>(e, rk[u], 1u, PE ? tk : 0ull);
+                    if (PE && tk) atomicAdd(&sK[rj[u]], tk);
                     k4 += tk;
                 }
                 if (PE) {   // records come in runs of equal i (per writing wavefront)
@@ -539,9 +576,8 @@ __global__ __launch_bounds__(NT, 8) void k_tri_blk(const int* __restrict__ list,
                     const int j = bh_find(hk, hp, hmask, ocol[k]);
                     if (j >= 0) {
                         const u64 tk = row_and_count<GM>(M, W, i, j);
-                        atomicAdd(&e.t[k], 1u);
+                        tk_add<PE, AT>(e, k, 1u, PE ? tk : 0ull);
                         if (PE && tk) {
-                            acc_add<AT, ACC_K>(e, k, tk);
                             atomicAdd(&sK[i], tk);
                             atomicAdd(&sK[j], tk);
                         }
@@ -558,11 +594,7 @@ __global__ __launch_bounds__(NT, 8) void k_tri_blk(const int* __restrict__ list,
         u32 tl = 0;
         for (int wd = 0; wd < W; wd++) tl += (u32)__popc(M[i * W + wd]);
         ntri += tl;
-        if (tl) atomicAdd(&e.t[o0 + i], tl);
-        if (PE) {
-            const u64 kl = sK[i] >> 1;
-            if (kl) acc_add<AT, ACC_K>(e, o0 + i, kl);
-        }
+        tk_add<PE, AT>(e, o0 + i, tl, PE ? (sK[i] >> 1) : 0ull);
     }
     k4 = wave_sum(k4);
     if (glt_lane() == 0) sRed[tid / GLT_WAVE] = k4;
@@ -576,7 +608,8 @@ __global__ __launch_bounds__(NT, 8) void k_tri_blk(const int* __restrict__ list,
     if (glt_lane() == 0 && ntri) atomicAdd(&gsum[gslot(ngid, a) * NSUMS + GS_TRI_WG], ntri);
 }
 
-static inline size_t tri_blk_lds(int smax, bool gm) {
+static inline size_t tri_blk_lds(int smax, bool gm, bool gx) {
+    if (gx) return 0;
     size_t b = (size_t)smax * (8 + 4 + 4 + 4);
     if (!gm) b += (size_t)smax * tri_row_words(smax, false) * 4;
     b += (size_t)tri_blk_ht(smax) * (4 + 2);
@@ -708,30 +741,37 @@ __global__ __launch_bounds__(TW_THREADS) void k_gather_wave(const int* __restric
     }
 }
 
-template <bool GM, bool REC, typename AT>
+// GM: the accumulators sG, sSg in the workgroup's slab region (gstride u32 words per
+// workgroup); GX (with GM): the per-neighbour arrays there too.  A launch takes the list
+// entries with out-degree <= smax, or with GX those above TB_LDS_SMAX.
+template <bool GM, bool REC, typename AT, bool GX>
 __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict__ list, int nlist, int smax,
                                                           const int* __restrict__ optr,
                                                           const int* __restrict__ ocol,
                                                           const int* __restrict__ ndeg, EdgeArrays e,
-                                                          u64* __restrict__ gslab, const u64* __restrict__ trec,
+                                                          u64* __restrict__ gslab, int64_t gstride,
+                                                          const u64* __restrict__ trec,
                                                           const u64* __restrict__ toff,
                                                           const int* __restrict__ tcnt) {
+    static_assert(GM || !GX, "global per-neighbour arrays only on the global-accumulator path");
     constexpr int SPOS = RunTables<TB_THREADS>::SPOS;
     extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
     __shared__ RunTables<REC ? GLT_WAVE : TB_THREADS> rt;
-    int* sS = (int*)dyn;
+    const int tid = threadIdx.x;
+    const int a = list[blockIdx.x];
+    const int o0 = optr[a];
+    const int s = optr[a + 1] - o0;
+    if (GX ? (s <= TB_LDS_SMAX) : (s > smax)) return;   // not this launch's entry (uniform per workgroup)
+    const int nh = REC ? tcnt[a] : 0;
+    if (REC && nh == 0) return;   // no triangle has a as its lowest vertex (uniform per block)
+    u64* gb = GM ? gslab + (int64_t)blockIdx.x * (gstride / 2) : nullptr;
+    int* sS = GX ? (int*)(gb + 2 * (int64_t)smax) : (int*)dyn;
     int* sOb = sS + smax;
     int* sLen = sOb + smax;
     u32* sT = (u32*)(sLen + smax);
     int* sD = (int*)(sT + smax);
-    u64* sG = GM ? gslab + (int64_t)blockIdx.x * 2 * smax : (u64*)(sD + smax + (smax & 1));
+    u64* sG = GM ? gb : (u64*)(sD + smax + (smax & 1));
     u64* sSg = sG + smax;
-    const int tid = threadIdx.x;
-    const int a = list[blockIdx.x];
-    const int nh = REC ? tcnt[a] : 0;
-    if (REC && nh == 0) return;   // no triangle has a as its lowest vertex (uniform per block)
-    const int o0 = optr[a];
-    const int s = optr[a + 1] - o0;
     const int da = ndeg[a];
     // REC: GR records per thread and round, each with the t of its third edge; the first
     // round's loads go out before the setup
@@ -802,7 +842,8 @@ __global__ __launch_bounds__(TB_THREADS) void k_gather_blk(const int* __restrict
     }
 }
 
-static inline size_t gather_blk_lds(int smax, bool gm) {
+static inline size_t gather_blk_lds(int smax, bool gm, bool gx) {
+    if (gx) return 0;
     return (size_t)(smax + 1) * 4 * 5 + (gm ? 0 : (size_t)smax * 8 * 2);
 }
 
@@ -860,8 +901,15 @@ __device__ __forceinline__ void wedge_bounds(int s, int lo, int hi, bool full, c
 #define WB_DW 4096
 #endif
 #define WH_T 1024        // huge class: a whole CU's LDS for bottom vertices with the most wedges
+#ifndef WH_HT
 #define WH_HT 8192
+#endif
+#ifndef WH_DW
 #define WH_DW 16384
+#endif
+#ifndef WH_PER_CU
+#define WH_PER_CU 1      // resident huge-class workgroups per CU
+#endif
 
 // One group of T threads per bottom vertex y (G groups per block).  For every wedge
 // y - w - x with x above y the group counts c(y, x) = number of such w in LDS: tops x in
@@ -1487,7 +1535,15 @@ __global__ void k_work_keys(const int* __restrict__ list, int nlist, int mode, i
 __global__ __launch_bounds__(256) void k_volume(const int* __restrict__ nsrow, const int* __restrict__ ncol,
                                                 const int* __restrict__ ndeg, int64_t S, u64* __restrict__ vol) {
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s < S) atomicAdd(&vol[nsrow[s]], (u64)ndeg[ncol[s]]);
+    u64 d = 0;
+    int x = 0x7fffffff;
+    if (s < S) {
+        x = nsrow[s];
+        d = (u64)ndeg[ncol[s]];
+    }
+    bool last;   // runs of one row are summed in the wavefront first
+    const u64 r = seg_sum_last(d, x, last);
+    if (last && x != 0x7fffffff && r) atomicAdd(&vol[x], r);
 }
 
 __global__ void k_copy_list(const u32* __restrict__ vals, int nlist, int* __restrict__ list) {
@@ -1578,31 +1634,46 @@ static void launch_tri_wave(const Dev& d, const int* lst, int c, hipStream_t st)
 #ifndef TB_BIG_THREADS
 #define TB_BIG_THREADS 1024
 #endif
-template <bool PE, bool GM, typename AT, int NT>
-static void launch_tri_blk_nt(const Dev& d, const int* lst, int c, int smax, hipStream_t st) {
-    const size_t lds = tri_blk_lds(smax, GM);
+template <bool PE, bool GM, typename AT, int NT, bool GX>
+static void launch_tri_blk_nt(const Dev& d, const int* lst, int c, int smax, int64_t gstride, hipStream_t st) {
+    const size_t lds = tri_blk_lds(smax, GM, GX);
     if (d.trec)
-        hipLaunchKernelGGL((k_tri_blk<PE, GM, true, AT, NT>), dim3(c), dim3(NT), lds, st, lst, c, smax, d.optr,
-                           d.ocol, d.e, d.gsum, d.gscratch, d.ngid, d.trec, d.toff, d.tcnt);
+        hipLaunchKernelGGL((k_tri_blk<PE, GM, true, AT, NT, GX>), dim3(c), dim3(NT), lds, st, lst, c, smax, d.optr,
+                           d.ocol, d.e, d.gsum, d.gscratch, gstride, d.ngid, d.trec, d.toff, d.tcnt);
     else
-        hipLaunchKernelGGL((k_tri_blk<PE, GM, false, AT, NT>), dim3(c), dim3(NT), lds, st, lst, c, smax, d.optr,
-                           d.ocol, d.e, d.gsum, d.gscratch, d.ngid, d.trec, d.toff, d.tcnt);
+        hipLaunchKernelGGL((k_tri_blk<PE, GM, false, AT, NT, GX>), dim3(c), dim3(NT), lds, st, lst, c, smax, d.optr,
+                           d.ocol, d.e, d.gsum, d.gscratch, gstride, d.ngid, d.trec, d.toff, d.tcnt);
 }
-template <bool PE, bool GM, typename AT>
-static void launch_tri_blk(const Dev& d, const int* lst, int c, int smax, hipStream_t st) {
-    if (smax <= 256) launch_tri_blk_nt<PE, GM, AT, TB_THREADS>(d, lst, c, smax, st);
-    else launch_tri_blk_nt<PE, GM, AT, TB_BIG_THREADS>(d, lst, c, smax, st);
+template <bool PE, bool GM, typename AT, bool GX = false>
+static void launch_tri_blk(const Dev& d, const int* lst, int c, int smax, int64_t gstride, hipStream_t st) {
+    if (smax <= 256) launch_tri_blk_nt<PE, GM, AT, TB_THREADS, GX>(d, lst, c, smax, gstride, st);
+    else launch_tri_blk_nt<PE, GM, AT, TB_BIG_THREADS, GX>(d, lst, c, smax, gstride, st);
 }
 
-template <bool GM, typename AT>
-static void launch_gather_blk(const Dev& d, const int* lst, int c, int smax, hipStream_t st) {
-    const size_t lds = gather_blk_lds(smax, GM);
+template <bool GM, typename AT, bool GX = false>
+static void launch_gather_blk(const Dev& d, const int* lst, int c, int smax, int64_t gstride, hipStream_t st) {
+    const size_t lds = gather_blk_lds(smax, GM, GX);
     if (d.trec)
-        hipLaunchKernelGGL((k_gather_blk<GM, true, AT>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax, d.optr,
-                           d.ocol, d.ndeg, d.e, (u64*)d.gscratch, d.trec, d.toff, d.tcnt);
+        hipLaunchKernelGGL((k_gather_blk<GM, true, AT, GX>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax, d.optr,
+                           d.ocol, d.ndeg, d.e, (u64*)d.gscratch, gstride, d.trec, d.toff, d.tcnt);
     else
-        hipLaunchKernelGGL((k_gather_blk<GM, false, AT>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax, d.optr,
-                           d.ocol, d.ndeg, d.e, (u64*)d.gscratch, d.trec, d.toff, d.tcnt);
+        hipLaunchKernelGGL((k_gather_blk<GM, false, AT, GX>), dim3(c), dim3(TB_THREADS), lds, st, lst, c, smax, d.optr,
+                           d.ocol, d.ndeg, d.e, (u64*)d.gscratch, gstride, d.trec, d.toff, d.tcnt);
+}
+
+// Words per workgroup of the global slab for the out-degree bucket above the LDS rows, whose
+// largest out-degree is smax: its triangle and gather launches share the regions.
+static inline int64_t gm_slab_words(int smax) {
+    const int s0 = smax < TB_LDS_SMAX ? smax : TB_LDS_SMAX;
+    int64_t w = tri_slab_words(s0, false);
+    const int64_t g0 = gather_slab_words(s0, false);
+    if (g0 > w) w = g0;
+    if (smax > TB_LDS_SMAX) {
+        const int64_t t1 = tri_slab_words(smax, true), g1 = gather_slab_words(smax, true);
+        if (t1 > w) w = t1;
+        if (g1 > w) w = g1;
+    }
+    return w;
 }
 
 // One group per list entry (grid from the host's count), or, with `resident` blocks, a grid
@@ -1629,6 +1700,7 @@ static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st, int res
 //   ev[14] start of the wave class          ev[6], ev[7] after the wave / mid classes
 //   ev[15] start of the workgroup class     ev[8], ev[9] after the workgroup / huge classes
 //   ev[10] after the last join              ev[11] after the combine
+//   ev[16] after the (t, K) unpack (mode 2: the second stream's gather path waits for it)
 // The passes share only read-only inputs and write distinct accumulators, so the streams
 // join only where a pass needs another's final values (the gather pass needs every t).
 // Wave class, and mid class, on stream s (ev[6], ev[7] after each).
@@ -1653,7 +1725,7 @@ static void wedge_mid_class(const Dev& d, int per_edge, const int* hc, hipStream
 template <typename AT>
 static void wedge_large(const Dev& d, int per_edge, const int* hc, hipStream_t s, hipEvent_t* ev) {
     const int* wc = hc + TB_N;
-    const int huge_grid = (wc[WB_BLK] + wc[WB_HUGE] > 0) ? d.num_cu : 0;
+    const int huge_grid = (wc[WB_BLK] + wc[WB_HUGE] > 0) ? d.num_cu * WH_PER_CU : 0;
     (void)hipEventRecord(ev[15], s);
     if (per_edge) launch_wedge<true, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
     else launch_wedge<false, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
@@ -1729,30 +1801,43 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
         const int smax = cnt[TB_N + WB_N + bkt];
         const bool gm = (bkt == TB_GLOBAL);
         const int* lst = tl + (int64_t)bkt * n;
-        // the global slab holds one M per workgroup: launch in groups that fit it
+        // the global slab holds one region per workgroup: launch in groups that fit it; the
+        // out-degrees above TB_LDS_SMAX get a second launch over the same entries (GX)
         int64_t grp = c;
+        const int64_t per = gm ? gm_slab_words(smax) : 0;
+        const int s0 = smax < TB_LDS_SMAX ? smax : TB_LDS_SMAX;
         if (gm) {
-            const int64_t per = (int64_t)smax * tri_row_words(smax, true);
             grp = d.gscratch_words / per;
             if (grp < 1) grp = 1;
         }
         for (int64_t off = 0; off < c; off += grp) {
             const int cc = (int)((c - off < grp) ? (c - off) : grp);
             if (per_edge) {
-                if (gm) launch_tri_blk<true, true, AT>(d, lst + off, cc, smax, sw);
-                else launch_tri_blk<true, false, AT>(d, lst + off, cc, smax, sw);
+                if (gm) {
+                    launch_tri_blk<true, true, AT>(d, lst + off, cc, s0, per, sw);
+                    if (smax > TB_LDS_SMAX) launch_tri_blk<true, true, AT, true>(d, lst + off, cc, smax, per, sw);
+                } else {
+                    launch_tri_blk<true, false, AT>(d, lst + off, cc, smax, 0, sw);
+                }
             } else {
-                if (gm) launch_tri_blk<false, true, AT>(d, lst + off, cc, smax, sw);
-                else launch_tri_blk<false, false, AT>(d, lst + off, cc, smax, sw);
+                if (gm) {
+                    launch_tri_blk<false, true, AT>(d, lst + off, cc, s0, per, sw);
+                    if (smax > TB_LDS_SMAX) launch_tri_blk<false, true, AT, true>(d, lst + off, cc, smax, per, sw);
+                } else {
+                    launch_tri_blk<false, false, AT>(d, lst + off, cc, smax, 0, sw);
+                }
             }
         }
     }
     (void)hipEventRecord(ev[3], sw);
+    // the gather passes need every triangle's t: the call's stream waits for the workgroup
+    // path, unpacks the narrow edges' (t, K) words, and the second stream waits for that
+    if (split) (void)hipStreamWaitEvent(st, ev[3], 0);
+    if (per_edge && m > 0)
+        hipLaunchKernelGGL(k_unpack_tk, dim3(cdiv(m, 256)), dim3(256), 0, st, e, m);
     if (split) {
-        // the gather passes need every triangle's t: each stream waits for the other's
-        // triangle path
-        (void)hipStreamWaitEvent(st, ev[3], 0);
-        (void)hipStreamWaitEvent(side, ev[2], 0);
+        (void)hipEventRecord(ev[16], st);
+        (void)hipStreamWaitEvent(side, ev[16], 0);
     }
     (void)hipEventRecord(ev[12], st);
     (void)hipEventRecord(ev[13], sw);
@@ -1775,16 +1860,19 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
             const int smax = cnt[TB_N + WB_N + bkt];
             const int* lst = tl + (int64_t)bkt * n;
             const bool gm = (bkt == TB_GLOBAL);
-            int64_t grp = c;
-            if (gm) {
-                const int64_t per = 2 * (int64_t)smax * 2;   // u64 accumulators, in u32 words
-                grp = d.gscratch_words / per;
-                if (grp < 1) grp = 1;
+            // the gather pass keeps its accumulators in LDS up to TB_LDS_SMAX (36 bytes per
+            // neighbour); only the out-degrees above it use slab regions (GX)
+            if (!gm || smax <= TB_LDS_SMAX) {
+                launch_gather_blk<false, AT>(d, lst, c, smax, 0, sw);
+                continue;
             }
+            const int64_t per = gm_slab_words(smax);
+            int64_t grp = d.gscratch_words / per;
+            if (grp < 1) grp = 1;
             for (int64_t off = 0; off < c; off += grp) {
                 const int cc = (int)((c - off < grp) ? (c - off) : grp);
-                if (gm) launch_gather_blk<true, AT>(d, lst + off, cc, smax, sw);
-                else launch_gather_blk<false, AT>(d, lst + off, cc, smax, sw);
+                launch_gather_blk<false, AT>(d, lst + off, cc, TB_LDS_SMAX, 0, sw);
+                launch_gather_blk<true, AT, true>(d, lst + off, cc, smax, per, sw);
             }
         }
     }
@@ -1845,8 +1933,8 @@ void glt_count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe, hi
 }
 
 int glt_combine_blocks(int m) { return combine_blocks(m); }
-// largest out-degree the block passes accept (LDS holds 5 ints per neighbour of a)
-int glt_max_out_degree() { return 3200; }
+// words per workgroup of the global slab for the bucket above the LDS rows (largest out-degree smax)
+int64_t glt_slab_words(int smax) { return gm_slab_words(smax); }
 int glt_wedge_table() { return WH_HT; }
 int glt_wedge_dense() { return WH_DW; }
 int glt_wave_table() { return WW_HT; }

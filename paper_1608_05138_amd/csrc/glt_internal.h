@@ -69,7 +69,7 @@ __host__ __device__ inline void wide_arrays(EdgeArrays& e, int m, int kw) {
 #define NWORK 8
 #define NSEG 11     // timed groups: prep, tri wave, tri wg, gather wave, gather wg, wedge wave, wedge mid,
                     // wedge wg, wedge huge, combine, total
-#define NEV 16      // events of one call (see count_passes)
+#define NEV 17      // events of one call (see count_passes)
 enum { S_C3 = 0, S_C4, S_C5, S_C7, S_C8, S_C9, S_C10, S_C11, S_C12, S_C13, S_C14, S_C15, S_C16,
        S_SPARE, S_K4x3, S_NC4 };
 // The per-group totals array (gsum) holds NSUMS words per line and uses S_K4x3, S_NC4 and

@@ -524,23 +524,52 @@ def test_inputs_pending_on_default_stream(ctx):
         del b
 
 
-def test_out_degree_limit(ctx):
-    """The largest supported out-degree in the degree order is 3200: K_3201 (out-degrees up to
-    3200, every vertex on the global-bitmap path above 640) counts exactly; K_3202 is refused
-    with GLT_E_UNSUPPORTED before any count is produced."""
-    import paper_1608_05138_amd as glt
+def test_out_degree_above_lds_rows(ctx):
+    """Out-degrees above 3200 in the degree order keep the workgroup passes' per-neighbour
+    arrays and hash in the global slab: K_{3301,3301} (the lowest-ranked vertex of one side
+    has out-degree 3301; no triangle) counts exactly, per edge
+    and globally, against the complete-bipartite closed forms; K_3201 (out-degrees up to
+    3200, the largest kept in LDS) still counts exactly."""
+    a = b = 3301
+    N, (rp, col) = gg.complete_bipartite(a, b)
+    say(f"complete-bipartite-{a}-{b} (out-degree above the LDS rows)")
+    X, pe = gpu(ctx, N, rp, col)
+    nz = {1: a * b, 4: a * comb(b, 2) + b * comb(a, 2), 6: comb(a, 3) + comb(b, 3),
+          10: comb(a, 2) * comb(b, 2), 11: a * comb(b, 3) + b * comb(a, 3),
+          17: comb(a, 4) + comb(b, 4)}
+    expect = [nz.get(i, 0) for i in range(1, 18)]
+    expect[1] = comb(N, 2) - a * b
+    assert X == expect
+    m = a * b
+    want = np.zeros((13, m), dtype=np.uint64)
+    want[1] = a + b - 2
+    want[6] = (a - 1) * (b - 1)
+    want[7] = comb(a - 1, 2) + comb(b - 1, 2)
+    np.testing.assert_array_equal(pe, want)
     n = 3201
     N, (rp, col) = gg.complete(n)
-    say(f"complete-{n} (limit)")
+    say(f"complete-{n}")
     X, _ = gpu(ctx, N, rp, col, per_edge=False)
     assert X == _closed_complete(n)
-    N2, (rp2, col2) = gg.complete(n + 1)
-    say(f"complete-{n + 1} (refused)")
-    with pytest.raises(glt.GltError) as ei:
-        ctx.count(rp2, col2, n=N2)
-    assert ei.value.status == -6, str(ei.value)
-    X, _ = gpu(ctx, N, rp, col, per_edge=False)   # the handle still works
-    assert X == _closed_complete(n)
+
+
+def test_out_degree_above_lds_rows_cocktail_party(ctx):
+    """K_3400 minus a perfect matching: every vertex has degree 3398, so the lowest-ranked
+    one has out-degree 3398 with triangles and 4-cliques over all of N+(a) (the per-neighbour
+    arrays and hash in the global slab); every edge's 13 counts and the global counts equal
+    the closed forms (pinned against brute force in the oracle tests)."""
+    from closed_forms import cocktail_party, cocktail_party_counts
+    k = 3400
+    rp, col = cocktail_party(k)
+    X0, pe0 = cocktail_party_counts(k)
+    say(f"cocktail-party-{k} (out-degree above the LDS rows)")
+    X, pe = gpu(ctx, k, rp, col)
+    assert X == X0
+    m = col.size // 2
+    want = np.repeat(np.asarray(pe0, dtype=np.uint64)[:, None], m, axis=1)
+    np.testing.assert_array_equal(pe, want)
+    G, _ = gpu(ctx, k, rp, col, per_edge=False)
+    assert G == X0
 
 
 def test_list_orders_agree():

@@ -587,3 +587,16 @@ def test_per_edge_substructures_invariant_under_relabelling():
         x, y = sorted((int(perm[a]), int(perm[b])))
         emap[k] = e2[(x, y)]
     np.testing.assert_array_equal(s["per_edge"][:, emap], base["per_edge"])
+
+
+def test_cocktail_party_closed_form():
+    """The cocktail-party closed forms (tests/closed_forms.py, used at k = 3400 on the GPU)
+    against the brute-force definition."""
+    from closed_forms import cocktail_party, cocktail_party_counts
+    for k in (4, 6, 8, 10, 14):
+        rp, col = cocktail_party(k)
+        b = oracle.brute(k, rp, col, per_edge=True)
+        X, pe = cocktail_party_counts(k)
+        assert b["X"] == X, k
+        for s_ in range(13):
+            assert (b["per_edge"][s_] == pe[s_]).all(), (k, s_)
