@@ -515,7 +515,10 @@ __global__ __launch_bounds__(NT, 8) void k_tri_blk(const int* __restrict__ list,
                         if (jj >= 0) {
                             j = jj;
                             atomicOr(&M[i * W + (j >> 5)], 1u << (j & 31));
-                            atomicOr(&M[j * W + (i >> 5)], 1u << (i & 31));
+                            // rows in global memory are filled above the diagonal only (the
+                            // lanes of a run set bits of one row); the mirror bits follow by
+                            // tile transposes below
+                            if (!GM) atomicOr(&M[j * W + (i >> 5)], 1u << (i & 31));
                         }
                     }
                     if (REC) {   // one slot reservation per wavefront and entry batch
@@ -529,6 +532,31 @@ __global__ __launch_bounds__(NT, 8) void k_tri_blk(const int* __restrict__ list,
             }
         }
         __syncthreads();   // the run tables are rebuilt for the next chunk
+    }
+    if constexpr (GM) {
+        // M = U | U^T: every 32 x 32 bit tile (I, J), I <= J, of the upper part U is transposed
+        // by one wavefront (32 ballots) into its mirror tile (J, I), which only it writes (an
+        // off-diagonal mirror holds no bit yet; a diagonal tile ORs into itself)
+        const int TWn = (s + 31) >> 5;
+        const int npairs = TWn * (TWn + 1) / 2;
+        const int ln = glt_lane();
+        for (int p = tid / GLT_WAVE; p < npairs; p += NT / GLT_WAVE) {
+            int I = 0, rem = p;
+            while (rem >= TWn - I) { rem -= TWn - I; I++; }
+            const int J = I + rem;
+            const int r = 32 * I + (ln & 31);
+            u32 u = 0;
+            if (ln < 32 && r < s) u = M[(int64_t)r * W + J];
+            u32 tr = 0;
+#pragma unroll 8
+            for (int c = 0; c < 32; c++) {
+                const u32 b = (u32)__ballot((u >> c) & 1u);   // bit q: row 32I + q has column 32J + c
+                if (ln == c) tr = b;
+            }
+            const int rr = 32 * J + ln;
+            if (ln < 32 && rr < s) M[(int64_t)rr * W + I] = (I == J) ? (tr | u) : tr;
+        }
+        __syncthreads();
     }
     u64 k4 = 0;
     // 4-cliques of every triangle (a, b_i, b_j): popcount(M_i & M_j); each credits the
