@@ -386,8 +386,9 @@ def mean_timing(samples):
 
 
 def acc_width(max_degree):
-    """Width of the per-edge accumulators the library uses for this maximum degree."""
-    return 4 if max_degree <= 46340 else 8
+    """Width of the per-edge credits: 32-bit for every narrow edge (all edges when the maximum
+    degree is at most 46,340, all but a small suffix of the degree order otherwise)."""
+    return 4
 
 
 def host_cpu():
@@ -481,7 +482,15 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES, 3 times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters against a known traffic)")
+    ap.add_argument("--read-probe", type=int, default=0, metavar="BYTES",
+                    help="only run the library's read-only probe over BYTES (1 untimed + 3 timed launches): "
+                         "a second calibration point of FETCH_SIZE")
     args = ap.parse_args()
+    if args.read_probe:
+        import paper_1608_05138_amd as glt
+        ms, nbytes = glt.probe("read", args.read_probe, reps=3)
+        print(json.dumps({"read_probe_bytes": nbytes, "launches": 4, "ms_per_launch": ms}))
+        return
     if args.copy_probe:
         import torch
         src = torch.ones(args.copy_probe // 4, dtype=torch.int32, device="cuda:0")

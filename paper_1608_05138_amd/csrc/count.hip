@@ -922,6 +922,7 @@ __device__ __forceinline__ void wedge_bounds(int s, int lo, int hi, bool full, c
 #define WM_DW 1024
 #endif
 #define WB_T 256
+#define WB_RESIDENT 4    // resident workgroup-class groups per CU for the bottoms the mid class hands over
 #ifndef WB_HT
 #define WB_HT 2048
 #endif
@@ -1599,7 +1600,7 @@ __global__ __launch_bounds__(256) void k_fold_gsum(u64* __restrict__ gsum, int n
     const int t = threadIdx.x;
     // spread work counters: words 0, 1, 4, 5 wedges of the wave, workgroup, mid and huge
     // classes as bucketed, 2, 3 triangle-pass list entries per path, 6 wedges of bottoms that
-    // moved from the workgroup to the huge class
+    // moved from the workgroup to the huge class, 7 from the mid to the workgroup class
     __shared__ u64 wsum[WSPREAD_WORDS];
     if (t < WSPREAD_WORDS) {
         u64 v = 0;
@@ -1609,10 +1610,10 @@ __global__ __launch_bounds__(256) void k_fold_gsum(u64* __restrict__ gsum, int n
     __syncthreads();
     if (t == 0) {
         work[0] = wsum[0];
-        work[1] = wsum[1] - wsum[6];
+        work[1] = wsum[1] - wsum[6] + wsum[7];
         work[2] = wsum[2];
         work[3] = wsum[3];
-        work[6] = wsum[4];
+        work[6] = wsum[4] - wsum[7];
         work[7] = wsum[5] + wsum[6];
     }
     if (ngraphs <= 0) {
@@ -1704,20 +1705,40 @@ static inline int64_t gm_slab_words(int smax) {
     return w;
 }
 
+// Where a wedge class sends the bottoms whose distinct tops overflow its tables: a list, its
+// device counter, and the work counter that moves their wedges between classes.
+struct WedgeDefer {
+    int* list = nullptr;
+    int* cnt = nullptr;
+    u64* work = nullptr;
+};
+
 // One group per list entry (grid from the host's count), or, with `resident` blocks, a grid
-// that walks the list up to the device count at `dcount`; `defer` > 0 lets overflowing
-// entries move to the list of class `defer`.
+// that walks the list up to the device count at `dcount`; overflowing entries go to `df`.
 template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16 = false, int IL = WEDGE_ILP>
-static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st, int resident = 0, int defer = -1) {
+static void launch_wedge_list(const Dev& d, const int* list, int cnt, const int* dcount, hipStream_t st, int resident,
+                              WedgeDefer df, u64* tstamp) {
     if (cnt <= 0 && resident <= 0) return;
     const int limit = d.wedge_limit < HT / 2 ? d.wedge_limit : HT / 2;
-    int* counts = d.counts + TB_N;
     const unsigned grid = resident > 0 ? (unsigned)resident : cdiv(cnt, G);
-    hipLaunchKernelGGL((k_wedge<PE, AT, T, G, HT, DW, P16, IL>), dim3(grid), dim3(T * G), 0, st,
-                       d.wlist + (int64_t)bkt * d.n, cnt, d.n, limit, d.wedge_dense, d.nrp, d.wb, d.ocol,
-                       d.s2k, d.wcnt, d.e, d.gsum, d.ngid, d.gvb, d.err, resident > 0 ? counts + bkt : nullptr,
-                       defer >= 0 ? d.wlist + (int64_t)defer * d.n : nullptr, defer >= 0 ? counts + defer : nullptr,
-                       defer >= 0 ? d.wspread + 6 : nullptr, bkt == WB_BLK ? d.tstamp : nullptr);
+    hipLaunchKernelGGL((k_wedge<PE, AT, T, G, HT, DW, P16, IL>), dim3(grid), dim3(T * G), 0, st, list, cnt, d.n,
+                       limit, d.wedge_dense, d.nrp, d.wb, d.ocol, d.s2k, d.wcnt, d.e, d.gsum, d.ngid, d.gvb, d.err,
+                       resident > 0 ? dcount : nullptr, df.list, df.cnt, df.work, tstamp);
+}
+
+// One class's own list (grid from the host's count, or resident walking the device count),
+// overflowing bottoms sent to class `defer` (>= 0).
+template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16 = false, int IL = WEDGE_ILP>
+static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st, int resident = 0, int defer = -1) {
+    int* counts = d.counts + TB_N;
+    WedgeDefer df;
+    if (defer >= 0) {
+        df.list = d.wlist + (int64_t)defer * d.n;
+        df.cnt = counts + defer;
+        df.work = d.wspread + 6;
+    }
+    launch_wedge_list<PE, AT, T, G, HT, DW, P16, IL>(d, d.wlist + (int64_t)bkt * d.n, cnt, counts + bkt, st, resident,
+                                                     df, bkt == WB_BLK ? d.tstamp : nullptr);
 }
 
 // Events of one call (all recorded, also used to fork and join; the stream modes are
@@ -1740,11 +1761,20 @@ static void wedge_wave_class(const Dev& d, int per_edge, const int* hc, hipStrea
     (void)hipEventRecord(ev[6], s);
 }
 
+// The mid class hands a bottom whose distinct tops overflow its tables on the first try to
+// the workgroup class (appended after that class's own entries, counted in CNT_MID_TO_WG)
+// instead of splitting its top range: on R-MAT most such bottoms would need several splits,
+// each re-scanning their sources (mid class 40.7 -> 1.3 ms, workgroup class 44.5 -> 52 ms).
 template <typename AT>
 static void wedge_mid_class(const Dev& d, int per_edge, const int* hc, hipStream_t s, hipEvent_t* ev) {
     const int* wc = hc + TB_N;
-    if (per_edge) launch_wedge<true, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, WB_MID, wc[WB_MID], s);
-    else launch_wedge<false, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, WB_MID, wc[WB_MID], s);
+    WedgeDefer df;
+    df.list = d.wlist + (int64_t)WB_BLK * d.n + wc[WB_BLK];
+    df.cnt = d.counts + CNT_MID_TO_WG;
+    df.work = d.wspread + 7;
+    const int* lst = d.wlist + (int64_t)WB_MID * d.n;
+    if (per_edge) launch_wedge_list<true, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, lst, wc[WB_MID], nullptr, s, 0, df, nullptr);
+    else launch_wedge_list<false, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, lst, wc[WB_MID], nullptr, s, 0, df, nullptr);
     (void)hipEventRecord(ev[7], s);
 }
 
@@ -1753,10 +1783,24 @@ static void wedge_mid_class(const Dev& d, int per_edge, const int* hc, hipStream
 template <typename AT>
 static void wedge_large(const Dev& d, int per_edge, const int* hc, hipStream_t s, hipEvent_t* ev) {
     const int* wc = hc + TB_N;
-    const int huge_grid = (wc[WB_BLK] + wc[WB_HUGE] > 0) ? d.num_cu * WH_PER_CU : 0;
+    const int huge_grid = (wc[WB_MID] + wc[WB_BLK] + wc[WB_HUGE] > 0) ? d.num_cu * WH_PER_CU : 0;
     (void)hipEventRecord(ev[15], s);
     if (per_edge) launch_wedge<true, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
     else launch_wedge<false, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
+    if (wc[WB_MID] > 0) {
+        // the bottoms the mid class handed over: a resident grid walks them up to their device
+        // count (unknown to the host), overflowing ones go on to the huge class
+        WedgeDefer df;
+        df.list = d.wlist + (int64_t)WB_HUGE * d.n;
+        df.cnt = d.counts + TB_N + WB_HUGE;
+        df.work = d.wspread + 6;
+        const int* lst = d.wlist + (int64_t)WB_BLK * d.n + wc[WB_BLK];
+        const int res = d.num_cu * WB_RESIDENT;
+        if (per_edge)
+            launch_wedge_list<true, AT, WB_T, 1, WB_HT, WB_DW>(d, lst, 0, d.counts + CNT_MID_TO_WG, s, res, df, nullptr);
+        else
+            launch_wedge_list<false, AT, WB_T, 1, WB_HT, WB_DW>(d, lst, 0, d.counts + CNT_MID_TO_WG, s, res, df, nullptr);
+    }
     (void)hipEventRecord(ev[8], s);
     if (per_edge) launch_wedge<true, AT, WH_T, 1, WH_HT, WH_DW, false, WEDGE_ILP_HUGE>(d, WB_HUGE, wc[WB_HUGE], s, huge_grid);
     else launch_wedge<false, AT, WH_T, 1, WH_HT, WH_DW, false, WEDGE_ILP_HUGE>(d, WB_HUGE, wc[WB_HUGE], s, huge_grid);

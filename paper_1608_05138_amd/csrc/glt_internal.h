@@ -94,9 +94,11 @@ enum { LO_WORK = 0, LO_DEGREE = 1, LO_NONE = 2, LO_RANDOM = 3, LO_VOLUME = 4, LO
 enum { TB_WAVE = 0, TB_BLK1, TB_BLK2, TB_GLOBAL, TB_N };   // triangle / gather passes
 enum { WB_WAVE = 0, WB_MID, WB_BLK, WB_HUGE, WB_N };        // wedge pass
 // d.counts words: TB_N triangle-list counts, WB_N wedge-list counts, TB_N largest out-degrees
-// per triangle list, then the accumulator split point kw (EdgeArrays).
+// per triangle list, the accumulator split point kw (EdgeArrays), and the number of bottoms
+// the mid wedge class handed to the workgroup class (appended after the latter's own list).
 #define CNT_KW (TB_N + WB_N + TB_N)
-#define CNT_WORDS (CNT_KW + 1)
+#define CNT_MID_TO_WG (CNT_KW + 1)
+#define CNT_WORDS (CNT_KW + 2)
 
 // Device pointers of one graph's workspace.
 struct Dev {

@@ -68,7 +68,8 @@ __global__ __launch_bounds__(256) void k_check_rows(const RP* __restrict__ rp, i
     if (x < n) {
         b = (int64_t)rp[x];
         const int64_t e = (int64_t)rp[x + 1];
-        ok = b >= 0 && e >= b && e <= S;
+        // offsets non-decreasing inside [0, S], starting at 0 and ending at S = 2m
+        ok = b >= 0 && e >= b && e <= S && (x > 0 || b == 0) && (x < n - 1 || e == S);
         deg[x] = ok ? (int)(e - b) : 0;
     }
     const int bad = wave_or((x < n && !ok) ? ERR_RANGE : 0);
