@@ -479,6 +479,9 @@ def main():
     ap.add_argument("--global-only", action="store_true", help="skip per-edge output")
     ap.add_argument("--order-study", action="store_true",
                     help="also time each order of the workgroup work lists (reported as order_study)")
+    ap.add_argument("--host-path", action="store_true",
+                    help="also run the 4-cycle pass on the host's threads (glt_host_wedges) after the timed "
+                         "steps and report its rate beside the device's (the hybrid scheme's CPU share)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES, 3 times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters against a known traffic)")
@@ -537,6 +540,26 @@ def main():
     work = ctx.last_work()
     print(f"[bench] {ms_per_step:.3f} ms/step; kernel groups " +
           ", ".join(f"{k}={v:.3f}" for k, v in timing.items()), file=sys.stderr, flush=True)
+
+    host_path = None
+    if args.host_path and per_edge:
+        # Section 4.3's hybrid scheme on this machine: the host's threads run the 4-cycle pass of
+        # the same graph; a CPU share of the wedges could save at most that share of the device's
+        # wedge pass, and needs the relabelled graph on the host every step (the copy below)
+        print("[bench] host path: the 4-cycle pass on host threads", file=sys.stderr, flush=True)
+        hr = ctx.host_wedges(0)
+        dev_ms = sum(timing[k] for k in ("wedge_wave", "wedge_mid", "wedge_wg", "wedge_huge"))
+        host_rate = hr["wedges"] / (hr["count_ms"] * 1e-3)
+        dev_rate = hr["wedges"] / (dev_ms * 1e-3)
+        share = host_rate / (host_rate + dev_rate)
+        host_path = {"threads": hr["threads"], "host": host_cpu(), "wedges": hr["wedges"],
+                     "host_ms": round(hr["count_ms"], 1), "host_wedges_per_s": host_rate,
+                     "device_wedge_pass_ms": round(dev_ms, 3), "device_wedges_per_s": dev_rate,
+                     "best_host_share": share, "best_saving_ms": round(share * dev_ms, 3),
+                     "copy_bytes": hr["bytes_copied"], "copy_ms": round(hr["copy_ms"], 3),
+                     "cycles4_agree": hr["cycles4"] == hr["gpu_cycles4"] and hr["credit_sum"] == 4 * hr["cycles4"]}
+        print(f"[bench] host path: {host_path}", file=sys.stderr, flush=True)
+        assert host_path["cycles4_agree"], "host and device 4-cycle totals differ"
 
     maxdeg = int(np.diff(rp.astype(np.int64)).max()) if n else 0
     acc = acc_width(maxdeg)
@@ -621,6 +644,7 @@ def main():
         **({"side_workload": side} if side else {}),
         **({"order_study_ms_per_step": study} if study else {}),
         **({"other_stream_modes_ms_per_step": other} if other else {}),
+        **({"host_path": host_path} if host_path else {}),
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on a bounded sample", file=sys.stderr, flush=True)

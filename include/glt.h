@@ -257,6 +257,31 @@ glt_status glt_autotune_batch(glt_ctx* ctx, const glt_batch* b, glt_schedule* be
  */
 glt_status glt_probe(int device, int kind, size_t bytes, int reps, float* ms, uint64_t* ops);
 
+/*
+ * The 4-cycle (wedge) pass of the last successful single-graph glt_count on this handle,
+ * run again on host threads: the CPU worker of Section 4.3's hybrid scheme (CPU workers take
+ * jobs from the front of the ordered queue in small chunks; here bottoms in rank order, 16 at
+ * a time, to whichever thread is free), for measuring what a host share of the work would
+ * cost beside the device.  Counts nothing for the caller: the per-edge credits land in a
+ * scratch host array and only totals are reported.  Copies the relabelled graph it needs
+ * from the handle's device workspace (pinned host memory, allocated and freed by the call).
+ *   threads  host threads (<= 0: all hardware threads)
+ *   r        out: the report below
+ * Errors: GLT_E_INVALID_ARG (null argument, or no single-graph count on the handle since its
+ * creation or its last batch call), GLT_E_OOM (host memory), GLT_E_DEVICE.
+ */
+typedef struct {
+    int32_t threads;        /* host threads used                                            */
+    uint64_t wedges;        /* wedges y - w - x (x above y) visited, each once per sweep     */
+    uint64_t cycles4;       /* non-induced 4-cycles found: sum over (y, x) of C(c(y, x), 2)  */
+    uint64_t gpu_cycles4;   /* the same total from the device's wedge pass of that call      */
+    uint64_t credit_sum;    /* sum of the per-edge 4-cycle credits (4 x cycles4 if correct)  */
+    uint64_t bytes_copied;  /* bytes copied from the device (offsets, wedge ranges, columns) */
+    double copy_ms;         /* wall time of those copies                                    */
+    double count_ms;        /* wall time of both sweeps over every bottom vertex            */
+} glt_host_wedge_report;
+glt_status glt_host_wedges(glt_ctx* ctx, int threads, glt_host_wedge_report* r);
+
 /* ------------------------------------------------------------------------------------ */
 /* Request server: continuous batching of graph-count requests on one device.            */
 /* Requests are admitted in arrival order into a device-resident pool as its budget      */

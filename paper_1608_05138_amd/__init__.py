@@ -40,13 +40,19 @@ EXPORTS = ["glt_create", "glt_destroy", "glt_last_error", "glt_version", "glt_co
            "glt_last_timing", "glt_last_work", "glt_count_batch", "glt_server_create",
            "glt_server_submit", "glt_server_poll", "glt_server_inflight", "glt_server_clock",
            "glt_server_destroy", "glt_get_schedule", "glt_set_schedule", "glt_autotune_batch",
-           "glt_probe", "glt_count_noalloc"]
+           "glt_probe", "glt_count_noalloc", "glt_host_wedges"]
 
 
 class GltError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{STATUS.get(status, status)}: {message}")
         self.status = status
+
+
+class glt_host_wedge_report(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("wedges", ctypes.c_uint64), ("cycles4", ctypes.c_uint64),
+                ("gpu_cycles4", ctypes.c_uint64), ("credit_sum", ctypes.c_uint64),
+                ("bytes_copied", ctypes.c_uint64), ("copy_ms", ctypes.c_double), ("count_ms", ctypes.c_double)]
 
 
 class glt_u128(ctypes.Structure):
@@ -147,6 +153,8 @@ def load_library(path: str = LIB_PATH):
     lib.glt_count_noalloc.argtypes = [P, ctypes.POINTER(glt_csr), ctypes.c_uint32,
                                       ctypes.POINTER(glt_u128), P, P]
     lib.glt_count_noalloc.restype = ctypes.c_int
+    lib.glt_host_wedges.argtypes = [P, ctypes.c_int, ctypes.POINTER(glt_host_wedge_report)]
+    lib.glt_host_wedges.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -201,6 +209,15 @@ class Context:
         buf = (ctypes.c_uint64 * len(self.WORK_KEYS))()
         k = self._lib.glt_last_work(self._h, buf, len(self.WORK_KEYS))
         return {name: int(buf[i]) for i, name in enumerate(self.WORK_KEYS[:k])}
+
+    def host_wedges(self, threads: int = 0):
+        """glt_host_wedges: the wedge pass of the last single-graph count again on `threads`
+        host threads (0: every thread this process may use); a dict of the report's fields."""
+        r = glt_host_wedge_report()
+        rc = self._lib.glt_host_wedges(self._h, threads, ctypes.byref(r))
+        if rc != 0:
+            raise GltError(rc, self.last_error() or "glt_host_wedges failed")
+        return {name: getattr(r, name) for name, _ in glt_host_wedge_report._fields_}
 
     def count_noalloc(self, row_ptr, col, n: int | None = None, per_edge: bool = False, out=None,
                       stream=None):

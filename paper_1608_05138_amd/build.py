@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libglt.so")
-SOURCES = ["prep.hip", "count.hip", "api.hip", "server.hip", "probe.hip"]
+SOURCES = ["prep.hip", "count.hip", "api.hip", "server.hip", "probe.hip", "host_wedge.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -64,6 +64,9 @@ struct glt_ctx {
     size_t slab_bytes = 0;
     hipEvent_t ev_null = nullptr;      // orders the handle's stream after the legacy default stream
     void* scratch = nullptr;           // device address of this device's glt_count_noalloc workspace
+    Dev last;                          // device arrays of the last single-graph count (glt_host_wedges)
+    bool last_valid = false;
+    uint64_t last_cycles4 = 0;         // its wedge pass's 4-cycle total
 };
 
 #define GLT_VERSION "glt 0.2 (gfx950)"
@@ -469,6 +472,7 @@ glt_status glt_run_batch_ptrs(glt_ctx* ctx, int64_t B, const int64_t* vb, const 
                               const int* const* rp_ptrs, const int* const* col_ptrs, glt_u128* out,
                               hipStream_t st) {
     ctx->err.clear();
+    ctx->last_valid = false;
     for (int64_t g = 0; g < B; g++)
         if (vb[g + 1] < vb[g] || sb[g + 1] < sb[g] || ((sb[g + 1] - sb[g]) & 1))
             return fail(ctx, GLT_E_INVALID_ARG, "graph %lld: bases not monotone or odd slot count", (long long)g);
@@ -654,6 +658,7 @@ glt_status count_one(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 ou
                      uint64_t* out_per_edge, void* stream_, bool noalloc) {
     if (!ctx) return GLT_E_INVALID_ARG;
     ctx->err.clear();
+    ctx->last_valid = false;
     if (!g || !out_global) return fail(ctx, GLT_E_INVALID_ARG, "null graph or output");
     const bool per_edge = (flags & GLT_PER_EDGE) != 0;
     if (flags & ~(uint32_t)(GLT_GLOBAL | GLT_PER_EDGE)) return fail(ctx, GLT_E_INVALID_ARG, "unknown flags");
@@ -733,10 +738,22 @@ glt_status count_one(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 ou
     if (!globals(n, m, C, k4x3 / 3, (i128)gs[S_NC4], per_edge, X, why))
         return fail(ctx, GLT_E_INTERNAL, "global combination failed: %s", why.c_str());
     store_x(X, out_global);
+    ctx->last = d;
+    ctx->last_valid = !noalloc;
+    ctx->last_cycles4 = gs[S_NC4];
     return GLT_OK;
 }
 
 }  // namespace
+
+bool glt_last_graph(const glt_ctx* ctx, Dev* d, uint64_t* cycles4) {
+    if (!ctx || !ctx->last_valid) return false;
+    *d = ctx->last;
+    *cycles4 = ctx->last_cycles4;
+    return true;
+}
+
+int glt_ctx_device(const glt_ctx* ctx) { return ctx->device; }
 
 extern "C" {
 

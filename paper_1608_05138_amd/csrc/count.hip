@@ -101,6 +101,9 @@ __global__ __launch_bounds__(256) void k_unpack_tk(EdgeArrays e, int m) {
 #define TW_G 4         // wavefronts per block in the wavefront triangle and gather passes
 #endif
 #define TW_THREADS (TW_G * GLT_WAVE)
+#ifndef TRI_BIG_MINB
+#define TRI_BIG_MINB 1 // resident 1024-thread triangle workgroups per CU the registers are sized for
+#endif
 #ifndef TRI_ILP
 #define TRI_ILP 4      // out-list entries per lane in flight in the triangle passes (8: more registers, slower)
 #endif
@@ -270,6 +273,22 @@ __device__ __forceinline__ int bh_find(const int* hk, const unsigned short* hp, 
     }
 }
 
+// A bit filter over S in LDS ahead of the hash: most out-list entries of the neighbours are
+// not in S (on the R-MAT graph 97.5 % in the 65..256 bucket), and a clear bit rejects one
+// with a single read.  BITS bits, indexed by the top bits of a multiplicative hash; at most
+// 1/32 of them are set for out-degrees up to 256 and 1/51 up to 640.
+#ifndef TRI_FILTER
+#define TRI_FILTER 1
+#endif
+template <int NT>
+struct TriFilter {
+    static constexpr int BITS = NT <= 256 ? 8192 : 32768;
+    static constexpr int LG = NT <= 256 ? 13 : 15;
+    static constexpr int WORDS = TRI_FILTER ? BITS / 32 : 1;
+};
+template <int LG>
+__device__ __forceinline__ u32 fhash(int x) { return ((u32)x * 0x9E3779B1u) >> (32 - LG); }
+
 // Triangle records (REC): every triangle (a, b_i, b_j) found while the rows are built is
 // written as (k << 32 | j << 16 | i), k the oriented index of (b_i, b_j), into a's slots
 // [toff[a], toff[a] + C(|N+(a)|, 2)) (each pair i < j at most once), and tcnt[a] holds
@@ -435,7 +454,7 @@ __device__ __forceinline__ u64 row_and_count(const u32* M, int W, int i, int j) 
 // also the per-neighbour arrays and the hash there.  A launch takes the list entries with
 // out-degree <= smax, or with GX those above TB_LDS_SMAX (each group skips the rest).
 template <bool PE, bool GM, bool REC, typename AT, int NT, bool GX>
-__global__ __launch_bounds__(NT, 8) void k_tri_blk(const int* __restrict__ list, int nlist, int smax,
+__global__ __launch_bounds__(NT, NT <= 256 ? 8 : TRI_BIG_MINB) void k_tri_blk(const int* __restrict__ list, int nlist, int smax,
                                                        const int* __restrict__ optr, const int* __restrict__ ocol,
                                                        EdgeArrays e, u64* __restrict__ gsum,
                                                        u32* __restrict__ gscratch, int64_t gstride,
@@ -448,6 +467,7 @@ __global__ __launch_bounds__(NT, 8) void k_tri_blk(const int* __restrict__ list,
     __shared__ RunTables<NT> rt;
     __shared__ u64 sRed[NT / GLT_WAVE];
     __shared__ int sNrec;
+    __shared__ u32 sF[TriFilter<NT>::WORDS];
     const int a = list[blockIdx.x];
     const int o0 = optr[a];
     const int s = optr[a + 1] - o0;
@@ -466,9 +486,11 @@ __global__ __launch_bounds__(NT, 8) void k_tri_blk(const int* __restrict__ list,
     unsigned short* hp = (unsigned short*)(hk + HT);
     const int tid = threadIdx.x;
     const int W = tri_row_words(s, GM);
+    constexpr int FLG = TriFilter<NT>::LG;
     for (int q = tid; q < HT; q += NT) hk[q] = -1;
+    if (TRI_FILTER) for (int q = tid; q < TriFilter<NT>::WORDS; q += NT) sF[q] = 0;
     __syncthreads();
-    // S, its out-list offsets and lengths; S into the hash
+    // S, its out-list offsets and lengths; S into the hash and the filter
     for (int i = tid; i < s; i += NT) {
         const int b = ocol[o0 + i];
         const int ob = optr[b];
@@ -476,6 +498,10 @@ __global__ __launch_bounds__(NT, 8) void k_tri_blk(const int* __restrict__ list,
         u32 h = bhash(b, hmask);
         while (atomicCAS(&hk[h], -1, b) != -1) h = (h + 1) & hmask;
         hp[h] = (unsigned short)i;
+        if (TRI_FILTER) {
+            const u32 f = fhash<FLG>(b);
+            atomicOr(&sF[f >> 5], 1u << (f & 31));
+        }
     }
     for (int q = tid; q < s * W; q += NT) M[q] = 0;
     if (tid == 0) sNrec = 0;
@@ -510,7 +536,12 @@ __global__ __launch_bounds__(NT, 8) void k_tri_blk(const int* __restrict__ list,
                 for (int u = 0; u < TRI_ILP; u++) {
                     const int i = is[u];
                     int j = s;
-                    if (xs[u] >= 0) {
+                    bool maybe = xs[u] >= 0;
+                    if (TRI_FILTER && maybe) {
+                        const u32 f = fhash<FLG>(xs[u]);
+                        maybe = (sF[f >> 5] >> (f & 31)) & 1u;
+                    }
+                    if (maybe) {
                         const int jj = bh_find(hk, hp, hmask, xs[u]);   // x in S lies above b_i: jj > i
                         if (jj >= 0) {
                             j = jj;
@@ -898,10 +929,13 @@ __device__ __forceinline__ void wedge_bounds(int s, int lo, int hi, bool full, c
 #endif
 #define WEDGE_STACK 40   // x-range stack per group (halving depth <= 32 for 31-bit ids)
 #ifndef WEDGE_ILP
-#define WEDGE_ILP 4      // wedges in flight per lane (8 measured slower: registers)
+#define WEDGE_ILP 2      // wedges per lane and batch; two batches are in flight (4 per batch: slower)
 #endif
 #ifndef WEDGE_ILP_HUGE
-#define WEDGE_ILP_HUGE 4 // the same for the 1024-thread class (at most 128 registers per lane)
+#define WEDGE_ILP_HUGE 2 // the same for the 1024-thread class (at most 128 registers per lane)
+#endif
+#ifndef WEDGE_PF
+#define WEDGE_PF 1       // each sweep loads the next batch's tops before it works on the current one
 #endif
 
 // Size classes of the wedge pass (wedges per bottom vertex y): threads per group, groups per
@@ -972,6 +1006,35 @@ __device__ __forceinline__ u32 cnt_get(const u32* a, int i) {
     else return a[i];
 }
 
+// Tops x (ocol at the wedge's oriented index, -1 past the end) of the IL super-tile
+// positions q, q + T, ... of a sweep; with the oriented index k and the run (source) i too.
+// Every lane loads (lanes past the end at position se - 1, which exists while se > sb0), so
+// the number of loads in flight is fixed and a later wait can leave the next batch's loads
+// pending.
+template <int T, int IL>
+__device__ __forceinline__ void wedge_tops(const RunTables<T>& rt, const int* __restrict__ ocol, int sb0, int se,
+                                           int q, int (&xs)[IL]) {
+#pragma unroll
+    for (int j = 0; j < IL; j++, q += T) {
+        const int qc = min(q, se - 1);
+        const int x = ocol[qc + runs_at(rt, qc - sb0).x];
+        xs[j] = q < se ? x : -1;
+    }
+}
+template <int T, int IL>
+__device__ __forceinline__ void wedge_slots(const RunTables<T>& rt, const int* __restrict__ ocol, int sb0, int se,
+                                            int q, int (&xs)[IL], int (&ks)[IL], int (&is)[IL]) {
+#pragma unroll
+    for (int j = 0; j < IL; j++, q += T) {
+        const int qc = min(q, se - 1);
+        const int2 r = runs_at(rt, qc - sb0);
+        ks[j] = qc + r.x;
+        is[j] = r.y;
+        const int x = ocol[ks[j]];
+        xs[j] = q < se ? x : -1;
+    }
+}
+
 template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16, int IL>
 __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, int nlist, int n, int limit,
                                                  int dense, const int* __restrict__ nrp,
@@ -1020,6 +1083,9 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
     const int top = ngid ? (int)gvb[ngid[y] + 1] : n;
     const int base = max(top - min(dense, DW), y + 1);   // tops >= base are counted densely
     const int nd = top - base;                            // dense counters in use, <= DW
+    // a top's count is at most the row length (one wedge per source), so below 2^25 the
+    // wavefront prefix of 64 counts stays below 2^31
+    const bool scan32 = (re - rb) < (1 << 25);
     if (tid == 0) { s_lo[g][0] = y + 1; s_hi[g][0] = top; s_sp[g] = 1; }
     u64 c4 = 0;
     grp_sync<T>();
@@ -1037,6 +1103,47 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
         grp_sync<T>();
         // count sweep, over chunks of T sources; source tid of a chunk has `len` wedges
         u64 c4r = 0;
+        // the overflow flag, read from LDS (a volatile access through a generic pointer would
+        // be a flat load, which waits for every global load in flight)
+        auto ovf_set = [&]() {
+            return __hip_atomic_load(&s_ovf[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
+        };
+        // counts the tops of one batch (-1: no wedge)
+        auto count_batch = [&](const int (&xs)[IL]) {
+#pragma unroll
+            for (int j = 0; j < IL; j++) {
+                const int x = xs[j];
+                if (x < 0) continue;
+                if (x >= base) {
+                    if (NR) cnt_add<P16>(dc, x - base);
+                    else c4r += cnt_inc<P16>(dc, x - base);
+                } else {
+                    u32 h = hslot(x, mask);
+                    bool done = false;
+                    for (int p = 0; p < HT; p++) {   // bounded probe: a full table is an overflow
+                        int cur = hk[h];
+                        if (cur == -1) {
+                            cur = atomicCAS(&hk[h], -1, x);
+                            if (cur == -1) {
+                                if (NR) cnt_add<P16>(hc, (int)h);
+                                else c4r += cnt_inc<P16>(hc, (int)h);
+                                if (atomicAdd(&s_dist[g], 1) >= limit) s_ovf[g] = 1;
+                                done = true;
+                                break;
+                            }
+                        }
+                        if (cur == x) {
+                            if (NR) cnt_add<P16>(hc, (int)h);
+                            else c4r += cnt_inc<P16>(hc, (int)h);
+                            done = true;
+                            break;
+                        }
+                        h = (h + 1) & mask;
+                    }
+                    if (!done) s_ovf[g] = 1;
+                }
+            }
+        };
         int tot1 = 0, len = 0, pre = 0;
         for (int c0 = rb; c0 < re; c0 += T) {
             const int s = c0 + tid;
@@ -1048,46 +1155,21 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
             for (int sb0 = 0; sb0 < tot; sb0 += SPOS) {
                 if (sb0 > 0) runs_next<T>(rt, sb0, len, pre, carry);
                 const int se = min(tot, sb0 + SPOS);
-                for (int q0 = sb0; q0 < se; q0 += IL * T) {
-                    if (*(volatile int*)&s_ovf[g]) break;
-                    int xs[IL];
-#pragma unroll
-                    for (int j = 0; j < IL; j++) {
-                        const int q = q0 + j * T + tid;
-                        xs[j] = (q < se) ? ocol[q + runs_at(rt, q - sb0).x] : -1;
-                    }
-#pragma unroll
-                    for (int j = 0; j < IL; j++) {
-                        const int x = xs[j];
-                        if (x < 0) continue;
-                        if (x >= base) {
-                            if (NR) cnt_add<P16>(dc, x - base);
-                            else c4r += cnt_inc<P16>(dc, x - base);
-                        } else {
-                            u32 h = hslot(x, mask);
-                            bool done = false;
-                            for (int p = 0; p < HT; p++) {   // bounded probe: a full table is an overflow
-                                int cur = hk[h];
-                                if (cur == -1) {
-                                    cur = atomicCAS(&hk[h], -1, x);
-                                    if (cur == -1) {
-                                        if (NR) cnt_add<P16>(hc, (int)h);
-                                        else c4r += cnt_inc<P16>(hc, (int)h);
-                                        if (atomicAdd(&s_dist[g], 1) >= limit) s_ovf[g] = 1;
-                                        done = true;
-                                        break;
-                                    }
-                                }
-                                if (cur == x) {
-                                    if (NR) cnt_add<P16>(hc, (int)h);
-                                    else c4r += cnt_inc<P16>(hc, (int)h);
-                                    done = true;
-                                    break;
-                                }
-                                h = (h + 1) & mask;
-                            }
-                            if (!done) s_ovf[g] = 1;
-                        }
+                // batches of IL * T positions; with WEDGE_PF two batches alternate between two
+                // register sets, the next one's tops in flight while the current one is counted
+                int xa[IL], xb[IL];
+                wedge_tops<T, IL>(rt, ocol, sb0, se, sb0 + tid, xa);
+                for (int q0 = sb0; q0 < se; q0 += (WEDGE_PF ? 2 : 1) * IL * T) {
+                    if (ovf_set()) break;
+                    if constexpr (WEDGE_PF) {
+                        wedge_tops<T, IL>(rt, ocol, sb0, se, q0 + IL * T + tid, xb);
+                        count_batch(xa);
+                        if (q0 + IL * T >= se || ovf_set()) break;
+                        wedge_tops<T, IL>(rt, ocol, sb0, se, q0 + 2 * IL * T + tid, xa);
+                        count_batch(xb);
+                    } else {
+                        if (q0 > sb0) wedge_tops<T, IL>(rt, ocol, sb0, se, q0 + tid, xa);
+                        count_batch(xa);
                     }
                 }
             }
@@ -1123,6 +1205,56 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
             // credit sweep: the counts of this range are final.  With one chunk of sources in
             // one super-tile the count sweep's run tables are still in place.
             const bool one = (re - rb) <= T && tot1 <= SPOS;
+            // credits the wedges of one batch starting at position q0 (x = -1: no wedge; the
+            // lane still takes part in the wavefront's prefix sums)
+            auto credit_batch = [&](int q0, int sb0, int se, const int (&xs)[IL], const int (&ks)[IL],
+                                    const int (&is)[IL]) {
+#pragma unroll
+                for (int j = 0; j < IL; j++) {
+                    const int x = xs[j], kj = ks[j], ij = is[j];
+                    u32 c = 0;
+                    if (x >= 0) {
+                        u32 cnt = 1;
+                        if (x >= base) {
+                            cnt = cnt_get<P16>(dc, x - base);
+                        } else {
+                            u32 h = hslot(x, mask);
+                            int p = 0;
+                            while (p < HT && hk[h] != x) { h = (h + 1) & mask; p++; }
+                            if (p < HT) cnt = cnt_get<P16>(hc, (int)h);
+                            else atomicOr(err, ERR_CAP);
+                        }
+                        c = cnt - 1;
+                        if (NR) c4 += (u64)c;   // sums to 2 x sum over tops of C(c, 2)
+                    }
+                    // the wavefront's lanes cover one word of the run tables, whose start
+                    // bits (and every idle lane) delimit the sources
+                    const int qw = q0 + j * T + (tid & ~(GLT_WAVE - 1));
+                    const int idle = se - qw;   // lanes >= idle have no wedge
+                    u64 F = rt.msk[(qw - sb0) >> 6] | 1ull;
+                    if (idle <= 0) F = ~0ull;
+                    else if (idle < GLT_WAVE) F |= ~0ull << idle;
+                    const int l = glt_lane();
+                    const bool first = (F >> l) & 1;
+                    const bool last = (l == GLT_WAVE - 1) || (((F >> l) >> 1) & 1);
+                    if (c) acc_add<AT, ACC_P>(e, kj, (u64)c);   // top edge (w, x)
+                    // bottom edge (y, w): with P the wave's inclusive prefix of c, a
+                    // source's sum is P(last lane) - P(first lane - 1): its first lane
+                    // subtracts its exclusive prefix and its last lane adds its inclusive
+                    // one (modular arithmetic, exact once both have landed).  While the
+                    // row is short enough that 64 counts sum below 2^31 the prefix is
+                    // formed in 32 bits and each lane's term sign-extended.
+                    AT v;
+                    if (sizeof(AT) == 4 || scan32) {
+                        const u32 P = wave_incl_scan<u32>(c);
+                        v = (AT)(int64_t)(int32_t)((last ? P : 0u) - (first ? P - c : 0u));
+                    } else {
+                        const AT P = wave_incl_scan<AT>((AT)c);
+                        v = (last ? P : (AT)0) - (first ? (AT)(P - c) : (AT)0);
+                    }
+                    if (v) atomicAdd(&sb[ij], v);
+                }
+            };
             for (int c0 = rb; c0 < re; c0 += T) {
                 const int s = c0 + tid;
                 int tot = tot1, carry = 0;
@@ -1137,57 +1269,19 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
                 for (int sb0 = 0; sb0 < tot; sb0 += SPOS) {
                     if (sb0 > 0) runs_next<T>(rt, sb0, len, pre, carry);
                     const int se = min(tot, sb0 + SPOS);
-                    for (int q0 = sb0; q0 < se; q0 += IL * T) {
-                        int xs[IL], ks[IL], is[IL];
-#pragma unroll
-                        for (int j = 0; j < IL; j++) {
-                            const int q = q0 + j * T + tid;
-                            xs[j] = -1;
-                            is[j] = 0;
-                            ks[j] = 0;
-                            if (q < se) {
-                                const int2 r = runs_at(rt, q - sb0);
-                                ks[j] = q + r.x;
-                                is[j] = r.y;
-                                xs[j] = ocol[ks[j]];
-                            }
-                        }
-#pragma unroll
-                        for (int j = 0; j < IL; j++) {
-                            const int x = xs[j];
-                            AT c = 0;
-                            if (x >= 0) {
-                                u32 cnt = 1;
-                                if (x >= base) {
-                                    cnt = cnt_get<P16>(dc, x - base);
-                                } else {
-                                    u32 h = hslot(x, mask);
-                                    int p = 0;
-                                    while (p < HT && hk[h] != x) { h = (h + 1) & mask; p++; }
-                                    if (p < HT) cnt = cnt_get<P16>(hc, (int)h);
-                                    else atomicOr(err, ERR_CAP);
-                                }
-                                c = (AT)(cnt - 1);
-                                if (NR) c4 += (u64)c;   // sums to 2 x sum over tops of C(c, 2)
-                            }
-                            // the wavefront's lanes cover one word of the run tables, whose start
-                            // bits (and every idle lane) delimit the sources
-                            const int qw = q0 + j * T + (tid & ~(GLT_WAVE - 1));
-                            const int idle = se - qw;   // lanes >= idle have no wedge
-                            u64 F = rt.msk[(qw - sb0) >> 6] | 1ull;
-                            if (idle <= 0) F = ~0ull;
-                            else if (idle < GLT_WAVE) F |= ~0ull << idle;
-                            const int l = glt_lane();
-                            const bool first = (F >> l) & 1;
-                            const bool last = (l == GLT_WAVE - 1) || (((F >> l) >> 1) & 1);
-                            if (c) acc_add<AT, ACC_P>(e, ks[j], (u64)c);   // top edge (w, x)
-                            // bottom edge (y, w): with P the wave's inclusive prefix of c, a
-                            // source's sum is P(last lane) - P(first lane - 1): its first lane
-                            // subtracts its exclusive prefix and its last lane adds its inclusive
-                            // one (modular arithmetic, exact once both have landed)
-                            const AT P = wave_incl_scan<AT>(c);
-                            const AT v = (last ? P : (AT)0) - (first ? (AT)(P - c) : (AT)0);
-                            if (v) atomicAdd(&sb[is[j]], v);
+                    // the same two alternating register sets as the count sweep
+                    int xa[IL], ka[IL], ia[IL], xb[IL], kb[IL], ib[IL];
+                    wedge_slots<T, IL>(rt, ocol, sb0, se, sb0 + tid, xa, ka, ia);
+                    for (int q0 = sb0; q0 < se; q0 += (WEDGE_PF ? 2 : 1) * IL * T) {
+                        if constexpr (WEDGE_PF) {
+                            wedge_slots<T, IL>(rt, ocol, sb0, se, q0 + IL * T + tid, xb, kb, ib);
+                            credit_batch(q0, sb0, se, xa, ka, ia);
+                            if (q0 + IL * T >= se) break;
+                            wedge_slots<T, IL>(rt, ocol, sb0, se, q0 + 2 * IL * T + tid, xa, ka, ia);
+                            credit_batch(q0 + IL * T, sb0, se, xb, kb, ib);
+                        } else {
+                            if (q0 > sb0) wedge_slots<T, IL>(rt, ocol, sb0, se, q0 + tid, xa, ka, ia);
+                            credit_batch(q0, sb0, se, xa, ka, ia);
                         }
                     }
                 }

@@ -185,3 +185,9 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
 void glt_count_passes(const Dev& d, int per_edge, const int* host_counts, u64* out_pe,
                       hipStream_t st, hipStream_t side, hipEvent_t* ev /* NEV events, ev[0] recorded by the caller */,
                       int mode /* streams: 0 one, 1 wedge pass on `side`, 2 workgroup paths on `side` */);
+
+// The device arrays of the handle's last successful single-graph count (false if there is
+// none) and the 4-cycle total of its wedge pass; the handle's device.
+struct glt_ctx;
+bool glt_last_graph(const glt_ctx* ctx, Dev* d, uint64_t* cycles4);
+int glt_ctx_device(const glt_ctx* ctx);
