@@ -159,6 +159,14 @@ def load_library(path: str = LIB_PATH):
     return lib
 
 
+def batch_counts(raw):
+    """[B, 17, 2] uint64 (low, high) halves -> B lists of 17 Python ints."""
+    lo = raw[..., 0].reshape(-1).tolist()
+    hi = raw[..., 1].reshape(-1).tolist()
+    flat = [l | (h << 64) if h else l for l, h in zip(lo, hi)]
+    return [flat[17 * g: 17 * g + 17] for g in range(len(flat) // 17)]
+
+
 def _is_torch(x):
     return type(x).__module__.startswith("torch")
 
@@ -337,22 +345,24 @@ class Context:
         b = glt_batch(B, vb.ctypes.data, sb.ctypes.data, rp_ptr, col_ptr, 1 if dev else 0)
         return b, (vb, sb, rp, col), stream
 
-    def count_batch(self, packed, stream=None):
+    def count_batch(self, packed, stream=None, raw: bool = False):
         """Global counts of every graph of a packed batch.
 
         packed: dict with vtx_base, slot_base (int64 numpy, B+1), row_ptr (int32), col
         (int32); row_ptr/col may be torch CUDA tensors (device) or numpy arrays (host).
-        Returns a list of B lists of 17 Python ints.
+        Returns a list of B lists of 17 Python ints, or with raw=True the library's output
+        as it is: a numpy uint64 array [B, 17, 2] of (low, high) 64-bit halves (batch_counts()
+        turns it into the lists).
         """
         b, _keep, stream = self._batch_struct(packed, stream)
         B = int(b.num_graphs)
-        X = (glt_u128 * (17 * max(B, 1)))()
-        rc = self._lib.glt_count_batch(self._h, ctypes.byref(b), GLT_GLOBAL, X,
+        X = np.zeros((max(B, 1), 17, 2), dtype=np.uint64)
+        rc = self._lib.glt_count_batch(self._h, ctypes.byref(b), GLT_GLOBAL,
+                                       X.ctypes.data_as(ctypes.POINTER(glt_u128)),
                                        ctypes.c_void_p(stream) if stream else None)
         if rc != 0:
             raise GltError(rc, self.last_error())
-        flat = [int(x.lo) | (int(x.hi) << 64) for x in X]
-        return [flat[17 * g: 17 * g + 17] for g in range(B)]
+        return X[:B] if raw else batch_counts(X[:B])
 
 
 class Server:
