@@ -237,7 +237,7 @@ __host__ __device__ inline int tri_row_words(int s, bool gm) {
 }
 
 __host__ __device__ inline int tri_blk_ht(int smax) {
-    const int f = smax <= 256 ? TRI_HT_F : smax <= 640 ? TRI_HT_F2 : 2;
+    const int f = smax <= 256 ? TRI_HT_F : smax <= TB_LDS_ROWS ? TRI_HT_F2 : 2;
     int h = 64;
     while (h < f * smax) h <<= 1;
     return h;
@@ -276,7 +276,7 @@ __device__ __forceinline__ int bh_find(const int* hk, const unsigned short* hp, 
 // A bit filter over S in LDS ahead of the hash: most out-list entries of the neighbours are
 // not in S (on the R-MAT graph 97.5 % in the 65..256 bucket), and a clear bit rejects one
 // with a single read.  BITS bits, indexed by the top bits of a multiplicative hash; at most
-// 1/32 of them are set for out-degrees up to 256 and 1/51 up to 640.
+// 1/32 of them are set for out-degrees up to 256 and 1/36 up to 896.
 #ifndef TRI_FILTER
 #define TRI_FILTER 1
 #endif

@@ -92,6 +92,12 @@ enum { LO_WORK = 0, LO_DEGREE = 1, LO_NONE = 2, LO_RANDOM = 3, LO_VOLUME = 4, LO
 
 // Bucket ids for the vertex work lists.
 enum { TB_WAVE = 0, TB_BLK1, TB_BLK2, TB_GLOBAL, TB_N };   // triangle / gather passes
+// Largest out-degree whose adjacency rows the workgroup triangle pass keeps in LDS (bucket
+// TB_BLK2): 896 rows of 28 words, the hash, the per-neighbour arrays and the run tables of a
+// 1024-thread group fill about 152 KB of the CU's 160 KB.
+#ifndef TB_LDS_ROWS
+#define TB_LDS_ROWS 896
+#endif
 enum { WB_WAVE = 0, WB_MID, WB_BLK, WB_HUGE, WB_N };        // wedge pass
 // d.counts words: TB_N triangle-list counts, WB_N wedge-list counts, TB_N largest out-degrees
 // per triangle list, the accumulator split point kw (EdgeArrays), and the number of bottoms

@@ -553,7 +553,7 @@ __device__ __forceinline__ int tbucket(int s) {
     if (s < 2) return -1;
     if (s <= 64) return TB_WAVE;
     if (s <= 256) return TB_BLK1;
-    if (s <= 640) return TB_BLK2;
+    if (s <= TB_LDS_ROWS) return TB_BLK2;
     return TB_GLOBAL;
 }
 

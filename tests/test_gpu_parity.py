@@ -131,8 +131,9 @@ def _closed_complete(n):
 
 
 def test_complete_graph_global_bitmap_path(ctx):
-    # K_n: out-degrees up to n-1 > 640 use the global-memory bitmap rows
-    n = 760
+    # K_n: out-degrees 65..n-1 take every workgroup path: LDS bitmap rows up to 896, the
+    # global-memory rows above
+    n = 1000
     N, (rp, col) = gg.complete(n)
     say(f"complete-{n}")
     X, pe = gpu(ctx, N, rp, col)
