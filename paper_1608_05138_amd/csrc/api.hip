@@ -185,6 +185,7 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
     if (ngraphs > 0) {
         d.gid = c.take<int>(n);
         d.ngid = c.take<int>(n);
+        d.vtop = c.take<int>(n);
         d.gvb = c.take<int64_t>(ngraphs + 1);
         d.gsb = c.take<int64_t>(ngraphs + 1);
         d.gparts = c.take<u64>((int64_t)ngraphs * 13 * 2);
@@ -200,7 +201,7 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
     } else {
         d.erec = c.take<u64>(4 * (int64_t)m);
         d.vrec = c.take<u64>(4 * (int64_t)n);
-        d.gid = d.ngid = nullptr;
+        d.gid = d.ngid = d.vtop = nullptr;
         d.gvb = d.gsb = nullptr;
         d.gparts = nullptr;
         d.glrp = d.glcol = nullptr;

@@ -956,6 +956,12 @@ __device__ __forceinline__ void wedge_bounds(int s, int lo, int hi, bool full, c
 #define WM_DW 1024
 #endif
 #define WB_T 256
+#ifndef WB_MINB
+#define WB_MINB 1        // workgroup class: resident groups per CU the registers are sized for
+#endif
+#ifndef WEDGE_ILP_WG
+#define WEDGE_ILP_WG WEDGE_ILP
+#endif
 #define WB_RESIDENT 4    // resident workgroup-class groups per CU for the bottoms the mid class hands over
 #ifndef WB_HT
 #define WB_HT 2048
@@ -1036,13 +1042,13 @@ __device__ __forceinline__ void wedge_slots(const RunTables<T>& rt, const int* _
 }
 
 template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16, int IL>
-__global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, int nlist, int n, int limit,
+__global__ __launch_bounds__(T * G, T == WB_T ? WB_MINB : 1) void k_wedge(const int* __restrict__ list, int nlist, int n, int limit,
                                                  int dense, const int* __restrict__ nrp,
                                                  const int2* __restrict__ wb,
                                                  const int* __restrict__ ocol, const int* __restrict__ s2k,
                                                  const u64* __restrict__ wcnt, EdgeArrays e,
                                                  u64* __restrict__ gsum, const int* __restrict__ ngid,
-                                                 const int64_t* __restrict__ gvb, int* __restrict__ err,
+                                                 const int* __restrict__ vtop, int* __restrict__ err,
                                                  const int* __restrict__ dcount, int* __restrict__ defer_list,
                                                  int* __restrict__ defer_cnt, u64* __restrict__ defer_work,
                                                  u64* __restrict__ tstamp) {
@@ -1075,12 +1081,20 @@ __global__ __launch_bounds__(T * G) void k_wedge(const int* __restrict__ list, i
     int* hk = s_hk[g];
     u32* hc = s_hc[g];
     AT* sb = s_b[g];
+    // A group walking several entries loads the next entry's row bounds and the entry after
+    // that one ahead, while it works on the current one.  Tops lie above y inside y's
+    // graph: a batch keeps each graph's ranks contiguous, vtop holds the end.
+    int y1 = list[first];
+    int y2 = first + stride < count ? list[first + stride] : 0;
+    int rb1 = nrp[y1], re1 = nrp[y1 + 1], top1 = vtop ? vtop[y1] : n;
     for (int item = first; item < count; item += stride) {
     grp_sync<T>();   // the previous entry's last reads of the group's LDS are done
-    const int y = list[item];
-    const int rb = nrp[y], re = nrp[y + 1];
-    // tops lie above y inside y's graph: a batch keeps each graph's ranks contiguous
-    const int top = ngid ? (int)gvb[ngid[y] + 1] : n;
+    const int y = y1, rb = rb1, re = re1, top = top1;
+    if (item + stride < count) {
+        y1 = y2;
+        rb1 = nrp[y1]; re1 = nrp[y1 + 1]; top1 = vtop ? vtop[y1] : n;
+        if (item + 2 * stride < count) y2 = list[item + 2 * stride];
+    }
     const int base = max(top - min(dense, DW), y + 1);   // tops >= base are counted densely
     const int nd = top - base;                            // dense counters in use, <= DW
     // a top's count is at most the row length (one wedge per source), so below 2^25 the
@@ -1809,6 +1823,24 @@ struct WedgeDefer {
 
 // One group per list entry (grid from the host's count), or, with `resident` blocks, a grid
 // that walks the list up to the device count at `dcount`; overflowing entries go to `df`.
+// Resident grids (workgroups per CU; 0: one group per list entry).  A resident group walks
+// several list entries and loads the next entry's bounds while it counts the current one:
+// the wave class, whose bottoms have at most 128 wedges, spends most of an entry's time on
+// that chain of dependent loads (10,000-graph batch: 41 -> 7 ms).  The mid class measured
+// slower resident (38 -> 51..68 ms: its heavier entries, walked with a fixed stride, balance
+// worse than one group per entry).
+#ifndef WEDGE_RES_WAVE
+#define WEDGE_RES_WAVE 8
+#endif
+#ifndef WEDGE_RES_MID
+#define WEDGE_RES_MID 0
+#endif
+// Workgroups for a list of cnt entries, G per workgroup: one per entry up to `cap`.
+static inline int resident_grid(int cnt, int G, int cap) {
+    const int64_t need = ((int64_t)cnt + G - 1) / G;
+    return (int)(need < cap ? need : cap);
+}
+
 template <bool PE, typename AT, int T, int G, int HT, int DW, bool P16 = false, int IL = WEDGE_ILP>
 static void launch_wedge_list(const Dev& d, const int* list, int cnt, const int* dcount, hipStream_t st, int resident,
                               WedgeDefer df, u64* tstamp) {
@@ -1816,7 +1848,7 @@ static void launch_wedge_list(const Dev& d, const int* list, int cnt, const int*
     const int limit = d.wedge_limit < HT / 2 ? d.wedge_limit : HT / 2;
     const unsigned grid = resident > 0 ? (unsigned)resident : cdiv(cnt, G);
     hipLaunchKernelGGL((k_wedge<PE, AT, T, G, HT, DW, P16, IL>), dim3(grid), dim3(T * G), 0, st, list, cnt, d.n,
-                       limit, d.wedge_dense, d.nrp, d.wb, d.ocol, d.s2k, d.wcnt, d.e, d.gsum, d.ngid, d.gvb, d.err,
+                       limit, d.wedge_dense, d.nrp, d.wb, d.ocol, d.s2k, d.wcnt, d.e, d.gsum, d.ngid, d.vtop, d.err,
                        resident > 0 ? dcount : nullptr, df.list, df.cnt, df.work, tstamp);
 }
 
@@ -1850,8 +1882,9 @@ static void launch_wedge(const Dev& d, int bkt, int cnt, hipStream_t st, int res
 template <typename AT>
 static void wedge_wave_class(const Dev& d, int per_edge, const int* hc, hipStream_t s, hipEvent_t* ev) {
     const int* wc = hc + TB_N;
-    if (per_edge) launch_wedge<true, AT, WW_T, WW_G, WW_HT, 0, false>(d, WB_WAVE, wc[WB_WAVE], s);
-    else launch_wedge<false, AT, WW_T, WW_G, WW_HT, 0>(d, WB_WAVE, wc[WB_WAVE], s);
+    const int res = wc[WB_WAVE] > 0 ? resident_grid(wc[WB_WAVE], WW_G, d.num_cu * WEDGE_RES_WAVE) : 0;
+    if (per_edge) launch_wedge<true, AT, WW_T, WW_G, WW_HT, 0, false>(d, WB_WAVE, wc[WB_WAVE], s, res);
+    else launch_wedge<false, AT, WW_T, WW_G, WW_HT, 0>(d, WB_WAVE, wc[WB_WAVE], s, res);
     (void)hipEventRecord(ev[6], s);
 }
 
@@ -1867,8 +1900,10 @@ static void wedge_mid_class(const Dev& d, int per_edge, const int* hc, hipStream
     df.cnt = d.counts + CNT_MID_TO_WG;
     df.work = d.wspread + 7;
     const int* lst = d.wlist + (int64_t)WB_MID * d.n;
-    if (per_edge) launch_wedge_list<true, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, lst, wc[WB_MID], nullptr, s, 0, df, nullptr);
-    else launch_wedge_list<false, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, lst, wc[WB_MID], nullptr, s, 0, df, nullptr);
+    const int* dc = d.counts + TB_N + WB_MID;
+    const int res = wc[WB_MID] > 0 ? resident_grid(wc[WB_MID], WM_G, d.num_cu * WEDGE_RES_MID) : 0;
+    if (per_edge) launch_wedge_list<true, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, lst, wc[WB_MID], dc, s, res, df, nullptr);
+    else launch_wedge_list<false, AT, WM_T, WM_G, WM_HT, WM_DW, true>(d, lst, wc[WB_MID], dc, s, res, df, nullptr);
     (void)hipEventRecord(ev[7], s);
 }
 
@@ -1879,8 +1914,8 @@ static void wedge_large(const Dev& d, int per_edge, const int* hc, hipStream_t s
     const int* wc = hc + TB_N;
     const int huge_grid = (wc[WB_MID] + wc[WB_BLK] + wc[WB_HUGE] > 0) ? d.num_cu * WH_PER_CU : 0;
     (void)hipEventRecord(ev[15], s);
-    if (per_edge) launch_wedge<true, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
-    else launch_wedge<false, AT, WB_T, 1, WB_HT, WB_DW>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
+    if (per_edge) launch_wedge<true, AT, WB_T, 1, WB_HT, WB_DW, false, WEDGE_ILP_WG>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
+    else launch_wedge<false, AT, WB_T, 1, WB_HT, WB_DW, false, WEDGE_ILP_WG>(d, WB_BLK, wc[WB_BLK], s, 0, WB_HUGE);
     if (wc[WB_MID] > 0) {
         // the bottoms the mid class handed over: a resident grid walks them up to their device
         // count (unknown to the host), overflowing ones go on to the huge class
@@ -1891,9 +1926,9 @@ static void wedge_large(const Dev& d, int per_edge, const int* hc, hipStream_t s
         const int* lst = d.wlist + (int64_t)WB_BLK * d.n + wc[WB_BLK];
         const int res = d.num_cu * WB_RESIDENT;
         if (per_edge)
-            launch_wedge_list<true, AT, WB_T, 1, WB_HT, WB_DW>(d, lst, 0, d.counts + CNT_MID_TO_WG, s, res, df, nullptr);
+            launch_wedge_list<true, AT, WB_T, 1, WB_HT, WB_DW, false, WEDGE_ILP_WG>(d, lst, 0, d.counts + CNT_MID_TO_WG, s, res, df, nullptr);
         else
-            launch_wedge_list<false, AT, WB_T, 1, WB_HT, WB_DW>(d, lst, 0, d.counts + CNT_MID_TO_WG, s, res, df, nullptr);
+            launch_wedge_list<false, AT, WB_T, 1, WB_HT, WB_DW, false, WEDGE_ILP_WG>(d, lst, 0, d.counts + CNT_MID_TO_WG, s, res, df, nullptr);
     }
     (void)hipEventRecord(ev[8], s);
     if (per_edge) launch_wedge<true, AT, WH_T, 1, WH_HT, WH_DW, false, WEDGE_ILP_HUGE>(d, WB_HUGE, wc[WB_HUGE], s, huge_grid);

@@ -159,6 +159,7 @@ struct Dev {
     int ngraphs;          // 0 for a single graph
     int* gid;             // original vertex -> graph (batched mode)
     int* ngid;            // relabelled vertex -> graph (batched mode), else null
+    int* vtop;            // relabelled vertex -> end of its graph's rank range (batched mode), else null
     u64* gsum;            // [max(1, ngraphs)][NSUMS] 4-clique / 4-cycle accumulators
     const int64_t* gvb;   // device copy of the per-graph vertex bases [ngraphs+1]
     const int64_t* gsb;   // device copy of the per-graph slot bases [ngraphs+1]

@@ -204,11 +204,14 @@ __global__ void k_iota_keys(const int* __restrict__ deg, const int* __restrict__
     }
 }
 
-// Rank i -> original id; also appends i to the list of its row's sort class.
+// Rank i -> original id; also appends i to the list of its row's sort class.  In a batch
+// also rank i's graph and the end of that graph's rank range (graphs keep contiguous ranges,
+// the ones their packed vertices had).
 __global__ __launch_bounds__(256) void k_apply_order(const u32* __restrict__ sorted_ids, const int* __restrict__ deg,
                                                      int n, int* __restrict__ order, int* __restrict__ rank,
                                                      int* __restrict__ ndeg, const int* __restrict__ gid,
-                                                     int* __restrict__ ngid, int* __restrict__ rlist,
+                                                     int* __restrict__ ngid, const int64_t* __restrict__ gvb,
+                                                     int* __restrict__ vtop, int* __restrict__ rlist,
                                                      int* __restrict__ rcnt) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     int cls = -1;
@@ -217,7 +220,10 @@ __global__ __launch_bounds__(256) void k_apply_order(const u32* __restrict__ sor
         order[i] = x;
         rank[x] = i;
         ndeg[i] = deg[x];
-        if (ngid) ngid[i] = gid[x];
+        if (ngid) {
+            ngid[i] = gid[x];
+            vtop[i] = (int)gvb[gid[x] + 1];
+        }
         cls = row_class(deg[x]);
     }
     block_append<RS_N>(rcnt, rlist, n, cls, i);
@@ -685,7 +691,7 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
     int* rlist = d.tlist;
     int* rcnt = d.err + 2 + RS_N;
     hipLaunchKernelGGL(k_apply_order, dim3(nblk(n, 256)), dim3(256), 0, st, cur ? d.val1 : d.val0, d.deg, n,
-                       d.order, d.rank, d.ndeg, d.gid, d.ngid, rlist, rcnt);
+                       d.order, d.rank, d.ndeg, d.gid, d.ngid, d.gvb, d.vtop, rlist, rcnt);
     // relabelled CSR offsets
     launch_excl_scan<int, int>(d.ndeg, d.nrp, n, d.itmp, d.nrp + n, st);
     // P2: entries placed in their relabelled rows, then every row sorted by neighbour rank
