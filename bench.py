@@ -23,16 +23,27 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 
-# Measured HBM traffic (bytes per execution of each kernel group) per workload, per-edge run:
+# Measured HBM traffic (bytes per execution of each kernel group: FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0, summed over the group's launches in one step) per workload, per-edge run:
 # rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, each a separate run of
-# `python3 bench.py --workload W --steps 1 --warmup 0 --no-cpu-baseline --no-side-workload
-# --no-probe`, scaled by the copy calibration (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0; see
-# --copy-probe).  The figures belong to the kernel sources with the hash below and are
-# reported only while they are unchanged.
-TRAFFIC_SOURCES = ["paper_1608_05138_amd/csrc/count.hip", "paper_1608_05138_amd/csrc/prep.hip"]
+# `python3 bench.py --workload W --steps 1 --warmup 0 --no-cpu-baseline [--no-side-workload]
+# --no-probe`.  The scales come from two calibration points: a 1 GiB device copy
+# (--copy-probe) reads FETCH_SIZE = 0.5 GiB and writes WRITE_SIZE = 1.0 GiB, and the
+# library's read-only probe over 1 GiB (--read-probe) reads FETCH_SIZE = 0.5 GiB.  The
+# figures belong to the kernel sources with the hash below and are reported only while
+# they are unchanged.
+TRAFFIC_SOURCES = ["paper_1608_05138_amd/csrc/count.hip", "paper_1608_05138_amd/csrc/prep.hip",
+                   "paper_1608_05138_amd/csrc/glt_internal.h", "paper_1608_05138_amd/csrc/prims.h"]
 TRAFFIC = {
-    "sha256": None,
-    "workloads": {},
+    "sha256": "2669a419c96a2af56df626469d57c408e147bcf493ee101517654319ed2e1a00",
+    "workloads": {
+        "rmat_s22": {"tri_wave": 26739623200, "tri_wg": 168681596928, "gather_wave": 3126250880,
+                     "gather_wg": 110024189184, "wedge_wave": 73574816, "wedge_mid": 3709879456,
+                     "wedge_wg": 74304967040, "wedge_huge": 458432498080},
+        "chung_lu_1m": {"tri_wave": 3313441440, "tri_wg": 3931819744, "gather_wave": 1484918272,
+                        "gather_wg": 2892998592, "wedge_wave": 82198720, "wedge_mid": 3526660064,
+                        "wedge_wg": 8912782528, "wedge_huge": 39936},
+    },
 }
 
 
@@ -232,7 +243,9 @@ def bench_batch(args):
     ctx = glt.Context(0)
     stream = torch.cuda.current_stream(dev).cuda_stream
     tuned = None
-    if not args.no_autotune:
+    if args.schedule:
+        ctx.set_schedule(**parse_schedule(args.schedule))
+    elif not args.no_autotune:
         # the schedule is picked on a separate draw of the same mix (other seeds), not on the
         # timed graphs
         _, tgraphs = gen_batch(args.tune_graphs, base=gg.BASE_SEED + 1003)
@@ -383,6 +396,16 @@ def atomic_rate(nbytes, wide):
                     f"wavefront over {max(int(nbytes), 1 << 20)} bytes, {ms:.3f} ms per launch"}
 
 
+def parse_schedule(spec):
+    """'k=v,k=v' -> {k: int(v)} (schedule fields by their glt_schedule names)."""
+    out = {}
+    for item in (spec or "").split(","):
+        if item.strip():
+            k, v = item.split("=")
+            out[k.strip()] = int(v)
+    return out
+
+
 def mean_timing(samples):
     keys = samples[0].keys()
     return {k: sum(t[k] for t in samples) / len(samples) for k in keys}
@@ -476,6 +499,9 @@ def main():
     ap.add_argument("--no-probe", action="store_true", help="skip the atomic-rate calibration of the roofline")
     ap.add_argument("--compare-modes", action="store_true",
                     help="single graph: also time the other stream modes (reported beside the line)")
+    ap.add_argument("--schedule", default=None, metavar="K=V,...",
+                    help="set schedule fields (glt_schedule names, e.g. wedge_stream=1,list_order=1) before timing; "
+                         "for the batch it replaces the autotuner")
     ap.add_argument("--stream-mode", type=int, default=None, choices=[0, 1, 2],
                     help="single graph: the schedule's stream mode (default: the library's, 2 = workgroup "
                          "triangle/gather paths beside the wavefront paths, 4-cycle pass alone)")
@@ -534,6 +560,8 @@ def main():
     per_edge = not args.global_only
     out = torch.empty((13, m), dtype=torch.int64, device=dev) if per_edge else None
     ctx = glt.Context(0)
+    if args.schedule:
+        ctx.set_schedule(**parse_schedule(args.schedule))
     if args.stream_mode is not None:
         ctx.set_schedule(wedge_stream=args.stream_mode)
     mode = ctx.schedule()["wedge_stream"]

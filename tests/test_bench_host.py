@@ -81,3 +81,9 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert p.returncode == 2
     assert "one GPU only" in p.stderr
+
+
+def test_parse_schedule():
+    assert bench.parse_schedule("wedge_stream=1, list_order=1") == {"wedge_stream": 1, "list_order": 1}
+    assert bench.parse_schedule("") == {}
+    assert bench.parse_schedule(None) == {}
