@@ -35,14 +35,14 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 TRAFFIC_SOURCES = ["paper_1608_05138_amd/csrc/count.hip", "paper_1608_05138_amd/csrc/prep.hip",
                    "paper_1608_05138_amd/csrc/glt_internal.h", "paper_1608_05138_amd/csrc/prims.h"]
 TRAFFIC = {
-    "sha256": "2669a419c96a2af56df626469d57c408e147bcf493ee101517654319ed2e1a00",
+    "sha256": "0a54f6707b850f58a7c75e8c7507223da5a6c937d0055e9e8e075f1c81fb79f8",
     "workloads": {
-        "rmat_s22": {"tri_wave": 26739623200, "tri_wg": 168681596928, "gather_wave": 3126250880,
-                     "gather_wg": 110024189184, "wedge_wave": 73574816, "wedge_mid": 3709879456,
-                     "wedge_wg": 74304967040, "wedge_huge": 458432498080},
-        "chung_lu_1m": {"tri_wave": 3313441440, "tri_wg": 3931819744, "gather_wave": 1484918272,
-                        "gather_wg": 2892998592, "wedge_wave": 82198720, "wedge_mid": 3526660064,
-                        "wedge_wg": 8912782528, "wedge_huge": 39936},
+        "rmat_s22": {"tri_wave": 26740285088, "tri_wg": 168627777376, "gather_wave": 3126267008,
+                     "gather_wg": 109913303296, "wedge_wave": 73619104, "wedge_mid": 3709839648,
+                     "wedge_wg": 75417677216, "wedge_huge": 458867245728},
+        "chung_lu_1m": {"tri_wave": 3309036288, "tri_wg": 3938143072, "gather_wave": 1483896192,
+                        "gather_wg": 2899442304, "wedge_wave": 82338752, "wedge_mid": 3525807680,
+                        "wedge_wg": 9052629696, "wedge_huge": 25600},
     },
 }
 
