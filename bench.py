@@ -33,16 +33,17 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # figures belong to the kernel sources with the hash below and are reported only while
 # they are unchanged.
 TRAFFIC_SOURCES = ["paper_1608_05138_amd/csrc/count.hip", "paper_1608_05138_amd/csrc/prep.hip",
-                   "paper_1608_05138_amd/csrc/glt_internal.h", "paper_1608_05138_amd/csrc/prims.h"]
+                   "paper_1608_05138_amd/csrc/glt_internal.h", "paper_1608_05138_amd/csrc/prims.h",
+                   "paper_1608_05138_amd/csrc/api.hip"]   # api.hip: the schedule the call runs with
 TRAFFIC = {
-    "sha256": "0a54f6707b850f58a7c75e8c7507223da5a6c937d0055e9e8e075f1c81fb79f8",
+    "sha256": "3338c8c8fc46eb9b9c46cfc1c9ef824fba3351bbd7ff2342dba50a5795fc799b",
     "workloads": {
-        "rmat_s22": {"tri_wave": 26740285088, "tri_wg": 168627777376, "gather_wave": 3126267008,
-                     "gather_wg": 109913303296, "wedge_wave": 73619104, "wedge_mid": 3709839648,
-                     "wedge_wg": 75417677216, "wedge_huge": 458867245728},
-        "chung_lu_1m": {"tri_wave": 3309036288, "tri_wg": 3938143072, "gather_wave": 1483896192,
-                        "gather_wg": 2899442304, "wedge_wave": 82338752, "wedge_mid": 3525807680,
-                        "wedge_wg": 9052629696, "wedge_huge": 25600},
+        "rmat_s22": {"tri_wave": 26746283424, "tri_wg": 171645890432, "gather_wave": 3124859776,
+                     "gather_wg": 111810584160, "wedge_wave": 73580064, "wedge_mid": 3705513568,
+                     "wedge_wg": 81626489792, "wedge_huge": 464976236064},
+        "chung_lu_1m": {"tri_wave": 3311582688, "tri_wg": 3935939552, "gather_wave": 1486274048,
+                        "gather_wg": 2901324736, "wedge_wave": 82283200, "wedge_mid": 3526249728,
+                        "wedge_wg": 9001283008, "wedge_huge": 25600},
     },
 }
 
@@ -310,7 +311,8 @@ def bench_batch(args):
         "work": work,
         "autotune": tuned,
         "schedule": ctx.schedule(),
-        "roofline": roofline(timing, work, False, acc_width(maxdeg)),
+        "roofline": roofline(timing, work, False, acc_width(maxdeg),
+                             prep=prep_bytes(int(packed["vtx_base"][-1]), m_total, 4)),
     }
     ctx.close()
     print(json.dumps(line), flush=True)
@@ -394,6 +396,19 @@ def atomic_rate(nbytes, wide):
     return {"rate": ops / (ms * 1e-3),
             "what": f"glt_probe {kind}: {ops} atomic adds of {'64' if wide else '32'}-bit words in runs of 64 per "
                     f"wavefront over {max(int(nbytes), 1 << 20)} bytes, {ms:.3f} ms per launch"}
+
+
+AUTO_LARGE_EDGES = 1 << 25   # the library's automatic schedule: see glt_schedule in include/glt.h
+
+
+def resolved_schedule(sched, m, batch=False):
+    """The stream mode and list order a call runs with: the schedule's, or (-1) the library's
+    automatic choice (mode 2; largest degree first for a single graph of >= 2^25 edges, else
+    the bucketing order)."""
+    large = not batch and m >= AUTO_LARGE_EDGES
+    mode = sched["wedge_stream"] if sched["wedge_stream"] >= 0 else 2
+    order = sched["list_order"] if sched["list_order"] >= 0 else (1 if large else 2)
+    return {"wedge_stream": mode, "list_order": order}
 
 
 def parse_schedule(spec):
@@ -669,6 +684,7 @@ def main():
                    "outputs": "global X1..X17 (u128) + 13 per-edge counts (u64)" if per_edge
                    else "global X1..X17 (u128)"},
         "schedule": ctx.schedule(),
+        "schedule_resolved": resolved_schedule(ctx.schedule(), m),
         "kernel_groups_ms": {k: round(float(v), 4) for k, v in timing.items()},
         "work": work,
         "roofline": roof,

@@ -160,8 +160,9 @@ glt_status glt_count_batch(glt_ctx* ctx, const glt_batch* b, uint32_t flags, glt
  * [1] triangle / 4-clique pass, one wavefront per vertex, [2] the same, one workgroup per
  * vertex, [3] per-edge gather pass, wavefront path, [4] the same, workgroup path,
  * [5]-[8] 4-cycle wedge pass, wave / mid / workgroup / huge class, [9] vertex sums, combine
- * and reduction, [10] the whole call.  With the schedule's wedge_stream = 1 the wedge pass
- * runs on a second stream beside entries [1]-[4]; with wedge_stream = 2 entries [2] and [4]
+ * and reduction, [10] the whole call.  In stream mode 1 (the schedule's wedge_stream, or its
+ * automatic choice) the wedge pass runs on a second stream beside entries [1]-[4]; in mode 2
+ * entries [2] and [4]
  * run beside [1] and [3], and [6] (mid class, second stream) beside [5] (wave class, after
  * the vertex sums on the call's stream); overlapping entries share the chip.  Returns the
  * number of entries written (<= cap, at most 11).
@@ -187,7 +188,7 @@ int glt_last_work(const glt_ctx* ctx, uint64_t* out, int cap);
  * Work schedule of a handle: how the counting passes split their work among size classes
  * (Section 4.3 splits edges by cost between workers; here vertices are split by their work
  * between wavefront and workgroup kernels).  Every schedule yields the same counts; only
- * the speed differs.  Defaults: 128, 2048, 16384, 4096, 1, 2^30, 2, 2, 0.
+ * the speed differs.  Defaults: 128, 2048, 16384, 4096, 1, 2^30, -1, -1, 0.
  */
 typedef struct {
     int32_t wedge_wave_max;    /* 4-cycle pass: bottom vertices with at most this many wedges
@@ -208,13 +209,15 @@ typedef struct {
                                   passes; 2 the workgroup paths of the triangle and gather
                                   passes on a second stream beside their wavefront paths,
                                   then the mid 4-cycle class there beside the vertex sums
-                                  and the wave class, the larger classes alone after both   */
+                                  and the wave class, the larger classes alone after both;
+                                  -1 (default): 2                                              */
     int32_t list_order;        /* order of the workgroup work lists (Section 4.3's edge order,
                                   Table 4's ordering study): 0 largest work first, 1 largest
-                                  degree first, 2 ascending rank (no sort; the default),
-                                  3 pseudo-random, 4 largest volume first (volume: the sum
-                                  of the neighbours' degrees), 5 smallest degree first,
-                                  6 smallest volume first                                     */
+                                  degree first, 2 ascending rank (no sort), 3 pseudo-random,
+                                  4 largest volume first (volume: the sum of the neighbours'
+                                  degrees), 5 smallest degree first, 6 smallest volume first;
+                                  -1 (default) chosen per call: 1 for a single graph of at
+                                  least 2^25 edges, else 2                                   */
     int32_t record_balance;    /* 1: time when each entry of the 4-cycle pass's workgroup-class
                                   list is done (one clock read per entry) and report the
                                   spread in glt_last_work entries [10], [11]; 0: off         */

@@ -51,13 +51,13 @@ struct glt_ctx {
     size_t trec_bytes = 0;
     size_t trec_cap = 0;               // largest record buffer the handle allocates
     int tri_records = 1;               // schedule: use triangle records when they fit
-    int wedge_stream = 2;              // schedule: stream mode (0 one stream: each kernel group has
+    int wedge_stream = -1;             // schedule: stream mode (-1 chosen per call, see resolve_schedule;
+                                       // 0 one stream: each kernel group has
                                        // the chip alone; 1 wedge pass on the side stream; 2 the
                                        // workgroup triangle / gather paths on the side stream, the
                                        // wedge pass alone)
-    int list_order = LO_NONE;          // schedule: order of the workgroup work lists (LO_*); with the
-                                       // second stream filling idle CUs, skipping the sort measured
-                                       // fastest (Chung-Lu 18.40 vs 18.67 ms, R-MAT 678 vs 688 ms)
+    int list_order = -1;               // schedule: order of the workgroup work lists (LO_*; -1 chosen
+                                       // per call, see resolve_schedule)
     int last_mode = 0;                 // the stream mode the last call's timing was taken in
     int wide_degree = 0;               // GLT_WIDE_DEGREE (tests): widen edges from this lower-endpoint degree
     void* slab = nullptr;              // larger global slab for the highest out-degrees (grown on demand)
@@ -348,6 +348,19 @@ u64* ensure_trec(glt_ctx* ctx, u64 slots, hipStream_t st) {
     return (u64*)ctx->trec;
 }
 
+// The schedule's automatic fields (-1): stream mode 2, and the work lists of a single graph
+// of at least 2^25 edges ordered largest degree first, of smaller graphs and batches left in
+// the bucketing order.  Measured: R-MAT scale 22 (6.4*10^7 edges) 414 ms in rank order, 406
+// with degree order; the Chung-Lu graph (10^7 edges) 17.1 ms in rank order, 17.6 with degree
+// order.  (Mode 1 takes R-MAT to 402-404 ms, but shares the chip between the triangle and
+// wedge passes, so no kernel's time is its own; it stays a schedule choice.)
+#define GLT_AUTO_LARGE_EDGES (1 << 25)
+void resolve_schedule(const glt_ctx* ctx, const Dev& d, int& mode, int& order) {
+    const bool large = d.ngraphs == 0 && d.m >= GLT_AUTO_LARGE_EDGES;
+    mode = ctx->wedge_stream >= 0 ? ctx->wedge_stream : 2;
+    order = ctx->list_order >= 0 ? ctx->list_order : (large ? LO_DEGREE : LO_NONE);
+}
+
 // Validation, preprocessing and the counting passes on a prepared CSR (rp, col) on the
 // device.  Host read-backs: validation flags after the row check and after the build.
 glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const int* col, bool per_edge,
@@ -357,7 +370,8 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
     d.wedge_mid_max = ctx->wedge_mid_max;
     d.wedge_wg_max = ctx->wedge_wg_max;
     d.num_cu = ctx->num_cu;
-    d.list_order = ctx->list_order;
+    int mode = 0;
+    resolve_schedule(ctx, d, mode, d.list_order);
     d.wedge_limit = ctx->wedge_limit;
     d.wedge_dense = ctx->wedge_dense;
     d.wide_degree = ctx->wide_degree;
@@ -407,8 +421,8 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
     ctx->bal_count = ctx->record_balance ? hc[TB_N + WB_BLK] : 0;
     wide_arrays(d.e, m, hc[CNT_KW]);
     d.acc32 = (!per_edge || hc[CNT_KW] >= m) ? 1 : 0;
-    ctx->last_mode = ctx->wedge_stream;
-    glt_count_passes(d, per_edge ? 1 : 0, hc, pe_dev, st, ctx->side, ctx->ev, ctx->wedge_stream);
+    ctx->last_mode = mode;
+    glt_count_passes(d, per_edge ? 1 : 0, hc, pe_dev, st, ctx->side, ctx->ev, mode);
     HIPCHK(hipGetLastError());
     return GLT_OK;
 }
@@ -851,11 +865,12 @@ glt_status glt_set_schedule(glt_ctx* ctx, const glt_schedule* s) {
     if (s->wedge_range_limit < 1 || s->wedge_range_limit > glt_wedge_table() / 2)
         return fail(ctx, GLT_E_INVALID_ARG, "wedge_range_limit must be in [1, %d]", glt_wedge_table() / 2);
     if (s->tri_records != 0 && s->tri_records != 1) return fail(ctx, GLT_E_INVALID_ARG, "tri_records must be 0 or 1");
-    if (s->wedge_stream < 0 || s->wedge_stream > 2) return fail(ctx, GLT_E_INVALID_ARG, "wedge_stream must be 0, 1 or 2");
+    if (s->wedge_stream < -1 || s->wedge_stream > 2)
+        return fail(ctx, GLT_E_INVALID_ARG, "wedge_stream must be -1 (automatic), 0, 1 or 2");
     if (s->record_balance != 0 && s->record_balance != 1)
         return fail(ctx, GLT_E_INVALID_ARG, "record_balance must be 0 or 1");
-    if (s->list_order < 0 || s->list_order >= LO_N)
-        return fail(ctx, GLT_E_INVALID_ARG, "list_order must be in [0, %d]", LO_N - 1);
+    if (s->list_order < -1 || s->list_order >= LO_N)
+        return fail(ctx, GLT_E_INVALID_ARG, "list_order must be -1 (automatic) or in [0, %d]", LO_N - 1);
     ctx->wedge_wave_max = s->wedge_wave_max;
     ctx->wedge_mid_max = s->wedge_mid_max;
     ctx->wedge_wg_max = s->wedge_wg_max;

@@ -87,3 +87,11 @@ def test_parse_schedule():
     assert bench.parse_schedule("wedge_stream=1, list_order=1") == {"wedge_stream": 1, "list_order": 1}
     assert bench.parse_schedule("") == {}
     assert bench.parse_schedule(None) == {}
+
+
+def test_resolved_schedule():
+    auto = {"wedge_stream": -1, "list_order": -1}
+    assert bench.resolved_schedule(auto, 1 << 25) == {"wedge_stream": 2, "list_order": 1}
+    assert bench.resolved_schedule(auto, (1 << 25) - 1) == {"wedge_stream": 2, "list_order": 2}
+    assert bench.resolved_schedule(auto, 1 << 28, batch=True) == {"wedge_stream": 2, "list_order": 2}
+    assert bench.resolved_schedule({"wedge_stream": 0, "list_order": 3}, 1 << 30) == {"wedge_stream": 0, "list_order": 3}

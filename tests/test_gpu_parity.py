@@ -584,9 +584,12 @@ def test_list_orders_agree():
     ref = oracle.count(n, rp, col)["X"]
     c = glt.Context(0)
     try:
+        # the defaults are the automatic choices (-1), which a schedule can also ask for
+        assert c.schedule()["list_order"] == -1 and c.schedule()["wedge_stream"] == -1
         base = None
-        for order in range(7):
+        for order in list(range(7)) + [-1]:
             c.set_schedule(list_order=order)
+            assert c.schedule()["list_order"] == order
             say(f"list-order {order}")
             X, pe = gpu(c, n, rp, col)
             assert X == ref, order
@@ -594,6 +597,10 @@ def test_list_orders_agree():
                 base = pe
             else:
                 np.testing.assert_array_equal(pe, base)
+        with pytest.raises(glt.GltError):
+            c.set_schedule(list_order=-2)
+        with pytest.raises(glt.GltError):
+            c.set_schedule(wedge_stream=3)
     finally:
         c.close()
 
