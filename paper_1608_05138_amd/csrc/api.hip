@@ -189,6 +189,9 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
         d.gvb = c.take<int64_t>(ngraphs + 1);
         d.gsb = c.take<int64_t>(ngraphs + 1);
         d.gparts = c.take<u64>((int64_t)ngraphs * 13 * 2);
+        d.gcb = c.take<int>(ngraphs + 1);
+        d.ncchunks = 0;
+        d.cparts = c.take<u64>(((int64_t)m / CG_CHUNK + ngraphs + 1) * 13 * 2);
         d.glrp = (const int**)c.take<int*>(ngraphs);
         d.glcol = (const int**)c.take<int*>(ngraphs);
         sg.rp = c.take<int>(n + 1);
@@ -204,6 +207,9 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
         d.gid = d.ngid = d.vtop = nullptr;
         d.gvb = d.gsb = nullptr;
         d.gparts = nullptr;
+        d.gcb = nullptr;
+        d.ncchunks = 0;
+        d.cparts = nullptr;
         d.glrp = d.glcol = nullptr;
         sg.rp = host_in ? (void*)c.take<char>((int64_t)(n + 1) * (rp64 ? 8 : 4)) : nullptr;
         sg.col = host_in ? c.take<int>(S) : nullptr;
@@ -506,6 +512,11 @@ glt_status glt_run_batch_ptrs(glt_ctx* ctx, int64_t B, const int64_t* vb, const 
     HIPCHK(hipMemcpyAsync((void*)d.gsb, sb, (size_t)(B + 1) * 8, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync((void*)d.glrp, rp_ptrs, (size_t)B * sizeof(void*), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync((void*)d.glcol, col_ptrs, (size_t)B * sizeof(void*), hipMemcpyHostToDevice, st));
+    // combine chunks: graph g's oriented edges (m_g of them) in pieces of CG_CHUNK
+    std::vector<int> cb((size_t)B + 1, 0);
+    for (int64_t g = 0; g < B; g++) cb[g + 1] = cb[g] + (int)(((sb[g + 1] - sb[g]) / 2 + CG_CHUNK - 1) / CG_CHUNK);
+    d.ncchunks = cb[B];
+    HIPCHK(hipMemcpyAsync(d.gcb, cb.data(), cb.size() * sizeof(int), hipMemcpyHostToDevice, st));
     glt_union_build(d, (int*)sg.rp, sg.col, st);
     HIPCHK(hipGetLastError());
     rc = run_pipeline(ctx, d, sg.rp, 0, sg.col, false, nullptr, st);

@@ -1579,16 +1579,26 @@ static void reduce_parts(const Dev& d, int nb, hipStream_t st) {
 // Batched global mode: one workgroup per graph over its oriented edges, unrestricted sums
 // with the graph's own n and m.
 __global__ __launch_bounds__(CB_THREADS) void k_combine_graphs(const int64_t* __restrict__ vb,
+                                                               const int* __restrict__ gcb, int ngraphs,
                                                                const int* __restrict__ optr, EdgeArrays e,
                                                                const int* __restrict__ ocol,
                                                                const int* __restrict__ ndeg,
-                                                               u64* __restrict__ gparts) {
+                                                               u64* __restrict__ cparts) {
     __shared__ u64 red[CB_THREADS / GLT_WAVE][NCS][2];
-    const int g = blockIdx.x;
+    const int b = blockIdx.x;
+    // this chunk's graph: the last g with gcb[g] <= b (graphs without edges own no chunk)
+    int glo = 0, ghi = ngraphs;
+    while (ghi - glo > 1) {
+        const int mid = (glo + ghi) >> 1;
+        if (gcb[mid] <= b) glo = mid; else ghi = mid;
+    }
+    const int g = glo;
     const int64_t ng = vb[g + 1] - vb[g];
     // graph g's vertices hold the ranks [vb[g], vb[g + 1]), so its oriented edges are the
     // contiguous range below (the sums do not depend on the edge order)
-    const int64_t e0 = optr[vb[g]], e1 = optr[vb[g + 1]], mg = e1 - e0;
+    const int64_t eg0 = optr[vb[g]], eg1 = optr[vb[g + 1]], mg = eg1 - eg0;
+    const int64_t e0 = eg0 + (int64_t)(b - gcb[g]) * CG_CHUNK;
+    const int64_t e1 = min(e0 + (int64_t)CG_CHUNK, eg1);
     u64 lo[NCS], hi[NCS];
 #pragma unroll
     for (int c = 0; c < NCS; c++) { lo[c] = 0; hi[c] = 0; }
@@ -1624,8 +1634,30 @@ __global__ __launch_bounds__(CB_THREADS) void k_combine_graphs(const int64_t* __
             L += red[q][c][0];
             H += red[q][c][1] + ((L < o) ? 1ull : 0ull);
         }
-        gparts[((int64_t)g * NCS + c) * 2] = L;
-        gparts[((int64_t)g * NCS + c) * 2 + 1] = H;
+        cparts[((int64_t)b * NCS + c) * 2] = L;
+        cparts[((int64_t)b * NCS + c) * 2 + 1] = H;
+    }
+}
+
+// Per graph (one wave each), the sum of its chunks' 128-bit partials (zero for a graph
+// without edges): lanes stride over the chunks, then a wave reduction.
+__global__ __launch_bounds__(GLT_WAVE) void k_fold_graph_parts(const int* __restrict__ gcb,
+                                                               const u64* __restrict__ cparts,
+                                                               u64* __restrict__ gparts) {
+    const int g = blockIdx.x, l = threadIdx.x;
+    const int b0 = gcb[g], b1 = gcb[g + 1];
+    for (int c = 0; c < NCS; c++) {
+        u64 L = 0, H = 0;
+        for (int b = b0 + l; b < b1; b += GLT_WAVE) {
+            const u64 o = L;
+            L += cparts[((int64_t)b * NCS + c) * 2];
+            H += cparts[((int64_t)b * NCS + c) * 2 + 1] + ((L < o) ? 1ull : 0ull);
+        }
+        wave_sum128(L, H);
+        if (l == 0) {
+            gparts[((int64_t)g * NCS + c) * 2] = L;
+            gparts[((int64_t)g * NCS + c) * 2 + 1] = H;
+        }
     }
 }
 
@@ -2100,8 +2132,10 @@ static void count_passes(const Dev& d, int per_edge, const int* hc, u64* out_pe,
     if (per_edge && n > 0 && m > 0 && !vsplit) vertex_sums<AT>(d, st);
     const int nb = combine_blocks(m);
     if (d.ngraphs > 0) {
-        hipLaunchKernelGGL(k_combine_graphs, dim3(d.ngraphs), dim3(CB_THREADS), 0, st, d.gvb, d.optr, e, d.ocol,
-                           d.ndeg, d.gparts);
+        if (d.ncchunks > 0)
+            hipLaunchKernelGGL(k_combine_graphs, dim3(d.ncchunks), dim3(CB_THREADS), 0, st, d.gvb, d.gcb, d.ngraphs,
+                               d.optr, e, d.ocol, d.ndeg, d.cparts);
+        hipLaunchKernelGGL(k_fold_graph_parts, dim3(d.ngraphs), dim3(GLT_WAVE), 0, st, d.gcb, d.cparts, d.gparts);
     } else if (m > 0) {
         ERec* er = (ERec*)d.erec;
         VRec* vr = (VRec*)d.vrec;

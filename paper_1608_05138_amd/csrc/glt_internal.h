@@ -98,6 +98,9 @@ enum { TB_WAVE = 0, TB_BLK1, TB_BLK2, TB_GLOBAL, TB_N };   // triangle / gather 
 #ifndef TB_LDS_ROWS
 #define TB_LDS_ROWS 896
 #endif
+// Oriented edges per combine workgroup of a batch (each graph's edges are cut into chunks of
+// this many, so a few large graphs still spread over many workgroups).
+#define CG_CHUNK 8192
 enum { WB_WAVE = 0, WB_MID, WB_BLK, WB_HUGE, WB_N };        // wedge pass
 // d.counts words: TB_N triangle-list counts, WB_N wedge-list counts, TB_N largest out-degrees
 // per triangle list, the accumulator split point kw (EdgeArrays), and the number of bottoms
@@ -164,6 +167,9 @@ struct Dev {
     const int64_t* gvb;   // device copy of the per-graph vertex bases [ngraphs+1]
     const int64_t* gsb;   // device copy of the per-graph slot bases [ngraphs+1]
     u64* gparts;          // [ngraphs][13][2] per-graph unrestricted sums (128-bit)
+    int* gcb;             // [ngraphs+1] first combine chunk of each graph (CG_CHUNK oriented edges each)
+    int ncchunks;         // combine chunks of the batch (gcb[ngraphs])
+    u64* cparts;          // [chunks][13][2] per-chunk unrestricted sums
     const int** glrp;     // device array of per-graph local-offset pointers [ngraphs]
     const int** glcol;    // device array of per-graph local-column pointers [ngraphs]
     // tuning (defaults; overridable per handle for testing)

@@ -150,31 +150,37 @@ __global__ __launch_bounds__(256) void k_union_rows(const int64_t* __restrict__ 
     if (bad) atomicOr(err, bad);
 }
 
-// One thread per union entry: local neighbour id -> union id (an out-of-range local id is
-// flagged and replaced by the entry's own row, which the self-loop check rejects too).
+// Local neighbour ids -> union ids, with the checks of every entry (id in range, no
+// self-loop).  Graph g's entries are cut into chunks of 2 CG_CHUNK, one workgroup each (gcb
+// numbers the chunks), so each thread reads the graph's own column array and the union row
+// index coalesced.
 __global__ __launch_bounds__(256) void k_union_cols(const int64_t* __restrict__ vb, const int64_t* __restrict__ sb,
-                                                    const u32* __restrict__ rowx, const int* __restrict__ gid,
-                                                    const int* const* __restrict__ glcol, int N, int64_t S,
+                                                    const int* __restrict__ gcb, int ngraphs,
+                                                    const u32* __restrict__ rowx,
+                                                    const int* const* __restrict__ glcol,
                                                     int* __restrict__ ucol, int* __restrict__ err) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.x;
+    int glo = 0, ghi = ngraphs;   // the chunk's graph: the last g with gcb[g] <= b
+    while (ghi - glo > 1) {
+        const int mid = (glo + ghi) >> 1;
+        if (gcb[mid] <= b) glo = mid; else ghi = mid;
+    }
+    const int g = glo;
+    const int64_t v0 = vb[g], ng = vb[g + 1] - v0, s0 = sb[g];
+    const int64_t j0 = (int64_t)(b - gcb[g]) * (2 * CG_CHUNK);
+    const int64_t j1 = min(j0 + 2 * CG_CHUNK, sb[g + 1] - s0);
+    const int* lc = glcol[g];
     int bad = 0;
-    if (s < S) {
-        const int v = (int)rowx[s + 1] - 1;
-        if (v < 0 || v >= N) {
-            bad = ERR_RANGE;
-            ucol[s] = 0;
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
+        const int c = lc[j];
+        const int64_t s = s0 + j;
+        const int64_t v = (int64_t)rowx[s + 1] - 1;   // the entry's union row
+        if (c < 0 || c >= ng || v < v0 || v >= v0 + ng) {
+            bad |= ERR_RANGE;
+            ucol[s] = (int)v0;
         } else {
-            const int g = gid[v];
-            const int64_t v0 = vb[g], ng = vb[g + 1] - v0;
-            const int64_t j = s - sb[g];
-            if (j < 0 || j >= sb[g + 1] - sb[g]) {
-                bad = ERR_RANGE;
-                ucol[s] = v;
-            } else {
-                const int c = glcol[g][j];
-                if (c < 0 || c >= ng) { bad = ERR_RANGE; ucol[s] = v; }
-                else ucol[s] = (int)(v0 + c);
-            }
+            ucol[s] = (int)(v0 + c);
+            if (v0 + c == v) bad |= ERR_SELF;
         }
     }
     bad = wave_or(bad);
@@ -246,64 +252,85 @@ __global__ __launch_bounds__(256) void k_place(const RP* __restrict__ rp, const 
     const int r = rank[x];
     const int64_t pos = (int64_t)nrp[r] + (s - (int64_t)rp[x]);
     key[pos] = (u32)rank[y];
-    val[pos] = (u32)s;
     nsrow[pos] = r;
-    upflag[s] = (y > x) ? 1u : 0u;
+    if (val) {   // per-edge output: the caller's slot rides along, and upward slots are flagged
+        val[pos] = (u32)s;
+        upflag[s] = (y > x) ? 1u : 0u;
+    }
 }
 
 #define PAD_KEY 0xffffffffu   // sorts after every rank (ranks are < 2^31)
 
+// The row sorts below order each relabelled row by neighbour rank in place (keys at the
+// row's own positions of the relabelled column array), carrying the caller's slot index when
+// KV (per-edge output needs it), and flag equal neighbours side by side: duplicate entries.
+__device__ __forceinline__ void flag_dups(int bad, int* err) {
+    bad = wave_or(bad);
+    if (glt_lane() == 0 && bad) atomicOr(err, bad);
+}
+
 // Rows of 2..RT_MAX entries: one thread per row, bitonic network over RT_MAX registers.
+template <bool KV>
 __global__ __launch_bounds__(256) void k_sort_tiny(const int* __restrict__ list, int cnt, const int* __restrict__ nrp,
-                                                   u32* __restrict__ key, u32* __restrict__ val) {
+                                                   u32* __restrict__ key, u32* __restrict__ val,
+                                                   int* __restrict__ err) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cnt) return;
-    const int r = list[i];
-    const int b = nrp[r], len = nrp[r + 1] - b;
-    u32 k[RT_MAX], v[RT_MAX];
+    int bad = 0;
+    if (i < cnt) {
+        const int r = list[i];
+        const int b = nrp[r], len = nrp[r + 1] - b;
+        u32 k[RT_MAX], v[RT_MAX];
 #pragma unroll
-    for (int j = 0; j < RT_MAX; j++) {
-        k[j] = (j < len) ? key[b + j] : PAD_KEY;
-        v[j] = (j < len) ? val[b + j] : 0u;
-    }
+        for (int j = 0; j < RT_MAX; j++) {
+            k[j] = (j < len) ? key[b + j] : PAD_KEY;
+            if (KV) v[j] = (j < len) ? val[b + j] : 0u;
+        }
 #pragma unroll
-    for (int kk = 2; kk <= RT_MAX; kk <<= 1) {
+        for (int kk = 2; kk <= RT_MAX; kk <<= 1) {
 #pragma unroll
-        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
 #pragma unroll
-            for (int a = 0; a < RT_MAX; a++) {
-                const int c = a ^ jj;
-                if (c > a) {
-                    const bool up = (a & kk) == 0;
-                    if ((k[a] > k[c]) == up) {
-                        const u32 tk = k[a]; k[a] = k[c]; k[c] = tk;
-                        const u32 tv = v[a]; v[a] = v[c]; v[c] = tv;
+                for (int a = 0; a < RT_MAX; a++) {
+                    const int c = a ^ jj;
+                    if (c > a) {
+                        const bool up = (a & kk) == 0;
+                        if ((k[a] > k[c]) == up) {
+                            const u32 tk = k[a]; k[a] = k[c]; k[c] = tk;
+                            if (KV) { const u32 tv = v[a]; v[a] = v[c]; v[c] = tv; }
+                        }
                     }
                 }
             }
         }
-    }
 #pragma unroll
-    for (int j = 0; j < RT_MAX; j++)
-        if (j < len) { key[b + j] = k[j]; val[b + j] = v[j]; }
+        for (int j = 0; j < RT_MAX; j++)
+            if (j < len) {
+                key[b + j] = k[j];
+                if (KV) val[b + j] = v[j];
+                if (j > 0 && k[j] == k[j - 1]) bad = ERR_DUP;
+            }
+    }
+    flag_dups(bad, err);
 }
 
 // Rows of RT_MAX+1..RW_MAX entries: one wavefront per row, bitonic over the lanes.
+template <bool KV>
 __global__ __launch_bounds__(256) void k_sort_wave(const int* __restrict__ list, int cnt, const int* __restrict__ nrp,
-                                                   u32* __restrict__ key, u32* __restrict__ val) {
+                                                   u32* __restrict__ key, u32* __restrict__ val,
+                                                   int* __restrict__ err) {
     const int i = blockIdx.x * (256 / GLT_WAVE) + threadIdx.x / GLT_WAVE;
     if (i >= cnt) return;   // whole wavefronts
     const int l = glt_lane();
     const int r = list[i];
     const int b = nrp[r], len = nrp[r + 1] - b;
     u32 k = (l < len) ? key[b + l] : PAD_KEY;
-    u32 v = (l < len) ? val[b + l] : 0u;
+    u32 v = (KV && l < len) ? val[b + l] : 0u;
 #pragma unroll
     for (int kk = 2; kk <= GLT_WAVE; kk <<= 1) {
 #pragma unroll
         for (int jj = kk >> 1; jj > 0; jj >>= 1) {
             const u32 ok = __shfl_xor(k, jj, GLT_WAVE);
-            const u32 ov = __shfl_xor(v, jj, GLT_WAVE);
+            const u32 ov = KV ? __shfl_xor(v, jj, GLT_WAVE) : 0u;
             const bool up = (l & kk) == 0;
             const bool lower = (l & jj) == 0;
             // lower lane of an ascending pair keeps the minimum, upper the maximum
@@ -311,13 +338,20 @@ __global__ __launch_bounds__(256) void k_sort_wave(const int* __restrict__ list,
             if (take) { k = ok; v = ov; }
         }
     }
-    if (l < len) { key[b + l] = k; val[b + l] = v; }
+    const u32 prev = __shfl_up(k, 1, GLT_WAVE);
+    if (l < len) {
+        key[b + l] = k;
+        if (KV) val[b + l] = v;
+    }
+    flag_dups((l > 0 && l < len && prev == k) ? ERR_DUP : 0, err);
 }
 
 // Rows of RW_MAX+1..RB_MAX entries: one workgroup per row, bitonic in LDS.
+template <bool KV>
 __global__ __launch_bounds__(256) void k_sort_blk(const int* __restrict__ list, int cnt, const int* __restrict__ nrp,
-                                                  u32* __restrict__ key, u32* __restrict__ val) {
-    __shared__ u32 sk[RB_MAX], sv[RB_MAX];
+                                                  u32* __restrict__ key, u32* __restrict__ val,
+                                                  int* __restrict__ err) {
+    __shared__ u32 sk[RB_MAX], sv[KV ? RB_MAX : 1];
     const int t = threadIdx.x;
     const int r = list[blockIdx.x];
     const int b = nrp[r], len = nrp[r + 1] - b;
@@ -325,7 +359,7 @@ __global__ __launch_bounds__(256) void k_sort_blk(const int* __restrict__ list, 
     while (P < len) P <<= 1;   // <= RB_MAX
     for (int j = t; j < P; j += 256) {
         sk[j] = (j < len) ? key[b + j] : PAD_KEY;
-        sv[j] = (j < len) ? val[b + j] : 0u;
+        if (KV) sv[j] = (j < len) ? val[b + j] : 0u;
     }
     __syncthreads();
     for (int kk = 2; kk <= P; kk <<= 1) {
@@ -337,13 +371,19 @@ __global__ __launch_bounds__(256) void k_sort_blk(const int* __restrict__ list, 
                 const u32 a = sk[lo], c = sk[hi];
                 if ((a > c) == up) {
                     sk[lo] = c; sk[hi] = a;
-                    const u32 tv = sv[lo]; sv[lo] = sv[hi]; sv[hi] = tv;
+                    if (KV) { const u32 tv = sv[lo]; sv[lo] = sv[hi]; sv[hi] = tv; }
                 }
             }
             __syncthreads();
         }
     }
-    for (int j = t; j < len; j += 256) { key[b + j] = sk[j]; val[b + j] = sv[j]; }
+    int bad = 0;
+    for (int j = t; j < len; j += 256) {
+        key[b + j] = sk[j];
+        if (KV) val[b + j] = sv[j];
+        if (j > 0 && sk[j] == sk[j - 1]) bad = ERR_DUP;
+    }
+    flag_dups(bad, err);
 }
 
 // Rows longer than RB_MAX: one 1024-thread workgroup per row, stable LSD radix passes over
@@ -355,9 +395,10 @@ __global__ __launch_bounds__(256) void k_sort_blk(const int* __restrict__ list, 
 #define SB_T 1024
 #define SB_DMAX 10
 #define SB_NB (1 << SB_DMAX)
+template <bool KV>
 __global__ __launch_bounds__(SB_T) void k_sort_big(const int* __restrict__ list, int cnt, const int* __restrict__ nrp,
                                                    u32* __restrict__ kA, u32* __restrict__ vA, u32* __restrict__ kB,
-                                                   u32* __restrict__ vB, int bits) {
+                                                   u32* __restrict__ vB, int bits, int* __restrict__ err) {
     static_assert(SB_NB <= SB_T, "one bucket per thread in the bucket loops");
     __shared__ u32 base[SB_NB];
     __shared__ u32 wcnt[SB_T / GLT_WAVE][SB_NB];
@@ -366,8 +407,8 @@ __global__ __launch_bounds__(SB_T) void k_sort_big(const int* __restrict__ list,
     const int r = list[blockIdx.x];
     const int64_t b = nrp[r];
     const int len = nrp[r + 1] - (int)b;
-    u32* ki = kA + b; u32* vi = vA + b;
-    u32* ko = kB + b; u32* vo = vB + b;
+    u32* ki = kA + b; u32* vi = KV ? vA + b : nullptr;
+    u32* ko = kB + b; u32* vo = KV ? vB + b : nullptr;
     const u64 lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (GLT_WAVE - lane));
     const int npass_all = (bits + SB_DMAX - 1) / SB_DMAX;
     const int dbits = npass_all > 0 ? (bits + npass_all - 1) / npass_all : 0;   // <= SB_DMAX
@@ -390,7 +431,7 @@ __global__ __launch_bounds__(SB_T) void k_sort_big(const int* __restrict__ list,
             const int j = j0 + t;
             const bool valid = j < len;
             const u32 k = valid ? ki[j] : 0u;
-            const u32 v = valid ? vi[j] : 0u;
+            const u32 v = (KV && valid) ? vi[j] : 0u;
             const u32 d = (k >> shift) & dmask;
             u64 peers = __ballot(valid);
             for (int bit = 0; bit < dbits; bit++) {
@@ -404,7 +445,7 @@ __global__ __launch_bounds__(SB_T) void k_sort_big(const int* __restrict__ list,
                 u32 off = base[d];
                 for (int q = 0; q < w; q++) off += wcnt[q][d];
                 ko[off + rk] = k;
-                vo[off + rk] = v;
+                if (KV) vo[off + rk] = v;
             }
             __syncthreads();
             if (t < nb) {
@@ -417,23 +458,18 @@ __global__ __launch_bounds__(SB_T) void k_sort_big(const int* __restrict__ list,
         u32* tk = ki; ki = ko; ko = tk;
         u32* tv = vi; vi = vo; vo = tv;
     }
-    if (npass & 1)
-        for (int j = t; j < len; j += SB_T) { kA[b + j] = kB[b + j]; vA[b + j] = vB[b + j]; }
-}
-
-// Sorted rows -> relabelled columns; equal neighbours side by side in a row are duplicates.
-__global__ __launch_bounds__(256) void k_unpack_cols(const u32* __restrict__ key, int64_t S,
-                                                     const int* __restrict__ nsrow, const int* __restrict__ nrp,
-                                                     int* __restrict__ ncol, int* __restrict__ err) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // ki holds the sorted row (every thread's writes of the last pass are ordered before
+    // these reads by the pass's final barrier)
     int bad = 0;
-    if (s < S) {
-        const u32 k = key[s];
-        ncol[s] = (int)k;
-        if (s > nrp[nsrow[s]] && key[s - 1] == k) bad = ERR_DUP;
+    for (int j = t; j < len; j += SB_T) {
+        const u32 k = ki[j];
+        if (j > 0 && ki[j - 1] == k) bad = ERR_DUP;
+        if (npass & 1) {
+            kA[b + j] = k;
+            if (KV) vA[b + j] = vi[j];
+        }
     }
-    bad = wave_or(bad);
-    if (glt_lane() == 0 && bad) atomicOr(err, bad);
+    flag_dups(bad, err);
 }
 
 // dlo[x] = number of neighbours ranked below x (the row is ascending, binary search).
@@ -455,6 +491,29 @@ __global__ __launch_bounds__(256) void k_vinfo(const int* __restrict__ nrp, cons
                                                int4* __restrict__ vinf) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x < n) vinf[x] = make_int4(nrp[x] + dlo[x], nrp[x + 1], optr[x], order[x]);
+}
+
+// First index p in [lo, hi] with a[p] >= x, a ascending on [lo, hi).  Each round loads seven
+// probes at once and keeps the eighth of the range between two of them, so a list of up to
+// 64 entries costs two rounds of loads where halving would chain six.
+__device__ __forceinline__ int lower_bound8(const int* __restrict__ a, int lo, int hi, int x) {
+    while (hi - lo > 8) {
+        const int q = (hi - lo) >> 3;   // >= 1; probes lo + q .. lo + 7q all lie below hi
+        int v[7];
+#pragma unroll
+        for (int j = 0; j < 7; j++) v[j] = a[lo + (j + 1) * q];
+        int c = 0;   // probes below x (a prefix of them, the list being ascending)
+#pragma unroll
+        for (int j = 0; j < 7; j++) c += v[j] < x ? 1 : 0;
+        const int nlo = c == 0 ? lo : lo + c * q + 1;
+        hi = c == 7 ? hi : lo + (c + 1) * q;
+        lo = nlo;
+    }
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < 8; j++)
+        if (lo + j < hi && a[lo + j] < x) c++;
+    return lo + c;
 }
 
 // One thread per relabelled entry s of row x (y = ncol[s]).  Upward entries (y > x) copy
@@ -519,7 +578,7 @@ __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ ncol
             // downward x -> y (y ranked below x): the edge's slot is x's place in N+(y), a short
             // list (out-degrees are bounded by sqrt(2m) in the degree order)
             const int yb = vy.x, ye = vy.y;
-            const int sp = lower_bound_i32(ncol, yb, ye, x);
+            const int sp = lower_bound8(ncol, yb, ye, x);
             const int k = vy.z + (sp - yb);
             if (sp >= ye || ncol[sp] != x || k >= m) {
                 bad = ERR_ASYM;
@@ -659,10 +718,11 @@ int glt_prep_validate(const Dev& d, const void* rp, int rp64, const int* col, hi
                            d.deg, d.rowx, d.err);
     launch_excl_scan<u32, u32>(d.rowx, d.rowx, S + 1, d.rs_tmp, (u32*)nullptr, st);
     if (S > 0) {
-        if (d.ngraphs > 0)
-            hipLaunchKernelGGL(k_union_cols, dim3(nblk(S, 256)), dim3(256), 0, st, d.gvb, d.gsb, d.rowx, d.gid,
-                               d.glcol, d.n, S, (int*)col, d.err);
-        hipLaunchKernelGGL(k_check_cols, dim3(nblk(S, 256)), dim3(256), 0, st, d.rowx, col, d.n, S, d.err);
+        if (d.ngraphs > 0)   // the union's columns, checked as they are written
+            hipLaunchKernelGGL(k_union_cols, dim3(d.ncchunks), dim3(256), 0, st, d.gvb, d.gsb, d.gcb, d.ngraphs,
+                               d.rowx, d.glcol, (int*)col, d.err);
+        else
+            hipLaunchKernelGGL(k_check_cols, dim3(nblk(S, 256)), dim3(256), 0, st, d.rowx, col, d.n, S, d.err);
     }
     unsigned gm = nblk(d.n, 256);
     if (gm > 2048) gm = 2048;
@@ -671,6 +731,24 @@ int glt_prep_validate(const Dev& d, const void* rp, int rp64, const int* col, hi
 }
 
 static inline int bitlen(u64 x) { int b = 0; while (x) { b++; x >>= 1; } return b; }
+
+template <bool KV>
+static void launch_row_sorts(const Dev& d, const int* rows, const int* rlist, u32* key, u32* val, hipStream_t st) {
+    const int n = d.n;
+    if (rows[RS_TINY] > 0)
+        hipLaunchKernelGGL(k_sort_tiny<KV>, dim3(nblk(rows[RS_TINY], 256)), dim3(256), 0, st,
+                           rlist + (int64_t)RS_TINY * n, rows[RS_TINY], d.nrp, key, val, d.err);
+    if (rows[RS_WAVE] > 0)
+        hipLaunchKernelGGL(k_sort_wave<KV>, dim3(nblk(rows[RS_WAVE], 256 / GLT_WAVE)), dim3(256), 0, st,
+                           rlist + (int64_t)RS_WAVE * n, rows[RS_WAVE], d.nrp, key, val, d.err);
+    if (rows[RS_BLK] > 0)
+        hipLaunchKernelGGL(k_sort_blk<KV>, dim3(rows[RS_BLK]), dim3(256), 0, st, rlist + (int64_t)RS_BLK * n,
+                           rows[RS_BLK], d.nrp, key, val, d.err);
+    if (rows[RS_BIG] > 0)
+        hipLaunchKernelGGL(k_sort_big<KV>, dim3(rows[RS_BIG]), dim3(SB_T), 0, st, rlist + (int64_t)RS_BIG * n,
+                           rows[RS_BIG], d.nrp, key, val, (u32*)d.key1, d.val1, bitlen((u64)(n > 1 ? n - 1 : 1)),
+                           d.err);
+}
 
 int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipStream_t st, const int* vinfo) {
     static_assert(RS_N <= TB_N, "row-sort lists live in the triangle-pass list area");
@@ -694,9 +772,11 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
                        d.order, d.rank, d.ndeg, d.gid, d.ngid, d.gvb, d.vtop, rlist, rcnt);
     // relabelled CSR offsets
     launch_excl_scan<int, int>(d.ndeg, d.nrp, n, d.itmp, d.nrp + n, st);
-    // P2: entries placed in their relabelled rows, then every row sorted by neighbour rank
-    u32* key = (u32*)d.key0;
-    u32* val = d.val0;
+    // P2: entries placed in their relabelled rows, then every row sorted by neighbour rank in
+    // place in the relabelled column array (duplicates flagged by the sorts).  The caller's
+    // slot index is carried and the caller's edges numbered only for per-edge output.
+    u32* key = (u32*)d.ncol;
+    u32* val = d.per_edge ? d.val0 : nullptr;
     if (S > 0) {
         if (rp64)
             hipLaunchKernelGGL(k_place<int64_t>, dim3(nblk(S, 256)), dim3(256), 0, st, (const int64_t*)rp, d.rowx, col,
@@ -704,21 +784,12 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
         else
             hipLaunchKernelGGL(k_place<int32_t>, dim3(nblk(S, 256)), dim3(256), 0, st, (const int32_t*)rp, d.rowx, col,
                                S, d.rank, d.nrp, key, val, d.nsrow, d.upx);
-        launch_excl_scan<u32, u32>(d.upx, d.upx, S, d.rs_tmp, (u32*)nullptr, st);
-        if (rows[RS_TINY] > 0)
-            hipLaunchKernelGGL(k_sort_tiny, dim3(nblk(rows[RS_TINY], 256)), dim3(256), 0, st,
-                               rlist + (int64_t)RS_TINY * n, rows[RS_TINY], d.nrp, key, val);
-        if (rows[RS_WAVE] > 0)
-            hipLaunchKernelGGL(k_sort_wave, dim3(nblk(rows[RS_WAVE], 256 / GLT_WAVE)), dim3(256), 0, st,
-                               rlist + (int64_t)RS_WAVE * n, rows[RS_WAVE], d.nrp, key, val);
-        if (rows[RS_BLK] > 0)
-            hipLaunchKernelGGL(k_sort_blk, dim3(rows[RS_BLK]), dim3(256), 0, st, rlist + (int64_t)RS_BLK * n,
-                               rows[RS_BLK], d.nrp, key, val);
-        if (rows[RS_BIG] > 0)
-            hipLaunchKernelGGL(k_sort_big, dim3(rows[RS_BIG]), dim3(SB_T), 0, st, rlist + (int64_t)RS_BIG * n,
-                               rows[RS_BIG], d.nrp, key, val, (u32*)d.key1, d.val1,
-                               bitlen((u64)(n > 1 ? n - 1 : 1)));
-        hipLaunchKernelGGL(k_unpack_cols, dim3(nblk(S, 256)), dim3(256), 0, st, key, S, d.nsrow, d.nrp, d.ncol, d.err);
+        if (d.per_edge) {
+            launch_excl_scan<u32, u32>(d.upx, d.upx, S, d.rs_tmp, (u32*)nullptr, st);
+            launch_row_sorts<true>(d, rows, rlist, key, val, st);
+        } else {
+            launch_row_sorts<false>(d, rows, rlist, key, val, st);
+        }
     }
     const u32* oslot = val;
     // P3: orientation
