@@ -493,29 +493,6 @@ __global__ __launch_bounds__(256) void k_vinfo(const int* __restrict__ nrp, cons
     if (x < n) vinf[x] = make_int4(nrp[x] + dlo[x], nrp[x + 1], optr[x], order[x]);
 }
 
-// First index p in [lo, hi] with a[p] >= x, a ascending on [lo, hi).  Each round loads seven
-// probes at once and keeps the eighth of the range between two of them, so a list of up to
-// 64 entries costs two rounds of loads where halving would chain six.
-__device__ __forceinline__ int lower_bound8(const int* __restrict__ a, int lo, int hi, int x) {
-    while (hi - lo > 8) {
-        const int q = (hi - lo) >> 3;   // >= 1; probes lo + q .. lo + 7q all lie below hi
-        int v[7];
-#pragma unroll
-        for (int j = 0; j < 7; j++) v[j] = a[lo + (j + 1) * q];
-        int c = 0;   // probes below x (a prefix of them, the list being ascending)
-#pragma unroll
-        for (int j = 0; j < 7; j++) c += v[j] < x ? 1 : 0;
-        const int nlo = c == 0 ? lo : lo + c * q + 1;
-        hi = c == 7 ? hi : lo + (c + 1) * q;
-        lo = nlo;
-    }
-    int c = 0;
-#pragma unroll
-    for (int j = 0; j < 8; j++)
-        if (lo + j < hi && a[lo + j] < x) c++;
-    return lo + c;
-}
-
 // One thread per relabelled entry s of row x (y = ncol[s]).  Upward entries (y > x) copy
 // themselves into the oriented CSR at index k and clear the edge's accumulators; downward
 // entries find their edge's k by binary search of x in N+(y), map themselves to k and (PE:
@@ -578,7 +555,7 @@ __global__ __launch_bounds__(256) void k_edge_index(const int* __restrict__ ncol
             // downward x -> y (y ranked below x): the edge's slot is x's place in N+(y), a short
             // list (out-degrees are bounded by sqrt(2m) in the degree order)
             const int yb = vy.x, ye = vy.y;
-            const int sp = lower_bound8(ncol, yb, ye, x);
+            const int sp = lower_bound_i32(ncol, yb, ye, x);
             const int k = vy.z + (sp - yb);
             if (sp >= ye || ncol[sp] != x || k >= m) {
                 bad = ERR_ASYM;
