@@ -164,7 +164,7 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
     d.nsrow = c.take<int>(S);
     d.tri = c.take<u64>(n);
     d.sdeg = c.take<u64>(n);
-    d.tlist = c.take<int>((int64_t)TB_N * n);
+    d.tlist = c.take<int>((int64_t)TL_SEGS * n);
     d.wlist = c.take<int>((int64_t)WB_N * n);
     d.nsum_slots = glt_combine_blocks(m > 0 ? m : 1);
     d.sums = c.take<u64>((int64_t)(d.nsum_slots + GLT_REDUCE_BLOCKS) * 13 * 2);   // + reduction stage

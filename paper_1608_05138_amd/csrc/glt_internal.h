@@ -19,12 +19,18 @@ enum {
 #define ERR_WORDS 16
 
 // Size classes of the per-row sort of P2 (entries per row).
-enum { RS_TINY = 0, RS_WAVE, RS_BLK, RS_BIG, RS_N };
-#define RT_MAX 16       // thread per row (sorting network in registers)
+enum { RS_TINY = 0, RS_WAVE, RS_WMID, RS_BLK, RS_BIG, RS_N };
+#ifndef RT_MAX
+#define RT_MAX 32       // thread per row (sorting network in registers)
+#endif
 #define RW_MAX 64       // wavefront per row (bitonic over lanes)
+#ifndef RM_MAX
+#define RM_MAX 256      // wavefront per row (bitonic in the wavefront's LDS)
+#endif
 #define RB_MAX 2048     // workgroup per row (bitonic in LDS); longer rows: radix passes
 __host__ __device__ inline int row_class(int64_t len) {
-    return len <= 1 ? -1 : len <= RT_MAX ? RS_TINY : len <= RW_MAX ? RS_WAVE : len <= RB_MAX ? RS_BLK : RS_BIG;
+    return len <= 1 ? -1 : len <= RT_MAX ? RS_TINY : len <= RW_MAX ? RS_WAVE : len <= RM_MAX ? RS_WMID
+                                     : len <= RB_MAX ? RS_BLK : RS_BIG;
 }
 
 // Per oriented edge (u -> v, u before v in the degree order) accumulators, one dense
@@ -92,6 +98,8 @@ enum { LO_WORK = 0, LO_DEGREE = 1, LO_NONE = 2, LO_RANDOM = 3, LO_VOLUME = 4, LO
 
 // Bucket ids for the vertex work lists.
 enum { TB_WAVE = 0, TB_BLK1, TB_BLK2, TB_GLOBAL, TB_N };   // triangle / gather passes
+// segments of n entries in the triangle-pass list area, which holds the row-sort lists first
+#define TL_SEGS (TB_N > RS_N ? TB_N : RS_N)
 // Largest out-degree whose adjacency rows the workgroup triangle pass keeps in LDS (bucket
 // TB_BLK2): 896 rows of 28 words, the hash, the per-neighbour arrays and the run tables of a
 // 1024-thread group fill about 152 KB of the CU's 160 KB.

@@ -316,13 +316,14 @@ def test_invalid_inputs_rejected(ctx):
 
 
 def _row_class_graph(seed):
-    """Rows of every length class of the per-row sort (a 5000-leaf star, a 1000-leaf star,
-    vertices of degree ~40 and ~10) over sparse noise, ids and row order shuffled."""
+    """Rows of every length class of the per-row sort (a 5000-leaf star, a 1000-leaf star, a
+    200-leaf star, vertices of degree ~40 and ~10) over sparse noise, ids and row order
+    shuffled."""
     rng = np.random.default_rng(seed)
     n = 7000
     lo, hi = gg.er_pairs(n, 9000, rng)
-    a = [lo, np.zeros(5000, np.int64), np.full(1000, 5001, np.int64)]
-    b = [hi, np.arange(1, 5001), np.arange(5002, 6002)]
+    a = [lo, np.zeros(5000, np.int64), np.full(1000, 5001, np.int64), np.full(200, 6200, np.int64)]
+    b = [hi, np.arange(1, 5001), np.arange(5002, 6002), np.arange(6300, 6500)]
     for v in range(6100, 6140):
         a.append(np.full(40, v, np.int64)); b.append(rng.choice(6000, 40, replace=False) + 1)
     a = np.concatenate(a); b = np.concatenate(b)
@@ -337,17 +338,19 @@ def _row_class_graph(seed):
 def test_row_sort_classes(ctx):
     n, rp, col = _row_class_graph(41)
     d = np.diff(rp)
-    assert d.max() > 2048 and ((d > 64) & (d <= 2048)).any() and ((d > 16) & (d <= 64)).any()
+    assert d.max() > 2048 and ((d > 256) & (d <= 2048)).any() and ((d > 64) & (d <= 256)).any()
+    assert ((d > 16) & (d <= 64)).any()
     check_vs_oracle(ctx, "row-sort-classes", n, rp, col)
 
 
-@pytest.mark.parametrize("length_class", ["tiny", "wave", "wg", "big"])
+@pytest.mark.parametrize("length_class", ["tiny", "wave", "wave_lds", "wg", "big"])
 def test_duplicate_in_each_row_class(ctx, length_class):
     """A duplicated neighbour is found whichever per-row sort handled the row."""
     import paper_1608_05138_amd as glt
     n, rp, col = _row_class_graph(43)
     d = np.diff(rp)
-    lo, hi = {"tiny": (2, 16), "wave": (17, 64), "wg": (65, 2048), "big": (2049, 1 << 30)}[length_class]
+    lo, hi = {"tiny": (2, 16), "wave": (17, 64), "wave_lds": (65, 256), "wg": (257, 2048),
+              "big": (2049, 1 << 30)}[length_class]
     r = int(np.flatnonzero((d >= lo) & (d <= hi - 2))[0])
     c = int(col[rp[r]])
     rows = [list(col[rp[i]:rp[i + 1]]) for i in range(n)]
