@@ -36,14 +36,16 @@ TRAFFIC_SOURCES = ["paper_1608_05138_amd/csrc/count.hip", "paper_1608_05138_amd/
                    "paper_1608_05138_amd/csrc/glt_internal.h", "paper_1608_05138_amd/csrc/prims.h",
                    "paper_1608_05138_amd/csrc/api.hip"]   # api.hip: the schedule the call runs with
 TRAFFIC = {
-    "sha256": "3338c8c8fc46eb9b9c46cfc1c9ef824fba3351bbd7ff2342dba50a5795fc799b",
+    "sha256": "7572a1e063e37e7e6748f4b832dfcb169d0e2a9f1955ac7e83f668f9768cf063",
     "workloads": {
-        "rmat_s22": {"tri_wave": 26746283424, "tri_wg": 171645890432, "gather_wave": 3124859776,
-                     "gather_wg": 111810584160, "wedge_wave": 73580064, "wedge_mid": 3705513568,
-                     "wedge_wg": 81626489792, "wedge_huge": 464976236064},
-        "chung_lu_1m": {"tri_wave": 3311582688, "tri_wg": 3935939552, "gather_wave": 1486274048,
-                        "gather_wg": 2901324736, "wedge_wave": 82283200, "wedge_mid": 3526249728,
-                        "wedge_wg": 9001283008, "wedge_huge": 25600},
+        "rmat_s22": {"tri_wave": 26744178752, "tri_wg": 171592723968,
+                     "gather_wave": 3127717760, "gather_wg": 111682517408,
+                     "wedge_wave": 73612576, "wedge_mid": 3705687648,
+                     "wedge_wg": 81522098208, "wedge_huge": 465092473120},
+        "chung_lu_1m": {"tri_wave": 3309770400, "tri_wg": 3951067520,
+                        "gather_wave": 1482188800, "gather_wg": 2905485792,
+                        "wedge_wave": 82298944, "wedge_mid": 3526636544,
+                        "wedge_wg": 8969144128, "wedge_huge": 39936},
     },
 }
 
