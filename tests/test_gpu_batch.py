@@ -136,6 +136,24 @@ def _gen(spec):
     return gg.batch_graph(spec)
 
 
+def test_batch_chunk_boundaries(ctx):
+    """Graphs whose edge counts sit at the per-graph chunk boundaries of the batch's union
+    columns and combine (8192 edges), with edgeless graphs between them: every graph's
+    counts equal the oracle's and its own single-graph call's."""
+    rng = np.random.default_rng(11)
+    graphs = []
+    for n, m in [(900, 8191), (0, 0), (1000, 8192), (5, 0), (1100, 8193), (1, 0), (2000, 16385), (40, 300)]:
+        lo, hi = gg.er_pairs(n, m, rng)
+        graphs.append((n, gg.csr_from_pairs(n, lo, hi)))
+    packed = gg.pack_batch(graphs)
+    say(f"batch-chunk-boundaries edges={packed['col'].size // 2}")
+    res = ctx.count_batch(_to_device(packed))
+    for g, (n, (rp, col)) in enumerate(graphs):
+        assert res[g] == oracle.count(n, rp, col)["X"], g
+        alone, _ = ctx.count(rp, col, n=n)
+        assert alone == res[g], g
+
+
 def test_batch_10k_vs_stored_oracle(ctx):
     """All 10,000 graphs of the batch mix (n ~ U{50..5000}, ER or Chung-Lu(2.5), mean degree
     ~ U[4, 64]) in one glt_count_batch call: every graph's 17 counts equal the stored
