@@ -36,16 +36,16 @@ TRAFFIC_SOURCES = ["paper_1608_05138_amd/csrc/count.hip", "paper_1608_05138_amd/
                    "paper_1608_05138_amd/csrc/glt_internal.h", "paper_1608_05138_amd/csrc/prims.h",
                    "paper_1608_05138_amd/csrc/api.hip"]   # api.hip: the schedule the call runs with
 TRAFFIC = {
-    "sha256": "7572a1e063e37e7e6748f4b832dfcb169d0e2a9f1955ac7e83f668f9768cf063",
+    "sha256": "8f039bb5f3d778c62d6d7956ee2236a625f7eb04db2c9c7cda2f94053891e396",
     "workloads": {
-        "rmat_s22": {"tri_wave": 26744178752, "tri_wg": 171592723968,
-                     "gather_wave": 3127717760, "gather_wg": 111682517408,
-                     "wedge_wave": 73612576, "wedge_mid": 3705687648,
-                     "wedge_wg": 81522098208, "wedge_huge": 465092473120},
-        "chung_lu_1m": {"tri_wave": 3309770400, "tri_wg": 3951067520,
-                        "gather_wave": 1482188800, "gather_wg": 2905485792,
-                        "wedge_wave": 82298944, "wedge_mid": 3526636544,
-                        "wedge_wg": 8969144128, "wedge_huge": 39936},
+        "rmat_s22": {"tri_wave": 26737952576, "tri_wg": 171720679936,
+                     "gather_wave": 3125487488, "gather_wg": 111823500576,
+                     "wedge_wave": 73633696, "wedge_mid": 3704891040,
+                     "wedge_wg": 81453711008, "wedge_huge": 465566029984},
+        "chung_lu_1m": {"tri_wave": 3308871360, "tri_wg": 3954266528,
+                        "gather_wave": 1482654592, "gather_wg": 2907905952,
+                        "wedge_wave": 82339648, "wedge_mid": 3526440608,
+                        "wedge_wg": 8959116864, "wedge_huge": 39936},
     },
 }
 

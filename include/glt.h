@@ -178,9 +178,12 @@ int glt_last_timing(const glt_ctx* ctx, float* ms, int cap);
  * path, [8] wedges of the mid class, [9] of the huge class; with the schedule's
  * record_balance, [10] the tail of the 4-cycle pass's workgroup class in nanoseconds (from
  * the time 95 % of its list entries were done to the time the last one was) and [11] the
- * span from the first entry done to the last (0 otherwise).  Returns the number of entries
- * written (<= cap, at most 12).  Used to state the algorithmic bytes of each kernel group
- * and the balance of the work lists (Section 4.3, Table 4's orderings).
+ * span from the first entry done to the last (0 otherwise); [12]-[15] the most wedges of one
+ * bottom vertex among those the schedule's bounds place in the wave, mid, workgroup and huge
+ * class (as bucketed: a bottom a class hands over to the next one counts in the first).
+ * Returns the number of entries written (<= cap, at most 16).  Used to state the
+ * algorithmic bytes of each kernel group and the balance of the work lists (Section 4.3,
+ * Table 4's orderings).
  */
 int glt_last_work(const glt_ctx* ctx, uint64_t* out, int cap);
 

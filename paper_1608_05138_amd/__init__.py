@@ -200,7 +200,8 @@ class Context:
     TIMING_KEYS = ["prep", "tri_wave", "tri_wg", "gather_wave", "gather_wg", "wedge_wave", "wedge_mid",
                    "wedge_wg", "wedge_huge", "combine", "total"]
     WORK_KEYS = ["n", "m", "wedges_wave", "wedges_wg", "tri_list_wave", "tri_list_wg", "triangles_wave",
-                 "triangles_wg", "wedges_mid", "wedges_huge", "wg_tail_ns", "wg_span_ns"]
+                 "triangles_wg", "wedges_mid", "wedges_huge", "wg_tail_ns", "wg_span_ns",
+                 "max_wedges_wave", "max_wedges_mid", "max_wedges_wg", "max_wedges_huge"]
 
     def last_timing(self):
         """dict of kernel-group times (ms) of the last count (HIP events on the stream each

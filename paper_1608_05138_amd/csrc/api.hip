@@ -41,7 +41,8 @@ struct glt_ctx {
     int num_cu = 256;
     int wedge_limit = 0;
     int wedge_dense = 0;
-    uint64_t work[2 + NWORK + 2] = {}; // n, m, the device work counters, the workgroup class's tail and span
+    // n, m, device work counters 0-7, the workgroup class's tail and span, device counters 8-11
+    uint64_t work[2 + NWORK + 2] = {};
     int record_balance = 0;            // schedule: time the entries of the workgroup wedge class
     int bal_count = 0;                 // entries of that list in the last call
     int clock_khz = 100000;            // device wall-clock rate
@@ -435,6 +436,12 @@ glt_status run_pipeline(glt_ctx* ctx, Dev& d, const void* rp, int rp64, const in
 
 // Kernel groups as (begin, end) events; the wedge groups (side stream) overlap the
 // triangle and gather groups, so the groups do not add up to the total.
+// The device work counters of a call into the handle's glt_last_work entries: counters 0-7
+// at [2]-[9], 8-11 at [12]-[15] (entries [10], [11] are the balance summary's).
+void set_work(glt_ctx* ctx, const u64* dev_work, bool valid) {
+    for (int i = 0; i < NWORK; i++) ctx->work[i < 8 ? 2 + i : 4 + i] = valid ? dev_work[i] : 0;
+}
+
 void record_timing(glt_ctx* ctx) {
     // group i runs from event be[i][0] to event be[i][1] (events as in count_passes)
     int be[NSEG][2] = {{0, 1}, {1, 2}, {2, 3}, {12, 4}, {4, 5}, {14, 6},
@@ -455,9 +462,9 @@ void record_timing(glt_ctx* ctx) {
 
 // Load-balance summary of the last call's workgroup wedge class (record_balance): from the
 // wall-clock times at which its list entries were done, the tail (95th percentile to the
-// last) and the span (first to last), in nanoseconds, into work[2 + NWORK], work[3 + NWORK].
+// last) and the span (first to last), in nanoseconds, into work[10], work[11].
 glt_status balance_summary(glt_ctx* ctx, const u64* tstamp, hipStream_t st) {
-    ctx->work[2 + NWORK] = ctx->work[3 + NWORK] = 0;
+    ctx->work[10] = ctx->work[11] = 0;
     const int c = ctx->bal_count;
     if (c <= 0 || !tstamp) return GLT_OK;
     std::vector<u64> t((size_t)c);
@@ -466,8 +473,8 @@ glt_status balance_summary(glt_ctx* ctx, const u64* tstamp, hipStream_t st) {
     std::sort(t.begin(), t.end());
     const double ns = 1e6 / (double)ctx->clock_khz;
     const u64 p95 = t[(size_t)((int64_t)(c - 1) * 95 / 100)];
-    ctx->work[2 + NWORK] = (uint64_t)((double)(t.back() - p95) * ns);
-    ctx->work[3 + NWORK] = (uint64_t)((double)(t.back() - t.front()) * ns);
+    ctx->work[10] = (uint64_t)((double)(t.back() - p95) * ns);
+    ctx->work[11] = (uint64_t)((double)(t.back() - t.front()) * ns);
     return GLT_OK;
 }
 
@@ -531,7 +538,7 @@ glt_status glt_run_batch_ptrs(glt_ctx* ctx, int64_t B, const int64_t* vb, const 
         return fail(ctx, GLT_E_INTERNAL, "an on-chip table bound of the wedge pass was exceeded");
     ctx->work[0] = (uint64_t)n;
     ctx->work[1] = (uint64_t)m;
-    for (int i = 0; i < NWORK; i++) ctx->work[2 + i] = ((u64*)((char*)ctx->hbuf + 1032))[i];
+    set_work(ctx, (const u64*)((char*)ctx->hbuf + 1032), true);
     record_timing(ctx);
     rc = balance_summary(ctx, d.tstamp, st);
     if (rc) return rc;
@@ -662,7 +669,7 @@ const char* glt_last_error(const glt_ctx* ctx) { return ctx ? ctx->err.c_str() :
 
 int glt_last_work(const glt_ctx* ctx, uint64_t* out, int cap) {
     if (!ctx || !out) return 0;
-    int k = cap < 4 + NWORK ? cap : 4 + NWORK;
+    const int k = cap < 4 + NWORK ? cap : 4 + NWORK;
     for (int i = 0; i < k; i++) out[i] = ctx->work[i];
     return k;
 }
@@ -750,7 +757,7 @@ glt_status count_one(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt_u128 ou
         return fail(ctx, GLT_E_INTERNAL, "an on-chip table bound of the wedge pass was exceeded");
     ctx->work[0] = (uint64_t)n;
     ctx->work[1] = (uint64_t)m;
-    for (int i = 0; i < NWORK; i++) ctx->work[2 + i] = n > 0 ? ((u64*)((char*)ctx->hbuf + 1032))[i] : 0;
+    set_work(ctx, (const u64*)((char*)ctx->hbuf + 1032), n > 0);
     record_timing(ctx);
     rc = balance_summary(ctx, d.tstamp, st);
     if (rc) return rc;

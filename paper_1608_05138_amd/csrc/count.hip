@@ -1740,11 +1740,16 @@ __global__ __launch_bounds__(256) void k_fold_gsum(u64* __restrict__ gsum, int n
     const int t = threadIdx.x;
     // spread work counters: words 0, 1, 4, 5 wedges of the wave, workgroup, mid and huge
     // classes as bucketed, 2, 3 triangle-pass list entries per path, 6 wedges of bottoms that
-    // moved from the workgroup to the huge class, 7 from the mid to the workgroup class
+    // moved from the workgroup to the huge class, 7 from the mid to the workgroup class,
+    // 8-11 the most wedges of one bottom bucketed to the wave, mid, workgroup, huge class
+    // (folded by maximum, work[8..11])
     __shared__ u64 wsum[WSPREAD_WORDS];
     if (t < WSPREAD_WORDS) {
         u64 v = 0;
-        for (int q = 0; q < GSPREAD; q++) v += wspread[q * WSPREAD_WORDS + t];
+        for (int q = 0; q < GSPREAD; q++) {
+            const u64 x = wspread[q * WSPREAD_WORDS + t];
+            v = t < 8 ? v + x : (x > v ? x : v);
+        }
         wsum[t] = v;
     }
     __syncthreads();
@@ -1755,6 +1760,7 @@ __global__ __launch_bounds__(256) void k_fold_gsum(u64* __restrict__ gsum, int n
         work[3] = wsum[3];
         work[6] = wsum[4] - wsum[7];
         work[7] = wsum[5] + wsum[6];
+        for (int c = 0; c < 4; c++) work[8 + c] = wsum[8 + c];
     }
     if (ngraphs <= 0) {
         u64 v = 0;

@@ -72,7 +72,7 @@ __host__ __device__ inline void wide_arrays(EdgeArrays& e, int m, int kw) {
 //   14     : 3 x (number of 4-cliques), from the triangle pass
 //   15     : number of non-induced 4-cycles, from the wedge pass
 #define NSUMS 16
-#define NWORK 8
+#define NWORK 12   // device work counters (glt_last_work entries [2]-[9], then [12]-[15])
 #define NSEG 11     // timed groups: prep, tri wave, tri wg, gather wave, gather wg, wedge wave, wedge mid,
                     // wedge wg, wedge huge, combine, total
 #define NEV 17      // events of one call (see count_passes)
@@ -83,7 +83,7 @@ enum { S_C3 = 0, S_C4, S_C5, S_C7, S_C8, S_C9, S_C10, S_C11, S_C12, S_C13, S_C14
 enum { GS_TRI_WAVE = 0, GS_TRI_WG = 1 };
 #define GLT_REDUCE_BLOCKS 256   // first-stage workgroups of the 128-bit partial-sum reduction
 #define GSPREAD 64   // lines of gsum a single graph's groups spread their atomics over
-#define WSPREAD_WORDS 8   // u64 per line of the spread work counters (folded into work[])
+#define WSPREAD_WORDS 12  // u64 per line of the spread work counters (folded into work[])
 // gsum line of a group: its graph in a batch, else spread by workgroup index
 __device__ __forceinline__ int64_t gslot(const int* ngid, int v) {
     return ngid ? (int64_t)ngid[v] : (int64_t)(blockIdx.x & (GSPREAD - 1));

@@ -716,9 +716,9 @@ __global__ __launch_bounds__(256) void k_wappend(const u64* __restrict__ wcnt, i
                                                  int wg_max, int* __restrict__ wlist, int* __restrict__ counts,
                                                  u64* __restrict__ wspread) {
     int cls[R], idx[R];
-    u64 wsum[WB_N];
+    u64 wsum[WB_N], wmax[WB_N];
 #pragma unroll
-    for (int c = 0; c < WB_N; c++) wsum[c] = 0;
+    for (int c = 0; c < WB_N; c++) { wsum[c] = 0; wmax[c] = 0; }
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int y = (blockIdx.x * R + r) * 256 + threadIdx.x;
@@ -731,23 +731,36 @@ __global__ __launch_bounds__(256) void k_wappend(const u64* __restrict__ wcnt, i
         cls[r] = q;
         idx[r] = y;
 #pragma unroll
-        for (int c = 0; c < WB_N; c++) wsum[c] += q == c ? wc : 0ull;
+        for (int c = 0; c < WB_N; c++) {
+            wsum[c] += q == c ? wc : 0ull;
+            wmax[c] = (q == c && wc > wmax[c]) ? wc : wmax[c];
+        }
     }
     block_append<WB_N, R>(counts, wlist, n, cls, idx);
     // wedges per class, summed per workgroup: wspread words 0 (wave), 1 (workgroup), 4 (mid),
-    // 5 (huge)
+    // 5 (huge); the most wedges of one bottom per class: words 8 + class
     __shared__ u64 cred[WB_N][256 / GLT_WAVE];
+    __shared__ u64 cmax[WB_N][256 / GLT_WAVE];
 #pragma unroll
     for (int c = 0; c < WB_N; c++) {
         const u64 v = wave_sum(wsum[c]);
-        if (glt_lane() == 0) cred[c][threadIdx.x / GLT_WAVE] = v;
+        const u64 x = ::wave_max(wmax[c]);   // (the parameter wave_max shadows it)
+        if (glt_lane() == 0) {
+            cred[c][threadIdx.x / GLT_WAVE] = v;
+            cmax[c][threadIdx.x / GLT_WAVE] = x;
+        }
     }
     __syncthreads();
     if (threadIdx.x < WB_N) {
-        u64 t = 0;
-        for (int k = 0; k < 256 / GLT_WAVE; k++) t += cred[threadIdx.x][k];
+        u64 t = 0, x = 0;
+        for (int k = 0; k < 256 / GLT_WAVE; k++) {
+            t += cred[threadIdx.x][k];
+            x = cmax[threadIdx.x][k] > x ? cmax[threadIdx.x][k] : x;
+        }
         const int wd = threadIdx.x == WB_WAVE ? 0 : threadIdx.x == WB_MID ? 4 : threadIdx.x == WB_BLK ? 1 : 5;
-        if (t) atomicAdd(&wspread[(blockIdx.x & (GSPREAD - 1)) * WSPREAD_WORDS + wd], t);
+        u64* line = wspread + (blockIdx.x & (GSPREAD - 1)) * WSPREAD_WORDS;
+        if (t) atomicAdd(&line[wd], t);
+        if (x) atomicMax(&line[8 + threadIdx.x], x);
     }
 }
 
