@@ -36,16 +36,16 @@ TRAFFIC_SOURCES = ["paper_1608_05138_amd/csrc/count.hip", "paper_1608_05138_amd/
                    "paper_1608_05138_amd/csrc/glt_internal.h", "paper_1608_05138_amd/csrc/prims.h",
                    "paper_1608_05138_amd/csrc/api.hip"]   # api.hip: the schedule the call runs with
 TRAFFIC = {
-    "sha256": "8f039bb5f3d778c62d6d7956ee2236a625f7eb04db2c9c7cda2f94053891e396",
+    "sha256": "73fa6ddad016c1d4c1fb4fbc1a41ec763da1304bffb32322affd362b3abd417b",
     "workloads": {
-        "rmat_s22": {"tri_wave": 26737952576, "tri_wg": 171720679936,
-                     "gather_wave": 3125487488, "gather_wg": 111823500576,
-                     "wedge_wave": 73633696, "wedge_mid": 3704891040,
-                     "wedge_wg": 81453711008, "wedge_huge": 465566029984},
-        "chung_lu_1m": {"tri_wave": 3308871360, "tri_wg": 3954266528,
-                        "gather_wave": 1482654592, "gather_wg": 2907905952,
-                        "wedge_wave": 82339648, "wedge_mid": 3526440608,
-                        "wedge_wg": 8959116864, "wedge_huge": 39936},
+        "rmat_s22": {"tri_wave": 26747343232, "tri_wg": 171744497280,
+                     "gather_wave": 3124170880, "gather_wg": 111728918048,
+                     "wedge_wave": 73645728, "wedge_mid": 3706944928,
+                     "wedge_wg": 81083508288, "wedge_huge": 465219909152},
+        "chung_lu_1m": {"tri_wave": 3309866624, "tri_wg": 3938736256,
+                        "gather_wave": 1486810112, "gather_wg": 2903087168,
+                        "wedge_wave": 82281280, "wedge_mid": 3526686624,
+                        "wedge_wg": 9036812864, "wedge_huge": 33792},
     },
 }
 

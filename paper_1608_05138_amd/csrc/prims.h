@@ -225,11 +225,42 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tile_apply(const Tin* in,
     }
 }
 
+// Inputs of at most SCAN_SMALL elements: one workgroup scans them in one launch (small
+// calls, such as the batches of a served stream, are bound by their launch count).  Thread
+// t owns up to SCAN_SMALL_ITEMS consecutive elements and reads all of them before writing
+// any, so out may alias in.
+#define SCAN_SMALL_THREADS 1024
+#define SCAN_SMALL_ITEMS 16
+#define SCAN_SMALL (SCAN_SMALL_THREADS * SCAN_SMALL_ITEMS)
+template <typename Tin, typename T>
+__global__ __launch_bounds__(SCAN_SMALL_THREADS) void k_scan_small(const Tin* in, T* out, int64_t n, T* total) {
+    __shared__ T lds[SCAN_SMALL_THREADS / GLT_WAVE];
+    const int per = (int)((n + SCAN_SMALL_THREADS - 1) / SCAN_SMALL_THREADS);   // <= SCAN_SMALL_ITEMS
+    const int64_t b0 = (int64_t)threadIdx.x * per;
+    T loc[SCAN_SMALL_ITEMS];
+    T acc = 0;
+#pragma unroll
+    for (int r = 0; r < SCAN_SMALL_ITEMS; r++) {
+        loc[r] = (r < per && b0 + r < n) ? (T)in[b0 + r] : (T)0;
+        acc += loc[r];
+    }
+    T tot;
+    T off = block_excl_scan<T, SCAN_SMALL_THREADS>(acc, lds, tot);
+#pragma unroll
+    for (int r = 0; r < SCAN_SMALL_ITEMS; r++)
+        if (r < per && b0 + r < n) { out[b0 + r] = off; off += loc[r]; }
+    if (threadIdx.x == 0 && total) *total = tot;
+}
+
 // out[i] = sum_{j<i} in[i]; out may alias in; total (device) optional.  tmp holds
 // ceil(n / SCAN_TILE) elements.
 template <typename Tin, typename T>
 static inline void launch_excl_scan(const Tin* in, T* out, int64_t n, T* tmp, T* total,
                                     hipStream_t st) {
+    if (n <= SCAN_SMALL) {
+        hipLaunchKernelGGL((k_scan_small<Tin, T>), dim3(1), dim3(SCAN_SMALL_THREADS), 0, st, in, out, n, total);
+        return;
+    }
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb == 0) nb = 1;
     hipLaunchKernelGGL((k_scan_tile_sums<Tin, T>), dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, in, n, tmp);
