@@ -36,16 +36,16 @@ TRAFFIC_SOURCES = ["paper_1608_05138_amd/csrc/count.hip", "paper_1608_05138_amd/
                    "paper_1608_05138_amd/csrc/glt_internal.h", "paper_1608_05138_amd/csrc/prims.h",
                    "paper_1608_05138_amd/csrc/api.hip"]   # api.hip: the schedule the call runs with
 TRAFFIC = {
-    "sha256": "73fa6ddad016c1d4c1fb4fbc1a41ec763da1304bffb32322affd362b3abd417b",
+    "sha256": "a4d1d26c1ca1c739ce841e721d07fadb7ff340d08cdfa8be78920f4c927f5f92",
     "workloads": {
-        "rmat_s22": {"tri_wave": 26747343232, "tri_wg": 171744497280,
-                     "gather_wave": 3124170880, "gather_wg": 111728918048,
-                     "wedge_wave": 73645728, "wedge_mid": 3706944928,
-                     "wedge_wg": 81083508288, "wedge_huge": 465219909152},
-        "chung_lu_1m": {"tri_wave": 3309866624, "tri_wg": 3938736256,
-                        "gather_wave": 1486810112, "gather_wg": 2903087168,
-                        "wedge_wave": 82281280, "wedge_mid": 3526686624,
-                        "wedge_wg": 9036812864, "wedge_huge": 33792},
+        "rmat_s22": {"tri_wave": 26736821824, "tri_wg": 171844107488,
+                     "gather_wave": 3124891264, "gather_wg": 111706421664,
+                     "wedge_wave": 73651360, "wedge_mid": 3705907968,
+                     "wedge_wg": 81078675936, "wedge_huge": 464773944224},
+        "chung_lu_1m": {"tri_wave": 3313149728, "tri_wg": 3927296864,
+                        "gather_wave": 1487717376, "gather_wg": 2899560256,
+                        "wedge_wave": 82324032, "wedge_mid": 3528868160,
+                        "wedge_wg": 9044038464, "wedge_huge": 33792},
     },
 }
 

@@ -184,15 +184,16 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
     d.ngraphs = ngraphs;
     d.gsum = c.take<u64>((int64_t)(ngraphs > 0 ? ngraphs : GSPREAD) * NSUMS);
     if (ngraphs > 0) {
+        d.gparts = c.take<u64>((int64_t)ngraphs * 13 * 2);   // right after gsum: one read-back takes both
         d.gid = c.take<int>(n);
         d.ngid = c.take<int>(n);
         d.vtop = c.take<int>(n);
-        d.gvb = c.take<int64_t>(ngraphs + 1);
-        d.gsb = c.take<int64_t>(ngraphs + 1);
-        d.gparts = c.take<u64>((int64_t)ngraphs * 13 * 2);
-        d.gcb = c.take<int>(ngraphs + 1);
         d.ncchunks = 0;
         d.cparts = c.take<u64>(((int64_t)m / CG_CHUNK + ngraphs + 1) * 13 * 2);
+        // the per-graph tables the host fills, side by side (one copy writes all five)
+        d.gvb = c.take<int64_t>(ngraphs + 1);
+        d.gsb = c.take<int64_t>(ngraphs + 1);
+        d.gcb = c.take<int>(ngraphs + 1);
         d.glrp = (const int**)c.take<int*>(ngraphs);
         d.glcol = (const int**)c.take<int*>(ngraphs);
         sg.rp = c.take<int>(n + 1);
@@ -515,30 +516,40 @@ glt_status glt_run_batch_ptrs(glt_ctx* ctx, int64_t B, const int64_t* vb, const 
     glt_status rc = ensure_ws(ctx, need, st);
     if (rc) return rc;
     carve(ctx->ws, n, m, 0, false, false, (int)B, 0, d, sg);
-    HIPCHK(hipMemcpyAsync((void*)d.gvb, vb, (size_t)(B + 1) * 8, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync((void*)d.gsb, sb, (size_t)(B + 1) * 8, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync((void*)d.glrp, rp_ptrs, (size_t)B * sizeof(void*), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync((void*)d.glcol, col_ptrs, (size_t)B * sizeof(void*), hipMemcpyHostToDevice, st));
-    // combine chunks: graph g's oriented edges (m_g of them) in pieces of CG_CHUNK
-    std::vector<int> cb((size_t)B + 1, 0);
+    // The per-graph tables (vertex and slot bases, combine chunks, offset and column
+    // pointers) are carved side by side: one host image at the same offsets, one copy.
+    // Combine chunks: graph g's oriented edges (m_g of them) in pieces of CG_CHUNK.
+    char* const d0 = (char*)d.gvb;
+    const size_t img_bytes = (size_t)((char*)(d.glcol + B) - d0);
+    std::vector<char> img(img_bytes, 0);
+    memcpy(img.data() + ((char*)d.gvb - d0), vb, (size_t)(B + 1) * 8);
+    memcpy(img.data() + ((char*)d.gsb - d0), sb, (size_t)(B + 1) * 8);
+    memcpy(img.data() + ((char*)d.glrp - d0), rp_ptrs, (size_t)B * sizeof(void*));
+    memcpy(img.data() + ((char*)d.glcol - d0), col_ptrs, (size_t)B * sizeof(void*));
+    int* cb = (int*)(img.data() + ((char*)d.gcb - d0));
     for (int64_t g = 0; g < B; g++) cb[g + 1] = cb[g] + (int)(((sb[g + 1] - sb[g]) / 2 + CG_CHUNK - 1) / CG_CHUNK);
     d.ncchunks = cb[B];
-    HIPCHK(hipMemcpyAsync(d.gcb, cb.data(), cb.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d0, img.data(), img_bytes, hipMemcpyHostToDevice, st));
     glt_union_build(d, (int*)sg.rp, sg.col, st);
     HIPCHK(hipGetLastError());
     rc = run_pipeline(ctx, d, sg.rp, 0, sg.col, false, nullptr, st);
     if (rc) return rc;
-    std::vector<u64> parts((size_t)B * 13 * 2), gs((size_t)B * NSUMS);
-    HIPCHK(hipMemcpyAsync(parts.data(), d.gparts, parts.size() * 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(gs.data(), d.gsum, gs.size() * 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 1024, d.err, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 1032, d.work, NWORK * sizeof(u64), hipMemcpyDeviceToHost, st));
+    // two read-backs: the per-graph sums (gsum, then gparts, carved side by side) and the
+    // flag / counter words (err through work, carved side by side at the start)
+    const size_t res_bytes = (size_t)((char*)(d.gparts + (size_t)B * 26) - (char*)d.gsum);
+    const size_t flag_bytes = (size_t)((char*)(d.work + NWORK) - (char*)d.err);
+    if (1024 + flag_bytes > 4096) return fail(ctx, GLT_E_INTERNAL, "flag words exceed the read-back buffer");
+    std::vector<u64> res(res_bytes / 8);
+    HIPCHK(hipMemcpyAsync(res.data(), d.gsum, res_bytes, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((char*)ctx->hbuf + 1024, d.err, flag_bytes, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    const u64* gs = res.data();
+    const u64* parts = res.data() + ((u64*)d.gparts - (u64*)d.gsum);
     if (((int*)((char*)ctx->hbuf + 1024))[0] & ERR_CAP)
         return fail(ctx, GLT_E_INTERNAL, "an on-chip table bound of the wedge pass was exceeded");
     ctx->work[0] = (uint64_t)n;
     ctx->work[1] = (uint64_t)m;
-    set_work(ctx, (const u64*)((char*)ctx->hbuf + 1032), true);
+    set_work(ctx, (const u64*)((char*)ctx->hbuf + 1024 + ((char*)d.work - (char*)d.err)), true);
     record_timing(ctx);
     rc = balance_summary(ctx, d.tstamp, st);
     if (rc) return rc;
