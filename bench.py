@@ -107,11 +107,26 @@ def _gen_large(seed):
     return n, gg.chung_lu(n, 2_000_000, 2.5, float(n - 1), seed)
 
 
-def bench_served(args):
+def gen_served_pools(pool_small, pool_large):
+    """The served benchmark's request pools (small graphs of the batch mix, large Chung-Lu
+    graphs), generated in parallel host processes before any device work."""
+    import multiprocessing as mp
+
+    import graphgen as gg
+    procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    print(f"[bench] generating request pool: {pool_small} small + {pool_large} large",
+          file=sys.stderr, flush=True)
+    specs = gg.batch_spec(pool_small, base=gg.BASE_SEED + 4)
+    with mp.get_context("fork").Pool(procs) as pool:
+        small = pool.map(_gen_batch_graph, specs, chunksize=8)
+        large = pool.map(_gen_large, [gg.graph_seed(gg.BASE_SEED + 5, i) for i in range(pool_large)])
+    return small, large
+
+
+def bench_served(args, pools=None, emit=True):
     """Open-loop Poisson request stream against the continuous-batching server, beside the
     same stream served one request per launch (FIFO).  Latency is measured from each
     request's scheduled arrival time."""
-    import multiprocessing as mp
     import threading
 
     import numpy as np
@@ -119,13 +134,7 @@ def bench_served(args):
     import graphgen as gg
     import paper_1608_05138_amd as glt
 
-    procs = max(1, min(16, len(os.sched_getaffinity(0))))
-    print(f"[bench] generating request pool: {args.pool_small} small + {args.pool_large} large",
-          file=sys.stderr, flush=True)
-    specs = gg.batch_spec(args.pool_small, base=gg.BASE_SEED + 4)
-    with mp.get_context("fork").Pool(procs) as pool:
-        small = pool.map(_gen_batch_graph, specs, chunksize=8)
-        large = pool.map(_gen_large, [gg.graph_seed(gg.BASE_SEED + 5, i) for i in range(args.pool_large)])
+    small, large = pools if pools is not None else gen_served_pools(args.pool_small, args.pool_large)
     ctx = glt.Context(0)
     alone_small = [ctx.count(rp, col, n=n)[0] for n, (rp, col) in small]
     alone_large = [ctx.count(rp, col, n=n)[0] for n, (rp, col) in large]
@@ -137,10 +146,10 @@ def bench_served(args):
         t += float(rng.exponential(1.0 / args.rate))
         if t >= args.serve_seconds:
             break
-        if args.pool_large and rng.random() < 0.01:
-            arrivals.append((t, 1, int(rng.integers(0, args.pool_large))))
+        if large and rng.random() < 0.01:
+            arrivals.append((t, 1, int(rng.integers(0, len(large)))))
         else:
-            arrivals.append((t, 0, int(rng.integers(0, args.pool_small))))
+            arrivals.append((t, 0, int(rng.integers(0, len(small)))))
 
     def serve(max_batch_graphs):
         srv = glt.Server(0, max_batch_graphs=max_batch_graphs)
@@ -219,14 +228,16 @@ def bench_served(args):
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic",
         "config": {"workload": "served", "rate_per_s": args.rate, "seconds": args.serve_seconds,
-                   "requests": len(arrivals), "pool": f"{args.pool_small} mixed small + {args.pool_large} "
+                   "requests": len(arrivals), "pool": f"{len(small)} mixed small + {len(large)} "
                    "Chung-Lu n=200000 m=2000000 (1% of arrivals)", "latency": "t_done - scheduled arrival"},
         "latency_ms": cb["latency_ms"], "continuous_batching": cb, "per_request_fifo": fifo,
     }
-    print(json.dumps(line), flush=True)
+    if emit:
+        print(json.dumps(line), flush=True)
+    return line
 
 
-def bench_batch(args):
+def bench_batch(args, graphs=None, emit=True):
     """Batched global counts of the 10,000-graph mix: graphs/s of one glt_count_batch call,
     next to the plain per-graph path (glt_count looped over the same graphs)."""
     import numpy as np
@@ -235,8 +246,9 @@ def bench_batch(args):
     import graphgen as gg
     import paper_1608_05138_amd as glt
 
-    print(f"[bench] generating {args.batch_graphs} batch graphs", file=sys.stderr, flush=True)
-    specs, graphs = gen_batch(args.batch_graphs)
+    if graphs is None:
+        print(f"[bench] generating {args.batch_graphs} batch graphs", file=sys.stderr, flush=True)
+        _, graphs = gen_batch(args.batch_graphs)
     packed = gg.pack_batch(graphs)
     m_total = int(packed["col"].size // 2)
     dev = torch.device("cuda:0")
@@ -317,7 +329,48 @@ def bench_batch(args):
                              prep=prep_bytes(int(packed["vtx_base"][-1]), m_total, 4)),
     }
     ctx.close()
-    print(json.dumps(line), flush=True)
+    if emit:
+        print(json.dumps(line), flush=True)
+    return line
+
+
+# The short runs of the batch and served workloads reported beside the R-MAT line (the full
+# lines come from --workload batch_10k and --workload served).  The batch runs with the
+# schedule the autotuner picks for it on a separate draw of the mix (wave bound 128, mid
+# bound 4096, dense window 4096, stream mode 1), without re-tuning.
+SIDE_BATCH = {"steps": 3, "warmup": 1,
+              "schedule": "wedge_wave_max=128,wedge_mid_max=4096,wedge_dense=4096,wedge_stream=1"}
+SIDE_SERVED = {"seconds": 10.0, "pool_small": 2000, "pool_large": 16}
+
+
+def side_batch_run(args, graphs):
+    import copy
+    a = copy.copy(args)
+    a.steps, a.warmup = SIDE_BATCH["steps"], SIDE_BATCH["warmup"]
+    a.schedule, a.no_per_graph, a.stream_mode = SIDE_BATCH["schedule"], True, None
+    try:
+        line = bench_batch(a, graphs=graphs, emit=False)
+    except Exception as exc:   # an auxiliary measurement: reported, never fatal to the line
+        return {"workload": "batch_10k", "error": repr(exc)}
+    out = {k: line[k] for k in ("value", "unit", "ms_per_step", "steps", "warmup", "kernel_groups_ms", "schedule")}
+    out.update({"workload": "batch_10k", "config": line["config"],
+                "note": "short run; the full line: bench.py --workload batch_10k"})
+    return out
+
+
+def side_served_run(args, pools):
+    import copy
+    a = copy.copy(args)
+    a.serve_seconds, a.no_per_graph = SIDE_SERVED["seconds"], True
+    try:
+        line = bench_served(a, pools=pools, emit=False)
+    except Exception as exc:   # an auxiliary measurement: reported, never fatal to the line
+        return {"workload": "served", "error": repr(exc)}
+    cb = line["continuous_batching"]
+    return {"workload": "served", "value": line["value"], "unit": line["unit"], "latency_ms": cb["latency_ms"],
+            "latency_ms_small": cb["latency_ms_small"], "latency_ms_large": cb["latency_ms_large"],
+            "mean_batch": cb["mean_batch"], "mismatches_vs_alone": cb["mismatches_vs_alone"],
+            "config": line["config"], "note": "short run; the full line: bench.py --workload served"}
 
 
 def group_bytes(work, per_edge, acc_bytes, records=True):
@@ -514,6 +567,8 @@ def main():
                     help="single graph: skip the second workload timed beside the line (the Chung-Lu "
                          "graph beside R-MAT)")
     ap.add_argument("--no-probe", action="store_true", help="skip the atomic-rate calibration of the roofline")
+    ap.add_argument("--no-side-serving", action="store_true",
+                    help="R-MAT line: skip the short batch and served runs reported beside it")
     ap.add_argument("--compare-modes", action="store_true",
                     help="single graph: also time the other stream modes (reported beside the line)")
     ap.add_argument("--schedule", default=None, metavar="K=V,...",
@@ -560,6 +615,13 @@ def main():
     if args.workload == "served":
         bench_served(args)
         return
+
+    # the batch and served workloads timed beside the R-MAT line: their graphs are generated
+    # first, by forked host processes, before this process touches the device
+    side_runs = args.workload == "rmat_s22" and not args.no_side_workload and not args.no_side_serving
+    if side_runs:
+        side_batch_graphs = gen_batch(args.batch_graphs)[1]
+        side_pools = gen_served_pools(SIDE_SERVED["pool_small"], SIDE_SERVED["pool_large"])
 
     import numpy as np
     import torch
@@ -699,6 +761,11 @@ def main():
         print("[bench] timing the oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(n, rp, col)
     ctx.close()
+    if side_runs:
+        print("[bench] side runs: the batch and served workloads (short)", file=sys.stderr, flush=True)
+        line["side_batch"] = side_batch_run(args, side_batch_graphs)
+        del side_batch_graphs
+        line["side_served"] = side_served_run(args, side_pools)
     print(json.dumps(line), flush=True)
 
 

@@ -95,3 +95,11 @@ def test_resolved_schedule():
     assert bench.resolved_schedule(auto, (1 << 25) - 1) == {"wedge_stream": 2, "list_order": 2}
     assert bench.resolved_schedule(auto, 1 << 28, batch=True) == {"wedge_stream": 2, "list_order": 2}
     assert bench.resolved_schedule({"wedge_stream": 0, "list_order": 3}, 1 << 30) == {"wedge_stream": 0, "list_order": 3}
+
+
+def test_side_run_settings():
+    """The short batch run beside the R-MAT line sets a valid schedule; the served run a
+    short stream over small pools."""
+    sc = bench.parse_schedule(bench.SIDE_BATCH["schedule"])
+    assert sc == {"wedge_wave_max": 128, "wedge_mid_max": 4096, "wedge_dense": 4096, "wedge_stream": 1}
+    assert bench.SIDE_BATCH["steps"] >= 1 and bench.SIDE_SERVED["seconds"] <= 30
