@@ -79,7 +79,7 @@ static inline unsigned nblk(int64_t items, int per) { return (unsigned)((items +
 // validation
 // ---------------------------------------------------------------------------------------
 // One thread per row (R sub-tiles of 256 rows per workgroup): offsets inside [0, S] and
-// monotone; degree; row-start counts; rows per sort class.
+// monotone; degree; row-start counts (when cnt is given); rows per sort class.
 template <typename RP, int R>
 __global__ __launch_bounds__(256) void k_check_rows(const RP* __restrict__ rp, int n, int64_t S,
                                                     int* __restrict__ deg, u32* __restrict__ cnt,
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void k_check_rows(const RP* __restrict__ rp, i
         bool last;
         const int key = ok ? (int)b : 0x7fffffff;
         const u32 c = seg_sum_last(ok ? 1u : 0u, key, last);
-        if (last && c && ok) atomicAdd(&cnt[b], c);
+        if (cnt && last && c && ok) atomicAdd(&cnt[b], c);
     }
     bad = wave_or(bad);
     if (glt_lane() == 0 && bad) atomicOr(err, bad);
@@ -176,16 +176,27 @@ __global__ __launch_bounds__(256) void k_union_rows(const int64_t* __restrict__ 
     if (bad) atomicOr(err, bad);
 }
 
-// Local neighbour ids -> union ids, with the checks of every entry (id in range, no
-// self-loop).  Graph g's entries are cut into chunks of 2 CG_CHUNK, one workgroup each (gcb
-// numbers the chunks), so each thread reads the graph's own column array and the union row
-// index coalesced.
-__global__ __launch_bounds__(256) void k_union_cols(const int64_t* __restrict__ vb, const int64_t* __restrict__ sb,
-                                                    const int* __restrict__ gcb, int ngraphs,
-                                                    const u32* __restrict__ rowx,
-                                                    const int* const* __restrict__ glcol,
-                                                    int* __restrict__ ucol, int* __restrict__ err) {
-    const int b = blockIdx.x;
+// Batch: per sub-chunk of US_SUB entries of one graph (its chunks of 2 CG_CHUNK entries are
+// numbered by gcb; one workgroup per sub-chunk) the union row of every entry, in the form
+// the relabelling reads (rowx[s + 1] = row + 1), its union column, and the checks of every
+// entry (id in range, no self-loop).  The sub-chunk's first row is found by rounds of 256
+// probes, its rows are expanded into LDS (one thread per row, from the union offsets) and
+// written out coalesced, so the union needs no row-start counting pass and no scan over all
+// entries.  Entries no row covers (offsets not monotone, which the row check flags too) are
+// flagged as well.
+#define US_SLOTS (2 * CG_CHUNK)
+#define US_SUB 4096   // entries expanded in LDS at a time
+__global__ __launch_bounds__(256) void k_union_slots(const int64_t* __restrict__ vb, const int64_t* __restrict__ sb,
+                                                     const int* __restrict__ gcb, int ngraphs,
+                                                     const int* __restrict__ urp,
+                                                     const int* const* __restrict__ glcol,
+                                                     u32* __restrict__ rowx, int* __restrict__ ucol,
+                                                     int* __restrict__ err) {
+    static_assert(US_SLOTS % US_SUB == 0, "sub-chunks tile a chunk");
+    __shared__ int srow[US_SUB];
+    __shared__ u64 sprobe[256 / GLT_WAVE];
+    __shared__ int64_t slo;
+    const int b = blockIdx.x / (US_SLOTS / US_SUB), t = threadIdx.x;   // chunk b, one sub-chunk of it
     int glo = 0, ghi = ngraphs;   // the chunk's graph: the last g with gcb[g] <= b
     while (ghi - glo > 1) {
         const int mid = (glo + ghi) >> 1;
@@ -193,20 +204,52 @@ __global__ __launch_bounds__(256) void k_union_cols(const int64_t* __restrict__ 
     }
     const int g = glo;
     const int64_t v0 = vb[g], ng = vb[g + 1] - v0, s0 = sb[g];
-    const int64_t j0 = (int64_t)(b - gcb[g]) * (2 * CG_CHUNK);
-    const int64_t j1 = min(j0 + 2 * CG_CHUNK, sb[g + 1] - s0);
+    const int64_t j0 = (int64_t)(b - gcb[g]) * US_SLOTS;
+    const int64_t j1 = min(j0 + US_SLOTS, sb[g + 1] - s0);
     const int* lc = glcol[g];
     int bad = 0;
-    for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
-        const int c = lc[j];
-        const int64_t s = s0 + j;
-        const int64_t v = (int64_t)rowx[s + 1] - 1;   // the entry's union row
-        if (c < 0 || c >= ng || v < v0 || v >= v0 + ng) {
-            bad |= ERR_RANGE;
-            ucol[s] = (int)v0;
-        } else {
-            ucol[s] = (int)(v0 + c);
-            if (v0 + c == v) bad |= ERR_SELF;
+    {
+        const int64_t q0 = j0 + (int64_t)(blockIdx.x % (US_SLOTS / US_SUB)) * US_SUB;
+        if (q0 >= j1) return;   // past the graph's last entry (whole workgroup)
+        const int64_t c0 = s0 + q0, c1 = s0 + min(q0 + US_SUB, j1);   // union entries [c0, c1)
+        // the row holding entry c0: the last row of the graph with offset <= c0 (the graph's
+        // first offset is its slot base s0 <= c0), by rounds of 256 probes at once
+        int64_t lo = v0, hi = v0 + ng;   // urp[lo] <= c0; the answer lies in [lo, hi)
+        while (hi - lo > 1) {
+            const int64_t step = (hi - lo + 255) / 256;
+            const int64_t p = lo + (int64_t)t * step;
+            const bool le = p < hi && (int64_t)urp[p] <= c0;   // probes <= c0 form a prefix
+            const u64 m = __ballot(le);
+            if (glt_lane() == 0) sprobe[t / GLT_WAVE] = m;
+            __syncthreads();
+            int cntle = 0;
+            for (int w = 0; w < 256 / GLT_WAVE; w++) cntle += __popcll(sprobe[w]);
+            __syncthreads();
+            const int64_t nlo = lo + (int64_t)(cntle - 1) * step;   // the last probe <= c0
+            hi = min(hi, nlo + step);
+            lo = nlo;
+        }
+        if (t == 0) slo = lo;
+        for (int i = t; i < US_SUB; i += 256) srow[i] = -1;
+        __syncthreads();
+        for (int64_t r = slo + t; r < v0 + ng; r += 256) {
+            const int64_t rb = urp[r], re = urp[r + 1];
+            if (rb >= c1) break;   // offsets ascend: every later row starts past the sub-chunk too
+            const int64_t e0 = rb > c0 ? rb : c0, e1 = re < c1 ? re : c1;
+            for (int64_t e = e0; e < e1; e++) srow[e - c0] = (int)r;
+        }
+        __syncthreads();
+        for (int64_t e = c0 + t; e < c1; e += 256) {
+            const int v = srow[e - c0];
+            const int c = lc[e - s0];
+            rowx[e + 1] = (u32)(v + 1);
+            if (v < 0 || c < 0 || c >= ng) {
+                bad |= ERR_RANGE;
+                ucol[e] = (int)v0;
+            } else {
+                ucol[e] = (int)(v0 + c);
+                if (v0 + c == v) bad |= ERR_SELF;
+            }
         }
     }
     bad = wave_or(bad);
@@ -796,13 +839,13 @@ __global__ void k_wide_split(const int* __restrict__ ndeg, const int* __restrict
 // host orchestration
 // ---------------------------------------------------------------------------------------
 template <int R>
-static void launch_check_rows(const Dev& d, const void* rp, int rp64, hipStream_t st) {
+static void launch_check_rows(const Dev& d, const void* rp, int rp64, u32* cnt, hipStream_t st) {
     if (rp64)
         hipLaunchKernelGGL((k_check_rows<int64_t, R>), dim3(nblk(d.n, 256 * R)), dim3(256), 0, st,
-                           (const int64_t*)rp, d.n, (int64_t)d.S, d.deg, d.rowx, d.err);
+                           (const int64_t*)rp, d.n, (int64_t)d.S, d.deg, cnt, d.err);
     else
         hipLaunchKernelGGL((k_check_rows<int32_t, R>), dim3(nblk(d.n, 256 * R)), dim3(256), 0, st,
-                           (const int32_t*)rp, d.n, (int64_t)d.S, d.deg, d.rowx, d.err);
+                           (const int32_t*)rp, d.n, (int64_t)d.S, d.deg, cnt, d.err);
 }
 
 int glt_prep_validate(const Dev& d, const void* rp, int rp64, const int* col, hipStream_t st) {
@@ -810,14 +853,17 @@ int glt_prep_validate(const Dev& d, const void* rp, int rp64, const int* col, hi
     if (d.ngraphs <= 0) (void)hipMemsetAsync(d.err, 0, ERR_WORDS * sizeof(int), st);
     if (d.n <= 0) return 0;
     const int64_t S = d.S;
-    launch_fill<u32>(d.rowx, S + 1, 0u, st);
-    if (tile_r(d.n) == 1) launch_check_rows<1>(d, rp, rp64, st);
-    else launch_check_rows<TILE_R_LARGE>(d, rp, rp64, st);
-    launch_excl_scan<u32, u32>(d.rowx, d.rowx, S + 1, d.rs_tmp, (u32*)nullptr, st);
+    // the row of every entry: in a batch written per chunk from the union offsets, else a
+    // prefix sum of row-start counts
+    u32* cnt = d.ngraphs > 0 ? nullptr : d.rowx;
+    if (cnt) launch_fill<u32>(d.rowx, S + 1, 0u, st);
+    if (tile_r(d.n) == 1) launch_check_rows<1>(d, rp, rp64, cnt, st);
+    else launch_check_rows<TILE_R_LARGE>(d, rp, rp64, cnt, st);
+    if (cnt) launch_excl_scan<u32, u32>(d.rowx, d.rowx, S + 1, d.rs_tmp, (u32*)nullptr, st);
     if (S > 0) {
-        if (d.ngraphs > 0)   // the union's columns, checked as they are written
-            hipLaunchKernelGGL(k_union_cols, dim3(d.ncchunks), dim3(256), 0, st, d.gvb, d.gsb, d.gcb, d.ngraphs,
-                               d.rowx, d.glcol, (int*)col, d.err);
+        if (d.ngraphs > 0)   // the union's rows and columns, checked as they are written
+            hipLaunchKernelGGL(k_union_slots, dim3(d.ncchunks * (US_SLOTS / US_SUB)), dim3(256), 0, st, d.gvb, d.gsb, d.gcb, d.ngraphs,
+                               (const int*)rp, d.glcol, d.rowx, (int*)col, d.err);
         else
             hipLaunchKernelGGL(k_check_cols, dim3(nblk(S, 256)), dim3(256), 0, st, d.rowx, col, d.n, S, d.err);
     }
