@@ -36,16 +36,16 @@ TRAFFIC_SOURCES = ["paper_1608_05138_amd/csrc/count.hip", "paper_1608_05138_amd/
                    "paper_1608_05138_amd/csrc/glt_internal.h", "paper_1608_05138_amd/csrc/prims.h",
                    "paper_1608_05138_amd/csrc/api.hip"]   # api.hip: the schedule the call runs with
 TRAFFIC = {
-    "sha256": "a4d1d26c1ca1c739ce841e721d07fadb7ff340d08cdfa8be78920f4c927f5f92",
+    "sha256": "7d3e2dc6b10e5cab84b66b577721ba23a7389882322dad6bdfc4544584769a02",
     "workloads": {
-        "rmat_s22": {"tri_wave": 26736821824, "tri_wg": 171844107488,
-                     "gather_wave": 3124891264, "gather_wg": 111706421664,
-                     "wedge_wave": 73651360, "wedge_mid": 3705907968,
-                     "wedge_wg": 81078675936, "wedge_huge": 464773944224},
-        "chung_lu_1m": {"tri_wave": 3313149728, "tri_wg": 3927296864,
-                        "gather_wave": 1487717376, "gather_wg": 2899560256,
-                        "wedge_wave": 82324032, "wedge_mid": 3528868160,
-                        "wedge_wg": 9044038464, "wedge_huge": 33792},
+        "rmat_s22": {"tri_wave": 26742541600, "tri_wg": 171650089888,
+                     "gather_wave": 3125375104, "gather_wg": 111760434784,
+                     "wedge_wave": 73580448, "wedge_mid": 3707078144,
+                     "wedge_wg": 81099511072, "wedge_huge": 465961133856},
+        "chung_lu_1m": {"tri_wave": 3305786656, "tri_wg": 3943896064,
+                        "gather_wave": 1483506944, "gather_wg": 2903478272,
+                        "wedge_wave": 82274624, "wedge_mid": 3526883584,
+                        "wedge_wg": 9035567424, "wedge_huge": 33792},
     },
 }
 
