@@ -89,16 +89,28 @@ def _gen_batch_graph(spec):
     return gg.batch_graph(spec)
 
 
+# Host processes that generate the batch and served graphs (not timed).  1: threads of this
+# process instead (numpy releases the interpreter lock in most of the work): under a
+# profiler that runs threads of its own in the process (rocprofv3 --pmc), forked generators
+# can deadlock on a lock one of those threads held at the fork.
+GEN_PROCS = [max(1, min(16, len(os.sched_getaffinity(0))))]
+
+
+def _gen_map(fn, items, chunksize):
+    import multiprocessing as mp
+    from multiprocessing.pool import ThreadPool
+    if GEN_PROCS[0] <= 1:
+        with ThreadPool(max(1, min(16, len(os.sched_getaffinity(0))))) as pool:
+            return pool.map(fn, items, chunksize=chunksize)
+    with mp.get_context("fork").Pool(GEN_PROCS[0]) as pool:
+        return pool.map(fn, items, chunksize=chunksize)
+
+
 def gen_batch(num_graphs, base=None):
     """The mixed batch, generated in parallel host processes (not timed)."""
-    import multiprocessing as mp
-
     import graphgen as gg
     specs = gg.batch_spec(num_graphs) if base is None else gg.batch_spec(num_graphs, base=base)
-    procs = max(1, min(16, len(os.sched_getaffinity(0))))
-    with mp.get_context("fork").Pool(procs) as pool:
-        graphs = pool.map(_gen_batch_graph, specs, chunksize=16)
-    return specs, graphs
+    return specs, _gen_map(_gen_batch_graph, specs, 16)
 
 
 def _gen_large(seed):
@@ -110,16 +122,12 @@ def _gen_large(seed):
 def gen_served_pools(pool_small, pool_large):
     """The served benchmark's request pools (small graphs of the batch mix, large Chung-Lu
     graphs), generated in parallel host processes before any device work."""
-    import multiprocessing as mp
-
     import graphgen as gg
-    procs = max(1, min(16, len(os.sched_getaffinity(0))))
     print(f"[bench] generating request pool: {pool_small} small + {pool_large} large",
           file=sys.stderr, flush=True)
     specs = gg.batch_spec(pool_small, base=gg.BASE_SEED + 4)
-    with mp.get_context("fork").Pool(procs) as pool:
-        small = pool.map(_gen_batch_graph, specs, chunksize=8)
-        large = pool.map(_gen_large, [gg.graph_seed(gg.BASE_SEED + 5, i) for i in range(pool_large)])
+    small = _gen_map(_gen_batch_graph, specs, 8)
+    large = _gen_map(_gen_large, [gg.graph_seed(gg.BASE_SEED + 5, i) for i in range(pool_large)], 1)
     return small, large
 
 
@@ -569,6 +577,9 @@ def main():
     ap.add_argument("--no-probe", action="store_true", help="skip the atomic-rate calibration of the roofline")
     ap.add_argument("--no-side-serving", action="store_true",
                     help="R-MAT line: skip the short batch and served runs reported beside it")
+    ap.add_argument("--gen-procs", type=int, default=None,
+                    help="host processes generating the batch / served graphs (default: up to 16; 1: threads "
+                         "of this process instead, for runs under a profiler)")
     ap.add_argument("--compare-modes", action="store_true",
                     help="single graph: also time the other stream modes (reported beside the line)")
     ap.add_argument("--schedule", default=None, metavar="K=V,...",
@@ -590,6 +601,8 @@ def main():
                     help="only run the library's read-only probe over BYTES (1 untimed + 3 timed launches): "
                          "a second calibration point of FETCH_SIZE")
     args = ap.parse_args()
+    if args.gen_procs is not None:
+        GEN_PROCS[0] = max(1, args.gen_procs)
     if args.read_probe:
         import paper_1608_05138_amd as glt
         ms, nbytes = glt.probe("read", args.read_probe, reps=3)
