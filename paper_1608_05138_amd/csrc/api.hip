@@ -137,6 +137,7 @@ size_t carve(void* base, int n, int m, int rp64, bool host_in, bool host_out, in
     d.counts = c.take<int>(CNT_WORDS);
     d.work = c.take<u64>(NWORK);
     d.final_sums = c.take<u64>(2 * 13);
+    d.apad = c.take<int>((int64_t)APAD_SLOTS * APAD_STRIDE);   // (after err..work: one read-back takes those)
     d.deg = c.take<int>(n);
     d.order = c.take<int>(n);
     d.rank = c.take<int>(n);

@@ -116,6 +116,10 @@ enum { WB_WAVE = 0, WB_MID, WB_BLK, WB_HUGE, WB_N };        // wedge pass
 #define CNT_KW (TB_N + WB_N + TB_N)
 #define CNT_MID_TO_WG (CNT_KW + 1)
 #define CNT_WORDS (CNT_KW + 2)
+// Padded accumulation of the work-list counters and largest out-degrees (then copied into
+// counts): APAD_SLOTS counters, APAD_STRIDE ints (4 KiB) apart.
+#define APAD_STRIDE 1024
+#define APAD_SLOTS (TB_N + WB_N + TB_N)
 
 // Device pointers of one graph's workspace.
 struct Dev {
@@ -150,6 +154,7 @@ struct Dev {
     u64* trec;        // triangle records (null: the passes re-scan the out-lists instead)
     int* wlist;       // wedge-pass vertex lists, WB_N segments of n
     int* counts;      // bucket counts and maxima (TB_N + WB_N + TB_N)
+    int* apad;        // [APAD_SLOTS * APAD_STRIDE] the same, accumulated apart (see k_pad_to_counts)
     u64* work;        // work counters [NWORK]: wedges (wave / workgroup class), triangle-pass list
                       // entries (wave / workgroup path), triangles found (wave / workgroup path),
                       // wedges (mid / huge class)

@@ -27,7 +27,7 @@ __device__ __forceinline__ int wave_or(int v) {
 // their index order, and each list takes one global atomic per workgroup (hundreds of
 // thousands of workgroups on a few counters would serialise).  Every thread of the
 // workgroup must call it, once per kernel.
-template <int NL, int R>
+template <int NL, int R, int CS = 1>   // CS: ints between consecutive list counters
 __device__ __forceinline__ void block_append(int* counters, int* lists, int64_t stride, const int (&cls)[R],
                                              const int (&value)[R]) {
     __shared__ int wc[R][NL][256 / GLT_WAVE];
@@ -55,7 +55,7 @@ __device__ __forceinline__ void block_append(int* counters, int* lists, int64_t 
                 wc[r][c][q] = tot;
                 tot += v;
             }
-        base[c] = tot ? atomicAdd(&counters[c], tot) : 0;
+        base[c] = tot ? atomicAdd(&counters[c * CS], tot) : 0;
     }
     __syncthreads();
 #pragma unroll
@@ -740,7 +740,7 @@ __global__ __launch_bounds__(256) void k_tbuckets(const int* __restrict__ optr, 
         sz[r] = s;
         if (x < n) toff[x] = (u64)s * (u64)(s > 0 ? s - 1 : 0) / 2;
     }
-    block_append<TB_N, R>(counts, tlist, n, cls, idx);   // (its barriers also order bmax's clearing)
+    block_append<TB_N, R, APAD_STRIDE>(counts, tlist, n, cls, idx);   // (its barriers also order bmax's clearing)
 #pragma unroll
     for (int r = 0; r < R; r++) {
         for (int q = 0; q < TB_N; q++) {
@@ -749,7 +749,7 @@ __global__ __launch_bounds__(256) void k_tbuckets(const int* __restrict__ optr, 
         }
     }
     __syncthreads();
-    if (threadIdx.x < TB_N && bmax[threadIdx.x]) atomicMax(&tmax[threadIdx.x], bmax[threadIdx.x]);
+    if (threadIdx.x < TB_N && bmax[threadIdx.x]) atomicMax(&tmax[threadIdx.x * APAD_STRIDE], bmax[threadIdx.x]);
 }
 
 // Bucket the wedge pass by wedges per vertex; per-class wedge totals go to the spread work
@@ -779,7 +779,7 @@ __global__ __launch_bounds__(256) void k_wappend(const u64* __restrict__ wcnt, i
             wmax[c] = (q == c && wc > wmax[c]) ? wc : wmax[c];
         }
     }
-    block_append<WB_N, R>(counts, wlist, n, cls, idx);
+    block_append<WB_N, R, APAD_STRIDE>(counts, wlist, n, cls, idx);
     // wedges per class, summed per workgroup: wspread words 0 (wave), 1 (workgroup), 4 (mid),
     // 5 (huge); the most wedges of one bottom per class: words 8 + class
     __shared__ u64 cred[WB_N][256 / GLT_WAVE];
@@ -805,6 +805,17 @@ __global__ __launch_bounds__(256) void k_wappend(const u64* __restrict__ wcnt, i
         if (t) atomicAdd(&line[wd], t);
         if (x) atomicMax(&line[8 + threadIdx.x], x);
     }
+}
+
+// The work-list counters and the triangle lists' largest out-degrees, accumulated APAD_STRIDE
+// ints apart (each in its own stretch of memory, so that the atomics of 10^5 workgroups on
+// different counters proceed in parallel instead of queueing on one line), into their
+// places in counts.
+__global__ void k_pad_to_counts(const int* __restrict__ apad, int* __restrict__ counts) {
+    const int t = threadIdx.x;
+    if (t < TB_N) counts[t] = apad[t * APAD_STRIDE];                                     // triangle lists
+    if (t < WB_N) counts[TB_N + t] = apad[(TB_N + t) * APAD_STRIDE];                     // wedge lists
+    if (t < TB_N) counts[TB_N + WB_N + t] = apad[(TB_N + WB_N + t) * APAD_STRIDE];       // largest out-degrees
 }
 
 // Split point kw of the per-edge accumulators (EdgeArrays): the first oriented edge whose
@@ -969,10 +980,12 @@ int glt_prep_build(const Dev& d, const void* rp, int rp64, const int* col, hipSt
     // path and mid wedge class ran 2.6 and 1.4 ms slower, more than the 3 ms that fewer
     // counter atomics save here, so the work lists keep one sub-tile per workgroup.
     const int mid_max = d.wedge_mid_max < 65535 ? d.wedge_mid_max : 65535;
-    hipLaunchKernelGGL(k_tbuckets<1>, dim3(nblk(n, 256)), dim3(256), 0, st, d.optr, n, d.tlist, d.counts,
-                       d.counts + TB_N + WB_N, d.toff);
+    launch_fill<int>(d.apad, (int64_t)APAD_SLOTS * APAD_STRIDE, 0, st);
+    hipLaunchKernelGGL(k_tbuckets<1>, dim3(nblk(n, 256)), dim3(256), 0, st, d.optr, n, d.tlist, d.apad,
+                       d.apad + (TB_N + WB_N) * APAD_STRIDE, d.toff);
     launch_excl_scan<u64, u64>(d.toff, d.toff, n, d.tmp64, d.toff + n, st);
     hipLaunchKernelGGL(k_wappend<1>, dim3(nblk(n, 256)), dim3(256), 0, st, d.wcnt, n, d.wedge_wave_max, mid_max,
-                       d.wedge_wg_max, d.wlist, d.counts + TB_N, d.wspread);
+                       d.wedge_wg_max, d.wlist, d.apad + TB_N * APAD_STRIDE, d.wspread);
+    hipLaunchKernelGGL(k_pad_to_counts, dim3(1), dim3(64), 0, st, d.apad, d.counts);
     return 0;
 }
