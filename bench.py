@@ -36,16 +36,16 @@ TRAFFIC_SOURCES = ["paper_1608_05138_amd/csrc/count.hip", "paper_1608_05138_amd/
                    "paper_1608_05138_amd/csrc/glt_internal.h", "paper_1608_05138_amd/csrc/prims.h",
                    "paper_1608_05138_amd/csrc/api.hip"]   # api.hip: the schedule the call runs with
 TRAFFIC = {
-    "sha256": "7d3e2dc6b10e5cab84b66b577721ba23a7389882322dad6bdfc4544584769a02",
+    "sha256": "2586c68192c34c0d03e72b82fc2f143cb0b3c4bb175be28dcdd21fbb7fc8d358",
     "workloads": {
-        "rmat_s22": {"tri_wave": 26742541600, "tri_wg": 171650089888,
-                     "gather_wave": 3125375104, "gather_wg": 111760434784,
-                     "wedge_wave": 73580448, "wedge_mid": 3707078144,
-                     "wedge_wg": 81099511072, "wedge_huge": 465961133856},
-        "chung_lu_1m": {"tri_wave": 3305786656, "tri_wg": 3943896064,
-                        "gather_wave": 1483506944, "gather_wg": 2903478272,
-                        "wedge_wave": 82274624, "wedge_mid": 3526883584,
-                        "wedge_wg": 9035567424, "wedge_huge": 33792},
+        "rmat_s22": {"tri_wave": 26754363552, "tri_wg": 171705554880,
+                     "gather_wave": 3117006368, "gather_wg": 111666061024,
+                     "wedge_wave": 73619360, "wedge_mid": 3705969728,
+                     "wedge_wg": 81054528000, "wedge_huge": 465482324096},
+        "chung_lu_1m": {"tri_wave": 3302591104, "tri_wg": 3931177888,
+                        "gather_wave": 1474011520, "gather_wg": 2901127584,
+                        "wedge_wave": 82251584, "wedge_mid": 3526643008,
+                        "wedge_wg": 8977609408, "wedge_huge": 33792},
     },
 }
 
