@@ -148,7 +148,12 @@ typedef struct {
  * graphs are independent, so their edge neighbourhoods are processed together in one pass
  * over the packed graph, Section 4.1).  flags must be GLT_GLOBAL.
  *   out  host array of B*17 glt_u128, graph g's counts at out[17*g .. 17*g+16]
- * Errors as glt_count; any invalid graph fails the whole call.
+ * Errors as glt_count; any invalid graph fails the whole call.  A large batch (at least 64
+ * graphs and 2^26 column entries, on a handle created without a memory budget) is counted
+ * as four parts (graph g in part g mod 4) by helper handles the handle creates on first use,
+ * on their own streams and host threads at the same time; the counts are the same, the
+ * handle's glt_last_work entries become the parts' sums (maxima for entries [10]-[15]) and
+ * its glt_last_timing entries the longest part's.
  */
 glt_status glt_count_batch(glt_ctx* ctx, const glt_batch* b, uint32_t flags, glt_u128* out, void* stream);
 

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/glt.h"
@@ -23,6 +24,12 @@ int64_t glt_slab_words(int smax);
 int glt_wedge_table();
 int glt_wave_table();
 int glt_wedge_dense();
+
+// Large batches (at least GLT_BATCH_SPLIT_GRAPHS graphs and 2^26 entries, on a handle without
+// a memory budget) are dealt round-robin to GLT_BATCH_PARTS parts counted at the same time.
+#define GLT_BATCH_PARTS 4
+#define GLT_BATCH_SPLIT_GRAPHS 64
+#define GLT_BATCH_SPLIT_SLOTS ((int64_t)1 << 26)
 
 struct glt_ctx {
     int device = 0;
@@ -65,6 +72,8 @@ struct glt_ctx {
     size_t slab_bytes = 0;
     hipEvent_t ev_null = nullptr;      // orders the handle's stream after the legacy default stream
     void* scratch = nullptr;           // device address of this device's glt_count_noalloc workspace
+    glt_ctx* part[GLT_BATCH_PARTS] = {};   // helper handles of large batches (created on first use)
+    hipEvent_t ev_part = nullptr;      // the parts' streams start after the caller's stream reaches it
     Dev last;                          // device arrays of the last single-graph count (glt_host_wedges)
     bool last_valid = false;
     uint64_t last_cycles4 = 0;         // its wedge pass's 4-cycle total
@@ -659,7 +668,12 @@ glt_status glt_create(int device, size_t hbm_budget_bytes, glt_ctx** out) {
 
 void glt_destroy(glt_ctx* ctx) {
     if (!ctx) return;
+    for (glt_ctx*& p : ctx->part) {
+        glt_destroy(p);
+        p = nullptr;
+    }
     (void)hipSetDevice(ctx->device);
+    if (ctx->ev_part) (void)hipEventDestroy(ctx->ev_part);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->stage) (void)hipFree(ctx->stage);
@@ -812,6 +826,80 @@ glt_status glt_count_noalloc(glt_ctx* ctx, const glt_csr* g, uint32_t flags, glt
     return count_one(ctx, g, flags, out_global, out_per_edge, stream, true);
 }
 
+// A large batch as GLT_BATCH_PARTS parts (graph g in part g mod K, in order), each counted by
+// a helper handle on its own stream and host thread, all at the same time: one part's
+// preprocessing (bound by scattered loads) overlaps the others' counting passes (bound by
+// instruction issue).  Every graph's counts are those of the whole batch's call.  The
+// handle's work counters become the parts' sums (maxima for the per-class maxima and the
+// balance entries), its kernel-group times the longest part's.
+static glt_status run_batch_parts(glt_ctx* ctx, int64_t B, const int64_t* vb, const int64_t* sb,
+                                  const int* const* rps, const int* const* cols, glt_u128* out, hipStream_t st) {
+    constexpr int K = GLT_BATCH_PARTS;
+    for (glt_ctx*& p : ctx->part)
+        if (!p) {
+            const glt_status rc = glt_create(ctx->device, 0, &p);
+            if (rc) return fail(ctx, rc, "creating a helper handle for the batch parts failed");
+        }
+    if (!ctx->ev_part) HIPCHK(hipEventCreateWithFlags(&ctx->ev_part, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ctx->ev_part, st));
+    std::vector<int64_t> pv[K], ps[K];
+    std::vector<const int*> pr[K], pc[K];
+    std::vector<glt_u128> po[K];
+    for (int k = 0; k < K; k++) { pv[k].assign(1, 0); ps[k].assign(1, 0); }
+    for (int64_t g = 0; g < B; g++) {
+        const int k = (int)(g % K);
+        pv[k].push_back(pv[k].back() + (vb[g + 1] - vb[g]));
+        ps[k].push_back(ps[k].back() + (sb[g + 1] - sb[g]));
+        pr[k].push_back(rps[g]);
+        pc[k].push_back(cols[g]);
+    }
+    glt_status rc[K];
+    std::vector<std::thread> th;
+    for (int k = 0; k < K; k++) {
+        glt_ctx* p = ctx->part[k];
+        p->wedge_wave_max = ctx->wedge_wave_max;
+        p->wedge_mid_max = ctx->wedge_mid_max;
+        p->wedge_wg_max = ctx->wedge_wg_max;
+        p->wedge_limit = ctx->wedge_limit;
+        p->wedge_dense = ctx->wedge_dense;
+        p->tri_records = ctx->tri_records;
+        p->wedge_stream = ctx->wedge_stream;
+        p->list_order = ctx->list_order;
+        p->record_balance = ctx->record_balance;
+        p->wide_degree = ctx->wide_degree;
+        HIPCHK(hipStreamWaitEvent(p->stream, ctx->ev_part, 0));
+        po[k].assign(pr[k].size() * 17, glt_u128{0, 0});
+        rc[k] = GLT_OK;
+    }
+    for (int k = 0; k < K; k++)
+        th.emplace_back([&, k] {
+            glt_ctx* p = ctx->part[k];
+            const int64_t Bk = (int64_t)pr[k].size();
+            rc[k] = Bk > 0 ? glt_run_batch_ptrs(p, Bk, pv[k].data(), ps[k].data(), pr[k].data(), pc[k].data(),
+                                               po[k].data(), p->stream)
+                           : GLT_OK;
+        });
+    for (std::thread& t : th) t.join();
+    for (int k = 0; k < K; k++)
+        if (rc[k]) return fail(ctx, rc[k], "%s", ctx->part[k]->err.c_str());
+    for (int64_t g = 0; g < B; g++) memcpy(&out[(size_t)g * 17], &po[g % K][(size_t)(g / K) * 17], 17 * sizeof(glt_u128));
+    ctx->work[0] = (uint64_t)vb[B];
+    ctx->work[1] = (uint64_t)(sb[B] / 2);
+    for (int i = 2; i < 2 + NWORK + 2; i++) {
+        uint64_t v = 0;
+        const bool maxed = i >= 10;   // the balance entries and the per-class maxima
+        for (int k = 0; k < K; k++) v = maxed ? std::max(v, ctx->part[k]->work[i]) : v + ctx->part[k]->work[i];
+        ctx->work[i] = v;
+    }
+    for (int i = 0; i < NSEG; i++) {
+        float t = 0.f;
+        for (int k = 0; k < K; k++) t = std::max(t, ctx->part[k]->timing[i]);
+        ctx->timing[i] = t;
+    }
+    ctx->last_mode = ctx->part[0]->last_mode;
+    return GLT_OK;
+}
+
 glt_status glt_count_batch(glt_ctx* ctx, const glt_batch* b, uint32_t flags, glt_u128* out, void* stream_) {
     if (!ctx) return GLT_E_INVALID_ARG;
     ctx->err.clear();
@@ -862,6 +950,9 @@ glt_status glt_count_batch(glt_ctx* ctx, const glt_batch* b, uint32_t flags, glt
         rps[(size_t)g] = rp + vb[g] + g;
         cols[(size_t)g] = col + sb[g];
     }
+    ctx->last_valid = false;
+    if (B >= GLT_BATCH_SPLIT_GRAPHS && S >= GLT_BATCH_SPLIT_SLOTS && ctx->budget == 0)
+        return run_batch_parts(ctx, B, vb, sb, rps.data(), cols.data(), out, st);
     return glt_run_batch_ptrs(ctx, B, vb, sb, rps.data(), cols.data(), out, st);
 }
 
